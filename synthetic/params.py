@@ -1,0 +1,61 @@
+"""Seeded parameter sets for the guess network (host side, float64).
+
+Tensor names and shapes (torch-style conv layout [out, in, ky, kx]):
+
+    conv1.w [C, 2, 3, 3]   conv1.b [C]
+    conv2.w [C, C, 3, 3]   conv2.b [C]
+    spec.w1 [C, C]         spec.b  [C]      (1x1 skip path of the spectral layer)
+    spec.wk [M, M, C, C]                    (per-mode channel mixing, [ky, kx, out, in])
+    conv4.w [C, C, 3, 3]   conv4.b [C]
+    conv5.w [C, C, 3, 3]   conv5.b [C]
+    conv6.w [1, C, 3, 3]   conv6.b [1]
+
+Weights are uniform in +-sqrt(6 / fan_in) (He-uniform); biases are drawn in
++-0.1 when ``random_bias`` is set (tests) and are zero otherwise.  With
+``zero_last`` the output layer starts at zero, so the untrained network returns
+the previous solution unchanged.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+PARAM_ORDER = ("conv1.w", "conv1.b", "conv2.w", "conv2.b", "spec.w1", "spec.b",
+               "spec.wk", "conv4.w", "conv4.b", "conv5.w", "conv5.b",
+               "conv6.w", "conv6.b")
+
+
+def param_shapes(channels: int = 32, modes: int = 16) -> dict:
+    C, M = channels, modes
+    return {
+        "conv1.w": (C, 2, 3, 3), "conv1.b": (C,),
+        "conv2.w": (C, C, 3, 3), "conv2.b": (C,),
+        "spec.w1": (C, C), "spec.b": (C,),
+        "spec.wk": (M, M, C, C),
+        "conv4.w": (C, C, 3, 3), "conv4.b": (C,),
+        "conv5.w": (C, C, 3, 3), "conv5.b": (C,),
+        "conv6.w": (1, C, 3, 3), "conv6.b": (1,),
+    }
+
+
+def guess_net_params(seed: int, channels: int = 32, modes: int = 16,
+                     zero_last: bool = False, random_bias: bool = True) -> dict:
+    rng = np.random.default_rng(seed)
+    out = {}
+    for name in PARAM_ORDER:
+        shape = param_shapes(channels, modes)[name]
+        if name.endswith(".b"):
+            out[name] = (rng.uniform(-0.1, 0.1, size=shape) if random_bias
+                         else np.zeros(shape))
+            continue
+        if name == "spec.wk":
+            fan_in = 2 * shape[3]
+        elif name == "spec.w1":
+            fan_in = 2 * shape[1]
+        else:
+            fan_in = shape[1] * shape[2] * shape[3]
+        bound = np.sqrt(6.0 / fan_in)
+        out[name] = rng.uniform(-bound, bound, size=shape)
+    if zero_last:
+        out["conv6.w"] = np.zeros_like(out["conv6.w"])
+        out["conv6.b"] = np.zeros_like(out["conv6.b"])
+    return out

@@ -1,0 +1,186 @@
+"""Pins for the NumPy FP64 guess-network oracle.
+
+Checked against: a brute-force direct sum for the convolution and torch's CPU
+conv2d in float64, SciPy's DST-I for the sine basis, the closed-form inverse
+of the Dirichlet Laplacian on the retained modes, central finite differences
+for every gradient, the Adam closed form after one step and torch's CPU Adam.
+"""
+import numpy as np
+import pytest
+import scipy.fft
+import torch
+
+from oracle import gmres as og
+from oracle import net
+from synthetic import DriftingGaussians, guess_net_params
+
+
+def small_params(C=4, M=3, seed=0):
+    return guess_net_params(seed, channels=C, modes=M, zero_last=False, random_bias=True)
+
+
+def test_conv_direct_sum_and_torch():
+    rng = np.random.default_rng(0)
+    x = rng.standard_normal((2, 3, 5, 6))
+    w = rng.standard_normal((4, 3, 3, 3))
+    b = rng.standard_normal(4)
+    y = net.conv3x3(x, w, b)
+    ref = np.zeros_like(y)
+    for bi in range(2):
+        for d in range(4):
+            for i in range(5):
+                for j in range(6):
+                    s = b[d]
+                    for c in range(3):
+                        for p in range(3):
+                            for q in range(3):
+                                ii, jj = i + p - 1, j + q - 1
+                                if 0 <= ii < 5 and 0 <= jj < 6:
+                                    s += w[d, c, p, q] * x[bi, c, ii, jj]
+                    ref[bi, d, i, j] = s
+    assert np.max(np.abs(y - ref)) < 1e-12
+    t = torch.nn.functional.conv2d(torch.from_numpy(x), torch.from_numpy(w), torch.from_numpy(b),
+                                   padding=1).numpy()
+    assert np.max(np.abs(y - t)) < 1e-12
+
+
+def test_sine_basis_is_dst1():
+    n, M = 37, 16
+    S = net.sine_basis(n, M)
+    rng = np.random.default_rng(1)
+    x = rng.standard_normal(n)
+    assert np.allclose(S @ x, scipy.fft.dst(x, type=1)[:M] / 2.0, atol=1e-12)
+    Sf = net.sine_basis(n, n)
+    assert np.allclose(Sf @ Sf.T, (n + 1) / 2.0 * np.eye(n), atol=1e-11)
+
+
+def test_spectral_layer_inverts_laplacian_on_retained_modes():
+    N, M, C = 40, 16, 1
+    h = 1.0 / (N + 1)
+    k = np.arange(1, M + 1)
+    lam1 = (4.0 / h ** 2) * np.sin(k * np.pi * h / 2) ** 2
+    lam = lam1[:, None] + lam1[None, :]                       # [ky, kx]
+    wk = (1.0 / lam)[:, :, None, None]
+    rng = np.random.default_rng(2)
+    coef = rng.standard_normal((M, M))
+    S = net.sine_basis(N, M)
+    f = S.T @ coef @ S                                         # f in the span of the retained modes
+    _, cache = net.spectral_forward(f[None, None], np.zeros((C, C)), np.zeros(C), wk)
+    z = cache[2][0, 0]                                         # pre-activation
+    assert np.max(np.abs(og.apply(z) - f)) <= 1e-11 * np.abs(f).max()
+
+
+def test_untrained_output_layer_returns_previous_solution():
+    p = guess_net_params(3, channels=8, modes=4, zero_last=True)
+    g = DriftingGaussians((20, 20), 2, 0.05, seed=9)
+    f = np.stack([g.field(1), g.field(2)])
+    u = np.stack([og.gmres(g.field(0), m=10, rtol=1e-6)[0], g.field(0) * 0.01])
+    guess, out, s = net.forward(p, f, u)
+    assert np.array_equal(guess, u) and np.all(out == 0)
+
+
+def test_forward_is_homogeneous_in_the_inputs():
+    """Scaling (f, u_prev) by a > 0 scales the guess by a (input normalisation)."""
+    p = small_params()
+    rng = np.random.default_rng(4)
+    f = rng.standard_normal((2, 9, 11))
+    u = rng.standard_normal((2, 9, 11)) * 0.01
+    g1, _, _ = net.forward(p, f, u)
+    g2, _, _ = net.forward(p, 7.5 * f, 7.5 * u)
+    assert np.allclose(g2, 7.5 * g1, rtol=1e-12, atol=1e-14)
+
+
+def test_zero_source_uses_unit_scale():
+    p = small_params()
+    u = np.random.default_rng(5).standard_normal((1, 6, 6))
+    g, out, s = net.forward(p, np.zeros((1, 6, 6)), u)
+    assert s[0] == 1.0 and np.all(np.isfinite(g))
+
+
+def test_loss_closed_form():
+    p = small_params()
+    rng = np.random.default_rng(6)
+    f = rng.standard_normal((3, 7, 8))
+    u = rng.standard_normal((3, 7, 8)) * 0.1
+    _, out, s = net.forward(p, f, u)
+    delta = rng.standard_normal(out.shape)
+    # choose the target so that out - t = delta
+    u_t = u + (out - delta) * s[:, None, None] / net.C_U
+    L, _ = net.loss_and_grads(p, f, u, u_t)
+    assert abs(L - np.sum(delta ** 2) / 3) <= 1e-10 * L
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_gradients_match_finite_differences(seed):
+    p = small_params(C=4, M=3, seed=seed)
+    rng = np.random.default_rng(10 + seed)
+    B, H, W = 2, 7, 6
+    f = rng.standard_normal((B, H, W))
+    u = rng.standard_normal((B, H, W)) * 0.05
+    ut = u + rng.standard_normal((B, H, W)) * 0.05
+    L, g = net.loss_and_grads(p, f, u, ut)
+    eps = 1e-6
+    for name in p:
+        d = rng.standard_normal(p[name].shape)
+        pp = {k: v.copy() for k, v in p.items()}
+        pm = {k: v.copy() for k, v in p.items()}
+        pp[name] = p[name] + eps * d
+        pm[name] = p[name] - eps * d
+        fd = (net.loss_and_grads(pp, f, u, ut)[0] - net.loss_and_grads(pm, f, u, ut)[0]) / (2 * eps)
+        an = float(np.sum(g[name] * d))
+        assert abs(fd - an) <= 1e-6 * max(abs(an), 1e-3 * abs(L)), name
+
+
+def test_gradients_match_torch_autograd():
+    """Same network written with torch CPU float64 ops and autograd."""
+    p = small_params(C=4, M=3, seed=2)
+    rng = np.random.default_rng(12)
+    B, H, W = 2, 8, 9
+    f = rng.standard_normal((B, H, W))
+    u = rng.standard_normal((B, H, W)) * 0.05
+    ut = u + rng.standard_normal((B, H, W)) * 0.05
+    L, g = net.loss_and_grads(p, f, u, ut)
+    T = {k: torch.tensor(v, requires_grad=True) for k, v in p.items()}
+    F = torch.nn.functional
+    x0, s = net.normalise(f, u)
+    x = torch.tensor(x0)
+    a = F.relu(F.conv2d(x, T["conv1.w"], T["conv1.b"], padding=1))
+    a = F.relu(F.conv2d(a, T["conv2.w"], T["conv2.b"], padding=1))
+    M = 3
+    Sy = torch.tensor(np.sin(np.arange(1, M + 1)[:, None] * np.pi * np.arange(1, H + 1)[None] / (H + 1)))
+    Sx = torch.tensor(np.sin(np.arange(1, M + 1)[:, None] * np.pi * np.arange(1, W + 1)[None] / (W + 1)))
+    X = Sy @ a @ Sx.T                                          # [B, C, M, M]
+    Y = torch.einsum("kldc,bckl->bdkl", T["spec.wk"], X)
+    ys = (2.0 / (H + 1)) * (2.0 / (W + 1)) * (Sy.T @ Y @ Sx)
+    a = F.relu(F.conv2d(a, T["spec.w1"][:, :, None, None], T["spec.b"]) + ys)
+    a = F.relu(F.conv2d(a, T["conv4.w"], T["conv4.b"], padding=1))
+    a = F.relu(F.conv2d(a, T["conv5.w"], T["conv5.b"], padding=1))
+    out = F.conv2d(a, T["conv6.w"], T["conv6.b"], padding=1)[:, 0]
+    t = torch.tensor(net.target(ut, u, s))
+    Lt = ((out - t) ** 2).sum() / B
+    Lt.backward()
+    assert abs(Lt.item() - L) <= 1e-12 * L
+    for k in p:
+        assert np.allclose(T[k].grad.numpy(), g[k], rtol=1e-9, atol=1e-12 * np.abs(g[k]).max()), k
+
+
+def test_adam_first_step_closed_form_and_torch():
+    rng = np.random.default_rng(3)
+    p = {"a": rng.standard_normal((4, 5)), "b": rng.standard_normal(3)}
+    grads = [{k: rng.standard_normal(v.shape) for k, v in p.items()} for _ in range(10)]
+    q = {k: v.copy() for k, v in p.items()}
+    st = {}
+    net.adam_step(q, grads[0], st, lr=1e-3)
+    for k in p:
+        step = p[k] - q[k]
+        assert np.allclose(step, 1e-3 * grads[0][k] / (np.abs(grads[0][k]) + 1e-8), rtol=1e-12, atol=0)
+    for gk in grads[1:]:
+        net.adam_step(q, gk, st, lr=1e-3)
+    T = {k: torch.tensor(v, requires_grad=True) for k, v in p.items()}
+    opt = torch.optim.Adam(list(T.values()), lr=1e-3, betas=(0.9, 0.999), eps=1e-8)
+    for gk in grads:
+        for k, t in T.items():
+            t.grad = torch.tensor(gk[k])
+        opt.step()
+    for k in p:
+        assert np.allclose(T[k].detach().numpy(), q[k], rtol=1e-12, atol=1e-15)
