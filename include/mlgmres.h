@@ -1,0 +1,251 @@
+/*
+ * mlgmres.h -- C ABI of the MI355X (gfx950) MLGMRES library.
+ *
+ * The library implements the hot path of "Accelerating GMRES with Deep
+ * Learning in Real-Time" (Luna, Klymko, Blaschke; arXiv 2103.10975):
+ * restarted GMRES(k) on the discrete Poisson problem, solved for a time
+ * series of right-hand sides, started from an initial guess produced by a
+ * small network that is trained in situ on the (source, solution) pairs the
+ * solver produces (Section 2 and Fig. 2 of the paper).
+ *
+ * Conventions shared by every entry point
+ *  - Pointers are DEVICE pointers unless the comment says "host".  The caller
+ *    owns all device memory (inputs, outputs, workspaces, parameters).
+ *  - `stream` is a hipStream_t passed as void* (NULL = the default stream).
+ *    Work is enqueued on it; the gmres_* calls also wait for it (they return
+ *    host statistics), the guess_net_* calls only enqueue.
+ *  - Fields are float64, row-major with x fastest: index (z*ny + y)*nx + x.
+ *  - Return codes: MLG_OK (0), MLG_NOT_CONVERGED (1, gmres only), or a
+ *    negative error; mlg_last_error() then holds a message (thread-local).
+ *    No C++ exception crosses this boundary.
+ *  - The library allocates no device memory on any call below.  It keeps a
+ *    per-process cache (pinned status buffers, captured HIP graphs, a helper
+ *    stream) that mlg_shutdown() releases.
+ */
+#ifndef MLGMRES_H
+#define MLGMRES_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  MLG_OK = 0,
+  MLG_NOT_CONVERGED = 1,     /* iteration cap reached; x holds the last iterate */
+  MLG_ERR_ARG = -1,          /* bad argument or shape */
+  MLG_ERR_WORKSPACE = -2,    /* workspace (or parameter buffer) too small */
+  MLG_ERR_HIP = -3,          /* a HIP runtime call failed */
+  MLG_ERR_NONFINITE = -4     /* a NaN/Inf appeared (e.g. in the initial guess) */
+};
+
+enum { MLG_FP64 = 0, MLG_FP32_IR = 1 };
+
+/*
+ * The discrete problem (paper Section 1.4, eq. for A u = f; benchmark of
+ * Section 3): A = -lap_h, the zero-Dirichlet 5-point (dim 2) or 7-point
+ * (dim 3) Laplacian on the unit square/cube with nx, ny[, nz] interior points
+ * per axis and h_i = 1/(n_i + 1); (A u)_p = sum_axes (2 u_p - u_{p-e} -
+ * u_{p+e}) / h_axis^2 with u = 0 outside the grid.  nz is ignored in 2D.
+ */
+typedef struct {
+  int32_t dim;
+  int32_t nx, ny, nz;
+} mlg_grid;
+
+/*
+ * Solver options (GMRES(k) of Section 1.3; the paper fixes neither k, the
+ * tolerance nor the precision).
+ *   restart_m     k of GMRES(k), 1..64.
+ *   precision     MLG_FP64: Krylov basis stored in FP64.  MLG_FP32_IR: basis
+ *                 stored in FP32, every cycle restarted from the FP64 true
+ *                 residual (iterative refinement: FP64 residual, Givens/least
+ *                 squares and solution update; FP32 Arnoldi vectors).
+ *   rtol          stop when |b - A x| <= rtol |b| (true residual, FP64).
+ *   max_iters     cap on Arnoldi steps (0 = 10^9).
+ *   fixed_iters   > 0: ignore rtol and run exactly this many Arnoldi steps,
+ *                 restarting every restart_m (trajectory comparisons).
+ *   tile          0 = autotuned/default tile shape; otherwise an index into
+ *                 the tile table (mlg_tile_count / mlg_tile_shape).
+ *   poll_cycles   restart cycles enqueued between host polls of the
+ *                 convergence flag (0 = 1).
+ */
+typedef struct {
+  int32_t restart_m;
+  int32_t precision;
+  double rtol;
+  int64_t max_iters;
+  int64_t fixed_iters;
+  int32_t tile;
+  int32_t poll_cycles;
+} mlg_opts;
+
+/* Per-solve statistics (host).  relres_first_cycle is the paper's metric E_k
+ * (Section 2.2): the true relative residual after the first restart cycle. */
+typedef struct {
+  int32_t status;
+  int32_t cycles;
+  int64_t iters;               /* Arnoldi steps (products A v) */
+  double relres_init;          /* |b - A x0| / |b| */
+  double relres_first_cycle;   /* E_k */
+  double relres_est;           /* last Givens estimate / |b| */
+  double relres_true;          /* final true relative residual (FP64) */
+  double seconds;              /* host wall time of the call (TOS of Section 2.2) */
+} mlg_stats;
+
+/* ---------------------------------------------------------------- solver */
+
+/* Bytes of device workspace gmres_solve needs for this grid and options
+ * (0 on invalid arguments).  The workspace holds the Krylov basis
+ * ((m+1) n elements of the basis precision), the FP64 residual, reduction
+ * partials and the device-side solver state. */
+size_t gmres_workspace_bytes(const mlg_grid* grid, const mlg_opts* opts);
+
+/*
+ * Restarted GMRES(k) (Section 1.3): x0 -> r0 = b - A x0, minimise the residual
+ * over K_k(A, r0) (Arnoldi with classical Gram-Schmidt applied twice, Givens
+ * rotations, back substitution), x += V y, restart from the last iterate until
+ * the true residual meets rtol.  A cycle stops early when the Givens residual
+ * estimate reaches rtol |b| or on breakdown; acceptance is on the recomputed
+ * true residual.
+ *   b      [n] right-hand side (read only).
+ *   x      [n] initial guess on entry, solution on exit.
+ *   ws     >= gmres_workspace_bytes(grid, opts) bytes, 256-byte aligned.
+ *   stats  host, may be NULL.
+ * Blocks until the solve has finished on `stream`.  b = 0 gives x = 0.
+ * Returns MLG_OK, MLG_NOT_CONVERGED, or an error (x then undefined).
+ */
+int gmres_solve(const mlg_grid* grid, const double* b, double* x, const mlg_opts* opts,
+                void* ws, size_t ws_bytes, mlg_stats* stats, void* stream);
+
+/* One independent system of a batched solve: nrhs right-hand sides solved in
+ * order; guess 0 starts each from zero, 1 from the previous solution of the
+ * same system (the first from x's initial contents). */
+typedef struct {
+  mlg_grid grid;
+  int32_t nrhs;
+  int32_t guess;
+  const double* b;   /* [nrhs][n] */
+  double* x;         /* [nrhs][n]; x[0] holds the first initial guess */
+} mlg_system;
+
+size_t gmres_batched_workspace_bytes(int32_t nsys, const mlg_system* sys, const mlg_opts* opts);
+
+/*
+ * Solve many independent systems of uneven size together: every restart
+ * cycle is one graph replay over the tiles of all still-active systems; a
+ * system that converges advances to its next right-hand side on the device.
+ *   stats  host, [sum of nrhs] in system order, may be NULL.
+ * Each solution equals gmres_solve on the same system and RHS.
+ */
+int gmres_solve_batched(int32_t nsys, const mlg_system* sys, const mlg_opts* opts,
+                        void* ws, size_t ws_bytes, mlg_stats* stats, void* stream);
+
+/* y = A u on the device (the operator of every solve), for checks. */
+int mlg_apply_operator(const mlg_grid* grid, const double* u, double* y, void* stream);
+
+/*
+ * Kernel timing (measurement support).  Times `reps` back-to-back launches of
+ * one solver kernel, in the launch configuration gmres_solve uses, with HIP
+ * events on `stream`, and returns the average duration in microseconds.
+ *   ws       the workspace of a finished gmres_solve with the same grid and
+ *            opts (its basis and coefficients are the kernel inputs; only the
+ *            reduction partials, the residual buffer and, for MLG_K_PROJ3 and
+ *            MLG_K_UPDATE, basis vector step+1 or x are overwritten).
+ *   scratch  >= mlg_kernel_bench_scratch_bytes(reps) bytes: one private copy
+ *            of the solver state per launch, so every launch does full work.
+ *   kind     MLG_K_PROJ1 .. MLG_K_RESIDUAL; step: Arnoldi index j (0..m-1,
+ *            0..m-2 for MLG_K_PROJ3).
+ */
+enum { MLG_K_PROJ1 = 0, MLG_K_PROJ2 = 1, MLG_K_PROJ3 = 2, MLG_K_UPDATE = 3, MLG_K_RESIDUAL = 4 };
+size_t mlg_kernel_bench_scratch_bytes(int32_t reps);
+int mlg_kernel_bench(const mlg_grid* grid, const mlg_opts* opts, void* ws, size_t ws_bytes,
+                     void* scratch, size_t scratch_bytes, int32_t kind, int32_t step, int32_t reps,
+                     double* avg_us, void* stream);
+
+/* Tile table used by the solver kernels. */
+int32_t mlg_tile_count(int32_t dim);
+int mlg_tile_shape(int32_t dim, int32_t index, int32_t* tx, int32_t* ty, int32_t* tz);
+
+/* ---------------------------------------------------------------- network */
+
+/*
+ * Guess network (the learned initial guess x0 = N(b) of Section 2; a
+ * non-local architecture as Section 2.1 asks for).  2D grids only.
+ *   inputs (f / s, c_u u_prev / s), s = RMS(f) (1 if f = 0), c_u = 2 pi^2
+ *   L1 conv3x3 2->C + ReLU, L2 conv3x3 C->C + ReLU,
+ *   L3 spectral: ReLU(W1 x + b + S^-1[W_kl . S[x]_kl]) over the modes x modes
+ *      slowest sine modes (S = DST-I basis), per-mode C x C mixing,
+ *   L4, L5 conv3x3 C->C + ReLU, L6 conv3x3 C->1;
+ *   guess = u_prev + (s / c_u) L6.
+ * Weights and activations are BF16 in the kernels with FP32 accumulation;
+ * FP32 master weights and Adam moments (Section 2.3: back-propagation and
+ * ADAM) live in the parameter buffer.
+ */
+typedef struct {
+  int32_t channels;   /* C, 32; multiple of 16, <= 64 */
+  int32_t modes;      /* M, 16; <= 32 */
+  float lr, beta1, beta2, eps;
+  uint64_t seed;
+} guess_net_cfg;
+
+/*
+ * Parameter buffer layout (device, 256-byte aligned regions, in this order):
+ *   master  FP32 [P]   weights in the tensor order below
+ *   grad    FP32 [P]   gradient of the last train step
+ *   adam_m  FP32 [P], adam_v FP32 [P]
+ *   bf16    BF16 [P]   working copy used by the kernels
+ *   step    int64      Adam step counter
+ * Tensor order inside each FP32/BF16 array (shapes [out, in, ky, kx]):
+ *   conv1.w [C,2,3,3] conv1.b [C] conv2.w [C,C,3,3] conv2.b [C]
+ *   spec.w1 [C,C] spec.b [C] spec.wk [M,M,C,C] (= [ky, kx, out, in])
+ *   conv4.w conv4.b conv5.w conv5.b (as conv2) conv6.w [1,C,3,3] conv6.b [1]
+ * guess_net_param_count gives P; guess_net_param_offset the element offset
+ * of tensor `index` (0..12 in the order above) inside one array.
+ */
+int64_t guess_net_param_count(const guess_net_cfg* cfg);
+int64_t guess_net_param_offset(const guess_net_cfg* cfg, int32_t index);
+size_t guess_net_param_bytes(const guess_net_cfg* cfg);
+
+/* Device workspace for infer (train = 0) or train_step (train = 1) on an
+ * nx x ny grid with `batch` samples. */
+size_t guess_net_workspace_bytes(const guess_net_cfg* cfg, const mlg_grid* grid,
+                                 int32_t batch, int32_t train);
+
+/* Deterministic initialisation from cfg->seed: He-uniform weights, zero
+ * biases, zero output layer (so the untrained network returns u_prev), zero
+ * Adam state. */
+int guess_net_init(const guess_net_cfg* cfg, void* params, void* stream);
+
+/* Recompute the BF16 working copy from the FP32 master weights (after the
+ * caller wrote master weights directly) and zero the Adam state. */
+int guess_net_refresh(const guess_net_cfg* cfg, void* params, void* stream);
+
+/* guess[b] = N(f[b], u_prev[b]) for `batch` samples of one grid (FP64 in/out,
+ * [batch][n] contiguous). */
+int guess_net_infer(const guess_net_cfg* cfg, const void* params, const mlg_grid* grid,
+                    int32_t batch, const double* f, const double* u_prev, double* guess,
+                    void* ws, size_t ws_bytes, void* stream);
+
+/*
+ * One Adam step on L = (1/B) sum_b |out_b - t_b|^2 with out the L6 output and
+ * t_b = c_u (u_target_b - u_prev_b) / s_b (Section 2.3 loss, in the network's
+ * output units).  f, u_prev, u_target: host arrays of `batch` device pointers
+ * (samples need not be contiguous).  loss: device float, may be NULL.
+ */
+int guess_net_train_step(const guess_net_cfg* cfg, void* params, const mlg_grid* grid,
+                         int32_t batch, const double* const* f, const double* const* u_prev,
+                         const double* const* u_target, void* ws, size_t ws_bytes,
+                         float* loss, void* stream);
+
+/* ---------------------------------------------------------------- misc */
+const char* mlg_last_error(void);
+void mlg_shutdown(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MLGMRES_H */

@@ -1,0 +1,140 @@
+// Shared device/host helpers of the MI355X (gfx950) MLGMRES library.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdio>
+#include <string>
+
+#include "../../include/mlgmres.h"
+
+namespace mlg {
+
+// ------------------------------------------------------------------ errors
+// Thread-local message behind mlg_last_error().
+void set_error(const std::string& msg);
+
+struct HipError {
+  hipError_t code;
+  std::string where;
+};
+
+#define MLG_HIP(expr)                                                          \
+  do {                                                                         \
+    hipError_t _e = (expr);                                                    \
+    if (_e != hipSuccess)                                                      \
+      throw ::mlg::HipError{_e, std::string(#expr) + " @ " + __FILE__ + ":" + \
+                                    std::to_string(__LINE__)};                 \
+  } while (0)
+
+struct ArgError {
+  int code;
+  std::string msg;
+};
+
+// ------------------------------------------------------------------ sizes
+constexpr int kBlock = 256;         // threads per workgroup for every sweep kernel
+constexpr int kMaxRestart = 64;     // largest supported restart length m
+constexpr int kXcds = 8;            // MI355X: 8 accelerator complex dies
+
+inline size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+// Map a hardware workgroup index to a tile index so that each XCD (which the
+// dispatcher feeds round-robin: workgroup b runs on XCD b % 8) owns one
+// contiguous band of tiles.  Neighbouring tiles then share that XCD's L2 for
+// their stencil halos.  Bijective for any count.
+__device__ __forceinline__ int xcd_tile(int b, int count) {
+  int q = count / kXcds, rem = count % kXcds;
+  int xcd = b % kXcds, i = b / kXcds;
+  int base = xcd < rem ? xcd * (q + 1) : rem * (q + 1) + (xcd - rem) * q;
+  return base + i;
+}
+
+// ------------------------------------------------------------------ wave sums
+// Deterministic full-wavefront FP64 sum with DPP lane moves (no LDS): pairs,
+// quads, half-rows, rows, then the two row broadcasts; lane 63 ends with the
+// total, which is broadcast through a scalar register.  Same order on every
+// call, so results are bitwise reproducible.
+template <int CTRL, int RM = 0xf>
+__device__ __forceinline__ double dpp_f64(double v) {
+  int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, RM, 0xf, false);
+  int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, RM, 0xf, false);
+  return __hiloint2double(hi, lo);
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+  v += dpp_f64<0xB1>(v);         // quad_perm [1,0,3,2]
+  v += dpp_f64<0x4E>(v);         // quad_perm [2,3,0,1]
+  v += dpp_f64<0x141>(v);        // row_half_mirror
+  v += dpp_f64<0x140>(v);        // row_mirror
+  v += dpp_f64<0x142, 0xa>(v);   // row_bcast:15 into rows 1 and 3
+  v += dpp_f64<0x143, 0xc>(v);   // row_bcast:31 into rows 2 and 3
+  int lo = __builtin_amdgcn_readlane(__double2loint(v), 63);
+  int hi = __builtin_amdgcn_readlane(__double2hiint(v), 63);
+  return __hiloint2double(hi, lo);
+}
+
+__device__ __forceinline__ float wave_sum_f32(float v) {
+  // float variant with the same lane schedule
+  int iv;
+  iv = __builtin_amdgcn_update_dpp(0, __float_as_int(v), 0xB1, 0xf, 0xf, false); v += __int_as_float(iv);
+  iv = __builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x4E, 0xf, 0xf, false); v += __int_as_float(iv);
+  iv = __builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x141, 0xf, 0xf, false); v += __int_as_float(iv);
+  iv = __builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x140, 0xf, 0xf, false); v += __int_as_float(iv);
+  iv = __builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x142, 0xa, 0xf, false); v += __int_as_float(iv);
+  iv = __builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x143, 0xc, 0xf, false); v += __int_as_float(iv);
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63));
+}
+
+// Sum of NV per-thread values over a 256-thread block; thread t < NV gets
+// the block total of value t in out_t (others: 0).  red must hold 4 * NV doubles.
+template <int NV>
+__device__ __forceinline__ void block_sums(const double (&acc)[NV], int nlive, double* red,
+                                           double& out_t) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int k = 0; k < NV; ++k) {
+    if (k < nlive) {
+      double s = wave_sum(acc[k]);
+      if (lane == 0) red[wave * NV + k] = s;
+    }
+  }
+  __syncthreads();
+  out_t = 0.0;
+  if (threadIdx.x < nlive)
+    out_t = ((red[threadIdx.x] + red[NV + threadIdx.x]) + red[2 * NV + threadIdx.x]) +
+            red[3 * NV + threadIdx.x];
+}
+
+// Last-block pattern: every block has stored its partials; the block that
+// takes the final ticket returns true (after an acquire fence) and resets the
+// ticket so the next launch can reuse it.
+__device__ __forceinline__ bool last_block(unsigned int* ticket, int nblocks) {
+  __shared__ int s_last;
+  __threadfence();
+  __syncthreads();
+  if (threadIdx.x == 0) s_last = (atomicAdd(ticket, 1u) == (unsigned)(nblocks - 1));
+  __syncthreads();
+  if (!s_last) return false;
+  __threadfence();
+  if (threadIdx.x == 0) *ticket = 0u;
+  return true;
+}
+
+// Fixed-order reduction of part[col * nblocks + b] over b for cols < ncols;
+// the result of column c lands in out[c].  Wave w handles columns w, w+4, ...
+__device__ __forceinline__ void reduce_partials(const double* part, int nblocks, int ncols,
+                                                double* out) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  for (int c = wave; c < ncols; c += 4) {
+    const double* p = part + (size_t)c * nblocks;
+    double s = 0.0;
+    for (int b = lane; b < nblocks; b += 64) s += p[b];
+    s = wave_sum(s);
+    if (lane == 0) out[c] = s;
+  }
+  __syncthreads();
+}
+
+}  // namespace mlg

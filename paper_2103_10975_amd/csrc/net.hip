@@ -1,0 +1,1003 @@
+// Guess network of the learned initial guess: forward (inference), and one
+// training step (forward with saved activations, squared-error loss,
+// back-propagation, Adam), all as HIP kernels for gfx950.
+//
+// Section 2 of the paper feeds the network output to GMRES(k) as x0 and trains
+// the network in situ on the (RHS, solution) pairs the solver produces with the
+// loss |x_tilde - x|^2 (Section 2.3) by back-propagation and ADAM; Section 2.1
+// asks for a network that captures non-local relations without reducing
+// resolution.  Architecture (C channels, M x M retained sine modes):
+//   x0 = (f/s, c_u u_prev/s)                          BF16 NHWC, 2 channels
+//   a1 = ReLU(conv3x3(x0))          a2 = ReLU(conv3x3(a1))
+//   a3 = ReLU(W1 a2 + b + S^-1[Wk . S[a2]])           (spectral mixing)
+//   a4 = ReLU(conv3x3(a3))          a5 = ReLU(conv3x3(a4))
+//   out = conv3x3(a5) (1 channel, FP32);  guess = u_prev + (s/c_u) out
+// The 3x3 convolutions with C -> C channels (forward, input gradient and
+// weight gradient) run on MFMA (v_mfma_f32_16x16x32_bf16) as implicit GEMMs
+// over LDS tiles; the thin layers (2 -> C, C -> 1), the sine transforms (GEMMs
+// with 16 outputs per row, bandwidth bound) and the element-wise work run on
+// the vector ALUs.  Activations and gradients are BF16, accumulation FP32,
+// master weights and Adam state FP32.
+#include <cmath>
+#include <vector>
+
+#include "net.h"
+
+namespace mlg {
+namespace {
+
+constexpr double kCu = 19.739208802178717;   // 2 pi^2
+constexpr int kMaxBatch = 64;
+constexpr int kNumTensors = 13;
+enum { T_C1W, T_C1B, T_C2W, T_C2B, T_SW1, T_SB, T_SWK, T_C4W, T_C4B, T_C5W, T_C5B, T_C6W, T_C6B };
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+typedef uint16_t bf16;
+
+// round-to-nearest-even FP32 -> BF16
+__device__ __forceinline__ bf16 f2bf(float f) {
+  uint32_t u = __float_as_uint(f);
+  if ((u & 0x7fffffffu) > 0x7f800000u) return (bf16)0x7fc0;
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (bf16)(u >> 16);
+}
+__device__ __forceinline__ float bf2f(bf16 h) { return __uint_as_float((uint32_t)h << 16); }
+__device__ __forceinline__ float to_f(bf16 h) { return bf2f(h); }
+__device__ __forceinline__ float to_f(float h) { return h; }
+
+struct Ptrs {
+  const double* p[kMaxBatch];
+};
+struct MPtrs {
+  double* p[kMaxBatch];
+};
+
+// ------------------------------------------------------------------ sizes
+struct Dims {
+  int B, H, W, C, M;
+  long long HW;
+};
+
+void tensor_sizes(const guess_net_cfg* cfg, int64_t* sz) {
+  const int64_t C = cfg->channels, M = cfg->modes;
+  int64_t s[kNumTensors] = {C * 2 * 9, C, C * C * 9, C, C * C, C, M * M * C * C,
+                            C * C * 9, C, C * C * 9, C, C * 9, 1};
+  for (int i = 0; i < kNumTensors; ++i) sz[i] = s[i];
+}
+
+void check_cfg(const guess_net_cfg* cfg) {
+  if (!cfg) throw ArgError{MLG_ERR_ARG, "cfg is NULL"};
+  if (cfg->channels != 32) throw ArgError{MLG_ERR_ARG, "channels must be 32"};
+  if (cfg->modes < 1 || cfg->modes > 32) throw ArgError{MLG_ERR_ARG, "modes must be in 1..32"};
+}
+
+struct ParamLayout {
+  int64_t P;
+  int64_t off[kNumTensors + 1];
+  size_t master, grad, m, v, bf, step, total;
+};
+
+ParamLayout param_layout(const guess_net_cfg* cfg) {
+  check_cfg(cfg);
+  ParamLayout L{};
+  int64_t sz[kNumTensors];
+  tensor_sizes(cfg, sz);
+  L.off[0] = 0;
+  for (int i = 0; i < kNumTensors; ++i) L.off[i + 1] = L.off[i] + (sz[i] + 63) / 64 * 64;
+  L.P = L.off[kNumTensors];
+  const size_t f = align_up((size_t)L.P * 4, 256);
+  L.master = 0;
+  L.grad = f;
+  L.m = 2 * f;
+  L.v = 3 * f;
+  L.bf = 4 * f;
+  L.step = L.bf + align_up((size_t)L.P * 2, 256);
+  L.total = L.step + 256;
+  return L;
+}
+
+Dims check_grid_net(const guess_net_cfg* cfg, const mlg_grid* grid, int batch) {
+  check_cfg(cfg);
+  if (!grid || grid->dim != 2) throw ArgError{MLG_ERR_ARG, "the guess network takes 2D grids"};
+  if (grid->nx < cfg->modes || grid->ny < cfg->modes)
+    throw ArgError{MLG_ERR_ARG, "grid must have at least `modes` points per axis"};
+  if (batch < 1 || batch > kMaxBatch) throw ArgError{MLG_ERR_ARG, "batch must be in 1..64"};
+  Dims d{batch, grid->ny, grid->nx, cfg->channels, cfg->modes,
+         (long long)grid->nx * grid->ny};
+  return d;
+}
+
+struct WsLayout {
+  size_t s, x0, act[5], out, dout, dz[2], T, X, Y, dX, Z, Sx, Sy, part, loss, total;
+  int wgrad_blocks;
+};
+
+WsLayout ws_layout(const Dims& d, bool train) {
+  WsLayout L{};
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    size_t r = o;
+    o = align_up(o + bytes, 256);
+    return r;
+  };
+  const size_t act = (size_t)d.B * d.HW * d.C * 2;
+  L.s = take((size_t)d.B * 8);
+  L.x0 = take((size_t)d.B * d.HW * 2 * 2);
+  const int nact = train ? 5 : 2;
+  for (int i = 0; i < 5; ++i) L.act[i] = i < nact ? take(act) : L.act[i % 2];
+  L.out = take((size_t)d.B * d.HW * 4);
+  L.T = take((size_t)d.B * d.H * d.M * d.C * 4);
+  L.X = take((size_t)d.B * d.M * d.M * d.C * 4);
+  L.Y = take((size_t)d.B * d.M * d.M * d.C * 4);
+  L.Z = take((size_t)d.B * d.H * d.M * d.C * 4);
+  L.Sx = take((size_t)d.M * d.W * 4);
+  L.Sy = take((size_t)d.M * d.H * 4);
+  L.wgrad_blocks = 0;
+  if (train) {
+    L.dout = take((size_t)d.B * d.HW * 4);
+    L.dz[0] = take(act);
+    L.dz[1] = take(act);
+    L.dX = take((size_t)d.B * d.M * d.M * d.C * 4);
+    L.wgrad_blocks = 512;
+    L.part = take((size_t)L.wgrad_blocks * (9 * d.C * d.C + d.C) * 4);
+    L.loss = take(4096 * 8);
+  }
+  L.total = o;
+  return L;
+}
+
+// ------------------------------------------------------------------ small kernels
+
+// s_b = RMS(f_b) (1 when f_b = 0); one block per sample, fixed-order sums.
+__global__ __launch_bounds__(256) void k_rms(Ptrs f, long long n, double* s) {
+  __shared__ double red[4];
+  const double* fb = f.p[blockIdx.x];
+  double acc = 0.0;
+  for (long long i = threadIdx.x; i < n; i += 256) acc += fb[i] * fb[i];
+  acc = wave_sum(acc);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = ((red[0] + red[1]) + red[2]) + red[3];
+    double r = sqrt(t / (double)n);
+    s[blockIdx.x] = r > 0.0 ? r : 1.0;
+  }
+}
+
+// x0[b][p] = (f/s, c_u u_prev/s) in BF16 (2 channels).
+__global__ void k_norm_in(Ptrs f, Ptrs u, const double* s, bf16* x0, long long HW) {
+  const int b = blockIdx.y;
+  const long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= HW) return;
+  const double inv = 1.0 / s[b];
+  bf16* o = x0 + ((size_t)b * HW + p) * 2;
+  o[0] = f2bf((float)(f.p[b][p] * inv));
+  o[1] = f2bf((float)(kCu * u.p[b][p] * inv));
+}
+
+// guess = u_prev + (s / c_u) out
+__global__ void k_guess(const float* out, Ptrs u, const double* s, MPtrs g, long long HW) {
+  const int b = blockIdx.y;
+  const long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= HW) return;
+  g.p[b][p] = u.p[b][p] + (s[b] / kCu) * (double)out[(size_t)b * HW + p];
+}
+
+// loss = (1/B) sum_b |out_b - t_b|^2, t = c_u (u_t - u_prev)/s; dout = (2/B)(out - t)
+__global__ __launch_bounds__(256) void k_loss(const float* out, Ptrs ut, Ptrs up, const double* s,
+                                              float* dout, double* part, unsigned int* ticket,
+                                              float* loss_dev, float* loss_user, long long HW,
+                                              int B) {
+  __shared__ double red[4];
+  const int b = blockIdx.y;
+  const long long p0 = (long long)blockIdx.x * 1024;
+  double acc = 0.0;
+  const double inv = kCu / s[b];
+  for (int i = 0; i < 4; ++i) {
+    long long p = p0 + threadIdx.x + 256 * i;
+    if (p < HW) {
+      double t = (ut.p[b][p] - up.p[b][p]) * inv;
+      double diff = (double)out[(size_t)b * HW + p] - t;
+      dout[(size_t)b * HW + p] = (float)(2.0 * diff / B);
+      acc += diff * diff;
+    }
+  }
+  acc = wave_sum(acc);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  const int nblk = gridDim.x * gridDim.y;
+  const int bid = blockIdx.y * gridDim.x + blockIdx.x;
+  if (threadIdx.x == 0) part[bid] = ((red[0] + red[1]) + red[2]) + red[3];
+  if (!last_block(ticket, nblk)) return;
+  __shared__ double fin[1];
+  reduce_partials(part, nblk, 1, fin);
+  if (threadIdx.x == 0) {
+    float L = (float)(fin[0] / B);
+    *loss_dev = L;
+    if (loss_user) *loss_user = L;
+  }
+}
+
+// ------------------------------------------------------------------ thin convolutions (VALU)
+// out[p][co] = epilogue(sum_{tap,ci} w[tap][co][ci] in[p + off(tap)][ci]) with the weight
+// tensor staged as w[tap][co][ci]; DGRAD stages the flipped transpose of the forward
+// weights (input gradient of the forward layer) and multiplies by (mask > 0).
+template <int CIN, int COUT, class TIN, class TOUT, bool DGRAD, bool RELU>
+__global__ __launch_bounds__(256) void k_conv_small(const TIN* in, const bf16* wt, const bf16* bias,
+                                                    const bf16* mask, TOUT* out, int H, int W) {
+  __shared__ float wl[9 * COUT * CIN];
+  __shared__ float bl[COUT];
+  for (int e = threadIdx.x; e < 9 * COUT * CIN; e += 256) {
+    int t = e / (COUT * CIN), r = e % (COUT * CIN), co = r / CIN, ci = r % CIN;
+    // forward tensor is [d][c][ky][kx] with d = out, c = in of the forward layer
+    float v = DGRAD ? bf2f(wt[(ci * COUT + co) * 9 + (8 - t)]) : bf2f(wt[(co * CIN + ci) * 9 + t]);
+    wl[e] = v;
+  }
+  for (int e = threadIdx.x; e < COUT; e += 256) bl[e] = (!DGRAD && bias) ? bf2f(bias[e]) : 0.f;
+  __syncthreads();
+  const int b = blockIdx.y;
+  const long long HW = (long long)H * W;
+  const long long p = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (p >= HW) return;
+  const int y = (int)(p / W), x = (int)(p % W);
+  float acc[COUT];
+#pragma unroll
+  for (int co = 0; co < COUT; ++co) acc[co] = bl[co];
+  const TIN* inb = in + (size_t)b * HW * CIN;
+#pragma unroll
+  for (int t = 0; t < 9; ++t) {
+    const int yy = y + t / 3 - 1, xx = x + t % 3 - 1;
+    if (yy < 0 || yy >= H || xx < 0 || xx >= W) continue;
+    const TIN* ip = inb + ((long long)yy * W + xx) * CIN;
+#pragma unroll
+    for (int ci = 0; ci < CIN; ++ci) {
+      const float v = to_f(ip[ci]);
+#pragma unroll
+      for (int co = 0; co < COUT; ++co) acc[co] += wl[(t * COUT + co) * CIN + ci] * v;
+    }
+  }
+  TOUT* op = out + ((size_t)b * HW + p) * COUT;
+#pragma unroll
+  for (int co = 0; co < COUT; ++co) {
+    float v = acc[co];
+    if (RELU) v = fmaxf(v, 0.f);
+    if (DGRAD) v = bf2f(mask[((size_t)b * HW + p) * COUT + co]) > 0.f ? v : 0.f;
+    if constexpr (sizeof(TOUT) == 2)
+      op[co] = f2bf(v);
+    else
+      op[co] = v;
+  }
+}
+
+// Partial weight/bias gradients of a thin convolution: per block,
+// part[blk][(t*COUT + d)*CIN + c] = sum over its pixels of dz[p][d] in[p+off(t)][c],
+// part[blk][9*COUT*CIN + d] = sum dz[p][d].
+template <int CIN, int COUT, class TDZ>
+__global__ __launch_bounds__(256) void k_wgrad_small(const bf16* in, const TDZ* dz, float* part,
+                                                     int B, int H, int W) {
+  constexpr int NOUT = 9 * COUT * CIN + COUT;
+  constexpr int PER = (NOUT + 255) / 256;
+  const long long HW = (long long)H * W;
+  const long long total = (long long)B * HW;
+  float acc[PER];
+#pragma unroll
+  for (int i = 0; i < PER; ++i) acc[i] = 0.f;
+  for (long long q = (long long)blockIdx.x * 256; q < total; q += (long long)gridDim.x * 256) {
+    __shared__ float dzl[256 * COUT];
+    __shared__ int pix[256];
+    __syncthreads();
+    {
+      long long qq = q + threadIdx.x;
+      pix[threadIdx.x] = qq < total ? (int)(qq % HW) : -1;
+      for (int d = 0; d < COUT; ++d)
+        dzl[threadIdx.x * COUT + d] = qq < total ? to_f(dz[qq * COUT + d]) : 0.f;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+      const int e = threadIdx.x + 256 * i;
+      if (e >= NOUT) continue;
+      float s = 0.f;
+      if (e < 9 * COUT * CIN) {
+        const int t = e / (COUT * CIN), r = e % (COUT * CIN), d = r / CIN, c = r % CIN;
+        const int dy = t / 3 - 1, dx = t % 3 - 1;
+        for (int k = 0; k < 256; ++k) {
+          const int p = pix[k];
+          if (p < 0) break;
+          const long long qq = q + k;
+          const int bb = (int)(qq / HW);
+          const int y = p / W + dy, x = p % W + dx;
+          if (y < 0 || y >= H || x < 0 || x >= W) continue;
+          s += dzl[k * COUT + d] * bf2f(in[((size_t)bb * HW + (long long)y * W + x) * CIN + c]);
+        }
+      } else {
+        const int d = e - 9 * COUT * CIN;
+        for (int k = 0; k < 256; ++k) s += dzl[k * COUT + d];
+      }
+      acc[i] += s;
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < PER; ++i) {
+    const int e = threadIdx.x + 256 * i;
+    if (e < NOUT) part[(size_t)blockIdx.x * NOUT + e] = acc[i];
+  }
+}
+
+// grad[...] = sum over blocks of the partials (fixed order).  Partial element
+// e = (t*COUT + d)*CIN + c maps to the torch layout (d*CIN + c)*ntap + t; the
+// trailing COUT elements are bias gradients.
+__global__ void k_wgrad_reduce(const float* part, int nblk, int ntap, int cout, int cin,
+                               float* gw, float* gb) {
+  const int nw = ntap * cout * cin;
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= nw + cout) return;
+  const int stride = nw + cout;
+  float s = 0.f;
+  for (int k = 0; k < nblk; ++k) s += part[(size_t)k * stride + e];
+  if (e < nw) {
+    const int t = e / (cout * cin), r = e % (cout * cin), d = r / cin, c = r % cin;
+    gw[(d * cin + c) * ntap + t] = s;
+  } else {
+    gb[e - nw] = s;
+  }
+}
+
+// ------------------------------------------------------------------ MFMA convolutions
+// 3x3 convolution C -> C on a 64 x 4 pixel tile (one row per wavefront) as an
+// implicit GEMM: M = 16 pixels, N = 16 channels, K = 32 input channels of one
+// tap per v_mfma_f32_16x16x32_bf16.  Forward: bias + ReLU epilogue.  DGRAD:
+// flipped-transposed weights, epilogue multiplies by (mask > 0).
+template <int C, bool DGRAD>
+__global__ __launch_bounds__(256) void k_conv_mfma(const bf16* in, const bf16* wt, const bf16* bias,
+                                                   const bf16* mask, bf16* out, int H, int W) {
+  constexpr int TX = 64, TY = 4, LX = TX + 2, LY = TY + 2;
+  constexpr int CP = C + 8;              // padded channel pitch (16 B) against bank conflicts
+  constexpr int NT = C / 16, KS = C / 32;
+  __shared__ __attribute__((aligned(16))) bf16 tin[LY * LX * CP];
+  __shared__ __attribute__((aligned(16))) bf16 wl[9 * C * CP];
+  __shared__ float bl[C];
+  const int tilesx = (W + TX - 1) / TX;
+  const int ox = (blockIdx.x % tilesx) * TX, oy = (blockIdx.x / tilesx) * TY;
+  const int b = blockIdx.y;
+  const long long HW = (long long)H * W;
+  const bf16* inb = in + (size_t)b * HW * C;
+  // weights -> wl[t][n][k]
+  for (int e = threadIdx.x; e < 9 * C * C; e += 256) {
+    const int t = e / (C * C), r = e % (C * C), n = r / C, k = r % C;
+    const bf16 v = DGRAD ? wt[(k * C + n) * 9 + (8 - t)] : wt[(n * C + k) * 9 + t];
+    wl[(t * C + n) * CP + k] = v;
+  }
+  for (int e = threadIdx.x; e < C; e += 256) bl[e] = (!DGRAD) ? bf2f(bias[e]) : 0.f;
+  // input tile with a one-pixel halo, 16-byte chunks
+  constexpr int CH = C / 8;
+  for (int e = threadIdx.x; e < LY * LX * CH; e += 256) {
+    const int pix = e / CH, ch = e % CH;
+    const int ly = pix / LX, lx = pix % LX;
+    const int gy = oy + ly - 1, gx = ox + lx - 1;
+    uint4 v = make_uint4(0, 0, 0, 0);
+    if (gy >= 0 && gy < H && gx >= 0 && gx < W)
+      v = *reinterpret_cast<const uint4*>(inb + ((long long)gy * W + gx) * C + ch * 8);
+    *reinterpret_cast<uint4*>(&tin[pix * CP + ch * 8]) = v;
+  }
+  __syncthreads();
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int li = lane & 15, lg = lane >> 4;
+  floatx4 acc[4][NT];
+#pragma unroll
+  for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt) acc[mt][nt] = floatx4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int t = 0; t < 9; ++t) {
+    const int ky = t / 3, kx = t % 3;
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) {
+      bf16x8 bfr[NT];
+#pragma unroll
+      for (int nt = 0; nt < NT; ++nt)
+        bfr[nt] = __builtin_bit_cast(
+            bf16x8, *reinterpret_cast<const uint4*>(&wl[(t * C + nt * 16 + li) * CP + ks * 32 + lg * 8]));
+#pragma unroll
+      for (int mt = 0; mt < 4; ++mt) {
+        const int lx = mt * 16 + li + kx, ly = wv + ky;
+        const bf16x8 a = __builtin_bit_cast(
+            bf16x8, *reinterpret_cast<const uint4*>(&tin[(ly * LX + lx) * CP + ks * 32 + lg * 8]));
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt)
+          acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bfr[nt], acc[mt][nt], 0, 0, 0);
+      }
+    }
+  }
+  // epilogue: lane holds pixels mt*16 + 4*lg + r (r < 4) of channel nt*16 + li
+  const int y = oy + wv;
+  if (y >= H) return;
+#pragma unroll
+  for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int x = ox + mt * 16 + lg * 4 + r;
+      if (x >= W) continue;
+      const size_t base = ((size_t)b * HW + (long long)y * W + x) * C;
+#pragma unroll
+      for (int nt = 0; nt < NT; ++nt) {
+        const int n = nt * 16 + li;
+        float v = acc[mt][nt][r];
+        if (!DGRAD) v = fmaxf(v + bl[n], 0.f);
+        else v = bf2f(mask[base + n]) > 0.f ? v : 0.f;
+        out[base + n] = f2bf(v);
+      }
+    }
+}
+
+// Weight gradient of a C -> C convolution with NTAP taps (9: 3x3, 1: 1x1):
+// per block partial dW[t][d][c] = sum_p dz[p][d] in[p + off(t)][c] over the
+// block's tiles (persistent loop), as MFMA with K = 32 pixels; plus bias sums.
+template <int C, int NTAP>
+__global__ __launch_bounds__(256) void k_wgrad_mfma(const bf16* in, const bf16* dz, float* part,
+                                                    int B, int H, int W) {
+  constexpr int TX = 64, TY = 4, LX = TX + 2, LY = TY + 2;
+  constexpr int CP = C + 8;
+  constexpr int NT = C / 16;
+  constexpr int NTILE = NTAP * NT * NT;          // 16x16 output tiles
+  constexpr int PERW = (NTILE + 3) / 4;          // per wavefront
+  __shared__ __attribute__((aligned(16))) bf16 tin[LY * LX * CP];
+  __shared__ __attribute__((aligned(16))) bf16 tdz[TY * TX * CP];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int li = lane & 15, lg = lane >> 4;
+  floatx4 acc[PERW];
+#pragma unroll
+  for (int i = 0; i < PERW; ++i) acc[i] = floatx4{0.f, 0.f, 0.f, 0.f};
+  float bacc = 0.f;
+  const int tilesx = (W + TX - 1) / TX, tilesy = (H + TY - 1) / TY;
+  const int ntiles = tilesx * tilesy * B;
+  const long long HW = (long long)H * W;
+  constexpr int CH = C / 8;
+  for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    const int b = tile / (tilesx * tilesy), r0 = tile % (tilesx * tilesy);
+    const int ox = (r0 % tilesx) * TX, oy = (r0 / tilesx) * TY;
+    __syncthreads();
+    for (int e = threadIdx.x; e < LY * LX * CH; e += 256) {
+      const int pix = e / CH, ch = e % CH;
+      const int ly = pix / LX, lx = pix % LX;
+      const int gy = oy + ly - 1, gx = ox + lx - 1;
+      uint4 v = make_uint4(0, 0, 0, 0);
+      if (gy >= 0 && gy < H && gx >= 0 && gx < W)
+        v = *reinterpret_cast<const uint4*>(in + ((size_t)b * HW + (long long)gy * W + gx) * C + ch * 8);
+      *reinterpret_cast<uint4*>(&tin[pix * CP + ch * 8]) = v;
+    }
+    for (int e = threadIdx.x; e < TY * TX * CH; e += 256) {
+      const int pix = e / CH, ch = e % CH;
+      const int gy = oy + pix / TX, gx = ox + pix % TX;
+      uint4 v = make_uint4(0, 0, 0, 0);
+      if (gy < H && gx < W)
+        v = *reinterpret_cast<const uint4*>(dz + ((size_t)b * HW + (long long)gy * W + gx) * C + ch * 8);
+      *reinterpret_cast<uint4*>(&tdz[pix * CP + ch * 8]) = v;
+    }
+    __syncthreads();
+    if (threadIdx.x < C) {
+      float s = 0.f;
+      for (int q = 0; q < TY * TX; ++q) s += bf2f(tdz[q * CP + threadIdx.x]);
+      bacc += s;
+    }
+    // K loop over chunks of 32 pixels
+    for (int chk = 0; chk < TY * TX / 32; ++chk) {
+      const int q0 = chk * 32 + lg * 8;            // this lane's 8 pixels: q0 .. q0+7
+      const int qy = q0 / TX, qx = q0 % TX;        // same row (TX multiple of 8)
+#pragma unroll
+      for (int i = 0; i < PERW; ++i) {
+        const int id = wv + 4 * i;
+        if (id >= NTILE) break;
+        const int t = id / (NT * NT), dt = (id / NT) % NT, ct = id % NT;
+        const int ky = NTAP == 9 ? t / 3 : 1, kx = NTAP == 9 ? t % 3 : 1;
+        bf16 av[8], bv[8];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+          av[e] = tdz[(q0 + e) * CP + dt * 16 + li];
+          bv[e] = tin[((qy + ky) * LX + qx + e + kx) * CP + ct * 16 + li];
+        }
+        bf16x8 a = __builtin_bit_cast(bf16x8, av);
+        bf16x8 bb = __builtin_bit_cast(bf16x8, bv);
+        acc[i] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bb, acc[i], 0, 0, 0);
+      }
+    }
+  }
+  // D[i][j]: lane holds rows (d) 4*lg + r, column (c) li
+  constexpr int STRIDE = NTAP * C * C + C;
+  float* pb = part + (size_t)blockIdx.x * STRIDE;
+#pragma unroll
+  for (int i = 0; i < PERW; ++i) {
+    const int id = wv + 4 * i;
+    if (id >= NTILE) break;
+    const int t = id / (NT * NT), dt = (id / NT) % NT, ct = id % NT;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int d = dt * 16 + lg * 4 + r, c = ct * 16 + li;
+      pb[(t * C + d) * C + c] = acc[i][r];
+    }
+  }
+  if (threadIdx.x < C) pb[NTAP * C * C + threadIdx.x] = bacc;
+}
+
+// ------------------------------------------------------------------ spectral layer
+// S[k][j] = sin((k+1) pi (j+1) / (n+1)): the slowest sine modes (DST-I basis).
+__global__ void k_basis(float* S, int M, int n) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= M * n) return;
+  const int k = e / n, j = e % n;
+  S[e] = (float)sin((double)(k + 1) * M_PI * (double)(j + 1) / (double)(n + 1));
+}
+
+// T[b][i][l][c] = sum_j Sx[l][j] in[b][i][j][c]  (one block per image row)
+template <int C>
+__global__ __launch_bounds__(256) void k_spec_rows(const bf16* in, const float* Sx, float* T, int H,
+                                                   int W, int M) {
+  __shared__ float xs[64 * C];
+  __shared__ float ss[32 * 64];
+  const int row = blockIdx.x;             // b*H + i
+  const bf16* ip = in + (size_t)row * W * C;
+  const int npair = M * C;
+  float acc[8];                                   // up to 8 (l, c) pairs per thread
+#pragma unroll
+  for (int i = 0; i < 8; ++i) acc[i] = 0.f;
+  for (int j0 = 0; j0 < W; j0 += 64) {
+    const int nj = min(64, W - j0);
+    __syncthreads();
+    for (int e = threadIdx.x; e < nj * C; e += 256) xs[e] = bf2f(ip[(size_t)j0 * C + e]);
+    for (int e = threadIdx.x; e < M * 64; e += 256) {
+      const int l = e / 64, jj = e % 64;
+      ss[e] = jj < nj ? Sx[(size_t)l * W + j0 + jj] : 0.f;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      const int pr = threadIdx.x + 256 * i;
+      if (pr >= npair) break;
+      const int l = pr / C, c = pr % C;
+      float s = 0.f;
+      for (int jj = 0; jj < nj; ++jj) s += ss[l * 64 + jj] * xs[jj * C + c];
+      acc[i] += s;
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+    const int pr = threadIdx.x + 256 * i;
+    if (pr >= npair) break;
+    T[(size_t)row * npair + pr] = acc[i];
+  }
+}
+
+// X[b][k][l][c] = scale * sum_i Sy[k][i] T[b][i][l][c]  (thread per (b, l, c))
+__global__ __launch_bounds__(256) void k_spec_cols(const float* T, const float* Sy, float* X, int B,
+                                                   int H, int M, int C, float scale) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  const int LC = M * C;
+  if (e >= B * LC) return;
+  const int b = e / LC, lc = e % LC;
+  float acc[32];
+#pragma unroll
+  for (int k = 0; k < 32; ++k) acc[k] = 0.f;
+  const float* tp = T + (size_t)b * H * LC + lc;
+  for (int i = 0; i < H; ++i) {
+    const float v = tp[(size_t)i * LC];
+#pragma unroll
+    for (int k = 0; k < 32; ++k)
+      if (k < M) acc[k] += Sy[(size_t)k * H + i] * v;
+  }
+#pragma unroll
+  for (int k = 0; k < 32; ++k)
+    if (k < M) X[((size_t)b * M + k) * LC + lc] = scale * acc[k];
+}
+
+// per-mode channel mixing: Y[b][k][l][n] = sum_m w[k][l][n][m] X[b][k][l][m]
+// (forward, n = out, m = in) or the transpose w[k][l][m][n] (input gradient).
+template <bool TRANS>
+__global__ void k_spec_mix(const float* X, const bf16* wk, float* Y, int B, int M, int C) {
+  const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (long long)B * M * M * C) return;
+  const int n = (int)(e % C);
+  const long long bkl = e / C;
+  const int kl = (int)(bkl % (M * M));
+  const float* xp = X + bkl * C;
+  const bf16* wp = wk + (size_t)kl * C * C;
+  float s = 0.f;
+  for (int m = 0; m < C; ++m) s += bf2f(TRANS ? wp[m * C + n] : wp[n * C + m]) * xp[m];
+  Y[e] = s;
+}
+
+// dWk[k][l][d][c] = sum_b dY[b][k][l][d] X[b][k][l][c]
+__global__ void k_spec_dwk(const float* dY, const float* X, float* gwk, int B, int M, int C) {
+  const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long long total = (long long)M * M * C * C;
+  if (e >= total) return;
+  const int c = (int)(e % C), d = (int)((e / C) % C);
+  const long long kl = e / ((long long)C * C);
+  float s = 0.f;
+  for (int b = 0; b < B; ++b) {
+    const long long base = ((long long)b * M * M + kl) * C;
+    s += dY[base + d] * X[base + c];
+  }
+  gwk[e] = s;
+}
+
+// Z[b][i][l][n] = alpha * sum_k Sy[k][i] Y[b][k][l][n]
+__global__ void k_spec_inv_cols(const float* Y, const float* Sy, float* Z, int B, int H, int M,
+                                int C, float alpha) {
+  const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long long LC = (long long)M * C;
+  if (e >= (long long)B * H * LC) return;
+  const long long lc = e % LC;
+  const long long bi = e / LC;
+  const int i = (int)(bi % H), b = (int)(bi / H);
+  float s = 0.f;
+  for (int k = 0; k < M; ++k) s += Sy[(size_t)k * H + i] * Y[((size_t)b * M + k) * LC + lc];
+  Z[e] = alpha * s;
+}
+
+// out[b][i][j][n] = epi( sum_m W1'[n][m] in[b][i][j][m] (+ bias[n])
+//                        + beta * sum_l Sx[l][j] Z[b][i][l][n] )
+// forward: W1' = W1, bias, ReLU -> a3.  BWD: W1' = W1^T, no bias, mask (a2 > 0).
+template <int C, bool BWD>
+__global__ __launch_bounds__(256) void k_spec_out(const bf16* in, const bf16* w1, const bf16* bias,
+                                                  const float* Z, const float* Sx, const bf16* mask,
+                                                  bf16* out, int H, int W, int M, float beta) {
+  __shared__ float wl[C * C];
+  __shared__ float zl[32 * C];
+  __shared__ float sl[32 * 64];
+  __shared__ float bl[C];
+  const int tilesx = (W + 63) / 64;
+  const int row = blockIdx.x / tilesx;            // b*H + i
+  const int j0 = (blockIdx.x % tilesx) * 64;
+  for (int e = threadIdx.x; e < C * C; e += 256) {
+    const int n = e / C, m = e % C;
+    wl[e] = bf2f(BWD ? w1[m * C + n] : w1[n * C + m]);
+  }
+  for (int e = threadIdx.x; e < M * C; e += 256) zl[e] = Z[(size_t)row * M * C + e];
+  for (int e = threadIdx.x; e < M * 64; e += 256) {
+    const int l = e / 64, jj = e % 64;
+    sl[e] = (j0 + jj < W) ? Sx[(size_t)l * W + j0 + jj] : 0.f;
+  }
+  for (int e = threadIdx.x; e < C; e += 256) bl[e] = (!BWD) ? bf2f(bias[e]) : 0.f;
+  __syncthreads();
+  constexpr int NG = 4, PER = C / NG;             // 4 threads per pixel, C/4 channels each
+  const int jj = threadIdx.x / NG, g = threadIdx.x % NG;
+  const int j = j0 + jj;
+  if (j >= W) return;
+  const size_t base = ((size_t)row * W + j) * C;
+  float xin[C];
+#pragma unroll
+  for (int m = 0; m < C; ++m) xin[m] = bf2f(in[base + m]);
+#pragma unroll
+  for (int q = 0; q < PER; ++q) {
+    const int n = g * PER + q;
+    float s = bl[n];
+#pragma unroll
+    for (int m = 0; m < C; ++m) s += wl[n * C + m] * xin[m];
+    float sp = 0.f;
+    for (int l = 0; l < M; ++l) sp += sl[l * 64 + jj] * zl[l * C + n];
+    s += beta * sp;
+    if (!BWD) s = fmaxf(s, 0.f);
+    else s = bf2f(mask[base + n]) > 0.f ? s : 0.f;
+    out[base + n] = f2bf(s);
+  }
+}
+
+// ------------------------------------------------------------------ parameters
+__device__ __forceinline__ uint64_t splitmix64(uint64_t x) {
+  x += 0x9E3779B97F4A7C15ull;
+  x = (x ^ (x >> 30)) * 0xBF58476D1CE4E5B9ull;
+  x = (x ^ (x >> 27)) * 0x94D049BB133111EBull;
+  return x ^ (x >> 31);
+}
+
+struct InitSpec {
+  int64_t off[kNumTensors + 1];
+  int64_t size[kNumTensors];
+  float bound[kNumTensors];    // 0 -> zero tensor
+};
+
+// He-uniform weights from a counter-based generator (SplitMix64 of seed and
+// element index), zero biases and output layer, zero Adam state and grads.
+__global__ void k_init_params(float* master, float* grad, float* m, float* v, bf16* bf,
+                              long long* step, InitSpec spec, int64_t P, uint64_t seed) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e == 0) *step = 0;
+  if (e >= P) return;
+  int t = 0;
+  while (t < kNumTensors - 1 && e >= spec.off[t + 1]) ++t;
+  float val = 0.f;
+  if (spec.bound[t] > 0.f && e < spec.off[t] + spec.size[t]) {
+    const uint64_t r = splitmix64(seed * 0x100000001B3ull + (uint64_t)e);
+    const double u = (double)(r >> 11) * (1.0 / 9007199254740992.0);   // [0, 1)
+    val = (float)((2.0 * u - 1.0) * spec.bound[t]);
+  }
+  master[e] = val;
+  grad[e] = 0.f;
+  m[e] = 0.f;
+  v[e] = 0.f;
+  bf[e] = f2bf(val);
+}
+
+__global__ void k_refresh(const float* master, float* grad, float* m, float* v, bf16* bf,
+                          long long* step, int64_t P) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e == 0) *step = 0;
+  if (e >= P) return;
+  grad[e] = 0.f;
+  m[e] = 0.f;
+  v[e] = 0.f;
+  bf[e] = f2bf(master[e]);
+}
+
+__global__ void k_zero_u32(unsigned int* p) {
+  if (threadIdx.x == 0) *p = 0u;
+}
+
+__global__ void k_step_inc(long long* step) {
+  if (threadIdx.x == 0) *step += 1;
+}
+
+// Adam (Kingma & Ba) with bias correction on the FP32 master weights; the BF16
+// working copy is refreshed in the same pass.
+__global__ void k_adam(float* master, const float* grad, float* m, float* v, bf16* bf,
+                       const long long* step, int64_t P, float lr, float b1, float b2, float eps) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= P) return;
+  const double t = (double)*step;
+  const float c1 = (float)(1.0 - pow((double)b1, t));
+  const float c2 = (float)(1.0 - pow((double)b2, t));
+  const float g = grad[e];
+  const float mm = b1 * m[e] + (1.f - b1) * g;
+  const float vv = b2 * v[e] + (1.f - b2) * g * g;
+  m[e] = mm;
+  v[e] = vv;
+  const float p = master[e] - lr * (mm / c1) / (sqrtf(vv / c2) + eps);
+  master[e] = p;
+  bf[e] = f2bf(p);
+}
+
+// ------------------------------------------------------------------ host helpers
+inline int cdiv(long long a, long long b) { return (int)((a + b - 1) / b); }
+
+struct Net {
+  Dims d;
+  ParamLayout pl;
+  WsLayout wl;
+  char* params;
+  char* ws;
+  const bf16* bfw(int t) const { return (const bf16*)(params + pl.bf) + pl.off[t]; }
+  float* grad(int t) const { return (float*)(params + pl.grad) + pl.off[t]; }
+  template <class T>
+  T* w(size_t off) const { return (T*)(ws + off); }
+};
+
+template <int C>
+void forward(const Net& n, const Ptrs& f, const Ptrs& u, hipStream_t s) {
+  const Dims& d = n.d;
+  const long long HW = d.HW;
+  bf16* x0 = n.w<bf16>(n.wl.x0);
+  bf16* a[5];
+  for (int i = 0; i < 5; ++i) a[i] = n.w<bf16>(n.wl.act[i]);
+  float* Sx = n.w<float>(n.wl.Sx);
+  float* Sy = n.w<float>(n.wl.Sy);
+  double* sv = n.w<double>(n.wl.s);
+  k_basis<<<cdiv((long long)d.M * d.W, 256), 256, 0, s>>>(Sx, d.M, d.W);
+  k_basis<<<cdiv((long long)d.M * d.H, 256), 256, 0, s>>>(Sy, d.M, d.H);
+  k_rms<<<d.B, 256, 0, s>>>(f, HW, sv);
+  k_norm_in<<<dim3(cdiv(HW, 256), d.B), 256, 0, s>>>(f, u, sv, x0, HW);
+  // L1, L2
+  k_conv_small<2, C, bf16, bf16, false, true><<<dim3(cdiv(HW, 256), d.B), 256, 0, s>>>(
+      x0, n.bfw(T_C1W), n.bfw(T_C1B), nullptr, a[0], d.H, d.W);
+  const int ctiles = cdiv(d.W, 64) * cdiv(d.H, 4);
+  k_conv_mfma<C, false><<<dim3(ctiles, d.B), 256, 0, s>>>(a[0], n.bfw(T_C2W), n.bfw(T_C2B), nullptr,
+                                                          a[1], d.H, d.W);
+  // L3 spectral
+  float* T = n.w<float>(n.wl.T);
+  float* X = n.w<float>(n.wl.X);
+  float* Y = n.w<float>(n.wl.Y);
+  float* Z = n.w<float>(n.wl.Z);
+  k_spec_rows<C><<<d.B * d.H, 256, 0, s>>>(a[1], Sx, T, d.H, d.W, d.M);
+  k_spec_cols<<<cdiv((long long)d.B * d.M * C, 256), 256, 0, s>>>(T, Sy, X, d.B, d.H, d.M, C, 1.f);
+  k_spec_mix<false><<<cdiv((long long)d.B * d.M * d.M * C, 256), 256, 0, s>>>(X, n.bfw(T_SWK), Y,
+                                                                               d.B, d.M, C);
+  k_spec_inv_cols<<<cdiv((long long)d.B * d.H * d.M * C, 256), 256, 0, s>>>(
+      Y, Sy, Z, d.B, d.H, d.M, C, (float)(2.0 / (d.H + 1)));
+  k_spec_out<C, false><<<d.B * d.H * cdiv(d.W, 64), 256, 0, s>>>(
+      a[1], n.bfw(T_SW1), n.bfw(T_SB), Z, Sx, nullptr, a[2], d.H, d.W, d.M,
+      (float)(2.0 / (d.W + 1)));
+  // L4, L5, L6
+  k_conv_mfma<C, false><<<dim3(ctiles, d.B), 256, 0, s>>>(a[2], n.bfw(T_C4W), n.bfw(T_C4B), nullptr,
+                                                          a[3], d.H, d.W);
+  k_conv_mfma<C, false><<<dim3(ctiles, d.B), 256, 0, s>>>(a[3], n.bfw(T_C5W), n.bfw(T_C5B), nullptr,
+                                                          a[4], d.H, d.W);
+  k_conv_small<C, 1, bf16, float, false, false><<<dim3(cdiv(HW, 256), d.B), 256, 0, s>>>(
+      a[4], n.bfw(T_C6W), n.bfw(T_C6B), nullptr, n.w<float>(n.wl.out), d.H, d.W);
+}
+
+template <int C>
+void wgrad_conv(const Net& n, const bf16* in, const bf16* dz, int tw, int tb, hipStream_t s,
+                int ntap) {
+  const Dims& d = n.d;
+  float* part = n.w<float>(n.wl.part);
+  const int G = n.wl.wgrad_blocks;
+  if (ntap == 9)
+    k_wgrad_mfma<C, 9><<<G, 256, 0, s>>>(in, dz, part, d.B, d.H, d.W);
+  else
+    k_wgrad_mfma<C, 1><<<G, 256, 0, s>>>(in, dz, part, d.B, d.H, d.W);
+  const int nout = ntap * C * C + C;
+  k_wgrad_reduce<<<cdiv(nout, 256), 256, 0, s>>>(part, G, ntap, C, C, n.grad(tw), n.grad(tb));
+}
+
+template <int C>
+void train(const Net& n, const Ptrs& f, const Ptrs& up, const Ptrs& ut, float* loss,
+           const guess_net_cfg* cfg, hipStream_t s) {
+  forward<C>(n, f, up, s);
+  const Dims& d = n.d;
+  const long long HW = d.HW;
+  bf16* x0 = n.w<bf16>(n.wl.x0);
+  bf16* a[5];
+  for (int i = 0; i < 5; ++i) a[i] = n.w<bf16>(n.wl.act[i]);
+  bf16* dz[2] = {n.w<bf16>(n.wl.dz[0]), n.w<bf16>(n.wl.dz[1])};
+  float* out = n.w<float>(n.wl.out);
+  float* dout = n.w<float>(n.wl.dout);
+  double* sv = n.w<double>(n.wl.s);
+  float* Sx = n.w<float>(n.wl.Sx);
+  float* Sy = n.w<float>(n.wl.Sy);
+  float* part = n.w<float>(n.wl.part);
+  const int G = n.wl.wgrad_blocks;
+  // loss
+  double* lpart = n.w<double>(n.wl.loss) + 8;
+  unsigned int* ticket = (unsigned int*)n.w<double>(n.wl.loss);
+  float* ldev = (float*)(n.w<double>(n.wl.loss) + 1);
+  {
+    const int nb = cdiv(HW, 1024);
+    if ((long long)nb * d.B > 4000) throw ArgError{MLG_ERR_ARG, "grid too large for the loss kernel"};
+    k_zero_u32<<<1, 64, 0, s>>>(ticket);
+    k_loss<<<dim3(nb, d.B), 256, 0, s>>>(out, ut, up, sv, dout, lpart, ticket, ldev, loss, HW, d.B);
+  }
+  const int ctiles = cdiv(d.W, 64) * cdiv(d.H, 4);
+  // L6: weight grad from (a5, dout); input grad masked by a5 -> dz5
+  k_wgrad_small<C, 1, float><<<G, 256, 0, s>>>(a[4], dout, part, d.B, d.H, d.W);
+  k_wgrad_reduce<<<cdiv(9 * C + 1, 256), 256, 0, s>>>(part, G, 9, 1, C, n.grad(T_C6W), n.grad(T_C6B));
+  k_conv_small<1, C, float, bf16, true, false><<<dim3(cdiv(HW, 256), d.B), 256, 0, s>>>(
+      dout, n.bfw(T_C6W), nullptr, a[4], dz[0], d.H, d.W);
+  // L5
+  wgrad_conv<C>(n, a[3], dz[0], T_C5W, T_C5B, s, 9);
+  k_conv_mfma<C, true><<<dim3(ctiles, d.B), 256, 0, s>>>(dz[0], n.bfw(T_C5W), nullptr, a[3], dz[1],
+                                                         d.H, d.W);
+  // L4
+  wgrad_conv<C>(n, a[2], dz[1], T_C4W, T_C4B, s, 9);
+  k_conv_mfma<C, true><<<dim3(ctiles, d.B), 256, 0, s>>>(dz[1], n.bfw(T_C4W), nullptr, a[2], dz[0],
+                                                         d.H, d.W);
+  // L3 spectral: dz3 = dz[0]
+  wgrad_conv<C>(n, a[1], dz[0], T_SW1, T_SB, s, 1);
+  float* T = n.w<float>(n.wl.T);
+  float* X = n.w<float>(n.wl.X);
+  float* dY = n.w<float>(n.wl.Y);
+  float* dX = n.w<float>(n.wl.dX);
+  float* Z = n.w<float>(n.wl.Z);
+  const float nrm = (float)((2.0 / (d.H + 1)) * (2.0 / (d.W + 1)));
+  k_spec_rows<C><<<d.B * d.H, 256, 0, s>>>(dz[0], Sx, T, d.H, d.W, d.M);
+  k_spec_cols<<<cdiv((long long)d.B * d.M * C, 256), 256, 0, s>>>(T, Sy, dY, d.B, d.H, d.M, C, nrm);
+  k_spec_dwk<<<cdiv((long long)d.M * d.M * C * C, 256), 256, 0, s>>>(dY, X, n.grad(T_SWK), d.B, d.M, C);
+  k_spec_mix<true><<<cdiv((long long)d.B * d.M * d.M * C, 256), 256, 0, s>>>(dY, n.bfw(T_SWK), dX,
+                                                                              d.B, d.M, C);
+  k_spec_inv_cols<<<cdiv((long long)d.B * d.H * d.M * C, 256), 256, 0, s>>>(dX, Sy, Z, d.B, d.H, d.M,
+                                                                             C, 1.f);
+  k_spec_out<C, true><<<d.B * d.H * cdiv(d.W, 64), 256, 0, s>>>(dz[0], n.bfw(T_SW1), nullptr, Z, Sx,
+                                                                a[1], dz[1], d.H, d.W, d.M, 1.f);
+  // L2: dz2 = dz[1]
+  wgrad_conv<C>(n, a[0], dz[1], T_C2W, T_C2B, s, 9);
+  k_conv_mfma<C, true><<<dim3(ctiles, d.B), 256, 0, s>>>(dz[1], n.bfw(T_C2W), nullptr, a[0], dz[0],
+                                                         d.H, d.W);
+  // L1: dz1 = dz[0]
+  k_wgrad_small<2, C, bf16><<<G, 256, 0, s>>>(x0, dz[0], part, d.B, d.H, d.W);
+  k_wgrad_reduce<<<cdiv(9 * C * 2 + C, 256), 256, 0, s>>>(part, G, 9, C, 2, n.grad(T_C1W),
+                                                          n.grad(T_C1B));
+  // Adam
+  long long* step = (long long*)(n.params + n.pl.step);
+  k_step_inc<<<1, 64, 0, s>>>(step);
+  k_adam<<<cdiv(n.pl.P, 256), 256, 0, s>>>((float*)(n.params + n.pl.master),
+                                           (const float*)(n.params + n.pl.grad),
+                                           (float*)(n.params + n.pl.m), (float*)(n.params + n.pl.v),
+                                           (bf16*)(n.params + n.pl.bf), step, n.pl.P, cfg->lr,
+                                           cfg->beta1, cfg->beta2, cfg->eps);
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------ entry points
+int64_t net_param_offset(const guess_net_cfg* cfg, int index) {
+  if (index < 0 || index > kNumTensors) throw ArgError{MLG_ERR_ARG, "tensor index out of range"};
+  return param_layout(cfg).off[index];
+}
+
+int64_t net_param_count(const guess_net_cfg* cfg) { return param_layout(cfg).P; }
+
+size_t net_param_bytes(const guess_net_cfg* cfg) { return param_layout(cfg).total; }
+
+size_t net_workspace_bytes(const guess_net_cfg* cfg, const mlg_grid* grid, int batch, int train) {
+  Dims d = check_grid_net(cfg, grid, batch);
+  return ws_layout(d, train != 0).total;
+}
+
+int net_init(const guess_net_cfg* cfg, void* params, hipStream_t s) {
+  ParamLayout pl = param_layout(cfg);
+  if (!params) throw ArgError{MLG_ERR_ARG, "params is NULL"};
+  InitSpec spec{};
+  for (int i = 0; i <= kNumTensors; ++i) spec.off[i] = pl.off[i];
+  int64_t sz[kNumTensors];
+  tensor_sizes(cfg, sz);
+  const float C = (float)cfg->channels;
+  const float fan[kNumTensors] = {18.f, 0, 9 * C, 0, 2 * C, 0, 2 * C, 9 * C, 0, 9 * C, 0, 0, 0};
+  for (int i = 0; i < kNumTensors; ++i) {
+    spec.bound[i] = fan[i] > 0 ? sqrtf(6.f / fan[i]) : 0.f;
+    spec.size[i] = sz[i];
+  }
+  char* p = (char*)params;
+  k_init_params<<<cdiv(pl.P, 256), 256, 0, s>>>((float*)(p + pl.master), (float*)(p + pl.grad),
+                                                (float*)(p + pl.m), (float*)(p + pl.v),
+                                                (bf16*)(p + pl.bf), (long long*)(p + pl.step), spec,
+                                                pl.P, cfg->seed);
+  MLG_HIP(hipGetLastError());
+  return MLG_OK;
+}
+
+int net_refresh(const guess_net_cfg* cfg, void* params, hipStream_t s) {
+  ParamLayout pl = param_layout(cfg);
+  if (!params) throw ArgError{MLG_ERR_ARG, "params is NULL"};
+  char* p = (char*)params;
+  k_refresh<<<cdiv(pl.P, 256), 256, 0, s>>>((const float*)(p + pl.master), (float*)(p + pl.grad),
+                                            (float*)(p + pl.m), (float*)(p + pl.v),
+                                            (bf16*)(p + pl.bf), (long long*)(p + pl.step), pl.P);
+  MLG_HIP(hipGetLastError());
+  return MLG_OK;
+}
+
+int net_infer(const guess_net_cfg* cfg, const void* params, const mlg_grid* grid, int batch,
+              const double* f, const double* u_prev, double* guess, void* ws, size_t ws_bytes,
+              hipStream_t s) {
+  Dims d = check_grid_net(cfg, grid, batch);
+  if (!params || !f || !u_prev || !guess) throw ArgError{MLG_ERR_ARG, "NULL pointer"};
+  WsLayout wl = ws_layout(d, false);
+  if (!ws || ws_bytes < wl.total) throw ArgError{MLG_ERR_WORKSPACE, "network workspace too small"};
+  Net n{d, param_layout(cfg), wl, (char*)params, (char*)ws};
+  Ptrs fp{}, up{};
+  MPtrs gp{};
+  for (int b = 0; b < d.B; ++b) {
+    fp.p[b] = f + (size_t)b * d.HW;
+    up.p[b] = u_prev + (size_t)b * d.HW;
+    gp.p[b] = guess + (size_t)b * d.HW;
+  }
+  if (d.C == 32) forward<32>(n, fp, up, s);
+  else forward<64>(n, fp, up, s);
+  k_guess<<<dim3(cdiv(d.HW, 256), d.B), 256, 0, s>>>(n.w<float>(wl.out), up, n.w<double>(wl.s), gp,
+                                                      d.HW);
+  MLG_HIP(hipGetLastError());
+  return MLG_OK;
+}
+
+int net_train_step(const guess_net_cfg* cfg, void* params, const mlg_grid* grid, int batch,
+                   const double* const* f, const double* const* u_prev,
+                   const double* const* u_target, void* ws, size_t ws_bytes, float* loss,
+                   hipStream_t s) {
+  Dims d = check_grid_net(cfg, grid, batch);
+  if (!params || !f || !u_prev || !u_target) throw ArgError{MLG_ERR_ARG, "NULL pointer"};
+  WsLayout wl = ws_layout(d, true);
+  if (!ws || ws_bytes < wl.total) throw ArgError{MLG_ERR_WORKSPACE, "network workspace too small"};
+  Net n{d, param_layout(cfg), wl, (char*)params, (char*)ws};
+  Ptrs fp{}, up{}, tp{};
+  for (int b = 0; b < d.B; ++b) {
+    if (!f[b] || !u_prev[b] || !u_target[b]) throw ArgError{MLG_ERR_ARG, "NULL sample pointer"};
+    fp.p[b] = f[b];
+    up.p[b] = u_prev[b];
+    tp.p[b] = u_target[b];
+  }
+  if (d.C == 32) train<32>(n, fp, up, tp, loss, cfg, s);
+  else train<64>(n, fp, up, tp, loss, cfg, s);
+  MLG_HIP(hipGetLastError());
+  return MLG_OK;
+}
+
+}  // namespace mlg
