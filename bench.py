@@ -1,0 +1,212 @@
+"""Benchmark: time-to-solution per right-hand side, learned guess vs plain GMRES.
+
+Workload (one GPU): the 512 x 512 zero-Dirichlet Poisson stream with four
+drifting Gaussian sources (sigma 0.03), GMRES(30), relative residual 1e-8.
+One step = one time step of the in-situ method: network guess from
+(f_t, u_{t-1}) -> GMRES(30) with the FP32 Krylov basis and FP64 refinement ->
+one training step of the network on the replay buffer.  `--warmup` steps run
+first (they also train the network in situ), then exactly `--steps` steps are
+timed.  The same right-hand sides are then solved by plain FP64 GMRES(30)
+from a zero guess (the comparison the metric names), and by FP64 GMRES from
+the previous solution.
+
+Printed: one JSON line with the metric, the roofline of the dominant kernel
+(HIP-event timing of its launches in the solve's launch configuration) and
+the CPU oracle timed on a bounded sample on this host.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import statistics
+import sys
+import time
+
+import numpy as np
+import torch
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "time-to-solution per RHS at rel. residual 1e-8: learned guess vs plain GMRES"
+HBM_PEAK_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=100)
+    ap.add_argument("--grid", type=int, default=512)
+    ap.add_argument("--restart", type=int, default=30)
+    ap.add_argument("--rtol", type=float, default=1e-8)
+    ap.add_argument("--seed", type=int, default=4000)
+    ap.add_argument("--cpu-seconds", type=float, default=15.0,
+                    help="budget of the CPU-oracle sample")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-baseline", action="store_true", help="skip the plain-GMRES legs")
+    ap.add_argument("--json-out", default=None)
+    return ap.parse_args()
+
+
+def kernel_roofline(mlg, shape, opts, b, reps=20):
+    """Average launch duration of every solver kernel over one cycle's steps,
+    in the launch configuration of the solve (HIP events on the stream)."""
+    grid = mlg.grid_of(shape)
+    ws = mlg.workspace(mlg.gmres_workspace_bytes(grid, opts))
+    x = torch.zeros_like(b)
+    fixed = mlg.Opts(restart_m=opts.restart_m, precision=opts.precision, rtol=opts.rtol,
+                     fixed_iters=opts.restart_m)
+    mlg.gmres_solve(grid, b, x, fixed, ws)                 # fills the basis of one full cycle
+    scratch = mlg.workspace(mlg.mlg_kernel_bench_scratch_bytes(reps))
+    m = opts.restart_m
+    n = int(np.prod(shape))
+    s = 8 if opts.precision == mlg.MLG_FP64 else 4
+    out = {}
+    for kind, name in mlg.KERNEL_NAMES.items():
+        if kind in (mlg.MLG_K_DOTS, mlg.MLG_K_COEF):
+            steps = range(m + 1)
+        elif kind == mlg.MLG_K_EXTEND:
+            steps = range(m)
+        else:
+            steps = [m]
+        us = [mlg.mlg_kernel_bench(grid, fixed, ws, scratch, kind, j, reps) for j in steps]
+        # algorithmic bytes per launch: what each kernel must move at minimum
+        if kind == mlg.MLG_K_DOTS:
+            byts = [(j + 1) * n * s for j in steps]              # read v_0..v_{j-1}, u_j
+        elif kind == mlg.MLG_K_EXTEND:
+            byts = [(j + 3) * n * s for j in steps]              # read V_{j-1}, u_j; write v_j, u_{j+1}
+        elif kind == mlg.MLG_K_UPDATE:
+            byts = [m * n * s + 2 * n * 8 for _ in steps]        # read V_m, read+write x
+        elif kind == mlg.MLG_K_RESIDUAL:
+            byts = [3 * n * 8 for _ in steps]                    # read x, b; write r
+        else:
+            byts = [0 for _ in steps]                            # one-workgroup reduction
+        out[name] = {"launches_per_cycle": len(us), "avg_us": statistics.fmean(us),
+                     "avg_bytes": statistics.fmean(byts), "cycle_us": sum(us)}
+    del ws, scratch
+    return out
+
+
+def cpu_baseline(shape, m, rtol, f0, plain_iters, budget_s):
+    """The FP64 CPU oracle (single thread) on a bounded sample: a fixed number
+    of Arnoldi steps on the first RHS, projected to the plain-GMRES iteration
+    count of the same RHS."""
+    from oracle import gmres as og
+    t0 = time.perf_counter()
+    og.gmres(f0, m=m, fixed_iters=m)                       # one cycle, to size the sample
+    per_cycle = time.perf_counter() - t0
+    cycles = max(1, int(budget_s / max(per_cycle, 1e-6)))
+    k = cycles * m
+    t0 = time.perf_counter()
+    og.gmres(f0, m=m, fixed_iters=k)
+    dt = time.perf_counter() - t0
+    per_iter = dt / k
+    return {"value": per_iter * plain_iters, "unit": "s/RHS", "cores": 1, "kind": "oracle",
+            "sample": f"{k} FP64 CGS2 GMRES({m}) Arnoldi steps of RHS 0 on {shape[0]}x{shape[1]} "
+                      f"({dt:.1f} s, {per_iter * 1e3:.2f} ms/step), projected to the "
+                      f"{plain_iters:.0f} steps plain GMRES needs per RHS"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus N > 1 is not supported"}))
+        sys.exit(2)
+    import paper_2103_10975_amd as mlg
+    from paper_2103_10975_amd.stream import StreamSolver
+    from synthetic import DriftingGaussians
+
+    torch.cuda.set_device(0)
+    shape = (args.grid, args.grid)
+    gen = DriftingGaussians(shape, 4, 0.03, seed=args.seed)
+    total = args.warmup + args.steps
+    fields = [torch.from_numpy(gen.field(t)).cuda() for t in range(total)]
+
+    learned = StreamSolver(shape, guess="learned", restart_m=args.restart, rtol=args.rtol,
+                           precision=mlg.MLG_FP32_IR, seed=args.seed, time_train=False)
+    for t in range(args.warmup):
+        learned.step(fields[t])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for t in range(args.warmup, total):
+        learned.step(fields[t])
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    timed = learned.records[args.warmup:]
+    tos_learned = statistics.fmean(r.tos for r in timed)
+
+    result = {
+        "metric": METRIC, "value": tos_learned, "unit": "s/RHS", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": 1e3 * elapsed / args.steps,
+        "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64 (f32 Krylov basis) + bf16 network",
+        "data": "synthetic",
+        "config": {"workload": f"2D 5-point Poisson {shape[0]}x{shape[1]}, 4 drifting Gaussian "
+                               f"sources (sigma 0.03), GMRES({args.restart}), rtol {args.rtol}, "
+                               "learned guess + FP32-basis refinement vs plain FP64 GMRES",
+                   "grid": list(shape), "restart_m": args.restart, "rtol": args.rtol,
+                   "seed": args.seed},
+        "learned": {"tos_mean": tos_learned, "tos_median": statistics.median(r.tos for r in timed),
+                    "iters_mean": statistics.fmean(r.iters for r in timed),
+                    "relres_init_mean": statistics.fmean(r.relres_init for r in timed),
+                    "E_k_mean": statistics.fmean(r.relres_first_cycle for r in timed),
+                    "guess_kinds": sorted(set(r.guess for r in timed))},
+    }
+
+    if not args.no_baseline:
+        legs = {}
+        for name, guess, prec in [("plain_fp64_zero", "zero", mlg.MLG_FP64),
+                                  ("fp64_prev", "prev", mlg.MLG_FP64)]:
+            sv = StreamSolver(shape, guess=guess, restart_m=args.restart, rtol=args.rtol,
+                              precision=prec)
+            if guess == "prev":
+                sv.u_prev.copy_(_solution_before(fields, args, mlg))
+                sv.t = 1
+            for t in range(args.warmup, total):
+                sv.step(fields[t])
+            legs[name] = {"tos_mean": statistics.fmean(r.tos for r in sv.records),
+                          "iters_mean": statistics.fmean(r.iters for r in sv.records)}
+            del sv
+        result["baselines"] = legs
+        result["speedup_vs_plain"] = legs["plain_fp64_zero"]["tos_mean"] / tos_learned
+        result["speedup_vs_prev_fp64"] = legs["fp64_prev"]["tos_mean"] / tos_learned
+
+    # roofline of the dominant kernel of the learned-guess solve
+    kr = kernel_roofline(mlg, shape, learned.opts, fields[0])
+    dom = max((k for k in kr if kr[k]["avg_bytes"] > 0), key=lambda k: kr[k]["cycle_us"])
+    d = kr[dom]
+    achieved = d["avg_bytes"] / (d["avg_us"] * 1e-6) / 1e9
+    result["roofline"] = {"kernel": dom, "bound": "hbm", "achieved": achieved,
+                          "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                          "traffic": None, "avg_us": d["avg_us"], "avg_bytes": d["avg_bytes"]}
+    result["kernels"] = {k: {"avg_us": v["avg_us"], "per_cycle": v["launches_per_cycle"],
+                             "GB/s": v["avg_bytes"] / v["avg_us"] / 1e3}
+                         for k, v in kr.items()}
+
+    if not args.no_cpu:
+        plain_iters = (result.get("baselines", {}).get("plain_fp64_zero", {}).get("iters_mean")
+                       or result["learned"]["iters_mean"])
+        result["cpu_baseline"] = cpu_baseline(shape, args.restart, args.rtol,
+                                              fields[args.warmup].cpu().numpy(), plain_iters,
+                                              args.cpu_seconds)
+    line = json.dumps(result)
+    print(line, flush=True)
+    if args.json_out:
+        with open(args.json_out, "w") as fh:
+            fh.write(line + "\n")
+
+
+def _solution_before(fields, args, mlg):
+    """u_{warmup-1} for the previous-solution leg: solved afresh in FP64."""
+    grid = mlg.grid_of(fields[0].shape)
+    opts = mlg.Opts(restart_m=args.restart, rtol=args.rtol)
+    ws = mlg.workspace(mlg.gmres_workspace_bytes(grid, opts))
+    x = torch.zeros_like(fields[0])
+    mlg.gmres_solve(grid, fields[args.warmup - 1], x, opts, ws)
+    return x
+
+
+if __name__ == "__main__":
+    main()

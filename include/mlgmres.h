@@ -150,16 +150,19 @@ int mlg_apply_operator(const mlg_grid* grid, const double* u, double* y, void* s
  * Kernel timing (measurement support).  Times `reps` back-to-back launches of
  * one solver kernel, in the launch configuration gmres_solve uses, with HIP
  * events on `stream`, and returns the average duration in microseconds.
+ * Kernels of one Arnoldi step j: MLG_K_DOTS (w = A u_j and the block dot
+ * products), MLG_K_COEF (one-workgroup sum, Hessenberg column, Givens),
+ * MLG_K_EXTEND (new basis vector v_j and direction u_{j+1}); once per cycle:
+ * MLG_K_UPDATE (x += V y) and MLG_K_RESIDUAL (r = b - A x).
  *   ws       the workspace of a finished gmres_solve with the same grid and
- *            opts (its basis and coefficients are the kernel inputs; only the
- *            reduction partials, the residual buffer and, for MLG_K_PROJ3 and
- *            MLG_K_UPDATE, basis vector step+1 or x are overwritten).
+ *            opts (its basis and coefficients are the kernel inputs; the
+ *            reduction partials, the residual buffer, and for MLG_K_EXTEND /
+ *            MLG_K_UPDATE basis vector `step` / x are overwritten).
  *   scratch  >= mlg_kernel_bench_scratch_bytes(reps) bytes: one private copy
  *            of the solver state per launch, so every launch does full work.
- *   kind     MLG_K_PROJ1 .. MLG_K_RESIDUAL; step: Arnoldi index j (0..m-1,
- *            0..m-2 for MLG_K_PROJ3).
+ *   step     Arnoldi index j: 0..m (0..m-1 for MLG_K_EXTEND).
  */
-enum { MLG_K_PROJ1 = 0, MLG_K_PROJ2 = 1, MLG_K_PROJ3 = 2, MLG_K_UPDATE = 3, MLG_K_RESIDUAL = 4 };
+enum { MLG_K_DOTS = 0, MLG_K_COEF = 1, MLG_K_EXTEND = 2, MLG_K_UPDATE = 3, MLG_K_RESIDUAL = 4 };
 size_t mlg_kernel_bench_scratch_bytes(int32_t reps);
 int mlg_kernel_bench(const mlg_grid* grid, const mlg_opts* opts, void* ws, size_t ws_bytes,
                      void* scratch, size_t scratch_bytes, int32_t kind, int32_t step, int32_t reps,

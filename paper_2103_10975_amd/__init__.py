@@ -222,9 +222,9 @@ def mlg_apply_operator(u: torch.Tensor, y: torch.Tensor, stream=None) -> None:
     _check(lib.mlg_apply_operator(ctypes.byref(g), _ptr(u), _ptr(y), _stream(stream)))
 
 
-MLG_K_PROJ1, MLG_K_PROJ2, MLG_K_PROJ3, MLG_K_UPDATE, MLG_K_RESIDUAL = range(5)
-KERNEL_NAMES = {MLG_K_PROJ1: "k_proj1", MLG_K_PROJ2: "k_proj2", MLG_K_PROJ3: "k_proj3",
-                MLG_K_UPDATE: "k_update", MLG_K_RESIDUAL: "k_residual"}
+MLG_K_DOTS, MLG_K_COEF, MLG_K_EXTEND, MLG_K_UPDATE, MLG_K_RESIDUAL = range(5)
+KERNEL_NAMES = {MLG_K_DOTS: "k_dots", MLG_K_COEF: "k_coef", MLG_K_EXTEND: "k_extend",
+                MLG_K_UPDATE: "k_update", MLG_K_RESIDUAL: "k_resid"}
 
 
 def mlg_kernel_bench_scratch_bytes(reps: int) -> int:

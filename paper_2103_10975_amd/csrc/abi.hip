@@ -47,9 +47,7 @@ void mlg_shutdown(void) {
 size_t gmres_workspace_bytes(const mlg_grid* grid, const mlg_opts* opts) {
   size_t out = 0;
   int rc = guarded([&] {
-    check_grid(grid);
-    check_opts(opts, grid->dim);
-    out = plan_layout(*grid, *opts).total;
+    out = solve_workspace_bytes(grid, opts);
     return 0;
   });
   return rc == 0 ? out : 0;

@@ -37,6 +37,7 @@ struct ArgError {
 constexpr int kBlock = 256;         // threads per workgroup for every sweep kernel
 constexpr int kMaxRestart = 64;     // largest supported restart length m
 constexpr int kXcds = 8;            // MI355X: 8 accelerator complex dies
+constexpr int kMaxGrid = 1024;      // workgroups per sweep kernel (4 per CU)
 
 inline size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
@@ -87,52 +88,35 @@ __device__ __forceinline__ float wave_sum_f32(float v) {
   return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63));
 }
 
-// Sum of NV per-thread values over a 256-thread block; thread t < NV gets
-// the block total of value t in out_t (others: 0).  red must hold 4 * NV doubles.
-template <int NV>
-__device__ __forceinline__ void block_sums(const double (&acc)[NV], int nlive, double* red,
-                                           double& out_t) {
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-#pragma unroll
-  for (int k = 0; k < NV; ++k) {
-    if (k < nlive) {
-      double s = wave_sum(acc[k]);
-      if (lane == 0) red[wave * NV + k] = s;
-    }
-  }
-  __syncthreads();
-  out_t = 0.0;
-  if (threadIdx.x < nlive)
-    out_t = ((red[threadIdx.x] + red[NV + threadIdx.x]) + red[2 * NV + threadIdx.x]) +
-            red[3 * NV + threadIdx.x];
-}
-
-// Last-block pattern: every block has stored its partials; the block that
-// takes the final ticket returns true (after an acquire fence) and resets the
-// ticket so the next launch can reuse it.
-__device__ __forceinline__ bool last_block(unsigned int* ticket, int nblocks) {
-  __shared__ int s_last;
-  __threadfence();
-  __syncthreads();
-  if (threadIdx.x == 0) s_last = (atomicAdd(ticket, 1u) == (unsigned)(nblocks - 1));
-  __syncthreads();
-  if (!s_last) return false;
-  __threadfence();
-  if (threadIdx.x == 0) *ticket = 0u;
-  return true;
-}
-
-// Fixed-order reduction of part[col * nblocks + b] over b for cols < ncols;
-// the result of column c lands in out[c].  Wave w handles columns w, w+4, ...
+// Sum of partials part[col * nblocks + b] over b (fixed order) for cols <
+// ncols, by one workgroup of kReduceThreads threads (nblocks <= kMaxGrid).
+// Every lane issues 32 independent loads per round (2 columns x 16 blocks),
+// so the latency of the partials is paid once per round, not once per load.
+constexpr int kReduceThreads = 1024;
 __device__ __forceinline__ void reduce_partials(const double* part, int nblocks, int ncols,
                                                 double* out) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  for (int c = wave; c < ncols; c += 4) {
-    const double* p = part + (size_t)c * nblocks;
-    double s = 0.0;
-    for (int b = lane; b < nblocks; b += 64) s += p[b];
-    s = wave_sum(s);
-    if (lane == 0) out[c] = s;
+  constexpr int NW = kReduceThreads / 64;
+  for (int c0 = wave; c0 < ncols; c0 += 2 * NW) {
+    double v[2][16];
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      const int c = c0 + NW * q;
+#pragma unroll
+      for (int i = 0; i < 16; ++i) {
+        const int b = lane + 64 * i;
+        v[q][i] = (c < ncols && b < nblocks) ? part[(size_t)c * nblocks + b] : 0.0;
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      const int c = c0 + NW * q;
+      double s = 0.0;
+#pragma unroll
+      for (int i = 0; i < 16; i += 4) s += (v[q][i] + v[q][i + 1]) + (v[q][i + 2] + v[q][i + 3]);
+      s = wave_sum(s);
+      if (lane == 0 && c < ncols) out[c] = s;
+    }
   }
   __syncthreads();
 }

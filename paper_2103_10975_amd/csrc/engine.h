@@ -9,20 +9,16 @@ struct TileDesc {
   int tx, ty, tz;
 };
 
-struct Layout {
-  size_t off_ctrl, off_part, off_r, off_V, total;
-};
-
 int tile_count(int dim);
 TileDesc tile_desc(int dim, int idx);
 void check_grid(const mlg_grid* grid);
 void check_opts(const mlg_opts* o, int dim);
-Layout plan_layout(const mlg_grid& gr, const mlg_opts& o);
 int default_tile(const mlg_grid& gr, const mlg_opts& o);
 
-// autotuner cache: best tile index for (grid, opts) or -1
+// tuned tile index for (grid, opts), or -1 when the tuner has no entry
 int autotune_lookup(const mlg_grid& gr, const mlg_opts& o);
 
+size_t solve_workspace_bytes(const mlg_grid* grid, const mlg_opts* opts);
 int solve(const mlg_grid* grid, const double* b, double* x, const mlg_opts* opts, void* ws,
           size_t ws_bytes, mlg_stats* stats, hipStream_t stream);
 int apply_operator(const mlg_grid* grid, const double* u, double* y, hipStream_t stream);

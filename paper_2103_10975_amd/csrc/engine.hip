@@ -1,0 +1,684 @@
+// Host engine of restarted GMRES(m) for one or many systems: workspace plan,
+// job tables, kernel dispatch over the tile table, per-cycle HIP graphs and
+// the host polling loop.  gmres_solve is the batched engine with one system
+// and one right-hand side.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "batched.h"
+#include "engine.h"
+#include "gmres_kernels.h"
+
+namespace mlg {
+
+// ------------------------------------------------------------------ tiles
+// Tile shapes (points per workgroup; 256 threads each).  2D tiles are 64 or
+// 128 points wide so that one wavefront reads a contiguous 512 B (FP64) row
+// segment of every basis vector.
+static const TileDesc kTiles2[] = {{64, 16, 1}, {64, 8, 1}, {128, 8, 1}, {64, 4, 1}};
+static const TileDesc kTiles3[] = {{64, 4, 4}, {32, 8, 4}, {64, 2, 4}};
+static constexpr int kNumTiles2 = sizeof(kTiles2) / sizeof(kTiles2[0]);
+static constexpr int kNumTiles3 = sizeof(kTiles3) / sizeof(kTiles3[0]);
+
+int tile_count(int dim) { return dim == 3 ? kNumTiles3 : kNumTiles2; }
+TileDesc tile_desc(int dim, int idx) { return dim == 3 ? kTiles3[idx] : kTiles2[idx]; }
+
+static int ceil_div(int a, int b) { return (a + b - 1) / b; }
+static size_t npoints(const mlg_grid& g) {
+  return (size_t)g.nx * g.ny * (g.dim == 3 ? g.nz : 1);
+}
+
+static Geo make_geo(const mlg_grid& gr, int tile, int nblk) {
+  TileDesc t = tile_desc(gr.dim, tile);
+  Geo g{};
+  g.nx = gr.nx;
+  g.ny = gr.ny;
+  g.nz = gr.dim == 3 ? gr.nz : 1;
+  g.tcx = ceil_div(g.nx, t.tx);
+  g.tcy = ceil_div(g.ny, t.ty);
+  g.tcz = ceil_div(g.nz, t.tz);
+  g.ntiles = g.tcx * g.tcy * g.tcz;
+  g.nblk = std::max(1, std::min({nblk, g.ntiles, kMaxGrid}));
+  double hx = 1.0 / (g.nx + 1.0), hy = 1.0 / (g.ny + 1.0), hz = 1.0 / (g.nz + 1.0);
+  g.cx = 1.0 / (hx * hx);
+  g.cy = 1.0 / (hy * hy);
+  g.cz = 1.0 / (hz * hz);
+  g.n = (long long)g.nx * g.ny * g.nz;
+  g.ldv = (long long)align_up((size_t)g.n, 64);
+  return g;
+}
+
+static int tiles_of(const mlg_grid& gr, int tile) { return make_geo(gr, tile, 1).ntiles; }
+
+void check_grid(const mlg_grid* grid) {
+  if (!grid) throw ArgError{MLG_ERR_ARG, "grid is NULL"};
+  if (grid->dim != 2 && grid->dim != 3) throw ArgError{MLG_ERR_ARG, "grid.dim must be 2 or 3"};
+  if (grid->nx < 1 || grid->ny < 1 || (grid->dim == 3 && grid->nz < 1))
+    throw ArgError{MLG_ERR_ARG, "grid sizes must be >= 1"};
+  long long n = (long long)grid->nx * grid->ny * (grid->dim == 3 ? grid->nz : 1);
+  if (n > (1LL << 31)) throw ArgError{MLG_ERR_ARG, "grid has more than 2^31 points"};
+}
+
+void check_opts(const mlg_opts* o, int dim) {
+  if (!o) throw ArgError{MLG_ERR_ARG, "opts is NULL"};
+  if (o->restart_m < 1 || o->restart_m > kMaxRestart)
+    throw ArgError{MLG_ERR_ARG, "restart_m must be in 1..64"};
+  if (o->precision != MLG_FP64 && o->precision != MLG_FP32_IR)
+    throw ArgError{MLG_ERR_ARG, "precision must be MLG_FP64 or MLG_FP32_IR"};
+  if (!(o->rtol >= 0.0)) throw ArgError{MLG_ERR_ARG, "rtol must be >= 0"};
+  if (o->max_iters < 0 || o->fixed_iters < 0) throw ArgError{MLG_ERR_ARG, "negative iteration cap"};
+  if (o->tile < 0 || o->tile > tile_count(dim)) throw ArgError{MLG_ERR_ARG, "tile index out of range"};
+}
+
+// Default tile when the caller leaves the choice to the library: the tuned
+// entry if there is one, else the widest tile that still yields >= 2
+// workgroups per CU (or the smallest tile).
+int default_tile(const mlg_grid& gr, const mlg_opts& o) {
+  int pick = autotune_lookup(gr, o);
+  if (pick >= 0) return pick;
+  if (gr.dim == 3) return 0;
+  if (tiles_of(gr, 0) >= 512) return 0;
+  if (tiles_of(gr, 1) >= 256) return 1;
+  return 3;
+}
+
+// ------------------------------------------------------------------ plan
+struct Group {
+  int dim, tile;
+  std::vector<int> systems;
+  std::vector<Job> jobs;
+  size_t off_jobs;
+};
+
+struct Plan {
+  int nsys;
+  size_t s;                         // basis element size
+  std::vector<Geo> geo;
+  std::vector<size_t> off_ctrl, off_part, off_r, off_V;
+  std::vector<Group> groups;
+  size_t off_hdr, off_stats, off_desc, off_init, total;
+  int total_rhs;
+};
+
+struct SysInit {                    // per-call fields of a system's control block
+  const double* b0;
+  double* x0;
+  int nrhs, guess;
+  Summary* stats;
+};
+
+static Plan make_plan(int nsys, const mlg_system* sys, const mlg_opts& o) {
+  Plan P{};
+  P.nsys = nsys;
+  P.s = o.precision == MLG_FP64 ? 8 : 4;
+  P.total_rhs = 0;
+  for (int i = 0; i < nsys; ++i) P.total_rhs += sys[i].nrhs;
+  // one group per dimension (all systems of a group share the tile shape)
+  for (int dim = 2; dim <= 3; ++dim) {
+    Group G{};
+    G.dim = dim;
+    int biggest = -1;
+    for (int i = 0; i < nsys; ++i)
+      if (sys[i].grid.dim == dim) {
+        G.systems.push_back(i);
+        if (biggest < 0 || npoints(sys[i].grid) > npoints(sys[biggest].grid)) biggest = i;
+      }
+    if (G.systems.empty()) continue;
+    G.tile = o.tile > 0 ? o.tile - 1 : default_tile(sys[biggest].grid, o);
+    if (G.tile >= tile_count(dim)) G.tile = tile_count(dim) - 1;
+    P.groups.push_back(G);
+  }
+  P.geo.resize(nsys);
+  for (auto& G : P.groups) {
+    long long total_tiles = 0;
+    for (int i : G.systems) total_tiles += tiles_of(sys[i].grid, G.tile);
+    const long long budget = std::min<long long>(total_tiles, kMaxGrid);
+    for (int i : G.systems) {
+      const int t = tiles_of(sys[i].grid, G.tile);
+      const int nb = (int)std::max<long long>(1, (budget * t + total_tiles - 1) / total_tiles);
+      P.geo[i] = make_geo(sys[i].grid, G.tile, nb);
+      const Geo& g = P.geo[i];
+      for (int b = 0; b < g.nblk; ++b) {
+        Job J;
+        J.sys = i;
+        J.t0 = (int)((long long)b * g.ntiles / g.nblk);
+        J.t1 = (int)((long long)(b + 1) * g.ntiles / g.nblk);
+        J.lblk = b;
+        G.jobs.push_back(J);
+      }
+    }
+  }
+  size_t o_ = 0;
+  auto take = [&](size_t bytes) {
+    size_t r = o_;
+    o_ = align_up(o_ + bytes, 256);
+    return r;
+  };
+  P.off_hdr = take(256);
+  P.off_stats = take((size_t)P.total_rhs * sizeof(Summary));
+  P.off_desc = take((size_t)nsys * sizeof(SysDesc));
+  P.off_init = take((size_t)nsys * sizeof(SysInit));
+  for (auto& G : P.groups) G.off_jobs = take(G.jobs.size() * sizeof(Job));
+  P.off_ctrl.resize(nsys);
+  P.off_part.resize(nsys);
+  P.off_r.resize(nsys);
+  P.off_V.resize(nsys);
+  for (int i = 0; i < nsys; ++i) {
+    const Geo& g = P.geo[i];
+    P.off_ctrl[i] = take(sizeof(Ctrl));
+    P.off_part[i] = take((size_t)(2 * kMaxRestart + 2) * g.nblk * 8);
+    P.off_r[i] = take((size_t)g.n * 8);
+    // m basis vectors v_0..v_{m-1}, then the two directions u_j, u_{j+1}
+    P.off_V[i] = take((size_t)(o.restart_m + 2) * g.ldv * P.s);
+  }
+  P.total = o_;
+  return P;
+}
+
+static void check_systems(int nsys, const mlg_system* sys, const mlg_opts* opts) {
+  if (nsys < 1 || !sys) throw ArgError{MLG_ERR_ARG, "need at least one system"};
+  if (!opts) throw ArgError{MLG_ERR_ARG, "opts is NULL"};
+  for (int i = 0; i < nsys; ++i) {
+    check_grid(&sys[i].grid);
+    check_opts(opts, sys[i].grid.dim);
+    if (sys[i].nrhs < 1) throw ArgError{MLG_ERR_ARG, "every system needs nrhs >= 1"};
+    if (sys[i].guess != 0 && sys[i].guess != 1) throw ArgError{MLG_ERR_ARG, "guess must be 0 or 1"};
+  }
+}
+
+size_t workspace_bytes(int nsys, const mlg_system* sys, const mlg_opts* opts) {
+  check_systems(nsys, sys, opts);
+  return make_plan(nsys, sys, *opts).total;
+}
+
+// ------------------------------------------------------------------ dispatch
+template <class T, class TL, int MM>
+static void enqueue_group_step(hipStream_t s, int kind, int nb, const Job* jobs, const SysDesc* sd,
+                               int j) {
+  switch (kind) {
+    case 0: k_begin<TL><<<nb, kBlock, 0, s>>>(jobs, sd); break;
+    case 1: k_resid<TL, true><<<nb, kBlock, 0, s>>>(jobs, sd); break;
+    case 2: k_start<T, TL><<<nb, kBlock, 0, s>>>(jobs, sd); break;
+    case 3: k_dots<T, TL, MM><<<nb, kBlock, 0, s>>>(jobs, sd, j); break;
+    case 4: k_extend<T, TL><<<nb, kBlock, 0, s>>>(jobs, sd, j); break;
+    case 5: k_update<T, TL><<<nb, kBlock, 0, s>>>(jobs, sd); break;
+    default: k_resid<TL, false><<<nb, kBlock, 0, s>>>(jobs, sd); break;
+  }
+}
+enum { G_BEGIN = 0, G_RESID0 = 1, G_START = 2, G_DOTS = 3, G_EXTEND = 4, G_UPDATE = 5, G_RESID = 6 };
+
+using GroupFn = void (*)(hipStream_t, int, int, const Job*, const SysDesc*, int);
+
+template <class T, class TL>
+static GroupFn pick_mm(int m) {
+  if (m <= 16) return &enqueue_group_step<T, TL, 16>;
+  if (m <= 32) return &enqueue_group_step<T, TL, 32>;
+  if (m <= 40) return &enqueue_group_step<T, TL, 40>;
+  return &enqueue_group_step<T, TL, 64>;
+}
+
+template <class TL>
+static GroupFn pick_prec(int prec, int m) {
+  return prec == MLG_FP64 ? pick_mm<double, TL>(m) : pick_mm<float, TL>(m);
+}
+
+#define MLG_TILE_SWITCH(DIM, IDX, EXPR_TL)                      \
+  if (DIM == 2) {                                               \
+    switch (IDX) {                                              \
+      case 0: { using TL = TileT<2, 64, 16, 1>; EXPR_TL; }      \
+      case 1: { using TL = TileT<2, 64, 8, 1>; EXPR_TL; }       \
+      case 2: { using TL = TileT<2, 128, 8, 1>; EXPR_TL; }      \
+      default: { using TL = TileT<2, 64, 4, 1>; EXPR_TL; }      \
+    }                                                           \
+  } else {                                                      \
+    switch (IDX) {                                              \
+      case 0: { using TL = TileT<3, 64, 4, 4>; EXPR_TL; }       \
+      case 1: { using TL = TileT<3, 32, 8, 4>; EXPR_TL; }       \
+      default: { using TL = TileT<3, 64, 2, 4>; EXPR_TL; }      \
+    }                                                           \
+  }
+
+static GroupFn group_fn(int dim, int tile, int prec, int m) {
+  MLG_TILE_SWITCH(dim, tile, return pick_prec<TL>(prec, m));
+}
+
+struct DevPlan {                    // device pointers of a plan inside a workspace
+  char* base;
+  unsigned int* hdr;
+  Summary* stats;
+  SysDesc* desc;
+  SysInit* init;
+  std::vector<const Job*> jobs;
+};
+
+static DevPlan dev_plan(const Plan& P, void* ws) {
+  DevPlan D;
+  D.base = (char*)ws;
+  D.hdr = (unsigned int*)(D.base + P.off_hdr);
+  D.stats = (Summary*)(D.base + P.off_stats);
+  D.desc = (SysDesc*)(D.base + P.off_desc);
+  D.init = (SysInit*)(D.base + P.off_init);
+  for (auto& G : P.groups) D.jobs.push_back((const Job*)(D.base + G.off_jobs));
+  return D;
+}
+
+static void enqueue_cycle(hipStream_t s, const Plan& P, const DevPlan& D, int prec, int m) {
+  std::vector<GroupFn> fns;
+  for (auto& G : P.groups) fns.push_back(group_fn(G.dim, G.tile, prec, m));
+  auto each = [&](int kind, int j) {
+    for (size_t gi = 0; gi < P.groups.size(); ++gi)
+      fns[gi](s, kind, (int)P.groups[gi].jobs.size(), D.jobs[gi], D.desc, j);
+  };
+  const int ns = P.nsys;
+  each(G_BEGIN, 0);
+  each(G_RESID0, 0);
+  k_rsum<true><<<ns, kReduceThreads, 0, s>>>(D.desc);
+  each(G_START, 0);
+  for (int j = 0; j <= m; ++j) {
+    each(G_DOTS, j);
+    k_coef<<<ns, kReduceThreads, 0, s>>>(D.desc, j);
+    if (j < m) each(G_EXTEND, j);
+  }
+  each(G_UPDATE, 0);
+  each(G_RESID, 0);
+  k_rsum<false><<<ns, kReduceThreads, 0, s>>>(D.desc);
+}
+
+// Per-call set-up of every control block (pointers, counts, options), and of
+// the shared counters.  One workgroup per system.
+__global__ void k_setup(const SysInit* init, const SysDesc* sd, unsigned int* hdr, int m,
+                        int fixed, long long limit, double rtol) {
+  const SysDesc* S = sd + blockIdx.x;
+  Ctrl* C = S->C;
+  if (threadIdx.x != 0) return;
+  const SysInit& I = init[blockIdx.x];
+  C->s = Summary{MLG_OK, 0, 0, 0.0, 0.0, 0.0, 0.0};
+  C->phase = PH_INIT;
+  C->cycle_end = 0;
+  C->k = 0;
+  C->m = m;
+  C->fixed = fixed;
+  C->guess = I.guess;
+  C->rhs = 0;
+  C->nrhs = I.nrhs;
+  C->limit = limit;
+  C->rtol = rtol;
+  C->b0 = I.b0;
+  C->x0 = I.x0;
+  C->stats = I.stats;
+  C->done = hdr;
+  if (blockIdx.x == 0) {
+    hdr[0] = 0u;
+    hdr[1] = 0u;
+  }
+}
+
+// ------------------------------------------------------------------ caches
+struct Runtime {
+  std::mutex mu;
+  std::map<std::string, std::pair<hipGraphExec_t, unsigned long long>> graphs;
+  unsigned long long tick = 0;
+  std::map<int, hipStream_t> capture_streams;
+  std::vector<std::pair<void*, size_t>> pinned_free;
+  std::vector<void*> pinned_all;
+};
+
+static Runtime& rt() {
+  static Runtime* r = new Runtime();
+  return *r;
+}
+
+static hipStream_t capture_stream(int dev) {
+  auto& R = rt();
+  auto it = R.capture_streams.find(dev);
+  if (it != R.capture_streams.end()) return it->second;
+  hipStream_t s;
+  MLG_HIP(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+  R.capture_streams[dev] = s;
+  return s;
+}
+
+static std::string plan_key(int dev, const void* ws, const Plan& P, int prec, int m) {
+  std::string k = std::to_string(dev) + ":" + std::to_string((uintptr_t)ws) + ":" +
+                  std::to_string(prec) + ":" + std::to_string(m) + ":" + std::to_string(P.total);
+  for (size_t i = 0; i < P.geo.size(); ++i) {
+    const Geo& g = P.geo[i];
+    k += "|" + std::to_string(g.nx) + "," + std::to_string(g.ny) + "," + std::to_string(g.nz) +
+         "," + std::to_string(g.ntiles) + "," + std::to_string(g.nblk);
+  }
+  for (auto& G : P.groups) k += "#" + std::to_string(G.dim) + "," + std::to_string(G.tile);
+  return k;
+}
+
+// Captured graph of one restart cycle for this workspace and plan.
+static hipGraphExec_t cycle_graph(const std::string& key, int dev, const Plan& P, const DevPlan& D,
+                                  int prec, int m) {
+  auto& R = rt();
+  std::lock_guard<std::mutex> lk(R.mu);
+  auto it = R.graphs.find(key);
+  if (it != R.graphs.end()) {
+    it->second.second = ++R.tick;
+    return it->second.first;
+  }
+  if (R.graphs.size() >= 32) {                      // evict the least recently used
+    auto victim = R.graphs.begin();
+    for (auto i = R.graphs.begin(); i != R.graphs.end(); ++i)
+      if (i->second.second < victim->second.second) victim = i;
+    hipGraphExecDestroy(victim->second.first);
+    R.graphs.erase(victim);
+  }
+  hipStream_t cs = capture_stream(dev);
+  hipGraph_t graph;
+  MLG_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeRelaxed));
+  enqueue_cycle(cs, P, D, prec, m);
+  hipError_t ce = hipStreamEndCapture(cs, &graph);
+  MLG_HIP(ce);
+  hipGraphExec_t exec;
+  hipError_t e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+  hipGraphDestroy(graph);
+  MLG_HIP(e);
+  R.graphs[key] = {exec, ++R.tick};
+  return exec;
+}
+
+// Pinned host staging buffer of at least `bytes` bytes, returned on scope exit.
+struct Pinned {
+  void* p = nullptr;
+  size_t n = 0;
+  explicit Pinned(size_t bytes) {
+    auto& R = rt();
+    std::lock_guard<std::mutex> lk(R.mu);
+    for (size_t i = 0; i < R.pinned_free.size(); ++i)
+      if (R.pinned_free[i].second >= bytes) {
+        p = R.pinned_free[i].first;
+        n = R.pinned_free[i].second;
+        R.pinned_free.erase(R.pinned_free.begin() + i);
+        return;
+      }
+    n = std::max<size_t>(align_up(bytes, 4096), 4096);
+    MLG_HIP(hipHostMalloc(&p, n, hipHostMallocDefault));
+    R.pinned_all.push_back(p);
+  }
+  ~Pinned() {
+    auto& R = rt();
+    std::lock_guard<std::mutex> lk(R.mu);
+    R.pinned_free.push_back({p, n});
+  }
+};
+
+void runtime_shutdown() {
+  auto& R = rt();
+  std::lock_guard<std::mutex> lk(R.mu);
+  for (auto& kv : R.graphs) hipGraphExecDestroy(kv.second.first);
+  R.graphs.clear();
+  for (auto& kv : R.capture_streams) hipStreamDestroy(kv.second);
+  R.capture_streams.clear();
+  for (auto* p : R.pinned_all) hipHostFree(p);
+  R.pinned_all.clear();
+  R.pinned_free.clear();
+}
+
+void batched_shutdown() {}
+
+// ------------------------------------------------------------------ solve
+static void upload_plan(const Plan& P, const DevPlan& D, int nsys, const mlg_system* sys,
+                        const mlg_opts& o, hipStream_t stream, Pinned& stage) {
+  // host images of the descriptors, init records and job tables
+  size_t off = 0;
+  char* h = (char*)stage.p;
+  auto put = [&](const void* src, size_t bytes, void* dst) {
+    std::memcpy(h + off, src, bytes);
+    MLG_HIP(hipMemcpyAsync(dst, h + off, bytes, hipMemcpyHostToDevice, stream));
+    off = align_up(off + bytes, 64);
+  };
+  std::vector<SysDesc> desc(nsys);
+  std::vector<SysInit> init(nsys);
+  int stat_base = 0;
+  for (int i = 0; i < nsys; ++i) {
+    desc[i].g = P.geo[i];
+    desc[i].C = (Ctrl*)(D.base + P.off_ctrl[i]);
+    desc[i].V = D.base + P.off_V[i];
+    desc[i].r = (double*)(D.base + P.off_r[i]);
+    desc[i].part = (double*)(D.base + P.off_part[i]);
+    init[i].b0 = sys[i].b;
+    init[i].x0 = sys[i].x;
+    init[i].nrhs = sys[i].nrhs;
+    init[i].guess = sys[i].guess;
+    init[i].stats = D.stats + stat_base;
+    stat_base += sys[i].nrhs;
+  }
+  put(desc.data(), desc.size() * sizeof(SysDesc), D.desc);
+  put(init.data(), init.size() * sizeof(SysInit), D.init);
+  for (size_t gi = 0; gi < P.groups.size(); ++gi)
+    put(P.groups[gi].jobs.data(), P.groups[gi].jobs.size() * sizeof(Job), (void*)D.jobs[gi]);
+  const long long limit = o.fixed_iters > 0 ? o.fixed_iters
+                          : (o.max_iters > 0 ? o.max_iters : 1000000000LL);
+  k_setup<<<nsys, 64, 0, stream>>>(D.init, D.desc, D.hdr, o.restart_m, o.fixed_iters > 0 ? 1 : 0,
+                                   limit, o.rtol);
+  MLG_HIP(hipGetLastError());
+}
+
+static size_t stage_bytes(const Plan& P) {
+  size_t b = P.nsys * (sizeof(SysDesc) + sizeof(SysInit)) + 256;
+  for (auto& G : P.groups) b += G.jobs.size() * sizeof(Job) + 64;
+  return b;
+}
+
+int batched_solve(int nsys, const mlg_system* sys, const mlg_opts* opts, void* ws, size_t ws_bytes,
+                  mlg_stats* stats, hipStream_t stream) {
+  auto t0 = std::chrono::steady_clock::now();
+  check_systems(nsys, sys, opts);
+  for (int i = 0; i < nsys; ++i)
+    if (!sys[i].b || !sys[i].x) throw ArgError{MLG_ERR_ARG, "b and x must be device pointers"};
+  if (!ws) throw ArgError{MLG_ERR_WORKSPACE, "workspace is NULL"};
+  if ((uintptr_t)ws % 256 != 0) throw ArgError{MLG_ERR_ARG, "workspace must be 256-byte aligned"};
+  const Plan P = make_plan(nsys, sys, *opts);
+  if (ws_bytes < P.total)
+    throw ArgError{MLG_ERR_WORKSPACE, "workspace too small: need " + std::to_string(P.total) +
+                                          " bytes, got " + std::to_string(ws_bytes)};
+  const DevPlan D = dev_plan(P, ws);
+  int dev = 0;
+  MLG_HIP(hipGetDevice(&dev));
+  const int m = opts->restart_m;
+  const long long limit = opts->fixed_iters > 0 ? opts->fixed_iters
+                          : (opts->max_iters > 0 ? opts->max_iters : 1000000000LL);
+
+  Pinned stage(stage_bytes(P));
+  upload_plan(P, D, nsys, sys, *opts, stream, stage);
+  hipGraphExec_t exec = cycle_graph(plan_key(dev, ws, P, opts->precision, m), dev, P, D,
+                                    opts->precision, m);
+  Pinned pin(std::max<size_t>(2 * 256, (size_t)P.total_rhs * sizeof(Summary)));
+  volatile unsigned int* host = (volatile unsigned int*)pin.p;   // [slot * 64]: done count
+  hipEvent_t ev[2];
+  MLG_HIP(hipEventCreateWithFlags(&ev[0], hipEventDisableTiming));
+  MLG_HIP(hipEventCreateWithFlags(&ev[1], hipEventDisableTiming));
+  struct EvGuard {
+    hipEvent_t* e;
+    ~EvGuard() { hipEventDestroy(e[0]); hipEventDestroy(e[1]); }
+  } evg{ev};
+
+  const int poll = opts->poll_cycles > 0 ? opts->poll_cycles : 1;
+  // Every cycle completes at least one Arnoldi step or one right-hand side of
+  // some unfinished system, so this many cycles always suffice; the cap only
+  // guards the host against a solver that stopped making progress.
+  long long rhs_total = P.total_rhs;
+  const long long max_groups = (limit + 2) * rhs_total / poll + 8;
+  int slot = 0, pending = -1;
+  bool done = false;
+  unsigned int last_progress = 0;
+  for (long long grp = 0; grp < max_groups && !done; ++grp) {
+    for (int c = 0; c < poll; ++c) MLG_HIP(hipGraphLaunch(exec, stream));
+    MLG_HIP(hipMemcpyAsync((void*)(host + 64 * slot), D.hdr, 8, hipMemcpyDeviceToHost, stream));
+    MLG_HIP(hipEventRecord(ev[slot], stream));
+    if (pending >= 0) {
+      MLG_HIP(hipEventSynchronize(ev[pending]));
+      if (host[64 * pending] >= (unsigned)nsys) {
+        done = true;
+      } else {
+        const unsigned int prog = host[64 * pending + 1];
+        if (grp > 1 && prog == last_progress)
+          throw HipError{hipErrorUnknown, "solver made no progress in a restart cycle"};
+        last_progress = prog;
+      }
+    }
+    pending = slot;
+    slot ^= 1;
+  }
+  MLG_HIP(hipMemcpyAsync((void*)host, D.hdr, 8, hipMemcpyDeviceToHost, stream));
+  MLG_HIP(hipStreamSynchronize(stream));
+  if (host[0] < (unsigned)nsys) throw HipError{hipErrorUnknown, "solver did not finish"};
+  std::vector<Summary> res(P.total_rhs);
+  MLG_HIP(hipMemcpyAsync(pin.p, D.stats, (size_t)P.total_rhs * sizeof(Summary),
+                         hipMemcpyDeviceToHost, stream));
+  MLG_HIP(hipStreamSynchronize(stream));
+  std::memcpy(res.data(), pin.p, (size_t)P.total_rhs * sizeof(Summary));
+  const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  int worst = MLG_OK;
+  for (int i = 0; i < P.total_rhs; ++i) {
+    const Summary& s = res[i];
+    if (s.status < 0 && (worst >= 0 || s.status < worst)) worst = s.status;
+    else if (worst >= 0 && s.status > worst) worst = s.status;
+    if (stats) {
+      stats[i].status = s.status;
+      stats[i].cycles = s.cycles;
+      stats[i].iters = s.iters;
+      stats[i].relres_init = s.relres_init;
+      stats[i].relres_first_cycle = s.relres_first;
+      stats[i].relres_est = s.relres_est;
+      stats[i].relres_true = s.relres_true;
+      stats[i].seconds = P.total_rhs == 1 ? secs : 0.0;
+    }
+  }
+  return worst;
+}
+
+size_t batched_workspace_bytes(int nsys, const mlg_system* sys, const mlg_opts* opts) {
+  return workspace_bytes(nsys, sys, opts);
+}
+
+static mlg_system single(const mlg_grid* grid, const double* b, double* x) {
+  mlg_system s{};
+  s.grid = *grid;
+  s.nrhs = 1;
+  s.guess = 0;
+  s.b = b;
+  s.x = x;
+  return s;
+}
+
+size_t solve_workspace_bytes(const mlg_grid* grid, const mlg_opts* opts) {
+  check_grid(grid);
+  mlg_system s = single(grid, nullptr, nullptr);
+  return workspace_bytes(1, &s, opts);
+}
+
+int solve(const mlg_grid* grid, const double* b, double* x, const mlg_opts* opts, void* ws,
+          size_t ws_bytes, mlg_stats* stats, hipStream_t stream) {
+  check_grid(grid);
+  if (!b || !x) throw ArgError{MLG_ERR_ARG, "b and x must be device pointers"};
+  mlg_system s = single(grid, b, x);
+  return batched_solve(1, &s, opts, ws, ws_bytes, stats, stream);
+}
+
+// ------------------------------------------------------------------ kernel timing
+template <class T, class TL, int MM>
+static void enqueue_one(hipStream_t s, int kind, int nb, const Job* jobs, const SysDesc* sd, int j) {
+  switch (kind) {
+    case MLG_K_DOTS: k_dots<T, TL, MM><<<nb, kBlock, 0, s>>>(jobs, sd, j); break;
+    case MLG_K_COEF: k_coef<<<1, kReduceThreads, 0, s>>>(sd, j); break;
+    case MLG_K_EXTEND: k_extend<T, TL><<<nb, kBlock, 0, s>>>(jobs, sd, j); break;
+    case MLG_K_UPDATE: k_update<T, TL><<<nb, kBlock, 0, s>>>(jobs, sd); break;
+    default: k_resid<TL, false><<<nb, kBlock, 0, s>>>(jobs, sd); break;
+  }
+}
+
+using OneFn = void (*)(hipStream_t, int, int, const Job*, const SysDesc*, int);
+
+template <class T, class TL>
+static OneFn pick_one_mm(int m) {
+  if (m <= 16) return &enqueue_one<T, TL, 16>;
+  if (m <= 32) return &enqueue_one<T, TL, 32>;
+  if (m <= 40) return &enqueue_one<T, TL, 40>;
+  return &enqueue_one<T, TL, 64>;
+}
+
+template <class TL>
+static OneFn pick_one(int prec, int m) {
+  return prec == MLG_FP64 ? pick_one_mm<double, TL>(m) : pick_one_mm<float, TL>(m);
+}
+
+static OneFn one_fn(int dim, int tile, int prec, int m) {
+  MLG_TILE_SWITCH(dim, tile, return pick_one<TL>(prec, m));
+}
+
+size_t kernel_bench_scratch_bytes(int reps) {
+  return (size_t)reps * (sizeof(Ctrl) + sizeof(SysDesc)) + 512;
+}
+
+double kernel_bench(const mlg_grid* grid, const mlg_opts* opts, void* ws, size_t ws_bytes,
+                    void* scratch, size_t scratch_bytes, int kind, int j, int reps,
+                    hipStream_t stream) {
+  check_grid(grid);
+  check_opts(opts, grid->dim);
+  if (kind < MLG_K_DOTS || kind > MLG_K_RESIDUAL) throw ArgError{MLG_ERR_ARG, "unknown kernel kind"};
+  if (j < 0 || j > opts->restart_m || (kind == MLG_K_EXTEND && j >= opts->restart_m))
+    throw ArgError{MLG_ERR_ARG, "step index out of range"};
+  if (reps < 1 || reps > 4096) throw ArgError{MLG_ERR_ARG, "reps must be in 1..4096"};
+  mlg_system s1 = single(grid, nullptr, nullptr);
+  const Plan P = make_plan(1, &s1, *opts);
+  if (!ws || ws_bytes < P.total) throw ArgError{MLG_ERR_WORKSPACE, "workspace too small"};
+  if (!scratch || scratch_bytes < kernel_bench_scratch_bytes(reps) || (uintptr_t)scratch % 256)
+    throw ArgError{MLG_ERR_WORKSPACE,
+                   "scratch must hold reps control blocks (mlg_kernel_bench_scratch_bytes)"};
+  const DevPlan D = dev_plan(P, ws);
+  Ctrl* copies = (Ctrl*)scratch;
+  SysDesc* descs = (SysDesc*)align_up((uintptr_t)((char*)scratch + (size_t)reps * sizeof(Ctrl)), 256);
+  const Group& G = P.groups[0];
+  OneFn fn = one_fn(G.dim, G.tile, opts->precision, opts->restart_m);
+  const int nb = (int)G.jobs.size();
+  hipEvent_t e0, e1;
+  MLG_HIP(hipEventCreate(&e0));
+  MLG_HIP(hipEventCreate(&e1));
+  struct Gd {
+    hipEvent_t a, b;
+    ~Gd() { hipEventDestroy(a); hipEventDestroy(b); }
+  } guard{e0, e1};
+  k_bench_setup<<<reps, 256, 0, stream>>>(D.desc, descs, copies, reps);
+  fn(stream, kind, nb, D.jobs[0], descs, j);                  // untimed warm-up launch
+  k_bench_setup<<<reps, 256, 0, stream>>>(D.desc, descs, copies, reps);
+  MLG_HIP(hipEventRecord(e0, stream));
+  for (int i = 0; i < reps; ++i) fn(stream, kind, nb, D.jobs[0], descs + i, j);
+  MLG_HIP(hipEventRecord(e1, stream));
+  MLG_HIP(hipGetLastError());
+  MLG_HIP(hipEventSynchronize(e1));
+  float ms = 0.f;
+  MLG_HIP(hipEventElapsedTime(&ms, e0, e1));
+  return 1000.0 * ms / reps;
+}
+
+// ------------------------------------------------------------------ operator
+template <class TL>
+static void enqueue_apply(hipStream_t s, const Geo& g, const double* u, double* y) {
+  k_apply<TL><<<g.nblk, kBlock, 0, s>>>(g, u, y);
+}
+using ApplyFn = void (*)(hipStream_t, const Geo&, const double*, double*);
+static ApplyFn apply_fn(int dim, int tile) { MLG_TILE_SWITCH(dim, tile, return &enqueue_apply<TL>); }
+
+int apply_operator(const mlg_grid* grid, const double* u, double* y, hipStream_t stream) {
+  check_grid(grid);
+  if (!u || !y) throw ArgError{MLG_ERR_ARG, "u and y must be device pointers"};
+  const int tile = grid->dim == 3 ? 0 : 1;
+  const Geo g = make_geo(*grid, tile, kMaxGrid);
+  apply_fn(grid->dim, tile)(stream, g, u, y);
+  MLG_HIP(hipGetLastError());
+  return MLG_OK;
+}
+
+}  // namespace mlg

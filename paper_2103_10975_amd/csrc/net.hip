@@ -18,6 +18,7 @@
 // with 16 outputs per row, bandwidth bound) and the element-wise work run on
 // the vector ALUs.  Activations and gradients are BF16, accumulation FP32,
 // master weights and Adam state FP32.
+#include <algorithm>
 #include <cmath>
 #include <vector>
 
@@ -184,36 +185,35 @@ __global__ void k_guess(const float* out, Ptrs u, const double* s, MPtrs g, long
   g.p[b][p] = u.p[b][p] + (s[b] / kCu) * (double)out[(size_t)b * HW + p];
 }
 
-// loss = (1/B) sum_b |out_b - t_b|^2, t = c_u (u_t - u_prev)/s; dout = (2/B)(out - t)
+// loss = (1/B) sum_b |out_b - t_b|^2, t = c_u (u_t - u_prev)/s; dout = (2/B)(out - t).
+// Per-workgroup partial sums of the squared error; k_loss_sum adds them.
 __global__ __launch_bounds__(256) void k_loss(const float* out, Ptrs ut, Ptrs up, const double* s,
-                                              float* dout, double* part, unsigned int* ticket,
-                                              float* loss_dev, float* loss_user, long long HW,
-                                              int B) {
+                                              float* dout, double* part, long long HW, int B) {
   __shared__ double red[4];
-  const int b = blockIdx.y;
-  const long long p0 = (long long)blockIdx.x * 1024;
   double acc = 0.0;
-  const double inv = kCu / s[b];
-  for (int i = 0; i < 4; ++i) {
-    long long p = p0 + threadIdx.x + 256 * i;
-    if (p < HW) {
-      double t = (ut.p[b][p] - up.p[b][p]) * inv;
-      double diff = (double)out[(size_t)b * HW + p] - t;
-      dout[(size_t)b * HW + p] = (float)(2.0 * diff / B);
-      acc += diff * diff;
-    }
+  const long long total = (long long)B * HW;
+  for (long long e = (long long)blockIdx.x * 256 + threadIdx.x; e < total;
+       e += (long long)gridDim.x * 256) {
+    const int b = (int)(e / HW);
+    const long long p = e % HW;
+    const double t = (ut.p[b][p] - up.p[b][p]) * (kCu / s[b]);
+    const double diff = (double)out[e] - t;
+    dout[e] = (float)(2.0 * diff / B);
+    acc += diff * diff;
   }
   acc = wave_sum(acc);
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
   __syncthreads();
-  const int nblk = gridDim.x * gridDim.y;
-  const int bid = blockIdx.y * gridDim.x + blockIdx.x;
-  if (threadIdx.x == 0) part[bid] = ((red[0] + red[1]) + red[2]) + red[3];
-  if (!last_block(ticket, nblk)) return;
+  if (threadIdx.x == 0) part[blockIdx.x] = ((red[0] + red[1]) + red[2]) + red[3];
+}
+
+__global__ __launch_bounds__(kReduceThreads) void k_loss_sum(const double* part, int nblk,
+                                                            float* loss_dev, float* loss_user,
+                                                            int B) {
   __shared__ double fin[1];
   reduce_partials(part, nblk, 1, fin);
   if (threadIdx.x == 0) {
-    float L = (float)(fin[0] / B);
+    const float L = (float)(fin[0] / B);
     *loss_dev = L;
     if (loss_user) *loss_user = L;
   }
@@ -730,10 +730,6 @@ __global__ void k_refresh(const float* master, float* grad, float* m, float* v, 
   bf[e] = f2bf(master[e]);
 }
 
-__global__ void k_zero_u32(unsigned int* p) {
-  if (threadIdx.x == 0) *p = 0u;
-}
-
 __global__ void k_step_inc(long long* step) {
   if (threadIdx.x == 0) *step += 1;
 }
@@ -848,13 +844,11 @@ void train(const Net& n, const Ptrs& f, const Ptrs& up, const Ptrs& ut, float* l
   const int G = n.wl.wgrad_blocks;
   // loss
   double* lpart = n.w<double>(n.wl.loss) + 8;
-  unsigned int* ticket = (unsigned int*)n.w<double>(n.wl.loss);
-  float* ldev = (float*)(n.w<double>(n.wl.loss) + 1);
+  float* ldev = (float*)n.w<double>(n.wl.loss);
   {
-    const int nb = cdiv(HW, 1024);
-    if ((long long)nb * d.B > 4000) throw ArgError{MLG_ERR_ARG, "grid too large for the loss kernel"};
-    k_zero_u32<<<1, 64, 0, s>>>(ticket);
-    k_loss<<<dim3(nb, d.B), 256, 0, s>>>(out, ut, up, sv, dout, lpart, ticket, ldev, loss, HW, d.B);
+    const int nb = (int)std::min<long long>(kMaxGrid, cdiv((long long)d.B * HW, 1024));
+    k_loss<<<nb, 256, 0, s>>>(out, ut, up, sv, dout, lpart, HW, d.B);
+    k_loss_sum<<<1, kReduceThreads, 0, s>>>(lpart, nb, ldev, loss, d.B);
   }
   const int ctiles = cdiv(d.W, 64) * cdiv(d.H, 4);
   // L6: weight grad from (a5, dout); input grad masked by a5 -> dz5
