@@ -177,12 +177,14 @@ int mlg_tile_shape(int32_t dim, int32_t index, int32_t* tx, int32_t* ty, int32_t
 /*
  * Guess network (the learned initial guess x0 = N(b) of Section 2; a
  * non-local architecture as Section 2.1 asks for).  2D grids only.
- *   inputs (f / s, c_u u_prev / s), s = RMS(f) (1 if f = 0), c_u = 2 pi^2
+ *   inputs (r / s_r, f / s_f): r = f - A u_prev, the FP64 residual of the
+ *      previous solution under the solver's operator A (a fixed first layer),
+ *      s_r = RMS(r), s_f = RMS(f) (a zero scale divides as 1), c_u = 2 pi^2
  *   L1 conv3x3 2->C + ReLU, L2 conv3x3 C->C + ReLU,
  *   L3 spectral: ReLU(W1 x + b + S^-1[W_kl . S[x]_kl]) over the modes x modes
  *      slowest sine modes (S = DST-I basis), per-mode C x C mixing,
  *   L4, L5 conv3x3 C->C + ReLU, L6 conv3x3 C->1;
- *   guess = u_prev + (s / c_u) L6.
+ *   guess = u_prev + (s_r / c_u) L6  (= u_prev when u_prev solves A u = f).
  * Weights and activations are BF16 in the kernels with FP32 accumulation;
  * FP32 master weights and Adam moments (Section 2.3: back-propagation and
  * ADAM) live in the parameter buffer.
@@ -234,8 +236,8 @@ int guess_net_infer(const guess_net_cfg* cfg, const void* params, const mlg_grid
 
 /*
  * One Adam step on L = (1/B) sum_b |out_b - t_b|^2 with out the L6 output and
- * t_b = c_u (u_target_b - u_prev_b) / s_b (Section 2.3 loss, in the network's
- * output units).  f, u_prev, u_target: host arrays of `batch` device pointers
+ * t_b = c_u (u_target_b - u_prev_b) / s_b, s_b = s_r of the sample with 0
+ * replaced by 1 (Section 2.3 loss, in the network's output units).  f, u_prev, u_target: host arrays of `batch` device pointers
  * (samples need not be contiguous).  loss: device float, may be NULL.
  */
 int guess_net_train_step(const guess_net_cfg* cfg, void* params, const mlg_grid* grid,

@@ -10,13 +10,16 @@ dense) without compressing resolution.
 
 The network built here (readings where the paper is silent are listed in the
 design notes of the repository):
-  inputs   (f / s, c_u u_prev / s), s = RMS(f) (s = 1 when f = 0), c_u = 2 pi^2
+  inputs   (r / s_r, f / s_f): r = f - A u_prev, the residual of the previous
+           solution formed in FP64 by the discrete Laplacian A (a fixed first
+           layer), s_r = RMS(r), s_f = RMS(f) (a zero scale is replaced by 1
+           for the division)
   L1 conv3x3 2->C + ReLU;  L2 conv3x3 C->C + ReLU
   L3 spectral: ReLU(W1 x + b + S^-1[W_kl . S[x]_kl]) on the M x M slowest
      sine modes (S = the DST-I basis sin(k pi i/(N+1)), k = 1..M), per-mode
      C x C channel mixing
   L4, L5 conv3x3 C->C + ReLU;  L6 conv3x3 C->1
-  guess = u_prev + (s / c_u) * L6
+  guess = u_prev + (s_r / c_u) * L6, c_u = 2 pi^2
 Convolutions are cross-correlations with zero padding (the Dirichlet zero),
 weights in [out, in, ky, kx] layout.  Everything is float64, NCHW, written
 from the definitions (numpy tensordot is the only library primitive).
@@ -25,16 +28,26 @@ from __future__ import annotations
 
 import numpy as np
 
+from . import gmres as _gmres
+
 C_U = 2.0 * np.pi ** 2
 
 
 # ---------------------------------------------------------------- pieces
+def _rms(a: np.ndarray) -> np.ndarray:
+    return np.sqrt(np.mean(a.reshape(a.shape[0], -1) ** 2, axis=1))
+
+
 def normalise(f: np.ndarray, u_prev: np.ndarray):
-    """Per-sample input scaling.  f, u_prev: [B, H, W] -> x [B, 2, H, W], s [B]."""
-    s = np.sqrt(np.mean(f.reshape(f.shape[0], -1) ** 2, axis=1))
-    s = np.where(s > 0.0, s, 1.0)
-    x = np.stack([f / s[:, None, None], C_U * u_prev / s[:, None, None]], axis=1)
-    return x, s
+    """Network input.  f, u_prev: [B, H, W] -> x [B, 2, H, W], s_r [B] (output
+    scale: RMS of the residual of u_prev) and s_in [B] (its input scale)."""
+    r = np.stack([f[b] - _gmres.apply(u_prev[b]) for b in range(f.shape[0])])
+    s_r = _rms(r)
+    s_in = np.where(s_r > 0.0, s_r, 1.0)
+    s_f = _rms(f)
+    s_f = np.where(s_f > 0.0, s_f, 1.0)
+    x = np.stack([r / s_in[:, None, None], f / s_f[:, None, None]], axis=1)
+    return x, s_r, s_in
 
 
 def conv3x3(x: np.ndarray, w: np.ndarray, b: np.ndarray) -> np.ndarray:
@@ -110,8 +123,8 @@ def spectral_backward(w1, wk, cache, dy):
 # ---------------------------------------------------------------- network
 def forward(params: dict, f: np.ndarray, u_prev: np.ndarray, keep: bool = False):
     """f, u_prev: [B, H, W] float64.  Returns (guess [B, H, W], out [B, H, W]
-    in normalised units, s [B][, cache])."""
-    x0, s = normalise(f, u_prev)
+    in normalised units, s_in [B][, cache])."""
+    x0, s_r, s = normalise(f, u_prev)
     c = {"x0": x0}
     a1 = np.maximum(conv3x3(x0, params["conv1.w"], params["conv1.b"]), 0.0)
     a2 = np.maximum(conv3x3(a1, params["conv2.w"], params["conv2.b"]), 0.0)
@@ -119,7 +132,7 @@ def forward(params: dict, f: np.ndarray, u_prev: np.ndarray, keep: bool = False)
     a4 = np.maximum(conv3x3(a3, params["conv4.w"], params["conv4.b"]), 0.0)
     a5 = np.maximum(conv3x3(a4, params["conv5.w"], params["conv5.b"]), 0.0)
     out = conv3x3(a5, params["conv6.w"], params["conv6.b"])[:, 0]
-    guess = u_prev + (s / C_U)[:, None, None] * out
+    guess = u_prev + (s_r / C_U)[:, None, None] * out
     if keep:
         c.update(a1=a1, a2=a2, a3=a3, a4=a4, a5=a5, spec=sc)
         return guess, out, s, c

@@ -188,17 +188,42 @@ __device__ __forceinline__ Mine mine(const Job* jobs, const SysDesc* sd) {
   return me;
 }
 
-// Block sums of the live slots of acc (slot k lands in column col(k)).
+// Block sums of the live slots of acc (slot k lands in column col(k)); each
+// workgroup writes its own entry of every live partial column.  Per chunk of
+// 16 slots a wavefront transposes its lanes' values through LDS (tr: 64 x 17
+// doubles per wavefront), four lanes sum 16 lanes each in a fixed order and
+// two lane exchanges combine them -- the same sums in every lane, so the
+// result is bitwise reproducible; then the four wavefronts are added.
+constexpr int kTrPitch = 17;
 template <int NV, class Live, class Col>
 __device__ __forceinline__ void store_partials(const double (&acc)[NV], Live live, Col col,
-                                               double* red, double* part, int nblk, int lblk) {
+                                               double* red, double* tr, double* part, int nblk,
+                                               int lblk) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  double* trw = tr + wave * 64 * kTrPitch;
+  const int sl = lane & 15, pq = lane >> 4;
 #pragma unroll
-  for (int k = 0; k < NV; ++k) {
-    if (live(k)) {
-      double s = wave_sum(acc[k]);
-      if (lane == 0) red[wave * NV + k] = s;
-    }
+  for (int k0 = 0; k0 < NV; k0 += 16) {
+    bool any = false;
+#pragma unroll
+    for (int q = 0; q < 16; ++q)
+      if (k0 + q < NV) any = any || live(k0 + q);
+    if (!any) continue;
+#pragma unroll
+    for (int q = 0; q < 16; ++q)
+      if (k0 + q < NV) trw[lane * kTrPitch + q] = acc[k0 + q];
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    double v = 0.0;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) v += trw[(pq * 16 + i) * kTrPitch + sl];
+    v += __shfl_xor(v, 16, 64);
+    v += __shfl_xor(v, 32, 64);
+    if (pq == 0 && k0 + sl < NV && live(k0 + sl)) red[wave * NV + k0 + sl] = v;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
   }
   __syncthreads();
   for (int k = threadIdx.x; k < NV; k += kBlock)
@@ -261,6 +286,7 @@ __global__ __launch_bounds__(kBlock) void k_resid(const Job* jobs, const SysDesc
   if (C->phase != (INIT ? PH_INIT : PH_RUN)) return;
   __shared__ double L[TL::LSZ];
   __shared__ double red[4 * 2];
+  __shared__ double tr[4 * 64 * kTrPitch];
   const Geo& g = me.S->g;
   const double* b = C->b0 + (size_t)C->rhs * g.n;
   const double* x = C->x0 + (size_t)C->rhs * g.n;
@@ -284,7 +310,7 @@ __global__ __launch_bounds__(kBlock) void k_resid(const Job* jobs, const SysDesc
       }
     }
   }
-  store_partials<2>(acc, [](int k) { return INIT || k == 0; }, [](int k) { return k; }, red,
+  store_partials<2>(acc, [](int k) { return INIT || k == 0; }, [](int k) { return k; }, red, tr,
                     me.S->part, g.nblk, me.job.lblk);
 }
 
@@ -382,10 +408,12 @@ __global__ __launch_bounds__(kBlock) void k_dots(const Job* jobs, const SysDesc*
   const Ctrl* C = me.S->C;
   if (C->phase != PH_RUN || C->cycle_end) return;
   constexpr int NV = 2 * MM + 2;     // s in 0..MM-1, t in MM..2MM-1, nu, mu
-  constexpr int KC = 8;
   constexpr int PPT = TL::PPT;
+  constexpr int KC0 = PPT >= 4 ? 8 : (PPT == 2 ? 16 : 32);
+  constexpr int KC = KC0 < MM ? KC0 : MM;
   __shared__ double L[TL::LSZ];
   __shared__ double red[4 * NV];
+  __shared__ double tr[4 * 64 * kTrPitch];
   const Geo& g = me.S->g;
   const T* __restrict__ V = (const T*)me.S->V;
   const T* __restrict__ U = V + (size_t)(C->m + (j & 1)) * g.ldv;
@@ -433,7 +461,7 @@ __global__ __launch_bounds__(kBlock) void k_dots(const Job* jobs, const SysDesc*
   store_partials<NV>(
       acc, [j](int k) { return (k < MM && k < j) || (k >= MM && k < MM + j) || k >= 2 * MM; },
       [j](int k) { return k < MM ? k : (k < 2 * MM ? j + (k - MM) : 2 * j + (k - 2 * MM)); }, red,
-      me.S->part, g.nblk, me.job.lblk);
+      tr, me.S->part, g.nblk, me.job.lblk);
 }
 
 // coef(j): one workgroup per system.  All threads stage the small per-cycle
@@ -458,14 +486,21 @@ __global__ __launch_bounds__(kReduceThreads) void k_coef(const SysDesc* sd, int 
   // Hessenberg columns 0..j-2 (rows <= c+1) for z = Hbar s
   for (int e = threadIdx.x; e < (j > 1 ? (j - 1) * LDH : 0); e += kReduceThreads)
     HuS[e] = C->Hu[e];
-  reduce_partials(S->part, S->g.nblk, 2 * j + 2, fin);
-  if (threadIdx.x >= 64) return;
-  // ---- wavefront 0: lane i owns row i (j <= 64)
+  // wavefront 0's per-row state, loaded together with the partials
   const int lane = threadIdx.x;
+  const bool w0 = threadIdx.x < 64;
+  const int c = j - 1;
+  const double hpi = (w0 && lane < j) ? C->hprev[lane] : 0.0;
+  const double csl = (w0 && lane < c) ? C->cs[lane] : 0.0;
+  const double snl = (w0 && lane < c) ? C->sn[lane] : 0.0;
+  const double gc = (w0 && j > 0) ? C->g[c] : 0.0;
+  const double glane = (w0 && lane < j) ? C->g[lane] : 0.0;
+  reduce_partials(S->part, S->g.nblk, 2 * j + 2, fin);
+  if (!w0) return;
+  // ---- wavefront 0: lane i owns row i (j <= 64)
   const double nu = fin[2 * j], mu = fin[2 * j + 1];
   const double si = lane < j ? fin[lane] : 0.0;
   const double ti = lane < j ? fin[j + lane] : 0.0;
-  const double hpi = lane < j ? C->hprev[lane] : 0.0;
   const double ss = wave_sum(si * si), hh = wave_sum(hpi * hpi), st = wave_sum(si * ti);
   double alpha;
   if (j == 0) {
@@ -473,7 +508,6 @@ __global__ __launch_bounds__(kReduceThreads) void k_coef(const SysDesc* sd, int 
   } else {
     // |u_j - V s|^2 = |u_j|^2 - |s|^2 (V orthonormal)
     alpha = sqrt(fmax(nu - ss, 0.0));
-    const int c = j - 1;
     // Hessenberg column c: first + second projection, subdiagonal alpha
     const double coli = lane < j ? hpi + si : (lane == j ? alpha : 0.0);
     if (lane <= j) {
@@ -481,8 +515,6 @@ __global__ __launch_bounds__(kReduceThreads) void k_coef(const SysDesc* sd, int 
       HuS[(size_t)c * LDH + lane] = coli;
     }
     // rotations G_0..G_{c-1}: carry the running entry down the column
-    const double csl = lane < c ? C->cs[lane] : 0.0;
-    const double snl = lane < c ? C->sn[lane] : 0.0;
     double carry = lane_bcast(coli, 0);
     double rot = 0.0;                 // rotated entry of this lane's row
     for (int i = 0; i < c; ++i) {
@@ -499,7 +531,6 @@ __global__ __launch_bounds__(kReduceThreads) void k_coef(const SysDesc* sd, int 
     }
     if (lane == c) rot = den;
     if (lane <= c) C->R[c * kMaxRestart + lane] = rot;
-    const double gc = C->g[c];
     const double est = fabs(sn * gc);
     const long long iters = C->s.iters + 1;
     // breakdown: the new direction is rounding noise relative to A v_{j-1}
@@ -529,7 +560,7 @@ __global__ __launch_bounds__(kReduceThreads) void k_coef(const SysDesc* sd, int 
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
       __builtin_amdgcn_wave_barrier();
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-      const double gl = lane < j ? (lane == c ? cc * gc : C->g[lane]) : 0.0;
+      const double gl = lane < j ? (lane == c ? cc * gc : glane) : 0.0;
       double accl = 0.0, yl = 0.0;
       for (int i = j - 1; i >= 0; --i) {
         const double yi = lane_bcast((gl - accl) / (lane < j ? Rs[lane * kMaxRestart + lane] : 1.0), i);
@@ -575,29 +606,54 @@ __global__ __launch_bounds__(kBlock) void k_extend(const Job* jobs, const SysDes
   const T* __restrict__ U = V + (size_t)(C->m + (j & 1)) * g.ldv;
   T* __restrict__ Unext = V + (size_t)(C->m + ((j + 1) & 1)) * g.ldv;
   const double ainv = 1.0 / C->alpha;
+  constexpr int PPT = TL::PPT;
+  constexpr int KC = PPT >= 4 ? 8 : (PPT == 2 ? 16 : 32);
   for (int tile = me.job.t0; tile < me.job.t1; ++tile) {
     int ox, oy, oz;
     tile_origin<TL>(g, tile, ox, oy, oz);
     __syncthreads();
     load_tile<TL>(L, U, g, ox, oy, oz);
     __syncthreads();
+    double uu[PPT], ww[PPT], a[PPT], bs[PPT];
+    long long pp[PPT];
+    bool ok[PPT];
 #pragma unroll
-    for (int i = 0; i < TL::PPT; ++i) {
+    for (int i = 0; i < PPT; ++i) {
       auto pr = point<TL>(g, ox, oy, oz, i);
-      if (pr.valid) {
-        const double w = stencil<TL>(L, g, pr.qx, pr.qy, pr.qz);
-        const double u = centre<TL>(L, pr.qx, pr.qy, pr.qz);
-        double a = 0.0, bsum = 0.0;
-        for (int k = 0; k < j; ++k) {
-          const double vk = (double)V[(size_t)k * g.ldv + pr.p];
-          a += vk * sY[k];
-          bsum += vk * cY[k];
-        }
-        const T vj = (T)((u - a) * ainv);
-        V[(size_t)j * g.ldv + pr.p] = vj;
-        Unext[pr.p] = (T)(w * ainv - bsum - cY[j] * (double)vj);
-      }
+      ok[i] = pr.valid;
+      pp[i] = pr.valid ? pr.p : 0;
+      uu[i] = pr.valid ? centre<TL>(L, pr.qx, pr.qy, pr.qz) : 0.0;
+      ww[i] = pr.valid ? stencil<TL>(L, g, pr.qx, pr.qy, pr.qz) : 0.0;
+      a[i] = 0.0;
+      bs[i] = 0.0;
     }
+    // all loads of a chunk are issued before any is used (clamped indices)
+    for (int kc = 0; kc < j; kc += KC) {
+      double v[KC][PPT];
+#pragma unroll
+      for (int q = 0; q < KC; ++q) {
+        const int ks = kc + q < j ? kc + q : j - 1;
+#pragma unroll
+        for (int i = 0; i < PPT; ++i) v[q][i] = (double)V[(size_t)ks * g.ldv + pp[i]];
+      }
+#pragma unroll
+      for (int q = 0; q < KC; ++q)
+        if (kc + q < j) {
+          const double sq = sY[kc + q], cq = cY[kc + q];
+#pragma unroll
+          for (int i = 0; i < PPT; ++i) {
+            a[i] += v[q][i] * sq;
+            bs[i] += v[q][i] * cq;
+          }
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < PPT; ++i)
+      if (ok[i]) {
+        const T vj = (T)((uu[i] - a[i]) * ainv);
+        V[(size_t)j * g.ldv + pp[i]] = vj;
+        Unext[pp[i]] = (T)(ww[i] * ainv - bs[i] - cY[j] * (double)vj);
+      }
   }
 }
 

@@ -11,7 +11,7 @@
 //   a1 = ReLU(conv3x3(x0))          a2 = ReLU(conv3x3(a1))
 //   a3 = ReLU(W1 a2 + b + S^-1[Wk . S[a2]])           (spectral mixing)
 //   a4 = ReLU(conv3x3(a3))          a5 = ReLU(conv3x3(a4))
-//   out = conv3x3(a5) (1 channel, FP32);  guess = u_prev + (s/c_u) out
+//   out = conv3x3(a5) (1 channel, FP32);  guess = u_prev + (s_r/c_u) out
 // The 3x3 convolutions with C -> C channels (forward, input gradient and
 // weight gradient) run on MFMA (v_mfma_f32_16x16x32_bf16) as implicit GEMMs
 // over LDS tiles; the thin layers (2 -> C, C -> 1), the sine transforms (GEMMs
@@ -110,7 +110,7 @@ Dims check_grid_net(const guess_net_cfg* cfg, const mlg_grid* grid, int batch) {
 }
 
 struct WsLayout {
-  size_t s, x0, act[5], out, dout, dz[2], T, X, Y, dX, Z, Sx, Sy, part, loss, total;
+  size_t s, r0, x0, act[5], out, dout, dz[2], T, X, Y, dX, Z, Sx, Sy, part, loss, total;
   int wgrad_blocks;
 };
 
@@ -123,7 +123,8 @@ WsLayout ws_layout(const Dims& d, bool train) {
     return r;
   };
   const size_t act = (size_t)d.B * d.HW * d.C * 2;
-  L.s = take((size_t)d.B * 8);
+  L.s = take((size_t)d.B * 8 * 3);        // s_r (raw), s_in, s_f
+  L.r0 = take((size_t)d.B * d.HW * 8);
   L.x0 = take((size_t)d.B * d.HW * 2 * 2);
   const int nact = train ? 5 : 2;
   for (int i = 0; i < 5; ++i) L.act[i] = i < nact ? take(act) : L.act[i % 2];
@@ -150,8 +151,24 @@ WsLayout ws_layout(const Dims& d, bool train) {
 
 // ------------------------------------------------------------------ small kernels
 
-// s_b = RMS(f_b) (1 when f_b = 0); one block per sample, fixed-order sums.
-__global__ __launch_bounds__(256) void k_rms(Ptrs f, long long n, double* s) {
+// r = f - A u_prev with the solver's operator (zero Dirichlet, h = 1/(N+1)).
+__global__ void k_resid_in(Ptrs f, Ptrs u, double* r, int H, int W) {
+  const int b = blockIdx.y;
+  const long long HW = (long long)H * W;
+  const long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= HW) return;
+  const int y = (int)(p / W), x = (int)(p % W);
+  const double* ub = u.p[b];
+  const double cx = (double)(W + 1) * (W + 1), cy = (double)(H + 1) * (H + 1);
+  const double c = ub[p];
+  const double w = x > 0 ? ub[p - 1] : 0.0, e = x < W - 1 ? ub[p + 1] : 0.0;
+  const double sN = y > 0 ? ub[p - W] : 0.0, nN = y < H - 1 ? ub[p + W] : 0.0;
+  r[(size_t)b * HW + p] = f.p[b][p] - ((2.0 * c - w - e) * cx + (2.0 * c - sN - nN) * cy);
+}
+
+// s = RMS(field_b) (raw) and its division-safe version (1 when 0); one block
+// per sample, fixed-order sums.
+__global__ __launch_bounds__(256) void k_rms(Ptrs f, long long n, double* s_raw, double* s_safe) {
   __shared__ double red[4];
   const double* fb = f.p[blockIdx.x];
   double acc = 0.0;
@@ -162,22 +179,23 @@ __global__ __launch_bounds__(256) void k_rms(Ptrs f, long long n, double* s) {
   if (threadIdx.x == 0) {
     double t = ((red[0] + red[1]) + red[2]) + red[3];
     double r = sqrt(t / (double)n);
-    s[blockIdx.x] = r > 0.0 ? r : 1.0;
+    if (s_raw) s_raw[blockIdx.x] = r;
+    s_safe[blockIdx.x] = r > 0.0 ? r : 1.0;
   }
 }
 
-// x0[b][p] = (f/s, c_u u_prev/s) in BF16 (2 channels).
-__global__ void k_norm_in(Ptrs f, Ptrs u, const double* s, bf16* x0, long long HW) {
+// x0[b][p] = (r/s_in, f/s_f) in BF16 (2 channels).
+__global__ void k_norm_in(const double* r, Ptrs f, const double* s_in, const double* s_f, bf16* x0,
+                          long long HW) {
   const int b = blockIdx.y;
   const long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= HW) return;
-  const double inv = 1.0 / s[b];
   bf16* o = x0 + ((size_t)b * HW + p) * 2;
-  o[0] = f2bf((float)(f.p[b][p] * inv));
-  o[1] = f2bf((float)(kCu * u.p[b][p] * inv));
+  o[0] = f2bf((float)(r[(size_t)b * HW + p] / s_in[b]));
+  o[1] = f2bf((float)(f.p[b][p] / s_f[b]));
 }
 
-// guess = u_prev + (s / c_u) out
+// guess = u_prev + (s_r / c_u) out
 __global__ void k_guess(const float* out, Ptrs u, const double* s, MPtrs g, long long HW) {
   const int b = blockIdx.y;
   const long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -777,11 +795,16 @@ void forward(const Net& n, const Ptrs& f, const Ptrs& u, hipStream_t s) {
   for (int i = 0; i < 5; ++i) a[i] = n.w<bf16>(n.wl.act[i]);
   float* Sx = n.w<float>(n.wl.Sx);
   float* Sy = n.w<float>(n.wl.Sy);
-  double* sv = n.w<double>(n.wl.s);
+  double* sv = n.w<double>(n.wl.s);            // s_r[B], s_in[B], s_f[B]
+  double* r0 = n.w<double>(n.wl.r0);
   k_basis<<<cdiv((long long)d.M * d.W, 256), 256, 0, s>>>(Sx, d.M, d.W);
   k_basis<<<cdiv((long long)d.M * d.H, 256), 256, 0, s>>>(Sy, d.M, d.H);
-  k_rms<<<d.B, 256, 0, s>>>(f, HW, sv);
-  k_norm_in<<<dim3(cdiv(HW, 256), d.B), 256, 0, s>>>(f, u, sv, x0, HW);
+  k_resid_in<<<dim3(cdiv(HW, 256), d.B), 256, 0, s>>>(f, u, r0, d.H, d.W);
+  Ptrs rp{};
+  for (int b = 0; b < d.B; ++b) rp.p[b] = r0 + (size_t)b * HW;
+  k_rms<<<d.B, 256, 0, s>>>(rp, HW, sv, sv + d.B);
+  k_rms<<<d.B, 256, 0, s>>>(f, HW, nullptr, sv + 2 * d.B);
+  k_norm_in<<<dim3(cdiv(HW, 256), d.B), 256, 0, s>>>(r0, f, sv + d.B, sv + 2 * d.B, x0, HW);
   // L1, L2
   k_conv_small<2, C, bf16, bf16, false, true><<<dim3(cdiv(HW, 256), d.B), 256, 0, s>>>(
       x0, n.bfw(T_C1W), n.bfw(T_C1B), nullptr, a[0], d.H, d.W);
@@ -847,7 +870,7 @@ void train(const Net& n, const Ptrs& f, const Ptrs& up, const Ptrs& ut, float* l
   float* ldev = (float*)n.w<double>(n.wl.loss);
   {
     const int nb = (int)std::min<long long>(kMaxGrid, cdiv((long long)d.B * HW, 1024));
-    k_loss<<<nb, 256, 0, s>>>(out, ut, up, sv, dout, lpart, HW, d.B);
+    k_loss<<<nb, 256, 0, s>>>(out, ut, up, sv + d.B, dout, lpart, HW, d.B);
     k_loss_sum<<<1, kReduceThreads, 0, s>>>(lpart, nb, ldev, loss, d.B);
   }
   const int ctiles = cdiv(d.W, 64) * cdiv(d.H, 4);

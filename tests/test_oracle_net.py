@@ -90,11 +90,31 @@ def test_forward_is_homogeneous_in_the_inputs():
     assert np.allclose(g2, 7.5 * g1, rtol=1e-12, atol=1e-14)
 
 
-def test_zero_source_uses_unit_scale():
+def test_zero_source_and_exact_previous_solution():
     p = small_params()
     u = np.random.default_rng(5).standard_normal((1, 6, 6))
     g, out, s = net.forward(p, np.zeros((1, 6, 6)), u)
-    assert s[0] == 1.0 and np.all(np.isfinite(g))
+    assert np.all(np.isfinite(g))
+    # a previous solution that already solves A u = f leaves nothing to correct
+    f = og.apply(u[0])[None]
+    g2, out2, s2 = net.forward(p, f, u)
+    assert s2[0] == 1.0 and np.array_equal(g2, u)
+
+
+def test_input_is_residual_of_previous_solution():
+    """Channel 0 is (f - A u_prev)/RMS, channel 1 is f/RMS: checked against the
+    sparse Kronecker-sum Laplacian."""
+    from test_oracle_gmres import sparse_laplacian
+    rng = np.random.default_rng(8)
+    f = rng.standard_normal((2, 9, 7))
+    u = rng.standard_normal((2, 9, 7))
+    x, s_r, s_in = net.normalise(f, u)
+    A = sparse_laplacian((9, 7))
+    for b in range(2):
+        r = f[b].ravel() - A @ u[b].ravel()
+        assert np.allclose(x[b, 0].ravel(), r / np.sqrt(np.mean(r ** 2)), rtol=1e-12, atol=1e-12)
+        assert np.allclose(x[b, 1], f[b] / np.sqrt(np.mean(f[b] ** 2)), rtol=1e-13)
+        assert abs(s_r[b] - np.sqrt(np.mean(r ** 2))) <= 1e-12 * s_r[b]
 
 
 def test_loss_closed_form():
@@ -142,7 +162,7 @@ def test_gradients_match_torch_autograd():
     L, g = net.loss_and_grads(p, f, u, ut)
     T = {k: torch.tensor(v, requires_grad=True) for k, v in p.items()}
     F = torch.nn.functional
-    x0, s = net.normalise(f, u)
+    x0, _, s = net.normalise(f, u)
     x = torch.tensor(x0)
     a = F.relu(F.conv2d(x, T["conv1.w"], T["conv1.b"], padding=1))
     a = F.relu(F.conv2d(a, T["conv2.w"], T["conv2.b"], padding=1))
