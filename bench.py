@@ -47,10 +47,14 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-baseline", action="store_true", help="skip the plain-GMRES legs")
     ap.add_argument("--json-out", default=None)
+    ap.add_argument("--probe", default=None, metavar="KERNEL",
+                    help="counter-collection run: a 256 MiB device copy (the byte-count "
+                         "calibration) then every step index of KERNEL (dots, extend, update, "
+                         "resid) once, in the learned-guess solve's launch configuration")
     return ap.parse_args()
 
 
-def kernel_roofline(mlg, shape, opts, b, reps=20):
+def kernel_roofline(mlg, shape, opts, b, reps=20, only=None):
     """Average launch duration of every solver kernel over one cycle's steps,
     in the launch configuration of the solve (HIP events on the stream)."""
     grid = mlg.grid_of(shape)
@@ -65,6 +69,8 @@ def kernel_roofline(mlg, shape, opts, b, reps=20):
     s = 8 if opts.precision == mlg.MLG_FP64 else 4
     out = {}
     for kind, name in mlg.KERNEL_NAMES.items():
+        if only is not None and name != only:
+            continue
         if kind in (mlg.MLG_K_DOTS, mlg.MLG_K_COEF):
             steps = range(m + 1)
         elif kind == mlg.MLG_K_EXTEND:
@@ -87,6 +93,30 @@ def kernel_roofline(mlg, shape, opts, b, reps=20):
                      "avg_bytes": statistics.fmean(byts), "cycle_us": sum(us)}
     del ws, scratch
     return out
+
+
+def counter_traffic(kernel, shape, precision_tag, m):
+    """HBM bytes per launch of `kernel` from the committed FETCH_SIZE/WRITE_SIZE
+    summary (profiles/<kernel>_<H>x<W>_traffic.md), or None when there is none
+    for this workload or the kernel sources changed since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", f"{kernel}_{shape[0]}x{shape[1]}_traffic.md")
+    if not os.path.exists(path):
+        return None
+    fields = {}
+    for line in open(path):
+        if ":" in line and not line.startswith(("|", "#", " ")):
+            k, _, v = line.partition(":")
+            fields[k.strip()] = v.strip()
+    if fields.get("workload_key") != f"{kernel} {shape[0]}x{shape[1]} {precision_tag} m{m}":
+        return None
+    h = hashlib.sha256()
+    for src in fields.get("kernel_sources", "").split():
+        with open(os.path.join(ROOT, src), "rb") as fh:
+            h.update(fh.read())
+    if h.hexdigest() != fields.get("kernel_source_sha256"):
+        return None
+    return float(fields["traffic_bytes_per_launch"])
 
 
 def cpu_baseline(shape, m, rtol, f0, plain_iters, budget_s):
@@ -120,6 +150,9 @@ def main():
 
     torch.cuda.set_device(0)
     shape = (args.grid, args.grid)
+    if args.probe:
+        probe(mlg, shape, args)
+        return
     gen = DriftingGaussians(shape, 4, 0.03, seed=args.seed)
     total = args.warmup + args.steps
     fields = [torch.from_numpy(gen.field(t)).cuda() for t in range(total)]
@@ -178,9 +211,11 @@ def main():
     dom = max((k for k in kr if kr[k]["avg_bytes"] > 0), key=lambda k: kr[k]["cycle_us"])
     d = kr[dom]
     achieved = d["avg_bytes"] / (d["avg_us"] * 1e-6) / 1e9
+    tag = "fp64" if learned.opts.precision == mlg.MLG_FP64 else "fp32"
     result["roofline"] = {"kernel": dom, "bound": "hbm", "achieved": achieved,
                           "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                          "traffic": None, "avg_us": d["avg_us"], "avg_bytes": d["avg_bytes"]}
+                          "traffic": counter_traffic(dom, shape, tag, args.restart),
+                          "avg_us": d["avg_us"], "avg_bytes": d["avg_bytes"]}
     result["kernels"] = {k: {"avg_us": v["avg_us"], "per_cycle": v["launches_per_cycle"],
                              "GB/s": v["avg_bytes"] / v["avg_us"] / 1e3}
                          for k, v in kr.items()}
@@ -196,6 +231,24 @@ def main():
     if args.json_out:
         with open(args.json_out, "w") as fh:
             fh.write(line + "\n")
+
+
+def probe(mlg, shape, args):
+    """Launches for hardware-counter runs (no timing is reported)."""
+    from synthetic import DriftingGaussians
+    names = {v.replace("k_", ""): v for v in mlg.KERNEL_NAMES.values()}
+    if args.probe not in names:
+        raise SystemExit(f"--probe takes one of {sorted(names)}")
+    a = torch.ones(64 << 20, dtype=torch.float32, device="cuda")       # 256 MiB
+    for _ in range(3):
+        a.clone()
+    torch.cuda.synchronize()
+    f0 = torch.from_numpy(DriftingGaussians(shape, 4, 0.03, seed=args.seed).field(0)).cuda()
+    opts = mlg.Opts(restart_m=args.restart, rtol=args.rtol, precision=mlg.MLG_FP32_IR)
+    r = kernel_roofline(mlg, shape, opts, f0, reps=1, only=names[args.probe])
+    torch.cuda.synchronize()
+    print(json.dumps({"probe": args.probe, "copy_bytes": 2 * a.numel() * 4,
+                      "avg_bytes": r[names[args.probe]]["avg_bytes"]}), flush=True)
 
 
 def _solution_before(fields, args, mlg):
