@@ -152,17 +152,21 @@ int mlg_apply_operator(const mlg_grid* grid, const double* u, double* y, void* s
  * events on `stream`, and returns the average duration in microseconds.
  * Kernels of one Arnoldi step j: MLG_K_DOTS (w = A u_j and the block dot
  * products), MLG_K_COEF (one-workgroup sum, Hessenberg column, Givens),
- * MLG_K_EXTEND (new basis vector v_j and direction u_{j+1}); once per cycle:
- * MLG_K_UPDATE (x += V y) and MLG_K_RESIDUAL (r = b - A x).
+ * MLG_K_EXTEND (new basis vector v_j and direction u_{j+1}), MLG_K_STEP (the
+ * solver's fused form of MLG_K_EXTEND at j and MLG_K_DOTS at j+1, one sweep
+ * over the basis); once per cycle: MLG_K_UPDATE (x += V y) and
+ * MLG_K_RESIDUAL (r = b - A x).
  *   ws       the workspace of a finished gmres_solve with the same grid and
  *            opts (its basis and coefficients are the kernel inputs; the
- *            reduction partials, the residual buffer, and for MLG_K_EXTEND /
- *            MLG_K_UPDATE basis vector `step` / x are overwritten).
+ *            reduction partials, the residual buffer, and for MLG_K_EXTEND,
+ *            MLG_K_STEP and MLG_K_UPDATE basis vector `step`, the direction
+ *            buffers and x are overwritten).
  *   scratch  >= mlg_kernel_bench_scratch_bytes(reps) bytes: one private copy
  *            of the solver state per launch, so every launch does full work.
- *   step     Arnoldi index j: 0..m (0..m-1 for MLG_K_EXTEND).
+ *   step     Arnoldi index j: 0..m (0..m-1 for MLG_K_EXTEND and MLG_K_STEP).
  */
-enum { MLG_K_DOTS = 0, MLG_K_COEF = 1, MLG_K_EXTEND = 2, MLG_K_UPDATE = 3, MLG_K_RESIDUAL = 4 };
+enum { MLG_K_DOTS = 0, MLG_K_COEF = 1, MLG_K_EXTEND = 2, MLG_K_UPDATE = 3, MLG_K_RESIDUAL = 4,
+       MLG_K_STEP = 5 };
 size_t mlg_kernel_bench_scratch_bytes(int32_t reps);
 int mlg_kernel_bench(const mlg_grid* grid, const mlg_opts* opts, void* ws, size_t ws_bytes,
                      void* scratch, size_t scratch_bytes, int32_t kind, int32_t step, int32_t reps,

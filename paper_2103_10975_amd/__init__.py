@@ -222,9 +222,9 @@ def mlg_apply_operator(u: torch.Tensor, y: torch.Tensor, stream=None) -> None:
     _check(lib.mlg_apply_operator(ctypes.byref(g), _ptr(u), _ptr(y), _stream(stream)))
 
 
-MLG_K_DOTS, MLG_K_COEF, MLG_K_EXTEND, MLG_K_UPDATE, MLG_K_RESIDUAL = range(5)
+MLG_K_DOTS, MLG_K_COEF, MLG_K_EXTEND, MLG_K_UPDATE, MLG_K_RESIDUAL, MLG_K_STEP = range(6)
 KERNEL_NAMES = {MLG_K_DOTS: "k_dots", MLG_K_COEF: "k_coef", MLG_K_EXTEND: "k_extend",
-                MLG_K_UPDATE: "k_update", MLG_K_RESIDUAL: "k_resid"}
+                MLG_K_UPDATE: "k_update", MLG_K_RESIDUAL: "k_resid", MLG_K_STEP: "k_step"}
 
 
 def mlg_kernel_bench_scratch_bytes(reps: int) -> int:

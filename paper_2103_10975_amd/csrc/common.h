@@ -52,6 +52,19 @@ __device__ __forceinline__ int xcd_tile(int b, int count) {
   return base + i;
 }
 
+// ------------------------------------------------------------------ global pointers
+// A pointer the kernel loads from memory (the per-system descriptors) is
+// generic to the compiler, which then emits flat instructions; those also
+// count against the LDS counter, so every LDS wait would wait for them too.
+// Everything the kernels reach through the descriptors is device memory;
+// these casts make those accesses global ones.
+template <class T>
+using gptr = __attribute__((address_space(1))) T*;
+template <class T>
+__device__ __forceinline__ gptr<T> gmem(T* p) {
+  return (gptr<T>)p;
+}
+
 // ------------------------------------------------------------------ wave sums
 // Deterministic full-wavefront FP64 sum with DPP lane moves (no LDS): pairs,
 // quads, half-rows, rows, then the two row broadcasts; lane 63 ends with the
@@ -76,6 +89,50 @@ __device__ __forceinline__ double wave_sum(double v) {
   return __hiloint2double(hi, lo);
 }
 
+// Wavefront reduce-scatters (fixed pairings, so bitwise reproducible): each
+// step sends half of a lane's remaining values to its partner across one lane
+// bit and adds the partner's copy of the half it keeps; once one value is
+// left, the remaining bits are summed outright.
+// rs16: 16 values per lane -> lane l holds the 64-lane sum of value
+// 8*b5 + 4*b4 + 2*b3 + b2 (b = bits of l); lanes differing in bits 0..1 agree.
+__device__ __forceinline__ double rs16(const double (&v)[16]) {
+  const int lane = threadIdx.x & 63;
+  double a[8], b[4], c[2];
+  const bool h5 = lane & 32, h4 = lane & 16, h3 = lane & 8, h2 = lane & 4;
+#pragma unroll
+  for (int i = 0; i < 8; ++i)
+    a[i] = (h5 ? v[8 + i] : v[i]) + __shfl_xor(h5 ? v[i] : v[8 + i], 32, 64);
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+    b[i] = (h4 ? a[4 + i] : a[i]) + __shfl_xor(h4 ? a[i] : a[4 + i], 16, 64);
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+    c[i] = (h3 ? b[2 + i] : b[i]) + dpp_f64<0x128>(h3 ? b[i] : b[2 + i]);   // row_ror:8
+  double d = (h2 ? c[1] : c[0]) + dpp_f64<0x141>(h2 ? c[0] : c[1]);      // row_half_mirror
+  d += dpp_f64<0x4E>(d);
+  d += dpp_f64<0xB1>(d);
+  return d;
+}
+__device__ __forceinline__ int rs16_slot(int lane) {
+  return ((lane >> 5) & 1) * 8 + ((lane >> 4) & 1) * 4 + ((lane >> 3) & 1) * 2 + ((lane >> 2) & 1);
+}
+// rs4: 4 values per lane -> lane l holds the 64-lane sum of value 2*b5 + b4.
+__device__ __forceinline__ double rs4(const double (&v)[4]) {
+  const int lane = threadIdx.x & 63;
+  const bool h5 = lane & 32, h4 = lane & 16;
+  double a[2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+    a[i] = (h5 ? v[2 + i] : v[i]) + __shfl_xor(h5 ? v[i] : v[2 + i], 32, 64);
+  double d = (h4 ? a[1] : a[0]) + __shfl_xor(h4 ? a[0] : a[1], 16, 64);
+  d += dpp_f64<0x128>(d);
+  d += dpp_f64<0x141>(d);
+  d += dpp_f64<0x4E>(d);
+  d += dpp_f64<0xB1>(d);
+  return d;
+}
+__device__ __forceinline__ int rs4_slot(int lane) { return ((lane >> 5) & 1) * 2 + ((lane >> 4) & 1); }
+
 __device__ __forceinline__ float wave_sum_f32(float v) {
   // float variant with the same lane schedule
   int iv;
@@ -93,7 +150,7 @@ __device__ __forceinline__ float wave_sum_f32(float v) {
 // Every lane issues 32 independent loads per round (2 columns x 16 blocks),
 // so the latency of the partials is paid once per round, not once per load.
 constexpr int kReduceThreads = 1024;
-__device__ __forceinline__ void reduce_partials(const double* part, int nblocks, int ncols,
+__device__ __forceinline__ void reduce_partials(gptr<const double> part, int nblocks, int ncols,
                                                 double* out) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   constexpr int NW = kReduceThreads / 64;

@@ -19,10 +19,11 @@
 namespace mlg {
 
 // ------------------------------------------------------------------ tiles
-// Tile shapes (points per workgroup; 256 threads each).  2D tiles are 64 or
-// 128 points wide so that one wavefront reads a contiguous 512 B (FP64) row
-// segment of every basis vector.
-static const TileDesc kTiles2[] = {{64, 16, 1}, {64, 8, 1}, {128, 8, 1}, {64, 4, 1}};
+// Tile shapes (points per workgroup; 256 threads each).  2D tiles are 32 to
+// 128 points wide so that a wavefront reads whole 128 B lines of every basis
+// vector; the narrow tall 32 x 8 tile has the smallest halo ring of the
+// one-point-per-thread tiles, which the fused Arnoldi step recomputes.
+static const TileDesc kTiles2[] = {{64, 16, 1}, {64, 8, 1}, {128, 8, 1}, {64, 4, 1}, {32, 8, 1}};
 static const TileDesc kTiles3[] = {{64, 4, 4}, {32, 8, 4}, {64, 2, 4}};
 static constexpr int kNumTiles2 = sizeof(kTiles2) / sizeof(kTiles2[0]);
 static constexpr int kNumTiles3 = sizeof(kTiles3) / sizeof(kTiles3[0]);
@@ -199,6 +200,19 @@ size_t workspace_bytes(int nsys, const mlg_system* sys, const mlg_opts* opts) {
 }
 
 // ------------------------------------------------------------------ dispatch
+// The fused step keeps the basis values of its points in registers; its
+// register bound follows the step index (so early steps of a cycle run at
+// high occupancy), not the restart length.
+template <class T, class TL>
+static void launch_step(hipStream_t s, int nb, const Job* jobs, const SysDesc* sd, int j) {
+  if (j < 8) k_step<T, TL, 8><<<nb, kBlock, 0, s>>>(jobs, sd, j);
+  else if (j < 16) k_step<T, TL, 16><<<nb, kBlock, 0, s>>>(jobs, sd, j);
+  else if (j < 24) k_step<T, TL, 24><<<nb, kBlock, 0, s>>>(jobs, sd, j);
+  else if (j < 32) k_step<T, TL, 32><<<nb, kBlock, 0, s>>>(jobs, sd, j);
+  else if (j < 40) k_step<T, TL, 40><<<nb, kBlock, 0, s>>>(jobs, sd, j);
+  else k_step<T, TL, 64><<<nb, kBlock, 0, s>>>(jobs, sd, j);
+}
+
 template <class T, class TL, int MM>
 static void enqueue_group_step(hipStream_t s, int kind, int nb, const Job* jobs, const SysDesc* sd,
                                int j) {
@@ -209,10 +223,12 @@ static void enqueue_group_step(hipStream_t s, int kind, int nb, const Job* jobs,
     case 3: k_dots<T, TL, MM><<<nb, kBlock, 0, s>>>(jobs, sd, j); break;
     case 4: k_extend<T, TL><<<nb, kBlock, 0, s>>>(jobs, sd, j); break;
     case 5: k_update<T, TL><<<nb, kBlock, 0, s>>>(jobs, sd); break;
+    case 7: launch_step<T, TL>(s, nb, jobs, sd, j); break;
     default: k_resid<TL, false><<<nb, kBlock, 0, s>>>(jobs, sd); break;
   }
 }
-enum { G_BEGIN = 0, G_RESID0 = 1, G_START = 2, G_DOTS = 3, G_EXTEND = 4, G_UPDATE = 5, G_RESID = 6 };
+enum { G_BEGIN = 0, G_RESID0 = 1, G_START = 2, G_DOTS = 3, G_EXTEND = 4, G_UPDATE = 5, G_RESID = 6,
+       G_STEP = 7 };
 
 using GroupFn = void (*)(hipStream_t, int, int, const Job*, const SysDesc*, int);
 
@@ -235,7 +251,8 @@ static GroupFn pick_prec(int prec, int m) {
       case 0: { using TL = TileT<2, 64, 16, 1>; EXPR_TL; }      \
       case 1: { using TL = TileT<2, 64, 8, 1>; EXPR_TL; }       \
       case 2: { using TL = TileT<2, 128, 8, 1>; EXPR_TL; }      \
-      default: { using TL = TileT<2, 64, 4, 1>; EXPR_TL; }      \
+      case 3: { using TL = TileT<2, 64, 4, 1>; EXPR_TL; }       \
+      default: { using TL = TileT<2, 32, 8, 1>; EXPR_TL; }      \
     }                                                           \
   } else {                                                      \
     switch (IDX) {                                              \
@@ -269,6 +286,12 @@ static DevPlan dev_plan(const Plan& P, void* ws) {
   return D;
 }
 
+// 2D grids take the fused extend + dots step (one basis sweep per Arnoldi
+// step; its recomputed halo ring is small next to the tile).  In 3D the ring
+// of a one-point-per-thread tile is larger than the tile, so 3D grids keep
+// the separate extend and dots sweeps.
+static bool fused_step(int dim) { return dim == 2; }
+
 static void enqueue_cycle(hipStream_t s, const Plan& P, const DevPlan& D, int prec, int m) {
   std::vector<GroupFn> fns;
   for (auto& G : P.groups) fns.push_back(group_fn(G.dim, G.tile, prec, m));
@@ -281,10 +304,19 @@ static void enqueue_cycle(hipStream_t s, const Plan& P, const DevPlan& D, int pr
   each(G_RESID0, 0);
   k_rsum<true><<<ns, kReduceThreads, 0, s>>>(D.desc);
   each(G_START, 0);
-  for (int j = 0; j <= m; ++j) {
-    each(G_DOTS, j);
-    k_coef<<<ns, kReduceThreads, 0, s>>>(D.desc, j);
-    if (j < m) each(G_EXTEND, j);
+  each(G_DOTS, 0);
+  k_coef<<<ns, kReduceThreads, 0, s>>>(D.desc, 0);
+  for (int j = 0; j < m; ++j) {
+    for (size_t gi = 0; gi < P.groups.size(); ++gi) {
+      const int nb = (int)P.groups[gi].jobs.size();
+      if (fused_step(P.groups[gi].dim)) {
+        fns[gi](s, G_STEP, nb, D.jobs[gi], D.desc, j);
+      } else {
+        fns[gi](s, G_EXTEND, nb, D.jobs[gi], D.desc, j);
+        fns[gi](s, G_DOTS, nb, D.jobs[gi], D.desc, j + 1);
+      }
+    }
+    k_coef<<<ns, kReduceThreads, 0, s>>>(D.desc, j + 1);
   }
   each(G_UPDATE, 0);
   each(G_RESID, 0);
@@ -595,6 +627,7 @@ static void enqueue_one(hipStream_t s, int kind, int nb, const Job* jobs, const 
     case MLG_K_COEF: k_coef<<<1, kReduceThreads, 0, s>>>(sd, j); break;
     case MLG_K_EXTEND: k_extend<T, TL><<<nb, kBlock, 0, s>>>(jobs, sd, j); break;
     case MLG_K_UPDATE: k_update<T, TL><<<nb, kBlock, 0, s>>>(jobs, sd); break;
+    case MLG_K_STEP: launch_step<T, TL>(s, nb, jobs, sd, j); break;
     default: k_resid<TL, false><<<nb, kBlock, 0, s>>>(jobs, sd); break;
   }
 }
@@ -627,8 +660,9 @@ double kernel_bench(const mlg_grid* grid, const mlg_opts* opts, void* ws, size_t
                     hipStream_t stream) {
   check_grid(grid);
   check_opts(opts, grid->dim);
-  if (kind < MLG_K_DOTS || kind > MLG_K_RESIDUAL) throw ArgError{MLG_ERR_ARG, "unknown kernel kind"};
-  if (j < 0 || j > opts->restart_m || (kind == MLG_K_EXTEND && j >= opts->restart_m))
+  if (kind < MLG_K_DOTS || kind > MLG_K_STEP) throw ArgError{MLG_ERR_ARG, "unknown kernel kind"};
+  if (j < 0 || j > opts->restart_m ||
+      ((kind == MLG_K_EXTEND || kind == MLG_K_STEP) && j >= opts->restart_m))
     throw ArgError{MLG_ERR_ARG, "step index out of range"};
   if (reps < 1 || reps > 4096) throw ArgError{MLG_ERR_ARG, "reps must be in 1..4096"};
   mlg_system s1 = single(grid, nullptr, nullptr);

@@ -140,40 +140,110 @@ __device__ __forceinline__ PointRef<TL> point(const Geo& g, int ox, int oy, int 
   return pr;
 }
 
-// Stage the tile of `src` plus a one-point halo into LDS as FP64; points
+// A tile with a RING-point halo as laid out in LDS.
+template <class TL, int RING>
+struct Halo {
+  static constexpr int X = TL::TX + 2 * RING, Y = TL::TY + 2 * RING;
+  static constexpr int Z = TL::DIM == 3 ? TL::TZ + 2 * RING : 1;
+  static constexpr int SZ = X * Y * Z;
+  // LDS index of tile-relative point (qx, qy, qz), which may lie in the halo
+  static __device__ __forceinline__ int at(int qx, int qy, int qz) {
+    return ((TL::DIM == 3 ? qz + RING : 0) * Y + (qy + RING)) * X + (qx + RING);
+  }
+};
+
+// Stage the tile of `src` plus a RING-point halo into LDS as FP64; points
 // outside the grid read as 0 (the Dirichlet boundary).
-template <class TL, class S>
-__device__ __forceinline__ void load_tile(double* L, const S* __restrict__ src, const Geo& g,
-                                          int ox, int oy, int oz) {
-  for (int e = threadIdx.x; e < TL::LSZ; e += kBlock) {
-    int lx = e % TL::LX;
-    int r = e / TL::LX;
-    int ly = r % TL::LY;
-    int lz = r / TL::LY;
-    int gx = ox + lx - 1, gy = oy + ly - 1, gz = TL::DIM == 3 ? oz + lz - 1 : 0;
-    double v = 0.0;
-    if (gx >= 0 && gx < g.nx && gy >= 0 && gy < g.ny && gz >= 0 && gz < g.nz)
-      v = (double)src[((long long)gz * g.ny + gy) * g.nx + gx];
-    L[e] = v;
+template <class TL, int RING = 1, class P>
+__device__ __forceinline__ void load_tile(double* L, P src, const Geo& g, int ox, int oy, int oz) {
+  using H = Halo<TL, RING>;
+  constexpr int NPT = (H::SZ + kBlock - 1) / kBlock;
+  // every load is issued unconditionally (out-of-grid points read element 0
+  // and are replaced by 0 afterwards), so no branch separates them
+  double v[NPT];
+  bool in[NPT];
+#pragma unroll
+  for (int h = 0; h < NPT; ++h) {
+    const int e = threadIdx.x + kBlock * h;
+    const int lx = e % H::X, r = e / H::X, ly = r % H::Y, lz = r / H::Y;
+    const int gx = ox + lx - RING, gy = oy + ly - RING, gz = TL::DIM == 3 ? oz + lz - RING : 0;
+    in[h] = e < H::SZ && gx >= 0 && gx < g.nx && gy >= 0 && gy < g.ny && gz >= 0 && gz < g.nz;
+    v[h] = (double)src[in[h] ? ((long long)gz * g.ny + gy) * g.nx + gx : 0];
+  }
+#pragma unroll
+  for (int h = 0; h < NPT; ++h) {
+    const int e = threadIdx.x + kBlock * h;
+    if (e < H::SZ) L[e] = in[h] ? v[h] : 0.0;
   }
 }
 
-// (A u) at a tile point from the LDS tile: sum over axes of
-// (2 u - u_minus - u_plus) / h^2.
-template <class TL>
-__device__ __forceinline__ double stencil(const double* L, const Geo& g, int qx, int qy, int qz) {
-  const int i = ((TL::DIM == 3 ? qz + 1 : 0) * TL::LY + (qy + 1)) * TL::LX + (qx + 1);
+// (A u) at LDS index i of a staged tile with row pitch px and plane pitch pxy:
+// sum over axes of (2 u - u_minus - u_plus) / h^2.  Not contracted, so that
+// every evaluation of the same point rounds identically wherever it is
+// inlined (the fused step recomputes halo points that another workgroup owns).
+template <int DIM>
+__device__ __forceinline__ double stencil_at(const double* L, const Geo& g, int i, int px, int pxy) {
+#pragma clang fp contract(off)
   const double c = L[i];
-  double a = (2.0 * c - L[i - 1] - L[i + 1]) * g.cx + (2.0 * c - L[i - TL::LX] - L[i + TL::LX]) * g.cy;
-  if (TL::DIM == 3)
-    a += (2.0 * c - L[i - TL::LX * TL::LY] - L[i + TL::LX * TL::LY]) * g.cz;
+  double a = (2.0 * c - L[i - 1] - L[i + 1]) * g.cx + (2.0 * c - L[i - px] - L[i + px]) * g.cy;
+  if (DIM == 3) a += (2.0 * c - L[i - pxy] - L[i + pxy]) * g.cz;
   return a;
 }
 
-// The tile point itself from the LDS tile.
+// (A u) at a tile point from a tile staged with a one-point halo.
+template <class TL>
+__device__ __forceinline__ double stencil(const double* L, const Geo& g, int qx, int qy, int qz) {
+  using H = Halo<TL, 1>;
+  return stencil_at<TL::DIM>(L, g, H::at(qx, qy, qz), H::X, H::X * H::Y);
+}
+
+// The tile point itself from a tile staged with a one-point halo.
 template <class TL>
 __device__ __forceinline__ double centre(const double* L, int qx, int qy, int qz) {
-  return L[((TL::DIM == 3 ? qz + 1 : 0) * TL::LY + (qy + 1)) * TL::LX + (qx + 1)];
+  return L[Halo<TL, 1>::at(qx, qy, qz)];
+}
+
+// Tile-relative position of ring point r (0 <= r < LSZ - P) of the one-point
+// halo: in 3D the two z faces first, then per interior z plane the rows above
+// and below the tile, then its left and right columns.
+template <class TL>
+__device__ __forceinline__ void ring_point(int r, int& qx, int& qy, int& qz) {
+  constexpr int LX = TL::LX, LY = TL::LY;
+  qz = 0;
+  if (TL::DIM == 3) {
+    constexpr int F = LX * LY;
+    if (r < 2 * F) {
+      qz = r < F ? -1 : TL::TZ;
+      const int q = r < F ? r : r - F;
+      qx = q % LX - 1;
+      qy = q / LX - 1;
+      return;
+    }
+    r -= 2 * F;
+    constexpr int SR = 2 * LX + 2 * TL::TY;
+    qz = r / SR;
+    r -= qz * SR;
+  }
+  if (r < 2 * LX) {
+    qy = r < LX ? -1 : TL::TY;
+    qx = (r < LX ? r : r - LX) - 1;
+  } else {
+    r -= 2 * LX;
+    qy = r >> 1;
+    qx = (r & 1) ? TL::TX : -1;
+  }
+}
+
+// v_j and u_{j+1} at one point from u_j, (A u_j) and the basis sums
+// a = V_{j-1} s, b = V_{j-1} cY there.  Explicit FMAs only: the fused step
+// evaluates this both for its own points and for halo points of its
+// neighbours, and both must round the same way.
+template <class T>
+__device__ __forceinline__ void extend_point(double uu, double ww, double a, double b, double ainv,
+                                             double cyj, T& vj, T& un) {
+#pragma clang fp contract(off)
+  vj = (T)((uu - a) * ainv);
+  un = (T)fma(-cyj, (double)vj, fma(ww, ainv, -b));
 }
 
 // This workgroup's job and system.
@@ -197,7 +267,7 @@ __device__ __forceinline__ Mine mine(const Job* jobs, const SysDesc* sd) {
 constexpr int kTrPitch = 17;
 template <int NV, class Live, class Col>
 __device__ __forceinline__ void store_partials(const double (&acc)[NV], Live live, Col col,
-                                               double* red, double* tr, double* part, int nblk,
+                                               double* red, double* tr, gptr<double> part, int nblk,
                                                int lblk) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   double* trw = tr + wave * 64 * kTrPitch;
@@ -234,9 +304,16 @@ __device__ __forceinline__ void store_partials(const double (&acc)[NV], Live liv
 
 // A finished right-hand side: record its statistics and move on to the next
 // one (phase INIT) or mark the system done.  One thread.
-__device__ inline void finish_rhs(Ctrl* C) {
+__device__ inline void finish_rhs(gptr<Ctrl> C) {
   atomicAdd(C->done + 1, 1u);
-  C->stats[C->rhs] = C->s;
+  const gptr<Summary> st = gmem(C->stats) + C->rhs;
+  st->status = C->s.status;
+  st->cycles = C->s.cycles;
+  st->iters = C->s.iters;
+  st->relres_init = C->s.relres_init;
+  st->relres_first = C->s.relres_first;
+  st->relres_est = C->s.relres_est;
+  st->relres_true = C->s.relres_true;
   C->rhs += 1;
   C->cycle_end = 1;
   if (C->rhs >= C->nrhs) {
@@ -261,11 +338,11 @@ __device__ __forceinline__ double lane_bcast(double v, int src) {
 template <class TL>
 __global__ __launch_bounds__(kBlock) void k_begin(const Job* jobs, const SysDesc* sd) {
   const Mine me = mine(jobs, sd);
-  const Ctrl* C = me.S->C;
+  const gptr<const Ctrl> C = gmem((const Ctrl*)me.S->C);
   if (C->phase != PH_INIT || C->rhs == 0) return;
-  const Geo& g = me.S->g;
-  double* x = C->x0 + (size_t)C->rhs * g.n;
-  const double* xp = x - g.n;
+  const Geo g = me.S->g;
+  gptr<double> x = gmem(C->x0) + (size_t)C->rhs * g.n;
+  gptr<const double> xp = x - g.n;
   const bool prev = C->guess == 1;
   for (int tile = me.job.t0; tile < me.job.t1; ++tile) {
     int ox, oy, oz;
@@ -282,15 +359,15 @@ __global__ __launch_bounds__(kBlock) void k_begin(const Job* jobs, const SysDesc
 template <class TL, bool INIT>
 __global__ __launch_bounds__(kBlock) void k_resid(const Job* jobs, const SysDesc* sd) {
   const Mine me = mine(jobs, sd);
-  const Ctrl* C = me.S->C;
+  const gptr<const Ctrl> C = gmem((const Ctrl*)me.S->C);
   if (C->phase != (INIT ? PH_INIT : PH_RUN)) return;
   __shared__ double L[TL::LSZ];
   __shared__ double red[4 * 2];
   __shared__ double tr[4 * 64 * kTrPitch];
-  const Geo& g = me.S->g;
-  const double* b = C->b0 + (size_t)C->rhs * g.n;
-  const double* x = C->x0 + (size_t)C->rhs * g.n;
-  double* r = me.S->r;
+  const Geo g = me.S->g;
+  gptr<const double> b = gmem(C->b0) + (size_t)C->rhs * g.n;
+  const gptr<double> x = gmem(C->x0) + (size_t)C->rhs * g.n;
+  gptr<double> r = gmem(me.S->r);
   double acc[2] = {0.0, 0.0};
   for (int tile = me.job.t0; tile < me.job.t1; ++tile) {
     int ox, oy, oz;
@@ -311,17 +388,17 @@ __global__ __launch_bounds__(kBlock) void k_resid(const Job* jobs, const SysDesc
     }
   }
   store_partials<2>(acc, [](int k) { return INIT || k == 0; }, [](int k) { return k; }, red, tr,
-                    me.S->part, g.nblk, me.job.lblk);
+                    gmem(me.S->part), g.nblk, me.job.lblk);
 }
 
 // beta = |r| (and |b| when starting): one workgroup per system.
 template <bool INIT>
 __global__ __launch_bounds__(kReduceThreads) void k_rsum(const SysDesc* sd) {
   const SysDesc* S = sd + blockIdx.x;
-  Ctrl* C = S->C;
+  const gptr<Ctrl> C = gmem(S->C);
   if (C->phase != (INIT ? PH_INIT : PH_RUN)) return;
   __shared__ double fin[2];
-  reduce_partials(S->part, S->g.nblk, INIT ? 2 : 1, fin);
+  reduce_partials(gmem((const double*)S->part), S->g.nblk, INIT ? 2 : 1, fin);
   if (threadIdx.x != 0) return;
   const double beta = sqrt(fin[0]);
   C->beta = beta;
@@ -376,13 +453,13 @@ __global__ __launch_bounds__(kReduceThreads) void k_rsum(const SysDesc* sd) {
 template <class T, class TL>
 __global__ __launch_bounds__(kBlock) void k_start(const Job* jobs, const SysDesc* sd) {
   const Mine me = mine(jobs, sd);
-  const Ctrl* C = me.S->C;
+  const gptr<const Ctrl> C = gmem((const Ctrl*)me.S->C);
   if (C->phase != PH_RUN && C->phase != PH_ZERO) return;
   const bool zero = C->phase == PH_ZERO;
-  const Geo& g = me.S->g;
-  T* U0 = (T*)me.S->V + (size_t)C->m * g.ldv;
-  const double* r = me.S->r;
-  double* x = C->x0 + (size_t)C->rhs * g.n;
+  const Geo g = me.S->g;
+  gptr<T> U0 = gmem((T*)me.S->V) + (size_t)C->m * g.ldv;
+  const gptr<double> r = gmem(me.S->r);
+  gptr<double> x = gmem(C->x0) + (size_t)C->rhs * g.n;
   for (int tile = me.job.t0; tile < me.job.t1; ++tile) {
     int ox, oy, oz;
     tile_origin<TL>(g, tile, ox, oy, oz);
@@ -405,7 +482,7 @@ __global__ __launch_bounds__(kBlock) void k_start(const Job* jobs, const SysDesc
 template <class T, class TL, int MM>
 __global__ __launch_bounds__(kBlock) void k_dots(const Job* jobs, const SysDesc* sd, int j) {
   const Mine me = mine(jobs, sd);
-  const Ctrl* C = me.S->C;
+  const gptr<const Ctrl> C = gmem((const Ctrl*)me.S->C);
   if (C->phase != PH_RUN || C->cycle_end) return;
   constexpr int NV = 2 * MM + 2;     // s in 0..MM-1, t in MM..2MM-1, nu, mu
   constexpr int PPT = TL::PPT;
@@ -414,9 +491,9 @@ __global__ __launch_bounds__(kBlock) void k_dots(const Job* jobs, const SysDesc*
   __shared__ double L[TL::LSZ];
   __shared__ double red[4 * NV];
   __shared__ double tr[4 * 64 * kTrPitch];
-  const Geo& g = me.S->g;
-  const T* __restrict__ V = (const T*)me.S->V;
-  const T* __restrict__ U = V + (size_t)(C->m + (j & 1)) * g.ldv;
+  const Geo g = me.S->g;
+  const gptr<const T> V = gmem((const T*)me.S->V);
+  const gptr<const T> U = V + (size_t)(C->m + (j & 1)) * g.ldv;
   double acc[NV];
 #pragma unroll
   for (int k = 0; k < NV; ++k) acc[k] = 0.0;
@@ -461,7 +538,7 @@ __global__ __launch_bounds__(kBlock) void k_dots(const Job* jobs, const SysDesc*
   store_partials<NV>(
       acc, [j](int k) { return (k < MM && k < j) || (k >= MM && k < MM + j) || k >= 2 * MM; },
       [j](int k) { return k < MM ? k : (k < 2 * MM ? j + (k - MM) : 2 * j + (k - 2 * MM)); }, red,
-      tr, me.S->part, g.nblk, me.job.lblk);
+      tr, gmem(me.S->part), g.nblk, me.job.lblk);
 }
 
 // coef(j): one workgroup per system.  All threads stage the small per-cycle
@@ -472,7 +549,7 @@ __global__ __launch_bounds__(kBlock) void k_dots(const Job* jobs, const SysDesc*
 // extend(j).  For a zero right-hand side, coef(0) ends the RHS.
 __global__ __launch_bounds__(kReduceThreads) void k_coef(const SysDesc* sd, int j) {
   const SysDesc* S = sd + blockIdx.x;
-  Ctrl* C = S->C;
+  const gptr<Ctrl> C = gmem(S->C);
   if (j == 0 && C->phase == PH_ZERO) {
     if (threadIdx.x == 0) finish_rhs(C);
     return;
@@ -495,7 +572,7 @@ __global__ __launch_bounds__(kReduceThreads) void k_coef(const SysDesc* sd, int 
   const double snl = (w0 && lane < c) ? C->sn[lane] : 0.0;
   const double gc = (w0 && j > 0) ? C->g[c] : 0.0;
   const double glane = (w0 && lane < j) ? C->g[lane] : 0.0;
-  reduce_partials(S->part, S->g.nblk, 2 * j + 2, fin);
+  reduce_partials(gmem((const double*)S->part), S->g.nblk, 2 * j + 2, fin);
   if (!w0) return;
   // ---- wavefront 0: lane i owns row i (j <= 64)
   const double nu = fin[2 * j], mu = fin[2 * j + 1];
@@ -593,7 +670,7 @@ __global__ __launch_bounds__(kReduceThreads) void k_coef(const SysDesc* sd, int 
 template <class T, class TL>
 __global__ __launch_bounds__(kBlock) void k_extend(const Job* jobs, const SysDesc* sd, int j) {
   const Mine me = mine(jobs, sd);
-  const Ctrl* C = me.S->C;
+  const gptr<const Ctrl> C = gmem((const Ctrl*)me.S->C);
   if (C->phase != PH_RUN || C->cycle_end) return;
   __shared__ double L[TL::LSZ];
   __shared__ double sY[kMaxRestart + 1], cY[kMaxRestart + 1];
@@ -601,10 +678,10 @@ __global__ __launch_bounds__(kBlock) void k_extend(const Job* jobs, const SysDes
     sY[k] = C->sY[k];
     cY[k] = C->cY[k];
   }
-  const Geo& g = me.S->g;
-  T* __restrict__ V = (T*)me.S->V;
-  const T* __restrict__ U = V + (size_t)(C->m + (j & 1)) * g.ldv;
-  T* __restrict__ Unext = V + (size_t)(C->m + ((j + 1) & 1)) * g.ldv;
+  const Geo g = me.S->g;
+  const gptr<T> V = gmem((T*)me.S->V);
+  const gptr<const T> U = V + (size_t)(C->m + (j & 1)) * g.ldv;
+  const gptr<T> Unext = V + (size_t)(C->m + ((j + 1) & 1)) * g.ldv;
   const double ainv = 1.0 / C->alpha;
   constexpr int PPT = TL::PPT;
   constexpr int KC = PPT >= 4 ? 8 : (PPT == 2 ? 16 : 32);
@@ -657,19 +734,229 @@ __global__ __launch_bounds__(kBlock) void k_extend(const Job* jobs, const SysDes
   }
 }
 
+// step(j) = extend(j) followed by dots(j+1), one sweep over the basis.
+// extend(j) needs u_j only at the workgroup's own points, but dots(j+1) needs
+// w = A u_{j+1}, i.e. u_{j+1} on a one-point halo around the tile as well.
+// The workgroup therefore recomputes u_{j+1} on that ring itself (u_j staged
+// with a two-point halo, the basis read at the ring points) -- bitwise the
+// values the owning workgroup stores, since both evaluate the same
+// uncontracted expressions in the same order.  The basis values of its own
+// points stay in registers between the extension and the products, so
+// V_{j-1} is read once per step:
+//   v_j = (u_j - V_{j-1} s) / alpha,  u_{j+1} = w_j/alpha - V_{j-1} cY - cY_j v_j
+//   partials of s' = V_j^T u_{j+1} (columns 0..j), t' = V_j^T w_{j+1}
+//   (j+1..2j+1), u_{j+1}^T u_{j+1} (2j+2), u_{j+1}^T w_{j+1} (2j+3).
+// The products of each tile are folded across the wavefront at once (chunks
+// of 8 basis vectors, 16 sums, reduce-scatter), so a lane carries only one
+// running sum per chunk and the kernel keeps its occupancy.
+template <class T, class TL, int MM>
+__global__ __launch_bounds__(kBlock) void k_step(const Job* jobs, const SysDesc* sd, int j) {
+  const Mine me = mine(jobs, sd);
+  const gptr<const Ctrl> C = gmem((const Ctrl*)me.S->C);
+  if (C->phase != PH_RUN || C->cycle_end) return;
+  using H1 = Halo<TL, 1>;
+  using H2 = Halo<TL, 2>;
+  constexpr int PPT = TL::PPT;
+  constexpr int KC = 8;
+  static_assert(MM % KC == 0, "register bound must be a multiple of the chunk");
+  constexpr int NCH = MM / KC;                       // chunks of 16 sums
+  constexpr int NS = 16 * NCH + 4;                   // sums per wavefront
+  constexpr int RS = H1::SZ - TL::P;                 // ring points
+  constexpr int RPT = (RS + kBlock - 1) / kBlock;
+  constexpr int HPT = (H2::SZ + kBlock - 1) / kBlock;
+  __shared__ double L2[H2::SZ];
+  __shared__ double L1[H1::SZ];
+  __shared__ double red[4 * NS];
+  __shared__ double sY[MM], cY[MM];
+  for (int k = threadIdx.x; k <= j; k += kBlock) {
+    if (k < j) sY[k] = C->sY[k];
+    cY[k] = C->cY[k];
+  }
+  const Geo g = me.S->g;
+  const gptr<T> V = gmem((T*)me.S->V);
+  const gptr<const T> U = V + (size_t)(C->m + (j & 1)) * g.ldv;
+  const gptr<T> Unext = V + (size_t)(C->m + ((j + 1) & 1)) * g.ldv;
+  const double ainv = 1.0 / C->alpha;
+  double accw[NCH + 1];
+#pragma unroll
+  for (int c = 0; c <= NCH; ++c) accw[c] = 0.0;
+  for (int tile = me.job.t0; tile < me.job.t1; ++tile) {
+    int ox, oy, oz;
+    tile_origin<TL>(g, tile, ox, oy, oz);
+    // ---- every global load of the tile is issued here, before any is used,
+    // unconditionally: indices are clamped into valid memory (basis slots
+    // >= j re-read v_{j-1}, points outside the grid read element 0) and the
+    // extra values are never used, so no branch splits the loads
+    T hv[HPT];                                        // u_j with a two-point halo
+    bool hin[HPT];
+#pragma unroll
+    for (int h = 0; h < HPT; ++h) {
+      const int e = threadIdx.x + kBlock * h;
+      const int lx = e % H2::X, r = e / H2::X, ly = r % H2::Y, lz = r / H2::Y;
+      const int gx = ox + lx - 2, gy = oy + ly - 2, gz = TL::DIM == 3 ? oz + lz - 2 : 0;
+      hin[h] = e < H2::SZ && gx >= 0 && gx < g.nx && gy >= 0 && gy < g.ny && gz >= 0 &&
+               gz < g.nz;
+      hv[h] = U[hin[h] ? ((long long)gz * g.ny + gy) * g.nx + gx : 0];
+    }
+    long long pp[PPT];
+    bool ok[PPT];
+    int q2[PPT], q1[PPT];
+#pragma unroll
+    for (int i = 0; i < PPT; ++i) {
+      auto pr = point<TL>(g, ox, oy, oz, i);
+      ok[i] = pr.valid;
+      pp[i] = pr.valid ? pr.p : 0;
+      q2[i] = H2::at(pr.qx, pr.qy, pr.qz);
+      q1[i] = H1::at(pr.qx, pr.qy, pr.qz);
+    }
+    int rq[RPT][3];
+    bool rin[RPT];
+    long long rp[RPT];
+#pragma unroll
+    for (int rr = 0; rr < RPT; ++rr) {
+      const int e = threadIdx.x + kBlock * rr;
+      ring_point<TL>(e < RS ? e : 0, rq[rr][0], rq[rr][1], rq[rr][2]);
+      const int gx = ox + rq[rr][0], gy = oy + rq[rr][1], gz = oz + rq[rr][2];
+      rin[rr] = e < RS && gx >= 0 && gx < g.nx && gy >= 0 && gy < g.ny && gz >= 0 && gz < g.nz;
+      rp[rr] = rin[rr] ? ((long long)gz * g.ny + gy) * g.nx + gx : 0;
+    }
+    T vr[MM][PPT];                                    // basis at this thread's points
+    T vg[MM][RPT];                                    // basis at this thread's ring points
+    const int jl = j > 0 ? j - 1 : 0;
+#pragma unroll
+    for (int k = 0; k < MM; ++k) {
+      const gptr<const T> Vk = V + (size_t)(k < j ? k : jl) * g.ldv;
+#pragma unroll
+      for (int i = 0; i < PPT; ++i) vr[k][i] = Vk[pp[i]];
+#pragma unroll
+      for (int rr = 0; rr < RPT; ++rr) vg[k][rr] = Vk[rp[rr]];
+    }
+    // ---- stage u_j (the previous tile's readers of L2/L1 are done)
+    __syncthreads();
+#pragma unroll
+    for (int h = 0; h < HPT; ++h) {
+      const int e = threadIdx.x + kBlock * h;
+      if (e < H2::SZ) L2[e] = hin[h] ? (double)hv[h] : 0.0;
+    }
+    __syncthreads();
+    const double cyj = cY[j];
+    // u_{j+1} on the ring (zero outside the grid)
+#pragma unroll
+    for (int rr = 0; rr < RPT; ++rr) {
+      const int e = threadIdx.x + kBlock * rr;
+      if (e < RS) {
+        double un = 0.0;
+        if (rin[rr]) {
+          const int i2 = H2::at(rq[rr][0], rq[rr][1], rq[rr][2]);
+          const double uu = L2[i2];
+          const double ww = stencil_at<TL::DIM>(L2, g, i2, H2::X, H2::X * H2::Y);
+          double a = 0.0, b = 0.0;
+#pragma unroll
+          for (int k = 0; k < MM; ++k)
+            if (k < j) {
+              a = fma((double)vg[k][rr], sY[k], a);
+              b = fma((double)vg[k][rr], cY[k], b);
+            }
+          T vj, unT;
+          extend_point<T>(uu, ww, a, b, ainv, cyj, vj, unT);
+          un = (double)unT;
+        }
+        L1[H1::at(rq[rr][0], rq[rr][1], rq[rr][2])] = un;
+      }
+    }
+    // v_j and u_{j+1} at this thread's points
+    double vjd[PPT];
+#pragma unroll
+    for (int i = 0; i < PPT; ++i) {
+      vjd[i] = 0.0;
+      double un = 0.0;
+      if (ok[i]) {
+        const double uu = L2[q2[i]];
+        const double ww = stencil_at<TL::DIM>(L2, g, q2[i], H2::X, H2::X * H2::Y);
+        double a = 0.0, b = 0.0;
+#pragma unroll
+        for (int k = 0; k < MM; ++k)
+          if (k < j) {
+            a = fma((double)vr[k][i], sY[k], a);
+            b = fma((double)vr[k][i], cY[k], b);
+          }
+        T vj, unT;
+        extend_point<T>(uu, ww, a, b, ainv, cyj, vj, unT);
+        V[(size_t)j * g.ldv + pp[i]] = vj;
+        Unext[pp[i]] = unT;
+        vjd[i] = (double)vj;
+        un = (double)unT;
+      }
+      L1[q1[i]] = un;
+    }
+    __syncthreads();
+    // products for step j+1, folded across the wavefront per chunk
+    double u1[PPT], w1[PPT];
+    double last[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int i = 0; i < PPT; ++i) {
+      u1[i] = ok[i] ? L1[q1[i]] : 0.0;
+      w1[i] = ok[i] ? stencil_at<TL::DIM>(L1, g, q1[i], H1::X, H1::X * H1::Y) : 0.0;
+      last[0] = fma(u1[i], u1[i], last[0]);
+      last[1] = fma(u1[i], w1[i], last[1]);
+      last[2] = fma(vjd[i], u1[i], last[2]);
+      last[3] = fma(vjd[i], w1[i], last[3]);
+    }
+#pragma unroll
+    for (int c = 0; c < NCH; ++c)
+      if (KC * c < j) {
+        double prod[16];
+#pragma unroll
+        for (int q = 0; q < KC; ++q) {
+          prod[q] = 0.0;
+          prod[KC + q] = 0.0;
+#pragma unroll
+          for (int i = 0; i < PPT; ++i) {
+            prod[q] = fma((double)vr[KC * c + q][i], u1[i], prod[q]);
+            prod[KC + q] = fma((double)vr[KC * c + q][i], w1[i], prod[KC + q]);
+          }
+        }
+        accw[c] += rs16(prod);
+      }
+    accw[NCH] += rs4(last);
+  }
+  // per-wavefront sums -> LDS -> block sums -> this workgroup's partials
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if ((lane & 3) == 0) {
+#pragma unroll
+    for (int c = 0; c < NCH; ++c) red[wave * NS + 16 * c + rs16_slot(lane)] = accw[c];
+  }
+  if ((lane & 15) == 0) red[wave * NS + 16 * NCH + rs4_slot(lane)] = accw[NCH];
+  __syncthreads();
+  const int jn = j + 1;
+  for (int k = threadIdx.x; k < NS; k += kBlock) {
+    int col = -1;
+    if (k < 16 * NCH) {
+      const int q = k & 15, bi = KC * (k >> 4) + (q & 7);
+      if (bi < j) col = q < KC ? bi : jn + bi;
+    } else {
+      const int f = k - 16 * NCH;                 // nu, mu, s_j, t_j
+      col = f == 0 ? 2 * jn : (f == 1 ? 2 * jn + 1 : (f == 2 ? j : jn + j));
+    }
+    if (col >= 0)
+      gmem(me.S->part)[(size_t)col * g.nblk + me.job.lblk] =
+          ((red[k] + red[NS + k]) + red[2 * NS + k]) + red[3 * NS + k];
+  }
+}
+
 // x += V_k y (FP64 accumulation into the FP64 iterate).
 template <class T, class TL>
 __global__ __launch_bounds__(kBlock) void k_update(const Job* jobs, const SysDesc* sd) {
   const Mine me = mine(jobs, sd);
-  const Ctrl* C = me.S->C;
+  const gptr<const Ctrl> C = gmem((const Ctrl*)me.S->C);
   if (C->phase != PH_RUN) return;
   __shared__ double ys[kMaxRestart];
   const int k = C->k;
   for (int l = threadIdx.x; l < k; l += kBlock) ys[l] = C->y[l];
   __syncthreads();
-  const Geo& g = me.S->g;
-  const T* __restrict__ V = (const T*)me.S->V;
-  double* x = C->x0 + (size_t)C->rhs * g.n;
+  const Geo g = me.S->g;
+  const gptr<const T> V = gmem((const T*)me.S->V);
+  gptr<double> x = gmem(C->x0) + (size_t)C->rhs * g.n;
   for (int tile = me.job.t0; tile < me.job.t1; ++tile) {
     int ox, oy, oz;
     tile_origin<TL>(g, tile, ox, oy, oz);

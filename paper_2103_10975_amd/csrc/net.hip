@@ -229,7 +229,7 @@ __global__ __launch_bounds__(kReduceThreads) void k_loss_sum(const double* part,
                                                             float* loss_dev, float* loss_user,
                                                             int B) {
   __shared__ double fin[1];
-  reduce_partials(part, nblk, 1, fin);
+  reduce_partials(gmem(part), nblk, 1, fin);
   if (threadIdx.x == 0) {
     const float L = (float)(fin[0] / B);
     *loss_dev = L;
