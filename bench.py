@@ -49,48 +49,53 @@ def parse():
     ap.add_argument("--json-out", default=None)
     ap.add_argument("--probe", default=None, metavar="KERNEL",
                     help="counter-collection run: a 256 MiB device copy (the byte-count "
-                         "calibration) then every step index of KERNEL (dots, extend, update, "
-                         "resid) once, in the learned-guess solve's launch configuration")
+                         "calibration) then every launch of KERNEL (step, dots, extend, update, "
+                         "resid) in one restart cycle, in the learned-guess solve's launch "
+                         "configuration")
     return ap.parse_args()
 
 
-def kernel_roofline(mlg, shape, opts, b, reps=20, only=None):
-    """Average launch duration of every solver kernel over one cycle's steps,
-    in the launch configuration of the solve (HIP events on the stream)."""
+def kernel_roofline(mlg, shape, opts, b, tile, fused, reps=20, only=None):
+    """Average launch duration of every solver kernel over one restart cycle,
+    in the launch configuration of the solve (tuned tile and per-step sweep
+    schedule; HIP events on the stream), with the algorithmic bytes of each
+    launch."""
     grid = mlg.grid_of(shape)
-    ws = mlg.workspace(mlg.gmres_workspace_bytes(grid, opts))
+    m = opts.restart_m
+    fixed = mlg.Opts(restart_m=m, precision=opts.precision, rtol=opts.rtol, fixed_iters=m,
+                     tile=tile)
+    ws = mlg.workspace(mlg.gmres_workspace_bytes(grid, fixed))
     x = torch.zeros_like(b)
-    fixed = mlg.Opts(restart_m=opts.restart_m, precision=opts.precision, rtol=opts.rtol,
-                     fixed_iters=opts.restart_m)
     mlg.gmres_solve(grid, b, x, fixed, ws)                 # fills the basis of one full cycle
     scratch = mlg.workspace(mlg.mlg_kernel_bench_scratch_bytes(reps))
-    m = opts.restart_m
     n = int(np.prod(shape))
     s = 8 if opts.precision == mlg.MLG_FP64 else 4
+    # the launches of one cycle: (kind, step index, algorithmic bytes)
+    launches = [(mlg.MLG_K_DOTS, 0, 1 * n * s)]           # w = A u_0 and |u_0|: read u_0
+    for j in range(m):
+        if (fused >> j) & 1:
+            # read v_0..v_{j-1}, u_j; write v_j, u_{j+1}
+            launches.append((mlg.MLG_K_STEP, j, (j + 3) * n * s))
+        else:
+            launches.append((mlg.MLG_K_EXTEND, j, (j + 3) * n * s))
+            launches.append((mlg.MLG_K_DOTS, j + 1, (j + 2) * n * s))   # read v_0..v_j, u_{j+1}
+    launches += [(mlg.MLG_K_COEF, j, 0) for j in range(m + 1)]        # one-workgroup sums
+    launches.append((mlg.MLG_K_UPDATE, m, m * n * s + 2 * n * 8))      # read V_m, read+write x
+    launches.append((mlg.MLG_K_RESIDUAL, m, 3 * n * 8))                # read x, b; write r
     out = {}
-    for kind, name in mlg.KERNEL_NAMES.items():
+    for kind, j, byts in launches:
+        name = mlg.KERNEL_NAMES[kind]
         if only is not None and name != only:
             continue
-        if kind in (mlg.MLG_K_DOTS, mlg.MLG_K_COEF):
-            steps = range(m + 1)
-        elif kind == mlg.MLG_K_EXTEND:
-            steps = range(m)
-        else:
-            steps = [m]
-        us = [mlg.mlg_kernel_bench(grid, fixed, ws, scratch, kind, j, reps) for j in steps]
-        # algorithmic bytes per launch: what each kernel must move at minimum
-        if kind == mlg.MLG_K_DOTS:
-            byts = [(j + 1) * n * s for j in steps]              # read v_0..v_{j-1}, u_j
-        elif kind == mlg.MLG_K_EXTEND:
-            byts = [(j + 3) * n * s for j in steps]              # read V_{j-1}, u_j; write v_j, u_{j+1}
-        elif kind == mlg.MLG_K_UPDATE:
-            byts = [m * n * s + 2 * n * 8 for _ in steps]        # read V_m, read+write x
-        elif kind == mlg.MLG_K_RESIDUAL:
-            byts = [3 * n * 8 for _ in steps]                    # read x, b; write r
-        else:
-            byts = [0 for _ in steps]                            # one-workgroup reduction
-        out[name] = {"launches_per_cycle": len(us), "avg_us": statistics.fmean(us),
-                     "avg_bytes": statistics.fmean(byts), "cycle_us": sum(us)}
+        us = mlg.mlg_kernel_bench(grid, fixed, ws, scratch, kind, j, reps)
+        d = out.setdefault(name, {"launches_per_cycle": 0, "us": [], "bytes": []})
+        d["launches_per_cycle"] += 1
+        d["us"].append(us)
+        d["bytes"].append(byts)
+    for d in out.values():
+        d["avg_us"] = statistics.fmean(d["us"])
+        d["avg_bytes"] = statistics.fmean(d["bytes"])
+        d["cycle_us"] = sum(d["us"])
     del ws, scratch
     return out
 
@@ -207,7 +212,10 @@ def main():
         result["speedup_vs_prev_fp64"] = legs["fp64_prev"]["tos_mean"] / tos_learned
 
     # roofline of the dominant kernel of the learned-guess solve
-    kr = kernel_roofline(mlg, shape, learned.opts, fields[0])
+    tile, fused = learned.tuned
+    result["config"]["tile"] = list(mlg.mlg_tile_shape(2, tile - 1))
+    result["config"]["fused_steps"] = bin(fused).count("1")
+    kr = kernel_roofline(mlg, shape, learned.opts, fields[0], tile, fused)
     dom = max((k for k in kr if kr[k]["avg_bytes"] > 0), key=lambda k: kr[k]["cycle_us"])
     d = kr[dom]
     achieved = d["avg_bytes"] / (d["avg_us"] * 1e-6) / 1e9
@@ -217,7 +225,7 @@ def main():
                           "traffic": counter_traffic(dom, shape, tag, args.restart),
                           "avg_us": d["avg_us"], "avg_bytes": d["avg_bytes"]}
     result["kernels"] = {k: {"avg_us": v["avg_us"], "per_cycle": v["launches_per_cycle"],
-                             "GB/s": v["avg_bytes"] / v["avg_us"] / 1e3}
+                             "GB/s": v["avg_bytes"] / v["avg_us"] / 1e3, "cycle_us": v["cycle_us"]}
                          for k, v in kr.items()}
 
     if not args.no_cpu:
@@ -245,7 +253,8 @@ def probe(mlg, shape, args):
     torch.cuda.synchronize()
     f0 = torch.from_numpy(DriftingGaussians(shape, 4, 0.03, seed=args.seed).field(0)).cuda()
     opts = mlg.Opts(restart_m=args.restart, rtol=args.rtol, precision=mlg.MLG_FP32_IR)
-    r = kernel_roofline(mlg, shape, opts, f0, reps=1, only=names[args.probe])
+    tile, fused = mlg.mlg_autotune(mlg.grid_of(shape), opts)
+    r = kernel_roofline(mlg, shape, opts, f0, tile, fused, reps=1, only=names[args.probe])
     torch.cuda.synchronize()
     print(json.dumps({"probe": args.probe, "copy_bytes": 2 * a.numel() * 4,
                       "avg_bytes": r[names[args.probe]]["avg_bytes"]}), flush=True)

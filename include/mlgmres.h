@@ -71,6 +71,10 @@ typedef struct {
  *                 the tile table (mlg_tile_count / mlg_tile_shape).
  *   poll_cycles   restart cycles enqueued between host polls of the
  *                 convergence flag (0 = 1).
+ *   schedule      how an Arnoldi step sweeps the basis (same arithmetic):
+ *                 0 = as tuned by mlg_autotune for this grid (separate sweeps
+ *                 when untuned), 1 = separate extend and dot-product sweeps,
+ *                 2 = the fused single sweep wherever the grid is 2D.
  */
 typedef struct {
   int32_t restart_m;
@@ -80,6 +84,7 @@ typedef struct {
   int64_t fixed_iters;
   int32_t tile;
   int32_t poll_cycles;
+  int32_t schedule;
 } mlg_opts;
 
 /* Per-solve statistics (host).  relres_first_cycle is the paper's metric E_k
@@ -175,6 +180,23 @@ int mlg_kernel_bench(const mlg_grid* grid, const mlg_opts* opts, void* ws, size_
 /* Tile table used by the solver kernels. */
 int32_t mlg_tile_count(int32_t dim);
 int mlg_tile_shape(int32_t dim, int32_t index, int32_t* tx, int32_t* ty, int32_t* tz);
+
+/*
+ * Autotuner.  For one grid and option set (precision, restart_m), times every
+ * tile shape and, per Arnoldi step, the separate extend + dot-product sweeps
+ * against the fused sweep, on synthetic data in `ws`, in the launch
+ * configuration the solver uses; records the fastest tile and per-step
+ * schedule in a process-wide table that gmres_solve / gmres_solve_batched
+ * consult when opts->tile == 0 (tile) and opts->schedule == 0 (schedule).
+ * A batched solve takes the entry of its largest system per dimension.
+ *   ws      >= mlg_autotune_workspace_bytes(grid, opts) bytes (overwritten).
+ *   tile    host, may be NULL: the chosen tile index (1-based, as opts->tile).
+ *   fused   host, may be NULL: bit j set = step j runs fused.
+ * Blocks until done.  Entries live until mlg_shutdown.
+ */
+size_t mlg_autotune_workspace_bytes(const mlg_grid* grid, const mlg_opts* opts);
+int mlg_autotune(const mlg_grid* grid, const mlg_opts* opts, void* ws, size_t ws_bytes,
+                 int32_t* tile, uint64_t* fused, void* stream);
 
 /* ---------------------------------------------------------------- network */
 

@@ -18,7 +18,8 @@ __all__ = [
     "Grid", "Opts", "Stats", "System", "NetCfg", "MLG_FP64", "MLG_FP32_IR",
     "grid_of", "lib", "gmres_workspace_bytes", "gmres_solve", "gmres_batched_workspace_bytes",
     "gmres_solve_batched", "mlg_apply_operator", "mlg_kernel_bench_scratch_bytes",
-    "mlg_kernel_bench", "mlg_tile_count", "mlg_tile_shape", "guess_net_param_count", "guess_net_param_offset", "guess_net_param_bytes",
+    "mlg_kernel_bench", "mlg_tile_count", "mlg_tile_shape", "mlg_autotune_workspace_bytes",
+    "mlg_autotune", "guess_net_param_count", "guess_net_param_offset", "guess_net_param_bytes",
     "guess_net_workspace_bytes", "guess_net_init", "guess_net_refresh", "guess_net_infer",
     "guess_net_train_step", "mlg_last_error", "mlg_shutdown", "MlgError", "EXPORTS",
 ]
@@ -34,8 +35,8 @@ MLG_FP64, MLG_FP32_IR = 0, 1
 EXPORTS = (
     "gmres_workspace_bytes", "gmres_solve", "gmres_batched_workspace_bytes",
     "gmres_solve_batched", "mlg_apply_operator", "mlg_kernel_bench_scratch_bytes",
-    "mlg_kernel_bench", "mlg_tile_count", "mlg_tile_shape",
-    "guess_net_param_count", "guess_net_param_offset", "guess_net_param_bytes",
+    "mlg_kernel_bench", "mlg_tile_count", "mlg_tile_shape", "mlg_autotune_workspace_bytes",
+    "mlg_autotune", "guess_net_param_count", "guess_net_param_offset", "guess_net_param_bytes",
     "guess_net_workspace_bytes", "guess_net_init", "guess_net_refresh", "guess_net_infer",
     "guess_net_train_step", "mlg_last_error", "mlg_shutdown",
 )
@@ -56,11 +57,12 @@ class Opts(ctypes.Structure):
     _fields_ = [("restart_m", ctypes.c_int32), ("precision", ctypes.c_int32),
                 ("rtol", ctypes.c_double), ("max_iters", ctypes.c_int64),
                 ("fixed_iters", ctypes.c_int64), ("tile", ctypes.c_int32),
-                ("poll_cycles", ctypes.c_int32)]
+                ("poll_cycles", ctypes.c_int32), ("schedule", ctypes.c_int32)]
 
     def __init__(self, restart_m=30, precision=MLG_FP64, rtol=1e-8, max_iters=0,
-                 fixed_iters=0, tile=0, poll_cycles=1):
-        super().__init__(restart_m, precision, rtol, max_iters, fixed_iters, tile, poll_cycles)
+                 fixed_iters=0, tile=0, poll_cycles=1, schedule=0):
+        super().__init__(restart_m, precision, rtol, max_iters, fixed_iters, tile, poll_cycles,
+                         schedule)
 
 
 class Stats(ctypes.Structure):
@@ -105,6 +107,8 @@ def _load():
                                             P(ctypes.c_double), vp]),
         "mlg_tile_count": (i32, [i32]),
         "mlg_tile_shape": (ctypes.c_int, [i32, i32, P(i32), P(i32), P(i32)]),
+        "mlg_autotune_workspace_bytes": (sz, [P(Grid), P(Opts)]),
+        "mlg_autotune": (ctypes.c_int, [P(Grid), P(Opts), vp, sz, P(i32), P(ctypes.c_uint64), vp]),
         "guess_net_param_count": (i64, [P(NetCfg)]),
         "guess_net_param_offset": (i64, [P(NetCfg), i32]),
         "guess_net_param_bytes": (sz, [P(NetCfg)]),
@@ -240,6 +244,26 @@ def mlg_kernel_bench(grid: Grid, opts: Opts, ws: torch.Tensor, scratch: torch.Te
                                 ws.numel(), _ptr(scratch, torch.uint8), scratch.numel(), kind, step,
                                 reps, ctypes.byref(out), _stream(stream)))
     return out.value
+
+
+def mlg_autotune_workspace_bytes(grid: Grid, opts: Opts) -> int:
+    n = lib.mlg_autotune_workspace_bytes(ctypes.byref(grid), ctypes.byref(opts))
+    if n == 0:
+        raise MlgError(MLG_ERR_ARG, mlg_last_error())
+    return n
+
+
+def mlg_autotune(grid: Grid, opts: Opts, ws: torch.Tensor | None = None, stream=None):
+    """Time every tile and per-step sweep schedule for (grid, opts) and record
+    the fastest for later solves with tile=0, schedule=0.  Returns (tile,
+    fused-step bit mask).  ws: scratch of mlg_autotune_workspace_bytes bytes
+    (allocated here when None)."""
+    if ws is None:
+        ws = workspace(mlg_autotune_workspace_bytes(grid, opts))
+    tile, fused = ctypes.c_int32(), ctypes.c_uint64()
+    _check(lib.mlg_autotune(ctypes.byref(grid), ctypes.byref(opts), _ptr(ws, torch.uint8),
+                            ws.numel(), ctypes.byref(tile), ctypes.byref(fused), _stream(stream)))
+    return tile.value, fused.value
 
 
 def mlg_tile_count(dim: int) -> int:

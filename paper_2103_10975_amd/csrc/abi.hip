@@ -40,6 +40,7 @@ void mlg_shutdown(void) {
   try {
     runtime_shutdown();
     batched_shutdown();
+    autotune_clear();
   } catch (...) {
   }
 }
@@ -89,6 +90,27 @@ int mlg_kernel_bench(const mlg_grid* grid, const mlg_opts* opts, void* ws, size_
     *avg_us = kernel_bench(grid, opts, ws, ws_bytes, scratch, scratch_bytes, kind, step, reps,
                            (hipStream_t)stream);
     return 0;
+  });
+}
+
+size_t mlg_autotune_workspace_bytes(const mlg_grid* grid, const mlg_opts* opts) {
+  size_t out = 0;
+  int rc = guarded([&] {
+    out = autotune_workspace_bytes(grid, opts);
+    return 0;
+  });
+  return rc == 0 ? out : 0;
+}
+
+int mlg_autotune(const mlg_grid* grid, const mlg_opts* opts, void* ws, size_t ws_bytes,
+                 int32_t* tile, uint64_t* fused, void* stream) {
+  return guarded([&] {
+    int t = 0;
+    unsigned long long f = 0;
+    const int rc = autotune(grid, opts, ws, ws_bytes, &t, &f, (hipStream_t)stream);
+    if (tile) *tile = t;
+    if (fused) *fused = (uint64_t)f;
+    return rc;
   });
 }
 

@@ -178,4 +178,52 @@ __device__ __forceinline__ void reduce_partials(gptr<const double> part, int nbl
   __syncthreads();
 }
 
+// The same sums split into rounds whose loads can be issued early: NB
+// blocks per lane per column (nblocks <= 64 NB), 32 / NB columns per
+// wavefront, so a round covers 16 * 32 / NB columns with 32 loads per lane.
+template <int NB>
+struct PartialsRound {
+  static constexpr int kPerWave = 32 / NB;
+  static constexpr int kCols = (kReduceThreads / 64) * kPerWave;
+  double v[kPerWave][NB];
+};
+template <int NB>
+__device__ __forceinline__ void partials_load(PartialsRound<NB>& r, gptr<const double> part,
+                                              int nblocks, int ncols, int c0) {
+  // only live columns are loaded (a wavefront-uniform test), and only live
+  // blocks (lanes past the last block are masked off): a single workgroup
+  // moves all the partials, so its load instruction count is its cost
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  constexpr int NW = kReduceThreads / 64;
+#pragma unroll
+  for (int q = 0; q < PartialsRound<NB>::kPerWave; ++q) {
+    const int c = c0 + q * NW + wave;
+#pragma unroll
+    for (int i = 0; i < NB; ++i) r.v[q][i] = 0.0;
+    if (c < ncols) {
+#pragma unroll
+      for (int i = 0; i < NB; ++i) {
+        const int b = lane + 64 * i;
+        if (b < nblocks) r.v[q][i] = part[(size_t)c * nblocks + b];
+      }
+    }
+  }
+}
+template <int NB>
+__device__ __forceinline__ void partials_sum(const PartialsRound<NB>& r, int nblocks, int ncols,
+                                             int c0, double* out) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  constexpr int NW = kReduceThreads / 64;
+#pragma unroll
+  for (int q = 0; q < PartialsRound<NB>::kPerWave; ++q) {
+    const int c = c0 + q * NW + wave;
+    if (c >= ncols) continue;                       // wavefront-uniform
+    double s = 0.0;
+#pragma unroll
+    for (int i = 0; i < NB; ++i) s += r.v[q][i];
+    s = wave_sum(s);
+    if (lane == 0) out[c] = s;
+  }
+}
+
 }  // namespace mlg

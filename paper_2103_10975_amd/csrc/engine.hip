@@ -24,7 +24,7 @@ namespace mlg {
 // vector; the narrow tall 32 x 8 tile has the smallest halo ring of the
 // one-point-per-thread tiles, which the fused Arnoldi step recomputes.
 static const TileDesc kTiles2[] = {{64, 16, 1}, {64, 8, 1}, {128, 8, 1}, {64, 4, 1}, {32, 8, 1}};
-static const TileDesc kTiles3[] = {{64, 4, 4}, {32, 8, 4}, {64, 2, 4}};
+static const TileDesc kTiles3[] = {{64, 2, 4}, {64, 2, 2}, {32, 4, 2}, {64, 4, 4}};
 static constexpr int kNumTiles2 = sizeof(kTiles2) / sizeof(kTiles2[0]);
 static constexpr int kNumTiles3 = sizeof(kTiles3) / sizeof(kTiles3[0]);
 
@@ -76,14 +76,13 @@ void check_opts(const mlg_opts* o, int dim) {
   if (!(o->rtol >= 0.0)) throw ArgError{MLG_ERR_ARG, "rtol must be >= 0"};
   if (o->max_iters < 0 || o->fixed_iters < 0) throw ArgError{MLG_ERR_ARG, "negative iteration cap"};
   if (o->tile < 0 || o->tile > tile_count(dim)) throw ArgError{MLG_ERR_ARG, "tile index out of range"};
+  if (o->schedule < 0 || o->schedule > 2) throw ArgError{MLG_ERR_ARG, "schedule must be 0, 1 or 2"};
 }
 
-// Default tile when the caller leaves the choice to the library: the tuned
-// entry if there is one, else the widest tile that still yields >= 2
-// workgroups per CU (or the smallest tile).
-int default_tile(const mlg_grid& gr, const mlg_opts& o) {
-  int pick = autotune_lookup(gr, o);
-  if (pick >= 0) return pick;
+// Default tile when the caller leaves the choice to the library and the
+// autotuner has no entry: the widest tile that still yields >= 2 workgroups
+// per CU (or the smallest tile).
+int default_tile(const mlg_grid& gr, const mlg_opts&) {
   if (gr.dim == 3) return 0;
   if (tiles_of(gr, 0) >= 512) return 0;
   if (tiles_of(gr, 1) >= 256) return 1;
@@ -93,6 +92,7 @@ int default_tile(const mlg_grid& gr, const mlg_opts& o) {
 // ------------------------------------------------------------------ plan
 struct Group {
   int dim, tile;
+  unsigned long long fused;         // bit j: step j runs as the fused sweep
   std::vector<int> systems;
   std::vector<Job> jobs;
   size_t off_jobs;
@@ -132,8 +132,15 @@ static Plan make_plan(int nsys, const mlg_system* sys, const mlg_opts& o) {
         if (biggest < 0 || npoints(sys[i].grid) > npoints(sys[biggest].grid)) biggest = i;
       }
     if (G.systems.empty()) continue;
-    G.tile = o.tile > 0 ? o.tile - 1 : default_tile(sys[biggest].grid, o);
+    TuneEntry te;
+    const bool tuned = autotune_find(sys[biggest].grid, o, &te);
+    G.tile = o.tile > 0 ? o.tile - 1 : (tuned ? te.tile : default_tile(sys[biggest].grid, o));
     if (G.tile >= tile_count(dim)) G.tile = tile_count(dim) - 1;
+    // the fused sweep exists for 2D grids only (in 3D its halo ring would
+    // exceed the tile)
+    if (dim == 3 || o.schedule == 1) G.fused = 0;
+    else if (o.schedule == 2) G.fused = ~0ULL;
+    else G.fused = tuned ? te.fused[G.tile] : 0;
     P.groups.push_back(G);
   }
   P.geo.resize(nsys);
@@ -200,30 +207,37 @@ size_t workspace_bytes(int nsys, const mlg_system* sys, const mlg_opts* opts) {
 }
 
 // ------------------------------------------------------------------ dispatch
-// The fused step keeps the basis values of its points in registers; its
-// register bound follows the step index (so early steps of a cycle run at
-// high occupancy), not the restart length.
-template <class T, class TL>
-static void launch_step(hipStream_t s, int nb, const Job* jobs, const SysDesc* sd, int j) {
-  if (j < 8) k_step<T, TL, 8><<<nb, kBlock, 0, s>>>(jobs, sd, j);
-  else if (j < 16) k_step<T, TL, 16><<<nb, kBlock, 0, s>>>(jobs, sd, j);
-  else if (j < 24) k_step<T, TL, 24><<<nb, kBlock, 0, s>>>(jobs, sd, j);
-  else if (j < 32) k_step<T, TL, 32><<<nb, kBlock, 0, s>>>(jobs, sd, j);
-  else if (j < 40) k_step<T, TL, 40><<<nb, kBlock, 0, s>>>(jobs, sd, j);
-  else k_step<T, TL, 64><<<nb, kBlock, 0, s>>>(jobs, sd, j);
+// Sweeps keep the basis values of their points in registers, MM slots of
+// them; MM is the smallest of 8, 16, 24, 32, 40, 64 that covers the step, so
+// early steps of a cycle run at high occupancy.
+#define MLG_MM_SWITCH(N, EXPR_MM)                                   \
+  if ((N) <= 8) { constexpr int MM = 8; EXPR_MM; }                  \
+  else if ((N) <= 16) { constexpr int MM = 16; EXPR_MM; }           \
+  else if ((N) <= 24) { constexpr int MM = 24; EXPR_MM; }           \
+  else if ((N) <= 32) { constexpr int MM = 32; EXPR_MM; }           \
+  else if ((N) <= 40) { constexpr int MM = 40; EXPR_MM; }           \
+  else { constexpr int MM = 64; EXPR_MM; }
+
+// coef(j) for ns systems whose partials come from at most maxblk workgroups.
+static void launch_coef(hipStream_t s, int ns, int maxblk, const SysDesc* sd, int j) {
+  if (maxblk <= 256) k_coef<4><<<ns, kReduceThreads, 0, s>>>(sd, j);
+  else if (maxblk <= 512) k_coef<8><<<ns, kReduceThreads, 0, s>>>(sd, j);
+  else k_coef<16><<<ns, kReduceThreads, 0, s>>>(sd, j);
 }
 
-template <class T, class TL, int MM>
+// kind: 0 begin, 1 initial residual, 2 start, 3 dots(j), 4 extend(j),
+// 5 update (j = restart length m), 6 residual, 7 fused step(j).
+template <class T, class TL>
 static void enqueue_group_step(hipStream_t s, int kind, int nb, const Job* jobs, const SysDesc* sd,
                                int j) {
   switch (kind) {
     case 0: k_begin<TL><<<nb, kBlock, 0, s>>>(jobs, sd); break;
     case 1: k_resid<TL, true><<<nb, kBlock, 0, s>>>(jobs, sd); break;
     case 2: k_start<T, TL><<<nb, kBlock, 0, s>>>(jobs, sd); break;
-    case 3: k_dots<T, TL, MM><<<nb, kBlock, 0, s>>>(jobs, sd, j); break;
-    case 4: k_extend<T, TL><<<nb, kBlock, 0, s>>>(jobs, sd, j); break;
-    case 5: k_update<T, TL><<<nb, kBlock, 0, s>>>(jobs, sd); break;
-    case 7: launch_step<T, TL>(s, nb, jobs, sd, j); break;
+    case 3: MLG_MM_SWITCH(j, (k_dots<T, TL, MM><<<nb, kBlock, 0, s>>>(jobs, sd, j))); break;
+    case 4: MLG_MM_SWITCH(j, (k_extend<T, TL, MM><<<nb, kBlock, 0, s>>>(jobs, sd, j))); break;
+    case 5: MLG_MM_SWITCH(j, (k_update<T, TL, MM><<<nb, kBlock, 0, s>>>(jobs, sd))); break;
+    case 7: MLG_MM_SWITCH(j + 1, (k_step<T, TL, MM><<<nb, kBlock, 0, s>>>(jobs, sd, j))); break;
     default: k_resid<TL, false><<<nb, kBlock, 0, s>>>(jobs, sd); break;
   }
 }
@@ -232,17 +246,9 @@ enum { G_BEGIN = 0, G_RESID0 = 1, G_START = 2, G_DOTS = 3, G_EXTEND = 4, G_UPDAT
 
 using GroupFn = void (*)(hipStream_t, int, int, const Job*, const SysDesc*, int);
 
-template <class T, class TL>
-static GroupFn pick_mm(int m) {
-  if (m <= 16) return &enqueue_group_step<T, TL, 16>;
-  if (m <= 32) return &enqueue_group_step<T, TL, 32>;
-  if (m <= 40) return &enqueue_group_step<T, TL, 40>;
-  return &enqueue_group_step<T, TL, 64>;
-}
-
 template <class TL>
-static GroupFn pick_prec(int prec, int m) {
-  return prec == MLG_FP64 ? pick_mm<double, TL>(m) : pick_mm<float, TL>(m);
+static GroupFn pick_prec(int prec) {
+  return prec == MLG_FP64 ? &enqueue_group_step<double, TL> : &enqueue_group_step<float, TL>;
 }
 
 #define MLG_TILE_SWITCH(DIM, IDX, EXPR_TL)                      \
@@ -256,14 +262,15 @@ static GroupFn pick_prec(int prec, int m) {
     }                                                           \
   } else {                                                      \
     switch (IDX) {                                              \
-      case 0: { using TL = TileT<3, 64, 4, 4>; EXPR_TL; }       \
-      case 1: { using TL = TileT<3, 32, 8, 4>; EXPR_TL; }       \
-      default: { using TL = TileT<3, 64, 2, 4>; EXPR_TL; }      \
+      case 0: { using TL = TileT<3, 64, 2, 4>; EXPR_TL; }       \
+      case 1: { using TL = TileT<3, 64, 2, 2>; EXPR_TL; }       \
+      case 2: { using TL = TileT<3, 32, 4, 2>; EXPR_TL; }       \
+      default: { using TL = TileT<3, 64, 4, 4>; EXPR_TL; }      \
     }                                                           \
   }
 
-static GroupFn group_fn(int dim, int tile, int prec, int m) {
-  MLG_TILE_SWITCH(dim, tile, return pick_prec<TL>(prec, m));
+static GroupFn group_fn(int dim, int tile, int prec) {
+  MLG_TILE_SWITCH(dim, tile, return pick_prec<TL>(prec));
 }
 
 struct DevPlan {                    // device pointers of a plan inside a workspace
@@ -286,15 +293,9 @@ static DevPlan dev_plan(const Plan& P, void* ws) {
   return D;
 }
 
-// 2D grids take the fused extend + dots step (one basis sweep per Arnoldi
-// step; its recomputed halo ring is small next to the tile).  In 3D the ring
-// of a one-point-per-thread tile is larger than the tile, so 3D grids keep
-// the separate extend and dots sweeps.
-static bool fused_step(int dim) { return dim == 2; }
-
 static void enqueue_cycle(hipStream_t s, const Plan& P, const DevPlan& D, int prec, int m) {
   std::vector<GroupFn> fns;
-  for (auto& G : P.groups) fns.push_back(group_fn(G.dim, G.tile, prec, m));
+  for (auto& G : P.groups) fns.push_back(group_fn(G.dim, G.tile, prec));
   auto each = [&](int kind, int j) {
     for (size_t gi = 0; gi < P.groups.size(); ++gi)
       fns[gi](s, kind, (int)P.groups[gi].jobs.size(), D.jobs[gi], D.desc, j);
@@ -304,21 +305,23 @@ static void enqueue_cycle(hipStream_t s, const Plan& P, const DevPlan& D, int pr
   each(G_RESID0, 0);
   k_rsum<true><<<ns, kReduceThreads, 0, s>>>(D.desc);
   each(G_START, 0);
+  int maxblk = 1;
+  for (const Geo& g : P.geo) maxblk = std::max(maxblk, g.nblk);
   each(G_DOTS, 0);
-  k_coef<<<ns, kReduceThreads, 0, s>>>(D.desc, 0);
+  launch_coef(s, ns, maxblk, D.desc, 0);
   for (int j = 0; j < m; ++j) {
     for (size_t gi = 0; gi < P.groups.size(); ++gi) {
       const int nb = (int)P.groups[gi].jobs.size();
-      if (fused_step(P.groups[gi].dim)) {
+      if ((P.groups[gi].fused >> j) & 1ULL) {
         fns[gi](s, G_STEP, nb, D.jobs[gi], D.desc, j);
       } else {
         fns[gi](s, G_EXTEND, nb, D.jobs[gi], D.desc, j);
         fns[gi](s, G_DOTS, nb, D.jobs[gi], D.desc, j + 1);
       }
     }
-    k_coef<<<ns, kReduceThreads, 0, s>>>(D.desc, j + 1);
+    launch_coef(s, ns, maxblk, D.desc, j + 1);
   }
-  each(G_UPDATE, 0);
+  each(G_UPDATE, m);
   each(G_RESID, 0);
   k_rsum<false><<<ns, kReduceThreads, 0, s>>>(D.desc);
 }
@@ -385,7 +388,8 @@ static std::string plan_key(int dev, const void* ws, const Plan& P, int prec, in
     k += "|" + std::to_string(g.nx) + "," + std::to_string(g.ny) + "," + std::to_string(g.nz) +
          "," + std::to_string(g.ntiles) + "," + std::to_string(g.nblk);
   }
-  for (auto& G : P.groups) k += "#" + std::to_string(G.dim) + "," + std::to_string(G.tile);
+  for (auto& G : P.groups)
+    k += "#" + std::to_string(G.dim) + "," + std::to_string(G.tile) + "," + std::to_string(G.fused);
   return k;
 }
 
@@ -620,35 +624,18 @@ int solve(const mlg_grid* grid, const double* b, double* x, const mlg_opts* opts
 }
 
 // ------------------------------------------------------------------ kernel timing
-template <class T, class TL, int MM>
-static void enqueue_one(hipStream_t s, int kind, int nb, const Job* jobs, const SysDesc* sd, int j) {
+// One launch of a solver kernel in the solve's configuration (kind: MLG_K_*;
+// j: step index, the restart length for MLG_K_UPDATE).
+static void enqueue_one(GroupFn fn, hipStream_t s, int kind, int nb, const Job* jobs,
+                        const SysDesc* sd, int j) {
   switch (kind) {
-    case MLG_K_DOTS: k_dots<T, TL, MM><<<nb, kBlock, 0, s>>>(jobs, sd, j); break;
-    case MLG_K_COEF: k_coef<<<1, kReduceThreads, 0, s>>>(sd, j); break;
-    case MLG_K_EXTEND: k_extend<T, TL><<<nb, kBlock, 0, s>>>(jobs, sd, j); break;
-    case MLG_K_UPDATE: k_update<T, TL><<<nb, kBlock, 0, s>>>(jobs, sd); break;
-    case MLG_K_STEP: launch_step<T, TL>(s, nb, jobs, sd, j); break;
-    default: k_resid<TL, false><<<nb, kBlock, 0, s>>>(jobs, sd); break;
+    case MLG_K_DOTS: fn(s, G_DOTS, nb, jobs, sd, j); break;
+    case MLG_K_COEF: launch_coef(s, 1, nb, sd, j); break;
+    case MLG_K_EXTEND: fn(s, G_EXTEND, nb, jobs, sd, j); break;
+    case MLG_K_UPDATE: fn(s, G_UPDATE, nb, jobs, sd, j); break;
+    case MLG_K_STEP: fn(s, G_STEP, nb, jobs, sd, j); break;
+    default: fn(s, G_RESID, nb, jobs, sd, j); break;
   }
-}
-
-using OneFn = void (*)(hipStream_t, int, int, const Job*, const SysDesc*, int);
-
-template <class T, class TL>
-static OneFn pick_one_mm(int m) {
-  if (m <= 16) return &enqueue_one<T, TL, 16>;
-  if (m <= 32) return &enqueue_one<T, TL, 32>;
-  if (m <= 40) return &enqueue_one<T, TL, 40>;
-  return &enqueue_one<T, TL, 64>;
-}
-
-template <class TL>
-static OneFn pick_one(int prec, int m) {
-  return prec == MLG_FP64 ? pick_one_mm<double, TL>(m) : pick_one_mm<float, TL>(m);
-}
-
-static OneFn one_fn(int dim, int tile, int prec, int m) {
-  MLG_TILE_SWITCH(dim, tile, return pick_one<TL>(prec, m));
 }
 
 size_t kernel_bench_scratch_bytes(int reps) {
@@ -675,7 +662,7 @@ double kernel_bench(const mlg_grid* grid, const mlg_opts* opts, void* ws, size_t
   Ctrl* copies = (Ctrl*)scratch;
   SysDesc* descs = (SysDesc*)align_up((uintptr_t)((char*)scratch + (size_t)reps * sizeof(Ctrl)), 256);
   const Group& G = P.groups[0];
-  OneFn fn = one_fn(G.dim, G.tile, opts->precision, opts->restart_m);
+  GroupFn fn = group_fn(G.dim, G.tile, opts->precision);
   const int nb = (int)G.jobs.size();
   hipEvent_t e0, e1;
   MLG_HIP(hipEventCreate(&e0));
@@ -685,16 +672,141 @@ double kernel_bench(const mlg_grid* grid, const mlg_opts* opts, void* ws, size_t
     ~Gd() { hipEventDestroy(a); hipEventDestroy(b); }
   } guard{e0, e1};
   k_bench_setup<<<reps, 256, 0, stream>>>(D.desc, descs, copies, reps);
-  fn(stream, kind, nb, D.jobs[0], descs, j);                  // untimed warm-up launch
+  const int jj = kind == MLG_K_UPDATE ? opts->restart_m : j;
+  enqueue_one(fn, stream, kind, nb, D.jobs[0], descs, jj);    // untimed warm-up launch
   k_bench_setup<<<reps, 256, 0, stream>>>(D.desc, descs, copies, reps);
   MLG_HIP(hipEventRecord(e0, stream));
-  for (int i = 0; i < reps; ++i) fn(stream, kind, nb, D.jobs[0], descs + i, j);
+  for (int i = 0; i < reps; ++i) enqueue_one(fn, stream, kind, nb, D.jobs[0], descs + i, jj);
   MLG_HIP(hipEventRecord(e1, stream));
   MLG_HIP(hipGetLastError());
   MLG_HIP(hipEventSynchronize(e1));
   float ms = 0.f;
   MLG_HIP(hipEventElapsedTime(&ms, e0, e1));
   return 1000.0 * ms / reps;
+}
+
+// ------------------------------------------------------------------ autotuner
+constexpr int kTuneReps = 5;
+
+// Synthetic right-hand side for tuning (a fixed smooth field plus a hashed
+// perturbation) and a zero initial guess.
+__global__ void k_tune_fill(double* b, double* x, long long n) {
+  const long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= n) return;
+  unsigned int h = (unsigned int)p * 2654435761u;
+  h ^= h >> 15;
+  h *= 2246822519u;
+  h ^= h >> 13;
+  b[p] = 1.0 + 0.5 * ((double)(h & 0xffff) / 65536.0 - 0.5);
+  x[p] = 0.0;
+}
+
+static size_t tune_solve_bytes(const mlg_grid* grid, const mlg_opts* opts) {
+  size_t mx = 0;
+  for (int t = 0; t < tile_count(grid->dim); ++t) {
+    mlg_opts o = *opts;
+    o.tile = t + 1;
+    mlg_system s1 = single(grid, nullptr, nullptr);
+    mx = std::max(mx, make_plan(1, &s1, o).total);
+  }
+  return align_up(mx, 256);
+}
+
+size_t autotune_workspace_bytes(const mlg_grid* grid, const mlg_opts* opts) {
+  check_grid(grid);
+  check_opts(opts, grid->dim);
+  const size_t n = npoints(*grid);
+  return tune_solve_bytes(grid, opts) + 2 * align_up(n * 8, 256) +
+         align_up(kernel_bench_scratch_bytes(kTuneReps), 256);
+}
+
+int autotune(const mlg_grid* grid, const mlg_opts* opts, void* ws, size_t ws_bytes, int* tile_out,
+             unsigned long long* fused_out, hipStream_t stream) {
+  check_grid(grid);
+  check_opts(opts, grid->dim);
+  if (!ws || ws_bytes < autotune_workspace_bytes(grid, opts) || (uintptr_t)ws % 256)
+    throw ArgError{MLG_ERR_WORKSPACE, "autotune workspace too small or misaligned"};
+  const size_t n = npoints(*grid);
+  const size_t solve_bytes = tune_solve_bytes(grid, opts);
+  char* base = (char*)ws;
+  double* b = (double*)(base + solve_bytes);
+  double* x = (double*)(base + solve_bytes + align_up(n * 8, 256));
+  char* scratch = base + solve_bytes + 2 * align_up(n * 8, 256);
+  const size_t scratch_bytes = align_up(kernel_bench_scratch_bytes(kTuneReps), 256);
+  const int m = opts->restart_m;
+  const bool two_d = grid->dim == 2;
+  // step indices sampled; costs in between are interpolated linearly
+  std::vector<int> js;
+  for (int q = 0; q <= 4; ++q) js.push_back(std::min(m - 1, q * (m - 1) / 4));
+  js.push_back(std::min(1, m - 1));
+  std::sort(js.begin(), js.end());
+  js.erase(std::unique(js.begin(), js.end()), js.end());
+  auto interp = [&](const std::vector<double>& v, int j) {
+    size_t i = 0;
+    while (i + 1 < js.size() && js[i + 1] < j) ++i;
+    if (i + 1 >= js.size() || js[i] >= j) return v[i];
+    const double w = double(j - js[i]) / double(js[i + 1] - js[i]);
+    return (1.0 - w) * v[i] + w * v[i + 1];
+  };
+  // stage 1: per tile, the per-step choice between the separate and the
+  // fused sweeps, from kernel timings
+  TuneEntry te{};
+  for (int t = 0; t < tile_count(grid->dim); ++t) {
+    mlg_opts o = *opts;
+    o.tile = t + 1;
+    o.schedule = 1;
+    o.fixed_iters = m;                         // one full cycle fills the basis
+    o.max_iters = 0;
+    k_tune_fill<<<(unsigned)((n + 255) / 256), 256, 0, stream>>>(b, x, (long long)n);
+    MLG_HIP(hipGetLastError());
+    solve(grid, b, x, &o, ws, solve_bytes, nullptr, stream);
+    auto bench = [&](int kind, int j) {
+      return kernel_bench(grid, &o, ws, solve_bytes, scratch, scratch_bytes, kind, j, kTuneReps,
+                          stream);
+    };
+    unsigned long long mask = 0;
+    if (two_d) {
+      std::vector<double> sep, fus;
+      for (int j : js) {
+        sep.push_back(bench(MLG_K_EXTEND, j) + bench(MLG_K_DOTS, j + 1));
+        fus.push_back(bench(MLG_K_STEP, j));
+      }
+      for (int j = 0; j < m; ++j)
+        if (interp(fus, j) < interp(sep, j)) mask |= 1ULL << j;
+    }
+    te.fused[t] = mask;
+  }
+  // stage 2: the tile whose whole restart cycles (graph launches, every
+  // kernel, the host poll) are fastest with its schedule
+  te.tile = default_tile(*grid, *opts);
+  autotune_store(*grid, *opts, te);
+  double best = 1e300;
+  for (int t = 0; t < tile_count(grid->dim); ++t) {
+    mlg_opts o = *opts;
+    o.tile = t + 1;
+    o.schedule = 0;                            // the stage-1 mask of this tile
+    o.fixed_iters = 2 * m;
+    o.max_iters = 0;
+    o.poll_cycles = 2;
+    double dt = 1e300;
+    for (int rep = 0; rep < 3; ++rep) {        // the first run also captures the graph
+      k_tune_fill<<<(unsigned)((n + 255) / 256), 256, 0, stream>>>(b, x, (long long)n);
+      MLG_HIP(hipGetLastError());
+      MLG_HIP(hipStreamSynchronize(stream));
+      const auto t0 = std::chrono::steady_clock::now();
+      solve(grid, b, x, &o, ws, solve_bytes, nullptr, stream);
+      const auto t1 = std::chrono::steady_clock::now();
+      if (rep > 0) dt = std::min(dt, std::chrono::duration<double>(t1 - t0).count());
+    }
+    if (dt < best) {
+      best = dt;
+      te.tile = t;
+    }
+  }
+  autotune_store(*grid, *opts, te);
+  if (tile_out) *tile_out = te.tile + 1;
+  if (fused_out) *fused_out = te.fused[te.tile];
+  return MLG_OK;
 }
 
 // ------------------------------------------------------------------ operator

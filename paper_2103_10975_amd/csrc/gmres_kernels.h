@@ -258,50 +258,6 @@ __device__ __forceinline__ Mine mine(const Job* jobs, const SysDesc* sd) {
   return me;
 }
 
-// Block sums of the live slots of acc (slot k lands in column col(k)); each
-// workgroup writes its own entry of every live partial column.  Per chunk of
-// 16 slots a wavefront transposes its lanes' values through LDS (tr: 64 x 17
-// doubles per wavefront), four lanes sum 16 lanes each in a fixed order and
-// two lane exchanges combine them -- the same sums in every lane, so the
-// result is bitwise reproducible; then the four wavefronts are added.
-constexpr int kTrPitch = 17;
-template <int NV, class Live, class Col>
-__device__ __forceinline__ void store_partials(const double (&acc)[NV], Live live, Col col,
-                                               double* red, double* tr, gptr<double> part, int nblk,
-                                               int lblk) {
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  double* trw = tr + wave * 64 * kTrPitch;
-  const int sl = lane & 15, pq = lane >> 4;
-#pragma unroll
-  for (int k0 = 0; k0 < NV; k0 += 16) {
-    bool any = false;
-#pragma unroll
-    for (int q = 0; q < 16; ++q)
-      if (k0 + q < NV) any = any || live(k0 + q);
-    if (!any) continue;
-#pragma unroll
-    for (int q = 0; q < 16; ++q)
-      if (k0 + q < NV) trw[lane * kTrPitch + q] = acc[k0 + q];
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    double v = 0.0;
-#pragma unroll
-    for (int i = 0; i < 16; ++i) v += trw[(pq * 16 + i) * kTrPitch + sl];
-    v += __shfl_xor(v, 16, 64);
-    v += __shfl_xor(v, 32, 64);
-    if (pq == 0 && k0 + sl < NV && live(k0 + sl)) red[wave * NV + k0 + sl] = v;
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-  }
-  __syncthreads();
-  for (int k = threadIdx.x; k < NV; k += kBlock)
-    if (live(k))
-      part[(size_t)col(k) * nblk + lblk] =
-          ((red[k] + red[NV + k]) + red[2 * NV + k]) + red[3 * NV + k];
-}
-
 // A finished right-hand side: record its statistics and move on to the next
 // one (phase INIT) or mark the system done.  One thread.
 __device__ inline void finish_rhs(gptr<Ctrl> C) {
@@ -329,6 +285,70 @@ __device__ __forceinline__ double lane_bcast(double v, int src) {
   const int lo = __builtin_amdgcn_readlane(__double2loint(v), src);
   const int hi = __builtin_amdgcn_readlane(__double2hiint(v), src);
   return __hiloint2double(hi, lo);
+}
+
+// The basis at N points per thread, every load issued at once and
+// unconditionally: slots k >= `live` re-read the last live vector (or
+// vector 0) and are never used, so no branch separates the loads.
+template <int MM, int N, class T>
+__device__ __forceinline__ void load_basis(T (&v)[MM][N], gptr<const T> V, long long ldv,
+                                           const long long (&p)[N], int live) {
+  const int last = live > 0 ? live - 1 : 0;
+#pragma unroll
+  for (int k = 0; k < MM; ++k) {
+    const gptr<const T> Vk = V + (size_t)(k < live ? k : last) * ldv;
+#pragma unroll
+    for (int i = 0; i < N; ++i) v[k][i] = Vk[p[i]];
+  }
+}
+
+// Products of the first `live` basis slots with x and y at this thread's
+// points, folded across the wavefront in chunks of 8 slots (16 sums each)
+// into acc[c]; `last` (4 further sums) goes to acc[MM / 8].
+template <int MM, int N, class T>
+__device__ __forceinline__ void fold_products(double (&acc)[MM / 8 + 1], const T (&v)[MM][N],
+                                              const double (&x)[N], const double (&y)[N],
+                                              const double (&last)[4], int live) {
+#pragma unroll
+  for (int c = 0; c < MM / 8; ++c)
+    if (8 * c < live) {
+      double prod[16];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        prod[q] = 0.0;
+        prod[8 + q] = 0.0;
+#pragma unroll
+        for (int i = 0; i < N; ++i) {
+          prod[q] = fma((double)v[8 * c + q][i], x[i], prod[q]);
+          prod[8 + q] = fma((double)v[8 * c + q][i], y[i], prod[8 + q]);
+        }
+      }
+      acc[c] += rs16(prod);
+    }
+  acc[MM / 8] += rs4(last);
+}
+
+// Block sums of the folded products into this workgroup's partial columns.
+// Sum index k < 16 * (MM / 8): basis slot 8 * (k / 16) + (k % 8), the x
+// product for k % 16 < 8, else the y product; then the 4 `last` sums.
+// col(slot, is_y) / col_last(f) give the partial column, or -1 for none.
+template <int MM, class ColFn, class LastFn>
+__device__ __forceinline__ void store_folded(const double (&acc)[MM / 8 + 1], double* red,
+                                             gptr<double> part, int nblk, int lblk, ColFn col,
+                                             LastFn col_last) {
+  constexpr int NCH = MM / 8, NS = 16 * NCH + 4;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if ((lane & 3) == 0) {
+#pragma unroll
+    for (int c = 0; c < NCH; ++c) red[wave * NS + 16 * c + rs16_slot(lane)] = acc[c];
+  }
+  if ((lane & 15) == 0) red[wave * NS + 16 * NCH + rs4_slot(lane)] = acc[NCH];
+  __syncthreads();
+  for (int k = threadIdx.x; k < NS; k += kBlock) {
+    const int cl = k < 16 * NCH ? col(8 * (k >> 4) + (k & 7), (k & 15) >= 8) : col_last(k - 16 * NCH);
+    if (cl >= 0)
+      part[(size_t)cl * nblk + lblk] = ((red[k] + red[NS + k]) + red[2 * NS + k]) + red[3 * NS + k];
+  }
 }
 
 // ---------------------------------------------------------------- kernels
@@ -361,34 +381,48 @@ __global__ __launch_bounds__(kBlock) void k_resid(const Job* jobs, const SysDesc
   const Mine me = mine(jobs, sd);
   const gptr<const Ctrl> C = gmem((const Ctrl*)me.S->C);
   if (C->phase != (INIT ? PH_INIT : PH_RUN)) return;
+  constexpr int PPT = TL::PPT;
   __shared__ double L[TL::LSZ];
-  __shared__ double red[4 * 2];
-  __shared__ double tr[4 * 64 * kTrPitch];
+  __shared__ double red[4 * 4];
   const Geo g = me.S->g;
   gptr<const double> b = gmem(C->b0) + (size_t)C->rhs * g.n;
-  const gptr<double> x = gmem(C->x0) + (size_t)C->rhs * g.n;
+  gptr<const double> x = gmem((const double*)C->x0) + (size_t)C->rhs * g.n;
   gptr<double> r = gmem(me.S->r);
-  double acc[2] = {0.0, 0.0};
+  double acc[1] = {0.0};
   for (int tile = me.job.t0; tile < me.job.t1; ++tile) {
     int ox, oy, oz;
     tile_origin<TL>(g, tile, ox, oy, oz);
+    long long pp[PPT];
+    bool ok[PPT];
+    int qc[PPT][3];
+    double bv[PPT];
+#pragma unroll
+    for (int i = 0; i < PPT; ++i) {
+      auto pr = point<TL>(g, ox, oy, oz, i);
+      ok[i] = pr.valid;
+      pp[i] = pr.valid ? pr.p : 0;
+      qc[i][0] = pr.qx;
+      qc[i][1] = pr.qy;
+      qc[i][2] = pr.qz;
+      bv[i] = b[pp[i]];
+    }
     __syncthreads();
     load_tile<TL>(L, x, g, ox, oy, oz);
     __syncthreads();
+    double last[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-    for (int i = 0; i < TL::PPT; ++i) {
-      auto pr = point<TL>(g, ox, oy, oz, i);
-      if (pr.valid) {
-        const double bi = b[pr.p];
-        const double ri = bi - stencil<TL>(L, g, pr.qx, pr.qy, pr.qz);
-        r[pr.p] = ri;
-        acc[0] += ri * ri;
-        acc[1] += bi * bi;
+    for (int i = 0; i < PPT; ++i)
+      if (ok[i]) {
+        const double ri = bv[i] - stencil<TL>(L, g, qc[i][0], qc[i][1], qc[i][2]);
+        r[pp[i]] = ri;
+        last[0] = fma(ri, ri, last[0]);
+        last[1] = fma(bv[i], bv[i], last[1]);
       }
-    }
+    acc[0] += rs4(last);
   }
-  store_partials<2>(acc, [](int k) { return INIT || k == 0; }, [](int k) { return k; }, red, tr,
-                    gmem(me.S->part), g.nblk, me.job.lblk);
+  store_folded<0>(acc, red, gmem(me.S->part), g.nblk, me.job.lblk,
+                  [](int, bool) { return -1; },
+                  [](int f) { return f == 0 || (INIT && f == 1) ? f : -1; });
 }
 
 // beta = |r| (and |b| when starting): one workgroup per system.
@@ -476,186 +510,225 @@ __global__ __launch_bounds__(kBlock) void k_start(const Job* jobs, const SysDesc
 
 // dots(j): w = A u_j; partials of s = V_{j-1}^T u_j (columns 0..j-1),
 // t = V_{j-1}^T w (columns j..2j-1), u^T u (column 2j), u^T w (column 2j+1).
-// The basis is read in chunks of KC vectors whose loads are all issued before
-// any is consumed (indices clamped into the live range, so no branch splits a
-// chunk), which keeps KC x PPT loads in flight per lane.
+// MM >= j bounds the basis slots held in registers; all loads of a tile are
+// issued before any is used.
 template <class T, class TL, int MM>
 __global__ __launch_bounds__(kBlock) void k_dots(const Job* jobs, const SysDesc* sd, int j) {
   const Mine me = mine(jobs, sd);
   const gptr<const Ctrl> C = gmem((const Ctrl*)me.S->C);
   if (C->phase != PH_RUN || C->cycle_end) return;
-  constexpr int NV = 2 * MM + 2;     // s in 0..MM-1, t in MM..2MM-1, nu, mu
   constexpr int PPT = TL::PPT;
-  constexpr int KC0 = PPT >= 4 ? 8 : (PPT == 2 ? 16 : 32);
-  constexpr int KC = KC0 < MM ? KC0 : MM;
+  constexpr int NS = 16 * (MM / 8) + 4;
   __shared__ double L[TL::LSZ];
-  __shared__ double red[4 * NV];
-  __shared__ double tr[4 * 64 * kTrPitch];
+  __shared__ double red[4 * NS];
   const Geo g = me.S->g;
   const gptr<const T> V = gmem((const T*)me.S->V);
   const gptr<const T> U = V + (size_t)(C->m + (j & 1)) * g.ldv;
-  double acc[NV];
+  double acc[MM / 8 + 1];
 #pragma unroll
-  for (int k = 0; k < NV; ++k) acc[k] = 0.0;
+  for (int c = 0; c <= MM / 8; ++c) acc[c] = 0.0;
   for (int tile = me.job.t0; tile < me.job.t1; ++tile) {
     int ox, oy, oz;
     tile_origin<TL>(g, tile, ox, oy, oz);
-    __syncthreads();
-    load_tile<TL>(L, U, g, ox, oy, oz);
-    __syncthreads();
-    double uu[PPT], ww[PPT];
     long long pp[PPT];
+    bool ok[PPT];
+    int qc[PPT][3];
 #pragma unroll
     for (int i = 0; i < PPT; ++i) {
       auto pr = point<TL>(g, ox, oy, oz, i);
+      ok[i] = pr.valid;
       pp[i] = pr.valid ? pr.p : 0;
-      uu[i] = pr.valid ? centre<TL>(L, pr.qx, pr.qy, pr.qz) : 0.0;
-      ww[i] = pr.valid ? stencil<TL>(L, g, pr.qx, pr.qy, pr.qz) : 0.0;
-      acc[2 * MM] += uu[i] * uu[i];
-      acc[2 * MM + 1] += uu[i] * ww[i];
+      qc[i][0] = pr.qx;
+      qc[i][1] = pr.qy;
+      qc[i][2] = pr.qz;
     }
+    T vr[MM][PPT];
+    load_basis<MM, PPT, T>(vr, V, g.ldv, pp, j);
+    __syncthreads();
+    load_tile<TL>(L, U, g, ox, oy, oz);
+    __syncthreads();
+    double uu[PPT], ww[PPT], last[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-    for (int kc = 0; kc < MM; kc += KC) {
-      if (kc >= j) break;
-      double v[KC][PPT];
-#pragma unroll
-      for (int q = 0; q < KC; ++q) {
-        const int ks = kc + q < j ? kc + q : j - 1;
-#pragma unroll
-        for (int i = 0; i < PPT; ++i) v[q][i] = (double)V[(size_t)ks * g.ldv + pp[i]];
-      }
-#pragma unroll
-      for (int q = 0; q < KC; ++q)
-        if (kc + q < j && kc + q < MM) {
-#pragma unroll
-          for (int i = 0; i < PPT; ++i) {
-            acc[kc + q] += v[q][i] * uu[i];
-            acc[MM + kc + q] += v[q][i] * ww[i];
-          }
-        }
+    for (int i = 0; i < PPT; ++i) {
+      uu[i] = ok[i] ? centre<TL>(L, qc[i][0], qc[i][1], qc[i][2]) : 0.0;
+      ww[i] = ok[i] ? stencil<TL>(L, g, qc[i][0], qc[i][1], qc[i][2]) : 0.0;
+      last[0] = fma(uu[i], uu[i], last[0]);
+      last[1] = fma(uu[i], ww[i], last[1]);
     }
+    fold_products<MM, PPT, T>(acc, vr, uu, ww, last, j);
   }
-  store_partials<NV>(
-      acc, [j](int k) { return (k < MM && k < j) || (k >= MM && k < MM + j) || k >= 2 * MM; },
-      [j](int k) { return k < MM ? k : (k < 2 * MM ? j + (k - MM) : 2 * j + (k - 2 * MM)); }, red,
-      tr, gmem(me.S->part), g.nblk, me.job.lblk);
+  store_folded<MM>(acc, red, gmem(me.S->part), g.nblk, me.job.lblk,
+                   [j](int slot, bool y) { return slot < j ? (y ? j + slot : slot) : -1; },
+                   [j](int f) { return f < 2 ? 2 * j + f : -1; });
 }
 
-// coef(j): one workgroup per system.  All threads stage the small per-cycle
-// state into LDS while they sum the partials; wavefront 0 then completes
-// Hessenberg column j-1 (second projection), applies the Givens rotations
-// (lane-parallel data, uniform loop with lane broadcasts), tests for the end
-// of the cycle (back substitution if so) and prepares the coefficients of
-// extend(j).  For a zero right-hand side, coef(0) ends the RHS.
+// coef(j): one workgroup per system.  Every global load of the launch (the
+// first round of partials, the Hessenberg columns, wavefront 0's per-row
+// state) is issued at once and consumed before the state is tested, so their
+// latencies overlap.  Wavefront 0 then completes Hessenberg column j-1
+// (second projection), applies the Givens rotations (lane-parallel data,
+// uniform loop with lane broadcasts), tests for the end of the cycle (back
+// substitution if so, with R staged by all threads) and prepares the
+// coefficients of the next sweep.  For a zero right-hand side, coef(0) ends
+// the RHS.
+template <int NB>
 __global__ __launch_bounds__(kReduceThreads) void k_coef(const SysDesc* sd, int j) {
-  const SysDesc* S = sd + blockIdx.x;
-  const gptr<Ctrl> C = gmem(S->C);
-  if (j == 0 && C->phase == PH_ZERO) {
-    if (threadIdx.x == 0) finish_rhs(C);
-    return;
-  }
-  if (C->phase != PH_RUN || C->cycle_end) return;
   constexpr int LDH = kMaxRestart + 1;
+  constexpr int HPT = (kMaxRestart * LDH + kReduceThreads - 1) / kReduceThreads;
+  constexpr int RPT = (kMaxRestart * kMaxRestart + kReduceThreads - 1) / kReduceThreads;
   __shared__ double fin[2 * kMaxRestart + 2];
   // Hessenberg columns (for z) or, at the end of a cycle, the rotated R
   __shared__ double HuS[kMaxRestart * LDH];
+  __shared__ int flag;
   double* Rs = HuS;
-  // Hessenberg columns 0..j-2 (rows <= c+1) for z = Hbar s
-  for (int e = threadIdx.x; e < (j > 1 ? (j - 1) * LDH : 0); e += kReduceThreads)
-    HuS[e] = C->Hu[e];
-  // wavefront 0's per-row state, loaded together with the partials
-  const int lane = threadIdx.x;
-  const bool w0 = threadIdx.x < 64;
+  const SysDesc* S = sd + blockIdx.x;
+  const gptr<Ctrl> C = gmem(S->C);
+  const gptr<const double> part = gmem((const double*)S->part);
+  const int nblk = S->g.nblk;
+  const int ncols = 2 * j + 2;
+  const int tid = threadIdx.x, lane = tid;
+  const bool w0 = tid < 64;
   const int c = j - 1;
-  const double hpi = (w0 && lane < j) ? C->hprev[lane] : 0.0;
-  const double csl = (w0 && lane < c) ? C->cs[lane] : 0.0;
-  const double snl = (w0 && lane < c) ? C->sn[lane] : 0.0;
-  const double gc = (w0 && j > 0) ? C->g[c] : 0.0;
-  const double glane = (w0 && lane < j) ? C->g[lane] : 0.0;
-  reduce_partials(gmem((const double*)S->part), S->g.nblk, 2 * j + 2, fin);
-  if (!w0) return;
-  // ---- wavefront 0: lane i owns row i (j <= 64)
-  const double nu = fin[2 * j], mu = fin[2 * j + 1];
-  const double si = lane < j ? fin[lane] : 0.0;
-  const double ti = lane < j ? fin[j + lane] : 0.0;
-  const double ss = wave_sum(si * si), hh = wave_sum(hpi * hpi), st = wave_sum(si * ti);
-  double alpha;
-  if (j == 0) {
-    alpha = sqrt(nu);
-  } else {
-    // |u_j - V s|^2 = |u_j|^2 - |s|^2 (V orthonormal)
-    alpha = sqrt(fmax(nu - ss, 0.0));
-    // Hessenberg column c: first + second projection, subdiagonal alpha
-    const double coli = lane < j ? hpi + si : (lane == j ? alpha : 0.0);
-    if (lane <= j) {
-      C->Hu[(size_t)c * LDH + lane] = coli;
-      HuS[(size_t)c * LDH + lane] = coli;
-    }
-    // rotations G_0..G_{c-1}: carry the running entry down the column
-    double carry = lane_bcast(coli, 0);
-    double rot = 0.0;                 // rotated entry of this lane's row
-    for (int i = 0; i < c; ++i) {
-      const double a = carry, bb = lane_bcast(coli, i + 1);
-      const double ci = lane_bcast(csl, i), sni = lane_bcast(snl, i);
-      if (lane == i) rot = ci * a + sni * bb;
-      carry = -sni * a + ci * bb;
-    }
-    const double den = hypot(carry, alpha);
-    double cc = 1.0, sn = 0.0;
-    if (den != 0.0) {
-      cc = carry / den;
-      sn = alpha / den;
-    }
-    if (lane == c) rot = den;
-    if (lane <= c) C->R[c * kMaxRestart + lane] = rot;
-    const double est = fabs(sn * gc);
-    const long long iters = C->s.iters + 1;
-    // breakdown: the new direction is rounding noise relative to A v_{j-1}
-    // (|A v_{j-1}|^2 = |u_j|^2 + |h_{j-1}|^2)
-    const bool breakdown = alpha <= 1e-14 * sqrt(nu + hh);
-    const bool bad = !isfinite(alpha) || !isfinite(est);
-    const bool stop = bad || iters >= C->limit || breakdown ||
-                      (!C->fixed && est <= C->tol_abs) || j == C->m;
-    if (lane == 0) {
-      C->cs[c] = cc;
-      C->sn[c] = sn;
-      C->g[c + 1] = -sn * gc;
-      C->g[c] = cc * gc;
-      C->s.iters = iters;
-      C->k = j;
-      C->s.relres_est = est / C->bnorm;
-      atomicAdd(C->done + 1, 1u);
-      if (bad) {
-        C->s.status = MLG_ERR_NONFINITE;
-        finish_rhs(C);
-      }
-    }
-    if (bad) return;
-    if (stop) {
-      // back substitution R y = g (R: j x j upper triangular), row i on lane i
-      for (int e = lane; e < j * kMaxRestart; e += 64) Rs[e] = C->R[e];
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-      __builtin_amdgcn_wave_barrier();
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-      const double gl = lane < j ? (lane == c ? cc * gc : glane) : 0.0;
-      double accl = 0.0, yl = 0.0;
-      for (int i = j - 1; i >= 0; --i) {
-        const double yi = lane_bcast((gl - accl) / (lane < j ? Rs[lane * kMaxRestart + lane] : 1.0), i);
-        if (lane == i) yl = yi;
-        if (lane < i) accl += Rs[i * kMaxRestart + lane] * yi;
-      }
-      if (lane < j) C->y[lane] = yl;
-      if (lane == 0) C->cycle_end = 1;
-      return;
-    }
+  // ---- all loads at once (clamped indices: the buffers are valid memory)
+  PartialsRound<NB> r0;
+  partials_load(r0, part, nblk, ncols, 0);
+  const int hlim = j > 1 ? (j - 1) * LDH : 0;        // columns 0..j-2 (rows <= c+1)
+  double hv[HPT];
+#pragma unroll
+  for (int k = 0; k < HPT; ++k) {
+    const int e = tid + kReduceThreads * k;
+    hv[k] = 0.0;
+    if (e < hlim) hv[k] = C->Hu[e];
   }
+  const double hpi = C->hprev[w0 && lane < j ? lane : 0];
+  const double csl = C->cs[w0 && lane < c ? lane : 0];
+  const double snl = C->sn[w0 && lane < c ? lane : 0];
+  const double gc = C->g[j > 0 ? c : 0];
+  const double glane = C->g[w0 && lane < j ? lane : 0];
+  partials_sum(r0, nblk, ncols, 0, fin);
+#pragma unroll
+  for (int k = 0; k < HPT; ++k) {
+    const int e = tid + kReduceThreads * k;
+    if (e < hlim) HuS[e] = hv[k];
+  }
+  for (int c0 = PartialsRound<NB>::kCols; c0 < ncols; c0 += PartialsRound<NB>::kCols) {
+    PartialsRound<NB> r;
+    partials_load(r, part, nblk, ncols, c0);
+    partials_sum(r, nblk, ncols, c0, fin);
+  }
+  if (j == 0 && C->phase == PH_ZERO) {
+    if (tid == 0) finish_rhs(C);
+    return;
+  }
+  if (C->phase != PH_RUN || C->cycle_end) return;
+  __syncthreads();
+  // ---- wavefront 0: lane i owns row i (j <= 64)
+  double nu = 0.0, mu = 0.0, si = 0.0, ti = 0.0, st = 0.0, alpha = 0.0;
+  double cc = 1.0, gnew = 0.0, rot = 0.0;
+  if (w0) {
+    nu = fin[2 * j];
+    mu = fin[2 * j + 1];
+    si = lane < j ? fin[lane] : 0.0;
+    ti = lane < j ? fin[j + lane] : 0.0;
+    const double hpl = lane < j ? hpi : 0.0;
+    const double ss = wave_sum(si * si), hh = wave_sum(hpl * hpl);
+    st = wave_sum(si * ti);
+    int fl = 0;                                       // 0 continue, 1 end of cycle, 2 failed
+    if (j == 0) {
+      alpha = sqrt(nu);
+    } else {
+      // |u_j - V s|^2 = |u_j|^2 - |s|^2 (V orthonormal)
+      alpha = sqrt(fmax(nu - ss, 0.0));
+      // Hessenberg column c: first + second projection, subdiagonal alpha
+      const double coli = lane < j ? hpl + si : (lane == j ? alpha : 0.0);
+      if (lane <= j) {
+        C->Hu[(size_t)c * LDH + lane] = coli;
+        HuS[(size_t)c * LDH + lane] = coli;
+      }
+      // rotations G_0..G_{c-1}: carry the running entry down the column
+      const double csv = lane < c ? csl : 0.0, snv = lane < c ? snl : 0.0;
+      double carry = lane_bcast(coli, 0);
+      for (int i = 0; i < c; ++i) {
+        const double a = carry, bb = lane_bcast(coli, i + 1);
+        const double ci = lane_bcast(csv, i), sni = lane_bcast(snv, i);
+        if (lane == i) rot = ci * a + sni * bb;
+        carry = -sni * a + ci * bb;
+      }
+      const double den = hypot(carry, alpha);
+      double sn = 0.0;
+      if (den != 0.0) {
+        cc = carry / den;
+        sn = alpha / den;
+      }
+      if (lane == c) rot = den;
+      if (lane <= c) C->R[c * kMaxRestart + lane] = rot;
+      gnew = cc * gc;
+      const double est = fabs(sn * gc);
+      const long long iters = C->s.iters + 1;
+      // breakdown: the new direction is rounding noise relative to A v_{j-1}
+      // (|A v_{j-1}|^2 = |u_j|^2 + |h_{j-1}|^2)
+      const bool breakdown = alpha <= 1e-14 * sqrt(nu + hh);
+      const bool bad = !isfinite(alpha) || !isfinite(est);
+      const bool stop = bad || iters >= C->limit || breakdown ||
+                        (!C->fixed && est <= C->tol_abs) || j == C->m;
+      if (lane == 0) {
+        C->cs[c] = cc;
+        C->sn[c] = sn;
+        C->g[c + 1] = -sn * gc;
+        C->g[c] = gnew;
+        C->s.iters = iters;
+        C->k = j;
+        C->s.relres_est = est / C->bnorm;
+        atomicAdd(C->done + 1, 1u);
+        if (bad) {
+          C->s.status = MLG_ERR_NONFINITE;
+          finish_rhs(C);
+        }
+      }
+      fl = bad ? 2 : (stop ? 1 : 0);
+    }
+    if (lane == 0) flag = fl;
+  }
+  __syncthreads();
+  const int fl = flag;
+  if (fl == 2) return;
+  if (fl == 1) {
+    // back substitution R y = g (R: j x j upper triangular), row i on lane i;
+    // columns 0..c-1 come from memory (staged by all threads), column c is
+    // wavefront 0's register
+    const int rlim = c * kMaxRestart;
+    double rv[RPT];
+#pragma unroll
+    for (int k = 0; k < RPT; ++k) {
+      const int e = tid + kReduceThreads * k;
+      rv[k] = 0.0;
+      if (e < rlim) rv[k] = C->R[e];
+    }
+    __syncthreads();                                  // HuS is no longer read
+#pragma unroll
+    for (int k = 0; k < RPT; ++k) {
+      const int e = tid + kReduceThreads * k;
+      if (e < rlim) Rs[e] = rv[k];
+    }
+    if (w0 && lane <= c) Rs[c * kMaxRestart + lane] = rot;
+    __syncthreads();
+    if (!w0) return;
+    const double gl = lane < j ? (lane == c ? gnew : glane) : 0.0;
+    double accl = 0.0, yl = 0.0;
+    for (int i = j - 1; i >= 0; --i) {
+      const double yi = lane_bcast((gl - accl) / (lane < j ? Rs[lane * kMaxRestart + lane] : 1.0), i);
+      if (lane == i) yl = yi;
+      if (lane < i) accl += Rs[i * kMaxRestart + lane] * yi;
+    }
+    if (lane < j) C->y[lane] = yl;
+    if (lane == 0) C->cycle_end = 1;
+    return;
+  }
+  if (!w0) return;
   // h_i = v_i^T A v_j with A v_j = (w - V_j z) / alpha, z = Hbar_{j-1} s
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
   double z = 0.0;
   if (lane <= j)
-    for (int c = (lane > 0 ? lane - 1 : 0); c < j; ++c) z += HuS[(size_t)c * LDH + lane] * fin[c];
+    for (int cc2 = (lane > 0 ? lane - 1 : 0); cc2 < j; ++cc2) z += HuS[(size_t)cc2 * LDH + lane] * fin[cc2];
   if (lane <= j) {
     const double vw = lane < j ? ti : (mu - st) / alpha;
     const double h = (vw - z) / alpha;
@@ -667,15 +740,16 @@ __global__ __launch_bounds__(kReduceThreads) void k_coef(const SysDesc* sd, int 
 }
 
 // extend(j): v_j = (u_j - V_{j-1} s) / alpha, u_{j+1} = w/alpha - V_j cY.
-template <class T, class TL>
+template <class T, class TL, int MM>
 __global__ __launch_bounds__(kBlock) void k_extend(const Job* jobs, const SysDesc* sd, int j) {
   const Mine me = mine(jobs, sd);
   const gptr<const Ctrl> C = gmem((const Ctrl*)me.S->C);
   if (C->phase != PH_RUN || C->cycle_end) return;
+  constexpr int PPT = TL::PPT;
   __shared__ double L[TL::LSZ];
-  __shared__ double sY[kMaxRestart + 1], cY[kMaxRestart + 1];
+  __shared__ double sY[MM], cY[MM + 1];
   for (int k = threadIdx.x; k <= j; k += kBlock) {
-    sY[k] = C->sY[k];
+    if (k < j) sY[k] = C->sY[k];
     cY[k] = C->cY[k];
   }
   const Geo g = me.S->g;
@@ -683,53 +757,43 @@ __global__ __launch_bounds__(kBlock) void k_extend(const Job* jobs, const SysDes
   const gptr<const T> U = V + (size_t)(C->m + (j & 1)) * g.ldv;
   const gptr<T> Unext = V + (size_t)(C->m + ((j + 1) & 1)) * g.ldv;
   const double ainv = 1.0 / C->alpha;
-  constexpr int PPT = TL::PPT;
-  constexpr int KC = PPT >= 4 ? 8 : (PPT == 2 ? 16 : 32);
   for (int tile = me.job.t0; tile < me.job.t1; ++tile) {
     int ox, oy, oz;
     tile_origin<TL>(g, tile, ox, oy, oz);
-    __syncthreads();
-    load_tile<TL>(L, U, g, ox, oy, oz);
-    __syncthreads();
-    double uu[PPT], ww[PPT], a[PPT], bs[PPT];
     long long pp[PPT];
     bool ok[PPT];
+    int qc[PPT][3];
 #pragma unroll
     for (int i = 0; i < PPT; ++i) {
       auto pr = point<TL>(g, ox, oy, oz, i);
       ok[i] = pr.valid;
       pp[i] = pr.valid ? pr.p : 0;
-      uu[i] = pr.valid ? centre<TL>(L, pr.qx, pr.qy, pr.qz) : 0.0;
-      ww[i] = pr.valid ? stencil<TL>(L, g, pr.qx, pr.qy, pr.qz) : 0.0;
-      a[i] = 0.0;
-      bs[i] = 0.0;
+      qc[i][0] = pr.qx;
+      qc[i][1] = pr.qy;
+      qc[i][2] = pr.qz;
     }
-    // all loads of a chunk are issued before any is used (clamped indices)
-    for (int kc = 0; kc < j; kc += KC) {
-      double v[KC][PPT];
-#pragma unroll
-      for (int q = 0; q < KC; ++q) {
-        const int ks = kc + q < j ? kc + q : j - 1;
-#pragma unroll
-        for (int i = 0; i < PPT; ++i) v[q][i] = (double)V[(size_t)ks * g.ldv + pp[i]];
-      }
-#pragma unroll
-      for (int q = 0; q < KC; ++q)
-        if (kc + q < j) {
-          const double sq = sY[kc + q], cq = cY[kc + q];
-#pragma unroll
-          for (int i = 0; i < PPT; ++i) {
-            a[i] += v[q][i] * sq;
-            bs[i] += v[q][i] * cq;
-          }
-        }
-    }
+    T vr[MM][PPT];
+    load_basis<MM, PPT, T>(vr, V, g.ldv, pp, j);
+    __syncthreads();
+    load_tile<TL>(L, U, g, ox, oy, oz);
+    __syncthreads();
+    const double cyj = cY[j];
 #pragma unroll
     for (int i = 0; i < PPT; ++i)
       if (ok[i]) {
-        const T vj = (T)((uu[i] - a[i]) * ainv);
+        const double uu = centre<TL>(L, qc[i][0], qc[i][1], qc[i][2]);
+        const double ww = stencil<TL>(L, g, qc[i][0], qc[i][1], qc[i][2]);
+        double a = 0.0, b = 0.0;
+#pragma unroll
+        for (int k = 0; k < MM; ++k)
+          if (k < j) {
+            a = fma((double)vr[k][i], sY[k], a);
+            b = fma((double)vr[k][i], cY[k], b);
+          }
+        T vj, un;
+        extend_point<T>(uu, ww, a, b, ainv, cyj, vj, un);
         V[(size_t)j * g.ldv + pp[i]] = vj;
-        Unext[pp[i]] = (T)(ww[i] * ainv - bs[i] - cY[j] * (double)vj);
+        Unext[pp[i]] = un;
       }
   }
 }
@@ -944,13 +1008,14 @@ __global__ __launch_bounds__(kBlock) void k_step(const Job* jobs, const SysDesc*
   }
 }
 
-// x += V_k y (FP64 accumulation into the FP64 iterate).
-template <class T, class TL>
+// x += V_k y (FP64 accumulation into the FP64 iterate); MM >= k.
+template <class T, class TL, int MM>
 __global__ __launch_bounds__(kBlock) void k_update(const Job* jobs, const SysDesc* sd) {
   const Mine me = mine(jobs, sd);
   const gptr<const Ctrl> C = gmem((const Ctrl*)me.S->C);
   if (C->phase != PH_RUN) return;
-  __shared__ double ys[kMaxRestart];
+  constexpr int PPT = TL::PPT;
+  __shared__ double ys[MM];
   const int k = C->k;
   for (int l = threadIdx.x; l < k; l += kBlock) ys[l] = C->y[l];
   __syncthreads();
@@ -960,14 +1025,26 @@ __global__ __launch_bounds__(kBlock) void k_update(const Job* jobs, const SysDes
   for (int tile = me.job.t0; tile < me.job.t1; ++tile) {
     int ox, oy, oz;
     tile_origin<TL>(g, tile, ox, oy, oz);
+    long long pp[PPT];
+    bool ok[PPT];
 #pragma unroll
-    for (int i = 0; i < TL::PPT; ++i) {
+    for (int i = 0; i < PPT; ++i) {
       auto pr = point<TL>(g, ox, oy, oz, i);
-      if (pr.valid) {
-        double s = x[pr.p];
-        for (int l = 0; l < k; ++l) s += ys[l] * (double)V[(size_t)l * g.ldv + pr.p];
-        x[pr.p] = s;
-      }
+      ok[i] = pr.valid;
+      pp[i] = pr.valid ? pr.p : 0;
+    }
+    T vr[MM][PPT];
+    load_basis<MM, PPT, T>(vr, V, g.ldv, pp, k);
+    double xs[PPT];
+#pragma unroll
+    for (int i = 0; i < PPT; ++i) xs[i] = x[pp[i]];
+#pragma unroll
+    for (int i = 0; i < PPT; ++i) {
+      double acc = xs[i];
+#pragma unroll
+      for (int l = 0; l < MM; ++l)
+        if (l < k) acc = fma(ys[l], (double)vr[l][i], acc);
+      if (ok[i]) x[pp[i]] = acc;
     }
   }
 }

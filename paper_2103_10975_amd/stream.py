@@ -25,6 +25,7 @@ import numpy as np
 import torch
 
 from . import (MLG_ERR_NONFINITE, MLG_FP32_IR, MlgError, NetCfg, Opts, grid_of, gmres_solve,
+               mlg_autotune,
                gmres_workspace_bytes, guess_net_infer, guess_net_init, guess_net_param_bytes,
                guess_net_train_step, guess_net_workspace_bytes, workspace)
 
@@ -77,13 +78,16 @@ class StreamSolver:
     def __init__(self, shape, guess: str = "learned", restart_m: int = 30, rtol: float = 1e-8,
                  precision: int = MLG_FP32_IR, warmup: int = 16, replay: int = 64, batch: int = 8,
                  net_cfg: NetCfg | None = None, seed: int = 0, train: bool = True,
-                 time_train: bool = True):
+                 time_train: bool = True, autotune: bool = True):
         if guess not in ("zero", "prev", "learned"):
             raise ValueError("guess must be zero, prev or learned")
         self.shape = tuple(shape)
         self.grid = grid_of(self.shape)
         self.guess_kind = guess
         self.opts = Opts(restart_m=restart_m, precision=precision, rtol=rtol)
+        # tile shape and per-step sweep schedule for this grid, timed once per
+        # process (solves with tile 0 / schedule 0 then use the recorded choice)
+        self.tuned = mlg_autotune(self.grid, self.opts) if autotune else None
         self.ws = workspace(gmres_workspace_bytes(self.grid, self.opts))
         self.warmup, self.batch = warmup, batch
         self.train_enabled = train and guess == "learned"

@@ -58,18 +58,22 @@ def test_operator_parity(mlg, shape):
     assert np.max(np.abs(y.cpu().numpy() - ref)) <= 1e-14 * np.abs(ref).max() * 8
 
 
+SCHEDULES = [1, 2]      # separate extend + dots sweeps; fused single sweep (2D)
+
+
+@pytest.mark.parametrize("schedule", SCHEDULES)
 @pytest.mark.parametrize("shape,m,k", [((64, 64), 20, 1), ((64, 64), 20, 20), ((64, 64), 20, 57),
                                        ((45, 77), 7, 30), ((20, 24, 28), 10, 25), ((130, 70), 30, 95)])
-def test_fixed_iteration_trajectory(mlg, shape, m, k):
+def test_fixed_iteration_trajectory(mlg, shape, m, k, schedule):
     """White-noise right-hand side and guess: the GMRES trajectory is well
     conditioned (CGS2 and MGS oracles agree to ~1e-13), so the GPU iterate after
     exactly k Arnoldi steps must match the oracle's to 1e-10."""
-    print("fixed", shape, m, k, flush=True)
+    print("fixed", shape, m, k, schedule, flush=True)
     rng = np.random.default_rng(17)
     b = rng.standard_normal(shape)
     x0 = 0.1 * rng.standard_normal(shape)
     xo, so = og.gmres(b, x0, m=m, fixed_iters=k)
-    xg, sg = run(mlg, b, x0, restart_m=m, fixed_iters=k)
+    xg, sg = run(mlg, b, x0, restart_m=m, fixed_iters=k, schedule=schedule)
     assert sg.iters == k and sg.cycles == so.cycles
     assert rel(xg, xo) <= 1e-10
     assert abs(sg.relres_first_cycle - so.relres_first_cycle) <= 1e-10 * so.relres_first_cycle
@@ -94,13 +98,14 @@ def test_fixed_iteration_smooth_source(mlg, k):
     assert abs(sg.relres_true - so.relres_true) <= 1e3 * sens * so.relres_true
 
 
+@pytest.mark.parametrize("schedule", SCHEDULES)
 @pytest.mark.parametrize("shape,m,tol", [((64, 64), 20, 1e-8), ((96, 80), 30, 1e-8),
                                          ((24, 24, 24), 20, 1e-8), ((33, 17, 21), 12, 1e-10)])
-def test_to_tolerance_parity(mlg, shape, m, tol):
-    print("tol", shape, m, tol, flush=True)
+def test_to_tolerance_parity(mlg, shape, m, tol, schedule):
+    print("tol", shape, m, tol, schedule, flush=True)
     b = DriftingGaussians(shape, 3, 0.05, seed=1000).field(0)
     xo, so = og.gmres(b, m=m, rtol=tol)
-    xg, sg = run(mlg, b, restart_m=m, rtol=tol)
+    xg, sg = run(mlg, b, restart_m=m, rtol=tol, schedule=schedule)
     assert sg.status == 0 and so.status == 0
     assert abs(sg.iters - so.iters) <= 1
     assert rel(xg, xo) <= 1e-8
@@ -108,13 +113,14 @@ def test_to_tolerance_parity(mlg, shape, m, tol):
     assert rn <= tol * bn
 
 
+@pytest.mark.parametrize("schedule", SCHEDULES)
 @pytest.mark.parametrize("shape,m,tol", [((64, 64), 20, 1e-8), ((128, 128), 30, 1e-10),
                                          ((24, 24, 24), 40, 1e-10), ((50, 70), 30, 1e-8)])
-def test_fp32_basis_refinement(mlg, shape, m, tol):
-    print("fp32", shape, m, tol, flush=True)
+def test_fp32_basis_refinement(mlg, shape, m, tol, schedule):
+    print("fp32", shape, m, tol, schedule, flush=True)
     b = DriftingGaussians(shape, 4, 0.05, seed=3000).field(0)
     xo, so = og.gmres(b, m=m, rtol=tol)
-    xg, sg = run(mlg, b, restart_m=m, rtol=tol, precision=1)
+    xg, sg = run(mlg, b, restart_m=m, rtol=tol, precision=1, schedule=schedule)
     assert sg.status == 0
     rn, bn = og.residual_norm(b, xg)                    # independent FP64 residual
     assert rn <= tol * bn
@@ -184,8 +190,11 @@ def test_deterministic_and_tiles_agree(mlg):
     x2, s2 = run(mlg, b, restart_m=20, rtol=1e-9)
     assert np.array_equal(x1, x2) and s1.iters == s2.iters
     for t in range(1, mlg.mlg_tile_count(2) + 1):
-        xt, st = run(mlg, b, restart_m=20, rtol=1e-9, tile=t)
-        assert abs(st.iters - s1.iters) <= 1 and rel(xt, x1) <= 1e-8
+        for schedule in SCHEDULES:
+            xt, st = run(mlg, b, restart_m=20, rtol=1e-9, tile=t, schedule=schedule)
+            assert abs(st.iters - s1.iters) <= 1 and rel(xt, x1) <= 1e-8
+            xr, sr = run(mlg, b, restart_m=20, rtol=1e-9, tile=t, schedule=schedule)
+            assert np.array_equal(xt, xr)
     b3 = DriftingGaussians((30, 26, 34), 3, 0.08, seed=8).field(0)
     x1, s1 = run(mlg, b3, restart_m=20, rtol=1e-9)
     for t in range(1, mlg.mlg_tile_count(3) + 1):
