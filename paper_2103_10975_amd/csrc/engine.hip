@@ -154,7 +154,7 @@ static Plan make_plan(int nsys, const mlg_system* sys, const mlg_opts& o) {
       P.geo[i] = make_geo(sys[i].grid, G.tile, nb);
       const Geo& g = P.geo[i];
       for (int b = 0; b < g.nblk; ++b) {
-        Job J;
+        Job J{};
         J.sys = i;
         J.t0 = (int)((long long)b * g.ntiles / g.nblk);
         J.t1 = (int)((long long)(b + 1) * g.ntiles / g.nblk);
@@ -492,8 +492,17 @@ static void upload_plan(const Plan& P, const DevPlan& D, int nsys, const mlg_sys
   }
   put(desc.data(), desc.size() * sizeof(SysDesc), D.desc);
   put(init.data(), init.size() * sizeof(SysInit), D.init);
-  for (size_t gi = 0; gi < P.groups.size(); ++gi)
-    put(P.groups[gi].jobs.data(), P.groups[gi].jobs.size() * sizeof(Job), (void*)D.jobs[gi]);
+  for (size_t gi = 0; gi < P.groups.size(); ++gi) {
+    std::vector<Job> jobs = P.groups[gi].jobs;
+    for (Job& J : jobs) {
+      J.m = o.restart_m;
+      J.g = desc[J.sys].g;
+      J.V = desc[J.sys].V;
+      J.r = desc[J.sys].r;
+      J.part = desc[J.sys].part;
+    }
+    put(jobs.data(), jobs.size() * sizeof(Job), (void*)D.jobs[gi]);
+  }
   const long long limit = o.fixed_iters > 0 ? o.fixed_iters
                           : (o.max_iters > 0 ? o.max_iters : 1000000000LL);
   k_setup<<<nsys, 64, 0, stream>>>(D.init, D.desc, D.hdr, o.restart_m, o.fixed_iters > 0 ? 1 : 0,

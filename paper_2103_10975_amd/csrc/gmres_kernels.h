@@ -90,11 +90,20 @@ struct SysDesc {
   double* part;   // reduction partials, column c at part[c * nblk]
 };
 
-// One workgroup's share of a launch: a contiguous tile range of one system.
+// One workgroup's share of a launch: a contiguous tile range of one system,
+// with a copy of that system's geometry and buffers so that a workgroup can
+// issue its data loads after a single table read (the control block, which
+// differs between kernel timing copies, is reached through the descriptor).
 struct Job {
   int sys;
   int t0, t1;
   int lblk;       // index of this workgroup among its system's workgroups
+  int m;          // restart length (the directions follow the m basis vectors)
+  int pad;
+  Geo g;
+  void* V;
+  double* r;
+  double* part;
 };
 
 template <int DIM_, int TX_, int TY_, int TZ_>
@@ -246,7 +255,7 @@ __device__ __forceinline__ void extend_point(double uu, double ww, double a, dou
   un = (T)fma(-cyj, (double)vj, fma(ww, ainv, -b));
 }
 
-// This workgroup's job and system.
+// This workgroup's job (by value) and its system's descriptor.
 struct Mine {
   Job job;
   const SysDesc* S;
@@ -360,7 +369,7 @@ __global__ __launch_bounds__(kBlock) void k_begin(const Job* jobs, const SysDesc
   const Mine me = mine(jobs, sd);
   const gptr<const Ctrl> C = gmem((const Ctrl*)me.S->C);
   if (C->phase != PH_INIT || C->rhs == 0) return;
-  const Geo g = me.S->g;
+  const Geo g = me.job.g;
   gptr<double> x = gmem(C->x0) + (size_t)C->rhs * g.n;
   gptr<const double> xp = x - g.n;
   const bool prev = C->guess == 1;
@@ -384,10 +393,10 @@ __global__ __launch_bounds__(kBlock) void k_resid(const Job* jobs, const SysDesc
   constexpr int PPT = TL::PPT;
   __shared__ double L[TL::LSZ];
   __shared__ double red[4 * 4];
-  const Geo g = me.S->g;
+  const Geo g = me.job.g;
   gptr<const double> b = gmem(C->b0) + (size_t)C->rhs * g.n;
   gptr<const double> x = gmem((const double*)C->x0) + (size_t)C->rhs * g.n;
-  gptr<double> r = gmem(me.S->r);
+  gptr<double> r = gmem(me.job.r);
   double acc[1] = {0.0};
   for (int tile = me.job.t0; tile < me.job.t1; ++tile) {
     int ox, oy, oz;
@@ -420,7 +429,7 @@ __global__ __launch_bounds__(kBlock) void k_resid(const Job* jobs, const SysDesc
       }
     acc[0] += rs4(last);
   }
-  store_folded<0>(acc, red, gmem(me.S->part), g.nblk, me.job.lblk,
+  store_folded<0>(acc, red, gmem(me.job.part), g.nblk, me.job.lblk,
                   [](int, bool) { return -1; },
                   [](int f) { return f == 0 || (INIT && f == 1) ? f : -1; });
 }
@@ -490,9 +499,9 @@ __global__ __launch_bounds__(kBlock) void k_start(const Job* jobs, const SysDesc
   const gptr<const Ctrl> C = gmem((const Ctrl*)me.S->C);
   if (C->phase != PH_RUN && C->phase != PH_ZERO) return;
   const bool zero = C->phase == PH_ZERO;
-  const Geo g = me.S->g;
-  gptr<T> U0 = gmem((T*)me.S->V) + (size_t)C->m * g.ldv;
-  const gptr<double> r = gmem(me.S->r);
+  const Geo g = me.job.g;
+  gptr<T> U0 = gmem((T*)me.job.V) + (size_t)me.job.m * g.ldv;
+  const gptr<double> r = gmem(me.job.r);
   gptr<double> x = gmem(C->x0) + (size_t)C->rhs * g.n;
   for (int tile = me.job.t0; tile < me.job.t1; ++tile) {
     int ox, oy, oz;
@@ -521,9 +530,9 @@ __global__ __launch_bounds__(kBlock) void k_dots(const Job* jobs, const SysDesc*
   constexpr int NS = 16 * (MM / 8) + 4;
   __shared__ double L[TL::LSZ];
   __shared__ double red[4 * NS];
-  const Geo g = me.S->g;
-  const gptr<const T> V = gmem((const T*)me.S->V);
-  const gptr<const T> U = V + (size_t)(C->m + (j & 1)) * g.ldv;
+  const Geo g = me.job.g;
+  const gptr<const T> V = gmem((const T*)me.job.V);
+  const gptr<const T> U = V + (size_t)(me.job.m + (j & 1)) * g.ldv;
   double acc[MM / 8 + 1];
 #pragma unroll
   for (int c = 0; c <= MM / 8; ++c) acc[c] = 0.0;
@@ -557,7 +566,7 @@ __global__ __launch_bounds__(kBlock) void k_dots(const Job* jobs, const SysDesc*
     }
     fold_products<MM, PPT, T>(acc, vr, uu, ww, last, j);
   }
-  store_folded<MM>(acc, red, gmem(me.S->part), g.nblk, me.job.lblk,
+  store_folded<MM>(acc, red, gmem(me.job.part), g.nblk, me.job.lblk,
                    [j](int slot, bool y) { return slot < j ? (y ? j + slot : slot) : -1; },
                    [j](int f) { return f < 2 ? 2 * j + f : -1; });
 }
@@ -752,10 +761,10 @@ __global__ __launch_bounds__(kBlock) void k_extend(const Job* jobs, const SysDes
     if (k < j) sY[k] = C->sY[k];
     cY[k] = C->cY[k];
   }
-  const Geo g = me.S->g;
-  const gptr<T> V = gmem((T*)me.S->V);
-  const gptr<const T> U = V + (size_t)(C->m + (j & 1)) * g.ldv;
-  const gptr<T> Unext = V + (size_t)(C->m + ((j + 1) & 1)) * g.ldv;
+  const Geo g = me.job.g;
+  const gptr<T> V = gmem((T*)me.job.V);
+  const gptr<const T> U = V + (size_t)(me.job.m + (j & 1)) * g.ldv;
+  const gptr<T> Unext = V + (size_t)(me.job.m + ((j + 1) & 1)) * g.ldv;
   const double ainv = 1.0 / C->alpha;
   for (int tile = me.job.t0; tile < me.job.t1; ++tile) {
     int ox, oy, oz;
@@ -817,7 +826,13 @@ template <class T, class TL, int MM>
 __global__ __launch_bounds__(kBlock) void k_step(const Job* jobs, const SysDesc* sd, int j) {
   const Mine me = mine(jobs, sd);
   const gptr<const Ctrl> C = gmem((const Ctrl*)me.S->C);
-  if (C->phase != PH_RUN || C->cycle_end) return;
+  // the control block is read now but tested only after the first tile's
+  // data loads are in flight (the job record alone locates the data)
+  const int phase = C->phase, cycle_end = C->cycle_end;
+  const double alpha = C->alpha;
+  const int tid = threadIdx.x;
+  const double sYl = tid < j ? C->sY[tid] : 0.0;
+  const double cYl = tid <= j ? C->cY[tid] : 0.0;
   using H1 = Halo<TL, 1>;
   using H2 = Halo<TL, 2>;
   constexpr int PPT = TL::PPT;
@@ -832,15 +847,11 @@ __global__ __launch_bounds__(kBlock) void k_step(const Job* jobs, const SysDesc*
   __shared__ double L1[H1::SZ];
   __shared__ double red[4 * NS];
   __shared__ double sY[MM], cY[MM];
-  for (int k = threadIdx.x; k <= j; k += kBlock) {
-    if (k < j) sY[k] = C->sY[k];
-    cY[k] = C->cY[k];
-  }
-  const Geo g = me.S->g;
-  const gptr<T> V = gmem((T*)me.S->V);
-  const gptr<const T> U = V + (size_t)(C->m + (j & 1)) * g.ldv;
-  const gptr<T> Unext = V + (size_t)(C->m + ((j + 1) & 1)) * g.ldv;
-  const double ainv = 1.0 / C->alpha;
+  const Geo g = me.job.g;
+  const gptr<T> V = gmem((T*)me.job.V);
+  const gptr<const T> U = V + (size_t)(me.job.m + (j & 1)) * g.ldv;
+  const gptr<T> Unext = V + (size_t)(me.job.m + ((j + 1) & 1)) * g.ldv;
+  const double ainv = 1.0 / alpha;
   double accw[NCH + 1];
 #pragma unroll
   for (int c = 0; c <= NCH; ++c) accw[c] = 0.0;
@@ -901,6 +912,11 @@ __global__ __launch_bounds__(kBlock) void k_step(const Job* jobs, const SysDesc*
     for (int h = 0; h < HPT; ++h) {
       const int e = threadIdx.x + kBlock * h;
       if (e < H2::SZ) L2[e] = hin[h] ? (double)hv[h] : 0.0;
+    }
+    if (tile == me.job.t0) {
+      if (phase != PH_RUN || cycle_end) return;      // uniform: the whole workgroup leaves
+      if (tid < j) sY[tid] = sYl;
+      if (tid <= j) cY[tid] = cYl;
     }
     __syncthreads();
     const double cyj = cY[j];
@@ -1003,7 +1019,7 @@ __global__ __launch_bounds__(kBlock) void k_step(const Job* jobs, const SysDesc*
       col = f == 0 ? 2 * jn : (f == 1 ? 2 * jn + 1 : (f == 2 ? j : jn + j));
     }
     if (col >= 0)
-      gmem(me.S->part)[(size_t)col * g.nblk + me.job.lblk] =
+      gmem(me.job.part)[(size_t)col * g.nblk + me.job.lblk] =
           ((red[k] + red[NS + k]) + red[2 * NS + k]) + red[3 * NS + k];
   }
 }
@@ -1019,8 +1035,8 @@ __global__ __launch_bounds__(kBlock) void k_update(const Job* jobs, const SysDes
   const int k = C->k;
   for (int l = threadIdx.x; l < k; l += kBlock) ys[l] = C->y[l];
   __syncthreads();
-  const Geo g = me.S->g;
-  const gptr<const T> V = gmem((const T*)me.S->V);
+  const Geo g = me.job.g;
+  const gptr<const T> V = gmem((const T*)me.job.V);
   gptr<double> x = gmem(C->x0) + (size_t)C->rhs * g.n;
   for (int tile = me.job.t0; tile < me.job.t1; ++tile) {
     int ox, oy, oz;
