@@ -46,6 +46,9 @@ def parse():
                     help="budget of the CPU-oracle sample")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-baseline", action="store_true", help="skip the plain-GMRES legs")
+    ap.add_argument("--no-batched", action="store_true", help="skip the batched-systems leg")
+    ap.add_argument("--batched-cycles", type=int, default=3,
+                    help="restart cycles per system in the batched leg")
     ap.add_argument("--json-out", default=None)
     ap.add_argument("--probe", default=None, metavar="KERNEL",
                     help="counter-collection run: a 256 MiB device copy (the byte-count "
@@ -100,10 +103,51 @@ def kernel_roofline(mlg, shape, opts, b, tile, fused, reps=20, only=None):
     return out
 
 
-def counter_traffic(kernel, shape, precision_tag, m):
-    """HBM bytes per launch of `kernel` from the committed FETCH_SIZE/WRITE_SIZE
-    summary (profiles/<kernel>_<H>x<W>_traffic.md), or None when there is none
-    for this workload or the kernel sources changed since the counters were taken."""
+def batched_leg(mlg, seed, cycles, m=30):
+    """Many uneven systems in one graph-replayed launch sequence: 64 2D grids
+    with sides drawn from {128, ..., 1024} and 8 3D grids of 64^3..128^3, one
+    drifting-Gaussian right-hand side each, FP32-basis GMRES(30) run for a
+    fixed number of restart cycles (the throughput of the batched engine, not a
+    convergence race: the largest grids need tens of thousands of steps)."""
+    from synthetic import DriftingGaussians
+    rng = np.random.default_rng(seed)
+    shapes = [(int(s), int(s)) for s in rng.choice([128, 192, 256, 384, 512, 768, 1024], 64)]
+    shapes += [(int(s),) * 3 for s in rng.integers(64, 129, 8)]
+    opts = mlg.Opts(restart_m=m, precision=mlg.MLG_FP32_IR, rtol=1e-8, fixed_iters=cycles * m)
+    for dim in (2, 3):          # tune the largest system of each dimension
+        big = max((sh for sh in shapes if len(sh) == dim), key=lambda sh: int(np.prod(sh)))
+        mlg.mlg_autotune(mlg.grid_of(big), mlg.Opts(restart_m=m, precision=mlg.MLG_FP32_IR))
+    bs, xs = [], []
+    for i, sh in enumerate(shapes):
+        g = DriftingGaussians(sh, 4, 0.03, seed=seed + i)
+        bs.append(torch.from_numpy(g.field(0)[None]).cuda())
+        xs.append(torch.zeros_like(bs[-1]))
+    systems = [mlg.make_system(b, x, 0) for b, x in zip(bs, xs)]
+    ws = mlg.workspace(mlg.gmres_batched_workspace_bytes(systems, opts))
+    mlg.gmres_solve_batched(systems, opts, ws)                  # captures the cycle graph
+    for x in xs:
+        x.zero_()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    stats = mlg.gmres_solve_batched(systems, opts, ws)
+    dt = time.perf_counter() - t0
+    n = sum(int(np.prod(sh)) for sh in shapes)
+    steps = cycles * m
+    # algorithmic bytes of one cycle per point (FP32 basis): the steps' sweeps
+    # (read j basis vectors and the direction, write two vectors) + update + residual
+    per_point = 4 * sum(j + 3 for j in range(m)) + (4 * m + 16) + 24
+    return {"systems": len(shapes), "points": n, "steps_per_system": steps,
+            "seconds": dt, "us_per_step": 1e6 * dt / steps,
+            "point_steps_per_s": n * steps / dt,
+            "effective_GB/s": n * per_point * cycles / dt / 1e9,
+            "iters_ok": all(st.iters == steps for st in stats)}
+
+
+def counter_traffic(kernel, shape, precision_tag, m, tile):
+    """HBM bytes per launch of `kernel` on tile shape `tile` (e.g. "64x16") from
+    the committed FETCH_SIZE/WRITE_SIZE summary
+    (profiles/<kernel>_<H>x<W>_traffic.md), or None when there is none for this
+    workload or the kernel sources changed since the counters were taken."""
     import hashlib
     path = os.path.join(ROOT, "profiles", f"{kernel}_{shape[0]}x{shape[1]}_traffic.md")
     if not os.path.exists(path):
@@ -121,7 +165,8 @@ def counter_traffic(kernel, shape, precision_tag, m):
             h.update(fh.read())
     if h.hexdigest() != fields.get("kernel_source_sha256"):
         return None
-    return float(fields["traffic_bytes_per_launch"])
+    v = fields.get(f"traffic_bytes_per_launch tile={tile}")
+    return float(v) if v else None
 
 
 def cpu_baseline(shape, m, rtol, f0, plain_iters, budget_s):
@@ -213,7 +258,8 @@ def main():
 
     # roofline of the dominant kernel of the learned-guess solve
     tile, fused = learned.tuned
-    result["config"]["tile"] = list(mlg.mlg_tile_shape(2, tile - 1))
+    tshape = mlg.mlg_tile_shape(2, tile - 1)
+    result["config"]["tile"] = list(tshape)
     result["config"]["fused_steps"] = bin(fused).count("1")
     kr = kernel_roofline(mlg, shape, learned.opts, fields[0], tile, fused)
     dom = max((k for k in kr if kr[k]["avg_bytes"] > 0), key=lambda k: kr[k]["cycle_us"])
@@ -222,11 +268,15 @@ def main():
     tag = "fp64" if learned.opts.precision == mlg.MLG_FP64 else "fp32"
     result["roofline"] = {"kernel": dom, "bound": "hbm", "achieved": achieved,
                           "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                          "traffic": counter_traffic(dom, shape, tag, args.restart),
+                          "traffic": counter_traffic(dom, shape, tag, args.restart,
+                                                     f"{tshape[0]}x{tshape[1]}"),
                           "avg_us": d["avg_us"], "avg_bytes": d["avg_bytes"]}
     result["kernels"] = {k: {"avg_us": v["avg_us"], "per_cycle": v["launches_per_cycle"],
                              "GB/s": v["avg_bytes"] / v["avg_us"] / 1e3, "cycle_us": v["cycle_us"]}
                          for k, v in kr.items()}
+
+    if not args.no_batched:
+        result["batched"] = batched_leg(mlg, args.seed, args.batched_cycles)
 
     if not args.no_cpu:
         plain_iters = (result.get("baselines", {}).get("plain_fp64_zero", {}).get("iters_mean")
@@ -242,7 +292,10 @@ def main():
 
 
 def probe(mlg, shape, args):
-    """Launches for hardware-counter runs (no timing is reported)."""
+    """Launches for hardware-counter runs (no timing is reported): a 256 MiB
+    device copy (the byte-count calibration), then for every tile shape one
+    restart cycle's launches of the probed kernel in the learned-guess solve's
+    configuration (fused steps for `step`), each step index once."""
     from synthetic import DriftingGaussians
     names = {v.replace("k_", ""): v for v in mlg.KERNEL_NAMES.values()}
     if args.probe not in names:
@@ -253,11 +306,14 @@ def probe(mlg, shape, args):
     torch.cuda.synchronize()
     f0 = torch.from_numpy(DriftingGaussians(shape, 4, 0.03, seed=args.seed).field(0)).cuda()
     opts = mlg.Opts(restart_m=args.restart, rtol=args.rtol, precision=mlg.MLG_FP32_IR)
-    tile, fused = mlg.mlg_autotune(mlg.grid_of(shape), opts)
-    r = kernel_roofline(mlg, shape, opts, f0, tile, fused, reps=1, only=names[args.probe])
+    fused = (1 << args.restart) - 1 if args.probe == "step" else 0
+    out = {}
+    for tile in range(1, mlg.mlg_tile_count(2) + 1):
+        r = kernel_roofline(mlg, shape, opts, f0, tile, fused, reps=1, only=names[args.probe])
+        out["x".join(map(str, mlg.mlg_tile_shape(2, tile - 1)[:2]))] = r[names[args.probe]]["avg_bytes"]
     torch.cuda.synchronize()
-    print(json.dumps({"probe": args.probe, "copy_bytes": 2 * a.numel() * 4,
-                      "avg_bytes": r[names[args.probe]]["avg_bytes"]}), flush=True)
+    print(json.dumps({"probe": args.probe, "copy_bytes": 2 * a.numel() * 4, "avg_bytes": out}),
+          flush=True)
 
 
 def _solution_before(fields, args, mlg):

@@ -147,7 +147,10 @@ static Plan make_plan(int nsys, const mlg_system* sys, const mlg_opts& o) {
   for (auto& G : P.groups) {
     long long total_tiles = 0;
     for (int i : G.systems) total_tiles += tiles_of(sys[i].grid, G.tile);
-    const long long budget = std::min<long long>(total_tiles, kMaxGrid);
+    // one system: up to kMaxGrid workgroups; several systems share a larger
+    // launch (each system still has at most kMaxGrid partials per column)
+    const long long budget =
+        std::min<long long>(total_tiles, G.systems.size() > 1 ? 4 * kMaxGrid : kMaxGrid);
     for (int i : G.systems) {
       const int t = tiles_of(sys[i].grid, G.tile);
       const int nb = (int)std::max<long long>(1, (budget * t + total_tiles - 1) / total_tiles);
@@ -786,10 +789,13 @@ int autotune(const mlg_grid* grid, const mlg_opts* opts, void* ws, size_t ws_byt
     te.fused[t] = mask;
   }
   // stage 2: the tile whose whole restart cycles (graph launches, every
-  // kernel, the host poll) are fastest with its schedule
-  te.tile = default_tile(*grid, *opts);
+  // kernel, the host poll) are fastest with its schedule; the default tile
+  // is kept unless another is at least 5% faster, so that timing noise does
+  // not flip the choice between near-equal tiles
+  const int dflt = default_tile(*grid, *opts);
+  te.tile = dflt;
   autotune_store(*grid, *opts, te);
-  double best = 1e300;
+  std::vector<double> cyc(tile_count(grid->dim), 1e300);
   for (int t = 0; t < tile_count(grid->dim); ++t) {
     mlg_opts o = *opts;
     o.tile = t + 1;
@@ -797,21 +803,18 @@ int autotune(const mlg_grid* grid, const mlg_opts* opts, void* ws, size_t ws_byt
     o.fixed_iters = 2 * m;
     o.max_iters = 0;
     o.poll_cycles = 2;
-    double dt = 1e300;
-    for (int rep = 0; rep < 3; ++rep) {        // the first run also captures the graph
+    for (int rep = 0; rep < 5; ++rep) {        // the first run also captures the graph
       k_tune_fill<<<(unsigned)((n + 255) / 256), 256, 0, stream>>>(b, x, (long long)n);
       MLG_HIP(hipGetLastError());
       MLG_HIP(hipStreamSynchronize(stream));
       const auto t0 = std::chrono::steady_clock::now();
       solve(grid, b, x, &o, ws, solve_bytes, nullptr, stream);
       const auto t1 = std::chrono::steady_clock::now();
-      if (rep > 0) dt = std::min(dt, std::chrono::duration<double>(t1 - t0).count());
-    }
-    if (dt < best) {
-      best = dt;
-      te.tile = t;
+      if (rep > 0) cyc[t] = std::min(cyc[t], std::chrono::duration<double>(t1 - t0).count());
     }
   }
+  const int fastest = (int)(std::min_element(cyc.begin(), cyc.end()) - cyc.begin());
+  te.tile = cyc[fastest] < 0.95 * cyc[dflt] ? fastest : dflt;
   autotune_store(*grid, *opts, te);
   if (tile_out) *tile_out = te.tile + 1;
   if (fused_out) *fused_out = te.fused[te.tile];

@@ -78,7 +78,7 @@ class StreamSolver:
     def __init__(self, shape, guess: str = "learned", restart_m: int = 30, rtol: float = 1e-8,
                  precision: int = MLG_FP32_IR, warmup: int = 16, replay: int = 64, batch: int = 8,
                  net_cfg: NetCfg | None = None, seed: int = 0, train: bool = True,
-                 time_train: bool = True, autotune: bool = True):
+                 time_train: bool = True, autotune: bool = True, tile: int = 0):
         if guess not in ("zero", "prev", "learned"):
             raise ValueError("guess must be zero, prev or learned")
         self.shape = tuple(shape)
@@ -86,8 +86,11 @@ class StreamSolver:
         self.guess_kind = guess
         self.opts = Opts(restart_m=restart_m, precision=precision, rtol=rtol)
         # tile shape and per-step sweep schedule for this grid, timed once per
-        # process (solves with tile 0 / schedule 0 then use the recorded choice)
+        # process (solves with tile 0 / schedule 0 then use the recorded choice;
+        # an explicit tile keeps the tuned schedule of that tile)
         self.tuned = mlg_autotune(self.grid, self.opts) if autotune else None
+        if tile:
+            self.opts.tile = tile
         self.ws = workspace(gmres_workspace_bytes(self.grid, self.opts))
         self.warmup, self.batch = warmup, batch
         self.train_enabled = train and guess == "learned"
