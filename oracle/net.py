@@ -31,6 +31,7 @@ import numpy as np
 from . import gmres as _gmres
 
 C_U = 2.0 * np.pi ** 2
+RHO = 32.0
 
 
 # ---------------------------------------------------------------- pieces
@@ -120,6 +121,36 @@ def spectral_backward(w1, wk, cache, dy):
     return dx, dw1, db, dwk
 
 
+def laplacian_modes(H: int, W: int, M: int) -> np.ndarray:
+    """lambda[k, l] of the zero-Dirichlet 5-point Laplacian (h = 1/(n+1)) on the
+    mode sin((k+1) pi y) sin((l+1) pi x), k, l < M (rows: y, columns: x)."""
+    k = np.arange(1, M + 1, dtype=np.float64)
+    ly = 4.0 * (H + 1) ** 2 * np.sin(k * np.pi / (2 * (H + 1))) ** 2
+    lx = 4.0 * (W + 1) ** 2 * np.sin(k * np.pi / (2 * (W + 1))) ** 2
+    return ly[:, None] + lx[None, :]
+
+
+def skip_forward(x_r: np.ndarray, g: np.ndarray):
+    """x_r [B, H, W] (residual channel), g [M, M] -> (out [B, H, W], X)."""
+    B, H, W = x_r.shape
+    M = g.shape[0]
+    Sy, Sx = sine_basis(H, M), sine_basis(W, M)
+    norm = (2.0 / (H + 1)) * (2.0 / (W + 1))
+    gain = RHO * g * C_U / laplacian_modes(H, W, M)
+    X = np.einsum("ki,bij,lj->bkl", Sy, x_r, Sx, optimize=True)
+    out = norm * np.einsum("ki,bkl,lj->bij", Sy, gain[None] * X, Sx, optimize=True)
+    return out, X
+
+
+def skip_backward(g: np.ndarray, X: np.ndarray, d_out: np.ndarray) -> np.ndarray:
+    B, H, W = d_out.shape
+    M = g.shape[0]
+    Sy, Sx = sine_basis(H, M), sine_basis(W, M)
+    norm = (2.0 / (H + 1)) * (2.0 / (W + 1))
+    dY = norm * np.einsum("ki,bij,lj->bkl", Sy, d_out, Sx, optimize=True)
+    return RHO * C_U / laplacian_modes(H, W, M) * np.sum(dY * X, axis=0)
+
+
 # ---------------------------------------------------------------- network
 def forward(params: dict, f: np.ndarray, u_prev: np.ndarray, keep: bool = False):
     """f, u_prev: [B, H, W] float64.  Returns (guess [B, H, W], out [B, H, W]
@@ -131,10 +162,11 @@ def forward(params: dict, f: np.ndarray, u_prev: np.ndarray, keep: bool = False)
     a3, sc = spectral_forward(a2, params["spec.w1"], params["spec.b"], params["spec.wk"])
     a4 = np.maximum(conv3x3(a3, params["conv4.w"], params["conv4.b"]), 0.0)
     a5 = np.maximum(conv3x3(a4, params["conv5.w"], params["conv5.b"]), 0.0)
-    out = conv3x3(a5, params["conv6.w"], params["conv6.b"])[:, 0]
+    skip, Xr = skip_forward(x0[:, 0], params["skip.g"])
+    out = conv3x3(a5, params["conv6.w"], params["conv6.b"])[:, 0] + skip
     guess = u_prev + (s_r / C_U)[:, None, None] * out
     if keep:
-        c.update(a1=a1, a2=a2, a3=a3, a4=a4, a5=a5, spec=sc)
+        c.update(a1=a1, a2=a2, a3=a3, a4=a4, a5=a5, spec=sc, Xr=Xr)
         return guess, out, s, c
     return guess, out, s
 
@@ -153,6 +185,7 @@ def loss_and_grads(params: dict, f, u_prev, u_target):
     loss = float(np.sum(diff ** 2) / B)
     g = {}
     d6 = (2.0 / B) * diff[:, None]
+    g["skip.g"] = skip_backward(params["skip.g"], c["Xr"], d6[:, 0])
     d5, g["conv6.w"], g["conv6.b"] = conv3x3_backward(c["a5"], params["conv6.w"], d6)
     d5 = d5 * (c["a5"] > 0.0)
     d4, g["conv5.w"], g["conv5.b"] = conv3x3_backward(c["a4"], params["conv5.w"], d5)

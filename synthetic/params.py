@@ -9,11 +9,14 @@ Tensor names and shapes (torch-style conv layout [out, in, ky, kx]):
     conv4.w [C, C, 3, 3]   conv4.b [C]
     conv5.w [C, C, 3, 3]   conv5.b [C]
     conv6.w [1, C, 3, 3]   conv6.b [1]
+    skip.g  [M, M]                          (per-mode gains of the spectral skip path)
 
 Weights are uniform in +-sqrt(6 / fan_in) (He-uniform); biases are drawn in
-+-0.1 when ``random_bias`` is set (tests) and are zero otherwise.  With
-``zero_last`` the output layer starts at zero, so the untrained network returns
-the previous solution unchanged.
++-0.1 when ``random_bias`` is set (tests) and are zero otherwise; the skip
+gains are uniform in [0, 2/32) (around the value 1/32 at which the path applies
+the exact inverse of A on its modes).  With ``zero_last`` the output layer and
+the skip gains start at zero, so the untrained network returns the previous
+solution unchanged.
 """
 from __future__ import annotations
 
@@ -21,7 +24,7 @@ import numpy as np
 
 PARAM_ORDER = ("conv1.w", "conv1.b", "conv2.w", "conv2.b", "spec.w1", "spec.b",
                "spec.wk", "conv4.w", "conv4.b", "conv5.w", "conv5.b",
-               "conv6.w", "conv6.b")
+               "conv6.w", "conv6.b", "skip.g")
 
 
 def param_shapes(channels: int = 32, modes: int = 16) -> dict:
@@ -34,6 +37,7 @@ def param_shapes(channels: int = 32, modes: int = 16) -> dict:
         "conv4.w": (C, C, 3, 3), "conv4.b": (C,),
         "conv5.w": (C, C, 3, 3), "conv5.b": (C,),
         "conv6.w": (1, C, 3, 3), "conv6.b": (1,),
+        "skip.g": (M, M),
     }
 
 
@@ -47,6 +51,9 @@ def guess_net_params(seed: int, channels: int = 32, modes: int = 16,
             out[name] = (rng.uniform(-0.1, 0.1, size=shape) if random_bias
                          else np.zeros(shape))
             continue
+        if name == "skip.g":
+            out[name] = rng.uniform(0.0, 2.0 / 32.0, size=shape)
+            continue
         if name == "spec.wk":
             fan_in = 2 * shape[3]
         elif name == "spec.w1":
@@ -58,4 +65,5 @@ def guess_net_params(seed: int, channels: int = 32, modes: int = 16,
     if zero_last:
         out["conv6.w"] = np.zeros_like(out["conv6.w"])
         out["conv6.b"] = np.zeros_like(out["conv6.b"])
+        out["skip.g"] = np.zeros_like(out["skip.g"])
     return out

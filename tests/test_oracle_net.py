@@ -117,6 +117,35 @@ def test_input_is_residual_of_previous_solution():
         assert abs(s_r[b] - np.sqrt(np.mean(r ** 2))) <= 1e-12 * s_r[b]
 
 
+def test_skip_path_is_the_truncated_inverse():
+    """With the convolutional output switched off and every skip gain at 1/RHO,
+    the correction d = guess - u_prev solves A d = P r exactly, P the
+    projection on the retained sine modes and r = f - A u_prev (checked
+    against the sparse Kronecker-sum Laplacian and an explicit projection)."""
+    from test_oracle_gmres import sparse_laplacian
+    H, W, M = 21, 17, 6
+    p = guess_net_params(7, channels=4, modes=M, zero_last=True)
+    p["skip.g"] = np.full((M, M), 1.0 / net.RHO)
+    rng = np.random.default_rng(11)
+    f = rng.standard_normal((2, H, W))
+    u = rng.standard_normal((2, H, W))
+    g, _, _ = net.forward(p, f, u)
+    A = sparse_laplacian((H, W))
+    # projection on the first M modes per axis: orthonormal sine rows
+    Qy = net.sine_basis(H, M) * np.sqrt(2.0 / (H + 1))
+    Qx = net.sine_basis(W, M) * np.sqrt(2.0 / (W + 1))
+    for b in range(2):
+        r = f[b] - (A @ u[b].ravel()).reshape(H, W)
+        Pr = Qy.T @ (Qy @ r @ Qx.T) @ Qx
+        d = (g[b] - u[b]).ravel()
+        assert np.allclose(A @ d, Pr.ravel(), rtol=0, atol=1e-9 * np.abs(Pr).max())
+    # the eigenvalues used are those of A
+    lam = net.laplacian_modes(H, W, M)
+    phi = np.outer(np.sin(3 * np.pi * np.arange(1, H + 1) / (H + 1)),
+                   np.sin(5 * np.pi * np.arange(1, W + 1) / (W + 1)))
+    assert np.allclose((A @ phi.ravel()).reshape(H, W), lam[2, 4] * phi, atol=1e-9 * lam[2, 4])
+
+
 def test_loss_closed_form():
     p = small_params()
     rng = np.random.default_rng(6)
@@ -176,6 +205,12 @@ def test_gradients_match_torch_autograd():
     a = F.relu(F.conv2d(a, T["conv4.w"], T["conv4.b"], padding=1))
     a = F.relu(F.conv2d(a, T["conv5.w"], T["conv5.b"], padding=1))
     out = F.conv2d(a, T["conv6.w"], T["conv6.b"], padding=1)[:, 0]
+    kk = np.arange(1, M + 1)
+    lam = torch.tensor((4.0 * (H + 1) ** 2 * np.sin(kk * np.pi / (2 * (H + 1))) ** 2)[:, None]
+                       + (4.0 * (W + 1) ** 2 * np.sin(kk * np.pi / (2 * (W + 1))) ** 2)[None, :])
+    Xr = Sy @ x[:, 0] @ Sx.T
+    out = out + (2.0 / (H + 1)) * (2.0 / (W + 1)) * (
+        Sy.T @ (32.0 * T["skip.g"] * (2 * np.pi ** 2) / lam * Xr) @ Sx)
     t = torch.tensor(net.target(ut, u, s))
     Lt = ((out - t) ** 2).sum() / B
     Lt.backward()
