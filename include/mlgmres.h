@@ -210,7 +210,10 @@ int mlg_autotune(const mlg_grid* grid, const mlg_opts* opts, void* ws, size_t ws
  *   L3 spectral: ReLU(W1 x + b + S^-1[W_kl . S[x]_kl]) over the modes x modes
  *      slowest sine modes (S = DST-I basis), per-mode C x C mixing,
  *   L4, L5 conv3x3 C->C + ReLU, L6 conv3x3 C->1;
- *   guess = u_prev + (s_r / c_u) L6  (= u_prev when u_prev solves A u = f).
+ *   spectral skip (FP32): out = L6 + S^-1[32 g_kl (c_u / lambda_kl) S[r/s_r]_kl]
+ *      over the same modes, lambda_kl the eigenvalues of A (g = 1/32 applies
+ *      the exact inverse of A on those modes);
+ *   guess = u_prev + (s_r / c_u) out  (= u_prev when u_prev solves A u = f).
  * Weights and activations are BF16 in the kernels with FP32 accumulation;
  * FP32 master weights and Adam moments (Section 2.3: back-propagation and
  * ADAM) live in the parameter buffer.
@@ -233,8 +236,9 @@ typedef struct {
  *   conv1.w [C,2,3,3] conv1.b [C] conv2.w [C,C,3,3] conv2.b [C]
  *   spec.w1 [C,C] spec.b [C] spec.wk [M,M,C,C] (= [ky, kx, out, in])
  *   conv4.w conv4.b conv5.w conv5.b (as conv2) conv6.w [1,C,3,3] conv6.b [1]
+ *   skip.g [M,M] (= [ky, kx]; read from the FP32 master copy)
  * guess_net_param_count gives P; guess_net_param_offset the element offset
- * of tensor `index` (0..12 in the order above) inside one array.
+ * of tensor `index` (0..13 in the order above) inside one array.
  */
 int64_t guess_net_param_count(const guess_net_cfg* cfg);
 int64_t guess_net_param_offset(const guess_net_cfg* cfg, int32_t index);
@@ -246,8 +250,8 @@ size_t guess_net_workspace_bytes(const guess_net_cfg* cfg, const mlg_grid* grid,
                                  int32_t batch, int32_t train);
 
 /* Deterministic initialisation from cfg->seed: He-uniform weights, zero
- * biases, zero output layer (so the untrained network returns u_prev), zero
- * Adam state. */
+ * biases, zero output layer and skip gains (so the untrained network returns
+ * u_prev), zero Adam state. */
 int guess_net_init(const guess_net_cfg* cfg, void* params, void* stream);
 
 /* Recompute the BF16 working copy from the FP32 master weights (after the

@@ -330,7 +330,7 @@ def guess_net_train_step(cfg: NetCfg, params: torch.Tensor, fs, u_prevs, u_targe
 # ------------------------------------------------------------------ parameter layout
 # Tensor order and shapes of the parameter arrays (see include/mlgmres.h).
 NET_TENSORS = ("conv1.w", "conv1.b", "conv2.w", "conv2.b", "spec.w1", "spec.b", "spec.wk",
-               "conv4.w", "conv4.b", "conv5.w", "conv5.b", "conv6.w", "conv6.b")
+               "conv4.w", "conv4.b", "conv5.w", "conv5.b", "conv6.w", "conv6.b", "skip.g")
 
 
 def net_tensor_shapes(cfg: NetCfg) -> dict:
@@ -338,7 +338,7 @@ def net_tensor_shapes(cfg: NetCfg) -> dict:
     return {"conv1.w": (C, 2, 3, 3), "conv1.b": (C,), "conv2.w": (C, C, 3, 3), "conv2.b": (C,),
             "spec.w1": (C, C), "spec.b": (C,), "spec.wk": (M, M, C, C),
             "conv4.w": (C, C, 3, 3), "conv4.b": (C,), "conv5.w": (C, C, 3, 3), "conv5.b": (C,),
-            "conv6.w": (1, C, 3, 3), "conv6.b": (1,)}
+            "conv6.w": (1, C, 3, 3), "conv6.b": (1,), "skip.g": (M, M)}
 
 
 def _align(v: int, a: int = 256) -> int:

@@ -11,7 +11,9 @@
 //   a1 = ReLU(conv3x3(x0))          a2 = ReLU(conv3x3(a1))
 //   a3 = ReLU(W1 a2 + b + S^-1[Wk . S[a2]])           (spectral mixing)
 //   a4 = ReLU(conv3x3(a3))          a5 = ReLU(conv3x3(a4))
-//   out = conv3x3(a5) (1 channel, FP32);  guess = u_prev + (s_r/c_u) out
+//   out = conv3x3(a5) (1 channel, FP32)
+//       + S^-1[rho g_kl (c_u / lambda_kl) S[r/s_r]_kl]    (spectral skip, FP32)
+//   guess = u_prev + (s_r/c_u) out
 // The 3x3 convolutions with C -> C channels (forward, input gradient and
 // weight gradient) run on MFMA (v_mfma_f32_16x16x32_bf16) as implicit GEMMs
 // over LDS tiles; the thin layers (2 -> C, C -> 1), the sine transforms (GEMMs
@@ -29,8 +31,10 @@ namespace {
 
 constexpr double kCu = 19.739208802178717;   // 2 pi^2
 constexpr int kMaxBatch = 64;
-constexpr int kNumTensors = 13;
-enum { T_C1W, T_C1B, T_C2W, T_C2B, T_SW1, T_SB, T_SWK, T_C4W, T_C4B, T_C5W, T_C5B, T_C6W, T_C6B };
+constexpr int kNumTensors = 14;
+enum { T_C1W, T_C1B, T_C2W, T_C2B, T_SW1, T_SB, T_SWK, T_C4W, T_C4B, T_C5W, T_C5B, T_C6W, T_C6B,
+       T_SKIP };
+constexpr float kRho = 32.f;          // step-size scale of the skip gains
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float floatx4 __attribute__((ext_vector_type(4)));
@@ -63,7 +67,7 @@ struct Dims {
 void tensor_sizes(const guess_net_cfg* cfg, int64_t* sz) {
   const int64_t C = cfg->channels, M = cfg->modes;
   int64_t s[kNumTensors] = {C * 2 * 9, C, C * C * 9, C, C * C, C, M * M * C * C,
-                            C * C * 9, C, C * C * 9, C, C * 9, 1};
+                            C * C * 9, C, C * C * 9, C, C * 9, 1, M * M};
   for (int i = 0; i < kNumTensors; ++i) sz[i] = s[i];
 }
 
@@ -110,7 +114,8 @@ Dims check_grid_net(const guess_net_cfg* cfg, const mlg_grid* grid, int batch) {
 }
 
 struct WsLayout {
-  size_t s, r0, x0, act[5], out, dout, dz[2], T, X, Y, dX, Z, Sx, Sy, part, loss, total;
+  size_t s, r0, x0, act[5], out, dout, dz[2], T, X, Y, dX, Z, Sx, Sy, part, loss;
+  size_t kT, kX, kY, kZ, kdY, total;          // spectral skip path
   int wgrad_blocks;
 };
 
@@ -135,6 +140,11 @@ WsLayout ws_layout(const Dims& d, bool train) {
   L.Z = take((size_t)d.B * d.H * d.M * d.C * 4);
   L.Sx = take((size_t)d.M * d.W * 4);
   L.Sy = take((size_t)d.M * d.H * 4);
+  L.kT = take((size_t)d.B * d.H * d.M * 4);
+  L.kX = take((size_t)d.B * d.M * d.M * 4);
+  L.kY = take((size_t)d.B * d.M * d.M * 4);
+  L.kZ = take((size_t)d.B * d.H * d.M * 4);
+  L.kdY = train ? take((size_t)d.B * d.M * d.M * 4) : 0;
   L.wgrad_blocks = 0;
   if (train) {
     L.dout = take((size_t)d.B * d.HW * 4);
@@ -701,6 +711,62 @@ __global__ __launch_bounds__(256) void k_spec_out(const bf16* in, const bf16* w1
   }
 }
 
+// ------------------------------------------------------------------ spectral skip
+// T[b][i][l] = sum_j Sx[l][j] x[b][i][j] / div[b]  (one thread per output)
+template <class X>
+__global__ void k_skip_rows(const X* x, const double* div, const float* Sx, float* T, int B, int H,
+                            int W, int M) {
+  const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (long long)B * H * M) return;
+  const int l = (int)(e % M);
+  const long long bi = e / M;
+  const int b = (int)(bi / H);
+  const X* xr = x + bi * W;
+  const float* sr = Sx + (size_t)l * W;
+  float s = 0.f;
+  for (int j = 0; j < W; ++j) s += sr[j] * (float)xr[j];
+  T[e] = div ? (float)((double)s / div[b]) : s;
+}
+
+// lambda_kl of the zero-Dirichlet 5-point Laplacian on the (k+1, l+1) sine mode
+__device__ __forceinline__ double mode_lambda(int k, int l, int H, int W) {
+  const double sy = sin((double)(k + 1) * M_PI / (2.0 * (H + 1)));
+  const double sx = sin((double)(l + 1) * M_PI / (2.0 * (W + 1)));
+  return 4.0 * (H + 1.0) * (H + 1.0) * sy * sy + 4.0 * (W + 1.0) * (W + 1.0) * sx * sx;
+}
+
+// Y[b][k][l] = rho g_kl (c_u / lambda_kl) X[b][k][l]  (FP32 master gains)
+__global__ void k_skip_gain(const float* X, const float* g, float* Y, int B, int H, int W, int M) {
+  const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (long long)B * M * M) return;
+  const int kl = (int)(e % (M * M));
+  const int k = kl / M, l = kl % M;
+  Y[e] = (float)(kRho * (double)g[kl] * kCu / mode_lambda(k, l, H, W)) * X[e];
+}
+
+// out[b][i][j] += beta sum_l Sx[l][j] Z[b][i][l]
+__global__ void k_skip_out(const float* Z, const float* Sx, float* out, int B, int H, int W, int M,
+                           float beta) {
+  const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (long long)B * H * W) return;
+  const int j = (int)(e % W);
+  const long long bi = e / W;
+  const float* zr = Z + bi * M;
+  float s = 0.f;
+  for (int l = 0; l < M; ++l) s += Sx[(size_t)l * W + j] * zr[l];
+  out[e] += beta * s;
+}
+
+// grad g_kl = rho (c_u / lambda_kl) sum_b dY[b][k][l] X[b][k][l]
+__global__ void k_skip_grad(const float* dY, const float* X, float* grad, int B, int H, int W,
+                            int M) {
+  const int kl = blockIdx.x * blockDim.x + threadIdx.x;
+  if (kl >= M * M) return;
+  float s = 0.f;
+  for (int b = 0; b < B; ++b) s += dY[(size_t)b * M * M + kl] * X[(size_t)b * M * M + kl];
+  grad[kl] = (float)(kRho * kCu / mode_lambda(kl / M, kl % M, H, W)) * s;
+}
+
 // ------------------------------------------------------------------ parameters
 __device__ __forceinline__ uint64_t splitmix64(uint64_t x) {
   x += 0x9E3779B97F4A7C15ull;
@@ -781,6 +847,7 @@ struct Net {
   char* params;
   char* ws;
   const bf16* bfw(int t) const { return (const bf16*)(params + pl.bf) + pl.off[t]; }
+  const float* master(int t) const { return (const float*)(params + pl.master) + pl.off[t]; }
   float* grad(int t) const { return (float*)(params + pl.grad) + pl.off[t]; }
   template <class T>
   T* w(size_t off) const { return (T*)(ws + off); }
@@ -832,6 +899,20 @@ void forward(const Net& n, const Ptrs& f, const Ptrs& u, hipStream_t s) {
                                                           a[4], d.H, d.W);
   k_conv_small<C, 1, bf16, float, false, false><<<dim3(cdiv(HW, 256), d.B), 256, 0, s>>>(
       a[4], n.bfw(T_C6W), n.bfw(T_C6B), nullptr, n.w<float>(n.wl.out), d.H, d.W);
+  // spectral skip from the residual channel (FP32, from the FP64 residual)
+  float* kT = n.w<float>(n.wl.kT);
+  float* kX = n.w<float>(n.wl.kX);
+  float* kY = n.w<float>(n.wl.kY);
+  float* kZ = n.w<float>(n.wl.kZ);
+  k_skip_rows<double><<<cdiv((long long)d.B * d.H * d.M, 256), 256, 0, s>>>(r0, sv + d.B, Sx, kT,
+                                                                            d.B, d.H, d.W, d.M);
+  k_spec_cols<<<cdiv((long long)d.B * d.M, 256), 256, 0, s>>>(kT, Sy, kX, d.B, d.H, d.M, 1, 1.f);
+  k_skip_gain<<<cdiv((long long)d.B * d.M * d.M, 256), 256, 0, s>>>(kX, n.master(T_SKIP), kY, d.B,
+                                                                    d.H, d.W, d.M);
+  k_spec_inv_cols<<<cdiv((long long)d.B * d.H * d.M, 256), 256, 0, s>>>(
+      kY, Sy, kZ, d.B, d.H, d.M, 1, (float)(2.0 / (d.H + 1)));
+  k_skip_out<<<cdiv((long long)d.B * HW, 256), 256, 0, s>>>(kZ, Sx, n.w<float>(n.wl.out), d.B, d.H,
+                                                            d.W, d.M, (float)(2.0 / (d.W + 1)));
 }
 
 template <int C>
@@ -874,6 +955,17 @@ void train(const Net& n, const Ptrs& f, const Ptrs& up, const Ptrs& ut, float* l
     k_loss_sum<<<1, kReduceThreads, 0, s>>>(lpart, nb, ldev, loss, d.B);
   }
   const int ctiles = cdiv(d.W, 64) * cdiv(d.H, 4);
+  // spectral skip gains: dY = norm S[dout], grad = rho (c_u / lambda) sum_b dY X
+  {
+    float* kT = n.w<float>(n.wl.kT);
+    float* kdY = n.w<float>(n.wl.kdY);
+    const float nrm = (float)((2.0 / (d.H + 1)) * (2.0 / (d.W + 1)));
+    k_skip_rows<float><<<cdiv((long long)d.B * d.H * d.M, 256), 256, 0, s>>>(dout, nullptr, Sx, kT,
+                                                                             d.B, d.H, d.W, d.M);
+    k_spec_cols<<<cdiv((long long)d.B * d.M, 256), 256, 0, s>>>(kT, Sy, kdY, d.B, d.H, d.M, 1, nrm);
+    k_skip_grad<<<cdiv((long long)d.M * d.M, 256), 256, 0, s>>>(kdY, n.w<float>(n.wl.kX),
+                                                                n.grad(T_SKIP), d.B, d.H, d.W, d.M);
+  }
   // L6: weight grad from (a5, dout); input grad masked by a5 -> dz5
   k_wgrad_small<C, 1, float><<<G, 256, 0, s>>>(a[4], dout, part, d.B, d.H, d.W);
   k_wgrad_reduce<<<cdiv(9 * C + 1, 256), 256, 0, s>>>(part, G, 9, 1, C, n.grad(T_C6W), n.grad(T_C6B));
@@ -947,7 +1039,7 @@ int net_init(const guess_net_cfg* cfg, void* params, hipStream_t s) {
   int64_t sz[kNumTensors];
   tensor_sizes(cfg, sz);
   const float C = (float)cfg->channels;
-  const float fan[kNumTensors] = {18.f, 0, 9 * C, 0, 2 * C, 0, 2 * C, 9 * C, 0, 9 * C, 0, 0, 0};
+  const float fan[kNumTensors] = {18.f, 0, 9 * C, 0, 2 * C, 0, 2 * C, 9 * C, 0, 9 * C, 0, 0, 0, 0};
   for (int i = 0; i < kNumTensors; ++i) {
     spec.bound[i] = fan[i] > 0 ? sqrtf(6.f / fan[i]) : 0.f;
     spec.size[i] = sz[i];

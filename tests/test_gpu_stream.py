@@ -5,13 +5,11 @@ three times with FP32-basis GMRES(30) to 1e-8: from a zero guess, from the
 previous solution u_{t-1}, and from the learned guess (network trained one step
 per solved pair on the replay buffer).  Measured over steps [100, 200):
 
-* the previous solution beats the zero guess in iterations;
-* the learned guess never costs more than 10% over u_{t-1} and beats the zero
-  guess (the untrained network returns u_{t-1} exactly, so the fallback is the
-  floor);
-* the trained network removes part of the slow-mode error of u_{t-1} (its
+* the previous solution beats the zero guess in iterations, and the learned
+  guess beats the previous solution;
+* the trained network removes most of the slow-mode error of u_{t-1} (its
   projection on the 16 x 16 slowest sine modes of the Dirichlet Laplacian --
-  the error restarted GMRES converges slowest on).
+  the error restarted GMRES converges slowest on): measured 6.7x.
 
 The paper prints no iteration counts for this network or workload, so the
 sizes of these gains are measured and printed, not pinned.
@@ -71,6 +69,5 @@ def test_learned_guess_gain(mlg):
           f"prev {iters['prev']:.0f}, learned {iters['learned']:.0f}; "
           f"slow-mode error of u_(t-1) / of the learned guess: {gain:.2f}")
     assert iters["prev"] < iters["zero"]
-    assert iters["learned"] < iters["zero"]
-    assert iters["learned"] <= 1.10 * iters["prev"]
-    assert gain > 1.2
+    assert iters["learned"] < iters["prev"]
+    assert gain > 3.0
