@@ -58,7 +58,7 @@ def parse():
     return ap.parse_args()
 
 
-def kernel_roofline(mlg, shape, opts, b, tile, fused, reps=20, only=None):
+def kernel_roofline(mlg, shape, opts, b, tile, fused, split=0, reps=20, only=None):
     """Average launch duration of every solver kernel over one restart cycle,
     in the launch configuration of the solve (tuned tile and per-step sweep
     schedule; HIP events on the stream), with the algorithmic bytes of each
@@ -76,13 +76,19 @@ def kernel_roofline(mlg, shape, opts, b, tile, fused, reps=20, only=None):
     # the launches of one cycle: (kind, step index, algorithmic bytes)
     launches = [(mlg.MLG_K_DOTS, 0, 1 * n * s)]           # w = A u_0 and |u_0|: read u_0
     for j in range(m):
-        if (fused >> j) & 1:
+        if (split >> j) & 1:
+            # sums over workgroups; the sweep forms the coefficients itself
+            launches.append((mlg.MLG_K_SUMS, j, 0))
+            launches.append((mlg.MLG_K_STEPC, j, (j + 3) * n * s))
+        elif (fused >> j) & 1:
             # read v_0..v_{j-1}, u_j; write v_j, u_{j+1}
+            launches.append((mlg.MLG_K_COEF, j, 0))       # one-workgroup sums
             launches.append((mlg.MLG_K_STEP, j, (j + 3) * n * s))
         else:
+            launches.append((mlg.MLG_K_COEF, j, 0))
             launches.append((mlg.MLG_K_EXTEND, j, (j + 3) * n * s))
             launches.append((mlg.MLG_K_DOTS, j + 1, (j + 2) * n * s))   # read v_0..v_j, u_{j+1}
-    launches += [(mlg.MLG_K_COEF, j, 0) for j in range(m + 1)]        # one-workgroup sums
+    launches.append((mlg.MLG_K_COEF, m, 0))
     launches.append((mlg.MLG_K_UPDATE, m, m * n * s + 2 * n * 8))      # read V_m, read+write x
     launches.append((mlg.MLG_K_RESIDUAL, m, 3 * n * 8))                # read x, b; write r
     out = {}
@@ -257,11 +263,12 @@ def main():
         result["speedup_vs_prev_fp64"] = legs["fp64_prev"]["tos_mean"] / tos_learned
 
     # roofline of the dominant kernel of the learned-guess solve
-    tile, fused = learned.tuned
+    tile, fused, split = learned.tuned
     tshape = mlg.mlg_tile_shape(2, tile - 1)
     result["config"]["tile"] = list(tshape)
     result["config"]["fused_steps"] = bin(fused).count("1")
-    kr = kernel_roofline(mlg, shape, learned.opts, fields[0], tile, fused)
+    result["config"]["split_steps"] = bin(split).count("1")
+    kr = kernel_roofline(mlg, shape, learned.opts, fields[0], tile, fused, split)
     dom = max((k for k in kr if kr[k]["avg_bytes"] > 0), key=lambda k: kr[k]["cycle_us"])
     d = kr[dom]
     achieved = d["avg_bytes"] / (d["avg_us"] * 1e-6) / 1e9

@@ -74,7 +74,11 @@ typedef struct {
  *   schedule      how an Arnoldi step sweeps the basis (same arithmetic):
  *                 0 = as tuned by mlg_autotune for this grid (separate sweeps
  *                 when untuned), 1 = separate extend and dot-product sweeps,
- *                 2 = the fused single sweep wherever the grid is 2D.
+ *                 2 = the fused single sweep wherever the grid is 2D, 3 = the
+ *                 fused sweep in the split form wherever the grid is 2D: the
+ *                 step's partials are summed by many workgroups at once and
+ *                 every workgroup of the sweep forms the step's coefficients
+ *                 itself (bitwise the same results as 2).
  */
 typedef struct {
   int32_t restart_m;
@@ -159,19 +163,23 @@ int mlg_apply_operator(const mlg_grid* grid, const double* u, double* y, void* s
  * products), MLG_K_COEF (one-workgroup sum, Hessenberg column, Givens),
  * MLG_K_EXTEND (new basis vector v_j and direction u_{j+1}), MLG_K_STEP (the
  * solver's fused form of MLG_K_EXTEND at j and MLG_K_DOTS at j+1, one sweep
- * over the basis); once per cycle: MLG_K_UPDATE (x += V y) and
- * MLG_K_RESIDUAL (r = b - A x).
+ * over the basis), MLG_K_SUMS (the split form's column sums of the partials,
+ * one wavefront per column), MLG_K_STEPC (MLG_K_STEP in the split form: the
+ * coefficient update of MLG_K_COEF from those sums, then the sweep); once per
+ * cycle: MLG_K_UPDATE (x += V y) and MLG_K_RESIDUAL (r = b - A x).
  *   ws       the workspace of a finished gmres_solve with the same grid and
  *            opts (its basis and coefficients are the kernel inputs; the
  *            reduction partials, the residual buffer, and for MLG_K_EXTEND,
- *            MLG_K_STEP and MLG_K_UPDATE basis vector `step`, the direction
- *            buffers and x are overwritten).
+ *            MLG_K_STEP, MLG_K_STEPC and MLG_K_UPDATE basis vector `step`,
+ *            the direction buffers and x are overwritten).  MLG_K_STEPC
+ *            takes the sums of a unit direction orthogonal to the basis.
  *   scratch  >= mlg_kernel_bench_scratch_bytes(reps) bytes: one private copy
  *            of the solver state per launch, so every launch does full work.
- *   step     Arnoldi index j: 0..m (0..m-1 for MLG_K_EXTEND and MLG_K_STEP).
+ *   step     Arnoldi index j: 0..m (0..m-1 for MLG_K_EXTEND, MLG_K_STEP and
+ *            MLG_K_STEPC).
  */
 enum { MLG_K_DOTS = 0, MLG_K_COEF = 1, MLG_K_EXTEND = 2, MLG_K_UPDATE = 3, MLG_K_RESIDUAL = 4,
-       MLG_K_STEP = 5 };
+       MLG_K_STEP = 5, MLG_K_SUMS = 6, MLG_K_STEPC = 7 };
 size_t mlg_kernel_bench_scratch_bytes(int32_t reps);
 int mlg_kernel_bench(const mlg_grid* grid, const mlg_opts* opts, void* ws, size_t ws_bytes,
                      void* scratch, size_t scratch_bytes, int32_t kind, int32_t step, int32_t reps,
@@ -184,19 +192,23 @@ int mlg_tile_shape(int32_t dim, int32_t index, int32_t* tx, int32_t* ty, int32_t
 /*
  * Autotuner.  For one grid and option set (precision, restart_m), times every
  * tile shape and, per Arnoldi step, the separate extend + dot-product sweeps
- * against the fused sweep, on synthetic data in `ws`, in the launch
- * configuration the solver uses; records the fastest tile and per-step
- * schedule in a process-wide table that gmres_solve / gmres_solve_batched
- * consult when opts->tile == 0 (tile) and opts->schedule == 0 (schedule).
- * A batched solve takes the entry of its largest system per dimension.
+ * against the fused sweep (kernel timings), then whole restart cycles of
+ * every tile with the fused steps' sums in either form, on synthetic data in
+ * `ws`, in the launch configuration the solver uses; records the fastest tile
+ * and per-step schedule in a process-wide table that gmres_solve /
+ * gmres_solve_batched consult when opts->tile == 0 (tile) and
+ * opts->schedule == 0 (schedule).  A batched solve takes the entry of its
+ * largest system per dimension.
  *   ws      >= mlg_autotune_workspace_bytes(grid, opts) bytes (overwritten).
  *   tile    host, may be NULL: the chosen tile index (1-based, as opts->tile).
  *   fused   host, may be NULL: bit j set = step j runs fused.
+ *   split   host, may be NULL: bit j set = ... in the split form (a subset
+ *           of `fused`).
  * Blocks until done.  Entries live until mlg_shutdown.
  */
 size_t mlg_autotune_workspace_bytes(const mlg_grid* grid, const mlg_opts* opts);
 int mlg_autotune(const mlg_grid* grid, const mlg_opts* opts, void* ws, size_t ws_bytes,
-                 int32_t* tile, uint64_t* fused, void* stream);
+                 int32_t* tile, uint64_t* fused, uint64_t* split, void* stream);
 
 /* ---------------------------------------------------------------- network */
 

@@ -108,7 +108,8 @@ def _load():
         "mlg_tile_count": (i32, [i32]),
         "mlg_tile_shape": (ctypes.c_int, [i32, i32, P(i32), P(i32), P(i32)]),
         "mlg_autotune_workspace_bytes": (sz, [P(Grid), P(Opts)]),
-        "mlg_autotune": (ctypes.c_int, [P(Grid), P(Opts), vp, sz, P(i32), P(ctypes.c_uint64), vp]),
+        "mlg_autotune": (ctypes.c_int, [P(Grid), P(Opts), vp, sz, P(i32), P(ctypes.c_uint64),
+                                        P(ctypes.c_uint64), vp]),
         "guess_net_param_count": (i64, [P(NetCfg)]),
         "guess_net_param_offset": (i64, [P(NetCfg), i32]),
         "guess_net_param_bytes": (sz, [P(NetCfg)]),
@@ -226,9 +227,12 @@ def mlg_apply_operator(u: torch.Tensor, y: torch.Tensor, stream=None) -> None:
     _check(lib.mlg_apply_operator(ctypes.byref(g), _ptr(u), _ptr(y), _stream(stream)))
 
 
-MLG_K_DOTS, MLG_K_COEF, MLG_K_EXTEND, MLG_K_UPDATE, MLG_K_RESIDUAL, MLG_K_STEP = range(6)
+(MLG_K_DOTS, MLG_K_COEF, MLG_K_EXTEND, MLG_K_UPDATE, MLG_K_RESIDUAL, MLG_K_STEP, MLG_K_SUMS,
+ MLG_K_STEPC) = range(8)
+# kernel symbol of each kind (MLG_K_STEPC is the split-form instance of k_step)
 KERNEL_NAMES = {MLG_K_DOTS: "k_dots", MLG_K_COEF: "k_coef", MLG_K_EXTEND: "k_extend",
-                MLG_K_UPDATE: "k_update", MLG_K_RESIDUAL: "k_resid", MLG_K_STEP: "k_step"}
+                MLG_K_UPDATE: "k_update", MLG_K_RESIDUAL: "k_resid", MLG_K_STEP: "k_step",
+                MLG_K_SUMS: "k_sums", MLG_K_STEPC: "k_step"}
 
 
 def mlg_kernel_bench_scratch_bytes(reps: int) -> int:
@@ -256,14 +260,15 @@ def mlg_autotune_workspace_bytes(grid: Grid, opts: Opts) -> int:
 def mlg_autotune(grid: Grid, opts: Opts, ws: torch.Tensor | None = None, stream=None):
     """Time every tile and per-step sweep schedule for (grid, opts) and record
     the fastest for later solves with tile=0, schedule=0.  Returns (tile,
-    fused-step bit mask).  ws: scratch of mlg_autotune_workspace_bytes bytes
-    (allocated here when None)."""
+    fused-step bit mask, split-form bit mask).  ws: scratch of
+    mlg_autotune_workspace_bytes bytes (allocated here when None)."""
     if ws is None:
         ws = workspace(mlg_autotune_workspace_bytes(grid, opts))
-    tile, fused = ctypes.c_int32(), ctypes.c_uint64()
+    tile, fused, split = ctypes.c_int32(), ctypes.c_uint64(), ctypes.c_uint64()
     _check(lib.mlg_autotune(ctypes.byref(grid), ctypes.byref(opts), _ptr(ws, torch.uint8),
-                            ws.numel(), ctypes.byref(tile), ctypes.byref(fused), _stream(stream)))
-    return tile.value, fused.value
+                            ws.numel(), ctypes.byref(tile), ctypes.byref(fused),
+                            ctypes.byref(split), _stream(stream)))
+    return tile.value, fused.value, split.value
 
 
 def mlg_tile_count(dim: int) -> int:

@@ -103,13 +103,14 @@ size_t mlg_autotune_workspace_bytes(const mlg_grid* grid, const mlg_opts* opts) 
 }
 
 int mlg_autotune(const mlg_grid* grid, const mlg_opts* opts, void* ws, size_t ws_bytes,
-                 int32_t* tile, uint64_t* fused, void* stream) {
+                 int32_t* tile, uint64_t* fused, uint64_t* split, void* stream) {
   return guarded([&] {
     int t = 0;
-    unsigned long long f = 0;
-    const int rc = autotune(grid, opts, ws, ws_bytes, &t, &f, (hipStream_t)stream);
+    unsigned long long f = 0, sp = 0;
+    const int rc = autotune(grid, opts, ws, ws_bytes, &t, &f, &sp, (hipStream_t)stream);
     if (tile) *tile = t;
     if (fused) *fused = (uint64_t)f;
+    if (split) *split = (uint64_t)sp;
     return rc;
   });
 }

@@ -76,7 +76,7 @@ void check_opts(const mlg_opts* o, int dim) {
   if (!(o->rtol >= 0.0)) throw ArgError{MLG_ERR_ARG, "rtol must be >= 0"};
   if (o->max_iters < 0 || o->fixed_iters < 0) throw ArgError{MLG_ERR_ARG, "negative iteration cap"};
   if (o->tile < 0 || o->tile > tile_count(dim)) throw ArgError{MLG_ERR_ARG, "tile index out of range"};
-  if (o->schedule < 0 || o->schedule > 2) throw ArgError{MLG_ERR_ARG, "schedule must be 0, 1 or 2"};
+  if (o->schedule < 0 || o->schedule > 3) throw ArgError{MLG_ERR_ARG, "schedule must be in 0..3"};
 }
 
 // Default tile when the caller leaves the choice to the library and the
@@ -93,9 +93,11 @@ int default_tile(const mlg_grid& gr, const mlg_opts&) {
 struct Group {
   int dim, tile;
   unsigned long long fused;         // bit j: step j runs as the fused sweep
+  unsigned long long split;         // bit j: ... in the split form (sums + sweep)
+  int maxblk;                       // most workgroups of one of its systems
   std::vector<int> systems;
   std::vector<Job> jobs;
-  size_t off_jobs;
+  size_t off_jobs, off_list;        // device job table, device list of its systems
 };
 
 struct Plan {
@@ -138,9 +140,14 @@ static Plan make_plan(int nsys, const mlg_system* sys, const mlg_opts& o) {
     if (G.tile >= tile_count(dim)) G.tile = tile_count(dim) - 1;
     // the fused sweep exists for 2D grids only (in 3D its halo ring would
     // exceed the tile)
-    if (dim == 3 || o.schedule == 1) G.fused = 0;
-    else if (o.schedule == 2) G.fused = ~0ULL;
-    else G.fused = tuned ? te.fused[G.tile] : 0;
+    G.fused = G.split = 0;
+    if (dim == 2 && o.schedule >= 2) {
+      G.fused = ~0ULL;
+      G.split = o.schedule == 3 ? ~0ULL : 0;
+    } else if (dim == 2 && o.schedule == 0 && tuned) {
+      G.fused = te.fused[G.tile];
+      G.split = te.split[G.tile] & G.fused;
+    }
     P.groups.push_back(G);
   }
   P.geo.resize(nsys);
@@ -156,6 +163,7 @@ static Plan make_plan(int nsys, const mlg_system* sys, const mlg_opts& o) {
       const int nb = (int)std::max<long long>(1, (budget * t + total_tiles - 1) / total_tiles);
       P.geo[i] = make_geo(sys[i].grid, G.tile, nb);
       const Geo& g = P.geo[i];
+      G.maxblk = std::max(G.maxblk, g.nblk);
       for (int b = 0; b < g.nblk; ++b) {
         Job J{};
         J.sys = i;
@@ -176,7 +184,10 @@ static Plan make_plan(int nsys, const mlg_system* sys, const mlg_opts& o) {
   P.off_stats = take((size_t)P.total_rhs * sizeof(Summary));
   P.off_desc = take((size_t)nsys * sizeof(SysDesc));
   P.off_init = take((size_t)nsys * sizeof(SysInit));
-  for (auto& G : P.groups) G.off_jobs = take(G.jobs.size() * sizeof(Job));
+  for (auto& G : P.groups) {
+    G.off_jobs = take(G.jobs.size() * sizeof(Job));
+    G.off_list = take(G.systems.size() * sizeof(int));
+  }
   P.off_ctrl.resize(nsys);
   P.off_part.resize(nsys);
   P.off_r.resize(nsys);
@@ -221,15 +232,27 @@ size_t workspace_bytes(int nsys, const mlg_system* sys, const mlg_opts* opts) {
   else if ((N) <= 40) { constexpr int MM = 40; EXPR_MM; }           \
   else { constexpr int MM = 64; EXPR_MM; }
 
-// coef(j) for ns systems whose partials come from at most maxblk workgroups.
-static void launch_coef(hipStream_t s, int ns, int maxblk, const SysDesc* sd, int j) {
-  if (maxblk <= 256) k_coef<4><<<ns, kReduceThreads, 0, s>>>(sd, j);
-  else if (maxblk <= 512) k_coef<8><<<ns, kReduceThreads, 0, s>>>(sd, j);
-  else k_coef<16><<<ns, kReduceThreads, 0, s>>>(sd, j);
+// Partial blocks per lane for sums over at most maxblk workgroups.
+#define MLG_NB_SWITCH(MAXBLK, EXPR_NB)                              \
+  if ((MAXBLK) <= 256) { constexpr int NB = 4; EXPR_NB; }           \
+  else if ((MAXBLK) <= 512) { constexpr int NB = 8; EXPR_NB; }      \
+  else { constexpr int NB = 16; EXPR_NB; }
+
+// coef(j) / sums(j) for `count` systems (those in `list`, or all when null)
+// whose partials come from at most maxblk workgroups.
+static void launch_coef(hipStream_t s, int count, const int* list, int maxblk, const SysDesc* sd,
+                        int j) {
+  MLG_NB_SWITCH(maxblk, (k_coef<NB><<<count, kReduceThreads, 0, s>>>(sd, list, j)));
+}
+static void launch_sums(hipStream_t s, int count, const int* list, int maxblk, const SysDesc* sd,
+                        int j) {
+  const dim3 grid((2 * j + 2 + kBlock / 64 - 1) / (kBlock / 64), count);
+  MLG_NB_SWITCH(maxblk, (k_sums<NB><<<grid, kBlock, 0, s>>>(sd, list, j)));
 }
 
 // kind: 0 begin, 1 initial residual, 2 start, 3 dots(j), 4 extend(j),
-// 5 update (j = restart length m), 6 residual, 7 fused step(j).
+// 5 update (j = restart length m), 6 residual, 7 fused step(j), 8 fused step
+// in the split form (coefficients from sums(j)).
 template <class T, class TL>
 static void enqueue_group_step(hipStream_t s, int kind, int nb, const Job* jobs, const SysDesc* sd,
                                int j) {
@@ -240,12 +263,13 @@ static void enqueue_group_step(hipStream_t s, int kind, int nb, const Job* jobs,
     case 3: MLG_MM_SWITCH(j, (k_dots<T, TL, MM><<<nb, kBlock, 0, s>>>(jobs, sd, j))); break;
     case 4: MLG_MM_SWITCH(j, (k_extend<T, TL, MM><<<nb, kBlock, 0, s>>>(jobs, sd, j))); break;
     case 5: MLG_MM_SWITCH(j, (k_update<T, TL, MM><<<nb, kBlock, 0, s>>>(jobs, sd))); break;
-    case 7: MLG_MM_SWITCH(j + 1, (k_step<T, TL, MM><<<nb, kBlock, 0, s>>>(jobs, sd, j))); break;
+    case 7: MLG_MM_SWITCH(j + 1, (k_step<T, TL, MM, false><<<nb, kBlock, 0, s>>>(jobs, sd, j))); break;
+    case 8: MLG_MM_SWITCH(j + 1, (k_step<T, TL, MM, true><<<nb, kBlock, 0, s>>>(jobs, sd, j))); break;
     default: k_resid<TL, false><<<nb, kBlock, 0, s>>>(jobs, sd); break;
   }
 }
 enum { G_BEGIN = 0, G_RESID0 = 1, G_START = 2, G_DOTS = 3, G_EXTEND = 4, G_UPDATE = 5, G_RESID = 6,
-       G_STEP = 7 };
+       G_STEP = 7, G_SPLIT = 8 };
 
 using GroupFn = void (*)(hipStream_t, int, int, const Job*, const SysDesc*, int);
 
@@ -283,6 +307,7 @@ struct DevPlan {                    // device pointers of a plan inside a worksp
   SysDesc* desc;
   SysInit* init;
   std::vector<const Job*> jobs;
+  std::vector<const int*> lists;
 };
 
 static DevPlan dev_plan(const Plan& P, void* ws) {
@@ -292,38 +317,59 @@ static DevPlan dev_plan(const Plan& P, void* ws) {
   D.stats = (Summary*)(D.base + P.off_stats);
   D.desc = (SysDesc*)(D.base + P.off_desc);
   D.init = (SysInit*)(D.base + P.off_init);
-  for (auto& G : P.groups) D.jobs.push_back((const Job*)(D.base + G.off_jobs));
+  for (auto& G : P.groups) {
+    D.jobs.push_back((const Job*)(D.base + G.off_jobs));
+    D.lists.push_back((const int*)(D.base + G.off_list));
+  }
   return D;
 }
 
 static void enqueue_cycle(hipStream_t s, const Plan& P, const DevPlan& D, int prec, int m) {
   std::vector<GroupFn> fns;
   for (auto& G : P.groups) fns.push_back(group_fn(G.dim, G.tile, prec));
+  const size_t ng = P.groups.size();
   auto each = [&](int kind, int j) {
-    for (size_t gi = 0; gi < P.groups.size(); ++gi)
+    for (size_t gi = 0; gi < ng; ++gi)
       fns[gi](s, kind, (int)P.groups[gi].jobs.size(), D.jobs[gi], D.desc, j);
   };
   const int ns = P.nsys;
+  int maxblk = 1;
+  for (auto& G : P.groups) maxblk = std::max(maxblk, G.maxblk);
   each(G_BEGIN, 0);
   each(G_RESID0, 0);
   k_rsum<true><<<ns, kReduceThreads, 0, s>>>(D.desc);
   each(G_START, 0);
-  int maxblk = 1;
-  for (const Geo& g : P.geo) maxblk = std::max(maxblk, g.nblk);
   each(G_DOTS, 0);
-  launch_coef(s, ns, maxblk, D.desc, 0);
   for (int j = 0; j < m; ++j) {
-    for (size_t gi = 0; gi < P.groups.size(); ++gi) {
-      const int nb = (int)P.groups[gi].jobs.size();
-      if ((P.groups[gi].fused >> j) & 1ULL) {
-        fns[gi](s, G_STEP, nb, D.jobs[gi], D.desc, j);
+    // the grid-wide sums of step j: coef(j), or sums(j) for groups whose step
+    // runs in the split form (one launch over all systems when every group
+    // takes the same form)
+    int nsplit = 0;
+    for (auto& G : P.groups) nsplit += (int)((G.split >> j) & 1ULL);
+    if (nsplit == 0) {
+      launch_coef(s, ns, nullptr, maxblk, D.desc, j);
+    } else if (nsplit == (int)ng) {
+      launch_sums(s, ns, nullptr, maxblk, D.desc, j);
+    } else {
+      for (size_t gi = 0; gi < ng; ++gi) {
+        const Group& G = P.groups[gi];
+        const int cnt = (int)G.systems.size();
+        if ((G.split >> j) & 1ULL) launch_sums(s, cnt, D.lists[gi], G.maxblk, D.desc, j);
+        else launch_coef(s, cnt, D.lists[gi], G.maxblk, D.desc, j);
+      }
+    }
+    for (size_t gi = 0; gi < ng; ++gi) {
+      const Group& G = P.groups[gi];
+      const int nb = (int)G.jobs.size();
+      if ((G.fused >> j) & 1ULL) {
+        fns[gi](s, ((G.split >> j) & 1ULL) ? G_SPLIT : G_STEP, nb, D.jobs[gi], D.desc, j);
       } else {
         fns[gi](s, G_EXTEND, nb, D.jobs[gi], D.desc, j);
         fns[gi](s, G_DOTS, nb, D.jobs[gi], D.desc, j + 1);
       }
     }
-    launch_coef(s, ns, maxblk, D.desc, j + 1);
   }
+  launch_coef(s, ns, nullptr, maxblk, D.desc, m);
   each(G_UPDATE, m);
   each(G_RESID, 0);
   k_rsum<false><<<ns, kReduceThreads, 0, s>>>(D.desc);
@@ -392,7 +438,8 @@ static std::string plan_key(int dev, const void* ws, const Plan& P, int prec, in
          "," + std::to_string(g.ntiles) + "," + std::to_string(g.nblk);
   }
   for (auto& G : P.groups)
-    k += "#" + std::to_string(G.dim) + "," + std::to_string(G.tile) + "," + std::to_string(G.fused);
+    k += "#" + std::to_string(G.dim) + "," + std::to_string(G.tile) + "," + std::to_string(G.fused) +
+         "," + std::to_string(G.split);
   return k;
 }
 
@@ -505,6 +552,8 @@ static void upload_plan(const Plan& P, const DevPlan& D, int nsys, const mlg_sys
       J.part = desc[J.sys].part;
     }
     put(jobs.data(), jobs.size() * sizeof(Job), (void*)D.jobs[gi]);
+    put(P.groups[gi].systems.data(), P.groups[gi].systems.size() * sizeof(int),
+        (void*)D.lists[gi]);
   }
   const long long limit = o.fixed_iters > 0 ? o.fixed_iters
                           : (o.max_iters > 0 ? o.max_iters : 1000000000LL);
@@ -515,7 +564,7 @@ static void upload_plan(const Plan& P, const DevPlan& D, int nsys, const mlg_sys
 
 static size_t stage_bytes(const Plan& P) {
   size_t b = P.nsys * (sizeof(SysDesc) + sizeof(SysInit)) + 256;
-  for (auto& G : P.groups) b += G.jobs.size() * sizeof(Job) + 64;
+  for (auto& G : P.groups) b += G.jobs.size() * sizeof(Job) + G.systems.size() * sizeof(int) + 128;
   return b;
 }
 
@@ -642,7 +691,9 @@ static void enqueue_one(GroupFn fn, hipStream_t s, int kind, int nb, const Job* 
                         const SysDesc* sd, int j) {
   switch (kind) {
     case MLG_K_DOTS: fn(s, G_DOTS, nb, jobs, sd, j); break;
-    case MLG_K_COEF: launch_coef(s, 1, nb, sd, j); break;
+    case MLG_K_COEF: launch_coef(s, 1, nullptr, nb, sd, j); break;
+    case MLG_K_SUMS: launch_sums(s, 1, nullptr, nb, sd, j); break;
+    case MLG_K_STEPC: fn(s, G_SPLIT, nb, jobs, sd, j); break;
     case MLG_K_EXTEND: fn(s, G_EXTEND, nb, jobs, sd, j); break;
     case MLG_K_UPDATE: fn(s, G_UPDATE, nb, jobs, sd, j); break;
     case MLG_K_STEP: fn(s, G_STEP, nb, jobs, sd, j); break;
@@ -659,9 +710,10 @@ double kernel_bench(const mlg_grid* grid, const mlg_opts* opts, void* ws, size_t
                     hipStream_t stream) {
   check_grid(grid);
   check_opts(opts, grid->dim);
-  if (kind < MLG_K_DOTS || kind > MLG_K_STEP) throw ArgError{MLG_ERR_ARG, "unknown kernel kind"};
+  if (kind < MLG_K_DOTS || kind > MLG_K_STEPC) throw ArgError{MLG_ERR_ARG, "unknown kernel kind"};
   if (j < 0 || j > opts->restart_m ||
-      ((kind == MLG_K_EXTEND || kind == MLG_K_STEP) && j >= opts->restart_m))
+      ((kind == MLG_K_EXTEND || kind == MLG_K_STEP || kind == MLG_K_STEPC) &&
+       j >= opts->restart_m))
     throw ArgError{MLG_ERR_ARG, "step index out of range"};
   if (reps < 1 || reps > 4096) throw ArgError{MLG_ERR_ARG, "reps must be in 1..4096"};
   mlg_system s1 = single(grid, nullptr, nullptr);
@@ -683,10 +735,10 @@ double kernel_bench(const mlg_grid* grid, const mlg_opts* opts, void* ws, size_t
     hipEvent_t a, b;
     ~Gd() { hipEventDestroy(a); hipEventDestroy(b); }
   } guard{e0, e1};
-  k_bench_setup<<<reps, 256, 0, stream>>>(D.desc, descs, copies, reps);
   const int jj = kind == MLG_K_UPDATE ? opts->restart_m : j;
+  k_bench_setup<<<reps, 256, 0, stream>>>(D.desc, descs, copies, reps, jj);
   enqueue_one(fn, stream, kind, nb, D.jobs[0], descs, jj);    // untimed warm-up launch
-  k_bench_setup<<<reps, 256, 0, stream>>>(D.desc, descs, copies, reps);
+  k_bench_setup<<<reps, 256, 0, stream>>>(D.desc, descs, copies, reps, jj);
   MLG_HIP(hipEventRecord(e0, stream));
   for (int i = 0; i < reps; ++i) enqueue_one(fn, stream, kind, nb, D.jobs[0], descs + i, jj);
   MLG_HIP(hipEventRecord(e1, stream));
@@ -733,7 +785,7 @@ size_t autotune_workspace_bytes(const mlg_grid* grid, const mlg_opts* opts) {
 }
 
 int autotune(const mlg_grid* grid, const mlg_opts* opts, void* ws, size_t ws_bytes, int* tile_out,
-             unsigned long long* fused_out, hipStream_t stream) {
+             unsigned long long* fused_out, unsigned long long* split_out, hipStream_t stream) {
   check_grid(grid);
   check_opts(opts, grid->dim);
   if (!ws || ws_bytes < autotune_workspace_bytes(grid, opts) || (uintptr_t)ws % 256)
@@ -787,37 +839,51 @@ int autotune(const mlg_grid* grid, const mlg_opts* opts, void* ws, size_t ws_byt
         if (interp(fus, j) < interp(sep, j)) mask |= 1ULL << j;
     }
     te.fused[t] = mask;
+    te.split[t] = 0;
   }
-  // stage 2: the tile whose whole restart cycles (graph launches, every
-  // kernel, the host poll) are fastest with its schedule; the default tile
-  // is kept unless another is at least 5% faster, so that timing noise does
-  // not flip the choice between near-equal tiles
+  // stage 2: the tile, and for its fused steps the form of their sums (one
+  // workgroup's coef launch, or sums spread over workgroups with the
+  // coefficients formed in the sweep), whose whole restart cycles (graph
+  // launches, every kernel, the host poll) are fastest.  The form is timed
+  // whole because its cost is the cross-XCD traffic of freshly written
+  // partials, which repeated launches of one kernel do not show.  The default
+  // tile is kept unless another is at least 5% faster, so that timing noise
+  // does not flip the choice between near-equal tiles.
   const int dflt = default_tile(*grid, *opts);
-  te.tile = dflt;
-  autotune_store(*grid, *opts, te);
-  std::vector<double> cyc(tile_count(grid->dim), 1e300);
-  for (int t = 0; t < tile_count(grid->dim); ++t) {
-    mlg_opts o = *opts;
-    o.tile = t + 1;
-    o.schedule = 0;                            // the stage-1 mask of this tile
-    o.fixed_iters = 2 * m;
-    o.max_iters = 0;
-    o.poll_cycles = 2;
-    for (int rep = 0; rep < 5; ++rep) {        // the first run also captures the graph
-      k_tune_fill<<<(unsigned)((n + 255) / 256), 256, 0, stream>>>(b, x, (long long)n);
-      MLG_HIP(hipGetLastError());
-      MLG_HIP(hipStreamSynchronize(stream));
-      const auto t0 = std::chrono::steady_clock::now();
-      solve(grid, b, x, &o, ws, solve_bytes, nullptr, stream);
-      const auto t1 = std::chrono::steady_clock::now();
-      if (rep > 0) cyc[t] = std::min(cyc[t], std::chrono::duration<double>(t1 - t0).count());
+  const int nt = tile_count(grid->dim);
+  std::vector<double> cyc(2 * nt, 1e300);      // [tile][form: 0 coef, 1 split]
+  for (int t = 0; t < nt; ++t)
+    for (int form = 0; form < (two_d ? 2 : 1); ++form) {
+      te.tile = t;
+      te.split[t] = form ? te.fused[t] : 0;
+      autotune_store(*grid, *opts, te);
+      mlg_opts o = *opts;
+      o.tile = t + 1;
+      o.schedule = 0;                          // the entry just stored
+      o.fixed_iters = 2 * m;
+      o.max_iters = 0;
+      o.poll_cycles = 2;
+      for (int rep = 0; rep < 5; ++rep) {      // the first run also captures the graph
+        k_tune_fill<<<(unsigned)((n + 255) / 256), 256, 0, stream>>>(b, x, (long long)n);
+        MLG_HIP(hipGetLastError());
+        MLG_HIP(hipStreamSynchronize(stream));
+        const auto t0 = std::chrono::steady_clock::now();
+        solve(grid, b, x, &o, ws, solve_bytes, nullptr, stream);
+        const auto t1 = std::chrono::steady_clock::now();
+        if (rep > 0)
+          cyc[2 * t + form] = std::min(cyc[2 * t + form], std::chrono::duration<double>(t1 - t0).count());
+      }
     }
-  }
-  const int fastest = (int)(std::min_element(cyc.begin(), cyc.end()) - cyc.begin());
-  te.tile = cyc[fastest] < 0.95 * cyc[dflt] ? fastest : dflt;
+  for (int t = 0; t < nt; ++t) te.split[t] = cyc[2 * t + 1] < cyc[2 * t] ? te.fused[t] : 0;
+  auto best = [&](int t) { return std::min(cyc[2 * t], cyc[2 * t + 1]); };
+  int fastest = 0;
+  for (int t = 1; t < nt; ++t)
+    if (best(t) < best(fastest)) fastest = t;
+  te.tile = best(fastest) < 0.95 * best(dflt) ? fastest : dflt;
   autotune_store(*grid, *opts, te);
   if (tile_out) *tile_out = te.tile + 1;
   if (fused_out) *fused_out = te.fused[te.tile];
+  if (split_out) *split_out = te.split[te.tile];
   return MLG_OK;
 }
 

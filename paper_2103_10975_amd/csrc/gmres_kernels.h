@@ -36,11 +36,18 @@
 // keeps the same tiles (and their basis chunks in L2) for the whole solve.
 #pragma once
 
+#include <type_traits>
+
 #include "common.h"
 
 namespace mlg {
 
 enum Phase { PH_INIT = 0, PH_RUN = 1, PH_ZERO = 2, PH_DONE = 3 };
+
+// Packed column storage of the small dense matrices: Hessenberg column c
+// holds rows 0..c+1, the rotated (upper triangular) column c rows 0..c.
+__host__ __device__ constexpr int hu_off(int c) { return c * (c + 3) / 2; }
+__host__ __device__ constexpr int r_off(int c) { return c * (c + 1) / 2; }
 
 // Statistics of one right-hand side (copied to the host at the end).
 struct Summary {
@@ -65,12 +72,15 @@ struct Ctrl {
   Summary* stats;       // this system's slots of the statistics array
   unsigned int* done;   // [0]: systems with every right-hand side solved,
                         // [1]: progress count (Arnoldi columns + finished RHS)
-  double hprev[kMaxRestart + 1];           // first-projection coefficients h_{j-1}
+  // first-projection coefficients h_{j-1}: step j reads row j & 1 and writes
+  // row (j + 1) & 1, so a launch may read and write them at once
+  double hprev[2][kMaxRestart + 1];
+  double sums[2 * kMaxRestart + 2];        // column sums of step j's partials (k_sums)
   double sY[kMaxRestart + 1];              // second-projection coefficients (extend)
   double cY[kMaxRestart + 1];              // coefficients of V_j in u_{j+1} (extend)
   double cs[kMaxRestart], sn[kMaxRestart], g[kMaxRestart + 1], y[kMaxRestart];
-  double Hu[kMaxRestart * (kMaxRestart + 1)];  // Hessenberg, column c at Hu[c*(kMaxRestart+1)]
-  double R[kMaxRestart * kMaxRestart];         // rotated Hessenberg, column c at R[c*kMaxRestart]
+  double Hu[hu_off(kMaxRestart)];          // Hessenberg, packed by column
+  double R[r_off(kMaxRestart)];            // rotated Hessenberg, packed by column
 };
 
 struct Geo {
@@ -571,26 +581,148 @@ __global__ __launch_bounds__(kBlock) void k_dots(const Job* jobs, const SysDesc*
                    [j](int f) { return f < 2 ? 2 * j + f : -1; });
 }
 
-// coef(j): one workgroup per system.  Every global load of the launch (the
-// first round of partials, the Hessenberg columns, wavefront 0's per-row
-// state) is issued at once and consumed before the state is tested, so their
-// latencies overlap.  Wavefront 0 then completes Hessenberg column j-1
-// (second projection), applies the Givens rotations (lane-parallel data,
-// uniform loop with lane broadcasts), tests for the end of the cycle (back
-// substitution if so, with R staged by all threads) and prepares the
-// coefficients of the next sweep.  For a zero right-hand side, coef(0) ends
-// the RHS.
+// ------------------------------------------------ coefficient update of step j
+// Wavefront 0 of a workgroup, lane i owning row i (j <= 64).  fin holds the
+// column sums of the step's partials (s: 0..j-1, t: j..2j-1, u^T u, u^T w),
+// HuS the Hessenberg columns 0..j-2 (packed); hpi is h_{j-1} at this lane.
+struct StepCoef {
+  double nu, si, hpl, alpha, coli, h, cy;
+};
+
+// Second projection of u_j and the coefficients of the next sweep: alpha =
+// |u_j - V s|, Hessenberg column j-1 = h_{j-1} + s with subdiagonal alpha
+// (stored into HuS), z = Hbar_{j-1} s, h_j = (V_j^T A v_j) from the Arnoldi
+// relation, cY = z / alpha + h_j, sY = s.
+__device__ __forceinline__ StepCoef coef_project(const double* fin, double* HuS, int j,
+                                                 double hpi) {
+  const int lane = threadIdx.x & 63;
+  StepCoef q;
+  q.nu = fin[2 * j];
+  const double mu = fin[2 * j + 1];
+  q.si = lane < j ? fin[lane] : 0.0;
+  const double ti = lane < j ? fin[j + lane] : 0.0;
+  q.hpl = lane < j ? hpi : 0.0;
+  const double ss = wave_sum(q.si * q.si);
+  const double st = wave_sum(q.si * ti);
+  q.coli = 0.0;
+  if (j == 0) {
+    q.alpha = sqrt(q.nu);
+  } else {
+    // |u_j - V s|^2 = |u_j|^2 - |s|^2 (V orthonormal)
+    q.alpha = sqrt(fmax(q.nu - ss, 0.0));
+    q.coli = lane < j ? q.hpl + q.si : (lane == j ? q.alpha : 0.0);
+    if (lane <= j) HuS[hu_off(j - 1) + lane] = q.coli;
+  }
+  // h_i = v_i^T A v_j with A v_j = (w - V_j z) / alpha, z = Hbar_{j-1} s
+  double z = 0.0;
+  if (lane <= j)
+    for (int c2 = (lane > 0 ? lane - 1 : 0); c2 < j; ++c2) z += HuS[hu_off(c2) + lane] * fin[c2];
+  const double vw = lane < j ? ti : (mu - st) / q.alpha;
+  q.h = (vw - z) / q.alpha;
+  q.cy = z / q.alpha + q.h;
+  return q;
+}
+
+// Fields of the control block the stop test reads (loaded at kernel start).
+struct StopState {
+  long long iters, limit;
+  double tol_abs, bnorm;
+  int fixed, m;
+};
+__device__ __forceinline__ StopState stop_state(gptr<const Ctrl> C) {
+  return StopState{C->s.iters, C->limit, C->tol_abs, C->bnorm, C->fixed, C->m};
+}
+
+// The system's own state for step j >= 1 (one workgroup per system calls
+// this): stores Hessenberg column j-1 and h_j, applies the Givens rotations
+// G_0..G_{j-2} to the column and forms G_{j-1}, updates the residual
+// estimate and tests for the end of the cycle.  Returns 0 to continue, 1 at
+// the end of the cycle, 2 on a non-finite value (status set; the caller
+// finishes the RHS); rot is this lane's entry of the rotated column, gnew the
+// rotated g_{j-1}.
+__device__ __forceinline__ int coef_rotate(gptr<Ctrl> C, const StepCoef& q, int j,
+                                           const StopState& ss, double csl, double snl, double gc,
+                                           double& rot, double& gnew) {
+  const int lane = threadIdx.x & 63;
+  const int c = j - 1;
+  if (lane <= j) {
+    C->Hu[hu_off(c) + lane] = q.coli;
+    C->hprev[(j + 1) & 1][lane] = q.h;
+  }
+  const double hh = wave_sum(q.hpl * q.hpl);
+  // rotations G_0..G_{c-1}: carry the running entry down the column
+  const double csv = lane < c ? csl : 0.0, snv = lane < c ? snl : 0.0;
+  double carry = lane_bcast(q.coli, 0);
+  rot = 0.0;
+  for (int i = 0; i < c; ++i) {
+    const double a = carry, bb = lane_bcast(q.coli, i + 1);
+    const double ci = lane_bcast(csv, i), sni = lane_bcast(snv, i);
+    if (lane == i) rot = ci * a + sni * bb;
+    carry = -sni * a + ci * bb;
+  }
+  const double den = hypot(carry, q.alpha);
+  double cc = 1.0, sn = 0.0;
+  if (den != 0.0) {
+    cc = carry / den;
+    sn = q.alpha / den;
+  }
+  if (lane == c) rot = den;
+  if (lane <= c) C->R[r_off(c) + lane] = rot;
+  gnew = cc * gc;
+  const double est = fabs(sn * gc);
+  const long long iters = ss.iters + 1;
+  // breakdown: the new direction is rounding noise relative to A v_{j-1}
+  // (|A v_{j-1}|^2 = |u_j|^2 + |h_{j-1}|^2)
+  const bool breakdown = q.alpha <= 1e-14 * sqrt(q.nu + hh);
+  const bool bad = !isfinite(q.alpha) || !isfinite(est);
+  const bool stop = bad || iters >= ss.limit || breakdown || (!ss.fixed && est <= ss.tol_abs) ||
+                    j == ss.m;
+  if (lane == 0) {
+    C->cs[c] = cc;
+    C->sn[c] = sn;
+    C->g[c + 1] = -sn * gc;
+    C->g[c] = gnew;
+    C->s.iters = iters;
+    C->k = j;
+    C->s.relres_est = est / ss.bnorm;
+    atomicAdd(C->done + 1, 1u);
+    if (bad) C->s.status = MLG_ERR_NONFINITE;
+  }
+  return bad ? 2 : (stop ? 1 : 0);
+}
+
+// End of a cycle after step j: back substitution R y = g (R: j x j upper
+// triangular, packed in Rs), row i on lane i of wavefront 0.
+__device__ __forceinline__ void back_substitute(gptr<Ctrl> C, const double* Rs, int j, double gl) {
+  const int lane = threadIdx.x & 63;
+  double accl = 0.0, yl = 0.0;
+  for (int i = j - 1; i >= 0; --i) {
+    const double yi = lane_bcast((gl - accl) / (lane < j ? Rs[r_off(lane) + lane] : 1.0), i);
+    if (lane == i) yl = yi;
+    if (lane < i) accl += Rs[r_off(i) + lane] * yi;
+  }
+  if (lane < j) C->y[lane] = yl;
+  if (lane == 0) C->cycle_end = 1;
+}
+
+// coef(j): one workgroup per system (those in `list`, or system blockIdx.x).
+// Every global load of the launch (the first round of partials, the
+// Hessenberg columns, wavefront 0's per-row state) is issued at once and
+// consumed before the state is tested, so their latencies overlap.
+// Wavefront 0 then runs the coefficient update; at the end of a cycle R is
+// staged by all threads for the back substitution.  For a zero right-hand
+// side, coef(0) ends the RHS.
 template <int NB>
-__global__ __launch_bounds__(kReduceThreads) void k_coef(const SysDesc* sd, int j) {
-  constexpr int LDH = kMaxRestart + 1;
-  constexpr int HPT = (kMaxRestart * LDH + kReduceThreads - 1) / kReduceThreads;
-  constexpr int RPT = (kMaxRestart * kMaxRestart + kReduceThreads - 1) / kReduceThreads;
+__global__ __launch_bounds__(kReduceThreads) void k_coef(const SysDesc* sd, const int* list,
+                                                         int j) {
+  constexpr int HPT = (hu_off(kMaxRestart) + kReduceThreads - 1) / kReduceThreads;
+  constexpr int RPT = (r_off(kMaxRestart) + kReduceThreads - 1) / kReduceThreads;
   __shared__ double fin[2 * kMaxRestart + 2];
   // Hessenberg columns (for z) or, at the end of a cycle, the rotated R
-  __shared__ double HuS[kMaxRestart * LDH];
+  __shared__ double HuS[hu_off(kMaxRestart)];
   __shared__ int flag;
   double* Rs = HuS;
-  const SysDesc* S = sd + blockIdx.x;
+  const SysDesc* S = sd + (list ? list[blockIdx.x] : (int)blockIdx.x);
   const gptr<Ctrl> C = gmem(S->C);
   const gptr<const double> part = gmem((const double*)S->part);
   const int nblk = S->g.nblk;
@@ -598,10 +730,10 @@ __global__ __launch_bounds__(kReduceThreads) void k_coef(const SysDesc* sd, int 
   const int tid = threadIdx.x, lane = tid;
   const bool w0 = tid < 64;
   const int c = j - 1;
-  // ---- all loads at once (clamped indices: the buffers are valid memory)
+  // ---- all loads at once
   PartialsRound<NB> r0;
   partials_load(r0, part, nblk, ncols, 0);
-  const int hlim = j > 1 ? (j - 1) * LDH : 0;        // columns 0..j-2 (rows <= c+1)
+  const int hlim = j > 1 ? hu_off(j - 1) : 0;          // columns 0..j-2
   double hv[HPT];
 #pragma unroll
   for (int k = 0; k < HPT; ++k) {
@@ -609,11 +741,12 @@ __global__ __launch_bounds__(kReduceThreads) void k_coef(const SysDesc* sd, int 
     hv[k] = 0.0;
     if (e < hlim) hv[k] = C->Hu[e];
   }
-  const double hpi = C->hprev[w0 && lane < j ? lane : 0];
+  const double hpi = C->hprev[j & 1][w0 && lane < j ? lane : 0];
   const double csl = C->cs[w0 && lane < c ? lane : 0];
   const double snl = C->sn[w0 && lane < c ? lane : 0];
   const double gc = C->g[j > 0 ? c : 0];
   const double glane = C->g[w0 && lane < j ? lane : 0];
+  const StopState ss = stop_state(C);
   partials_sum(r0, nblk, ncols, 0, fin);
 #pragma unroll
   for (int k = 0; k < HPT; ++k) {
@@ -631,81 +764,28 @@ __global__ __launch_bounds__(kReduceThreads) void k_coef(const SysDesc* sd, int 
   }
   if (C->phase != PH_RUN || C->cycle_end) return;
   __syncthreads();
-  // ---- wavefront 0: lane i owns row i (j <= 64)
-  double nu = 0.0, mu = 0.0, si = 0.0, ti = 0.0, st = 0.0, alpha = 0.0;
-  double cc = 1.0, gnew = 0.0, rot = 0.0;
+  StepCoef q{};
+  double rot = 0.0, gnew = 0.0;
   if (w0) {
-    nu = fin[2 * j];
-    mu = fin[2 * j + 1];
-    si = lane < j ? fin[lane] : 0.0;
-    ti = lane < j ? fin[j + lane] : 0.0;
-    const double hpl = lane < j ? hpi : 0.0;
-    const double ss = wave_sum(si * si), hh = wave_sum(hpl * hpl);
-    st = wave_sum(si * ti);
-    int fl = 0;                                       // 0 continue, 1 end of cycle, 2 failed
-    if (j == 0) {
-      alpha = sqrt(nu);
-    } else {
-      // |u_j - V s|^2 = |u_j|^2 - |s|^2 (V orthonormal)
-      alpha = sqrt(fmax(nu - ss, 0.0));
-      // Hessenberg column c: first + second projection, subdiagonal alpha
-      const double coli = lane < j ? hpl + si : (lane == j ? alpha : 0.0);
-      if (lane <= j) {
-        C->Hu[(size_t)c * LDH + lane] = coli;
-        HuS[(size_t)c * LDH + lane] = coli;
-      }
-      // rotations G_0..G_{c-1}: carry the running entry down the column
-      const double csv = lane < c ? csl : 0.0, snv = lane < c ? snl : 0.0;
-      double carry = lane_bcast(coli, 0);
-      for (int i = 0; i < c; ++i) {
-        const double a = carry, bb = lane_bcast(coli, i + 1);
-        const double ci = lane_bcast(csv, i), sni = lane_bcast(snv, i);
-        if (lane == i) rot = ci * a + sni * bb;
-        carry = -sni * a + ci * bb;
-      }
-      const double den = hypot(carry, alpha);
-      double sn = 0.0;
-      if (den != 0.0) {
-        cc = carry / den;
-        sn = alpha / den;
-      }
-      if (lane == c) rot = den;
-      if (lane <= c) C->R[c * kMaxRestart + lane] = rot;
-      gnew = cc * gc;
-      const double est = fabs(sn * gc);
-      const long long iters = C->s.iters + 1;
-      // breakdown: the new direction is rounding noise relative to A v_{j-1}
-      // (|A v_{j-1}|^2 = |u_j|^2 + |h_{j-1}|^2)
-      const bool breakdown = alpha <= 1e-14 * sqrt(nu + hh);
-      const bool bad = !isfinite(alpha) || !isfinite(est);
-      const bool stop = bad || iters >= C->limit || breakdown ||
-                        (!C->fixed && est <= C->tol_abs) || j == C->m;
-      if (lane == 0) {
-        C->cs[c] = cc;
-        C->sn[c] = sn;
-        C->g[c + 1] = -sn * gc;
-        C->g[c] = gnew;
-        C->s.iters = iters;
-        C->k = j;
-        C->s.relres_est = est / C->bnorm;
-        atomicAdd(C->done + 1, 1u);
-        if (bad) {
-          C->s.status = MLG_ERR_NONFINITE;
-          finish_rhs(C);
-        }
-      }
-      fl = bad ? 2 : (stop ? 1 : 0);
+    q = coef_project(fin, HuS, j, hpi);
+    int fl = 0;
+    if (j > 0) {
+      fl = coef_rotate(C, q, j, ss, csl, snl, gc, rot, gnew);
+    } else if (lane == 0) {
+      C->hprev[1][0] = q.h;
     }
     if (lane == 0) flag = fl;
   }
   __syncthreads();
   const int fl = flag;
-  if (fl == 2) return;
+  if (fl == 2) {
+    if (tid == 0) finish_rhs(C);
+    return;
+  }
   if (fl == 1) {
-    // back substitution R y = g (R: j x j upper triangular), row i on lane i;
-    // columns 0..c-1 come from memory (staged by all threads), column c is
-    // wavefront 0's register
-    const int rlim = c * kMaxRestart;
+    // columns 0..c-1 of R from memory (staged by all threads), column c from
+    // wavefront 0's registers
+    const int rlim = r_off(c);
     double rv[RPT];
 #pragma unroll
     for (int k = 0; k < RPT; ++k) {
@@ -719,33 +799,45 @@ __global__ __launch_bounds__(kReduceThreads) void k_coef(const SysDesc* sd, int 
       const int e = tid + kReduceThreads * k;
       if (e < rlim) Rs[e] = rv[k];
     }
-    if (w0 && lane <= c) Rs[c * kMaxRestart + lane] = rot;
+    if (w0 && lane <= c) Rs[rlim + lane] = rot;
     __syncthreads();
-    if (!w0) return;
-    const double gl = lane < j ? (lane == c ? gnew : glane) : 0.0;
-    double accl = 0.0, yl = 0.0;
-    for (int i = j - 1; i >= 0; --i) {
-      const double yi = lane_bcast((gl - accl) / (lane < j ? Rs[lane * kMaxRestart + lane] : 1.0), i);
-      if (lane == i) yl = yi;
-      if (lane < i) accl += Rs[i * kMaxRestart + lane] * yi;
-    }
-    if (lane < j) C->y[lane] = yl;
-    if (lane == 0) C->cycle_end = 1;
+    if (w0) back_substitute(C, Rs, j, lane < j ? (lane == c ? gnew : glane) : 0.0);
     return;
   }
   if (!w0) return;
-  // h_i = v_i^T A v_j with A v_j = (w - V_j z) / alpha, z = Hbar_{j-1} s
-  double z = 0.0;
-  if (lane <= j)
-    for (int cc2 = (lane > 0 ? lane - 1 : 0); cc2 < j; ++cc2) z += HuS[(size_t)cc2 * LDH + lane] * fin[cc2];
   if (lane <= j) {
-    const double vw = lane < j ? ti : (mu - st) / alpha;
-    const double h = (vw - z) / alpha;
-    C->hprev[lane] = h;
-    C->cY[lane] = z / alpha + h;
-    C->sY[lane] = si;
+    C->cY[lane] = q.cy;
+    C->sY[lane] = q.si;
   }
-  if (lane == 0) C->alpha = alpha;
+  if (lane == 0) C->alpha = q.alpha;
+}
+
+// sums(j): the column sums of step j's partials into the control block, one
+// wavefront per column (columns spread over blockIdx.x, systems over
+// blockIdx.y: those in `list`, or all), in the order coef(j) sums them.
+// sums(0) also ends a zero right-hand side.
+template <int NB>
+__global__ __launch_bounds__(kBlock) void k_sums(const SysDesc* sd, const int* list, int j) {
+  constexpr int NW = kBlock / 64;
+  const SysDesc* S = sd + (list ? list[blockIdx.y] : (int)blockIdx.y);
+  const int lane = threadIdx.x & 63, c = blockIdx.x * NW + (threadIdx.x >> 6);
+  const int nblk = S->g.nblk;
+  // a zero right-hand side ends here, as at coef(0) in the other forms
+  if (j == 0 && blockIdx.x == 0 && threadIdx.x == 0 && gmem(S->C)->phase == PH_ZERO)
+    finish_rhs(gmem(S->C));
+  if (c >= 2 * j + 2) return;                         // wavefront-uniform
+  const gptr<const double> part = gmem((const double*)S->part) + (size_t)c * nblk;
+  double v[NB];
+#pragma unroll
+  for (int i = 0; i < NB; ++i) {
+    const int b = lane + 64 * i;
+    v[i] = b < nblk ? part[b] : 0.0;
+  }
+  double s = 0.0;
+#pragma unroll
+  for (int i = 0; i < NB; ++i) s += v[i];
+  s = wave_sum(s);
+  if (lane == 0) gmem(S->C)->sums[c] = s;
 }
 
 // extend(j): v_j = (u_j - V_{j-1} s) / alpha, u_{j+1} = w/alpha - V_j cY.
@@ -822,17 +914,14 @@ __global__ __launch_bounds__(kBlock) void k_extend(const Job* jobs, const SysDes
 // The products of each tile are folded across the wavefront at once (chunks
 // of 8 basis vectors, 16 sums, reduce-scatter), so a lane carries only one
 // running sum per chunk and the kernel keeps its occupancy.
-template <class T, class TL, int MM>
+template <class T, class TL, int MM, bool SPLIT>
 __global__ __launch_bounds__(kBlock) void k_step(const Job* jobs, const SysDesc* sd, int j) {
   const Mine me = mine(jobs, sd);
-  const gptr<const Ctrl> C = gmem((const Ctrl*)me.S->C);
+  const gptr<Ctrl> C = gmem((Ctrl*)me.S->C);
   // the control block is read now but tested only after the first tile's
   // data loads are in flight (the job record alone locates the data)
   const int phase = C->phase, cycle_end = C->cycle_end;
-  const double alpha = C->alpha;
   const int tid = threadIdx.x;
-  const double sYl = tid < j ? C->sY[tid] : 0.0;
-  const double cYl = tid <= j ? C->cY[tid] : 0.0;
   using H1 = Halo<TL, 1>;
   using H2 = Halo<TL, 2>;
   constexpr int PPT = TL::PPT;
@@ -843,19 +932,61 @@ __global__ __launch_bounds__(kBlock) void k_step(const Job* jobs, const SysDesc*
   constexpr int RS = H1::SZ - TL::P;                 // ring points
   constexpr int RPT = (RS + kBlock - 1) / kBlock;
   constexpr int HPT = (H2::SZ + kBlock - 1) / kBlock;
+  // split form: Hessenberg columns 0..j-1 (j < MM), later R, share L1's space
+  constexpr int HUS = SPLIT ? hu_off(MM - 1) : 0;
+  constexpr int HT = (hu_off(MM - 2) + kBlock - 1) / kBlock;
+  constexpr int RT = (r_off(MM - 2) + kBlock - 1) / kBlock;
+  constexpr int L1SZ = H1::SZ > HUS ? H1::SZ : HUS;
+  // staged coefficient inputs (split form, first tile only) share red's space
+  constexpr int CF = 0, CH = 2 * MM + 2, CC = CH + MM, CSN = CC + MM, CG = CSN + MM;
+  static_assert(CG + MM + 1 <= 4 * NS, "coefficient staging exceeds the reduction buffer");
   __shared__ double L2[H2::SZ];
-  __shared__ double L1[H1::SZ];
+  __shared__ double L1[L1SZ];
   __shared__ double red[4 * NS];
   __shared__ double sY[MM], cY[MM];
+  __shared__ double sAlpha;
+  __shared__ int sFlag;
   const Geo g = me.job.g;
   const gptr<T> V = gmem((T*)me.job.V);
   const gptr<const T> U = V + (size_t)(me.job.m + (j & 1)) * g.ldv;
   const gptr<T> Unext = V + (size_t)(me.job.m + ((j + 1) & 1)) * g.ldv;
-  const double ainv = 1.0 / alpha;
+  const bool writer = me.job.lblk == 0;
+  const int c = j - 1;
+  double ainv = 0.0, sYl = 0.0, cYl = 0.0;
+  double stA = 0.0, stB = 0.0, hs[SPLIT ? HT : 1];
+  StopState ss{};
+  if constexpr (!SPLIT) {
+    // coefficients from coef(j)
+    ainv = 1.0 / C->alpha;
+    sYl = tid < j ? C->sY[tid] : 0.0;
+    cYl = tid <= j ? C->cY[tid] : 0.0;
+  } else {
+    // inputs of the coefficient update, loaded unconditionally at clamped
+    // indices: A = column sums (2j+2) then h_{j-1} (j); B (used by the
+    // system's first workgroup only) = cs, sn (j-1 each) then g (j); the
+    // Hessenberg columns 0..j-2
+    const int nA = 3 * j + 2, nB = 3 * j - 2, hlim = j > 1 ? hu_off(j - 1) : 0;
+    const int a = tid < nA ? tid : 0;
+    const gptr<const double> pa = a < 2 * j + 2 ? C->sums + a : C->hprev[j & 1] + (a - (2 * j + 2));
+    stA = *pa;
+    const int b = tid < nB ? tid : 0;
+    const gptr<const double> pb = b < c ? C->cs + b : (b < 2 * c ? C->sn + (b - c) : C->g + (b - 2 * c));
+    stB = *pb;
+#pragma unroll
+    for (int k = 0; k < HT; ++k) {
+      const int e = tid + kBlock * k;
+      hs[k] = C->Hu[e < hlim ? e : 0];
+    }
+    ss = stop_state(C);
+  }
   double accw[NCH + 1];
 #pragma unroll
-  for (int c = 0; c <= NCH; ++c) accw[c] = 0.0;
-  for (int tile = me.job.t0; tile < me.job.t1; ++tile) {
+  for (int cc = 0; cc <= NCH; ++cc) accw[cc] = 0.0;
+  // the first tile is peeled off the tile loop (a straight-line copy of the
+  // body), so that no loop-carried register reuse makes its data loads wait
+  // for the coefficient inputs issued before them
+  auto sweep = [&](const int tile, auto first_c) -> bool {
+    constexpr bool FIRST = decltype(first_c)::value;
     int ox, oy, oz;
     tile_origin<TL>(g, tile, ox, oy, oz);
     // ---- every global load of the tile is issued here, before any is used,
@@ -913,10 +1044,74 @@ __global__ __launch_bounds__(kBlock) void k_step(const Job* jobs, const SysDesc*
       const int e = threadIdx.x + kBlock * h;
       if (e < H2::SZ) L2[e] = hin[h] ? (double)hv[h] : 0.0;
     }
-    if (tile == me.job.t0) {
-      if (phase != PH_RUN || cycle_end) return;      // uniform: the whole workgroup leaves
-      if (tid < j) sY[tid] = sYl;
-      if (tid <= j) cY[tid] = cYl;
+    if constexpr (FIRST) {
+      if constexpr (SPLIT) {
+        // the coefficient inputs go to LDS before any branch, so that waiting
+        // for them does not wait for the tile's data loads
+        const int nA = 3 * j + 2, nB = 3 * j - 2, hlim = j > 1 ? hu_off(j - 1) : 0;
+        if (tid < nA) red[tid < 2 * j + 2 ? CF + tid : CH + tid - (2 * j + 2)] = stA;
+        if (tid < nB) red[tid < c ? CC + tid : (tid < 2 * c ? CSN + tid - c : CG + tid - 2 * c)] = stB;
+#pragma unroll
+        for (int k = 0; k < HT; ++k) {
+          const int e = tid + kBlock * k;
+          if (e < hlim) L1[e] = hs[k];
+        }
+      }
+      if (phase != PH_RUN || cycle_end) return false;  // uniform: the whole workgroup leaves
+      if constexpr (!SPLIT) {
+        if (tid < j) sY[tid] = sYl;
+        if (tid <= j) cY[tid] = cYl;
+      } else {
+        // ---- coefficient update of step j (this workgroup's own copy; the
+        // system's first workgroup also advances the system's state)
+        double* fin = red + CF;
+        __syncthreads();
+        double rot = 0.0, gnew = 0.0;
+        if (tid < 64) {
+          const int lane = tid;
+          const StepCoef q = coef_project(fin, L1, j, red[CH + (lane < j ? lane : 0)]);
+          if (lane < j) sY[lane] = q.si;
+          if (lane <= j) cY[lane] = q.cy;
+          if (lane == 0) sAlpha = q.alpha;
+          int fl = 0;
+          if (writer) {
+            if (j > 0)
+              fl = coef_rotate(C, q, j, ss, red[CC + (lane < c ? lane : 0)],
+                               red[CSN + (lane < c ? lane : 0)], red[CG + c], rot, gnew);
+            else if (lane == 0)
+              C->hprev[1][0] = q.h;
+          }
+          if (lane == 0) sFlag = fl;
+        }
+        __syncthreads();
+        // only the system's first workgroup can stop here; the others finish
+        // the sweep, whose results no later step reads
+        const int fl = sFlag;
+        if (fl != 0) {
+          if (fl == 2 && tid == 0) finish_rhs(C);
+          if (fl == 1) {
+            // end of the cycle: R in L1's space (columns 0..c-1 from memory,
+            // column c from wavefront 0's registers), then y
+            const int rlim = r_off(c);
+            double rv[RT];
+#pragma unroll
+            for (int k = 0; k < RT; ++k) {
+              const int e = tid + kBlock * k;
+              rv[k] = C->R[e < rlim ? e : 0];
+            }
+#pragma unroll
+            for (int k = 0; k < RT; ++k) {
+              const int e = tid + kBlock * k;
+              if (e < rlim) L1[e] = rv[k];
+            }
+            if (tid <= c) L1[rlim + tid] = rot;
+            __syncthreads();
+            if (tid < 64) back_substitute(C, L1, j, tid < j ? (tid == c ? gnew : red[CG + tid]) : 0.0);
+          }
+          return false;
+        }
+        ainv = 1.0 / sAlpha;
+      }
     }
     __syncthreads();
     const double cyj = cY[j];
@@ -999,7 +1194,10 @@ __global__ __launch_bounds__(kBlock) void k_step(const Job* jobs, const SysDesc*
         accw[c] += rs16(prod);
       }
     accw[NCH] += rs4(last);
-  }
+    return true;
+  };
+  if (!sweep(me.job.t0, std::true_type{})) return;
+  for (int tile = me.job.t0 + 1; tile < me.job.t1; ++tile) sweep(tile, std::false_type{});
   // per-wavefront sums -> LDS -> block sums -> this workgroup's partials
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   if ((lane & 3) == 0) {
@@ -1069,19 +1267,25 @@ __global__ __launch_bounds__(kBlock) void k_update(const Job* jobs, const SysDes
 // each keeps the coefficients of the finished solve but is marked running
 // with a zero tolerance, so every timed launch does its full work.
 // descs[i] is the system descriptor pointing at copy i.
-__global__ void k_bench_setup(const SysDesc* src_desc, SysDesc* descs, Ctrl* copies, int n) {
+__global__ void k_bench_setup(const SysDesc* src_desc, SysDesc* descs, Ctrl* copies, int n,
+                              int j) {
   const int i = blockIdx.x;
   if (i >= n) return;
   const unsigned int* s = (const unsigned int*)src_desc->C;
   unsigned int* d = (unsigned int*)(copies + i);
   for (int e = threadIdx.x; e < (int)(sizeof(Ctrl) / 4); e += blockDim.x) d[e] = s[e];
   __syncthreads();
+  Ctrl* c = copies + i;
+  // column sums of a unit direction orthogonal to the basis (alpha = 1), so a
+  // split step at j runs its full sweep
+  for (int e = threadIdx.x; e < 2 * kMaxRestart + 2; e += blockDim.x)
+    c->sums[e] = e == 2 * j ? 1.0 : 0.0;
   if (threadIdx.x == 0) {
-    Ctrl* c = copies + i;
     c->phase = PH_RUN;
     c->rhs = 0;
     c->cycle_end = 0;
     c->tol_abs = 0.0;
+    c->fixed = 1;
     c->limit = 1LL << 62;
     c->k = c->m;
     if (!(c->alpha > 0.0)) c->alpha = 1.0;

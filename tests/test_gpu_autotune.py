@@ -33,16 +33,17 @@ def test_autotune_choice_is_used(mlg, shape, m, precision):
     print("autotune", shape, m, precision, flush=True)
     grid = mlg.grid_of(shape)
     tune = mlg.Opts(restart_m=m, precision=precision)
-    tile, fused = mlg.mlg_autotune(grid, tune)
-    print(f"  tile {tile} fused mask {fused:#x}")
+    tile, fused, split = mlg.mlg_autotune(grid, tune)
+    print(f"  tile {tile} fused mask {fused:#x} split mask {split:#x}")
     assert 1 <= tile <= mlg.mlg_tile_count(len(shape))
-    assert fused < (1 << m)
+    assert fused < (1 << m) and split & ~fused == 0
     if len(shape) == 3:
         assert fused == 0                       # no fused sweep in 3D
     b = DriftingGaussians(shape, 3, 0.06, seed=42).field(0)
     tol = 1e-9
     xa, sa = solve(mlg, b, restart_m=m, rtol=tol, precision=precision)
     # the same tile with the tuned mask forced through an explicit schedule
+    # (both forms of the fused sweep give the same bits)
     sched = 2 if fused == (1 << m) - 1 else (1 if fused == 0 else None)
     if sched is not None:
         xe, se = solve(mlg, b, restart_m=m, rtol=tol, precision=precision, tile=tile,

@@ -87,8 +87,30 @@ def test_batched_equals_single(mlg):
             k += 1
 
 
-def test_batched_edge_cases(mlg):
-    print("batched edges", flush=True)
+def test_batched_split_form_matches_fused(mlg):
+    """A batch of 2D and 3D systems with the split form: the 2D group sums its
+    partials over workgroups while the 3D group keeps one coef launch per
+    system; every solution matches the fused form bitwise."""
+    print("batched split", flush=True)
+    nrhs, m, tol = 2, 12, 1e-10
+    rhs = streams(nrhs, 700)
+    out = []
+    for schedule in (2, 3):
+        bs = [torch.from_numpy(r).cuda() for r in rhs]
+        xs = [torch.zeros_like(b) for b in bs]
+        systems = [mlg.make_system(b, x, 1) for b, x in zip(bs, xs)]
+        opts = mlg.Opts(restart_m=m, rtol=tol, schedule=schedule)
+        ws = mlg.workspace(mlg.gmres_batched_workspace_bytes(systems, opts))
+        stats = mlg.gmres_solve_batched(systems, opts, ws)
+        out.append(([x.cpu().numpy() for x in xs], [(s.iters, s.status) for s in stats]))
+    for a, b in zip(out[0][0], out[1][0]):
+        assert np.array_equal(a, b)
+    assert out[0][1] == out[1][1]
+
+
+@pytest.mark.parametrize("schedule", [0, 3])
+def test_batched_edge_cases(mlg, schedule):
+    print("batched edges", schedule, flush=True)
     # a zero right-hand side, an exactly solvable one and a NaN guess in one batch
     sh = (20, 24)
     g = DriftingGaussians(sh, 2, 0.1, seed=1)
@@ -99,7 +121,7 @@ def test_batched_edge_cases(mlg):
     x2 = torch.zeros_like(b2)
     x2[0, 3, 3] = float("nan")
     systems = [mlg.make_system(b, x, 0), mlg.make_system(b2, x2, 0)]
-    opts = mlg.Opts(restart_m=10, rtol=1e-8)
+    opts = mlg.Opts(restart_m=10, rtol=1e-8, schedule=schedule)
     ws = mlg.workspace(mlg.gmres_batched_workspace_bytes(systems, opts))
     with pytest.raises(mlg.MlgError) as e:
         mlg.gmres_solve_batched(systems, opts, ws)

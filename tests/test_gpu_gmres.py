@@ -58,7 +58,9 @@ def test_operator_parity(mlg, shape):
     assert np.max(np.abs(y.cpu().numpy() - ref)) <= 1e-14 * np.abs(ref).max() * 8
 
 
-SCHEDULES = [1, 2]      # separate extend + dots sweeps; fused single sweep (2D)
+# separate extend + dots sweeps; fused single sweep (2D); the fused sweep in
+# the split form (sums over workgroups, coefficients formed in the sweep)
+SCHEDULES = [1, 2, 3]
 
 
 @pytest.mark.parametrize("schedule", SCHEDULES)
@@ -129,11 +131,12 @@ def test_fp32_basis_refinement(mlg, shape, m, tol, schedule):
     assert err <= 2 * kappa(shape) * tol
 
 
-def test_edge_cases(mlg):
+@pytest.mark.parametrize("schedule", [0, 3])
+def test_edge_cases(mlg, schedule):
     shape = (40, 40)
-    print("edge", flush=True)
+    print("edge", schedule, flush=True)
     # b = 0 -> x = 0, no iterations
-    x, st = run(mlg, np.zeros(shape), np.ones(shape), restart_m=10)
+    x, st = run(mlg, np.zeros(shape), np.ones(shape), restart_m=10, schedule=schedule)
     assert st.iters == 0 and np.all(x == 0)
     # eigenvector right-hand side: one Arnoldi step (happy breakdown)
     n = 40
@@ -141,20 +144,21 @@ def test_edge_cases(mlg):
     t = np.sin(2 * np.pi * np.arange(1, n + 1) / (n + 1))
     phi = np.outer(t, s)
     lam = 4 * (n + 1) ** 2 * (np.sin(3 * np.pi / (2 * (n + 1))) ** 2 + np.sin(2 * np.pi / (2 * (n + 1))) ** 2)
-    x, st = run(mlg, lam * phi, restart_m=10)
+    x, st = run(mlg, lam * phi, restart_m=10, schedule=schedule)
     assert st.iters == 1 and np.max(np.abs(x - phi)) <= 1e-13
     # iteration cap -> NOT_CONVERGED with the last iterate kept
     b = DriftingGaussians(shape, 2, 0.1, seed=4).field(0)
-    x, st = run(mlg, b, restart_m=10, rtol=1e-12, max_iters=7, allow_not_converged=True)
+    x, st = run(mlg, b, restart_m=10, rtol=1e-12, max_iters=7, allow_not_converged=True,
+                schedule=schedule)
     assert st.status == 1 and st.iters == 7
     xo, so = og.gmres(b, m=10, rtol=1e-12, max_iters=7)
     assert rel(x, xo) <= 1e-10
     # already converged guess -> nothing to do
     xs, _ = og.gmres(b, m=10, rtol=1e-12)
-    x, st = run(mlg, b, xs, restart_m=10, rtol=1e-8)
+    x, st = run(mlg, b, xs, restart_m=10, rtol=1e-8, schedule=schedule)
     assert st.iters == 0 and np.array_equal(x, xs)
     # restart length 1 and a 1x1 grid
-    x, st = run(mlg, np.array([[2.0]]), restart_m=1)
+    x, st = run(mlg, np.array([[2.0]]), restart_m=1, schedule=schedule)
     assert st.status == 0 and abs(x[0, 0] - 2.0 / 16.0) <= 1e-15
 
 
@@ -180,6 +184,28 @@ def test_errors(mlg):
     # the workspace is reusable after an error
     st = mlg.gmres_solve(grid, b, x, opts, mlg.workspace(need))
     assert st.status == 0
+
+
+@pytest.mark.parametrize("shape,m,kw", [
+    ((64, 64), 20, dict(fixed_iters=57)),
+    ((130, 70), 30, dict(rtol=1e-10)),
+    ((96, 80), 50, dict(rtol=1e-10)),                          # register bound 64 (steps >= 40)
+    ((512, 512), 30, dict(rtol=1e-6, precision=1)),
+    ((1536, 1024), 40, dict(fixed_iters=45, precision=1)),     # several tiles per workgroup
+    ((33, 47), 10, dict(rtol=1e-12, max_iters=23, allow_not_converged=True)),
+])
+def test_split_form_matches_fused(mlg, shape, m, kw):
+    """The split form sums the same partials in the same order and forms the
+    coefficients with the same expressions, so it must reproduce the fused
+    form bitwise, on every tile shape."""
+    print("split", shape, m, kw, flush=True)
+    b = DriftingGaussians(shape, 3, 0.05, seed=11).field(0)
+    for t in range(1, mlg.mlg_tile_count(2) + 1):
+        x2, s2 = run(mlg, b, restart_m=m, tile=t, schedule=2, **dict(kw))
+        x3, s3 = run(mlg, b, restart_m=m, tile=t, schedule=3, **dict(kw))
+        assert np.array_equal(x2, x3), t
+        assert (s2.iters, s2.cycles, s2.status) == (s3.iters, s3.cycles, s3.status), t
+        assert s2.relres_true == s3.relres_true and s2.relres_first_cycle == s3.relres_first_cycle
 
 
 def test_deterministic_and_tiles_agree(mlg):
