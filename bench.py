@@ -302,7 +302,8 @@ def probe(mlg, shape, args):
     """Launches for hardware-counter runs (no timing is reported): a 256 MiB
     device copy (the byte-count calibration), then for every tile shape one
     restart cycle's launches of the probed kernel in the learned-guess solve's
-    configuration (fused steps for `step`), each step index once."""
+    configuration (fused steps in the split form for `step` and `sums`), each
+    step index once."""
     from synthetic import DriftingGaussians
     names = {v.replace("k_", ""): v for v in mlg.KERNEL_NAMES.values()}
     if args.probe not in names:
@@ -313,10 +314,11 @@ def probe(mlg, shape, args):
     torch.cuda.synchronize()
     f0 = torch.from_numpy(DriftingGaussians(shape, 4, 0.03, seed=args.seed).field(0)).cuda()
     opts = mlg.Opts(restart_m=args.restart, rtol=args.rtol, precision=mlg.MLG_FP32_IR)
-    fused = (1 << args.restart) - 1 if args.probe == "step" else 0
+    fused = (1 << args.restart) - 1 if args.probe in ("step", "sums") else 0
     out = {}
     for tile in range(1, mlg.mlg_tile_count(2) + 1):
-        r = kernel_roofline(mlg, shape, opts, f0, tile, fused, reps=1, only=names[args.probe])
+        r = kernel_roofline(mlg, shape, opts, f0, tile, fused, fused, reps=1,
+                            only=names[args.probe])
         out["x".join(map(str, mlg.mlg_tile_shape(2, tile - 1)[:2]))] = r[names[args.probe]]["avg_bytes"]
     torch.cuda.synchronize()
     print(json.dumps({"probe": args.probe, "copy_bytes": 2 * a.numel() * 4, "avg_bytes": out}),
