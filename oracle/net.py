@@ -19,7 +19,12 @@ design notes of the repository):
      sine modes (S = the DST-I basis sin(k pi i/(N+1)), k = 1..M), per-mode
      C x C channel mixing
   L4, L5 conv3x3 C->C + ReLU;  L6 conv3x3 C->1
-  guess = u_prev + (s_r / c_u) * L6, c_u = 2 pi^2
+  skip     S^-1[rho g_kl (c_u / lambda_kl) S[r / s_r]_kl] on the K x K slowest
+           sine modes (the exact inverse of A there when rho g = 1)
+  out = L6 - P_K L6 + skip, P_K the orthogonal projection on the skip's K x K
+        modes: the skip path alone sets the output on its band, the
+        convolutional branch the rest
+  guess = u_prev + (s_r / c_u) * out, c_u = 2 pi^2
 Convolutions are cross-correlations with zero padding (the Dirichlet zero),
 weights in [out, in, ky, kx] layout.  Everything is float64, NCHW, written
 from the definitions (numpy tensordot is the only library primitive).
@@ -142,6 +147,16 @@ def skip_forward(x_r: np.ndarray, g: np.ndarray):
     return out, X
 
 
+def band_project(y: np.ndarray, K: int) -> np.ndarray:
+    """P_K y: the orthogonal projection of y [B, H, W] on the K x K slowest
+    sine modes (orthonormal rows sqrt(2/(n+1)) S)."""
+    B, H, W = y.shape
+    Sy, Sx = sine_basis(H, K), sine_basis(W, K)
+    norm = (2.0 / (H + 1)) * (2.0 / (W + 1))
+    Y = np.einsum("ki,bij,lj->bkl", Sy, y, Sx, optimize=True)
+    return norm * np.einsum("ki,bkl,lj->bij", Sy, Y, Sx, optimize=True)
+
+
 def skip_backward(g: np.ndarray, X: np.ndarray, d_out: np.ndarray) -> np.ndarray:
     B, H, W = d_out.shape
     M = g.shape[0]
@@ -163,7 +178,8 @@ def forward(params: dict, f: np.ndarray, u_prev: np.ndarray, keep: bool = False)
     a4 = np.maximum(conv3x3(a3, params["conv4.w"], params["conv4.b"]), 0.0)
     a5 = np.maximum(conv3x3(a4, params["conv5.w"], params["conv5.b"]), 0.0)
     skip, Xr = skip_forward(x0[:, 0], params["skip.g"])
-    out = conv3x3(a5, params["conv6.w"], params["conv6.b"])[:, 0] + skip
+    c6 = conv3x3(a5, params["conv6.w"], params["conv6.b"])[:, 0]
+    out = c6 - band_project(c6, params["skip.g"].shape[0]) + skip
     guess = u_prev + (s_r / C_U)[:, None, None] * out
     if keep:
         c.update(a1=a1, a2=a2, a3=a3, a4=a4, a5=a5, spec=sc, Xr=Xr)
@@ -186,6 +202,8 @@ def loss_and_grads(params: dict, f, u_prev, u_target):
     g = {}
     d6 = (2.0 / B) * diff[:, None]
     g["skip.g"] = skip_backward(params["skip.g"], c["Xr"], d6[:, 0])
+    # the projection is symmetric: the conv branch sees the gradient off the band
+    d6 = d6 - band_project(d6[:, 0], params["skip.g"].shape[0])[:, None]
     d5, g["conv6.w"], g["conv6.b"] = conv3x3_backward(c["a5"], params["conv6.w"], d6)
     d5 = d5 * (c["a5"] > 0.0)
     d4, g["conv5.w"], g["conv5.b"] = conv3x3_backward(c["a4"], params["conv5.w"], d5)

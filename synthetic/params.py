@@ -9,7 +9,7 @@ Tensor names and shapes (torch-style conv layout [out, in, ky, kx]):
     conv4.w [C, C, 3, 3]   conv4.b [C]
     conv5.w [C, C, 3, 3]   conv5.b [C]
     conv6.w [1, C, 3, 3]   conv6.b [1]
-    skip.g  [M, M]                          (per-mode gains of the spectral skip path)
+    skip.g  [K, K]                          (per-mode gains of the spectral skip path)
 
 Weights are uniform in +-sqrt(6 / fan_in) (He-uniform); biases are drawn in
 +-0.1 when ``random_bias`` is set (tests) and are zero otherwise; the skip
@@ -27,8 +27,9 @@ PARAM_ORDER = ("conv1.w", "conv1.b", "conv2.w", "conv2.b", "spec.w1", "spec.b",
                "conv6.w", "conv6.b", "skip.g")
 
 
-def param_shapes(channels: int = 32, modes: int = 16) -> dict:
+def param_shapes(channels: int = 32, modes: int = 16, skip_modes: int | None = None) -> dict:
     C, M = channels, modes
+    K = M if skip_modes is None else skip_modes
     return {
         "conv1.w": (C, 2, 3, 3), "conv1.b": (C,),
         "conv2.w": (C, C, 3, 3), "conv2.b": (C,),
@@ -37,16 +38,17 @@ def param_shapes(channels: int = 32, modes: int = 16) -> dict:
         "conv4.w": (C, C, 3, 3), "conv4.b": (C,),
         "conv5.w": (C, C, 3, 3), "conv5.b": (C,),
         "conv6.w": (1, C, 3, 3), "conv6.b": (1,),
-        "skip.g": (M, M),
+        "skip.g": (K, K),
     }
 
 
 def guess_net_params(seed: int, channels: int = 32, modes: int = 16,
-                     zero_last: bool = False, random_bias: bool = True) -> dict:
+                     zero_last: bool = False, random_bias: bool = True,
+                     skip_modes: int | None = None) -> dict:
     rng = np.random.default_rng(seed)
     out = {}
     for name in PARAM_ORDER:
-        shape = param_shapes(channels, modes)[name]
+        shape = param_shapes(channels, modes, skip_modes)[name]
         if name.endswith(".b"):
             out[name] = (rng.uniform(-0.1, 0.1, size=shape) if random_bias
                          else np.zeros(shape))

@@ -15,8 +15,9 @@ from oracle import net
 from synthetic import DriftingGaussians, guess_net_params
 
 
-def small_params(C=4, M=3, seed=0):
-    return guess_net_params(seed, channels=C, modes=M, zero_last=False, random_bias=True)
+def small_params(C=4, M=3, seed=0, K=None):
+    return guess_net_params(seed, channels=C, modes=M, zero_last=False, random_bias=True,
+                            skip_modes=K)
 
 
 def test_conv_direct_sum_and_torch():
@@ -146,6 +147,33 @@ def test_skip_path_is_the_truncated_inverse():
     assert np.allclose((A @ phi.ravel()).reshape(H, W), lam[2, 4] * phi, atol=1e-9 * lam[2, 4])
 
 
+def test_guess_is_exact_on_the_skip_band_whatever_the_convolutions():
+    """With every skip gain at 1/RHO and random (nonzero) convolutions, the
+    correction d = guess - u_prev agrees with the exact correction A^-1 r
+    (dense LU solve) on the K x K skip band, and the convolutional branch
+    still acts off the band."""
+    from test_oracle_gmres import sparse_laplacian
+    H, W, M, K = 13, 11, 3, 5
+    p = guess_net_params(9, channels=4, modes=M, skip_modes=K)
+    p["skip.g"] = np.full((K, K), 1.0 / net.RHO)
+    rng = np.random.default_rng(21)
+    f = rng.standard_normal((2, H, W))
+    u = rng.standard_normal((2, H, W))
+    g, _, _ = net.forward(p, f, u)
+    A = sparse_laplacian((H, W)).toarray()
+    Qy = net.sine_basis(H, K) * np.sqrt(2.0 / (H + 1))
+    Qx = net.sine_basis(W, K) * np.sqrt(2.0 / (W + 1))
+    for b in range(2):
+        r = f[b] - (A @ u[b].ravel()).reshape(H, W)
+        d_exact = np.linalg.solve(A, r.ravel()).reshape(H, W)
+        d = g[b] - u[b]
+        on_band = Qy @ d @ Qx.T
+        assert np.allclose(on_band, Qy @ d_exact @ Qx.T, rtol=0,
+                           atol=1e-10 * np.abs(Qy @ d_exact @ Qx.T).max())
+        off_band = d - Qy.T @ on_band @ Qx
+        assert np.linalg.norm(off_band) > 1e-3 * np.linalg.norm(d)
+
+
 def test_loss_closed_form():
     p = small_params()
     rng = np.random.default_rng(6)
@@ -161,7 +189,7 @@ def test_loss_closed_form():
 
 @pytest.mark.parametrize("seed", [0, 1])
 def test_gradients_match_finite_differences(seed):
-    p = small_params(C=4, M=3, seed=seed)
+    p = small_params(C=4, M=3, seed=seed, K=4)
     rng = np.random.default_rng(10 + seed)
     B, H, W = 2, 7, 6
     f = rng.standard_normal((B, H, W))
@@ -182,7 +210,7 @@ def test_gradients_match_finite_differences(seed):
 
 def test_gradients_match_torch_autograd():
     """Same network written with torch CPU float64 ops and autograd."""
-    p = small_params(C=4, M=3, seed=2)
+    p = small_params(C=4, M=3, seed=2, K=5)
     rng = np.random.default_rng(12)
     B, H, W = 2, 8, 9
     f = rng.standard_normal((B, H, W))
@@ -204,13 +232,17 @@ def test_gradients_match_torch_autograd():
     a = F.relu(F.conv2d(a, T["spec.w1"][:, :, None, None], T["spec.b"]) + ys)
     a = F.relu(F.conv2d(a, T["conv4.w"], T["conv4.b"], padding=1))
     a = F.relu(F.conv2d(a, T["conv5.w"], T["conv5.b"], padding=1))
-    out = F.conv2d(a, T["conv6.w"], T["conv6.b"], padding=1)[:, 0]
-    kk = np.arange(1, M + 1)
+    c6 = F.conv2d(a, T["conv6.w"], T["conv6.b"], padding=1)[:, 0]
+    K = 5
+    Ky = torch.tensor(np.sin(np.arange(1, K + 1)[:, None] * np.pi * np.arange(1, H + 1)[None] / (H + 1)))
+    Kx = torch.tensor(np.sin(np.arange(1, K + 1)[:, None] * np.pi * np.arange(1, W + 1)[None] / (W + 1)))
+    nrm = (2.0 / (H + 1)) * (2.0 / (W + 1))
+    kk = np.arange(1, K + 1)
     lam = torch.tensor((4.0 * (H + 1) ** 2 * np.sin(kk * np.pi / (2 * (H + 1))) ** 2)[:, None]
                        + (4.0 * (W + 1) ** 2 * np.sin(kk * np.pi / (2 * (W + 1))) ** 2)[None, :])
-    Xr = Sy @ x[:, 0] @ Sx.T
-    out = out + (2.0 / (H + 1)) * (2.0 / (W + 1)) * (
-        Sy.T @ (32.0 * T["skip.g"] * (2 * np.pi ** 2) / lam * Xr) @ Sx)
+    Xr = Ky @ x[:, 0] @ Kx.T
+    out = c6 - nrm * (Ky.T @ (Ky @ c6 @ Kx.T) @ Kx) + nrm * (
+        Ky.T @ (32.0 * T["skip.g"] * (2 * np.pi ** 2) / lam * Xr) @ Kx)
     t = torch.tensor(net.target(ut, u, s))
     Lt = ((out - t) ** 2).sum() / B
     Lt.backward()
