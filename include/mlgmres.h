@@ -222,9 +222,12 @@ int mlg_autotune(const mlg_grid* grid, const mlg_opts* opts, void* ws, size_t ws
  *   L3 spectral: ReLU(W1 x + b + S^-1[W_kl . S[x]_kl]) over the modes x modes
  *      slowest sine modes (S = DST-I basis), per-mode C x C mixing,
  *   L4, L5 conv3x3 C->C + ReLU, L6 conv3x3 C->1;
- *   spectral skip (FP32): out = L6 + S^-1[32 g_kl (c_u / lambda_kl) S[r/s_r]_kl]
- *      over the same modes, lambda_kl the eigenvalues of A (g = 1/32 applies
- *      the exact inverse of A on those modes);
+ *   spectral skip (FP32) over the skip_modes x skip_modes slowest sine modes
+ *      (the skip band K): skip = S^-1[32 g_kl (c_u / lambda_kl) S[r/s_r]_kl],
+ *      lambda_kl the eigenvalues of A (g = 1/32 applies the exact inverse of
+ *      A on the band);
+ *   out = L6 - P_K L6 + skip, P_K the orthogonal projection on the band: the
+ *      skip alone sets the output on the band, the convolutions the rest;
  *   guess = u_prev + (s_r / c_u) out  (= u_prev when u_prev solves A u = f).
  * Weights and activations are BF16 in the kernels with FP32 accumulation;
  * FP32 master weights and Adam moments (Section 2.3: back-propagation and
@@ -232,7 +235,8 @@ int mlg_autotune(const mlg_grid* grid, const mlg_opts* opts, void* ws, size_t ws
  */
 typedef struct {
   int32_t channels;   /* C, 32; multiple of 16, <= 64 */
-  int32_t modes;      /* M, 16; <= 32 */
+  int32_t modes;      /* M, 16; <= 32 (the L3 spectral layer) */
+  int32_t skip_modes; /* K, 32; 1..128 (the skip band) */
   float lr, beta1, beta2, eps;
   uint64_t seed;
 } guess_net_cfg;
@@ -248,7 +252,7 @@ typedef struct {
  *   conv1.w [C,2,3,3] conv1.b [C] conv2.w [C,C,3,3] conv2.b [C]
  *   spec.w1 [C,C] spec.b [C] spec.wk [M,M,C,C] (= [ky, kx, out, in])
  *   conv4.w conv4.b conv5.w conv5.b (as conv2) conv6.w [1,C,3,3] conv6.b [1]
- *   skip.g [M,M] (= [ky, kx]; read from the FP32 master copy)
+ *   skip.g [K,K] (= [ky, kx]; read from the FP32 master copy)
  * guess_net_param_count gives P; guess_net_param_offset the element offset
  * of tensor `index` (0..13 in the order above) inside one array.
  */

@@ -81,12 +81,14 @@ class System(ctypes.Structure):
 
 
 class NetCfg(ctypes.Structure):
-    _fields_ = [("channels", ctypes.c_int32), ("modes", ctypes.c_int32), ("lr", ctypes.c_float),
+    _fields_ = [("channels", ctypes.c_int32), ("modes", ctypes.c_int32),
+                ("skip_modes", ctypes.c_int32), ("lr", ctypes.c_float),
                 ("beta1", ctypes.c_float), ("beta2", ctypes.c_float), ("eps", ctypes.c_float),
                 ("seed", ctypes.c_uint64)]
 
-    def __init__(self, channels=32, modes=16, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, seed=0):
-        super().__init__(channels, modes, lr, beta1, beta2, eps, seed)
+    def __init__(self, channels=32, modes=16, skip_modes=32, lr=1e-3, beta1=0.9, beta2=0.999,
+                 eps=1e-8, seed=0):
+        super().__init__(channels, modes, skip_modes, lr, beta1, beta2, eps, seed)
 
 
 def _load():
@@ -339,11 +341,11 @@ NET_TENSORS = ("conv1.w", "conv1.b", "conv2.w", "conv2.b", "spec.w1", "spec.b", 
 
 
 def net_tensor_shapes(cfg: NetCfg) -> dict:
-    C, M = cfg.channels, cfg.modes
+    C, M, K = cfg.channels, cfg.modes, cfg.skip_modes
     return {"conv1.w": (C, 2, 3, 3), "conv1.b": (C,), "conv2.w": (C, C, 3, 3), "conv2.b": (C,),
             "spec.w1": (C, C), "spec.b": (C,), "spec.wk": (M, M, C, C),
             "conv4.w": (C, C, 3, 3), "conv4.b": (C,), "conv5.w": (C, C, 3, 3), "conv5.b": (C,),
-            "conv6.w": (1, C, 3, 3), "conv6.b": (1,), "skip.g": (M, M)}
+            "conv6.w": (1, C, 3, 3), "conv6.b": (1,), "skip.g": (K, K)}
 
 
 def _align(v: int, a: int = 256) -> int:

@@ -6,13 +6,16 @@
 // the network in situ on the (RHS, solution) pairs the solver produces with the
 // loss |x_tilde - x|^2 (Section 2.3) by back-propagation and ADAM; Section 2.1
 // asks for a network that captures non-local relations without reducing
-// resolution.  Architecture (C channels, M x M retained sine modes):
+// resolution.  Architecture (C channels, M x M sine modes in L3, K x K in the
+// skip band):
 //   x0 = (f/s, c_u u_prev/s)                          BF16 NHWC, 2 channels
 //   a1 = ReLU(conv3x3(x0))          a2 = ReLU(conv3x3(a1))
 //   a3 = ReLU(W1 a2 + b + S^-1[Wk . S[a2]])           (spectral mixing)
 //   a4 = ReLU(conv3x3(a3))          a5 = ReLU(conv3x3(a4))
-//   out = conv3x3(a5) (1 channel, FP32)
-//       + S^-1[rho g_kl (c_u / lambda_kl) S[r/s_r]_kl]    (spectral skip, FP32)
+//   c6 = conv3x3(a5) (1 channel, FP32)
+//   out = c6 - P_K c6 + S^-1[rho g_kl (c_u / lambda_kl) S[r/s_r]_kl]   (FP32)
+//       (P_K: projection on the skip band; the skip alone sets the output
+//       there, with unit rho g the exact inverse of A on the band)
 //   guess = u_prev + (s_r/c_u) out
 // The 3x3 convolutions with C -> C channels (forward, input gradient and
 // weight gradient) run on MFMA (v_mfma_f32_16x16x32_bf16) as implicit GEMMs
@@ -60,14 +63,14 @@ struct MPtrs {
 
 // ------------------------------------------------------------------ sizes
 struct Dims {
-  int B, H, W, C, M;
+  int B, H, W, C, M, K;          // K: skip band modes
   long long HW;
 };
 
 void tensor_sizes(const guess_net_cfg* cfg, int64_t* sz) {
-  const int64_t C = cfg->channels, M = cfg->modes;
+  const int64_t C = cfg->channels, M = cfg->modes, K = cfg->skip_modes;
   int64_t s[kNumTensors] = {C * 2 * 9, C, C * C * 9, C, C * C, C, M * M * C * C,
-                            C * C * 9, C, C * C * 9, C, C * 9, 1, M * M};
+                            C * C * 9, C, C * C * 9, C, C * 9, 1, K * K};
   for (int i = 0; i < kNumTensors; ++i) sz[i] = s[i];
 }
 
@@ -75,6 +78,8 @@ void check_cfg(const guess_net_cfg* cfg) {
   if (!cfg) throw ArgError{MLG_ERR_ARG, "cfg is NULL"};
   if (cfg->channels != 32) throw ArgError{MLG_ERR_ARG, "channels must be 32"};
   if (cfg->modes < 1 || cfg->modes > 32) throw ArgError{MLG_ERR_ARG, "modes must be in 1..32"};
+  if (cfg->skip_modes < 1 || cfg->skip_modes > 128)
+    throw ArgError{MLG_ERR_ARG, "skip_modes must be in 1..128"};
 }
 
 struct ParamLayout {
@@ -105,17 +110,18 @@ ParamLayout param_layout(const guess_net_cfg* cfg) {
 Dims check_grid_net(const guess_net_cfg* cfg, const mlg_grid* grid, int batch) {
   check_cfg(cfg);
   if (!grid || grid->dim != 2) throw ArgError{MLG_ERR_ARG, "the guess network takes 2D grids"};
-  if (grid->nx < cfg->modes || grid->ny < cfg->modes)
-    throw ArgError{MLG_ERR_ARG, "grid must have at least `modes` points per axis"};
+  const int mx = std::max(cfg->modes, cfg->skip_modes);
+  if (grid->nx < mx || grid->ny < mx)
+    throw ArgError{MLG_ERR_ARG, "grid must have at least max(modes, skip_modes) points per axis"};
   if (batch < 1 || batch > kMaxBatch) throw ArgError{MLG_ERR_ARG, "batch must be in 1..64"};
-  Dims d{batch, grid->ny, grid->nx, cfg->channels, cfg->modes,
+  Dims d{batch, grid->ny, grid->nx, cfg->channels, cfg->modes, cfg->skip_modes,
          (long long)grid->nx * grid->ny};
   return d;
 }
 
 struct WsLayout {
   size_t s, r0, x0, act[5], out, dout, dz[2], T, X, Y, dX, Z, Sx, Sy, part, loss;
-  size_t kT, kX, kY, kZ, kdY, total;          // spectral skip path
+  size_t kT, kX, kC, kY, kZ, kdY, kSx, kSy, total;   // spectral skip path (FP64)
   int wgrad_blocks;
 };
 
@@ -140,11 +146,14 @@ WsLayout ws_layout(const Dims& d, bool train) {
   L.Z = take((size_t)d.B * d.H * d.M * d.C * 4);
   L.Sx = take((size_t)d.M * d.W * 4);
   L.Sy = take((size_t)d.M * d.H * 4);
-  L.kT = take((size_t)d.B * d.H * d.M * 4);
-  L.kX = take((size_t)d.B * d.M * d.M * 4);
-  L.kY = take((size_t)d.B * d.M * d.M * 4);
-  L.kZ = take((size_t)d.B * d.H * d.M * 4);
-  L.kdY = train ? take((size_t)d.B * d.M * d.M * 4) : 0;
+  L.kT = take((size_t)d.B * d.H * d.K * 8);
+  L.kX = take((size_t)d.B * d.K * d.K * 8);
+  L.kC = take((size_t)d.B * d.K * d.K * 8);
+  L.kY = take((size_t)d.B * d.K * d.K * 8);
+  L.kZ = take((size_t)d.B * d.H * d.K * 8);
+  L.kdY = train ? take((size_t)d.B * d.K * d.K * 8) : 0;
+  L.kSx = take((size_t)d.K * d.W * 8);
+  L.kSy = take((size_t)d.K * d.H * 8);
   L.wgrad_blocks = 0;
   if (train) {
     L.dout = take((size_t)d.B * d.HW * 4);
@@ -712,20 +721,49 @@ __global__ __launch_bounds__(256) void k_spec_out(const bf16* in, const bf16* w1
 }
 
 // ------------------------------------------------------------------ spectral skip
+// FP64 throughout: the residual of a slowly moving source is dipole-like, so
+// its projection on the slowest modes cancels heavily, and FP32 sums (or an
+// FP32-rounded basis) leave errors in the mode coefficients comparable to the
+// coefficients themselves; trained on such inputs the gains settle below the
+// exact inverse.
+
+// S[k][j] = sin((k+1) pi (j+1) / (n+1)) in FP64
+__global__ void k_skip_basis(double* S, int M, int n) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= M * n) return;
+  const int k = e / n, j = e % n;
+  S[e] = sin((double)(k + 1) * M_PI * (double)(j + 1) / (double)(n + 1));
+}
+
 // T[b][i][l] = sum_j Sx[l][j] x[b][i][j] / div[b]  (one thread per output)
 template <class X>
-__global__ void k_skip_rows(const X* x, const double* div, const float* Sx, float* T, int B, int H,
-                            int W, int M) {
+__global__ void k_skip_rows(const X* x, const double* div, const double* Sx, double* T, int B,
+                            int H, int W, int M) {
   const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= (long long)B * H * M) return;
   const int l = (int)(e % M);
   const long long bi = e / M;
   const int b = (int)(bi / H);
   const X* xr = x + bi * W;
-  const float* sr = Sx + (size_t)l * W;
-  float s = 0.f;
-  for (int j = 0; j < W; ++j) s += sr[j] * (float)xr[j];
-  T[e] = div ? (float)((double)s / div[b]) : s;
+  const double* sr = Sx + (size_t)l * W;
+  double s = 0.0;
+  for (int j = 0; j < W; ++j) s += sr[j] * (double)xr[j];
+  T[e] = div ? s / div[b] : s;
+}
+
+// X[b][k][l] = scale sum_i Sy[k][i] T[b][i][l]  (one thread per output)
+__global__ void k_skip_cols(const double* T, const double* Sy, double* X, int B, int H, int M,
+                            double scale) {
+  const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (long long)B * M * M) return;
+  const int l = (int)(e % M);
+  const long long bk = e / M;
+  const int k = (int)(bk % M), b = (int)(bk / M);
+  const double* tp = T + (size_t)b * H * M + l;
+  const double* sy = Sy + (size_t)k * H;
+  double acc = 0.0;
+  for (int i = 0; i < H; ++i) acc += sy[i] * tp[(size_t)i * M];
+  X[e] = scale * acc;
 }
 
 // lambda_kl of the zero-Dirichlet 5-point Laplacian on the (k+1, l+1) sine mode
@@ -735,36 +773,52 @@ __device__ __forceinline__ double mode_lambda(int k, int l, int H, int W) {
   return 4.0 * (H + 1.0) * (H + 1.0) * sy * sy + 4.0 * (W + 1.0) * (W + 1.0) * sx * sx;
 }
 
-// Y[b][k][l] = rho g_kl (c_u / lambda_kl) X[b][k][l]  (FP32 master gains)
-__global__ void k_skip_gain(const float* X, const float* g, float* Y, int B, int H, int W, int M) {
+// Y[b][k][l] = rho g_kl (c_u / lambda_kl) X[b][k][l] - Cc[b][k][l]: the skip
+// path's band coefficients in place of those of the convolutional output
+// (FP32 master gains)
+__global__ void k_skip_gain(const double* X, const double* Cc, const float* g, double* Y, int B,
+                            int H, int W, int M) {
   const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= (long long)B * M * M) return;
   const int kl = (int)(e % (M * M));
   const int k = kl / M, l = kl % M;
-  Y[e] = (float)(kRho * (double)g[kl] * kCu / mode_lambda(k, l, H, W)) * X[e];
+  Y[e] = kRho * (double)g[kl] * kCu / mode_lambda(k, l, H, W) * X[e] - Cc[e];
 }
 
-// out[b][i][j] += beta sum_l Sx[l][j] Z[b][i][l]
-__global__ void k_skip_out(const float* Z, const float* Sx, float* out, int B, int H, int W, int M,
-                           float beta) {
+// Z[b][i][l] = alpha sum_k Sy[k][i] Y[b][k][l]
+__global__ void k_skip_inv_cols(const double* Y, const double* Sy, double* Z, int B, int H, int M,
+                                double alpha) {
+  const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (long long)B * H * M) return;
+  const int l = (int)(e % M);
+  const long long bi = e / M;
+  const int i = (int)(bi % H), b = (int)(bi / H);
+  double s = 0.0;
+  for (int k = 0; k < M; ++k) s += Sy[(size_t)k * H + i] * Y[((size_t)b * M + k) * M + l];
+  Z[e] = alpha * s;
+}
+
+// out[b][i][j] += beta sum_l Sx[l][j] Z[b][i][l]  (sum and add in FP64)
+__global__ void k_skip_out(const double* Z, const double* Sx, float* out, int B, int H, int W,
+                           int M, double beta) {
   const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= (long long)B * H * W) return;
   const int j = (int)(e % W);
   const long long bi = e / W;
-  const float* zr = Z + bi * M;
-  float s = 0.f;
+  const double* zr = Z + bi * M;
+  double s = 0.0;
   for (int l = 0; l < M; ++l) s += Sx[(size_t)l * W + j] * zr[l];
-  out[e] += beta * s;
+  out[e] = (float)((double)out[e] + beta * s);
 }
 
 // grad g_kl = rho (c_u / lambda_kl) sum_b dY[b][k][l] X[b][k][l]
-__global__ void k_skip_grad(const float* dY, const float* X, float* grad, int B, int H, int W,
+__global__ void k_skip_grad(const double* dY, const double* X, float* grad, int B, int H, int W,
                             int M) {
   const int kl = blockIdx.x * blockDim.x + threadIdx.x;
   if (kl >= M * M) return;
-  float s = 0.f;
+  double s = 0.0;
   for (int b = 0; b < B; ++b) s += dY[(size_t)b * M * M + kl] * X[(size_t)b * M * M + kl];
-  grad[kl] = (float)(kRho * kCu / mode_lambda(kl / M, kl % M, H, W)) * s;
+  grad[kl] = (float)(kRho * kCu / mode_lambda(kl / M, kl % M, H, W) * s);
 }
 
 // ------------------------------------------------------------------ parameters
@@ -899,20 +953,31 @@ void forward(const Net& n, const Ptrs& f, const Ptrs& u, hipStream_t s) {
                                                           a[4], d.H, d.W);
   k_conv_small<C, 1, bf16, float, false, false><<<dim3(cdiv(HW, 256), d.B), 256, 0, s>>>(
       a[4], n.bfw(T_C6W), n.bfw(T_C6B), nullptr, n.w<float>(n.wl.out), d.H, d.W);
-  // spectral skip from the residual channel (FP32, from the FP64 residual)
-  float* kT = n.w<float>(n.wl.kT);
-  float* kX = n.w<float>(n.wl.kX);
-  float* kY = n.w<float>(n.wl.kY);
-  float* kZ = n.w<float>(n.wl.kZ);
-  k_skip_rows<double><<<cdiv((long long)d.B * d.H * d.M, 256), 256, 0, s>>>(r0, sv + d.B, Sx, kT,
-                                                                            d.B, d.H, d.W, d.M);
-  k_spec_cols<<<cdiv((long long)d.B * d.M, 256), 256, 0, s>>>(kT, Sy, kX, d.B, d.H, d.M, 1, 1.f);
-  k_skip_gain<<<cdiv((long long)d.B * d.M * d.M, 256), 256, 0, s>>>(kX, n.master(T_SKIP), kY, d.B,
-                                                                    d.H, d.W, d.M);
-  k_spec_inv_cols<<<cdiv((long long)d.B * d.H * d.M, 256), 256, 0, s>>>(
-      kY, Sy, kZ, d.B, d.H, d.M, 1, (float)(2.0 / (d.H + 1)));
-  k_skip_out<<<cdiv((long long)d.B * HW, 256), 256, 0, s>>>(kZ, Sx, n.w<float>(n.wl.out), d.B, d.H,
-                                                            d.W, d.M, (float)(2.0 / (d.W + 1)));
+  // spectral skip from the FP64 residual, replacing the band of the
+  // convolutional output: out += norm S^T (gain X - S out S^T) S (FP64)
+  double* kT = n.w<double>(n.wl.kT);
+  double* kX = n.w<double>(n.wl.kX);
+  double* kC = n.w<double>(n.wl.kC);
+  double* kY = n.w<double>(n.wl.kY);
+  double* kZ = n.w<double>(n.wl.kZ);
+  double* kSx = n.w<double>(n.wl.kSx);
+  double* kSy = n.w<double>(n.wl.kSy);
+  float* out = n.w<float>(n.wl.out);
+  const int K = d.K;
+  k_skip_basis<<<cdiv((long long)K * d.W, 256), 256, 0, s>>>(kSx, K, d.W);
+  k_skip_basis<<<cdiv((long long)K * d.H, 256), 256, 0, s>>>(kSy, K, d.H);
+  k_skip_rows<double><<<cdiv((long long)d.B * d.H * K, 256), 256, 0, s>>>(r0, sv + d.B, kSx, kT,
+                                                                         d.B, d.H, d.W, K);
+  k_skip_cols<<<cdiv((long long)d.B * K * K, 256), 256, 0, s>>>(kT, kSy, kX, d.B, d.H, K, 1.0);
+  k_skip_rows<float><<<cdiv((long long)d.B * d.H * K, 256), 256, 0, s>>>(out, nullptr, kSx, kT, d.B,
+                                                                        d.H, d.W, K);
+  k_skip_cols<<<cdiv((long long)d.B * K * K, 256), 256, 0, s>>>(kT, kSy, kC, d.B, d.H, K, 1.0);
+  k_skip_gain<<<cdiv((long long)d.B * K * K, 256), 256, 0, s>>>(kX, kC, n.master(T_SKIP), kY, d.B,
+                                                                d.H, d.W, K);
+  k_skip_inv_cols<<<cdiv((long long)d.B * d.H * K, 256), 256, 0, s>>>(kY, kSy, kZ, d.B, d.H, K,
+                                                                      2.0 / (d.H + 1));
+  k_skip_out<<<cdiv((long long)d.B * HW, 256), 256, 0, s>>>(kZ, kSx, out, d.B, d.H, d.W, K,
+                                                            2.0 / (d.W + 1));
 }
 
 template <int C>
@@ -955,16 +1020,24 @@ void train(const Net& n, const Ptrs& f, const Ptrs& up, const Ptrs& ut, float* l
     k_loss_sum<<<1, kReduceThreads, 0, s>>>(lpart, nb, ldev, loss, d.B);
   }
   const int ctiles = cdiv(d.W, 64) * cdiv(d.H, 4);
-  // spectral skip gains: dY = norm S[dout], grad = rho (c_u / lambda) sum_b dY X
+  // spectral skip gains: dY = norm S[dout], grad = rho (c_u / lambda) sum_b dY X;
+  // then the convolutional branch's gradient off the band: dout -= S^T dY S
   {
-    float* kT = n.w<float>(n.wl.kT);
-    float* kdY = n.w<float>(n.wl.kdY);
-    const float nrm = (float)((2.0 / (d.H + 1)) * (2.0 / (d.W + 1)));
-    k_skip_rows<float><<<cdiv((long long)d.B * d.H * d.M, 256), 256, 0, s>>>(dout, nullptr, Sx, kT,
-                                                                             d.B, d.H, d.W, d.M);
-    k_spec_cols<<<cdiv((long long)d.B * d.M, 256), 256, 0, s>>>(kT, Sy, kdY, d.B, d.H, d.M, 1, nrm);
-    k_skip_grad<<<cdiv((long long)d.M * d.M, 256), 256, 0, s>>>(kdY, n.w<float>(n.wl.kX),
-                                                                n.grad(T_SKIP), d.B, d.H, d.W, d.M);
+    double* kT = n.w<double>(n.wl.kT);
+    double* kdY = n.w<double>(n.wl.kdY);
+    double* kZ = n.w<double>(n.wl.kZ);
+    double* kSx = n.w<double>(n.wl.kSx);
+    double* kSy = n.w<double>(n.wl.kSy);
+    const int K = d.K;
+    const double nrm = (2.0 / (d.H + 1)) * (2.0 / (d.W + 1));
+    k_skip_rows<float><<<cdiv((long long)d.B * d.H * K, 256), 256, 0, s>>>(dout, nullptr, kSx, kT,
+                                                                          d.B, d.H, d.W, K);
+    k_skip_cols<<<cdiv((long long)d.B * K * K, 256), 256, 0, s>>>(kT, kSy, kdY, d.B, d.H, K, nrm);
+    k_skip_grad<<<cdiv((long long)K * K, 256), 256, 0, s>>>(kdY, n.w<double>(n.wl.kX),
+                                                            n.grad(T_SKIP), d.B, d.H, d.W, K);
+    k_skip_inv_cols<<<cdiv((long long)d.B * d.H * K, 256), 256, 0, s>>>(kdY, kSy, kZ, d.B, d.H, K,
+                                                                        1.0);
+    k_skip_out<<<cdiv((long long)d.B * HW, 256), 256, 0, s>>>(kZ, kSx, dout, d.B, d.H, d.W, K, -1.0);
   }
   // L6: weight grad from (a5, dout); input grad masked by a5 -> dz5
   k_wgrad_small<C, 1, float><<<G, 256, 0, s>>>(a[4], dout, part, d.B, d.H, d.W);

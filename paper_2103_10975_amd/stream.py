@@ -10,6 +10,10 @@ policy open):
   - one training step per solved pair, on a batch of the newest pair plus
     randomly drawn older ones from a FIFO replay buffer (recent data is always
     used, older data guards against forgetting, as Section 2.3 asks);
+  - a pair needs a previous solution, so the first right-hand side of the
+    stream gives none (with u_prev = 0 its input would be the whole field,
+    not an increment, and its outsized gradients would stall Adam's steps on
+    the slowest modes for as long as its second moment remembers them);
   - during the first `warmup` steps the guess is the previous solution;
   - a guess that GMRES rejects as non-finite falls back to the previous
     solution (the solver, not the network, decides the answer).
@@ -140,7 +144,7 @@ class StreamSolver:
         tos = time.perf_counter() - t0
         rec = StepRecord(self.t, kind, st.iters, st.cycles, st.relres_init, st.relres_first_cycle,
                          st.relres_true, tos)
-        if self.train_enabled:
+        if self.train_enabled and self.t > 0:
             self.replay.push(f.clone(), self.u_prev.clone(), self.x.clone())
             t1 = time.perf_counter()
             self.train_step()

@@ -6,10 +6,12 @@ previous solution u_{t-1}, and from the learned guess (network trained one step
 per solved pair on the replay buffer).  Measured over steps [100, 200):
 
 * the previous solution beats the zero guess in iterations, and the learned
-  guess beats the previous solution;
-* the trained network removes most of the slow-mode error of u_{t-1} (its
-  projection on the 16 x 16 slowest sine modes of the Dirichlet Laplacian --
-  the error restarted GMRES converges slowest on): measured 6.7x.
+  guess needs well under the previous solution's count (measured 2041 vs
+  5352; the skip gains are still converging over this window);
+* the trained network removes nearly all of the slow-mode error of u_{t-1}
+  (its projection on the 16 x 16 slowest sine modes of the Dirichlet
+  Laplacian -- the error restarted GMRES converges slowest on): measured
+  832x.
 
 The paper prints no iteration counts for this network or workload, so the
 sizes of these gains are measured and printed, not pinned.
@@ -69,5 +71,5 @@ def test_learned_guess_gain(mlg):
           f"prev {iters['prev']:.0f}, learned {iters['learned']:.0f}; "
           f"slow-mode error of u_(t-1) / of the learned guess: {gain:.2f}")
     assert iters["prev"] < iters["zero"]
-    assert iters["learned"] < iters["prev"]
-    assert gain > 3.0
+    assert iters["learned"] < 0.6 * iters["prev"]
+    assert gain > 100.0
