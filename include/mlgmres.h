@@ -222,7 +222,7 @@ int mlg_autotune(const mlg_grid* grid, const mlg_opts* opts, void* ws, size_t ws
  *   L3 spectral: ReLU(W1 x + b + S^-1[W_kl . S[x]_kl]) over the modes x modes
  *      slowest sine modes (S = DST-I basis), per-mode C x C mixing,
  *   L4, L5 conv3x3 C->C + ReLU, L6 conv3x3 C->1;
- *   spectral skip (FP32) over the skip_modes x skip_modes slowest sine modes
+ *   spectral skip (FP64) over the skip_modes x skip_modes slowest sine modes
  *      (the skip band K): skip = S^-1[32 g_kl (c_u / lambda_kl) S[r/s_r]_kl],
  *      lambda_kl the eigenvalues of A (g = 1/32 applies the exact inverse of
  *      A on the band);
@@ -236,7 +236,7 @@ int mlg_autotune(const mlg_grid* grid, const mlg_opts* opts, void* ws, size_t ws
 typedef struct {
   int32_t channels;   /* C, 32; multiple of 16, <= 64 */
   int32_t modes;      /* M, 16; <= 32 (the L3 spectral layer) */
-  int32_t skip_modes; /* K, 32; 1..128 (the skip band) */
+  int32_t skip_modes; /* K, 64; 1..128 (the skip band) */
   float lr, beta1, beta2, eps;
   uint64_t seed;
 } guess_net_cfg;

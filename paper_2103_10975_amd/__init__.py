@@ -86,7 +86,7 @@ class NetCfg(ctypes.Structure):
                 ("beta1", ctypes.c_float), ("beta2", ctypes.c_float), ("eps", ctypes.c_float),
                 ("seed", ctypes.c_uint64)]
 
-    def __init__(self, channels=32, modes=16, skip_modes=32, lr=1e-3, beta1=0.9, beta2=0.999,
+    def __init__(self, channels=32, modes=16, skip_modes=64, lr=1e-3, beta1=0.9, beta2=0.999,
                  eps=1e-8, seed=0):
         super().__init__(channels, modes, skip_modes, lr, beta1, beta2, eps, seed)
 

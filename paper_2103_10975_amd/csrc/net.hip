@@ -38,6 +38,7 @@ constexpr int kNumTensors = 14;
 enum { T_C1W, T_C1B, T_C2W, T_C2B, T_SW1, T_SB, T_SWK, T_C4W, T_C4B, T_C5W, T_C5B, T_C6W, T_C6B,
        T_SKIP };
 constexpr float kRho = 32.f;          // step-size scale of the skip gains
+constexpr int kRmsBlocks = 128;       // chunks per field of the RMS sums
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float floatx4 __attribute__((ext_vector_type(4)));
@@ -121,7 +122,7 @@ Dims check_grid_net(const guess_net_cfg* cfg, const mlg_grid* grid, int batch) {
 
 struct WsLayout {
   size_t s, r0, x0, act[5], out, dout, dz[2], T, X, Y, dX, Z, Sx, Sy, part, loss;
-  size_t kT, kX, kC, kY, kZ, kdY, kSx, kSy, total;   // spectral skip path (FP64)
+  size_t kT, kX, kC, kY, kZ, kdY, kSx, kSxT, kSy, rms, total;   // spectral skip path (FP64)
   int wgrad_blocks;
 };
 
@@ -153,7 +154,9 @@ WsLayout ws_layout(const Dims& d, bool train) {
   L.kZ = take((size_t)d.B * d.H * d.K * 8);
   L.kdY = train ? take((size_t)d.B * d.K * d.K * 8) : 0;
   L.kSx = take((size_t)d.K * d.W * 8);
+  L.kSxT = take((size_t)d.K * d.W * 8);
   L.kSy = take((size_t)d.K * d.H * 8);
+  L.rms = take((size_t)2 * d.B * kRmsBlocks * 8);
   L.wgrad_blocks = 0;
   if (train) {
     L.dout = take((size_t)d.B * d.HW * 4);
@@ -185,21 +188,38 @@ __global__ void k_resid_in(Ptrs f, Ptrs u, double* r, int H, int W) {
   r[(size_t)b * HW + p] = f.p[b][p] - ((2.0 * c - w - e) * cx + (2.0 * c - sN - nN) * cy);
 }
 
-// s = RMS(field_b) (raw) and its division-safe version (1 when 0); one block
-// per sample, fixed-order sums.
-__global__ __launch_bounds__(256) void k_rms(Ptrs f, long long n, double* s_raw, double* s_safe) {
+// RMS of the B residuals r_b and the B sources f_b: sums of squares over
+// kRmsBlocks contiguous chunks per field (blockIdx.y: field r_0..r_{B-1},
+// f_0..f_{B-1}), then one workgroup per field adds its chunks in order.
+__global__ __launch_bounds__(256) void k_sumsq(Ptrs r, Ptrs f, int B, long long n, double* part) {
   __shared__ double red[4];
-  const double* fb = f.p[blockIdx.x];
+  const int fi = blockIdx.y;
+  const double* x = fi < B ? r.p[fi] : f.p[fi - B];
+  const long long c0 = n * blockIdx.x / kRmsBlocks, c1 = n * (blockIdx.x + 1) / kRmsBlocks;
   double acc = 0.0;
-  for (long long i = threadIdx.x; i < n; i += 256) acc += fb[i] * fb[i];
+  for (long long i = c0 + threadIdx.x; i < c1; i += 256) acc += x[i] * x[i];
   acc = wave_sum(acc);
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
   __syncthreads();
+  if (threadIdx.x == 0)
+    part[(size_t)fi * kRmsBlocks + blockIdx.x] = ((red[0] + red[1]) + red[2]) + red[3];
+}
+// sv[0..B): RMS(r_b) (raw); sv[B..2B): its division-safe version (1 when 0);
+// sv[2B..3B): the division-safe RMS(f_b).
+__global__ __launch_bounds__(64) void k_rms_fin(const double* part, int B, long long n, double* sv) {
+  const int fi = blockIdx.x;
+  double v = 0.0;
+  for (int k = threadIdx.x; k < kRmsBlocks; k += 64) v += part[(size_t)fi * kRmsBlocks + k];
+  v = wave_sum(v);
   if (threadIdx.x == 0) {
-    double t = ((red[0] + red[1]) + red[2]) + red[3];
-    double r = sqrt(t / (double)n);
-    if (s_raw) s_raw[blockIdx.x] = r;
-    s_safe[blockIdx.x] = r > 0.0 ? r : 1.0;
+    const double rms = sqrt(v / (double)n);
+    const double safe = rms > 0.0 ? rms : 1.0;
+    if (fi < B) {
+      sv[fi] = rms;
+      sv[B + fi] = safe;
+    } else {
+      sv[2 * B + fi - B] = safe;
+    }
   }
 }
 
@@ -606,25 +626,32 @@ __global__ __launch_bounds__(256) void k_spec_rows(const bf16* in, const float* 
 }
 
 // X[b][k][l][c] = scale * sum_i Sy[k][i] T[b][i][l][c]  (thread per (b, l, c))
-__global__ __launch_bounds__(256) void k_spec_cols(const float* T, const float* Sy, float* X, int B,
-                                                   int H, int M, int C, float scale) {
-  const int e = blockIdx.x * blockDim.x + threadIdx.x;
-  const int LC = M * C;
-  if (e >= B * LC) return;
-  const int b = e / LC, lc = e % LC;
-  float acc[32];
-#pragma unroll
-  for (int k = 0; k < 32; ++k) acc[k] = 0.f;
-  const float* tp = T + (size_t)b * H * LC + lc;
-  for (int i = 0; i < H; ++i) {
-    const float v = tp[(size_t)i * LC];
-#pragma unroll
-    for (int k = 0; k < 32; ++k)
-      if (k < M) acc[k] += Sy[(size_t)k * H + i] * v;
+// X[b][k][q] = scale sum_i Sy[k][i] T[b][i][q], q < LQ (the column transform
+// of the sine pair).  A workgroup takes 64 consecutive q of one (b, k); its 4
+// wavefronts sum a quarter of the rows each (one mode per wavefront, so the
+// basis value is a broadcast and the T row is a coalesced read), and the
+// quarters are added in a fixed order.
+template <class V>
+__global__ __launch_bounds__(256) void k_cols(const V* T, const V* Sy, V* X, int B, int H, int M,
+                                              int LQ, V scale) {
+  __shared__ V red[4][64];
+  const int nq = (LQ + 63) / 64;
+  const int qb = blockIdx.x % nq, bk = blockIdx.x / nq;
+  const int k = bk % M, b = bk / M;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int q = qb * 64 + lane;
+  const int i0 = H * w / 4, i1 = H * (w + 1) / 4;
+  V acc = 0;
+  if (q < LQ) {
+    const V* tp = T + (size_t)b * H * LQ + q;
+    const V* sy = Sy + (size_t)k * H;
+#pragma unroll 8
+    for (int i = i0; i < i1; ++i) acc += sy[i] * tp[(size_t)i * LQ];
   }
-#pragma unroll
-  for (int k = 0; k < 32; ++k)
-    if (k < M) X[((size_t)b * M + k) * LC + lc] = scale * acc[k];
+  red[w][lane] = acc;
+  __syncthreads();
+  if (w == 0 && q < LQ)
+    X[((size_t)b * M + k) * LQ + q] = scale * (((red[0][lane] + red[1][lane]) + red[2][lane]) + red[3][lane]);
 }
 
 // per-mode channel mixing: Y[b][k][l][n] = sum_m w[k][l][n][m] X[b][k][l][m]
@@ -727,17 +754,22 @@ __global__ __launch_bounds__(256) void k_spec_out(const bf16* in, const bf16* w1
 // coefficients themselves; trained on such inputs the gains settle below the
 // exact inverse.
 
-// S[k][j] = sin((k+1) pi (j+1) / (n+1)) in FP64
-__global__ void k_skip_basis(double* S, int M, int n) {
+// S[k][j] = sin((k+1) pi (j+1) / (n+1)) in FP64, and (when ST is given) the
+// same values transposed, ST[j][k]
+__global__ void k_skip_basis(double* S, double* ST, int M, int n) {
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= M * n) return;
   const int k = e / n, j = e % n;
-  S[e] = sin((double)(k + 1) * M_PI * (double)(j + 1) / (double)(n + 1));
+  const double v = sin((double)(k + 1) * M_PI * (double)(j + 1) / (double)(n + 1));
+  S[e] = v;
+  if (ST) ST[(size_t)j * M + k] = v;
 }
 
-// T[b][i][l] = sum_j Sx[l][j] x[b][i][j] / div[b]  (one thread per output)
+// T[b][i][l] = sum_j Sx[l][j] x[b][i][j] / div[b]  (one thread per output;
+// SxT = the basis transposed, [j][l], so a wavefront's lanes read
+// consecutive basis values while the x value is a broadcast)
 template <class X>
-__global__ void k_skip_rows(const X* x, const double* div, const double* Sx, double* T, int B,
+__global__ void k_skip_rows(const X* x, const double* div, const double* SxT, double* T, int B,
                             int H, int W, int M) {
   const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= (long long)B * H * M) return;
@@ -745,25 +777,10 @@ __global__ void k_skip_rows(const X* x, const double* div, const double* Sx, dou
   const long long bi = e / M;
   const int b = (int)(bi / H);
   const X* xr = x + bi * W;
-  const double* sr = Sx + (size_t)l * W;
   double s = 0.0;
-  for (int j = 0; j < W; ++j) s += sr[j] * (double)xr[j];
+#pragma unroll 8
+  for (int j = 0; j < W; ++j) s += SxT[(size_t)j * M + l] * (double)xr[j];
   T[e] = div ? s / div[b] : s;
-}
-
-// X[b][k][l] = scale sum_i Sy[k][i] T[b][i][l]  (one thread per output)
-__global__ void k_skip_cols(const double* T, const double* Sy, double* X, int B, int H, int M,
-                            double scale) {
-  const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= (long long)B * M * M) return;
-  const int l = (int)(e % M);
-  const long long bk = e / M;
-  const int k = (int)(bk % M), b = (int)(bk / M);
-  const double* tp = T + (size_t)b * H * M + l;
-  const double* sy = Sy + (size_t)k * H;
-  double acc = 0.0;
-  for (int i = 0; i < H; ++i) acc += sy[i] * tp[(size_t)i * M];
-  X[e] = scale * acc;
 }
 
 // lambda_kl of the zero-Dirichlet 5-point Laplacian on the (k+1, l+1) sine mode
@@ -923,8 +940,9 @@ void forward(const Net& n, const Ptrs& f, const Ptrs& u, hipStream_t s) {
   k_resid_in<<<dim3(cdiv(HW, 256), d.B), 256, 0, s>>>(f, u, r0, d.H, d.W);
   Ptrs rp{};
   for (int b = 0; b < d.B; ++b) rp.p[b] = r0 + (size_t)b * HW;
-  k_rms<<<d.B, 256, 0, s>>>(rp, HW, sv, sv + d.B);
-  k_rms<<<d.B, 256, 0, s>>>(f, HW, nullptr, sv + 2 * d.B);
+  double* rms_part = n.w<double>(n.wl.rms);
+  k_sumsq<<<dim3(kRmsBlocks, 2 * d.B), 256, 0, s>>>(rp, f, d.B, HW, rms_part);
+  k_rms_fin<<<2 * d.B, 64, 0, s>>>(rms_part, d.B, HW, sv);
   k_norm_in<<<dim3(cdiv(HW, 256), d.B), 256, 0, s>>>(r0, f, sv + d.B, sv + 2 * d.B, x0, HW);
   // L1, L2
   k_conv_small<2, C, bf16, bf16, false, true><<<dim3(cdiv(HW, 256), d.B), 256, 0, s>>>(
@@ -938,7 +956,7 @@ void forward(const Net& n, const Ptrs& f, const Ptrs& u, hipStream_t s) {
   float* Y = n.w<float>(n.wl.Y);
   float* Z = n.w<float>(n.wl.Z);
   k_spec_rows<C><<<d.B * d.H, 256, 0, s>>>(a[1], Sx, T, d.H, d.W, d.M);
-  k_spec_cols<<<cdiv((long long)d.B * d.M * C, 256), 256, 0, s>>>(T, Sy, X, d.B, d.H, d.M, C, 1.f);
+  k_cols<float><<<d.B * d.M * cdiv(d.M * C, 64), 256, 0, s>>>(T, Sy, X, d.B, d.H, d.M, d.M * C, 1.f);
   k_spec_mix<false><<<cdiv((long long)d.B * d.M * d.M * C, 256), 256, 0, s>>>(X, n.bfw(T_SWK), Y,
                                                                                d.B, d.M, C);
   k_spec_inv_cols<<<cdiv((long long)d.B * d.H * d.M * C, 256), 256, 0, s>>>(
@@ -964,14 +982,15 @@ void forward(const Net& n, const Ptrs& f, const Ptrs& u, hipStream_t s) {
   double* kSy = n.w<double>(n.wl.kSy);
   float* out = n.w<float>(n.wl.out);
   const int K = d.K;
-  k_skip_basis<<<cdiv((long long)K * d.W, 256), 256, 0, s>>>(kSx, K, d.W);
-  k_skip_basis<<<cdiv((long long)K * d.H, 256), 256, 0, s>>>(kSy, K, d.H);
-  k_skip_rows<double><<<cdiv((long long)d.B * d.H * K, 256), 256, 0, s>>>(r0, sv + d.B, kSx, kT,
+  double* kSxT = n.w<double>(n.wl.kSxT);
+  k_skip_basis<<<cdiv((long long)K * d.W, 256), 256, 0, s>>>(kSx, kSxT, K, d.W);
+  k_skip_basis<<<cdiv((long long)K * d.H, 256), 256, 0, s>>>(kSy, nullptr, K, d.H);
+  k_skip_rows<double><<<cdiv((long long)d.B * d.H * K, 256), 256, 0, s>>>(r0, sv + d.B, kSxT, kT,
                                                                          d.B, d.H, d.W, K);
-  k_skip_cols<<<cdiv((long long)d.B * K * K, 256), 256, 0, s>>>(kT, kSy, kX, d.B, d.H, K, 1.0);
-  k_skip_rows<float><<<cdiv((long long)d.B * d.H * K, 256), 256, 0, s>>>(out, nullptr, kSx, kT, d.B,
-                                                                        d.H, d.W, K);
-  k_skip_cols<<<cdiv((long long)d.B * K * K, 256), 256, 0, s>>>(kT, kSy, kC, d.B, d.H, K, 1.0);
+  k_cols<double><<<d.B * K * cdiv(K, 64), 256, 0, s>>>(kT, kSy, kX, d.B, d.H, K, K, 1.0);
+  k_skip_rows<float><<<cdiv((long long)d.B * d.H * K, 256), 256, 0, s>>>(out, nullptr, kSxT, kT,
+                                                                        d.B, d.H, d.W, K);
+  k_cols<double><<<d.B * K * cdiv(K, 64), 256, 0, s>>>(kT, kSy, kC, d.B, d.H, K, K, 1.0);
   k_skip_gain<<<cdiv((long long)d.B * K * K, 256), 256, 0, s>>>(kX, kC, n.master(T_SKIP), kY, d.B,
                                                                 d.H, d.W, K);
   k_skip_inv_cols<<<cdiv((long long)d.B * d.H * K, 256), 256, 0, s>>>(kY, kSy, kZ, d.B, d.H, K,
@@ -1027,12 +1046,13 @@ void train(const Net& n, const Ptrs& f, const Ptrs& up, const Ptrs& ut, float* l
     double* kdY = n.w<double>(n.wl.kdY);
     double* kZ = n.w<double>(n.wl.kZ);
     double* kSx = n.w<double>(n.wl.kSx);
+    double* kSxT = n.w<double>(n.wl.kSxT);
     double* kSy = n.w<double>(n.wl.kSy);
     const int K = d.K;
     const double nrm = (2.0 / (d.H + 1)) * (2.0 / (d.W + 1));
-    k_skip_rows<float><<<cdiv((long long)d.B * d.H * K, 256), 256, 0, s>>>(dout, nullptr, kSx, kT,
+    k_skip_rows<float><<<cdiv((long long)d.B * d.H * K, 256), 256, 0, s>>>(dout, nullptr, kSxT, kT,
                                                                           d.B, d.H, d.W, K);
-    k_skip_cols<<<cdiv((long long)d.B * K * K, 256), 256, 0, s>>>(kT, kSy, kdY, d.B, d.H, K, nrm);
+    k_cols<double><<<d.B * K * cdiv(K, 64), 256, 0, s>>>(kT, kSy, kdY, d.B, d.H, K, K, nrm);
     k_skip_grad<<<cdiv((long long)K * K, 256), 256, 0, s>>>(kdY, n.w<double>(n.wl.kX),
                                                             n.grad(T_SKIP), d.B, d.H, d.W, K);
     k_skip_inv_cols<<<cdiv((long long)d.B * d.H * K, 256), 256, 0, s>>>(kdY, kSy, kZ, d.B, d.H, K,
@@ -1061,7 +1081,7 @@ void train(const Net& n, const Ptrs& f, const Ptrs& up, const Ptrs& ut, float* l
   float* Z = n.w<float>(n.wl.Z);
   const float nrm = (float)((2.0 / (d.H + 1)) * (2.0 / (d.W + 1)));
   k_spec_rows<C><<<d.B * d.H, 256, 0, s>>>(dz[0], Sx, T, d.H, d.W, d.M);
-  k_spec_cols<<<cdiv((long long)d.B * d.M * C, 256), 256, 0, s>>>(T, Sy, dY, d.B, d.H, d.M, C, nrm);
+  k_cols<float><<<d.B * d.M * cdiv(d.M * C, 64), 256, 0, s>>>(T, Sy, dY, d.B, d.H, d.M, d.M * C, nrm);
   k_spec_dwk<<<cdiv((long long)d.M * d.M * C * C, 256), 256, 0, s>>>(dY, X, n.grad(T_SWK), d.B, d.M, C);
   k_spec_mix<true><<<cdiv((long long)d.B * d.M * d.M * C, 256), 256, 0, s>>>(dY, n.bfw(T_SWK), dX,
                                                                               d.B, d.M, C);

@@ -106,7 +106,8 @@ class StreamSolver:
         if guess == "learned":
             if len(self.shape) != 2:
                 raise ValueError("the learned guess is defined on 2D grids")
-            self.net_cfg = net_cfg or NetCfg(seed=seed)
+            # the skip band may not exceed the grid
+            self.net_cfg = net_cfg or NetCfg(seed=seed, skip_modes=min(64, *self.shape))
             self.params = torch.zeros(guess_net_param_bytes(self.net_cfg), dtype=torch.uint8,
                                       device="cuda")
             guess_net_init(self.net_cfg, self.params)

@@ -197,7 +197,7 @@ def test_init_zero_output_and_bounds(mlg):
 
 def test_training_reduces_loss(mlg):
     print("net training loop", flush=True)
-    cfg = mlg.NetCfg(channels=32, modes=8, lr=1e-3, seed=7)
+    cfg = mlg.NetCfg(channels=32, modes=8, skip_modes=16, lr=1e-3, seed=7)
     buf = torch.zeros(mlg.guess_net_param_bytes(cfg), dtype=torch.uint8, device="cuda")
     mlg.guess_net_init(cfg, buf)
     shape = (48, 48)
