@@ -233,7 +233,12 @@ def main():
     tos_learned = statistics.fmean(r.tos for r in timed)
     warm = learned.records[:args.warmup]
     gains = mlg.net_unpack(learned.net_cfg, mlg.net_views(learned.net_cfg, learned.params)["master"])
-    gain_err = float((32.0 * gains["skip.g"] - 1.0).abs().max())
+    # error of the trained skip gains against the exact inverse (rho g = 1):
+    # over the 16 x 16 slowest modes (where the sources put their content) and
+    # the median over the whole band (its fastest modes carry next to nothing
+    # and barely move from their initial zero)
+    gerr = (32.0 * gains["skip.g"] - 1.0).abs()
+    gain_err = {"max_16x16": float(gerr[:16, :16].max()), "median_band": float(gerr.median())}
 
     result = {
         "metric": METRIC, "value": tos_learned, "unit": "s/RHS", "n_gpus": 1,
@@ -252,7 +257,7 @@ def main():
                     "relres_init_mean": statistics.fmean(r.relres_init for r in timed),
                     "E_k_mean": statistics.fmean(r.relres_first_cycle for r in timed),
                     "guess_kinds": sorted(set(r.guess for r in timed)),
-                    "skip_gain_max_error": gain_err},
+                    "skip_gain_error": gain_err},
         # the in-situ learning phase before the timed window: every step
         # solved (guess, GMRES) and trained once
         "stream": {"steps": args.warmup, "seconds": stream_s,
