@@ -280,6 +280,64 @@ __global__ __launch_bounds__(kReduceThreads) void k_loss_sum(const double* part,
 // out[p][co] = epilogue(sum_{tap,ci} w[tap][co][ci] in[p + off(tap)][ci]) with the weight
 // tensor staged as w[tap][co][ci]; DGRAD stages the flipped transpose of the forward
 // weights (input gradient of the forward layer) and multiplies by (mask > 0).
+// A pixel's channel vector in 16-byte pieces when the channel count allows
+// (8 BF16 or 4 FP32 per piece), else element by element.
+template <int N>
+__device__ __forceinline__ void load_ch(const bf16* p, float (&v)[N]) {
+  if constexpr (N % 8 == 0) {
+#pragma unroll
+    for (int q = 0; q < N / 8; ++q) {
+      const uint4 u = reinterpret_cast<const uint4*>(p)[q];
+      const uint32_t w[4] = {u.x, u.y, u.z, u.w};
+#pragma unroll
+      for (int h = 0; h < 4; ++h) {
+        v[8 * q + 2 * h] = __uint_as_float(w[h] << 16);
+        v[8 * q + 2 * h + 1] = __uint_as_float(w[h] & 0xffff0000u);
+      }
+    }
+  } else {
+#pragma unroll
+    for (int i = 0; i < N; ++i) v[i] = bf2f(p[i]);
+  }
+}
+template <int N>
+__device__ __forceinline__ void load_ch(const float* p, float (&v)[N]) {
+  if constexpr (N % 4 == 0) {
+#pragma unroll
+    for (int q = 0; q < N / 4; ++q) {
+      const float4 u = reinterpret_cast<const float4*>(p)[q];
+      v[4 * q] = u.x;
+      v[4 * q + 1] = u.y;
+      v[4 * q + 2] = u.z;
+      v[4 * q + 3] = u.w;
+    }
+  } else {
+#pragma unroll
+    for (int i = 0; i < N; ++i) v[i] = p[i];
+  }
+}
+template <int N>
+__device__ __forceinline__ void store_ch(bf16* p, const float (&v)[N]) {
+  if constexpr (N % 8 == 0) {
+#pragma unroll
+    for (int q = 0; q < N / 8; ++q) {
+      uint32_t w[4];
+#pragma unroll
+      for (int h = 0; h < 4; ++h)
+        w[h] = (uint32_t)f2bf(v[8 * q + 2 * h]) | ((uint32_t)f2bf(v[8 * q + 2 * h + 1]) << 16);
+      reinterpret_cast<uint4*>(p)[q] = make_uint4(w[0], w[1], w[2], w[3]);
+    }
+  } else {
+#pragma unroll
+    for (int i = 0; i < N; ++i) p[i] = f2bf(v[i]);
+  }
+}
+template <int N>
+__device__ __forceinline__ void store_ch(float* p, const float (&v)[N]) {
+#pragma unroll
+  for (int i = 0; i < N; ++i) p[i] = v[i];
+}
+
 template <int CIN, int COUT, class TIN, class TOUT, bool DGRAD, bool RELU>
 __global__ __launch_bounds__(256) void k_conv_small(const TIN* in, const bf16* wt, const bf16* bias,
                                                     const bf16* mask, TOUT* out, int H, int W) {
@@ -306,49 +364,63 @@ __global__ __launch_bounds__(256) void k_conv_small(const TIN* in, const bf16* w
   for (int t = 0; t < 9; ++t) {
     const int yy = y + t / 3 - 1, xx = x + t % 3 - 1;
     if (yy < 0 || yy >= H || xx < 0 || xx >= W) continue;
-    const TIN* ip = inb + ((long long)yy * W + xx) * CIN;
+    float v[CIN];
+    load_ch<CIN>(inb + ((long long)yy * W + xx) * CIN, v);
 #pragma unroll
     for (int ci = 0; ci < CIN; ++ci) {
-      const float v = to_f(ip[ci]);
 #pragma unroll
-      for (int co = 0; co < COUT; ++co) acc[co] += wl[(t * COUT + co) * CIN + ci] * v;
+      for (int co = 0; co < COUT; ++co) acc[co] += wl[(t * COUT + co) * CIN + ci] * v[ci];
     }
   }
-  TOUT* op = out + ((size_t)b * HW + p) * COUT;
+  if (RELU) {
 #pragma unroll
-  for (int co = 0; co < COUT; ++co) {
-    float v = acc[co];
-    if (RELU) v = fmaxf(v, 0.f);
-    if (DGRAD) v = bf2f(mask[((size_t)b * HW + p) * COUT + co]) > 0.f ? v : 0.f;
-    if constexpr (sizeof(TOUT) == 2)
-      op[co] = f2bf(v);
-    else
-      op[co] = v;
+    for (int co = 0; co < COUT; ++co) acc[co] = fmaxf(acc[co], 0.f);
   }
+  if constexpr (DGRAD) {
+    float mk[COUT];
+    load_ch<COUT>(mask + ((size_t)b * HW + p) * COUT, mk);
+#pragma unroll
+    for (int co = 0; co < COUT; ++co) acc[co] = mk[co] > 0.f ? acc[co] : 0.f;
+  }
+  store_ch<COUT>(out + ((size_t)b * HW + p) * COUT, acc);
 }
 
-// Partial weight/bias gradients of a thin convolution: per block,
-// part[blk][(t*COUT + d)*CIN + c] = sum over its pixels of dz[p][d] in[p+off(t)][c],
-// part[blk][9*COUT*CIN + d] = sum dz[p][d].
+// Partial weight/bias gradients of a thin convolution (CIN -> COUT with one
+// side small): per workgroup,
+//   part[blk][(t*COUT + d)*CIN + c] = sum over its pixels of dz[p][d] in[p+off(t)][c],
+//   part[blk][9*COUT*CIN + d] = sum dz[p][d].
+// A workgroup walks tiles of 4 rows x 64 columns (grid-stride over all
+// samples' tiles); each tile's input (one-pixel halo, zero outside the image)
+// and output gradient are staged in LDS, and every thread sums its weight
+// entries over the tile from LDS.
 template <int CIN, int COUT, class TDZ>
-__global__ __launch_bounds__(256) void k_wgrad_small(const bf16* in, const TDZ* dz, float* part,
-                                                     int B, int H, int W) {
+__global__ __launch_bounds__(256) void k_wgrad_thin(const bf16* in, const TDZ* dz, float* part,
+                                                    int B, int H, int W) {
+  constexpr int TW = 64, TH = 4, LW = TW + 2, LH = TH + 2;
   constexpr int NOUT = 9 * COUT * CIN + COUT;
   constexpr int PER = (NOUT + 255) / 256;
+  __shared__ float xl[LH * LW * CIN];
+  __shared__ float gl[TH * TW * COUT];
+  const int tx = (W + TW - 1) / TW, ty = (H + TH - 1) / TH;
+  const int ntiles = B * tx * ty;
   const long long HW = (long long)H * W;
-  const long long total = (long long)B * HW;
   float acc[PER];
 #pragma unroll
   for (int i = 0; i < PER; ++i) acc[i] = 0.f;
-  for (long long q = (long long)blockIdx.x * 256; q < total; q += (long long)gridDim.x * 256) {
-    __shared__ float dzl[256 * COUT];
-    __shared__ int pix[256];
+  for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    const int b = tile / (tx * ty), r = tile % (tx * ty);
+    const int y0 = (r / tx) * TH, x0 = (r % tx) * TW;
     __syncthreads();
-    {
-      long long qq = q + threadIdx.x;
-      pix[threadIdx.x] = qq < total ? (int)(qq % HW) : -1;
-      for (int d = 0; d < COUT; ++d)
-        dzl[threadIdx.x * COUT + d] = qq < total ? to_f(dz[qq * COUT + d]) : 0.f;
+    for (int e = threadIdx.x; e < LH * LW * CIN; e += 256) {
+      const int c = e % CIN, q = e / CIN, lx = q % LW, ly = q / LW;
+      const int y = y0 + ly - 1, x = x0 + lx - 1;
+      xl[e] = (y >= 0 && y < H && x >= 0 && x < W)
+                  ? bf2f(in[((size_t)b * HW + (long long)y * W + x) * CIN + c]) : 0.f;
+    }
+    for (int e = threadIdx.x; e < TH * TW * COUT; e += 256) {
+      const int d = e % COUT, q = e / COUT, px = q % TW, py = q / TW;
+      const int y = y0 + py, x = x0 + px;
+      gl[e] = (y < H && x < W) ? to_f(dz[((size_t)b * HW + (long long)y * W + x) * COUT + d]) : 0.f;
     }
     __syncthreads();
 #pragma unroll
@@ -357,20 +429,15 @@ __global__ __launch_bounds__(256) void k_wgrad_small(const bf16* in, const TDZ* 
       if (e >= NOUT) continue;
       float s = 0.f;
       if (e < 9 * COUT * CIN) {
-        const int t = e / (COUT * CIN), r = e % (COUT * CIN), d = r / CIN, c = r % CIN;
-        const int dy = t / 3 - 1, dx = t % 3 - 1;
-        for (int k = 0; k < 256; ++k) {
-          const int p = pix[k];
-          if (p < 0) break;
-          const long long qq = q + k;
-          const int bb = (int)(qq / HW);
-          const int y = p / W + dy, x = p % W + dx;
-          if (y < 0 || y >= H || x < 0 || x >= W) continue;
-          s += dzl[k * COUT + d] * bf2f(in[((size_t)bb * HW + (long long)y * W + x) * CIN + c]);
-        }
+        const int t = e / (COUT * CIN), rr = e % (COUT * CIN), d = rr / CIN, c = rr % CIN;
+        const int dy = t / 3, dx = t % 3;              // halo offsets of the tap
+        for (int py = 0; py < TH; ++py)
+#pragma unroll 8
+          for (int px = 0; px < TW; ++px)
+            s += gl[(py * TW + px) * COUT + d] * xl[((py + dy) * LW + px + dx) * CIN + c];
       } else {
         const int d = e - 9 * COUT * CIN;
-        for (int k = 0; k < 256; ++k) s += dzl[k * COUT + d];
+        for (int q = 0; q < TH * TW; ++q) s += gl[q * COUT + d];
       }
       acc[i] += s;
     }
@@ -391,8 +458,15 @@ __global__ void k_wgrad_reduce(const float* part, int nblk, int ntap, int cout, 
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= nw + cout) return;
   const int stride = nw + cout;
-  float s = 0.f;
-  for (int k = 0; k < nblk; ++k) s += part[(size_t)k * stride + e];
+  // eight running sums (independent loads in flight), added in a fixed order
+  float a[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+  int k = 0;
+  for (; k + 8 <= nblk; k += 8) {
+#pragma unroll
+    for (int q = 0; q < 8; ++q) a[q] += part[(size_t)(k + q) * stride + e];
+  }
+  for (; k < nblk; ++k) a[0] += part[(size_t)k * stride + e];
+  const float s = ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
   if (e < nw) {
     const int t = e / (cout * cin), r = e % (cout * cin), d = r / cin, c = r % cin;
     gw[(d * cin + c) * ntap + t] = s;
@@ -420,11 +494,13 @@ __global__ __launch_bounds__(256) void k_conv_mfma(const bf16* in, const bf16* w
   const int b = blockIdx.y;
   const long long HW = (long long)H * W;
   const bf16* inb = in + (size_t)b * HW * C;
-  // weights -> wl[t][n][k]
+  // weights -> wl[t][n][k], read in the tensor's own order (coalesced) and
+  // scattered into LDS: forward wt[n][k][t], input gradient wt[k][n][8 - t]
   for (int e = threadIdx.x; e < 9 * C * C; e += 256) {
-    const int t = e / (C * C), r = e % (C * C), n = r / C, k = r % C;
-    const bf16 v = DGRAD ? wt[(k * C + n) * 9 + (8 - t)] : wt[(n * C + k) * 9 + t];
-    wl[(t * C + n) * CP + k] = v;
+    const int i0 = e / (C * 9), i1 = (e / 9) % C, tt = e % 9;
+    const bf16 v = wt[e];
+    if (DGRAD) wl[((8 - tt) * C + i1) * CP + i0] = v;
+    else wl[(tt * C + i0) * CP + i1] = v;
   }
   for (int e = threadIdx.x; e < C; e += 256) bl[e] = (!DGRAD) ? bf2f(bias[e]) : 0.f;
   // input tile with a one-pixel halo, 16-byte chunks
@@ -1060,7 +1136,7 @@ void train(const Net& n, const Ptrs& f, const Ptrs& up, const Ptrs& ut, float* l
     k_skip_out<<<cdiv((long long)d.B * HW, 256), 256, 0, s>>>(kZ, kSx, dout, d.B, d.H, d.W, K, -1.0);
   }
   // L6: weight grad from (a5, dout); input grad masked by a5 -> dz5
-  k_wgrad_small<C, 1, float><<<G, 256, 0, s>>>(a[4], dout, part, d.B, d.H, d.W);
+  k_wgrad_thin<C, 1, float><<<G, 256, 0, s>>>(a[4], dout, part, d.B, d.H, d.W);
   k_wgrad_reduce<<<cdiv(9 * C + 1, 256), 256, 0, s>>>(part, G, 9, 1, C, n.grad(T_C6W), n.grad(T_C6B));
   k_conv_small<1, C, float, bf16, true, false><<<dim3(cdiv(HW, 256), d.B), 256, 0, s>>>(
       dout, n.bfw(T_C6W), nullptr, a[4], dz[0], d.H, d.W);
@@ -1094,7 +1170,7 @@ void train(const Net& n, const Ptrs& f, const Ptrs& up, const Ptrs& ut, float* l
   k_conv_mfma<C, true><<<dim3(ctiles, d.B), 256, 0, s>>>(dz[1], n.bfw(T_C2W), nullptr, a[0], dz[0],
                                                          d.H, d.W);
   // L1: dz1 = dz[0]
-  k_wgrad_small<2, C, bf16><<<G, 256, 0, s>>>(x0, dz[0], part, d.B, d.H, d.W);
+  k_wgrad_thin<2, C, bf16><<<G, 256, 0, s>>>(x0, dz[0], part, d.B, d.H, d.W);
   k_wgrad_reduce<<<cdiv(9 * C * 2 + C, 256), 256, 0, s>>>(part, G, 9, C, 2, n.grad(T_C1W),
                                                           n.grad(T_C1B));
   // Adam
