@@ -69,8 +69,7 @@ typedef struct {
  *                 restarting every restart_m (trajectory comparisons).
  *   tile          0 = autotuned/default tile shape; otherwise an index into
  *                 the tile table (mlg_tile_count / mlg_tile_shape).
- *   poll_cycles   graph chunks of a restart cycle (about m/5 steps each)
- *                 enqueued between host polls of the
+ *   poll_cycles   restart cycles enqueued between host polls of the
  *                 convergence flag (0 = 1).
  *   schedule      how an Arnoldi step sweeps the basis (same arithmetic):
  *                 0 = as tuned by mlg_autotune for this grid (separate sweeps

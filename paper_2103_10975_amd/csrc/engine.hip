@@ -324,11 +324,7 @@ static DevPlan dev_plan(const Plan& P, void* ws) {
   return D;
 }
 
-// Steps [j0, j1) of a restart cycle, preceded by the cycle's head (initial
-// guess, residual, u_0, dots(0)) when `head` and followed by its tail (coef(m),
-// update, true residual) when `tail`.
-static void enqueue_cycle_part(hipStream_t s, const Plan& P, const DevPlan& D, int prec, int m,
-                               int j0, int j1, bool head, bool tail) {
+static void enqueue_cycle(hipStream_t s, const Plan& P, const DevPlan& D, int prec, int m) {
   std::vector<GroupFn> fns;
   for (auto& G : P.groups) fns.push_back(group_fn(G.dim, G.tile, prec));
   const size_t ng = P.groups.size();
@@ -339,14 +335,12 @@ static void enqueue_cycle_part(hipStream_t s, const Plan& P, const DevPlan& D, i
   const int ns = P.nsys;
   int maxblk = 1;
   for (auto& G : P.groups) maxblk = std::max(maxblk, G.maxblk);
-  if (head) {
-    each(G_BEGIN, 0);
-    each(G_RESID0, 0);
-    k_rsum<true><<<ns, kReduceThreads, 0, s>>>(D.desc);
-    each(G_START, 0);
-    each(G_DOTS, 0);
-  }
-  for (int j = j0; j < j1; ++j) {
+  each(G_BEGIN, 0);
+  each(G_RESID0, 0);
+  k_rsum<true><<<ns, kReduceThreads, 0, s>>>(D.desc);
+  each(G_START, 0);
+  each(G_DOTS, 0);
+  for (int j = 0; j < m; ++j) {
     // the grid-wide sums of step j: coef(j), or sums(j) for groups whose step
     // runs in the split form (one launch over all systems when every group
     // takes the same form)
@@ -375,23 +369,10 @@ static void enqueue_cycle_part(hipStream_t s, const Plan& P, const DevPlan& D, i
       }
     }
   }
-  if (tail) {
-    launch_coef(s, ns, nullptr, maxblk, D.desc, m);
-    each(G_UPDATE, m);
-    each(G_RESID, 0);
-    k_rsum<false><<<ns, kReduceThreads, 0, s>>>(D.desc);
-  }
-}
-
-// A restart cycle is replayed as kCycleChunks graphs of about m / kCycleChunks
-// steps each, so that the host can stop enqueueing as soon as a chunk reports
-// every system done (kernels of a finished system still launch, as no-ops).
-constexpr int kCycleChunks = 5;
-static int chunk_count(int m) { return std::min(m, kCycleChunks); }
-static void chunk_steps(int m, int c, int& j0, int& j1) {
-  const int nc = chunk_count(m);
-  j0 = m * c / nc;
-  j1 = m * (c + 1) / nc;
+  launch_coef(s, ns, nullptr, maxblk, D.desc, m);
+  each(G_UPDATE, m);
+  each(G_RESID, 0);
+  k_rsum<false><<<ns, kReduceThreads, 0, s>>>(D.desc);
 }
 
 // Per-call set-up of every control block (pointers, counts, options), and of
@@ -426,7 +407,7 @@ __global__ void k_setup(const SysInit* init, const SysDesc* sd, unsigned int* hd
 // ------------------------------------------------------------------ caches
 struct Runtime {
   std::mutex mu;
-  std::map<std::string, std::pair<std::vector<hipGraphExec_t>, unsigned long long>> graphs;
+  std::map<std::string, std::pair<hipGraphExec_t, unsigned long long>> graphs;
   unsigned long long tick = 0;
   std::map<int, hipStream_t> capture_streams;
   std::vector<std::pair<void*, size_t>> pinned_free;
@@ -462,11 +443,9 @@ static std::string plan_key(int dev, const void* ws, const Plan& P, int prec, in
   return k;
 }
 
-// Captured graphs of one restart cycle (its chunks, in order) for this
-// workspace and plan.
-static const std::vector<hipGraphExec_t>& cycle_graphs(const std::string& key, int dev,
-                                                       const Plan& P, const DevPlan& D, int prec,
-                                                       int m) {
+// Captured graph of one restart cycle for this workspace and plan.
+static hipGraphExec_t cycle_graph(const std::string& key, int dev, const Plan& P, const DevPlan& D,
+                                  int prec, int m) {
   auto& R = rt();
   std::lock_guard<std::mutex> lk(R.mu);
   auto it = R.graphs.find(key);
@@ -478,32 +457,21 @@ static const std::vector<hipGraphExec_t>& cycle_graphs(const std::string& key, i
     auto victim = R.graphs.begin();
     for (auto i = R.graphs.begin(); i != R.graphs.end(); ++i)
       if (i->second.second < victim->second.second) victim = i;
-    for (hipGraphExec_t g : victim->second.first) hipGraphExecDestroy(g);
+    hipGraphExecDestroy(victim->second.first);
     R.graphs.erase(victim);
   }
   hipStream_t cs = capture_stream(dev);
-  std::vector<hipGraphExec_t> execs;
-  const int nc = chunk_count(m);
-  for (int c = 0; c < nc; ++c) {
-    int j0, j1;
-    chunk_steps(m, c, j0, j1);
-    hipGraph_t graph;
-    MLG_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeRelaxed));
-    enqueue_cycle_part(cs, P, D, prec, m, j0, j1, c == 0, c == nc - 1);
-    hipError_t ce = hipStreamEndCapture(cs, &graph);
-    MLG_HIP(ce);
-    hipGraphExec_t exec;
-    hipError_t e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
-    hipGraphDestroy(graph);
-    if (e != hipSuccess) {
-      for (hipGraphExec_t g : execs) hipGraphExecDestroy(g);
-      MLG_HIP(e);
-    }
-    execs.push_back(exec);
-  }
-  auto& slot = R.graphs[key];
-  slot = {std::move(execs), ++R.tick};
-  return slot.first;
+  hipGraph_t graph;
+  MLG_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeRelaxed));
+  enqueue_cycle(cs, P, D, prec, m);
+  hipError_t ce = hipStreamEndCapture(cs, &graph);
+  MLG_HIP(ce);
+  hipGraphExec_t exec;
+  hipError_t e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+  hipGraphDestroy(graph);
+  MLG_HIP(e);
+  R.graphs[key] = {exec, ++R.tick};
+  return exec;
 }
 
 // Pinned host staging buffer of at least `bytes` bytes, returned on scope exit.
@@ -534,8 +502,7 @@ struct Pinned {
 void runtime_shutdown() {
   auto& R = rt();
   std::lock_guard<std::mutex> lk(R.mu);
-  for (auto& kv : R.graphs)
-    for (hipGraphExec_t g : kv.second.first) hipGraphExecDestroy(g);
+  for (auto& kv : R.graphs) hipGraphExecDestroy(kv.second.first);
   R.graphs.clear();
   for (auto& kv : R.capture_streams) hipStreamDestroy(kv.second);
   R.capture_streams.clear();
@@ -622,10 +589,8 @@ int batched_solve(int nsys, const mlg_system* sys, const mlg_opts* opts, void* w
 
   Pinned stage(stage_bytes(P));
   upload_plan(P, D, nsys, sys, *opts, stream, stage);
-  // copy: the cached vector may be evicted by another thread's solve
-  const std::vector<hipGraphExec_t> chunks =
-      cycle_graphs(plan_key(dev, ws, P, opts->precision, m), dev, P, D, opts->precision, m);
-  const int nc = (int)chunks.size();
+  hipGraphExec_t exec = cycle_graph(plan_key(dev, ws, P, opts->precision, m), dev, P, D,
+                                    opts->precision, m);
   Pinned pin(std::max<size_t>(2 * 256, (size_t)P.total_rhs * sizeof(Summary)));
   volatile unsigned int* host = (volatile unsigned int*)pin.p;   // [slot * 64]: done count
   hipEvent_t ev[2];
@@ -636,39 +601,31 @@ int batched_solve(int nsys, const mlg_system* sys, const mlg_opts* opts, void* w
     ~EvGuard() { hipEventDestroy(e[0]); hipEventDestroy(e[1]); }
   } evg{ev};
 
-  // Chunks are enqueued in cycle order, `poll` at a time; the host then
-  // waits for the previous group (one group stays in flight) and stops as
-  // soon as every system is done.  Every restart cycle completes at least
-  // one Arnoldi step or one right-hand side of some unfinished system, so
-  // this many chunks always suffice; the cap only guards the host against a
-  // solver that stopped making progress (checked once per cycle, since a
-  // chunk after a cycle's early end is legitimately idle).
   const int poll = opts->poll_cycles > 0 ? opts->poll_cycles : 1;
+  // Every cycle completes at least one Arnoldi step or one right-hand side of
+  // some unfinished system, so this many cycles always suffice; the cap only
+  // guards the host against a solver that stopped making progress.
   long long rhs_total = P.total_rhs;
-  const long long max_chunks = ((limit + 2) * rhs_total + 8) * nc;
+  const long long max_groups = (limit + 2) * rhs_total / poll + 8;
   int slot = 0, pending = -1;
-  long long pending_end = -1;                   // last chunk index of the pending group
   bool done = false;
   unsigned int last_progress = 0;
-  long long next = 0;
-  while (next < max_chunks && !done) {
-    for (int q = 0; q < poll; ++q, ++next) MLG_HIP(hipGraphLaunch(chunks[next % nc], stream));
+  for (long long grp = 0; grp < max_groups && !done; ++grp) {
+    for (int c = 0; c < poll; ++c) MLG_HIP(hipGraphLaunch(exec, stream));
     MLG_HIP(hipMemcpyAsync((void*)(host + 64 * slot), D.hdr, 8, hipMemcpyDeviceToHost, stream));
     MLG_HIP(hipEventRecord(ev[slot], stream));
     if (pending >= 0) {
       MLG_HIP(hipEventSynchronize(ev[pending]));
       if (host[64 * pending] >= (unsigned)nsys) {
         done = true;
-      } else if ((pending_end + 1) / nc != (pending_end + 1 - poll) / nc) {
-        // the pending group completed a cycle: it must have made progress
+      } else {
         const unsigned int prog = host[64 * pending + 1];
-        if (pending_end >= 2 * nc && prog == last_progress)
+        if (grp > 1 && prog == last_progress)
           throw HipError{hipErrorUnknown, "solver made no progress in a restart cycle"};
         last_progress = prog;
       }
     }
     pending = slot;
-    pending_end = next - 1;
     slot ^= 1;
   }
   MLG_HIP(hipMemcpyAsync((void*)host, D.hdr, 8, hipMemcpyDeviceToHost, stream));
