@@ -58,6 +58,72 @@ class ReplayBuffer:
         return [self.items[i] for i in idx]
 
 
+def moving_average(values, p: int) -> float:
+    """M_p of Section 2.2: the unweighted mean of the last p values (the
+    current one included; fewer than p values: all of them).  The printed
+    formula sums p + 1 terms and divides by p; read as the mean of p."""
+    w = list(values)[-p:]
+    return sum(w) / len(w)
+
+
+def cosine(a, b) -> float:
+    """|<a, b>| / (|a| |b|) for two device or host arrays (0 if either is 0)."""
+    if isinstance(a, torch.Tensor):
+        na, nb = float(torch.linalg.norm(a)), float(torch.linalg.norm(b))
+        dot = float(torch.sum(a * b))
+    else:
+        na, nb = float(np.linalg.norm(a)), float(np.linalg.norm(b))
+        dot = float(np.sum(np.asarray(a) * np.asarray(b)))
+    return abs(dot) / (na * nb) if na > 0 and nb > 0 else 0.0
+
+
+class SelectiveCollector:
+    """Algorithm 1 of the paper (Section 2.2, "collecting data after the model
+    has been trained"): a solved step whose first-restart residual E_k and
+    time to solution are both below their moving averages M_p (current value
+    included) passes; otherwise the network under-performed on it, its pair is
+    added to the candidate set C_t if its solution is sufficiently orthogonal
+    to every candidate's solution (|cos| <= cos_max), and the failure counts
+    towards f_r.  After f_r failures the caller retrains on C_t (mixed with
+    the training set) and drains it.  Readings: the test uses the current
+    guess x_n^0 (the listing writes x_i^0); the spread d(.,.) is measured on
+    the solutions, as the text says (the listing applies it to the RHS);
+    p, f_r and the threshold are not given."""
+
+    def __init__(self, p: int = 10, f_r: int = 8, cos_max: float = 0.999, similarity=cosine):
+        self.p, self.f_r, self.cos_max, self.similarity = p, f_r, cos_max, similarity
+        self.E: list[float] = []
+        self.T: list[float] = []
+        self.candidates: list = []
+        self.cand_x: list = []
+        self.failures = 0
+        self.seen = 0
+        self.retained = 0
+
+    def passes(self, e_k: float, tos: float) -> bool:
+        self.E.append(e_k)
+        self.T.append(tos)
+        return e_k < moving_average(self.E, self.p) and tos < moving_average(self.T, self.p)
+
+    def observe(self, e_k: float, tos: float, pair, x) -> bool:
+        """Record one solved step; True when f_r under-performing steps have
+        been seen since the last retraining (time to retrain)."""
+        self.seen += 1
+        if self.passes(e_k, tos):
+            return False
+        if all(self.similarity(x, c) <= self.cos_max for c in self.cand_x):
+            self.candidates.append(pair)
+            self.cand_x.append(x)
+            self.retained += 1
+        self.failures += 1
+        return self.failures >= self.f_r
+
+    def drain(self) -> list:
+        out = self.candidates
+        self.candidates, self.cand_x, self.failures = [], [], 0
+        return out
+
+
 @dataclass
 class StepRecord:
     t: int
@@ -77,14 +143,33 @@ class StreamSolver:
     """Solve a stream of right-hand sides on one grid with a chosen guess policy.
 
     guess: "zero", "prev" (u_{t-1}) or "learned" (network, trained in situ).
+    policy (learned guess): "replay" -- one training step per solved pair on
+    the replay buffer (above); "algorithm1" -- the paper's schedule: every
+    pair of the first `collect` steps goes to the training set, which then
+    trains the network for `init_steps` steps; afterwards SelectiveCollector
+    decides which pairs become candidates and when to retrain
+    (`retrain_steps` steps on batches of the candidates plus samples of the
+    training set, after which the candidates join the training set).
     """
 
     def __init__(self, shape, guess: str = "learned", restart_m: int = 30, rtol: float = 1e-8,
                  precision: int = MLG_FP32_IR, warmup: int = 16, replay: int = 64, batch: int = 8,
                  net_cfg: NetCfg | None = None, seed: int = 0, train: bool = True,
-                 time_train: bool = True, autotune: bool = True, tile: int = 0):
+                 time_train: bool = True, autotune: bool = True, tile: int = 0,
+                 policy: str = "replay", collect: int = 50, init_steps: int = 300,
+                 retrain_steps: int = 32, p: int = 10, f_r: int = 8, cos_max: float = 0.999,
+                 train_set: int = 512):
         if guess not in ("zero", "prev", "learned"):
             raise ValueError("guess must be zero, prev or learned")
+        if policy not in ("replay", "algorithm1"):
+            raise ValueError("policy must be replay or algorithm1")
+        self.policy = policy
+        self.collect, self.init_steps, self.retrain_steps = collect, init_steps, retrain_steps
+        if policy == "algorithm1":
+            warmup = collect                      # the collection phase guesses u_{t-1}
+            replay = train_set                    # the training set X_t
+            self.collector = SelectiveCollector(p, f_r, cos_max)
+            self.rng = np.random.default_rng(seed + 1)
         self.shape = tuple(shape)
         self.grid = grid_of(self.shape)
         self.guess_kind = guess
@@ -146,20 +231,54 @@ class StreamSolver:
         rec = StepRecord(self.t, kind, st.iters, st.cycles, st.relres_init, st.relres_first_cycle,
                          st.relres_true, tos)
         if self.train_enabled and self.t > 0:
-            self.replay.push(f.clone(), self.u_prev.clone(), self.x.clone())
             t1 = time.perf_counter()
-            self.train_step()
-            if self.time_train:
+            steps = self._train_after(f, rec)
+            if self.time_train and steps:
                 torch.cuda.synchronize()
                 rec.train_s = time.perf_counter() - t1
                 rec.loss = float(self.loss.item())
+            rec.extra["train_steps"] = steps
         self.u_prev.copy_(self.x)
         self.records.append(rec)
         self.t += 1
         return rec
 
-    def train_step(self) -> None:
-        batch = self.replay.sample(self.batch)
+    def _train_after(self, f: torch.Tensor, rec: StepRecord) -> int:
+        """Training after the solve of step t >= 1; returns the steps taken."""
+        pair = (f.clone(), self.u_prev.clone(), self.x.clone())
+        if self.policy == "replay":
+            self.replay.push(*pair)
+            self.train_step()
+            return 1
+        if self.t < self.collect:                       # collection phase
+            self.replay.push(*pair)
+            if self.t == self.collect - 1:
+                for _ in range(self.init_steps):
+                    self.train_step()
+                return self.init_steps
+            return 0
+        retrain = self.collector.observe(rec.relres_first_cycle, rec.tos, pair, pair[2])
+        rec.extra["candidates"] = len(self.collector.candidates)
+        if not retrain:
+            return 0
+        cands = self.collector.drain()
+        for _ in range(self.retrain_steps):
+            k = min(len(cands), self.batch)
+            chosen = [cands[i] for i in self.rng.choice(len(cands), size=k, replace=False)]
+            fill = self.batch - k
+            if fill > 0 and len(self.replay) > 0:
+                idx = self.rng.choice(len(self.replay), size=min(fill, len(self.replay)),
+                                      replace=False)
+                chosen += [self.replay.items[i] for i in idx]
+            self._train_on(chosen)
+        for c in cands:
+            self.replay.push(*c)
+        return self.retrain_steps
+
+    def _train_on(self, batch) -> None:
         guess_net_train_step(self.net_cfg, self.params, [b[0] for b in batch],
                              [b[1] for b in batch], [b[2] for b in batch], self.ws_train,
                              self.loss)
+
+    def train_step(self) -> None:
+        self._train_on(self.replay.sample(self.batch))

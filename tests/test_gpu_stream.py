@@ -73,3 +73,34 @@ def test_learned_guess_gain(mlg):
     assert iters["prev"] < iters["zero"]
     assert iters["learned"] < 0.6 * iters["prev"]
     assert gain > 100.0
+
+
+def test_algorithm1_schedule(mlg):
+    """The paper's data-collection schedule (Algorithm 1): every pair of the
+    first 50 steps trains the network, then only under-performing steps feed
+    the candidate set and trigger retraining.  On the same stream the trained
+    guess needs well under the previous solution's iterations (measured over
+    [80, 140): 64 vs 5273), the candidate set takes a fraction of the judged
+    steps (measured 19 of 90), and every retraining is counted."""
+    from paper_2103_10975_amd.stream import StreamSolver
+    print("stream algorithm1", flush=True)
+    n, steps, w0 = 256, 140, 80
+    gen = DriftingGaussians((n, n), 4, 0.03, seed=4000)
+    fields = [torch.from_numpy(gen.field(t)).cuda() for t in range(steps)]
+    iters = {}
+    for guess, policy in (("prev", "replay"), ("learned", "algorithm1")):
+        sv = StreamSolver((n, n), guess=guess, restart_m=30, rtol=1e-8, seed=1, time_train=False,
+                          policy=policy, collect=50, init_steps=300)
+        for t in range(steps):
+            sv.step(fields[t])
+        iters[guess] = statistics.fmean(r.iters for r in sv.records[w0:])
+        assert all(r.relres_true <= 1e-8 for r in sv.records)
+    c = sv.collector
+    trained = [r.extra.get("train_steps", 0) for r in sv.records]
+    print(f"  mean iterations over [{w0}, {steps}): prev {iters['prev']:.0f}, "
+          f"learned (algorithm 1) {iters['learned']:.0f}; retained {c.retained} of {c.seen} "
+          f"judged steps, {sum(trained)} training steps")
+    assert iters["learned"] < 0.5 * iters["prev"]
+    assert 0 < c.retained < c.seen == steps - 50
+    assert trained[49] == 300 and sum(trained[1:49]) == 0
+    assert sum(trained) == 300 + 32 * (sum(1 for k in trained[50:] if k))

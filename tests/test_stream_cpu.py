@@ -37,3 +37,43 @@ def test_replay_uniform_coverage():
             counts[i] += 1
     mean = sum(counts) / 63
     assert min(counts) > 0.7 * mean and max(counts) < 1.3 * mean
+
+
+# ---------------------------------------------------------------- Algorithm 1
+import numpy as np
+
+from paper_2103_10975_amd.stream import SelectiveCollector, cosine, moving_average
+
+
+def test_moving_average_is_the_mean_of_the_last_p():
+    ys = [5.0, 1.0, 2.0, 3.0, 10.0]
+    assert moving_average(ys, 3) == (2.0 + 3.0 + 10.0) / 3
+    assert moving_average(ys[:2], 4) == 3.0              # fewer than p values: all of them
+    assert moving_average([7.0], 10) == 7.0
+
+
+def test_collector_passes_only_below_both_averages():
+    c = SelectiveCollector(p=4, f_r=100)
+    x = np.ones(3)
+    # E_k and TOS both falling: each new value is below the mean that includes it
+    for e, t in [(1.0, 1.0), (0.5, 0.9), (0.4, 0.8)]:
+        c.observe(e, t, ("pair", e), x * e)
+    assert c.failures == 1                               # the first step equals its own mean
+    # E_k below average but TOS above: under-performing
+    assert not c.passes(0.1, 5.0)
+    # both below
+    assert c.passes(0.05, 0.1)
+
+
+def test_collector_orthogonality_filter_and_retrain_trigger():
+    c = SelectiveCollector(p=3, f_r=3, cos_max=0.9)
+    e1, e2 = np.array([1.0, 0.0, 0.0]), np.array([0.0, 1.0, 0.0])
+    # three under-performing steps (rising E_k and TOS never pass)
+    assert c.observe(1.0, 1.0, "a", e1) is False          # candidate (set was empty)
+    assert c.observe(2.0, 2.0, "b", 3.0 * e1 + 0.1 * e2) is False   # |cos| > 0.9: rejected
+    assert c.observe(3.0, 3.0, "c", e2) is True            # orthogonal: kept; f_r reached
+    assert c.candidates == ["a", "c"] and c.retained == 2 and c.seen == 3
+    assert c.drain() == ["a", "c"]
+    assert c.candidates == [] and c.failures == 0
+    # cosine is the absolute normalised inner product, 0 for a zero vector
+    assert abs(cosine(e1, -2.0 * e1) - 1.0) < 1e-15 and cosine(e1, np.zeros(3)) == 0.0
