@@ -80,6 +80,76 @@ class DriftingGaussians:
         return out
 
 
+class RandomDipoles:
+    """The multi-scale workload of Section 3 ("Neural Network Designed for
+    Multiple Scales"): every step's source is one asymmetric dipole whose two
+    poles each have two scales, placed, separated and scaled at random anew at
+    every step (steps are independent, so u_{t-1} is a poor guess).
+
+    Step t draws from ``default_rng([seed, t])`` (any step can be generated on
+    its own), in this order: the dipole centre c ~ U[0.3, 0.7]^d; the pole
+    separation l ~ U[0.08, 0.3] along a uniformly random direction e (2D: angle;
+    3D: normalised N(0, I_3)); the overall amplitude s ~ U[0.5, 2]; the negative
+    pole's strength ratio q ~ U[0.4, 1]; one width factor per pole k+, k- ~
+    U[0.75, 1.5].  Then
+
+        f_t = s * (P(x; c + l e / 2, k+ (0.015, 0.06))
+                   - q * P(x; c - l e / 2, k- (0.025, 0.10)))
+
+    with P(x; p, (a, b)) = G(x; p, a) + 0.5 G(x; p, b) and G the unit-height
+    Gaussian exp(-|x - p|^2 / (2 sigma^2)): a narrow core and a wide skirt per
+    pole, the two poles different in widths and strength.  Layout as
+    ``DriftingGaussians``."""
+
+    WIDTHS_POS = (0.015, 0.06)
+    WIDTHS_NEG = (0.025, 0.10)
+    SKIRT = 0.5
+
+    def __init__(self, shape, seed: int):
+        self.shape = tuple(int(s) for s in shape)
+        self.dim = len(self.shape)
+        if self.dim not in (2, 3):
+            raise ValueError("shape must have 2 or 3 axes")
+        self.seed = int(seed)
+
+    def draw(self, t: int) -> dict:
+        """The random parameters of step t."""
+        rng = np.random.default_rng([self.seed, int(t)])
+        c = rng.uniform(0.3, 0.7, size=self.dim)
+        sep = rng.uniform(0.08, 0.3)
+        if self.dim == 2:
+            th = rng.uniform(0.0, 2.0 * np.pi)
+            e = np.array([np.cos(th), np.sin(th)])
+        else:
+            v = rng.standard_normal(3)
+            e = v / np.linalg.norm(v)
+        s = rng.uniform(0.5, 2.0)
+        q = rng.uniform(0.4, 1.0)
+        kp, kn = rng.uniform(0.75, 1.5, size=2)
+        return {"centre": c, "sep": sep, "dir": e, "scale": s, "ratio": q,
+                "pos": c + 0.5 * sep * e, "neg": c - 0.5 * sep * e,
+                "widths_pos": tuple(kp * w for w in self.WIDTHS_POS),
+                "widths_neg": tuple(kn * w for w in self.WIDTHS_NEG)}
+
+    def _gauss(self, axes, p, sigma):
+        inv = 1.0 / (2.0 * sigma ** 2)
+        f = [np.exp(-(ax - pc) ** 2 * inv) for ax, pc in zip(axes, p)]
+        if self.dim == 2:
+            return np.outer(f[1], f[0])
+        return f[2][:, None, None] * f[1][None, :, None] * f[0][None, None, :]
+
+    def field(self, t: int) -> np.ndarray:
+        """f_t on the grid, float64, shape ``self.shape``."""
+        d = self.draw(t)
+        axes = [grid_coords(n) for n in reversed(self.shape)]   # x, y[, z]
+        out = np.zeros(self.shape, dtype=np.float64)
+        for w, k in zip(d["widths_pos"], (1.0, self.SKIRT)):
+            out += k * self._gauss(axes, d["pos"], w)
+        for w, k in zip(d["widths_neg"], (1.0, self.SKIRT)):
+            out -= d["ratio"] * k * self._gauss(axes, d["neg"], w)
+        return d["scale"] * out
+
+
 def system_sizes_batched(seed: int, n2d: int = 64, n3d: int = 8):
     """Grid sides of the uneven batched workload: 2D sides drawn uniformly from
     {128, 192, 256, 384, 512, 768, 1024}, 3D sides uniformly from 64..128."""
