@@ -69,3 +69,40 @@ def guess_net_params(seed: int, channels: int = 32, modes: int = 16,
         out["conv6.b"] = np.zeros_like(out["conv6.b"])
         out["skip.g"] = np.zeros_like(out["skip.g"])
     return out
+
+
+def fluid_net_params(seed: int, channels: int = 32, levels: int = 4, max_blocks: int = 2,
+                     random_bias: bool = True, zero_last: bool = False,
+                     zero_block_out: bool = True) -> dict:
+    """Seeded parameters of the multi-scale (pooling pyramid) guess network, in
+    its tensor order: per level conv1.w [C, 2, 3, 3], conv1.b, conv2.w
+    [C, C, 3, 3], conv2.b; per residual block a.w, a.b, b.w, b.b ([C, C, 3, 3],
+    [C]); head.conv1.w [C, C, 3, 3], head.conv1.b, head.conv2.w [1, C, 3, 3],
+    head.conv2.b [1].  He-uniform weights, biases in +-0.1 when
+    ``random_bias``; with ``zero_block_out`` every block's second convolution
+    (weights and bias) is zero, with ``zero_last`` the output layer is."""
+    rng = np.random.default_rng(seed)
+    C = channels
+    out = {}
+    for l in range(levels):
+        out[f"lvl{l}.conv1.w"], out[f"lvl{l}.conv1.b"] = _conv(rng, C, 2, random_bias)
+        out[f"lvl{l}.conv2.w"], out[f"lvl{l}.conv2.b"] = _conv(rng, C, C, random_bias)
+    for i in range(max_blocks):
+        out[f"blk{i}.a.w"], out[f"blk{i}.a.b"] = _conv(rng, C, C, random_bias)
+        out[f"blk{i}.b.w"], out[f"blk{i}.b.b"] = _conv(rng, C, C, random_bias)
+        if zero_block_out:
+            out[f"blk{i}.b.w"] = np.zeros_like(out[f"blk{i}.b.w"])
+            out[f"blk{i}.b.b"] = np.zeros_like(out[f"blk{i}.b.b"])
+    out["head.conv1.w"], out["head.conv1.b"] = _conv(rng, C, C, random_bias)
+    out["head.conv2.w"], out["head.conv2.b"] = _conv(rng, 1, C, random_bias)
+    if zero_last:
+        out["head.conv2.w"] = np.zeros_like(out["head.conv2.w"])
+        out["head.conv2.b"] = np.zeros_like(out["head.conv2.b"])
+    return out
+
+
+def _conv(rng, cout: int, cin: int, random_bias: bool):
+    bound = np.sqrt(6.0 / (9 * cin))
+    w = rng.uniform(-bound, bound, size=(cout, cin, 3, 3))
+    b = rng.uniform(-0.1, 0.1, size=(cout,)) if random_bias else np.zeros(cout)
+    return w, b
