@@ -291,6 +291,75 @@ int guess_net_train_step(const guess_net_cfg* cfg, void* params, const mlg_grid*
                          const double* const* u_target, void* ws, size_t ws_bytes,
                          float* loss, void* stream);
 
+/* ------------------------------------------------- multi-scale network */
+
+/*
+ * The multi-scale guess network of Section 2.1: a variant of the FluidNet
+ * pressure model with residual blocks stacked before the output layer and
+ * appended while training runs.  2D grids whose sides are multiples of
+ * 2^(levels-1).
+ *   inputs   (r / s_r, f / s_f) as for guess_net (r = f - A u_prev in FP64)
+ *   pyramid  X_0 = inputs, X_l = 2x2 average pool of X_{l-1}, l < levels
+ *   level l  y_l = ReLU(conv3x3 C->C (ReLU(conv3x3 2->C (X_l))))
+ *   sum      S_0 = sum_l of y_l upsampled (nearest, 2^l x 2^l) to the grid
+ *   block i  S_{i+1} = S_i + conv3x3(ReLU(conv3x3(S_i))), i < blocks
+ *   head     out = conv3x3 C->1 (ReLU(conv3x3 C->C (S_blocks)))
+ *   guess    u_prev + (s_r / c_u) out
+ * `blocks` (0..max_blocks) is an argument of every call: storage exists
+ * for max_blocks, and the caller grows the active count (a new block's
+ * second convolution starts at zero, so it begins as the identity).
+ * BF16 weights and activations, FP32 accumulation, FP32 master weights and
+ * Adam moments, as for guess_net.
+ */
+typedef struct {
+  int32_t channels;   /* C, 32 */
+  int32_t levels;     /* pyramid levels, 1..6 (levels - 1 poolings) */
+  int32_t max_blocks; /* residual blocks with storage, 0..8 */
+  float lr, beta1, beta2, eps;
+  uint64_t seed;
+} fluid_net_cfg;
+
+/*
+ * Parameter buffer: the same regions as guess_net (master, grad, adam_m,
+ * adam_v FP32 [P]; bf16 [P]; int64 step).  Tensor order (shapes [out, in,
+ * ky, kx]): for each level l: conv1.w [C,2,3,3] conv1.b [C] conv2.w
+ * [C,C,3,3] conv2.b [C]; for each block i < max_blocks: a.w [C,C,3,3] a.b
+ * [C] b.w [C,C,3,3] b.b [C]; then head.conv1.w [C,C,3,3] head.conv1.b [C]
+ * head.conv2.w [1,C,3,3] head.conv2.b [1].  fluid_net_param_offset gives the
+ * element offset of tensor `index` (0 .. 4 levels + 4 max_blocks + 4).
+ */
+int64_t fluid_net_param_count(const fluid_net_cfg* cfg);
+int64_t fluid_net_param_offset(const fluid_net_cfg* cfg, int32_t index);
+size_t fluid_net_param_bytes(const fluid_net_cfg* cfg);
+
+/* Device workspace for infer (train = 0) or train_step (train = 1); it holds
+ * the activations of all max_blocks blocks. */
+size_t fluid_net_workspace_bytes(const fluid_net_cfg* cfg, const mlg_grid* grid,
+                                 int32_t batch, int32_t train);
+
+/* Deterministic initialisation from cfg->seed: He-uniform weights, zero
+ * biases, zero second convolution in every block, zero output layer (the
+ * untrained network returns u_prev), zero Adam state. */
+int fluid_net_init(const fluid_net_cfg* cfg, void* params, void* stream);
+
+/* BF16 working copy from the FP32 master weights; zero Adam state. */
+int fluid_net_refresh(const fluid_net_cfg* cfg, void* params, void* stream);
+
+/* guess[b] = N(f[b], u_prev[b]) with `blocks` active blocks (FP64 in/out,
+ * [batch][n] contiguous). */
+int fluid_net_infer(const fluid_net_cfg* cfg, const void* params, int32_t blocks,
+                    const mlg_grid* grid, int32_t batch, const double* f,
+                    const double* u_prev, double* guess, void* ws, size_t ws_bytes,
+                    void* stream);
+
+/* One Adam step on the guess_net loss with `blocks` active blocks; the
+ * gradients of inactive blocks are zero, so they do not move.  Arguments as
+ * guess_net_train_step. */
+int fluid_net_train_step(const fluid_net_cfg* cfg, void* params, int32_t blocks,
+                         const mlg_grid* grid, int32_t batch, const double* const* f,
+                         const double* const* u_prev, const double* const* u_target,
+                         void* ws, size_t ws_bytes, float* loss, void* stream);
+
 /* ---------------------------------------------------------------- misc */
 const char* mlg_last_error(void);
 void mlg_shutdown(void);

@@ -21,7 +21,10 @@ __all__ = [
     "mlg_kernel_bench", "mlg_tile_count", "mlg_tile_shape", "mlg_autotune_workspace_bytes",
     "mlg_autotune", "guess_net_param_count", "guess_net_param_offset", "guess_net_param_bytes",
     "guess_net_workspace_bytes", "guess_net_init", "guess_net_refresh", "guess_net_infer",
-    "guess_net_train_step", "mlg_last_error", "mlg_shutdown", "MlgError", "EXPORTS",
+    "guess_net_train_step", "FluidCfg", "fluid_net_param_count", "fluid_net_param_offset",
+    "fluid_net_param_bytes", "fluid_net_workspace_bytes", "fluid_net_init", "fluid_net_refresh",
+    "fluid_net_infer", "fluid_net_train_step", "mlg_last_error", "mlg_shutdown", "MlgError",
+    "EXPORTS",
 ]
 
 HERE = os.path.dirname(os.path.abspath(__file__))
@@ -38,7 +41,9 @@ EXPORTS = (
     "mlg_kernel_bench", "mlg_tile_count", "mlg_tile_shape", "mlg_autotune_workspace_bytes",
     "mlg_autotune", "guess_net_param_count", "guess_net_param_offset", "guess_net_param_bytes",
     "guess_net_workspace_bytes", "guess_net_init", "guess_net_refresh", "guess_net_infer",
-    "guess_net_train_step", "mlg_last_error", "mlg_shutdown",
+    "guess_net_train_step", "fluid_net_param_count", "fluid_net_param_offset",
+    "fluid_net_param_bytes", "fluid_net_workspace_bytes", "fluid_net_init", "fluid_net_refresh",
+    "fluid_net_infer", "fluid_net_train_step", "mlg_last_error", "mlg_shutdown",
 )
 
 
@@ -91,6 +96,17 @@ class NetCfg(ctypes.Structure):
         super().__init__(channels, modes, skip_modes, lr, beta1, beta2, eps, seed)
 
 
+class FluidCfg(ctypes.Structure):
+    _fields_ = [("channels", ctypes.c_int32), ("levels", ctypes.c_int32),
+                ("max_blocks", ctypes.c_int32), ("lr", ctypes.c_float),
+                ("beta1", ctypes.c_float), ("beta2", ctypes.c_float), ("eps", ctypes.c_float),
+                ("seed", ctypes.c_uint64)]
+
+    def __init__(self, channels=32, levels=4, max_blocks=4, lr=1e-3, beta1=0.9, beta2=0.999,
+                 eps=1e-8, seed=0):
+        super().__init__(channels, levels, max_blocks, lr, beta1, beta2, eps, seed)
+
+
 def _load():
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is missing: run paper_2103_10975_amd/build.py "
@@ -121,6 +137,16 @@ def _load():
         "guess_net_infer": (ctypes.c_int, [P(NetCfg), vp, P(Grid), i32, vp, vp, vp, vp, sz, vp]),
         "guess_net_train_step": (ctypes.c_int, [P(NetCfg), vp, P(Grid), i32, P(vp), P(vp), P(vp),
                                                 vp, sz, vp, vp]),
+        "fluid_net_param_count": (i64, [P(FluidCfg)]),
+        "fluid_net_param_offset": (i64, [P(FluidCfg), i32]),
+        "fluid_net_param_bytes": (sz, [P(FluidCfg)]),
+        "fluid_net_workspace_bytes": (sz, [P(FluidCfg), P(Grid), i32, i32]),
+        "fluid_net_init": (ctypes.c_int, [P(FluidCfg), vp, vp]),
+        "fluid_net_refresh": (ctypes.c_int, [P(FluidCfg), vp, vp]),
+        "fluid_net_infer": (ctypes.c_int, [P(FluidCfg), vp, i32, P(Grid), i32, vp, vp, vp, vp, sz,
+                                           vp]),
+        "fluid_net_train_step": (ctypes.c_int, [P(FluidCfg), vp, i32, P(Grid), i32, P(vp), P(vp),
+                                                P(vp), vp, sz, vp, vp]),
         "mlg_last_error": (ctypes.c_char_p, []),
         "mlg_shutdown": (None, []),
     }
@@ -352,9 +378,10 @@ def _align(v: int, a: int = 256) -> int:
     return (v + a - 1) // a * a
 
 
-def net_views(cfg: NetCfg, params: torch.Tensor) -> dict:
-    """Views of the regions of a parameter buffer (uint8 device tensor)."""
-    P = guess_net_param_count(cfg)
+def net_views(cfg, params: torch.Tensor) -> dict:
+    """Views of the regions of a parameter buffer (uint8 device tensor) of
+    either network (NetCfg or FluidCfg)."""
+    P = fluid_net_param_count(cfg) if isinstance(cfg, FluidCfg) else guess_net_param_count(cfg)
     f = _align(P * 4)
     step = 4 * f + _align(P * 2)
     return {"master": params[0:P * 4].view(torch.float32),
@@ -386,6 +413,109 @@ def net_unpack(cfg: NetCfg, flat: torch.Tensor) -> dict:
     out = {}
     for i, name in enumerate(NET_TENSORS):
         off = guess_net_param_offset(cfg, i)
+        n = int(torch.tensor(shapes[name]).prod())
+        out[name] = flat[off:off + n].reshape(shapes[name]).clone()
+    return out
+
+
+# ------------------------------------------------------------------ multi-scale network
+def fluid_net_param_count(cfg: FluidCfg) -> int:
+    return lib.fluid_net_param_count(ctypes.byref(cfg))
+
+
+def fluid_net_param_offset(cfg: FluidCfg, index: int) -> int:
+    return lib.fluid_net_param_offset(ctypes.byref(cfg), index)
+
+
+def fluid_net_param_bytes(cfg: FluidCfg) -> int:
+    return lib.fluid_net_param_bytes(ctypes.byref(cfg))
+
+
+def fluid_net_workspace_bytes(cfg: FluidCfg, grid: Grid, batch: int, train: bool) -> int:
+    n = lib.fluid_net_workspace_bytes(ctypes.byref(cfg), ctypes.byref(grid), batch, int(train))
+    if n == 0:
+        raise MlgError(MLG_ERR_ARG, mlg_last_error())
+    return n
+
+
+def fluid_net_init(cfg: FluidCfg, params: torch.Tensor, stream=None) -> None:
+    _check(lib.fluid_net_init(ctypes.byref(cfg), _ptr(params, torch.uint8), _stream(stream)))
+
+
+def fluid_net_refresh(cfg: FluidCfg, params: torch.Tensor, stream=None) -> None:
+    _check(lib.fluid_net_refresh(ctypes.byref(cfg), _ptr(params, torch.uint8), _stream(stream)))
+
+
+def fluid_net_infer(cfg: FluidCfg, params: torch.Tensor, blocks: int, f: torch.Tensor,
+                    u_prev: torch.Tensor, guess: torch.Tensor, ws: torch.Tensor,
+                    stream=None) -> None:
+    """f, u_prev, guess: [batch, ny, nx] (or [ny, nx]) float64 device tensors."""
+    batch = 1 if f.dim() == 2 else f.shape[0]
+    g = grid_of(f.shape[-2:])
+    _check(lib.fluid_net_infer(ctypes.byref(cfg), _ptr(params, torch.uint8), blocks,
+                               ctypes.byref(g), batch, _ptr(f), _ptr(u_prev), _ptr(guess),
+                               _ptr(ws, torch.uint8), ws.numel(), _stream(stream)))
+
+
+def fluid_net_train_step(cfg: FluidCfg, params: torch.Tensor, blocks: int, fs, u_prevs, u_targets,
+                         ws: torch.Tensor, loss: torch.Tensor | None = None, stream=None) -> None:
+    """fs, u_prevs, u_targets: lists of [ny, nx] float64 device tensors."""
+    batch = len(fs)
+    g = grid_of(fs[0].shape)
+    arr = lambda ts: (ctypes.c_void_p * batch)(*[_ptr(t) for t in ts])  # noqa: E731
+    lp = _ptr(loss, torch.float32) if loss is not None else None
+    _check(lib.fluid_net_train_step(ctypes.byref(cfg), _ptr(params, torch.uint8), blocks,
+                                    ctypes.byref(g), batch, arr(fs), arr(u_prevs), arr(u_targets),
+                                    _ptr(ws, torch.uint8), ws.numel(), lp, _stream(stream)))
+
+
+def fluid_tensor_names(cfg: FluidCfg) -> list:
+    """Tensor order of the multi-scale network's parameter arrays."""
+    names = []
+    for l in range(cfg.levels):
+        names += [f"lvl{l}.conv1.w", f"lvl{l}.conv1.b", f"lvl{l}.conv2.w", f"lvl{l}.conv2.b"]
+    for i in range(cfg.max_blocks):
+        names += [f"blk{i}.a.w", f"blk{i}.a.b", f"blk{i}.b.w", f"blk{i}.b.b"]
+    return names + ["head.conv1.w", "head.conv1.b", "head.conv2.w", "head.conv2.b"]
+
+
+def fluid_tensor_shapes(cfg: FluidCfg) -> dict:
+    C = cfg.channels
+    out = {}
+    for name in fluid_tensor_names(cfg):
+        if name == "head.conv2.b":
+            out[name] = (1,)
+        elif name.endswith(".b"):
+            out[name] = (C,)
+        elif name == "head.conv2.w":
+            out[name] = (1, C, 3, 3)
+        elif name.startswith("lvl") and ".conv1." in name:
+            out[name] = (C, 2, 3, 3)
+        else:
+            out[name] = (C, C, 3, 3)
+    return out
+
+
+def fluid_pack(cfg: FluidCfg, tensors: dict) -> torch.Tensor:
+    """Host float32 [P] array from a dict of tensors (names and shapes above)."""
+    out = torch.zeros(fluid_net_param_count(cfg), dtype=torch.float32)
+    shapes = fluid_tensor_shapes(cfg)
+    for i, name in enumerate(fluid_tensor_names(cfg)):
+        off = fluid_net_param_offset(cfg, i)
+        t = torch.as_tensor(tensors[name], dtype=torch.float32).reshape(-1)
+        if t.numel() != int(torch.tensor(shapes[name]).prod()):
+            raise ValueError(f"{name}: expected shape {shapes[name]}")
+        out[off:off + t.numel()] = t
+    return out
+
+
+def fluid_unpack(cfg: FluidCfg, flat: torch.Tensor) -> dict:
+    """Dict of host float64 tensors from a float32 [P] array (inverse of fluid_pack)."""
+    flat = flat.detach().to("cpu", torch.float64)
+    shapes = fluid_tensor_shapes(cfg)
+    out = {}
+    for i, name in enumerate(fluid_tensor_names(cfg)):
+        off = fluid_net_param_offset(cfg, i)
         n = int(torch.tensor(shapes[name]).prod())
         out[name] = flat[off:off + n].reshape(shapes[name]).clone()
     return out

@@ -192,4 +192,68 @@ int guess_net_train_step(const guess_net_cfg* cfg, void* params, const mlg_grid*
   });
 }
 
+int64_t fluid_net_param_count(const fluid_net_cfg* cfg) {
+  int64_t out = -1;
+  guarded([&] {
+    out = fluid_param_count(cfg);
+    return 0;
+  });
+  return out;
+}
+
+int64_t fluid_net_param_offset(const fluid_net_cfg* cfg, int32_t index) {
+  int64_t out = -1;
+  guarded([&] {
+    out = fluid_param_offset(cfg, index);
+    return 0;
+  });
+  return out;
+}
+
+size_t fluid_net_param_bytes(const fluid_net_cfg* cfg) {
+  size_t out = 0;
+  guarded([&] {
+    out = fluid_param_bytes(cfg);
+    return 0;
+  });
+  return out;
+}
+
+size_t fluid_net_workspace_bytes(const fluid_net_cfg* cfg, const mlg_grid* grid, int32_t batch,
+                                 int32_t train) {
+  size_t out = 0;
+  guarded([&] {
+    out = fluid_workspace_bytes(cfg, grid, batch, train);
+    return 0;
+  });
+  return out;
+}
+
+int fluid_net_init(const fluid_net_cfg* cfg, void* params, void* stream) {
+  return guarded([&] { return fluid_init(cfg, params, (hipStream_t)stream); });
+}
+
+int fluid_net_refresh(const fluid_net_cfg* cfg, void* params, void* stream) {
+  return guarded([&] { return fluid_refresh(cfg, params, (hipStream_t)stream); });
+}
+
+int fluid_net_infer(const fluid_net_cfg* cfg, const void* params, int32_t blocks,
+                    const mlg_grid* grid, int32_t batch, const double* f, const double* u_prev,
+                    double* guess, void* ws, size_t ws_bytes, void* stream) {
+  return guarded([&] {
+    return fluid_infer(cfg, params, blocks, grid, batch, f, u_prev, guess, ws, ws_bytes,
+                       (hipStream_t)stream);
+  });
+}
+
+int fluid_net_train_step(const fluid_net_cfg* cfg, void* params, int32_t blocks,
+                         const mlg_grid* grid, int32_t batch, const double* const* f,
+                         const double* const* u_prev, const double* const* u_target, void* ws,
+                         size_t ws_bytes, float* loss, void* stream) {
+  return guarded([&] {
+    return fluid_train_step(cfg, params, blocks, grid, batch, f, u_prev, u_target, ws, ws_bytes,
+                            loss, (hipStream_t)stream);
+  });
+}
+
 }  // extern "C"

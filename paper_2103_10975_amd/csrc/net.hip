@@ -479,8 +479,11 @@ __global__ void k_wgrad_reduce(const float* part, int nblk, int ntap, int cout, 
 // 3x3 convolution C -> C on a 64 x 4 pixel tile (one row per wavefront) as an
 // implicit GEMM: M = 16 pixels, N = 16 channels, K = 32 input channels of one
 // tap per v_mfma_f32_16x16x32_bf16.  Forward: bias + ReLU epilogue.  DGRAD:
-// flipped-transposed weights, epilogue multiplies by (mask > 0).
-template <int C, bool DGRAD>
+// flipped-transposed weights, epilogue multiplies by (mask > 0).  RES: a
+// linear epilogue (bias in the forward form) that adds `mask` as a residual
+// (none when it is NULL); each output element reads only its own residual
+// element, so `out` may alias it.
+template <int C, bool DGRAD, bool RES = false>
 __global__ __launch_bounds__(256) void k_conv_mfma(const bf16* in, const bf16* wt, const bf16* bias,
                                                    const bf16* mask, bf16* out, int H, int W) {
   constexpr int TX = 64, TY = 4, LX = TX + 2, LY = TY + 2;
@@ -557,8 +560,14 @@ __global__ __launch_bounds__(256) void k_conv_mfma(const bf16* in, const bf16* w
       for (int nt = 0; nt < NT; ++nt) {
         const int n = nt * 16 + li;
         float v = acc[mt][nt][r];
-        if (!DGRAD) v = fmaxf(v + bl[n], 0.f);
-        else v = bf2f(mask[base + n]) > 0.f ? v : 0.f;
+        if constexpr (RES) {
+          v += bl[n];
+          if (mask) v += bf2f(mask[base + n]);
+        } else if constexpr (!DGRAD) {
+          v = fmaxf(v + bl[n], 0.f);
+        } else {
+          v = bf2f(mask[base + n]) > 0.f ? v : 0.f;
+        }
         out[base + n] = f2bf(v);
       }
     }
@@ -922,21 +931,25 @@ __device__ __forceinline__ uint64_t splitmix64(uint64_t x) {
   return x ^ (x >> 31);
 }
 
-struct InitSpec {
-  int64_t off[kNumTensors + 1];
-  int64_t size[kNumTensors];
-  float bound[kNumTensors];    // 0 -> zero tensor
+template <int NT>
+struct InitSpecT {
+  int64_t off[NT + 1];
+  int64_t size[NT];
+  float bound[NT];    // 0 -> zero tensor
 };
+using InitSpec = InitSpecT<kNumTensors>;
 
 // He-uniform weights from a counter-based generator (SplitMix64 of seed and
 // element index), zero biases and output layer, zero Adam state and grads.
+template <int NT>
 __global__ void k_init_params(float* master, float* grad, float* m, float* v, bf16* bf,
-                              long long* step, InitSpec spec, int64_t P, uint64_t seed) {
+                              long long* step, InitSpecT<NT> spec, int ntensors, int64_t P,
+                              uint64_t seed) {
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e == 0) *step = 0;
   if (e >= P) return;
   int t = 0;
-  while (t < kNumTensors - 1 && e >= spec.off[t + 1]) ++t;
+  while (t < ntensors - 1 && e >= spec.off[t + 1]) ++t;
   float val = 0.f;
   if (spec.bound[t] > 0.f && e < spec.off[t] + spec.size[t]) {
     const uint64_t r = splitmix64(seed * 0x100000001B3ull + (uint64_t)e);
@@ -1183,6 +1196,400 @@ void train(const Net& n, const Ptrs& f, const Ptrs& up, const Ptrs& ut, float* l
                                            cfg->beta1, cfg->beta2, cfg->eps);
 }
 
+
+// ------------------------------------------------------------------ multi-scale network
+// The FluidNet-variant guess network (Section 2.1): a 2x2 average-pooling
+// pyramid of the input, per level conv3x3 2->C + ReLU and conv3x3 C->C + ReLU,
+// the levels upsampled (nearest) to the full grid and summed, R residual
+// blocks S += conv3x3(ReLU(conv3x3(S))), then conv3x3 C->C + ReLU and
+// conv3x3 C->1.  Every convolution runs on the kernels above; the pyramid adds
+// three small bandwidth-bound kernels.
+constexpr int kFluidC = 32;
+constexpr int kFluidMaxLevels = 6;
+constexpr int kFluidMaxBlocks = 8;
+constexpr int kFluidMaxTensors = 4 * kFluidMaxLevels + 4 * kFluidMaxBlocks + 4;
+
+struct LvlPtrs {
+  const bf16* p[kFluidMaxLevels];
+};
+
+// Coarse input X_c = avgpool2(X_f) of the 2-channel BF16 input, one thread per
+// coarse pixel, FP32 sum rounded once.
+__global__ void k_pool_in(const bf16* xf, bf16* xc, int Hc, int Wc) {
+  const int b = blockIdx.y;
+  const long long HWc = (long long)Hc * Wc;
+  const long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= HWc) return;
+  const int i = (int)(p / Wc), j = (int)(p % Wc);
+  const long long Wf = 2LL * Wc;
+  const bf16* base = xf + ((size_t)b * 4 * HWc + (size_t)(2 * i) * Wf + 2 * j) * 2;
+  float s0 = 0.f, s1 = 0.f;
+#pragma unroll
+  for (int dy = 0; dy < 2; ++dy)
+#pragma unroll
+    for (int dx = 0; dx < 2; ++dx) {
+      const bf16* px = base + ((size_t)dy * Wf + dx) * 2;
+      s0 += bf2f(px[0]);
+      s1 += bf2f(px[1]);
+    }
+  bf16* o = xc + ((size_t)b * HWc + p) * 2;
+  o[0] = f2bf(0.25f * s0);
+  o[1] = f2bf(0.25f * s1);
+}
+
+// S[p] = sum over levels l (in order) of y_l[p >> l]: nearest upsampling of
+// every level and their sum, one thread per 8 channels of a full-grid pixel.
+template <int C>
+__global__ __launch_bounds__(256) void k_upsum(LvlPtrs y, int L, bf16* S, int H, int W) {
+  constexpr int CH = C / 8;
+  const int b = blockIdx.y;
+  const long long HW = (long long)H * W;
+  const long long e = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (e >= HW * CH) return;
+  const long long pix = e / CH;
+  const int ch = (int)(e % CH);
+  const int yy = (int)(pix / W), xx = (int)(pix % W);
+  float acc[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+  for (int l = 0; l < L; ++l) {
+    const int Hl = H >> l, Wl = W >> l;
+    float v[8];
+    load_ch<8>(y.p[l] + (((size_t)b * Hl + (yy >> l)) * Wl + (xx >> l)) * C + ch * 8, v);
+#pragma unroll
+    for (int k = 0; k < 8; ++k) acc[k] += v[k];
+  }
+  store_ch<8>(S + ((size_t)b * HW + pix) * C + ch * 8, acc);
+}
+
+// Adjoint of the upsampling, one level down: Pc = the sum of each 2x2 block of
+// Pf (FP32; Pc may be NULL at the coarsest level), and dz = Pc (Y > 0) in BF16
+// (the gradient of that level's ReLU output).
+template <int C, class TI>
+__global__ __launch_bounds__(256) void k_sumpool_mask(const TI* Pf, float* Pc, const bf16* Y,
+                                                      bf16* dz, int Hc, int Wc) {
+  constexpr int CH = C / 8;
+  const int b = blockIdx.y;
+  const long long HWc = (long long)Hc * Wc;
+  const long long e = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (e >= HWc * CH) return;
+  const long long pix = e / CH;
+  const int ch = (int)(e % CH);
+  const int i = (int)(pix / Wc), j = (int)(pix % Wc);
+  const long long Wf = 2LL * Wc;
+  float acc[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int dy = 0; dy < 2; ++dy)
+#pragma unroll
+    for (int dx = 0; dx < 2; ++dx) {
+      float v[8];
+      load_ch<8>(Pf + (((size_t)b * 2 * Hc + 2 * i + dy) * Wf + 2 * j + dx) * C + ch * 8, v);
+#pragma unroll
+      for (int k = 0; k < 8; ++k) acc[k] += v[k];
+    }
+  const size_t o = ((size_t)b * HWc + pix) * C + ch * 8;
+  if (Pc) store_ch<8>(Pc + o, acc);
+  float m[8];
+  load_ch<8>(Y + o, m);
+#pragma unroll
+  for (int k = 0; k < 8; ++k) acc[k] = m[k] > 0.f ? acc[k] : 0.f;
+  store_ch<8>(dz + o, acc);
+}
+
+// dz = d (Y > 0), 8 elements per thread.
+__global__ void k_mask8(const bf16* d, const bf16* Y, bf16* dz, long long n8) {
+  const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n8) return;
+  float v[8], m[8];
+  load_ch<8>(d + e * 8, v);
+  load_ch<8>(Y + e * 8, m);
+#pragma unroll
+  for (int k = 0; k < 8; ++k) v[k] = m[k] > 0.f ? v[k] : 0.f;
+  store_ch<8>(dz + e * 8, v);
+}
+
+__global__ void k_fill0(float* p, long long n) {
+  const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < n) p[e] = 0.f;
+}
+
+struct FDims {
+  int B, H, W, L, R;   // R: blocks with storage (cfg->max_blocks)
+  long long HW;
+};
+
+void check_fluid_cfg(const fluid_net_cfg* cfg) {
+  if (!cfg) throw ArgError{MLG_ERR_ARG, "cfg is NULL"};
+  if (cfg->channels != kFluidC) throw ArgError{MLG_ERR_ARG, "channels must be 32"};
+  if (cfg->levels < 1 || cfg->levels > kFluidMaxLevels)
+    throw ArgError{MLG_ERR_ARG, "levels must be in 1..6"};
+  if (cfg->max_blocks < 0 || cfg->max_blocks > kFluidMaxBlocks)
+    throw ArgError{MLG_ERR_ARG, "max_blocks must be in 0..8"};
+}
+
+int fl_ntensors(const fluid_net_cfg* cfg) { return 4 * cfg->levels + 4 * cfg->max_blocks + 4; }
+inline int fl_lvl(int l, int k) { return 4 * l + k; }
+inline int fl_blk(const FDims& d, int i, int k) { return 4 * d.L + 4 * i + k; }
+inline int fl_head(const FDims& d, int k) { return 4 * d.L + 4 * d.R + k; }
+
+// element counts and He-uniform fan-ins (0: zero-initialised) per tensor
+void fluid_sizes(const fluid_net_cfg* cfg, int64_t* sz, float* fan) {
+  const int64_t C = kFluidC;
+  int t = 0;
+  auto put = [&](int64_t n, float f) {
+    sz[t] = n;
+    fan[t] = f;
+    ++t;
+  };
+  for (int l = 0; l < cfg->levels; ++l) {
+    put(C * 2 * 9, 18.f);
+    put(C, 0.f);
+    put(C * C * 9, 9.f * C);
+    put(C, 0.f);
+  }
+  for (int i = 0; i < cfg->max_blocks; ++i) {
+    put(C * C * 9, 9.f * C);
+    put(C, 0.f);
+    put(C * C * 9, 0.f);      // a new block starts as the identity
+    put(C, 0.f);
+  }
+  put(C * C * 9, 9.f * C);
+  put(C, 0.f);
+  put(C * 9, 0.f);            // zero output layer: the untrained network returns u_prev
+  put(1, 0.f);
+}
+
+struct FLayout {
+  int n;
+  int64_t P;
+  int64_t off[kFluidMaxTensors + 1];
+  size_t master, grad, m, v, bf, step, total;
+};
+
+FLayout fluid_layout(const fluid_net_cfg* cfg) {
+  check_fluid_cfg(cfg);
+  FLayout L{};
+  int64_t sz[kFluidMaxTensors];
+  float fan[kFluidMaxTensors];
+  fluid_sizes(cfg, sz, fan);
+  L.n = fl_ntensors(cfg);
+  L.off[0] = 0;
+  for (int i = 0; i < L.n; ++i) L.off[i + 1] = L.off[i] + (sz[i] + 63) / 64 * 64;
+  L.P = L.off[L.n];
+  const size_t f = align_up((size_t)L.P * 4, 256);
+  L.master = 0;
+  L.grad = f;
+  L.m = 2 * f;
+  L.v = 3 * f;
+  L.bf = 4 * f;
+  L.step = L.bf + align_up((size_t)L.P * 2, 256);
+  L.total = L.step + 256;
+  return L;
+}
+
+FDims check_fluid_grid(const fluid_net_cfg* cfg, const mlg_grid* grid, int batch) {
+  check_fluid_cfg(cfg);
+  if (!grid || grid->dim != 2) throw ArgError{MLG_ERR_ARG, "the guess network takes 2D grids"};
+  const int q = 1 << (cfg->levels - 1);
+  if (grid->nx < 1 || grid->ny < 1 || grid->nx % q || grid->ny % q)
+    throw ArgError{MLG_ERR_ARG, "grid sides must be multiples of 2^(levels-1)"};
+  if (batch < 1 || batch > kMaxBatch) throw ArgError{MLG_ERR_ARG, "batch must be in 1..64"};
+  return FDims{batch, grid->ny, grid->nx, cfg->levels, cfg->max_blocks,
+               (long long)grid->nx * grid->ny};
+}
+
+struct FWs {
+  size_t s, r0, rms, X[kFluidMaxLevels], A[kFluidMaxLevels], Y[kFluidMaxLevels];
+  size_t S[kFluidMaxBlocks + 1], Hb[kFluidMaxBlocks], o, out;
+  size_t dout, dS, d1, d2, P[2], part, loss, total;
+  int wgrad_blocks;
+};
+
+FWs fluid_ws(const FDims& d, bool train) {
+  FWs L{};
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    size_t r = o;
+    o = align_up(o + bytes, 256);
+    return r;
+  };
+  const size_t full = (size_t)d.B * d.HW * kFluidC * 2;
+  L.s = take((size_t)d.B * 8 * 3);
+  L.r0 = take((size_t)d.B * d.HW * 8);
+  L.rms = take((size_t)2 * d.B * kRmsBlocks * 8);
+  for (int l = 0; l < d.L; ++l) {
+    const size_t hw = (size_t)(d.H >> l) * (d.W >> l);
+    L.X[l] = take((size_t)d.B * hw * 2 * 2);
+    L.A[l] = take((size_t)d.B * hw * kFluidC * 2);
+    L.Y[l] = take((size_t)d.B * hw * kFluidC * 2);
+  }
+  for (int i = 0; i <= d.R; ++i) L.S[i] = take(full);
+  for (int i = 0; i < d.R; ++i) L.Hb[i] = take(full);
+  L.o = take(full);
+  L.out = take((size_t)d.B * d.HW * 4);
+  if (train) {
+    L.dout = take((size_t)d.B * d.HW * 4);
+    L.dS = take(full);
+    L.d1 = take(full);
+    L.d2 = take(full);
+    const size_t q = (size_t)d.B * (d.HW / 4) * kFluidC * 4;
+    L.P[0] = take(q);
+    L.P[1] = take(q);
+    L.wgrad_blocks = 512;
+    L.part = take((size_t)L.wgrad_blocks * (9 * kFluidC * kFluidC + kFluidC) * 4);
+    L.loss = take(4096 * 8);
+  }
+  L.total = o;
+  return L;
+}
+
+struct FNet {
+  FDims d;
+  FLayout pl;
+  FWs wl;
+  char* params;
+  char* ws;
+  const bf16* bfw(int t) const { return (const bf16*)(params + pl.bf) + pl.off[t]; }
+  float* grad(int t) const { return (float*)(params + pl.grad) + pl.off[t]; }
+  template <class T>
+  T* w(size_t off) const { return (T*)(ws + off); }
+};
+
+void fluid_forward(const FNet& n, const Ptrs& f, const Ptrs& u, int blocks, hipStream_t s) {
+  constexpr int C = kFluidC;
+  const FDims& d = n.d;
+  const long long HW = d.HW;
+  double* sv = n.w<double>(n.wl.s);
+  double* r0 = n.w<double>(n.wl.r0);
+  k_resid_in<<<dim3(cdiv(HW, 256), d.B), 256, 0, s>>>(f, u, r0, d.H, d.W);
+  Ptrs rp{};
+  for (int b = 0; b < d.B; ++b) rp.p[b] = r0 + (size_t)b * HW;
+  double* rms_part = n.w<double>(n.wl.rms);
+  k_sumsq<<<dim3(kRmsBlocks, 2 * d.B), 256, 0, s>>>(rp, f, d.B, HW, rms_part);
+  k_rms_fin<<<2 * d.B, 64, 0, s>>>(rms_part, d.B, HW, sv);
+  k_norm_in<<<dim3(cdiv(HW, 256), d.B), 256, 0, s>>>(r0, f, sv + d.B, sv + 2 * d.B,
+                                                      n.w<bf16>(n.wl.X[0]), HW);
+  for (int l = 1; l < d.L; ++l) {
+    const int Hl = d.H >> l, Wl = d.W >> l;
+    k_pool_in<<<dim3(cdiv((long long)Hl * Wl, 256), d.B), 256, 0, s>>>(
+        n.w<bf16>(n.wl.X[l - 1]), n.w<bf16>(n.wl.X[l]), Hl, Wl);
+  }
+  LvlPtrs yp{};
+  for (int l = 0; l < d.L; ++l) {
+    const int Hl = d.H >> l, Wl = d.W >> l;
+    const long long hw = (long long)Hl * Wl;
+    k_conv_small<2, C, bf16, bf16, false, true><<<dim3(cdiv(hw, 256), d.B), 256, 0, s>>>(
+        n.w<bf16>(n.wl.X[l]), n.bfw(fl_lvl(l, 0)), n.bfw(fl_lvl(l, 1)), nullptr,
+        n.w<bf16>(n.wl.A[l]), Hl, Wl);
+    k_conv_mfma<C, false><<<dim3(cdiv(Wl, 64) * cdiv(Hl, 4), d.B), 256, 0, s>>>(
+        n.w<bf16>(n.wl.A[l]), n.bfw(fl_lvl(l, 2)), n.bfw(fl_lvl(l, 3)), nullptr,
+        n.w<bf16>(n.wl.Y[l]), Hl, Wl);
+    yp.p[l] = n.w<bf16>(n.wl.Y[l]);
+  }
+  k_upsum<C><<<dim3(cdiv(HW * (C / 8), 256), d.B), 256, 0, s>>>(yp, d.L, n.w<bf16>(n.wl.S[0]),
+                                                                d.H, d.W);
+  const dim3 cg(cdiv(d.W, 64) * cdiv(d.H, 4), d.B);
+  for (int i = 0; i < blocks; ++i) {
+    k_conv_mfma<C, false><<<cg, 256, 0, s>>>(n.w<bf16>(n.wl.S[i]), n.bfw(fl_blk(d, i, 0)),
+                                             n.bfw(fl_blk(d, i, 1)), nullptr,
+                                             n.w<bf16>(n.wl.Hb[i]), d.H, d.W);
+    k_conv_mfma<C, false, true><<<cg, 256, 0, s>>>(n.w<bf16>(n.wl.Hb[i]), n.bfw(fl_blk(d, i, 2)),
+                                                   n.bfw(fl_blk(d, i, 3)), n.w<bf16>(n.wl.S[i]),
+                                                   n.w<bf16>(n.wl.S[i + 1]), d.H, d.W);
+  }
+  k_conv_mfma<C, false><<<cg, 256, 0, s>>>(n.w<bf16>(n.wl.S[blocks]), n.bfw(fl_head(d, 0)),
+                                           n.bfw(fl_head(d, 1)), nullptr, n.w<bf16>(n.wl.o), d.H,
+                                           d.W);
+  k_conv_small<C, 1, bf16, float, false, false><<<dim3(cdiv(HW, 256), d.B), 256, 0, s>>>(
+      n.w<bf16>(n.wl.o), n.bfw(fl_head(d, 2)), n.bfw(fl_head(d, 3)), nullptr,
+      n.w<float>(n.wl.out), d.H, d.W);
+}
+
+void fl_wgrad9(const FNet& n, const bf16* in, const bf16* dz, int tw, int tb, int H, int W,
+               hipStream_t s) {
+  constexpr int C = kFluidC;
+  float* part = n.w<float>(n.wl.part);
+  const int G = n.wl.wgrad_blocks;
+  k_wgrad_mfma<C, 9><<<G, 256, 0, s>>>(in, dz, part, n.d.B, H, W);
+  k_wgrad_reduce<<<cdiv(9 * C * C + C, 256), 256, 0, s>>>(part, G, 9, C, C, n.grad(tw), n.grad(tb));
+}
+
+void fluid_train(const FNet& n, const Ptrs& f, const Ptrs& up, const Ptrs& ut, int blocks,
+                 float* loss, const fluid_net_cfg* cfg, hipStream_t s) {
+  constexpr int C = kFluidC;
+  fluid_forward(n, f, up, blocks, s);
+  const FDims& d = n.d;
+  const long long HW = d.HW;
+  double* sv = n.w<double>(n.wl.s);
+  float* out = n.w<float>(n.wl.out);
+  float* dout = n.w<float>(n.wl.dout);
+  float* part = n.w<float>(n.wl.part);
+  const int G = n.wl.wgrad_blocks;
+  bf16* dS = n.w<bf16>(n.wl.dS);
+  bf16* d1 = n.w<bf16>(n.wl.d1);
+  bf16* d2 = n.w<bf16>(n.wl.d2);
+  {
+    double* lpart = n.w<double>(n.wl.loss) + 8;
+    float* ldev = (float*)n.w<double>(n.wl.loss);
+    const int nb = (int)std::min<long long>(kMaxGrid, cdiv((long long)d.B * HW, 1024));
+    k_loss<<<nb, 256, 0, s>>>(out, ut, up, sv + d.B, dout, lpart, HW, d.B);
+    k_loss_sum<<<1, kReduceThreads, 0, s>>>(lpart, nb, ldev, loss, d.B);
+  }
+  const dim3 cg(cdiv(d.W, 64) * cdiv(d.H, 4), d.B);
+  // head: out = conv(o), o = ReLU(conv(S_R))
+  bf16* o = n.w<bf16>(n.wl.o);
+  k_wgrad_thin<C, 1, float><<<G, 256, 0, s>>>(o, dout, part, d.B, d.H, d.W);
+  k_wgrad_reduce<<<cdiv(9 * C + 1, 256), 256, 0, s>>>(part, G, 9, 1, C, n.grad(fl_head(d, 2)),
+                                                       n.grad(fl_head(d, 3)));
+  k_conv_small<1, C, float, bf16, true, false><<<dim3(cdiv(HW, 256), d.B), 256, 0, s>>>(
+      dout, n.bfw(fl_head(d, 2)), nullptr, o, d1, d.H, d.W);
+  fl_wgrad9(n, n.w<bf16>(n.wl.S[blocks]), d1, fl_head(d, 0), fl_head(d, 1), d.H, d.W, s);
+  k_conv_mfma<C, true, true><<<cg, 256, 0, s>>>(d1, n.bfw(fl_head(d, 0)), nullptr, nullptr, dS,
+                                                d.H, d.W);
+  // residual blocks, last first: dS accumulates in place
+  for (int i = blocks - 1; i >= 0; --i) {
+    bf16* hb = n.w<bf16>(n.wl.Hb[i]);
+    fl_wgrad9(n, hb, dS, fl_blk(d, i, 2), fl_blk(d, i, 3), d.H, d.W, s);
+    k_conv_mfma<C, true><<<cg, 256, 0, s>>>(dS, n.bfw(fl_blk(d, i, 2)), nullptr, hb, d1, d.H, d.W);
+    fl_wgrad9(n, n.w<bf16>(n.wl.S[i]), d1, fl_blk(d, i, 0), fl_blk(d, i, 1), d.H, d.W, s);
+    k_conv_mfma<C, true, true><<<cg, 256, 0, s>>>(d1, n.bfw(fl_blk(d, i, 0)), nullptr, dS, dS,
+                                                  d.H, d.W);
+  }
+  // levels: the gradient of y_l is the 2^l x 2^l block sum of dS, masked
+  float* P[2] = {n.w<float>(n.wl.P[0]), n.w<float>(n.wl.P[1])};
+  for (int l = 0; l < d.L; ++l) {
+    const int Hl = d.H >> l, Wl = d.W >> l;
+    const long long hw = (long long)Hl * Wl;
+    const bf16* Y = n.w<bf16>(n.wl.Y[l]);
+    float* pc = l + 1 < d.L ? P[l & 1] : nullptr;
+    if (l == 0)
+      k_mask8<<<cdiv((long long)d.B * HW * C / 8, 256), 256, 0, s>>>(dS, Y, d1,
+                                                                    (long long)d.B * HW * C / 8);
+    else if (l == 1)
+      k_sumpool_mask<C, bf16><<<dim3(cdiv(hw * (C / 8), 256), d.B), 256, 0, s>>>(dS, pc, Y, d1, Hl,
+                                                                                Wl);
+    else
+      k_sumpool_mask<C, float><<<dim3(cdiv(hw * (C / 8), 256), d.B), 256, 0, s>>>(
+          P[(l - 1) & 1], pc, Y, d1, Hl, Wl);
+    bf16* A = n.w<bf16>(n.wl.A[l]);
+    fl_wgrad9(n, A, d1, fl_lvl(l, 2), fl_lvl(l, 3), Hl, Wl, s);
+    k_conv_mfma<C, true><<<dim3(cdiv(Wl, 64) * cdiv(Hl, 4), d.B), 256, 0, s>>>(
+        d1, n.bfw(fl_lvl(l, 2)), nullptr, A, d2, Hl, Wl);
+    k_wgrad_thin<2, C, bf16><<<G, 256, 0, s>>>(n.w<bf16>(n.wl.X[l]), d2, part, d.B, Hl, Wl);
+    k_wgrad_reduce<<<cdiv(9 * C * 2 + C, 256), 256, 0, s>>>(part, G, 9, C, 2, n.grad(fl_lvl(l, 0)),
+                                                            n.grad(fl_lvl(l, 1)));
+  }
+  // blocks beyond the active ones take no step
+  const int64_t z0 = n.pl.off[fl_blk(d, blocks, 0)], z1 = n.pl.off[fl_head(d, 0)];
+  if (z1 > z0)
+    k_fill0<<<cdiv(z1 - z0, 256), 256, 0, s>>>((float*)(n.params + n.pl.grad) + z0, z1 - z0);
+  long long* step = (long long*)(n.params + n.pl.step);
+  k_step_inc<<<1, 64, 0, s>>>(step);
+  k_adam<<<cdiv(n.pl.P, 256), 256, 0, s>>>((float*)(n.params + n.pl.master),
+                                           (const float*)(n.params + n.pl.grad),
+                                           (float*)(n.params + n.pl.m), (float*)(n.params + n.pl.v),
+                                           (bf16*)(n.params + n.pl.bf), step, n.pl.P, cfg->lr,
+                                           cfg->beta1, cfg->beta2, cfg->eps);
+}
+
 }  // namespace
 
 // ------------------------------------------------------------------ entry points
@@ -1214,10 +1621,10 @@ int net_init(const guess_net_cfg* cfg, void* params, hipStream_t s) {
     spec.size[i] = sz[i];
   }
   char* p = (char*)params;
-  k_init_params<<<cdiv(pl.P, 256), 256, 0, s>>>((float*)(p + pl.master), (float*)(p + pl.grad),
+  k_init_params<kNumTensors><<<cdiv(pl.P, 256), 256, 0, s>>>((float*)(p + pl.master), (float*)(p + pl.grad),
                                                 (float*)(p + pl.m), (float*)(p + pl.v),
                                                 (bf16*)(p + pl.bf), (long long*)(p + pl.step), spec,
-                                                pl.P, cfg->seed);
+                                                kNumTensors, pl.P, cfg->seed);
   MLG_HIP(hipGetLastError());
   return MLG_OK;
 }
@@ -1274,6 +1681,102 @@ int net_train_step(const guess_net_cfg* cfg, void* params, const mlg_grid* grid,
   }
   if (d.C == 32) train<32>(n, fp, up, tp, loss, cfg, s);
   else train<64>(n, fp, up, tp, loss, cfg, s);
+  MLG_HIP(hipGetLastError());
+  return MLG_OK;
+}
+
+// ------------------------------------------------------------------ multi-scale network entry points
+int64_t fluid_param_offset(const fluid_net_cfg* cfg, int index) {
+  FLayout pl = fluid_layout(cfg);
+  if (index < 0 || index > pl.n) throw ArgError{MLG_ERR_ARG, "tensor index out of range"};
+  return pl.off[index];
+}
+
+int64_t fluid_param_count(const fluid_net_cfg* cfg) { return fluid_layout(cfg).P; }
+
+size_t fluid_param_bytes(const fluid_net_cfg* cfg) { return fluid_layout(cfg).total; }
+
+size_t fluid_workspace_bytes(const fluid_net_cfg* cfg, const mlg_grid* grid, int batch, int train) {
+  return fluid_ws(check_fluid_grid(cfg, grid, batch), train != 0).total;
+}
+
+int fluid_init(const fluid_net_cfg* cfg, void* params, hipStream_t s) {
+  FLayout pl = fluid_layout(cfg);
+  if (!params) throw ArgError{MLG_ERR_ARG, "params is NULL"};
+  InitSpecT<kFluidMaxTensors> spec{};
+  int64_t sz[kFluidMaxTensors];
+  float fan[kFluidMaxTensors];
+  fluid_sizes(cfg, sz, fan);
+  for (int i = 0; i <= pl.n; ++i) spec.off[i] = pl.off[i];
+  for (int i = 0; i < pl.n; ++i) {
+    spec.size[i] = sz[i];
+    spec.bound[i] = fan[i] > 0.f ? sqrtf(6.f / fan[i]) : 0.f;
+  }
+  char* p = (char*)params;
+  k_init_params<kFluidMaxTensors><<<cdiv(pl.P, 256), 256, 0, s>>>(
+      (float*)(p + pl.master), (float*)(p + pl.grad), (float*)(p + pl.m), (float*)(p + pl.v),
+      (bf16*)(p + pl.bf), (long long*)(p + pl.step), spec, pl.n, pl.P, cfg->seed);
+  MLG_HIP(hipGetLastError());
+  return MLG_OK;
+}
+
+int fluid_refresh(const fluid_net_cfg* cfg, void* params, hipStream_t s) {
+  FLayout pl = fluid_layout(cfg);
+  if (!params) throw ArgError{MLG_ERR_ARG, "params is NULL"};
+  char* p = (char*)params;
+  k_refresh<<<cdiv(pl.P, 256), 256, 0, s>>>((const float*)(p + pl.master), (float*)(p + pl.grad),
+                                            (float*)(p + pl.m), (float*)(p + pl.v),
+                                            (bf16*)(p + pl.bf), (long long*)(p + pl.step), pl.P);
+  MLG_HIP(hipGetLastError());
+  return MLG_OK;
+}
+
+static void check_blocks(const fluid_net_cfg* cfg, int blocks) {
+  if (blocks < 0 || blocks > cfg->max_blocks)
+    throw ArgError{MLG_ERR_ARG, "blocks must be in 0..max_blocks"};
+}
+
+int fluid_infer(const fluid_net_cfg* cfg, const void* params, int blocks, const mlg_grid* grid,
+                int batch, const double* f, const double* u_prev, double* guess, void* ws,
+                size_t ws_bytes, hipStream_t s) {
+  FDims d = check_fluid_grid(cfg, grid, batch);
+  check_blocks(cfg, blocks);
+  if (!params || !f || !u_prev || !guess) throw ArgError{MLG_ERR_ARG, "NULL pointer"};
+  FWs wl = fluid_ws(d, false);
+  if (!ws || ws_bytes < wl.total) throw ArgError{MLG_ERR_WORKSPACE, "network workspace too small"};
+  FNet n{d, fluid_layout(cfg), wl, (char*)params, (char*)ws};
+  Ptrs fp{}, up{};
+  MPtrs gp{};
+  for (int b = 0; b < d.B; ++b) {
+    fp.p[b] = f + (size_t)b * d.HW;
+    up.p[b] = u_prev + (size_t)b * d.HW;
+    gp.p[b] = guess + (size_t)b * d.HW;
+  }
+  fluid_forward(n, fp, up, blocks, s);
+  k_guess<<<dim3(cdiv(d.HW, 256), d.B), 256, 0, s>>>(n.w<float>(wl.out), up, n.w<double>(wl.s), gp,
+                                                      d.HW);
+  MLG_HIP(hipGetLastError());
+  return MLG_OK;
+}
+
+int fluid_train_step(const fluid_net_cfg* cfg, void* params, int blocks, const mlg_grid* grid,
+                     int batch, const double* const* f, const double* const* u_prev,
+                     const double* const* u_target, void* ws, size_t ws_bytes, float* loss,
+                     hipStream_t s) {
+  FDims d = check_fluid_grid(cfg, grid, batch);
+  check_blocks(cfg, blocks);
+  if (!params || !f || !u_prev || !u_target) throw ArgError{MLG_ERR_ARG, "NULL pointer"};
+  FWs wl = fluid_ws(d, true);
+  if (!ws || ws_bytes < wl.total) throw ArgError{MLG_ERR_WORKSPACE, "network workspace too small"};
+  FNet n{d, fluid_layout(cfg), wl, (char*)params, (char*)ws};
+  Ptrs fp{}, up{}, tp{};
+  for (int b = 0; b < d.B; ++b) {
+    if (!f[b] || !u_prev[b] || !u_target[b]) throw ArgError{MLG_ERR_ARG, "NULL sample pointer"};
+    fp.p[b] = f[b];
+    up.p[b] = u_prev[b];
+    tp.p[b] = u_target[b];
+  }
+  fluid_train(n, fp, up, tp, blocks, loss, cfg, s);
   MLG_HIP(hipGetLastError());
   return MLG_OK;
 }
