@@ -28,8 +28,10 @@ from dataclasses import dataclass, field
 import numpy as np
 import torch
 
-from . import (MLG_ERR_NONFINITE, MLG_FP32_IR, MlgError, NetCfg, Opts, grid_of, gmres_solve,
-               mlg_autotune,
+from . import (MLG_ERR_NONFINITE, MLG_FP32_IR, FluidCfg, MlgError, NetCfg, Opts, grid_of,
+               gmres_solve, mlg_autotune,
+               fluid_net_infer, fluid_net_init, fluid_net_param_bytes, fluid_net_train_step,
+               fluid_net_workspace_bytes,
                gmres_workspace_bytes, guess_net_infer, guess_net_init, guess_net_param_bytes,
                guess_net_train_step, guess_net_workspace_bytes, workspace)
 
@@ -124,6 +126,49 @@ class SelectiveCollector:
         return out
 
 
+class BlockGrowth:
+    """When to append a residual block to the multi-scale network (Section
+    2.1: blocks are added before the output layer as the network's progress
+    stagnates).  Training losses are averaged over windows of `window` steps;
+    when a window's mean is not at least `min_gain` (relative) below the
+    previous window's, the network grows by one block (up to `max_blocks`) and
+    the comparison restarts.  The paper gives no rule; this one is ours."""
+
+    def __init__(self, window: int = 50, min_gain: float = 0.05, max_blocks: int = 4):
+        self.window, self.min_gain, self.max_blocks = window, min_gain, max_blocks
+        self.blocks = 0
+        self.cur: list[float] = []
+        self.prev_mean: float | None = None
+        self.events: list[tuple[int, int]] = []     # (training step, blocks after)
+        self.steps = 0
+
+    def observe(self, loss: float) -> bool:
+        """Record one training loss; True when a block was just appended."""
+        self.steps += 1
+        self.cur.append(loss)
+        if len(self.cur) < self.window:
+            return False
+        mean = sum(self.cur) / len(self.cur)
+        self.cur = []
+        prev, self.prev_mean = self.prev_mean, mean
+        if prev is None or self.blocks >= self.max_blocks or mean < (1.0 - self.min_gain) * prev:
+            return False
+        self.blocks += 1
+        self.prev_mean = None
+        self.events.append((self.steps, self.blocks))
+        return True
+
+
+def fluid_levels(shape, coarsest: int = 8, most: int = 6) -> int:
+    """Pyramid levels for a grid: the most (<= `most`) for which both sides
+    divide by 2^(levels-1) and the coarsest level keeps >= `coarsest` points
+    per side."""
+    L = 1
+    while L < most and all(n % (1 << L) == 0 and n >> L >= coarsest for n in shape):
+        L += 1
+    return L
+
+
 @dataclass
 class StepRecord:
     t: int
@@ -143,6 +188,9 @@ class StreamSolver:
     """Solve a stream of right-hand sides on one grid with a chosen guess policy.
 
     guess: "zero", "prev" (u_{t-1}) or "learned" (network, trained in situ).
+    network (learned guess): "spectral" (the guess_net network) or "fluid"
+    (the multi-scale pooling-pyramid network, growing residual blocks by
+    BlockGrowth up to `max_blocks`).
     policy (learned guess): "replay" -- one training step per solved pair on
     the replay buffer (above); "algorithm1" -- the paper's schedule: every
     pair of the first `collect` steps goes to the training set, which then
@@ -158,11 +206,15 @@ class StreamSolver:
                  time_train: bool = True, autotune: bool = True, tile: int = 0,
                  policy: str = "replay", collect: int = 50, init_steps: int = 300,
                  retrain_steps: int = 32, p: int = 10, f_r: int = 8, cos_max: float = 0.999,
-                 train_set: int = 512):
+                 train_set: int = 512, network: str = "spectral", fluid_cfg: FluidCfg | None = None,
+                 max_blocks: int = 4, grow_window: int = 50, grow_min_gain: float = 0.05):
         if guess not in ("zero", "prev", "learned"):
             raise ValueError("guess must be zero, prev or learned")
         if policy not in ("replay", "algorithm1"):
             raise ValueError("policy must be replay or algorithm1")
+        if network not in ("spectral", "fluid"):
+            raise ValueError("network must be spectral or fluid")
+        self.network = network
         self.policy = policy
         self.collect, self.init_steps, self.retrain_steps = collect, init_steps, retrain_steps
         if policy == "algorithm1":
@@ -191,13 +243,23 @@ class StreamSolver:
         if guess == "learned":
             if len(self.shape) != 2:
                 raise ValueError("the learned guess is defined on 2D grids")
-            # the skip band may not exceed the grid
-            self.net_cfg = net_cfg or NetCfg(seed=seed, skip_modes=min(64, *self.shape))
-            self.params = torch.zeros(guess_net_param_bytes(self.net_cfg), dtype=torch.uint8,
-                                      device="cuda")
-            guess_net_init(self.net_cfg, self.params)
-            self.ws_infer = workspace(guess_net_workspace_bytes(self.net_cfg, self.grid, 1, False))
-            self.ws_train = workspace(guess_net_workspace_bytes(self.net_cfg, self.grid, batch, True))
+            if network == "fluid":
+                self.net_cfg = fluid_cfg or FluidCfg(seed=seed, levels=fluid_levels(self.shape),
+                                                     max_blocks=max_blocks)
+                self.growth = BlockGrowth(grow_window, grow_min_gain, self.net_cfg.max_blocks)
+                self.params = torch.zeros(fluid_net_param_bytes(self.net_cfg), dtype=torch.uint8,
+                                          device="cuda")
+                fluid_net_init(self.net_cfg, self.params)
+                nbytes = lambda b, tr: fluid_net_workspace_bytes(self.net_cfg, self.grid, b, tr)  # noqa: E731
+            else:
+                # the skip band may not exceed the grid
+                self.net_cfg = net_cfg or NetCfg(seed=seed, skip_modes=min(64, *self.shape))
+                self.params = torch.zeros(guess_net_param_bytes(self.net_cfg), dtype=torch.uint8,
+                                          device="cuda")
+                guess_net_init(self.net_cfg, self.params)
+                nbytes = lambda b, tr: guess_net_workspace_bytes(self.net_cfg, self.grid, b, tr)  # noqa: E731
+            self.ws_infer = workspace(nbytes(1, False))
+            self.ws_train = workspace(nbytes(batch, True))
             self.loss = torch.zeros(1, dtype=torch.float32, device="cuda")
             self.replay = ReplayBuffer(replay, seed)
 
@@ -209,9 +271,12 @@ class StreamSolver:
         if self.guess_kind == "prev" or self.t < self.warmup:
             self.x.copy_(self.u_prev)
             return "prev"
-        guess_net_infer(self.net_cfg, self.params, f.view(1, *self.shape),
-                        self.u_prev.view(1, *self.shape), self.x.view(1, *self.shape),
-                        self.ws_infer)
+        args = (f.view(1, *self.shape), self.u_prev.view(1, *self.shape),
+                self.x.view(1, *self.shape), self.ws_infer)
+        if self.network == "fluid":
+            fluid_net_infer(self.net_cfg, self.params, self.growth.blocks, *args)
+        else:
+            guess_net_infer(self.net_cfg, self.params, *args)
         return "learned"
 
     def step(self, f: torch.Tensor) -> StepRecord:
@@ -276,9 +341,13 @@ class StreamSolver:
         return self.retrain_steps
 
     def _train_on(self, batch) -> None:
-        guess_net_train_step(self.net_cfg, self.params, [b[0] for b in batch],
-                             [b[1] for b in batch], [b[2] for b in batch], self.ws_train,
-                             self.loss)
+        args = ([b[0] for b in batch], [b[1] for b in batch], [b[2] for b in batch],
+                self.ws_train, self.loss)
+        if self.network == "fluid":
+            fluid_net_train_step(self.net_cfg, self.params, self.growth.blocks, *args)
+            self.growth.observe(float(self.loss.item()))
+        else:
+            guess_net_train_step(self.net_cfg, self.params, *args)
 
     def train_step(self) -> None:
         self._train_on(self.replay.sample(self.batch))

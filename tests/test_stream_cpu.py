@@ -77,3 +77,33 @@ def test_collector_orthogonality_filter_and_retrain_trigger():
     assert c.candidates == [] and c.failures == 0
     # cosine is the absolute normalised inner product, 0 for a zero vector
     assert abs(cosine(e1, -2.0 * e1) - 1.0) < 1e-15 and cosine(e1, np.zeros(3)) == 0.0
+
+
+def test_block_growth_on_stagnation():
+    from paper_2103_10975_amd.stream import BlockGrowth
+    g = BlockGrowth(window=4, min_gain=0.1, max_blocks=2)
+    # falling fast: no growth
+    for v in [100, 90, 80, 70, 50, 45, 40, 35]:
+        assert not g.observe(v)
+    # window mean 40 vs previous 42.5: less than 10 % better -> grow
+    grown = [g.observe(v) for v in [41, 40, 40, 39]]
+    assert grown == [False, False, False, True] and g.blocks == 1 and g.events == [(12, 1)]
+    # the comparison restarts: the next window only sets the reference
+    assert not any(g.observe(v) for v in [40, 40, 40, 40])
+    for v in [40, 40, 40]:
+        assert not g.observe(v)
+    assert g.observe(40) and g.blocks == 2
+    # at the cap nothing more grows
+    for _ in range(3):
+        assert not any(g.observe(40) for _ in range(4))
+    assert g.blocks == 2
+
+
+def test_fluid_levels():
+    from paper_2103_10975_amd.stream import fluid_levels
+    assert fluid_levels((512, 512)) == 6
+    assert fluid_levels((256, 256)) == 6
+    assert fluid_levels((64, 64)) == 4       # 64 -> 8 at the coarsest
+    assert fluid_levels((96, 136)) == 4      # 136 = 8 * 17
+    assert fluid_levels((50, 64)) == 2       # 50 = 2 * 25
+    assert fluid_levels((7, 9)) == 1
