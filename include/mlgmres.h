@@ -360,6 +360,38 @@ int fluid_net_train_step(const fluid_net_cfg* cfg, void* params, int32_t blocks,
                          const double* const* u_prev, const double* const* u_target,
                          void* ws, size_t ws_bytes, float* loss, void* stream);
 
+/* ------------------------------------------------- linear model */
+
+/*
+ * The single-layer linear model of Section 3: x0 = T b with one dense
+ * n x n matrix T (n = points of the grid, 1..16384), the paper's simplified
+ * network for studying the spectrum of A T.  T is FP32, row-major over the
+ * grid's row-major points; products accumulate in FP64.
+ * Parameter buffer (device): T FP32 [n*n], then (256-byte aligned) the
+ * gradient of the last train step FP32 [n*n].
+ */
+size_t linear_guess_param_bytes(const mlg_grid* grid);
+
+/* Device workspace of a train step with `batch` (1..16) samples. */
+size_t linear_guess_workspace_bytes(const mlg_grid* grid, int32_t batch);
+
+/* T = 0 and gradient = 0 (the untrained model guesses zero). */
+int linear_guess_init(const mlg_grid* grid, void* params, void* stream);
+
+/* x0[i] = T b[i] for `batch` (1..16) samples, [batch][n] contiguous, FP64. */
+int linear_guess_infer(const mlg_grid* grid, const void* params, int32_t batch,
+                       const double* b, double* x0, void* stream);
+
+/*
+ * One gradient-descent step on L = (1/B) sum_i |T b_i - x_i|^2 (Section 2.3
+ * loss): T -= lr (2/B) sum_i (T b_i - x_i) b_i^T.  b, x: host arrays of
+ * `batch` device pointers to FP64 [n]; loss: device float (L before the
+ * step), may be NULL.
+ */
+int linear_guess_train_step(const mlg_grid* grid, void* params, float lr, int32_t batch,
+                            const double* const* b, const double* const* x, void* ws,
+                            size_t ws_bytes, float* loss, void* stream);
+
 /* ---------------------------------------------------------------- misc */
 const char* mlg_last_error(void);
 void mlg_shutdown(void);

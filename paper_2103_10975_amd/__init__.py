@@ -23,8 +23,9 @@ __all__ = [
     "guess_net_workspace_bytes", "guess_net_init", "guess_net_refresh", "guess_net_infer",
     "guess_net_train_step", "FluidCfg", "fluid_net_param_count", "fluid_net_param_offset",
     "fluid_net_param_bytes", "fluid_net_workspace_bytes", "fluid_net_init", "fluid_net_refresh",
-    "fluid_net_infer", "fluid_net_train_step", "mlg_last_error", "mlg_shutdown", "MlgError",
-    "EXPORTS",
+    "fluid_net_infer", "fluid_net_train_step", "linear_guess_param_bytes",
+    "linear_guess_workspace_bytes", "linear_guess_init", "linear_guess_infer",
+    "linear_guess_train_step", "mlg_last_error", "mlg_shutdown", "MlgError", "EXPORTS",
 ]
 
 HERE = os.path.dirname(os.path.abspath(__file__))
@@ -43,7 +44,9 @@ EXPORTS = (
     "guess_net_workspace_bytes", "guess_net_init", "guess_net_refresh", "guess_net_infer",
     "guess_net_train_step", "fluid_net_param_count", "fluid_net_param_offset",
     "fluid_net_param_bytes", "fluid_net_workspace_bytes", "fluid_net_init", "fluid_net_refresh",
-    "fluid_net_infer", "fluid_net_train_step", "mlg_last_error", "mlg_shutdown",
+    "fluid_net_infer", "fluid_net_train_step", "linear_guess_param_bytes",
+    "linear_guess_workspace_bytes", "linear_guess_init", "linear_guess_infer",
+    "linear_guess_train_step", "mlg_last_error", "mlg_shutdown",
 )
 
 
@@ -147,6 +150,12 @@ def _load():
                                            vp]),
         "fluid_net_train_step": (ctypes.c_int, [P(FluidCfg), vp, i32, P(Grid), i32, P(vp), P(vp),
                                                 P(vp), vp, sz, vp, vp]),
+        "linear_guess_param_bytes": (sz, [P(Grid)]),
+        "linear_guess_workspace_bytes": (sz, [P(Grid), i32]),
+        "linear_guess_init": (ctypes.c_int, [P(Grid), vp, vp]),
+        "linear_guess_infer": (ctypes.c_int, [P(Grid), vp, i32, vp, vp, vp]),
+        "linear_guess_train_step": (ctypes.c_int, [P(Grid), vp, ctypes.c_float, i32, P(vp), P(vp),
+                                                   vp, sz, vp, vp]),
         "mlg_last_error": (ctypes.c_char_p, []),
         "mlg_shutdown": (None, []),
     }
@@ -519,3 +528,53 @@ def fluid_unpack(cfg: FluidCfg, flat: torch.Tensor) -> dict:
         n = int(torch.tensor(shapes[name]).prod())
         out[name] = flat[off:off + n].reshape(shapes[name]).clone()
     return out
+
+
+# ------------------------------------------------------------------ linear model
+def linear_guess_param_bytes(grid: Grid) -> int:
+    n = lib.linear_guess_param_bytes(ctypes.byref(grid))
+    if n == 0:
+        raise MlgError(MLG_ERR_ARG, mlg_last_error())
+    return n
+
+
+def linear_guess_workspace_bytes(grid: Grid, batch: int) -> int:
+    n = lib.linear_guess_workspace_bytes(ctypes.byref(grid), batch)
+    if n == 0:
+        raise MlgError(MLG_ERR_ARG, mlg_last_error())
+    return n
+
+
+def linear_guess_init(grid: Grid, params: torch.Tensor, stream=None) -> None:
+    _check(lib.linear_guess_init(ctypes.byref(grid), _ptr(params, torch.uint8), _stream(stream)))
+
+
+def linear_guess_infer(grid: Grid, params: torch.Tensor, b: torch.Tensor, x0: torch.Tensor,
+                       stream=None) -> None:
+    """b, x0: float64 device tensors holding `batch` contiguous fields of the
+    grid's n points ([batch, n], [n] or grid-shaped with a leading batch axis)."""
+    n = grid.nx * grid.ny * (grid.nz if grid.dim == 3 else 1)
+    if b.numel() % n or x0.numel() != b.numel():
+        raise ValueError("b and x0 must hold the same whole number of grid fields")
+    batch = b.numel() // n
+    _check(lib.linear_guess_infer(ctypes.byref(grid), _ptr(params, torch.uint8), batch, _ptr(b),
+                                  _ptr(x0), _stream(stream)))
+
+
+def linear_guess_train_step(grid: Grid, params: torch.Tensor, lr: float, bs, xs, ws: torch.Tensor,
+                            loss: torch.Tensor | None = None, stream=None) -> None:
+    """bs, xs: lists of float64 device tensors of the grid's n points."""
+    batch = len(bs)
+    arr = lambda ts: (ctypes.c_void_p * batch)(*[_ptr(t) for t in ts])  # noqa: E731
+    lp = _ptr(loss, torch.float32) if loss is not None else None
+    _check(lib.linear_guess_train_step(ctypes.byref(grid), _ptr(params, torch.uint8), lr, batch,
+                                       arr(bs), arr(xs), _ptr(ws, torch.uint8), ws.numel(), lp,
+                                       _stream(stream)))
+
+
+def linear_views(grid: Grid, params: torch.Tensor) -> dict:
+    """T and its last gradient as [n, n] float32 views of a parameter buffer."""
+    half = linear_guess_param_bytes(grid) // 2
+    n = grid.nx * grid.ny * (grid.nz if grid.dim == 3 else 1)
+    return {"T": params[:n * n * 4].view(torch.float32).view(n, n),
+            "grad": params[half:half + n * n * 4].view(torch.float32).view(n, n)}

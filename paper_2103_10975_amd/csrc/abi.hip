@@ -4,6 +4,7 @@
 
 #include "engine.h"
 #include "net.h"
+#include "linear.h"
 #include "batched.h"
 
 namespace mlg {
@@ -253,6 +254,41 @@ int fluid_net_train_step(const fluid_net_cfg* cfg, void* params, int32_t blocks,
   return guarded([&] {
     return fluid_train_step(cfg, params, blocks, grid, batch, f, u_prev, u_target, ws, ws_bytes,
                             loss, (hipStream_t)stream);
+  });
+}
+
+size_t linear_guess_param_bytes(const mlg_grid* grid) {
+  size_t out = 0;
+  guarded([&] {
+    out = lin_param_bytes(grid);
+    return 0;
+  });
+  return out;
+}
+
+size_t linear_guess_workspace_bytes(const mlg_grid* grid, int32_t batch) {
+  size_t out = 0;
+  guarded([&] {
+    out = lin_workspace_bytes(grid, batch);
+    return 0;
+  });
+  return out;
+}
+
+int linear_guess_init(const mlg_grid* grid, void* params, void* stream) {
+  return guarded([&] { return lin_init(grid, params, (hipStream_t)stream); });
+}
+
+int linear_guess_infer(const mlg_grid* grid, const void* params, int32_t batch, const double* b,
+                       double* x0, void* stream) {
+  return guarded([&] { return lin_infer(grid, params, batch, b, x0, (hipStream_t)stream); });
+}
+
+int linear_guess_train_step(const mlg_grid* grid, void* params, float lr, int32_t batch,
+                            const double* const* b, const double* const* x, void* ws,
+                            size_t ws_bytes, float* loss, void* stream) {
+  return guarded([&] {
+    return lin_train_step(grid, params, lr, batch, b, x, ws, ws_bytes, loss, (hipStream_t)stream);
   });
 }
 

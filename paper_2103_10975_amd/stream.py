@@ -33,7 +33,9 @@ from . import (MLG_ERR_NONFINITE, MLG_FP32_IR, FluidCfg, MlgError, NetCfg, Opts,
                fluid_net_infer, fluid_net_init, fluid_net_param_bytes, fluid_net_train_step,
                fluid_net_workspace_bytes,
                gmres_workspace_bytes, guess_net_infer, guess_net_init, guess_net_param_bytes,
-               guess_net_train_step, guess_net_workspace_bytes, workspace)
+               guess_net_train_step, guess_net_workspace_bytes, linear_guess_infer,
+               linear_guess_init, linear_guess_param_bytes, linear_guess_train_step,
+               linear_guess_workspace_bytes, workspace)
 
 
 class ReplayBuffer:
@@ -187,7 +189,10 @@ class StepRecord:
 class StreamSolver:
     """Solve a stream of right-hand sides on one grid with a chosen guess policy.
 
-    guess: "zero", "prev" (u_{t-1}) or "learned" (network, trained in situ).
+    guess: "zero", "prev" (u_{t-1}), "learned" (network, trained in situ) or
+    "linear" (the single-layer model x0 = T f_t of Section 3, one
+    gradient-descent step of rate `lin_lr` per solved pair on the replay
+    buffer).
     network (learned guess): "spectral" (the guess_net network) or "fluid"
     (the multi-scale pooling-pyramid network, growing residual blocks by
     BlockGrowth up to `max_blocks`).
@@ -207,9 +212,11 @@ class StreamSolver:
                  policy: str = "replay", collect: int = 50, init_steps: int = 300,
                  retrain_steps: int = 32, p: int = 10, f_r: int = 8, cos_max: float = 0.999,
                  train_set: int = 512, network: str = "spectral", fluid_cfg: FluidCfg | None = None,
-                 max_blocks: int = 4, grow_window: int = 50, grow_min_gain: float = 0.05):
-        if guess not in ("zero", "prev", "learned"):
-            raise ValueError("guess must be zero, prev or learned")
+                 max_blocks: int = 4, grow_window: int = 50, grow_min_gain: float = 0.05,
+                 lin_lr: float = 0.1):
+        if guess not in ("zero", "prev", "learned", "linear"):
+            raise ValueError("guess must be zero, prev, learned or linear")
+        self.lin_lr = lin_lr
         if policy not in ("replay", "algorithm1"):
             raise ValueError("policy must be replay or algorithm1")
         if network not in ("spectral", "fluid"):
@@ -234,12 +241,20 @@ class StreamSolver:
             self.opts.tile = tile
         self.ws = workspace(gmres_workspace_bytes(self.grid, self.opts))
         self.warmup, self.batch = warmup, batch
-        self.train_enabled = train and guess == "learned"
+        self.train_enabled = train and guess in ("learned", "linear")
         self.time_train = time_train
         self.t = 0
         self.u_prev = torch.zeros(self.shape, dtype=torch.float64, device="cuda")
         self.x = torch.empty_like(self.u_prev)
         self.records: list[StepRecord] = []
+        if guess == "linear":
+            self.warmup = 1
+            self.params = torch.zeros(linear_guess_param_bytes(self.grid), dtype=torch.uint8,
+                                      device="cuda")
+            linear_guess_init(self.grid, self.params)
+            self.ws_train = workspace(linear_guess_workspace_bytes(self.grid, batch))
+            self.loss = torch.zeros(1, dtype=torch.float32, device="cuda")
+            self.replay = ReplayBuffer(replay, seed)
         if guess == "learned":
             if len(self.shape) != 2:
                 raise ValueError("the learned guess is defined on 2D grids")
@@ -271,6 +286,9 @@ class StreamSolver:
         if self.guess_kind == "prev" or self.t < self.warmup:
             self.x.copy_(self.u_prev)
             return "prev"
+        if self.guess_kind == "linear":
+            linear_guess_infer(self.grid, self.params, f.reshape(1, -1), self.x.view(1, -1))
+            return "linear"
         args = (f.view(1, *self.shape), self.u_prev.view(1, *self.shape),
                 self.x.view(1, *self.shape), self.ws_infer)
         if self.network == "fluid":
@@ -287,9 +305,9 @@ class StreamSolver:
         try:
             st = gmres_solve(self.grid, f, self.x, self.opts, self.ws)
         except MlgError as e:
-            if e.code != MLG_ERR_NONFINITE or kind != "learned":
+            if e.code != MLG_ERR_NONFINITE or kind not in ("learned", "linear"):
                 raise
-            kind = "learned->prev"
+            kind = kind + "->prev"
             self.x.copy_(self.u_prev)
             st = gmres_solve(self.grid, f, self.x, self.opts, self.ws)
         tos = time.perf_counter() - t0
@@ -341,6 +359,11 @@ class StreamSolver:
         return self.retrain_steps
 
     def _train_on(self, batch) -> None:
+        if self.guess_kind == "linear":
+            linear_guess_train_step(self.grid, self.params, self.lin_lr,
+                                    [b[0].reshape(-1) for b in batch],
+                                    [b[2].reshape(-1) for b in batch], self.ws_train, self.loss)
+            return
         args = ([b[0] for b in batch], [b[1] for b in batch], [b[2] for b in batch],
                 self.ws_train, self.loss)
         if self.network == "fluid":

@@ -3,5 +3,5 @@
 This package draws random numbers and evaluates the source fields the paper's
 benchmark uses; it holds none of the solver's or the network's arithmetic.
 """
-from .rhs import DriftingGaussians, RandomDipoles, grid_coords, system_sizes_batched  # noqa: F401
+from .rhs import DriftingGaussians, RandomBlob, RandomDipoles, grid_coords, system_sizes_batched  # noqa: F401
 from .params import fluid_net_params, guess_net_params  # noqa: F401

@@ -150,6 +150,32 @@ class RandomDipoles:
         return d["scale"] * out
 
 
+class RandomBlob:
+    """The linear-model workload of Section 3: one localized source moved at
+    random.  Step t draws its centre c ~ U[0.05, 0.95]^d from
+    ``default_rng([seed, t])`` (any step can be generated on its own), and
+    f_t = exp(-|x - c|^2 / (2 sigma^2)).  Layout as ``DriftingGaussians``."""
+
+    def __init__(self, shape, sigma: float, seed: int):
+        self.shape = tuple(int(s) for s in shape)
+        self.dim = len(self.shape)
+        if self.dim not in (2, 3):
+            raise ValueError("shape must have 2 or 3 axes")
+        self.sigma, self.seed = float(sigma), int(seed)
+
+    def centre(self, t: int) -> np.ndarray:
+        return np.random.default_rng([self.seed, int(t)]).uniform(0.05, 0.95, size=self.dim)
+
+    def field(self, t: int) -> np.ndarray:
+        c = self.centre(t)
+        axes = [grid_coords(n) for n in reversed(self.shape)]
+        inv = 1.0 / (2.0 * self.sigma ** 2)
+        f = [np.exp(-(ax - cc) ** 2 * inv) for ax, cc in zip(axes, c)]
+        if self.dim == 2:
+            return np.outer(f[1], f[0])
+        return f[2][:, None, None] * f[1][None, :, None] * f[0][None, None, :]
+
+
 def system_sizes_batched(seed: int, n2d: int = 64, n3d: int = 8):
     """Grid sides of the uneven batched workload: 2D sides drawn uniformly from
     {128, 192, 256, 384, 512, 768, 1024}, 3D sides uniformly from 64..128."""

@@ -86,3 +86,16 @@ def test_dipole_is_two_asymmetric_two_scale_poles():
         assert f[ip, jp] > 0 > f[im, jm]
         assert np.hypot(x[jp] - d["pos"][0], x[ip] - d["pos"][1]) < 0.03
         assert np.hypot(x[jm] - d["neg"][0], x[im] - d["neg"][1]) < 0.06
+
+
+def test_random_blob():
+    from synthetic import RandomBlob
+    g = RandomBlob((30, 30), 0.03, seed=3)
+    f = g.field(4)
+    c = g.centre(4)
+    x = np.arange(1, 31) / 31.0
+    X, Y = np.meshgrid(x, x)
+    assert np.allclose(f, np.exp(-((X - c[0]) ** 2 + (Y - c[1]) ** 2) / (2 * 0.03 ** 2)), rtol=1e-13)
+    assert np.array_equal(RandomBlob((30, 30), 0.03, seed=3).field(4), f)
+    cs = np.array([g.centre(t) for t in range(200)])
+    assert cs.min() >= 0.05 and cs.max() <= 0.95 and cs.std(axis=0).min() > 0.2
