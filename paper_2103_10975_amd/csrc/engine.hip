@@ -401,6 +401,7 @@ __global__ void k_setup(const SysInit* init, const SysDesc* sd, unsigned int* hd
   if (blockIdx.x == 0) {
     hdr[0] = 0u;
     hdr[1] = 0u;
+    hdr[2] = 0u;
   }
 }
 
@@ -607,26 +608,46 @@ int batched_solve(int nsys, const mlg_system* sys, const mlg_opts* opts, void* w
   // guards the host against a solver that stopped making progress.
   long long rhs_total = P.total_rhs;
   const long long max_groups = (limit + 2) * rhs_total / poll + 8;
-  int slot = 0, pending = -1;
-  bool done = false;
-  unsigned int last_progress = 0;
-  for (long long grp = 0; grp < max_groups && !done; ++grp) {
+  // Groups of `poll` cycles are launched one ahead of the group whose header
+  // the host reads, so the device never waits for the host -- except when the
+  // group read forecasts (header [2]) that the group in flight finishes every
+  // system: then the host waits for it before launching more, which saves a
+  // whole cycle of no-op kernels at the end of a solve, and costs one host
+  // round trip when the forecast was wrong.
+  int slot = 0, queue[2] = {0, 0}, nq = 0;
+  auto launch = [&]() {
     for (int c = 0; c < poll; ++c) MLG_HIP(hipGraphLaunch(exec, stream));
-    MLG_HIP(hipMemcpyAsync((void*)(host + 64 * slot), D.hdr, 8, hipMemcpyDeviceToHost, stream));
+    MLG_HIP(hipMemcpyAsync((void*)(host + 64 * slot), D.hdr, 12, hipMemcpyDeviceToHost, stream));
     MLG_HIP(hipEventRecord(ev[slot], stream));
-    if (pending >= 0) {
-      MLG_HIP(hipEventSynchronize(ev[pending]));
-      if (host[64 * pending] >= (unsigned)nsys) {
-        done = true;
-      } else {
-        const unsigned int prog = host[64 * pending + 1];
-        if (grp > 1 && prog == last_progress)
-          throw HipError{hipErrorUnknown, "solver made no progress in a restart cycle"};
-        last_progress = prog;
-      }
-    }
-    pending = slot;
+    queue[nq++] = slot;
     slot ^= 1;
+  };
+  bool forecast = false;
+  unsigned int last_progress = 0;
+  long long grp = 0, reads = 0;
+  launch();
+  ++grp;
+  while (true) {
+    if (!forecast && nq < 2 && grp < max_groups) {
+      launch();
+      ++grp;
+    }
+    const int p = queue[0];
+    queue[0] = queue[1];
+    --nq;
+    MLG_HIP(hipEventSynchronize(ev[p]));
+    const unsigned int fin = host[64 * p], prog = host[64 * p + 1], fc = host[64 * p + 2];
+    if (fin >= (unsigned)nsys) break;
+    if (reads > 0 && prog == last_progress)
+      throw HipError{hipErrorUnknown, "solver made no progress in a restart cycle"};
+    ++reads;
+    last_progress = prog;
+    forecast = fin + fc >= (unsigned)nsys;
+    if (nq == 0) {
+      if (grp >= max_groups) break;
+      launch();
+      ++grp;
+    }
   }
   MLG_HIP(hipMemcpyAsync((void*)host, D.hdr, 8, hipMemcpyDeviceToHost, stream));
   MLG_HIP(hipStreamSynchronize(stream));

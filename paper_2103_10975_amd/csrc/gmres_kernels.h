@@ -71,7 +71,9 @@ struct Ctrl {
   double* x0;           // solutions [nrhs][n]
   Summary* stats;       // this system's slots of the statistics array
   unsigned int* done;   // [0]: systems with every right-hand side solved,
-                        // [1]: progress count (Arnoldi columns + finished RHS)
+                        // [1]: progress count (Arnoldi columns + finished RHS),
+                        // [2]: systems forecast to finish in the next cycle
+                        //      (counted by this cycle's k_rsum<false>)
   // first-projection coefficients h_{j-1}: step j reads row j & 1 and writes
   // row (j + 1) & 1, so a launch may read and write them at once
   double hprev[2][kMaxRestart + 1];
@@ -449,6 +451,8 @@ template <bool INIT>
 __global__ __launch_bounds__(kReduceThreads) void k_rsum(const SysDesc* sd) {
   const SysDesc* S = sd + blockIdx.x;
   const gptr<Ctrl> C = gmem(S->C);
+  // k_rsum<true> opens every cycle: clear the cycle's forecast count
+  if (INIT && blockIdx.x == 0 && threadIdx.x == 0) C->done[2] = 0u;
   if (C->phase != (INIT ? PH_INIT : PH_RUN)) return;
   __shared__ double fin[2];
   reduce_partials(gmem((const double*)S->part), S->g.nblk, INIT ? 2 : 1, fin);
@@ -488,6 +492,7 @@ __global__ __launch_bounds__(kReduceThreads) void k_rsum(const SysDesc* sd) {
   const int cycles = C->s.cycles + 1;
   C->s.cycles = cycles;
   const double rr = beta / C->bnorm;
+  const double rr_prev = C->s.relres_true;     // at the start of this cycle
   C->s.relres_true = rr;
   if (cycles == 1) C->s.relres_first = rr;
   if (!isfinite(beta)) {
@@ -499,6 +504,11 @@ __global__ __launch_bounds__(kReduceThreads) void k_rsum(const SysDesc* sd) {
   if (conv || C->s.iters >= C->limit || beta == 0.0) {
     C->s.status = (conv || C->fixed || beta == 0.0) ? MLG_OK : MLG_NOT_CONVERGED;
     finish_rhs(C);
+  } else if (!C->fixed && C->rhs + 1 >= C->nrhs && rr * (rr / rr_prev) <= C->rtol) {
+    // forecast for the host's scheduling only: the last right-hand side, its
+    // residual extrapolated by this cycle's reduction factor, reaches the
+    // tolerance in the next cycle
+    atomicAdd(C->done + 2, 1u);
   }
 }
 
