@@ -850,22 +850,41 @@ __global__ void k_skip_basis(double* S, double* ST, int M, int n) {
   if (ST) ST[(size_t)j * M + k] = v;
 }
 
-// T[b][i][l] = sum_j Sx[l][j] x[b][i][j] / div[b]  (one thread per output;
-// SxT = the basis transposed, [j][l], so a wavefront's lanes read
-// consecutive basis values while the x value is a broadcast)
+// T[b][i][l] = sum_j Sx[l][j] x[b][i][j] / div[b]: one workgroup per row
+// (b, i); its four wavefronts take a quarter of the row each, lanes the modes
+// l (SxT = the basis transposed, [j][l], so lanes read consecutive basis
+// values while x is a broadcast), four independent sums per lane; the
+// quarters are added in a fixed order through LDS.
 template <class X>
-__global__ void k_skip_rows(const X* x, const double* div, const double* SxT, double* T, int B,
-                            int H, int W, int M) {
-  const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= (long long)B * H * M) return;
-  const int l = (int)(e % M);
-  const long long bi = e / M;
+__global__ __launch_bounds__(256) void k_skip_rows(const X* x, const double* div, const double* SxT,
+                                                   double* T, int B, int H, int W, int M) {
+  __shared__ double part[4][64];
+  const long long bi = blockIdx.x;
   const int b = (int)(bi / H);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const X* xr = x + bi * W;
-  double s = 0.0;
-#pragma unroll 8
-  for (int j = 0; j < W; ++j) s += SxT[(size_t)j * M + l] * (double)xr[j];
-  T[e] = div ? s / div[b] : s;
+  const int j0 = W * w / 4, j1 = W * (w + 1) / 4;
+  for (int l0 = 0; l0 < M; l0 += 64) {
+    const int l = l0 + lane;
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+    if (l < M) {
+      int j = j0;
+      for (; j + 4 <= j1; j += 4) {
+        s0 += SxT[(size_t)j * M + l] * (double)xr[j];
+        s1 += SxT[(size_t)(j + 1) * M + l] * (double)xr[j + 1];
+        s2 += SxT[(size_t)(j + 2) * M + l] * (double)xr[j + 2];
+        s3 += SxT[(size_t)(j + 3) * M + l] * (double)xr[j + 3];
+      }
+      for (; j < j1; ++j) s0 += SxT[(size_t)j * M + l] * (double)xr[j];
+    }
+    part[w][lane] = (s0 + s1) + (s2 + s3);
+    __syncthreads();
+    if (w == 0 && l < M) {
+      const double t = (part[0][lane] + part[1][lane]) + (part[2][lane] + part[3][lane]);
+      T[bi * M + l] = div ? t / div[b] : t;
+    }
+    __syncthreads();
+  }
 }
 
 // lambda_kl of the zero-Dirichlet 5-point Laplacian on the (k+1, l+1) sine mode
@@ -895,9 +914,17 @@ __global__ void k_skip_inv_cols(const double* Y, const double* Sy, double* Z, in
   const int l = (int)(e % M);
   const long long bi = e / M;
   const int i = (int)(bi % H), b = (int)(bi / H);
-  double s = 0.0;
-  for (int k = 0; k < M; ++k) s += Sy[(size_t)k * H + i] * Y[((size_t)b * M + k) * M + l];
-  Z[e] = alpha * s;
+  const double* Yb = Y + (size_t)b * M * M + l;
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+  int k = 0;
+  for (; k + 4 <= M; k += 4) {
+    s0 += Sy[(size_t)k * H + i] * Yb[(size_t)k * M];
+    s1 += Sy[(size_t)(k + 1) * H + i] * Yb[(size_t)(k + 1) * M];
+    s2 += Sy[(size_t)(k + 2) * H + i] * Yb[(size_t)(k + 2) * M];
+    s3 += Sy[(size_t)(k + 3) * H + i] * Yb[(size_t)(k + 3) * M];
+  }
+  for (; k < M; ++k) s0 += Sy[(size_t)k * H + i] * Yb[(size_t)k * M];
+  Z[e] = alpha * ((s0 + s1) + (s2 + s3));
 }
 
 // out[b][i][j] += beta sum_l Sx[l][j] Z[b][i][l]  (sum and add in FP64)
@@ -908,9 +935,16 @@ __global__ void k_skip_out(const double* Z, const double* Sx, float* out, int B,
   const int j = (int)(e % W);
   const long long bi = e / W;
   const double* zr = Z + bi * M;
-  double s = 0.0;
-  for (int l = 0; l < M; ++l) s += Sx[(size_t)l * W + j] * zr[l];
-  out[e] = (float)((double)out[e] + beta * s);
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+  int l = 0;
+  for (; l + 4 <= M; l += 4) {
+    s0 += Sx[(size_t)l * W + j] * zr[l];
+    s1 += Sx[(size_t)(l + 1) * W + j] * zr[l + 1];
+    s2 += Sx[(size_t)(l + 2) * W + j] * zr[l + 2];
+    s3 += Sx[(size_t)(l + 3) * W + j] * zr[l + 3];
+  }
+  for (; l < M; ++l) s0 += Sx[(size_t)l * W + j] * zr[l];
+  out[e] = (float)((double)out[e] + beta * ((s0 + s1) + (s2 + s3)));
 }
 
 // grad g_kl = rho (c_u / lambda_kl) sum_b dY[b][k][l] X[b][k][l]
@@ -1074,10 +1108,10 @@ void forward(const Net& n, const Ptrs& f, const Ptrs& u, hipStream_t s) {
   double* kSxT = n.w<double>(n.wl.kSxT);
   k_skip_basis<<<cdiv((long long)K * d.W, 256), 256, 0, s>>>(kSx, kSxT, K, d.W);
   k_skip_basis<<<cdiv((long long)K * d.H, 256), 256, 0, s>>>(kSy, nullptr, K, d.H);
-  k_skip_rows<double><<<cdiv((long long)d.B * d.H * K, 256), 256, 0, s>>>(r0, sv + d.B, kSxT, kT,
+  k_skip_rows<double><<<d.B * d.H, 256, 0, s>>>(r0, sv + d.B, kSxT, kT,
                                                                          d.B, d.H, d.W, K);
   k_cols<double><<<d.B * K * cdiv(K, 64), 256, 0, s>>>(kT, kSy, kX, d.B, d.H, K, K, 1.0);
-  k_skip_rows<float><<<cdiv((long long)d.B * d.H * K, 256), 256, 0, s>>>(out, nullptr, kSxT, kT,
+  k_skip_rows<float><<<d.B * d.H, 256, 0, s>>>(out, nullptr, kSxT, kT,
                                                                         d.B, d.H, d.W, K);
   k_cols<double><<<d.B * K * cdiv(K, 64), 256, 0, s>>>(kT, kSy, kC, d.B, d.H, K, K, 1.0);
   k_skip_gain<<<cdiv((long long)d.B * K * K, 256), 256, 0, s>>>(kX, kC, n.master(T_SKIP), kY, d.B,
@@ -1139,7 +1173,7 @@ void train(const Net& n, const Ptrs& f, const Ptrs& up, const Ptrs& ut, float* l
     double* kSy = n.w<double>(n.wl.kSy);
     const int K = d.K;
     const double nrm = (2.0 / (d.H + 1)) * (2.0 / (d.W + 1));
-    k_skip_rows<float><<<cdiv((long long)d.B * d.H * K, 256), 256, 0, s>>>(dout, nullptr, kSxT, kT,
+    k_skip_rows<float><<<d.B * d.H, 256, 0, s>>>(dout, nullptr, kSxT, kT,
                                                                           d.B, d.H, d.W, K);
     k_cols<double><<<d.B * K * cdiv(K, 64), 256, 0, s>>>(kT, kSy, kdY, d.B, d.H, K, K, nrm);
     k_skip_grad<<<cdiv((long long)K * K, 256), 256, 0, s>>>(kdY, n.w<double>(n.wl.kX),
