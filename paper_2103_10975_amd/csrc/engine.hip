@@ -14,19 +14,20 @@
 
 #include "batched.h"
 #include "engine.h"
-#include "gmres_kernels.h"
+#include "dispatch.h"
 
 namespace mlg {
 
 // ------------------------------------------------------------------ tiles
-// Tile shapes (points per workgroup; 256 threads each).  2D tiles are 32 to
-// 128 points wide so that a wavefront reads whole 128 B lines of every basis
-// vector; the narrow tall 32 x 8 tile has the smallest halo ring of the
-// one-point-per-thread tiles, which the fused Arnoldi step recomputes.
-static const TileDesc kTiles2[] = {{64, 16, 1}, {64, 8, 1}, {128, 8, 1}, {64, 4, 1}, {32, 8, 1}};
-static const TileDesc kTiles3[] = {{64, 2, 4}, {64, 2, 2}, {32, 4, 2}, {64, 4, 4}};
-static constexpr int kNumTiles2 = sizeof(kTiles2) / sizeof(kTiles2[0]);
-static constexpr int kNumTiles3 = sizeof(kTiles3) / sizeof(kTiles3[0]);
+template <int DIM, int IDX>
+constexpr TileDesc tile_of() {
+  using TL = typename TileOf<DIM, IDX>::type;
+  return TileDesc{TL::TX, TL::TY, TL::TZ};
+}
+static const TileDesc kTiles2[kNumTiles2] = {tile_of<2, 0>(), tile_of<2, 1>(), tile_of<2, 2>(),
+                                             tile_of<2, 3>(), tile_of<2, 4>()};
+static const TileDesc kTiles3[kNumTiles3] = {tile_of<3, 0>(), tile_of<3, 1>(), tile_of<3, 2>(),
+                                             tile_of<3, 3>()};
 
 int tile_count(int dim) { return dim == 3 ? kNumTiles3 : kNumTiles2; }
 TileDesc tile_desc(int dim, int idx) { return dim == 3 ? kTiles3[idx] : kTiles2[idx]; }
@@ -221,17 +222,6 @@ size_t workspace_bytes(int nsys, const mlg_system* sys, const mlg_opts* opts) {
 }
 
 // ------------------------------------------------------------------ dispatch
-// Sweeps keep the basis values of their points in registers, MM slots of
-// them; MM is the smallest of 8, 16, 24, 32, 40, 64 that covers the step, so
-// early steps of a cycle run at high occupancy.
-#define MLG_MM_SWITCH(N, EXPR_MM)                                   \
-  if ((N) <= 8) { constexpr int MM = 8; EXPR_MM; }                  \
-  else if ((N) <= 16) { constexpr int MM = 16; EXPR_MM; }           \
-  else if ((N) <= 24) { constexpr int MM = 24; EXPR_MM; }           \
-  else if ((N) <= 32) { constexpr int MM = 32; EXPR_MM; }           \
-  else if ((N) <= 40) { constexpr int MM = 40; EXPR_MM; }           \
-  else { constexpr int MM = 64; EXPR_MM; }
-
 // Partial blocks per lane for sums over at most maxblk workgroups.
 #define MLG_NB_SWITCH(MAXBLK, EXPR_NB)                              \
   if ((MAXBLK) <= 256) { constexpr int NB = 4; EXPR_NB; }           \
@@ -250,54 +240,13 @@ static void launch_sums(hipStream_t s, int count, const int* list, int maxblk, c
   MLG_NB_SWITCH(maxblk, (k_sums<NB><<<grid, kBlock, 0, s>>>(sd, list, j)));
 }
 
-// kind: 0 begin, 1 initial residual, 2 start, 3 dots(j), 4 extend(j),
-// 5 update (j = restart length m), 6 residual, 7 fused step(j), 8 fused step
-// in the split form (coefficients from sums(j)).
-template <class T, class TL>
-static void enqueue_group_step(hipStream_t s, int kind, int nb, const Job* jobs, const SysDesc* sd,
-                               int j) {
-  switch (kind) {
-    case 0: k_begin<TL><<<nb, kBlock, 0, s>>>(jobs, sd); break;
-    case 1: k_resid<TL, true><<<nb, kBlock, 0, s>>>(jobs, sd); break;
-    case 2: k_start<T, TL><<<nb, kBlock, 0, s>>>(jobs, sd); break;
-    case 3: MLG_MM_SWITCH(j, (k_dots<T, TL, MM><<<nb, kBlock, 0, s>>>(jobs, sd, j))); break;
-    case 4: MLG_MM_SWITCH(j, (k_extend<T, TL, MM><<<nb, kBlock, 0, s>>>(jobs, sd, j))); break;
-    case 5: MLG_MM_SWITCH(j, (k_update<T, TL, MM><<<nb, kBlock, 0, s>>>(jobs, sd))); break;
-    case 7: MLG_MM_SWITCH(j + 1, (k_step<T, TL, MM, false><<<nb, kBlock, 0, s>>>(jobs, sd, j))); break;
-    case 8: MLG_MM_SWITCH(j + 1, (k_step<T, TL, MM, true><<<nb, kBlock, 0, s>>>(jobs, sd, j))); break;
-    default: k_resid<TL, false><<<nb, kBlock, 0, s>>>(jobs, sd); break;
-  }
-}
-enum { G_BEGIN = 0, G_RESID0 = 1, G_START = 2, G_DOTS = 3, G_EXTEND = 4, G_UPDATE = 5, G_RESID = 6,
-       G_STEP = 7, G_SPLIT = 8 };
-
-using GroupFn = void (*)(hipStream_t, int, int, const Job*, const SysDesc*, int);
-
-template <class TL>
-static GroupFn pick_prec(int prec) {
-  return prec == MLG_FP64 ? &enqueue_group_step<double, TL> : &enqueue_group_step<float, TL>;
-}
-
-#define MLG_TILE_SWITCH(DIM, IDX, EXPR_TL)                      \
-  if (DIM == 2) {                                               \
-    switch (IDX) {                                              \
-      case 0: { using TL = TileT<2, 64, 16, 1>; EXPR_TL; }      \
-      case 1: { using TL = TileT<2, 64, 8, 1>; EXPR_TL; }       \
-      case 2: { using TL = TileT<2, 128, 8, 1>; EXPR_TL; }      \
-      case 3: { using TL = TileT<2, 64, 4, 1>; EXPR_TL; }       \
-      default: { using TL = TileT<2, 32, 8, 1>; EXPR_TL; }      \
-    }                                                           \
-  } else {                                                      \
-    switch (IDX) {                                              \
-      case 0: { using TL = TileT<3, 64, 2, 4>; EXPR_TL; }       \
-      case 1: { using TL = TileT<3, 64, 2, 2>; EXPR_TL; }       \
-      case 2: { using TL = TileT<3, 32, 4, 2>; EXPR_TL; }       \
-      default: { using TL = TileT<3, 64, 4, 4>; EXPR_TL; }      \
-    }                                                           \
-  }
-
-static GroupFn group_fn(int dim, int tile, int prec) {
-  MLG_TILE_SWITCH(dim, tile, return pick_prec<TL>(prec));
+GroupFn group_fn(int dim, int tile, int prec) {
+  const int p = prec == MLG_FP64 ? 0 : 1;
+#define MLG_SWEEP_PICK(P, D, T) \
+  if (p == P && dim == D && tile == T) return MLG_SWEEP_NAME(P, D, T)();
+  MLG_SWEEP_ALL(MLG_SWEEP_PICK)
+#undef MLG_SWEEP_PICK
+  throw ArgError{MLG_ERR_ARG, "no sweep kernels for this tile"};
 }
 
 struct DevPlan {                    // device pointers of a plan inside a workspace

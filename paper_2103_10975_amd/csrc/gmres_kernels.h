@@ -376,7 +376,7 @@ __device__ __forceinline__ void store_folded(const double (&acc)[MM / 8 + 1], do
 
 // begin: initial guess of a system that starts a right-hand side other than
 // its first (whose guess the caller provides): zero, or the previous solution.
-template <class TL>
+template <class T, class TL>
 __global__ __launch_bounds__(kBlock) void k_begin(const Job* jobs, const SysDesc* sd) {
   const Mine me = mine(jobs, sd);
   const gptr<const Ctrl> C = gmem((const Ctrl*)me.S->C);
@@ -397,7 +397,7 @@ __global__ __launch_bounds__(kBlock) void k_begin(const Job* jobs, const SysDesc
 }
 
 // r = b - A x: partials of |r|^2 and, when starting a right-hand side, |b|^2.
-template <class TL, bool INIT>
+template <class T, class TL, bool INIT>
 __global__ __launch_bounds__(kBlock) void k_resid(const Job* jobs, const SysDesc* sd) {
   const Mine me = mine(jobs, sd);
   const gptr<const Ctrl> C = gmem((const Ctrl*)me.S->C);
