@@ -19,10 +19,14 @@ design notes of the repository):
      sine modes (S = the DST-I basis sin(k pi i/(N+1)), k = 1..M), per-mode
      C x C channel mixing
   L4, L5 conv3x3 C->C + ReLU;  L6 conv3x3 C->1
-  skip     S^-1[rho g_kl (c_u / lambda_kl) S[r / s_r]_kl] on the K x K slowest
-           sine modes (the exact inverse of A there when rho g = 1)
-  out = L6 - P_K L6 + skip, P_K the orthogonal projection on the skip's K x K
-        modes: the skip path alone sets the output on its band, the
+  band     S^-1[w_kl S[r / s_r]_kl] on the K x K slowest sine modes (the
+           band; K = 0 switches it off): a linear spectral path whose
+           per-mode weights w are learned from the solver's pairs, as the
+           least-squares minimiser of the loss over those weights,
+           w_kl = sum X T / sum X^2 over the training samples seen (X, T the
+           band coefficients of the residual input and of the target)
+  out = L6 - P_K L6 + band, P_K the orthogonal projection on the K x K
+        modes: the band path alone sets the output there, the
         convolutional branch the rest
   guess = u_prev + (s_r / c_u) * out, c_u = 2 pi^2
 Convolutions are cross-correlations with zero padding (the Dirichlet zero),
@@ -36,7 +40,6 @@ import numpy as np
 from . import gmres as _gmres
 
 C_U = 2.0 * np.pi ** 2
-RHO = 32.0
 
 
 # ---------------------------------------------------------------- pieces
@@ -126,24 +129,22 @@ def spectral_backward(w1, wk, cache, dy):
     return dx, dw1, db, dwk
 
 
-def laplacian_modes(H: int, W: int, M: int) -> np.ndarray:
-    """lambda[k, l] of the zero-Dirichlet 5-point Laplacian (h = 1/(n+1)) on the
-    mode sin((k+1) pi y) sin((l+1) pi x), k, l < M (rows: y, columns: x)."""
-    k = np.arange(1, M + 1, dtype=np.float64)
-    ly = 4.0 * (H + 1) ** 2 * np.sin(k * np.pi / (2 * (H + 1))) ** 2
-    lx = 4.0 * (W + 1) ** 2 * np.sin(k * np.pi / (2 * (W + 1))) ** 2
-    return ly[:, None] + lx[None, :]
+def band_weights(sxt: np.ndarray, sxx: np.ndarray) -> np.ndarray:
+    """Per-mode band weights from the running sums: sxt / sxx, 0 where no
+    sample has touched the mode (sxx = 0)."""
+    safe = np.where(sxx > 0.0, sxx, 1.0)
+    return np.where(sxx > 0.0, sxt / safe, 0.0)
 
 
-def skip_forward(x_r: np.ndarray, g: np.ndarray):
-    """x_r [B, H, W] (residual channel), g [M, M] -> (out [B, H, W], X)."""
+def skip_forward(x_r: np.ndarray, w: np.ndarray):
+    """Band path.  x_r [B, H, W] (residual channel), w [K, K] -> (out [B, H, W], X)
+    with X [B, K, K] the band coefficients of x_r."""
     B, H, W = x_r.shape
-    M = g.shape[0]
-    Sy, Sx = sine_basis(H, M), sine_basis(W, M)
+    K = w.shape[0]
+    Sy, Sx = sine_basis(H, K), sine_basis(W, K)
     norm = (2.0 / (H + 1)) * (2.0 / (W + 1))
-    gain = RHO * g * C_U / laplacian_modes(H, W, M)
     X = np.einsum("ki,bij,lj->bkl", Sy, x_r, Sx, optimize=True)
-    out = norm * np.einsum("ki,bkl,lj->bij", Sy, gain[None] * X, Sx, optimize=True)
+    out = norm * np.einsum("ki,bkl,lj->bij", Sy, w[None] * X, Sx, optimize=True)
     return out, X
 
 
@@ -157,16 +158,29 @@ def band_project(y: np.ndarray, K: int) -> np.ndarray:
     return norm * np.einsum("ki,bkl,lj->bij", Sy, Y, Sx, optimize=True)
 
 
-def skip_backward(g: np.ndarray, X: np.ndarray, d_out: np.ndarray) -> np.ndarray:
-    B, H, W = d_out.shape
-    M = g.shape[0]
-    Sy, Sx = sine_basis(H, M), sine_basis(W, M)
-    norm = (2.0 / (H + 1)) * (2.0 / (W + 1))
-    dY = norm * np.einsum("ki,bij,lj->bkl", Sy, d_out, Sx, optimize=True)
-    return RHO * C_U / laplacian_modes(H, W, M) * np.sum(dY * X, axis=0)
+def band_stats(f: np.ndarray, u_prev: np.ndarray, u_target: np.ndarray, K: int):
+    """The per-mode sums a training batch adds to the band's least-squares
+    state: (sum_b X_b T_b, sum_b X_b^2) [K, K], X_b = S[r_b / s_b] the band
+    coefficients of the residual input and T_b = S[t_b] those of the target
+    t_b (both in the unnormalised sine basis; the band's share of the loss,
+    norm * sum_b sum_kl (w_kl X_b - T_b)^2, is minimal at w = sum X T /
+    sum X^2, mode by mode, since the orthonormal sine modes decouple)."""
+    x0, _, s = normalise(f, u_prev)
+    t = target(u_target, u_prev, s)
+    H, W = f.shape[1:]
+    Sy, Sx = sine_basis(H, K), sine_basis(W, K)
+    X = np.einsum("ki,bij,lj->bkl", Sy, x0[:, 0], Sx, optimize=True)
+    T = np.einsum("ki,bij,lj->bkl", Sy, t, Sx, optimize=True)
+    return np.sum(X * T, axis=0), np.sum(X * X, axis=0)
 
 
 # ---------------------------------------------------------------- network
+def band_modes(params: dict) -> int:
+    """K of the band path (0: no band path)."""
+    w = params.get("band.w")
+    return 0 if w is None else int(w.shape[0])
+
+
 def forward(params: dict, f: np.ndarray, u_prev: np.ndarray, keep: bool = False):
     """f, u_prev: [B, H, W] float64.  Returns (guess [B, H, W], out [B, H, W]
     in normalised units, s_in [B][, cache])."""
@@ -177,12 +191,15 @@ def forward(params: dict, f: np.ndarray, u_prev: np.ndarray, keep: bool = False)
     a3, sc = spectral_forward(a2, params["spec.w1"], params["spec.b"], params["spec.wk"])
     a4 = np.maximum(conv3x3(a3, params["conv4.w"], params["conv4.b"]), 0.0)
     a5 = np.maximum(conv3x3(a4, params["conv5.w"], params["conv5.b"]), 0.0)
-    skip, Xr = skip_forward(x0[:, 0], params["skip.g"])
     c6 = conv3x3(a5, params["conv6.w"], params["conv6.b"])[:, 0]
-    out = c6 - band_project(c6, params["skip.g"].shape[0]) + skip
+    K = band_modes(params)
+    out = c6
+    if K > 0:
+        band, _ = skip_forward(x0[:, 0], params["band.w"])
+        out = c6 - band_project(c6, K) + band
     guess = u_prev + (s_r / C_U)[:, None, None] * out
     if keep:
-        c.update(a1=a1, a2=a2, a3=a3, a4=a4, a5=a5, spec=sc, Xr=Xr)
+        c.update(a1=a1, a2=a2, a3=a3, a4=a4, a5=a5, spec=sc)
         return guess, out, s, c
     return guess, out, s
 
@@ -193,7 +210,8 @@ def target(u_target: np.ndarray, u_prev: np.ndarray, s: np.ndarray) -> np.ndarra
 
 
 def loss_and_grads(params: dict, f, u_prev, u_target):
-    """L = (1/B) sum_b |out_b - t_b|_2^2 and its gradient for every parameter."""
+    """L = (1/B) sum_b |out_b - t_b|_2^2 and its gradient for every parameter
+    trained by gradient (all but the band weights)."""
     B = f.shape[0]
     _, out, s, c = forward(params, f, u_prev, keep=True)
     t = target(u_target, u_prev, s)
@@ -201,9 +219,11 @@ def loss_and_grads(params: dict, f, u_prev, u_target):
     loss = float(np.sum(diff ** 2) / B)
     g = {}
     d6 = (2.0 / B) * diff[:, None]
-    g["skip.g"] = skip_backward(params["skip.g"], c["Xr"], d6[:, 0])
-    # the projection is symmetric: the conv branch sees the gradient off the band
-    d6 = d6 - band_project(d6[:, 0], params["skip.g"].shape[0])[:, None]
+    K = band_modes(params)
+    if K > 0:
+        # the projection is symmetric: the conv branch sees the gradient off
+        # the band (the band weights are fitted by band_stats, not by gradient)
+        d6 = d6 - band_project(d6[:, 0], K)[:, None]
     d5, g["conv6.w"], g["conv6.b"] = conv3x3_backward(c["a5"], params["conv6.w"], d6)
     d5 = d5 * (c["a5"] > 0.0)
     d4, g["conv5.w"], g["conv5.b"] = conv3x3_backward(c["a4"], params["conv5.w"], d5)

@@ -9,13 +9,12 @@ Tensor names and shapes (torch-style conv layout [out, in, ky, kx]):
     conv4.w [C, C, 3, 3]   conv4.b [C]
     conv5.w [C, C, 3, 3]   conv5.b [C]
     conv6.w [1, C, 3, 3]   conv6.b [1]
-    skip.g  [K, K]                          (per-mode gains of the spectral skip path)
+    band.w  [K, K]                          (per-mode weights of the band path; absent for K = 0)
 
 Weights are uniform in +-sqrt(6 / fan_in) (He-uniform); biases are drawn in
-+-0.1 when ``random_bias`` is set (tests) and are zero otherwise; the skip
-gains are uniform in [0, 2/32) (around the value 1/32 at which the path applies
-the exact inverse of A on its modes).  With ``zero_last`` the output layer and
-the skip gains start at zero, so the untrained network returns the previous
++-0.1 when ``random_bias`` is set (tests) and are zero otherwise; the band
+weights are uniform in [0, 1).  With ``zero_last`` the output layer and the
+band weights start at zero, so the untrained network returns the previous
 solution unchanged.
 """
 from __future__ import annotations
@@ -24,7 +23,7 @@ import numpy as np
 
 PARAM_ORDER = ("conv1.w", "conv1.b", "conv2.w", "conv2.b", "spec.w1", "spec.b",
                "spec.wk", "conv4.w", "conv4.b", "conv5.w", "conv5.b",
-               "conv6.w", "conv6.b", "skip.g")
+               "conv6.w", "conv6.b", "band.w")
 
 
 def param_shapes(channels: int = 32, modes: int = 16, skip_modes: int | None = None) -> dict:
@@ -38,7 +37,7 @@ def param_shapes(channels: int = 32, modes: int = 16, skip_modes: int | None = N
         "conv4.w": (C, C, 3, 3), "conv4.b": (C,),
         "conv5.w": (C, C, 3, 3), "conv5.b": (C,),
         "conv6.w": (1, C, 3, 3), "conv6.b": (1,),
-        "skip.g": (K, K),
+        "band.w": (K, K),
     }
 
 
@@ -49,12 +48,14 @@ def guess_net_params(seed: int, channels: int = 32, modes: int = 16,
     out = {}
     for name in PARAM_ORDER:
         shape = param_shapes(channels, modes, skip_modes)[name]
+        if name == "band.w" and shape[0] == 0:
+            continue
         if name.endswith(".b"):
             out[name] = (rng.uniform(-0.1, 0.1, size=shape) if random_bias
                          else np.zeros(shape))
             continue
-        if name == "skip.g":
-            out[name] = rng.uniform(0.0, 2.0 / 32.0, size=shape)
+        if name == "band.w":
+            out[name] = rng.uniform(0.0, 1.0, size=shape)
             continue
         if name == "spec.wk":
             fan_in = 2 * shape[3]
@@ -67,7 +68,8 @@ def guess_net_params(seed: int, channels: int = 32, modes: int = 16,
     if zero_last:
         out["conv6.w"] = np.zeros_like(out["conv6.w"])
         out["conv6.b"] = np.zeros_like(out["conv6.b"])
-        out["skip.g"] = np.zeros_like(out["skip.g"])
+        if "band.w" in out:
+            out["band.w"] = np.zeros_like(out["band.w"])
     return out
 
 

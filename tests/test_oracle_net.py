@@ -3,7 +3,10 @@
 Checked against: a brute-force direct sum for the convolution and torch's CPU
 conv2d in float64, SciPy's DST-I for the sine basis, the closed-form inverse
 of the Dirichlet Laplacian on the retained modes, central finite differences
-for every gradient, the Adam closed form after one step and torch's CPU Adam.
+for every gradient, the Adam closed form after one step and torch's CPU Adam;
+the band's least-squares fit against the closed-form eigenvalues of A (one
+consistent pair from a dense solve) and against brute-force perturbation of
+the loss it minimises.
 """
 import numpy as np
 import pytest
@@ -13,6 +16,15 @@ import torch
 from oracle import gmres as og
 from oracle import net
 from synthetic import DriftingGaussians, guess_net_params
+
+
+def laplacian_modes(H, W, K):
+    """lambda[k, l] of the zero-Dirichlet 5-point Laplacian (h = 1/(n+1)) on
+    the mode sin((k+1) pi y) sin((l+1) pi x), k, l < K (closed form)."""
+    k = np.arange(1, K + 1, dtype=np.float64)
+    ly = 4.0 * (H + 1) ** 2 * np.sin(k * np.pi / (2 * (H + 1))) ** 2
+    lx = 4.0 * (W + 1) ** 2 * np.sin(k * np.pi / (2 * (W + 1))) ** 2
+    return ly[:, None] + lx[None, :]
 
 
 def small_params(C=4, M=3, seed=0, K=None):
@@ -118,15 +130,15 @@ def test_input_is_residual_of_previous_solution():
         assert abs(s_r[b] - np.sqrt(np.mean(r ** 2))) <= 1e-12 * s_r[b]
 
 
-def test_skip_path_is_the_truncated_inverse():
-    """With the convolutional output switched off and every skip gain at 1/RHO,
-    the correction d = guess - u_prev solves A d = P r exactly, P the
+def test_band_path_is_the_truncated_inverse():
+    """With the convolutional output switched off and the band weights at
+    c_u / lambda_kl, the correction d = guess - u_prev solves A d = P r exactly, P the
     projection on the retained sine modes and r = f - A u_prev (checked
     against the sparse Kronecker-sum Laplacian and an explicit projection)."""
     from test_oracle_gmres import sparse_laplacian
     H, W, M = 21, 17, 6
     p = guess_net_params(7, channels=4, modes=M, zero_last=True)
-    p["skip.g"] = np.full((M, M), 1.0 / net.RHO)
+    p["band.w"] = net.C_U / laplacian_modes(H, W, M)
     rng = np.random.default_rng(11)
     f = rng.standard_normal((2, H, W))
     u = rng.standard_normal((2, H, W))
@@ -141,21 +153,21 @@ def test_skip_path_is_the_truncated_inverse():
         d = (g[b] - u[b]).ravel()
         assert np.allclose(A @ d, Pr.ravel(), rtol=0, atol=1e-9 * np.abs(Pr).max())
     # the eigenvalues used are those of A
-    lam = net.laplacian_modes(H, W, M)
+    lam = laplacian_modes(H, W, M)
     phi = np.outer(np.sin(3 * np.pi * np.arange(1, H + 1) / (H + 1)),
                    np.sin(5 * np.pi * np.arange(1, W + 1) / (W + 1)))
     assert np.allclose((A @ phi.ravel()).reshape(H, W), lam[2, 4] * phi, atol=1e-9 * lam[2, 4])
 
 
-def test_guess_is_exact_on_the_skip_band_whatever_the_convolutions():
-    """With every skip gain at 1/RHO and random (nonzero) convolutions, the
+def test_guess_is_exact_on_the_band_whatever_the_convolutions():
+    """With the band weights at c_u / lambda_kl and random (nonzero) convolutions, the
     correction d = guess - u_prev agrees with the exact correction A^-1 r
     (dense LU solve) on the K x K skip band, and the convolutional branch
     still acts off the band."""
     from test_oracle_gmres import sparse_laplacian
     H, W, M, K = 13, 11, 3, 5
     p = guess_net_params(9, channels=4, modes=M, skip_modes=K)
-    p["skip.g"] = np.full((K, K), 1.0 / net.RHO)
+    p["band.w"] = net.C_U / laplacian_modes(H, W, K)
     rng = np.random.default_rng(21)
     f = rng.standard_normal((2, H, W))
     u = rng.standard_normal((2, H, W))
@@ -196,8 +208,9 @@ def test_gradients_match_finite_differences(seed):
     u = rng.standard_normal((B, H, W)) * 0.05
     ut = u + rng.standard_normal((B, H, W)) * 0.05
     L, g = net.loss_and_grads(p, f, u, ut)
+    assert set(g) == set(p) - {"band.w"}
     eps = 1e-6
-    for name in p:
+    for name in g:
         d = rng.standard_normal(p[name].shape)
         pp = {k: v.copy() for k, v in p.items()}
         pm = {k: v.copy() for k, v in p.items()}
@@ -237,18 +250,83 @@ def test_gradients_match_torch_autograd():
     Ky = torch.tensor(np.sin(np.arange(1, K + 1)[:, None] * np.pi * np.arange(1, H + 1)[None] / (H + 1)))
     Kx = torch.tensor(np.sin(np.arange(1, K + 1)[:, None] * np.pi * np.arange(1, W + 1)[None] / (W + 1)))
     nrm = (2.0 / (H + 1)) * (2.0 / (W + 1))
-    kk = np.arange(1, K + 1)
-    lam = torch.tensor((4.0 * (H + 1) ** 2 * np.sin(kk * np.pi / (2 * (H + 1))) ** 2)[:, None]
-                       + (4.0 * (W + 1) ** 2 * np.sin(kk * np.pi / (2 * (W + 1))) ** 2)[None, :])
     Xr = Ky @ x[:, 0] @ Kx.T
-    out = c6 - nrm * (Ky.T @ (Ky @ c6 @ Kx.T) @ Kx) + nrm * (
-        Ky.T @ (32.0 * T["skip.g"] * (2 * np.pi ** 2) / lam * Xr) @ Kx)
+    out = c6 - nrm * (Ky.T @ (Ky @ c6 @ Kx.T) @ Kx) + nrm * (Ky.T @ (T["band.w"] * Xr) @ Kx)
     t = torch.tensor(net.target(ut, u, s))
     Lt = ((out - t) ** 2).sum() / B
     Lt.backward()
     assert abs(Lt.item() - L) <= 1e-12 * L
-    for k in p:
+    for k in g:
         assert np.allclose(T[k].grad.numpy(), g[k], rtol=1e-9, atol=1e-12 * np.abs(g[k]).max()), k
+
+
+def test_without_band_the_output_is_the_last_convolution():
+    """K = 0 (no band path): out is the L6 convolution itself, so the guess is
+    u_prev + (s_r / c_u) L6(a5) with nothing projected."""
+    p = guess_net_params(13, channels=4, modes=3, zero_last=False, skip_modes=0)
+    assert "band.w" not in p
+    rng = np.random.default_rng(23)
+    f = rng.standard_normal((2, 8, 10))
+    u = rng.standard_normal((2, 8, 10)) * 0.1
+    guess, out, s, c = net.forward(p, f, u, keep=True)
+    c6 = net.conv3x3(c["a5"], p["conv6.w"], p["conv6.b"])[:, 0]
+    assert np.array_equal(out, c6)
+    s_r = np.sqrt(np.mean((f - np.stack([og.apply(ub) for ub in u])) ** 2, axis=(1, 2)))
+    assert np.allclose(guess, u + (s_r / net.C_U)[:, None, None] * c6, rtol=1e-13, atol=1e-15)
+
+
+def test_band_fit_recovers_the_inverse_eigenvalues():
+    """One consistent pair (u_t = A^-1 f_t from a dense LU solve, u_prev
+    arbitrary): the least-squares band weights equal c_u / lambda_kl of the
+    closed form on every band mode, on a non-square grid (a transposed basis
+    or a scale taken from s_f instead of s_r would fail)."""
+    from test_oracle_gmres import sparse_laplacian
+    H, W, K = 19, 14, 6
+    A = sparse_laplacian((H, W)).toarray()
+    g = DriftingGaussians((H, W), 3, 0.08, seed=3)
+    f = g.field(2)[None]
+    u_prev = np.linalg.solve(A, g.field(1).ravel()).reshape(1, H, W)
+    u_t = np.linalg.solve(A, f[0].ravel()).reshape(1, H, W)
+    sxt, sxx = net.band_stats(f, u_prev, u_t, K)
+    w = net.band_weights(sxt, sxx)
+    expect = net.C_U / laplacian_modes(H, W, K)
+    assert np.all(sxx > 0)
+    assert np.allclose(w, expect, rtol=1e-9, atol=0)
+    # with those weights and no convolutional output, the guess is u_t on the band
+    p = guess_net_params(4, channels=4, modes=3, zero_last=True, skip_modes=K)
+    p["band.w"] = w
+    guess, _, _ = net.forward(p, f, u_prev)
+    Qy = net.sine_basis(H, K) * np.sqrt(2.0 / (H + 1))
+    Qx = net.sine_basis(W, K) * np.sqrt(2.0 / (W + 1))
+    on = Qy @ (guess[0] - u_t[0]) @ Qx.T
+    assert np.abs(on).max() <= 1e-9 * np.abs(Qy @ (u_t[0] - u_prev[0]) @ Qx.T).max()
+
+
+def test_band_fit_is_the_least_squares_minimiser():
+    """Inconsistent random pairs: with the convolutional output off, the loss
+    as a function of the band weights is minimal at the fitted weights (every
+    perturbation raises it; the central difference along random directions
+    vanishes)."""
+    H, W, K, B = 9, 12, 4, 3
+    rng = np.random.default_rng(17)
+    f = rng.standard_normal((B, H, W))
+    u = rng.standard_normal((B, H, W)) * 0.05
+    ut = u + rng.standard_normal((B, H, W)) * 0.05
+    p = guess_net_params(5, channels=4, modes=3, zero_last=True, skip_modes=K)
+    sxt, sxx = net.band_stats(f, u, ut, K)
+    p["band.w"] = net.band_weights(sxt, sxx)
+    L0, _ = net.loss_and_grads(p, f, u, ut)
+    L_zero, _ = net.loss_and_grads({**p, "band.w": np.zeros((K, K))}, f, u, ut)
+    assert L0 < L_zero
+    eps = 1e-4
+    for _ in range(5):
+        d = rng.standard_normal((K, K))
+        Lp, _ = net.loss_and_grads({**p, "band.w": p["band.w"] + eps * d}, f, u, ut)
+        Lm, _ = net.loss_and_grads({**p, "band.w": p["band.w"] - eps * d}, f, u, ut)
+        assert Lp > L0 and Lm > L0
+        # slope at the minimum vs the slope at w = 0 along the same direction
+        Lz, _ = net.loss_and_grads({**p, "band.w": eps * d}, f, u, ut)
+        assert abs(Lp - Lm) <= 1e-6 * abs(Lz - L_zero)
 
 
 def test_adam_first_step_closed_form_and_torch():
