@@ -12,7 +12,7 @@ LIB = os.path.join(HERE, "liboracle_gmres.so")
 def build(force: bool = True) -> str:
     if force or not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
         tmp = LIB + ".tmp"
-        subprocess.check_call(["gcc", "-O2", "-fPIC", "-shared", "-std=c99",
+        subprocess.check_call(["gcc", "-O2", "-fPIC", "-shared", "-std=c99", "-fopenmp",
                                "-fno-fast-math", "-ffp-contract=off",
                                "-o", tmp, SRC, "-lm"])
         os.replace(tmp, LIB)

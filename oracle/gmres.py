@@ -56,8 +56,16 @@ def lib():
         L.or_arnoldi.argtypes = [ctypes.c_int32, i64, i64, i64, dp, ctypes.c_int32,
                                  ctypes.c_int32, dp, dp]
         L.or_arnoldi.restype = ctypes.c_int32
+        L.or_set_threads.argtypes = [ctypes.c_int32]
+        L.or_set_threads.restype = None
+        L.or_set_threads(1)
         _lib = L
     return _lib
+
+
+def set_threads(n: int) -> None:
+    """OpenMP threads of the oracle's loops (results do not depend on it)."""
+    lib().or_set_threads(int(n))
 
 
 def _dims(shape):

@@ -22,8 +22,14 @@
  * Readings where the paper is silent (tolerance relative to |b|, stop on the
  * Givens estimate and accept on the true residual, breakdown threshold,
  * iteration = one Arnoldi step) are stated at the point of use.
+ *
+ * Threads (for timing the oracle on every core of a host): the operator and
+ * the vector updates split their loops over OpenMP threads; every dot
+ * product is the sequential sum of fixed 4096-element chunks, each summed
+ * in order, so the result does not depend on the thread count (bitwise).
  */
 #include <math.h>
+#include <omp.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -38,6 +44,12 @@ typedef struct {
     double relres_true;         /* final true relative residual */
 } or_stats;
 
+/* Threads used by the loops below (1 by default). */
+void or_set_threads(int32_t n)
+{
+    omp_set_num_threads(n > 0 ? n : 1);
+}
+
 /* (A u)_p = sum over axes of (2 u_p - u_{p-e} - u_{p+e}) / h_axis^2, u = 0
  * outside the interior.  Layout: index = (z*ny + y)*nx + x. */
 void or_apply(int32_t dim, int64_t nx, int64_t ny, int64_t nz,
@@ -47,6 +59,7 @@ void or_apply(int32_t dim, int64_t nx, int64_t ny, int64_t nz,
     double hz = 1.0 / (double)(nz + 1);
     double cx = 1.0 / (hx * hx), cy = 1.0 / (hy * hy), cz = 1.0 / (hz * hz);
     if (dim == 2) nz = 1;
+    #pragma omp parallel for collapse(2) schedule(static)
     for (int64_t z = 0; z < nz; ++z)
         for (int64_t y = 0; y < ny; ++y)
             for (int64_t x = 0; x < nx; ++x) {
@@ -66,10 +79,24 @@ void or_apply(int32_t dim, int64_t nx, int64_t ny, int64_t nz,
             }
 }
 
+/* sum_i a_i b_i: the chunks of 4096 elements are summed in order, then the
+ * chunk sums in order (the same result for any thread count). */
+#define OR_CHUNK 4096
 static double dot(int64_t n, const double *a, const double *b)
 {
+    int64_t nc = (n + OR_CHUNK - 1) / OR_CHUNK;
+    double part_small[64];
+    double *part = nc <= 64 ? part_small : (double *)malloc(sizeof(double) * (size_t)nc);
+    #pragma omp parallel for schedule(static)
+    for (int64_t c = 0; c < nc; ++c) {
+        int64_t i1 = (c + 1) * OR_CHUNK < n ? (c + 1) * OR_CHUNK : n;
+        double s = 0.0;
+        for (int64_t i = c * OR_CHUNK; i < i1; ++i) s += a[i] * b[i];
+        part[c] = s;
+    }
     double s = 0.0;
-    for (int64_t i = 0; i < n; ++i) s += a[i] * b[i];
+    for (int64_t c = 0; c < nc; ++c) s += part[c];
+    if (part != part_small) free(part);
     return s;
 }
 
@@ -105,6 +132,7 @@ static void orthogonalise(int ortho, int64_t n, int j, const double *V, double *
         for (int i = 0; i <= j; ++i) {
             const double *vi = V + (size_t)i * (size_t)n;
             double h = dot(n, vi, w);
+            #pragma omp parallel for schedule(static)
             for (int64_t p = 0; p < n; ++p) w[p] -= h * vi[p];
             hcol[i] = h;
         }
@@ -115,6 +143,7 @@ static void orthogonalise(int ortho, int64_t n, int j, const double *V, double *
         for (int i = 0; i <= j; ++i) tmp[i] = dot(n, V + (size_t)i * (size_t)n, w);
         for (int i = 0; i <= j; ++i) {
             const double *vi = V + (size_t)i * (size_t)n;
+            #pragma omp parallel for schedule(static)
             for (int64_t p = 0; p < n; ++p) w[p] -= tmp[i] * vi[p];
             hcol[i] += tmp[i];
         }
@@ -167,6 +196,7 @@ int32_t or_gmres(int32_t dim, int64_t nx, int64_t ny, int64_t nz,
     double *scratch = (double *)malloc(sizeof(double) * (size_t)(m + 1));
 
     or_apply(dim, nx, ny, nz, x, r);
+    #pragma omp parallel for schedule(static)
     for (int64_t i = 0; i < n; ++i) r[i] = b[i] - r[i];
     double beta = sqrt(dot(n, r, r));
     st->relres_init = beta / bnorm;
@@ -181,6 +211,7 @@ int32_t or_gmres(int32_t dim, int64_t nx, int64_t ny, int64_t nz,
     int64_t iters = 0;
 
     while (!converged && iters < limit && beta > 0.0) {
+        #pragma omp parallel for schedule(static)
         for (int64_t i = 0; i < n; ++i) V[i] = r[i] / beta;
         for (int i = 0; i <= m; ++i) g[i] = 0.0;
         g[0] = beta;
@@ -215,6 +246,7 @@ int32_t or_gmres(int32_t dim, int64_t nx, int64_t ny, int64_t nz,
             if (hist) hist[iters] = st->relres_est;
             if (iters >= limit || breakdown) break;
             if (!fixed && fabs(g[j + 1]) <= rtol * bnorm) break;
+            #pragma omp parallel for schedule(static)
             for (int64_t p = 0; p < n; ++p) V[(size_t)(j + 1) * nn + p] = w[p] / hnext;
         }
 
@@ -226,9 +258,11 @@ int32_t or_gmres(int32_t dim, int64_t nx, int64_t ny, int64_t nz,
         }
         for (int l = 0; l < k; ++l) {
             const double *vl = V + (size_t)l * nn;
+            #pragma omp parallel for schedule(static)
             for (int64_t p = 0; p < n; ++p) x[p] += y[l] * vl[p];
         }
         or_apply(dim, nx, ny, nz, x, r);
+        #pragma omp parallel for schedule(static)
         for (int64_t i = 0; i < n; ++i) r[i] = b[i] - r[i];
         beta = sqrt(dot(n, r, r));
         st->cycles += 1;

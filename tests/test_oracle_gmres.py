@@ -204,3 +204,19 @@ def test_edge_cases():
     # restart length 1 still converges (steepest-descent-like GMRES(1) on SPD)
     x1, st1 = og.gmres(DriftingGaussians((6, 6), 1, 0.2, seed=4).field(0), m=1, rtol=1e-8)
     assert st1.status == 0
+
+
+def test_thread_count_does_not_change_results():
+    """The oracle's OpenMP loops and fixed-chunk dot products give bitwise the
+    same GMRES trajectory with 1 and with several threads (2D and 3D)."""
+    from synthetic import DriftingGaussians
+    for shape in [(70, 90), (20, 24, 18)]:
+        b = DriftingGaussians(shape, 3, 0.05, seed=12).field(0)
+        out = []
+        for nt in (1, 4):
+            og.set_threads(nt)
+            x, st = og.gmres(b, m=20, fixed_iters=95)
+            out.append((x, st))
+        og.set_threads(1)
+        assert np.array_equal(out[0][0], out[1][0])
+        assert out[0][1] == out[1][1]
