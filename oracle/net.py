@@ -24,7 +24,8 @@ design notes of the repository):
            per-mode weights w are learned from the solver's pairs, as the
            least-squares minimiser of the loss over those weights,
            w_kl = sum X T / sum X^2 over the training samples seen (X, T the
-           band coefficients of the residual input and of the target)
+           band coefficients of the right-hand side the correction
+           u_t - u_prev solves exactly and of the target; see band_stats)
   out = L6 - P_K L6 + band, P_K the orthogonal projection on the K x K
         modes: the band path alone sets the output there, the
         convolutional branch the rest
@@ -160,16 +161,22 @@ def band_project(y: np.ndarray, K: int) -> np.ndarray:
 
 def band_stats(f: np.ndarray, u_prev: np.ndarray, u_target: np.ndarray, K: int):
     """The per-mode sums a training batch adds to the band's least-squares
-    state: (sum_b X_b T_b, sum_b X_b^2) [K, K], X_b = S[r_b / s_b] the band
-    coefficients of the residual input and T_b = S[t_b] those of the target
-    t_b (both in the unnormalised sine basis; the band's share of the loss,
-    norm * sum_b sum_kl (w_kl X_b - T_b)^2, is minimal at w = sum X T /
-    sum X^2, mode by mode, since the orthonormal sine modes decouple)."""
-    x0, _, s = normalise(f, u_prev)
+    state: (sum_b X_b T_b, sum_b X_b^2) [K, K].  The pair is made exact: the
+    solver's u_t solves A u_t = f_t - r_fin exactly (r_fin its final
+    residual), so the correction d = u_t - u_prev solves A d = r - r_fin,
+    r = f_t - A u_prev; X_b = S[A d_b / s_b] and T_b = S[t_b] are the band
+    coefficients of that right-hand side and of the target t_b = c_u d_b / s_b
+    (unnormalised sine basis, s_b the input scale of the sample).  The band's
+    share of the loss on these pairs, norm * sum_b sum_kl (w_kl X_b - T_b)^2,
+    is minimal at w = sum X T / sum X^2, mode by mode, since the orthonormal
+    sine modes decouple."""
+    _, _, s = normalise(f, u_prev)
+    d = u_target - u_prev
     t = target(u_target, u_prev, s)
+    ad = np.stack([_gmres.apply(db) for db in d]) / s[:, None, None]
     H, W = f.shape[1:]
     Sy, Sx = sine_basis(H, K), sine_basis(W, K)
-    X = np.einsum("ki,bij,lj->bkl", Sy, x0[:, 0], Sx, optimize=True)
+    X = np.einsum("ki,bij,lj->bkl", Sy, ad, Sx, optimize=True)
     T = np.einsum("ki,bij,lj->bkl", Sy, t, Sx, optimize=True)
     return np.sum(X * T, axis=0), np.sum(X * X, axis=0)
 

@@ -276,56 +276,73 @@ def test_without_band_the_output_is_the_last_convolution():
 
 
 def test_band_fit_recovers_the_inverse_eigenvalues():
-    """One consistent pair (u_t = A^-1 f_t from a dense LU solve, u_prev
-    arbitrary): the least-squares band weights equal c_u / lambda_kl of the
-    closed form on every band mode, on a non-square grid (a transposed basis
-    or a scale taken from s_f instead of s_r would fail)."""
-    from test_oracle_gmres import sparse_laplacian
+    """One pair from a loose solve (GMRES to 1e-4 only): since the fit pairs
+    the correction with the right-hand side it solves exactly, the
+    least-squares band weights equal c_u / lambda_kl of the closed form on
+    every band mode to rounding, on a non-square grid (a transposed basis, a
+    scale taken from s_f instead of s_r, or a fit on the residual input
+    instead -- 1e-4 off here -- would fail)."""
     H, W, K = 19, 14, 6
-    A = sparse_laplacian((H, W)).toarray()
     g = DriftingGaussians((H, W), 3, 0.08, seed=3)
     f = g.field(2)[None]
-    u_prev = np.linalg.solve(A, g.field(1).ravel()).reshape(1, H, W)
-    u_t = np.linalg.solve(A, f[0].ravel()).reshape(1, H, W)
+    u_prev = og.gmres(g.field(1), m=10, rtol=1e-4)[0][None]
+    u_t = og.gmres(f[0], u_prev[0], m=10, rtol=1e-4)[0][None]
     sxt, sxx = net.band_stats(f, u_prev, u_t, K)
     w = net.band_weights(sxt, sxx)
     expect = net.C_U / laplacian_modes(H, W, K)
     assert np.all(sxx > 0)
-    assert np.allclose(w, expect, rtol=1e-9, atol=0)
-    # with those weights and no convolutional output, the guess is u_t on the band
+    assert np.allclose(w, expect, rtol=1e-10, atol=0)
+    # the same fit on the network's own input (the residual of u_prev) is off
+    # by the loose solve's error
+    x0, _, s = net.normalise(f, u_prev)
+    Sy, Sx = net.sine_basis(H, K), net.sine_basis(W, K)
+    Xr = Sy @ x0[0, 0] @ Sx.T
+    Tt = Sy @ net.target(u_t, u_prev, s)[0] @ Sx.T
+    assert np.max(np.abs(Tt / Xr / expect - 1.0)) > 1e-6
+    # with the fitted weights and no convolutional output, the guess solves
+    # A d = r exactly on the band (dense LU)
+    from test_oracle_gmres import sparse_laplacian
+    A = sparse_laplacian((H, W)).toarray()
     p = guess_net_params(4, channels=4, modes=3, zero_last=True, skip_modes=K)
     p["band.w"] = w
     guess, _, _ = net.forward(p, f, u_prev)
+    r = f[0] - (A @ u_prev[0].ravel()).reshape(H, W)
+    d_exact = np.linalg.solve(A, r.ravel()).reshape(H, W)
     Qy = net.sine_basis(H, K) * np.sqrt(2.0 / (H + 1))
     Qx = net.sine_basis(W, K) * np.sqrt(2.0 / (W + 1))
-    on = Qy @ (guess[0] - u_t[0]) @ Qx.T
-    assert np.abs(on).max() <= 1e-9 * np.abs(Qy @ (u_t[0] - u_prev[0]) @ Qx.T).max()
+    on = Qy @ (guess[0] - u_prev[0] - d_exact) @ Qx.T
+    assert np.abs(on).max() <= 1e-10 * np.abs(Qy @ d_exact @ Qx.T).max()
 
 
 def test_band_fit_is_the_least_squares_minimiser():
-    """Inconsistent random pairs: with the convolutional output off, the loss
-    as a function of the band weights is minimal at the fitted weights (every
-    perturbation raises it; the central difference along random directions
-    vanishes)."""
+    """Random (inconsistent) pairs: the fitted weights minimise the band's
+    loss on the exact pairs -- the network loss with f = A u_t (so that the
+    residual input is A d exactly) and the convolutional output off: every
+    perturbation raises it and the central difference along random
+    directions vanishes."""
     H, W, K, B = 9, 12, 4, 3
     rng = np.random.default_rng(17)
-    f = rng.standard_normal((B, H, W))
     u = rng.standard_normal((B, H, W)) * 0.05
     ut = u + rng.standard_normal((B, H, W)) * 0.05
+    fe = np.stack([og.apply(ub) for ub in ut])            # r_fin = 0: the exact pair
+    sxt, sxx = net.band_stats(fe, u, ut, K)
     p = guess_net_params(5, channels=4, modes=3, zero_last=True, skip_modes=K)
-    sxt, sxx = net.band_stats(f, u, ut, K)
     p["band.w"] = net.band_weights(sxt, sxx)
-    L0, _ = net.loss_and_grads(p, f, u, ut)
-    L_zero, _ = net.loss_and_grads({**p, "band.w": np.zeros((K, K))}, f, u, ut)
+    # with one sample the fit does not depend on f (only on the pair A d, d)
+    f1 = fe[:1] + 1e-3 * rng.standard_normal((1, H, W))
+    w1 = net.band_weights(*net.band_stats(f1, u[:1], ut[:1], K))
+    assert np.allclose(w1, net.band_weights(*net.band_stats(fe[:1], u[:1], ut[:1], K)),
+                       rtol=1e-12, atol=0)
+    L0, _ = net.loss_and_grads(p, fe, u, ut)
+    L_zero, _ = net.loss_and_grads({**p, "band.w": np.zeros((K, K))}, fe, u, ut)
     assert L0 < L_zero
     eps = 1e-4
     for _ in range(5):
         d = rng.standard_normal((K, K))
-        Lp, _ = net.loss_and_grads({**p, "band.w": p["band.w"] + eps * d}, f, u, ut)
-        Lm, _ = net.loss_and_grads({**p, "band.w": p["band.w"] - eps * d}, f, u, ut)
+        Lp, _ = net.loss_and_grads({**p, "band.w": p["band.w"] + eps * d}, fe, u, ut)
+        Lm, _ = net.loss_and_grads({**p, "band.w": p["band.w"] - eps * d}, fe, u, ut)
         assert Lp > L0 and Lm > L0
-        # slope at the minimum vs the slope at w = 0 along the same direction
-        Lz, _ = net.loss_and_grads({**p, "band.w": eps * d}, f, u, ut)
+        Lz, _ = net.loss_and_grads({**p, "band.w": eps * d}, fe, u, ut)
         assert abs(Lp - Lm) <= 1e-6 * abs(Lz - L_zero)
 
 
