@@ -1,21 +1,33 @@
-"""Benchmark: time-to-solution per right-hand side, learned guess vs plain GMRES.
+"""Benchmark: time-to-solution per RHS, learned guess vs plain GMRES.
 
 Workload (one GPU): the 512 x 512 zero-Dirichlet Poisson stream with four
 drifting Gaussian sources (sigma 0.03), GMRES(30), relative residual 1e-8.
 One step = one time step of the in-situ method: network guess from
 (f_t, u_{t-1}) -> GMRES(30) with the FP32 Krylov basis and FP64 refinement ->
-one training step of the network on the replay buffer.  `--warmup` steps run
-first (they also train the network in situ: its spectral skip gains reach the
-exact inverse of A on their band after about 300 steps of the stream), then
-exactly `--steps` steps are timed.  The same right-hand sides are then solved
-by plain FP64 GMRES(30) from a zero guess (the comparison the metric names),
-and by FP64 GMRES from the previous solution.  Beside the timed window, the
-whole stream (learning phase included) is summarised: mean time to solution
-and iterations per RHS, and the training time.
+one training step of the network on the replay buffer (Fig. 2 of the paper).
+
+Phases of the stream (all on the same right-hand sides):
+  learn   `--learn` steps (default 400, whatever --warmup says): the in-situ
+          method from an untrained network; a shadow network trains on the
+          same batches (the configuration's network without a band path),
+          its guesses unused;
+  warmup  `--warmup` further untimed steps of the method;
+  timed   exactly `--steps` steps of the method, bracketed by synchronisation
+          (`value` = their mean time to solution per RHS; `ms_per_step` also
+          counts the method's own training step).
+The same timed right-hand sides are then solved from the same previous
+solutions by the comparison legs: plain FP64 GMRES from zero (the metric's
+baseline), FP64 and FP32-basis GMRES from u_{t-1}, the configuration's
+network without a band path (trained in situ by Adam on the same pairs), the
+learned network with its convolutional output switched off, and the band at
+its analytic optimum c_u / lambda_kl with nothing trained (what learning
+converges to).  Whole-stream totals (training included) are reported beside
+the timed window.
 
 Printed: one JSON line with the metric, the roofline of the dominant kernel
-(HIP-event timing of its launches in the solve's launch configuration) and
-the CPU oracle timed on a bounded sample on this host.
+(HIP-event timing of its launches in the solve's launch configuration), the
+same per-step rooflines at the large single-system sizes, and the CPU oracle
+timed on a bounded sample on this host (one thread and all threads).
 """
 from __future__ import annotations
 
@@ -23,6 +35,7 @@ import argparse
 import json
 import os
 import statistics
+import subprocess
 import sys
 import time
 
@@ -40,16 +53,19 @@ def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=400)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--learn", type=int, default=400,
+                    help="in-situ learning steps before the warm-up and the timed window")
     ap.add_argument("--grid", type=int, default=512)
     ap.add_argument("--restart", type=int, default=30)
     ap.add_argument("--rtol", type=float, default=1e-8)
     ap.add_argument("--seed", type=int, default=4000)
-    ap.add_argument("--cpu-seconds", type=float, default=15.0,
-                    help="budget of the CPU-oracle sample")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0,
+                    help="budget of each CPU-oracle sample")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--no-baseline", action="store_true", help="skip the plain-GMRES legs")
+    ap.add_argument("--no-baseline", action="store_true", help="skip the comparison legs")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched-systems leg")
+    ap.add_argument("--no-scale", action="store_true", help="skip the large-size rooflines")
     ap.add_argument("--batched-cycles", type=int, default=3,
                     help="restart cycles per system in the batched leg")
     ap.add_argument("--json-out", default=None)
@@ -58,14 +74,20 @@ def parse():
                          "calibration) then every launch of KERNEL (step, dots, extend, update, "
                          "resid) in one restart cycle, in the learned-guess solve's launch "
                          "configuration")
+    ap.add_argument("--probe-grid", default=None,
+                    help="with --probe: another workload, e.g. 1024x1024:fp64:30, "
+                         "2048x2048:fp32:40 or 160x160x160:fp32:40")
     return ap.parse_args()
 
 
 def kernel_roofline(mlg, shape, opts, b, tile, fused, split=0, reps=20, only=None):
     """Average launch duration of every solver kernel over one restart cycle,
     in the launch configuration of the solve (tuned tile and per-step sweep
-    schedule; HIP events on the stream), with the algorithmic bytes of each
-    launch."""
+    schedule; HIP events on the stream), with two byte counts per launch:
+    `bytes`, what the kernel itself must move (the fused sweep reads the basis
+    once), and `bytes_cgs2`, the CGS2 step's algorithmic bytes
+    (2(j+1) + 1) n s of step j -- two sweeps over v_0..v_j and one vector
+    written -- credited to the launch that completes the step."""
     grid = mlg.grid_of(shape)
     m = opts.restart_m
     fixed = mlg.Opts(restart_m=m, precision=opts.precision, rtol=opts.rtol, fixed_iters=m,
@@ -76,39 +98,91 @@ def kernel_roofline(mlg, shape, opts, b, tile, fused, split=0, reps=20, only=Non
     scratch = mlg.workspace(mlg.mlg_kernel_bench_scratch_bytes(reps))
     n = int(np.prod(shape))
     s = 8 if opts.precision == mlg.MLG_FP64 else 4
-    # the launches of one cycle: (kind, step index, algorithmic bytes)
-    launches = [(mlg.MLG_K_DOTS, 0, 1 * n * s)]           # w = A u_0 and |u_0|: read u_0
+    step = lambda j: (2 * (j + 1) + 1) * n * s             # noqa: E731
+    # the launches of one cycle: (kind, step index, bytes, CGS2 bytes)
+    launches = [(mlg.MLG_K_DOTS, 0, 1 * n * s, 0)]         # w = A u_0 and |u_0|: read u_0
     for j in range(m):
         if (split >> j) & 1:
             # sums over workgroups; the sweep forms the coefficients itself
-            launches.append((mlg.MLG_K_SUMS, j, 0))
-            launches.append((mlg.MLG_K_STEPC, j, (j + 3) * n * s))
+            launches.append((mlg.MLG_K_SUMS, j, 0, 0))
+            launches.append((mlg.MLG_K_STEPC, j, (j + 3) * n * s, step(j)))
         elif (fused >> j) & 1:
             # read v_0..v_{j-1}, u_j; write v_j, u_{j+1}
-            launches.append((mlg.MLG_K_COEF, j, 0))       # one-workgroup sums
-            launches.append((mlg.MLG_K_STEP, j, (j + 3) * n * s))
+            launches.append((mlg.MLG_K_COEF, j, 0, 0))     # one-workgroup sums
+            launches.append((mlg.MLG_K_STEP, j, (j + 3) * n * s, step(j)))
         else:
-            launches.append((mlg.MLG_K_COEF, j, 0))
-            launches.append((mlg.MLG_K_EXTEND, j, (j + 3) * n * s))
-            launches.append((mlg.MLG_K_DOTS, j + 1, (j + 2) * n * s))   # read v_0..v_j, u_{j+1}
-    launches.append((mlg.MLG_K_COEF, m, 0))
-    launches.append((mlg.MLG_K_UPDATE, m, m * n * s + 2 * n * 8))      # read V_m, read+write x
-    launches.append((mlg.MLG_K_RESIDUAL, m, 3 * n * 8))                # read x, b; write r
+            # separate sweeps: half of the step's CGS2 bytes to each
+            launches.append((mlg.MLG_K_COEF, j, 0, 0))
+            launches.append((mlg.MLG_K_EXTEND, j, (j + 3) * n * s, step(j) / 2))
+            launches.append((mlg.MLG_K_DOTS, j + 1, (j + 2) * n * s, step(j) / 2))  # read v_0..v_j, u_{j+1}
+    launches.append((mlg.MLG_K_COEF, m, 0, 0))
+    launches.append((mlg.MLG_K_UPDATE, m, m * n * s + 2 * n * 8, m * n * s + 2 * n * 8))
+    launches.append((mlg.MLG_K_RESIDUAL, m, 3 * n * 8, 3 * n * 8))   # read x, b; write r
     out = {}
-    for kind, j, byts in launches:
+    for kind, j, byts, cg in launches:
         name = mlg.KERNEL_NAMES[kind]
         if only is not None and name != only:
             continue
         us = mlg.mlg_kernel_bench(grid, fixed, ws, scratch, kind, j, reps)
-        d = out.setdefault(name, {"launches_per_cycle": 0, "us": [], "bytes": []})
+        d = out.setdefault(name, {"launches_per_cycle": 0, "us": [], "bytes": [], "cgs2": []})
         d["launches_per_cycle"] += 1
         d["us"].append(us)
         d["bytes"].append(byts)
+        d["cgs2"].append(cg)
     for d in out.values():
         d["avg_us"] = statistics.fmean(d["us"])
         d["avg_bytes"] = statistics.fmean(d["bytes"])
+        d["avg_cgs2"] = statistics.fmean(d["cgs2"])
         d["cycle_us"] = sum(d["us"])
     del ws, scratch
+    return out
+
+
+def roofline_of(kr):
+    """Dominant kernel (by time per cycle, among kernels that move data) and
+    the whole cycle: achieved GB/s on the CGS2 byte model and on the bytes
+    the kernels themselves move."""
+    dom = max((k for k in kr if kr[k]["avg_bytes"] > 0), key=lambda k: kr[k]["cycle_us"])
+    d = kr[dom]
+    us = sum(v["cycle_us"] for v in kr.values())
+    cg = sum(sum(v["cgs2"]) for v in kr.values())
+    own = sum(sum(v["bytes"]) for v in kr.values())
+    return {"kernel": dom, "avg_us": d["avg_us"],
+            "achieved": d["avg_cgs2"] / (d["avg_us"] * 1e-6) / 1e9,
+            "achieved_own_bytes": d["avg_bytes"] / (d["avg_us"] * 1e-6) / 1e9,
+            "cycle_us": us, "cycle_GBs_cgs2": cg / (us * 1e-6) / 1e9,
+            "cycle_GBs_own": own / (us * 1e-6) / 1e9}
+
+
+def scale_rooflines(mlg, seed):
+    """Per-step rooflines of one restart cycle at the large single-system
+    sizes, whose Krylov basis does not fit the 256 MB last-level cache:
+    1024^2 FP64 GMRES(30), 2048^2 and 160^3 FP32 basis GMRES(40), each in its
+    autotuned launch configuration, on a drifting-Gaussian right-hand side."""
+    from synthetic import DriftingGaussians
+    out = {}
+    for shape, prec, m, src, sigma in [((1024, 1024), mlg.MLG_FP64, 30, 5, 0.02),
+                                       ((2048, 2048), mlg.MLG_FP32_IR, 40, 5, 0.02),
+                                       ((160, 160, 160), mlg.MLG_FP32_IR, 40, 5, 0.03)]:
+        opts = mlg.Opts(restart_m=m, precision=prec, rtol=1e-10)
+        tile, fused, split = mlg.mlg_autotune(mlg.grid_of(shape), opts)
+        b = torch.from_numpy(DriftingGaussians(shape, src, sigma, seed=seed).field(0)).cuda()
+        kr = kernel_roofline(mlg, shape, opts, b, tile, fused, split, reps=10)
+        r = roofline_of(kr)
+        key = "x".join(map(str, shape)) + ("_fp64" if prec == mlg.MLG_FP64 else "_fp32") + f"_m{m}"
+        r.update({"frac": r["achieved"] / HBM_PEAK_GBS,
+                  "cycle_frac_cgs2": r["cycle_GBs_cgs2"] / HBM_PEAK_GBS,
+                  "cycle_frac_own": r["cycle_GBs_own"] / HBM_PEAK_GBS,
+                  "us_per_step": r["cycle_us"] / m,
+                  "tile": list(mlg.mlg_tile_shape(len(shape), tile - 1)),
+                  "fused_steps": bin(fused).count("1"), "split_steps": bin(split).count("1"),
+                  "kernels": {k: {"avg_us": v["avg_us"], "per_cycle": v["launches_per_cycle"],
+                                  "GB/s_own": (v["avg_bytes"] / v["avg_us"] / 1e3
+                                               if v["avg_us"] > 0 else 0.0)}
+                              for k, v in kr.items()}})
+        out[key] = r
+        del b
+        torch.cuda.empty_cache()
     return out
 
 
@@ -142,13 +216,13 @@ def batched_leg(mlg, seed, cycles, m=30):
     dt = time.perf_counter() - t0
     n = sum(int(np.prod(sh)) for sh in shapes)
     steps = cycles * m
-    # algorithmic bytes of one cycle per point (FP32 basis): the steps' sweeps
-    # (read j basis vectors and the direction, write two vectors) + update + residual
-    per_point = 4 * sum(j + 3 for j in range(m)) + (4 * m + 16) + 24
+    # algorithmic bytes of one cycle per point (FP32 basis), CGS2 model: the
+    # steps' two sweeps and one write, + update + residual
+    per_point = 4 * sum(2 * (j + 1) + 1 for j in range(m)) + (4 * m + 16) + 24
     return {"systems": len(shapes), "points": n, "steps_per_system": steps,
             "seconds": dt, "us_per_step": 1e6 * dt / steps,
             "point_steps_per_s": n * steps / dt,
-            "effective_GB/s": n * per_point * cycles / dt / 1e9,
+            "GBs_cgs2": n * per_point * cycles / dt / 1e9,
             "iters_ok": all(st.iters == steps for st in stats)}
 
 
@@ -158,7 +232,7 @@ def counter_traffic(kernel, shape, precision_tag, m, tile):
     (profiles/<kernel>_<H>x<W>_traffic.md), or None when there is none for this
     workload or the kernel sources changed since the counters were taken."""
     import hashlib
-    path = os.path.join(ROOT, "profiles", f"{kernel}_{shape[0]}x{shape[1]}_traffic.md")
+    path = os.path.join(ROOT, "profiles", f"{kernel}_{'x'.join(map(str, shape))}_traffic.md")
     if not os.path.exists(path):
         return None
     fields = {}
@@ -166,7 +240,7 @@ def counter_traffic(kernel, shape, precision_tag, m, tile):
         if ":" in line and not line.startswith(("|", "#", " ")):
             k, _, v = line.partition(":")
             fields[k.strip()] = v.strip()
-    if fields.get("workload_key") != f"{kernel} {shape[0]}x{shape[1]} {precision_tag} m{m}":
+    if fields.get("workload_key") != f"{kernel} {'x'.join(map(str, shape))} {precision_tag} m{m}":
         return None
     h = hashlib.sha256()
     for src in fields.get("kernel_sources", "").split():
@@ -178,24 +252,131 @@ def counter_traffic(kernel, shape, precision_tag, m, tile):
     return float(v) if v else None
 
 
-def cpu_baseline(shape, m, rtol, f0, plain_iters, budget_s):
-    """The FP64 CPU oracle (single thread) on a bounded sample: a fixed number
-    of Arnoldi steps on the first RHS, projected to the plain-GMRES iteration
-    count of the same RHS."""
+def host_cpu():
+    """CPU model, sockets and cores of this host (from lscpu)."""
+    info = {}
+    try:
+        txt = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        for line in txt.splitlines():
+            k, _, v = line.partition(":")
+            info[k.strip()] = v.strip()
+    except (OSError, subprocess.SubprocessError):
+        pass
+    sockets = int(info.get("Socket(s)", "0") or 0)
+    cps = int(info.get("Core(s) per socket", "0") or 0)
+    return {"model": info.get("Model name", "unknown"), "sockets": sockets,
+            "physical_cores": sockets * cps, "logical_cpus": os.cpu_count(),
+            "usable_cpus": len(os.sched_getaffinity(0))}
+
+
+def cpu_baseline(shape, m, f0, plain_iters, budget_s):
+    """The FP64 CPU oracle on a bounded sample: a fixed number of Arnoldi
+    steps of plain GMRES(m) on the first timed RHS, projected to the
+    plain-GMRES iteration count of the timed window; with one thread and with
+    every thread this process may use (OpenMP over grid rows; the results are
+    bitwise the same)."""
     from oracle import gmres as og
-    t0 = time.perf_counter()
-    og.gmres(f0, m=m, fixed_iters=m)                       # one cycle, to size the sample
-    per_cycle = time.perf_counter() - t0
-    cycles = max(1, int(budget_s / max(per_cycle, 1e-6)))
-    k = cycles * m
-    t0 = time.perf_counter()
-    og.gmres(f0, m=m, fixed_iters=k)
-    dt = time.perf_counter() - t0
-    per_iter = dt / k
-    return {"value": per_iter * plain_iters, "unit": "s/RHS", "cores": 1, "kind": "oracle",
-            "sample": f"{k} FP64 CGS2 GMRES({m}) Arnoldi steps of RHS 0 on {shape[0]}x{shape[1]} "
-                      f"({dt:.1f} s, {per_iter * 1e3:.2f} ms/step), projected to the "
-                      f"{plain_iters:.0f} steps plain GMRES needs per RHS"}
+    cpu = host_cpu()
+    threads = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or cpu["usable_cpus"]
+    runs = {}
+    for nt in sorted({1, threads}):
+        og.set_threads(nt)
+        t0 = time.perf_counter()
+        og.gmres(f0, m=m, fixed_iters=m)                   # one cycle, to size the sample
+        per_cycle = time.perf_counter() - t0
+        k = max(1, int(budget_s / max(per_cycle, 1e-6))) * m
+        t0 = time.perf_counter()
+        og.gmres(f0, m=m, fixed_iters=k)
+        dt = time.perf_counter() - t0
+        runs[nt] = {"steps": k, "seconds": dt, "ms_per_step": 1e3 * dt / k,
+                    "s_per_rhs": dt / k * plain_iters}
+    og.set_threads(1)
+    best = min(runs, key=lambda t: runs[t]["s_per_rhs"])
+    return {"value": runs[best]["s_per_rhs"], "unit": "s/RHS", "cores": best, "kind": "oracle",
+            "sample": f"FP64 CGS2 GMRES({m}) Arnoldi steps of the first timed RHS on "
+                      f"{'x'.join(map(str, shape))}, timed with "
+                      + " and ".join(f"{t} thread(s) ({r['steps']} steps, {r['seconds']:.1f} s, "
+                                     f"{r['ms_per_step']:.2f} ms/step)" for t, r in runs.items())
+                      + f", projected to the {plain_iters:.0f} steps plain GMRES needs per RHS",
+            "threads": {str(t): r for t, r in runs.items()}, "host": cpu}
+
+
+def legs_on_window(mlg, sv, fields, prevs, t0, args):
+    """The comparison legs on the timed right-hand sides, each started from the
+    same previous solution the learned run had."""
+    from paper_2103_10975_amd import stream as st
+    shape = sv.shape
+    grid = sv.grid
+    K = sv.net_cfg.skip_modes
+    fp32 = mlg.Opts(restart_m=args.restart, precision=mlg.MLG_FP32_IR, rtol=args.rtol)
+    fp64 = mlg.Opts(restart_m=args.restart, precision=mlg.MLG_FP64, rtol=args.rtol)
+    ws = {p: mlg.workspace(mlg.gmres_workspace_bytes(grid, o)) for p, o in
+          ((0, fp64), (1, fp32))}
+    # the band at its analytic optimum (c_u / lambda_kl of the 5-point
+    # Laplacian), convolutional output zero: nothing trained
+    ana_cfg = mlg.NetCfg(skip_modes=K, seed=args.seed)
+    ana = torch.zeros(mlg.guess_net_param_bytes(ana_cfg), dtype=torch.uint8, device="cuda")
+    mlg.guess_net_init(ana_cfg, ana)
+    H, W = shape
+    k = np.arange(1, K + 1, dtype=np.float64)
+    lam = (4.0 * (H + 1) ** 2 * np.sin(k * np.pi / (2 * (H + 1))) ** 2)[:, None] + \
+          (4.0 * (W + 1) ** 2 * np.sin(k * np.pi / (2 * (W + 1))) ** 2)[None, :]
+    mlg.net_set_band(ana_cfg, ana, 2.0 * np.pi ** 2 / lam)
+    ana_ws = mlg.workspace(mlg.guess_net_workspace_bytes(ana_cfg, grid, 1, False))
+    # the trained network with its convolutional output switched off
+    bo = sv.params.clone()
+    v = mlg.net_views(sv.net_cfg, bo)
+    for i in (11, 12):                                  # conv6.w, conv6.b
+        o0 = mlg.guess_net_param_offset(sv.net_cfg, i)
+        o1 = mlg.guess_net_param_offset(sv.net_cfg, i + 1)
+        v["master"][o0:o1].zero_()
+    mlg.guess_net_refresh(sv.net_cfg, bo)
+
+    def guess_fn(kind):
+        def f(t, up, x):
+            if kind == "zero":
+                x.zero_()
+            elif kind == "prev":
+                x.copy_(up)
+            elif kind == "config_net":
+                sv.shadow_guess(0, fields[t], up, x)
+            elif kind == "band_analytic":
+                mlg.guess_net_infer(ana_cfg, ana, fields[t].view(1, *shape), up.view(1, *shape),
+                                    x.view(1, *shape), ana_ws)
+            elif kind == "learned_band_only":
+                mlg.guess_net_infer(sv.net_cfg, bo, fields[t].view(1, *shape),
+                                    up.view(1, *shape), x.view(1, *shape), sv.ws_infer)
+        return f
+
+    legs = {}
+    x = torch.empty_like(prevs[0])
+    for name, kind, prec in [("plain_fp64_zero", "zero", 0), ("fp64_prev", "prev", 0),
+                             ("fp32_prev", "prev", 1), ("config_net_fp32", "config_net", 1),
+                             ("learned_band_only_fp32", "learned_band_only", 1),
+                             ("band_analytic_untrained_fp32", "band_analytic", 1)]:
+        g = guess_fn(kind)
+        recs = []
+        for i, up in enumerate(prevs):
+            t = t0 + i
+            torch.cuda.synchronize()
+            ts = time.perf_counter()
+            g(t, up, x)
+            stt = mlg.gmres_solve(grid, fields[t], x, fp64 if prec == 0 else fp32, ws[prec])
+            recs.append((time.perf_counter() - ts, stt))
+        legs[name] = leg_summary(recs)
+    return legs
+
+
+def leg_summary(recs):
+    tos = [r[0] for r in recs]
+    sts = [r[1] for r in recs]
+    return {"tos_mean": statistics.fmean(tos), "tos_median": statistics.median(tos),
+            "tos_p90": float(np.percentile(tos, 90)),
+            "iters_mean": statistics.fmean(s.iters for s in sts),
+            "relres_init_median": statistics.median(s.relres_init for s in sts),
+            "E_k_median": statistics.median(s.relres_first_cycle for s in sts),
+            "relres_iter5_median": statistics.median(s.relres_iter5 for s in sts),
+            "relres_true_max": max(s.relres_true for s in sts)}
 
 
 def main():
@@ -213,107 +394,124 @@ def main():
         probe(mlg, shape, args)
         return
     gen = DriftingGaussians(shape, 4, 0.03, seed=args.seed)
-    total = args.warmup + args.steps
+    t_warm, t_timed = args.learn, args.learn + args.warmup
+    total = t_timed + args.steps
     fields = [torch.from_numpy(gen.field(t)).cuda() for t in range(total)]
 
-    learned = StreamSolver(shape, guess="learned", restart_m=args.restart, rtol=args.rtol,
-                           precision=mlg.MLG_FP32_IR, seed=args.seed, time_train=False)
+    # the learned method, with the configuration's network without a band
+    # path as a shadow trained on the same batches
+    shadow = mlg.NetCfg(skip_modes=0, seed=args.seed)
+    sv = StreamSolver(shape, guess="learned", restart_m=args.restart, rtol=args.rtol,
+                      precision=mlg.MLG_FP32_IR, seed=args.seed, time_train=False,
+                      shadow_cfgs=[shadow])
     torch.cuda.synchronize()
     ts0 = time.perf_counter()
-    for t in range(args.warmup):
-        learned.step(fields[t])
+    for t in range(t_warm):
+        sv.step(fields[t])
     torch.cuda.synchronize()
-    stream_s = time.perf_counter() - ts0
+    learn_s = time.perf_counter() - ts0
+    sv.train_shadows = False                  # the shadows are frozen from here on
+    ts1 = time.perf_counter()
+    for t in range(t_warm, t_timed):
+        sv.step(fields[t])
+    torch.cuda.synchronize()
+    warm_s = time.perf_counter() - ts1
+    prevs = []
+    torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for t in range(args.warmup, total):
-        learned.step(fields[t])
+    for t in range(t_timed, total):
+        prevs.append(sv.u_prev.clone())
+        sv.step(fields[t])
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
-    timed = learned.records[args.warmup:]
+    timed = sv.records[t_timed:]
     tos_learned = statistics.fmean(r.tos for r in timed)
-    warm = learned.records[:args.warmup]
-    gains = mlg.net_unpack(learned.net_cfg, mlg.net_views(learned.net_cfg, learned.params)["master"])
-    # error of the trained skip gains against the exact inverse (rho g = 1):
-    # over the 16 x 16 slowest modes (where the sources put their content) and
-    # the median over the whole band (its fastest modes carry next to nothing
-    # and barely move from their initial zero)
-    gerr = (32.0 * gains["skip.g"] - 1.0).abs()
-    gain_err = {"max_16x16": float(gerr[:16, :16].max()), "median_band": float(gerr.median())}
-
+    learn = sv.records[:t_warm]
+    K = sv.net_cfg.skip_modes
+    w = mlg.net_band_weights(sv.net_cfg, sv.params).cpu().numpy()
+    H, W = shape
+    kk = np.arange(1, K + 1, dtype=np.float64)
+    lam = (4.0 * (H + 1) ** 2 * np.sin(kk * np.pi / (2 * (H + 1))) ** 2)[:, None] + \
+          (4.0 * (W + 1) ** 2 * np.sin(kk * np.pi / (2 * (W + 1))) ** 2)[None, :]
+    werr = np.abs(w * lam / (2.0 * np.pi ** 2) - 1.0)
+    stream_total_s = learn_s + warm_s + elapsed
+    solve_s = sum(r.tos for r in sv.records)
     result = {
         "metric": METRIC, "value": tos_learned, "unit": "s/RHS", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": 1e3 * elapsed / args.steps,
         "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f64 (f32 Krylov basis) + bf16 network",
-        "data": "synthetic",
+        "dtype": "f64 (f32 Krylov basis) + bf16 network", "data": "synthetic",
         "config": {"workload": f"2D 5-point Poisson {shape[0]}x{shape[1]}, 4 drifting Gaussian "
                                f"sources (sigma 0.03), GMRES({args.restart}), rtol {args.rtol}, "
-                               "learned guess + FP32-basis refinement vs plain FP64 GMRES",
+                               "in-situ learned guess + FP32-basis refinement vs plain FP64 GMRES",
                    "grid": list(shape), "restart_m": args.restart, "rtol": args.rtol,
-                   "seed": args.seed},
+                   "seed": args.seed, "learn_steps": args.learn, "band_modes": K,
+                   "timed_steps": [t_timed, total - 1]},
         "learned": {"tos_mean": tos_learned, "tos_median": statistics.median(r.tos for r in timed),
                     "tos_p90": float(np.percentile([r.tos for r in timed], 90)),
                     "iters_mean": statistics.fmean(r.iters for r in timed),
-                    "relres_init_mean": statistics.fmean(r.relres_init for r in timed),
-                    "E_k_mean": statistics.fmean(r.relres_first_cycle for r in timed),
+                    "relres_init_median": statistics.median(r.relres_init for r in timed),
+                    "E_k_median": statistics.median(r.relres_first_cycle for r in timed),
+                    "relres_iter5_median": statistics.median(r.relres_iter5 for r in timed),
                     "guess_kinds": sorted(set(r.guess for r in timed)),
-                    "skip_gain_error": gain_err},
-        # the in-situ learning phase before the timed window: every step
-        # solved (guess, GMRES) and trained once
-        "stream": {"steps": args.warmup, "seconds": stream_s,
-                   "tos_mean": statistics.fmean(r.tos for r in warm) if warm else None,
-                   "iters_mean": statistics.fmean(r.iters for r in warm) if warm else None,
-                   "train_s_per_step": ((stream_s - sum(r.tos for r in warm)) / len(warm)
-                                        if warm else None)},
+                    "band_weight_error_vs_analytic": {
+                        "max_16x16": float(werr[:16, :16].max()), "median_band": float(np.median(werr))}},
+        # the whole stream of the in-situ method, training included
+        "stream": {"steps": total, "seconds": stream_total_s,
+                   "solve_seconds": solve_s, "train_and_overhead_seconds": stream_total_s - solve_s,
+                   "tos_mean": solve_s / total,
+                   "iters_mean": statistics.fmean(r.iters for r in sv.records),
+                   "learn_phase": {"steps": args.learn, "seconds": learn_s,
+                                   "tos_mean": statistics.fmean(r.tos for r in learn),
+                                   "iters_mean": statistics.fmean(r.iters for r in learn)},
+                   "train_ms_per_step_timed": 1e3 * (elapsed - sum(r.tos for r in timed)) / args.steps},
     }
+    print(json.dumps({"progress": "timed window done", "value": tos_learned}), flush=True)
 
     if not args.no_baseline:
-        legs = {}
-        for name, guess, prec in [("plain_fp64_zero", "zero", mlg.MLG_FP64),
-                                  ("fp64_prev", "prev", mlg.MLG_FP64)]:
-            sv = StreamSolver(shape, guess=guess, restart_m=args.restart, rtol=args.rtol,
-                              precision=prec)
-            if guess == "prev":
-                sv.u_prev.copy_(_solution_before(fields, args, mlg))
-                sv.t = 1
-            for t in range(args.warmup, total):
-                sv.step(fields[t])
-            legs[name] = {"tos_mean": statistics.fmean(r.tos for r in sv.records),
-                          "iters_mean": statistics.fmean(r.iters for r in sv.records)}
-            del sv
-        result["baselines"] = legs
-        result["speedup_vs_plain"] = legs["plain_fp64_zero"]["tos_mean"] / tos_learned
+        legs = legs_on_window(mlg, sv, fields, prevs, t_timed, args)
+        result["legs"] = legs
+        result["speedup_vs_plain_fp64"] = legs["plain_fp64_zero"]["tos_mean"] / tos_learned
         result["speedup_vs_prev_fp64"] = legs["fp64_prev"]["tos_mean"] / tos_learned
+        result["speedup_vs_prev_fp32"] = legs["fp32_prev"]["tos_mean"] / tos_learned
+        result["iters_learned_over_prev_fp32"] = (result["learned"]["iters_mean"]
+                                                  / legs["fp32_prev"]["iters_mean"])
+        result["stream"]["plain_fp64_projected_seconds"] = legs["plain_fp64_zero"]["tos_mean"] * total
+        print(json.dumps({"progress": "legs done"}), flush=True)
 
     # roofline of the dominant kernel of the learned-guess solve
-    tile, fused, split = learned.tuned
+    tile, fused, split = sv.tuned
     tshape = mlg.mlg_tile_shape(2, tile - 1)
     result["config"]["tile"] = list(tshape)
     result["config"]["fused_steps"] = bin(fused).count("1")
     result["config"]["split_steps"] = bin(split).count("1")
-    kr = kernel_roofline(mlg, shape, learned.opts, fields[0], tile, fused, split)
-    dom = max((k for k in kr if kr[k]["avg_bytes"] > 0), key=lambda k: kr[k]["cycle_us"])
-    d = kr[dom]
-    achieved = d["avg_bytes"] / (d["avg_us"] * 1e-6) / 1e9
-    tag = "fp64" if learned.opts.precision == mlg.MLG_FP64 else "fp32"
-    result["roofline"] = {"kernel": dom, "bound": "hbm", "achieved": achieved,
-                          "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                          "traffic": counter_traffic(dom, shape, tag, args.restart,
+    kr = kernel_roofline(mlg, shape, sv.opts, fields[0], tile, fused, split)
+    r = roofline_of(kr)
+    tag = "fp64" if sv.opts.precision == mlg.MLG_FP64 else "fp32"
+    result["roofline"] = {"kernel": r["kernel"], "bound": "hbm", "achieved": r["achieved"],
+                          "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                          "frac": r["achieved"] / HBM_PEAK_GBS,
+                          "traffic": counter_traffic(r["kernel"], shape, tag, args.restart,
                                                      f"{tshape[0]}x{tshape[1]}"),
-                          "avg_us": d["avg_us"], "avg_bytes": d["avg_bytes"]}
+                          "bytes_model": "CGS2 (2(j+1)+1) n s per Arnoldi step",
+                          "achieved_own_bytes": r["achieved_own_bytes"],
+                          "avg_us": r["avg_us"], "cycle_us": r["cycle_us"],
+                          "cycle_frac_cgs2": r["cycle_GBs_cgs2"] / HBM_PEAK_GBS}
     result["kernels"] = {k: {"avg_us": v["avg_us"], "per_cycle": v["launches_per_cycle"],
-                             "GB/s": v["avg_bytes"] / v["avg_us"] / 1e3, "cycle_us": v["cycle_us"]}
-                         for k, v in kr.items()}
+                             "GB/s_own": v["avg_bytes"] / v["avg_us"] / 1e3 if v["avg_us"] else 0,
+                             "cycle_us": v["cycle_us"]} for k, v in kr.items()}
+    if not args.no_scale:
+        result["roofline_at_scale"] = scale_rooflines(mlg, args.seed)
+        print(json.dumps({"progress": "large-size rooflines done"}), flush=True)
 
     if not args.no_batched:
         result["batched"] = batched_leg(mlg, args.seed, args.batched_cycles)
 
     if not args.no_cpu:
-        plain_iters = (result.get("baselines", {}).get("plain_fp64_zero", {}).get("iters_mean")
+        plain_iters = (result.get("legs", {}).get("plain_fp64_zero", {}).get("iters_mean")
                        or result["learned"]["iters_mean"])
-        result["cpu_baseline"] = cpu_baseline(shape, args.restart, args.rtol,
-                                              fields[args.warmup].cpu().numpy(), plain_iters,
-                                              args.cpu_seconds)
+        result["cpu_baseline"] = cpu_baseline(shape, args.restart, fields[t_timed].cpu().numpy(),
+                                              plain_iters, args.cpu_seconds)
     line = json.dumps(result)
     print(line, flush=True)
     if args.json_out:
@@ -323,10 +521,11 @@ def main():
 
 def probe(mlg, shape, args):
     """Launches for hardware-counter runs (no timing is reported): a 256 MiB
-    device copy (the byte-count calibration), then for every tile shape one
-    restart cycle's launches of the probed kernel in the learned-guess solve's
-    configuration (fused steps in the split form for `step` and `sums`), each
-    step index once."""
+    device copy (the byte-count calibration), then one restart cycle's
+    launches of the probed kernel, each step index once.  On the benchmark's
+    workload: for every tile shape, in the learned-guess solve's configuration
+    (fused steps in the split form for `step` and `sums`).  With --probe-grid:
+    that workload in its autotuned configuration."""
     from synthetic import DriftingGaussians
     names = {v.replace("k_", ""): v for v in mlg.KERNEL_NAMES.values()}
     if args.probe not in names:
@@ -335,27 +534,30 @@ def probe(mlg, shape, args):
     for _ in range(3):
         a.clone()
     torch.cuda.synchronize()
+    if args.probe_grid:
+        dims, prec, m = args.probe_grid.split(":")
+        shape = tuple(int(v) for v in dims.split("x"))
+        opts = mlg.Opts(restart_m=int(m), rtol=1e-10,
+                        precision=mlg.MLG_FP64 if prec == "fp64" else mlg.MLG_FP32_IR)
+        tile, fused, split = mlg.mlg_autotune(mlg.grid_of(shape), opts)
+        runs = [(tile, fused, split)]
+    else:
+        opts = mlg.Opts(restart_m=args.restart, rtol=args.rtol, precision=mlg.MLG_FP32_IR)
+        fused = (1 << args.restart) - 1 if args.probe in ("step", "sums") else 0
+        runs = [(t, fused, fused) for t in range(1, mlg.mlg_tile_count(2) + 1)]
     f0 = torch.from_numpy(DriftingGaussians(shape, 4, 0.03, seed=args.seed).field(0)).cuda()
-    opts = mlg.Opts(restart_m=args.restart, rtol=args.rtol, precision=mlg.MLG_FP32_IR)
-    fused = (1 << args.restart) - 1 if args.probe in ("step", "sums") else 0
     out = {}
-    for tile in range(1, mlg.mlg_tile_count(2) + 1):
-        r = kernel_roofline(mlg, shape, opts, f0, tile, fused, fused, reps=1,
+    for tile, fused, split in runs:
+        r = kernel_roofline(mlg, shape, opts, f0, tile, fused, split, reps=1,
                             only=names[args.probe])
-        out["x".join(map(str, mlg.mlg_tile_shape(2, tile - 1)[:2]))] = r[names[args.probe]]["avg_bytes"]
+        ts = mlg.mlg_tile_shape(len(shape), tile - 1)
+        key = "x".join(map(str, ts[:len(shape)]))
+        out[key] = {"launches": r[names[args.probe]]["launches_per_cycle"],
+                    "avg_bytes": r[names[args.probe]]["avg_bytes"],
+                    "avg_cgs2": r[names[args.probe]]["avg_cgs2"]}
     torch.cuda.synchronize()
-    print(json.dumps({"probe": args.probe, "copy_bytes": 2 * a.numel() * 4, "avg_bytes": out}),
-          flush=True)
-
-
-def _solution_before(fields, args, mlg):
-    """u_{warmup-1} for the previous-solution leg: solved afresh in FP64."""
-    grid = mlg.grid_of(fields[0].shape)
-    opts = mlg.Opts(restart_m=args.restart, rtol=args.rtol)
-    ws = mlg.workspace(mlg.gmres_workspace_bytes(grid, opts))
-    x = torch.zeros_like(fields[0])
-    mlg.gmres_solve(grid, fields[args.warmup - 1], x, opts, ws)
-    return x
+    print(json.dumps({"probe": args.probe, "workload": "x".join(map(str, shape)),
+                      "copy_bytes": 2 * a.numel() * 4, "per_tile": out}), flush=True)
 
 
 if __name__ == "__main__":

@@ -102,6 +102,9 @@ typedef struct {
   double relres_est;           /* last Givens estimate / |b| */
   double relres_true;          /* final true relative residual (FP64) */
   double seconds;              /* host wall time of the call (TOS of Section 2.2) */
+  double relres_iter5;         /* Givens residual estimate / |b| after the 5th Arnoldi
+                                  step (after the last one if fewer were taken): the
+                                  fifth-iteration residual Section 3 judges guesses by */
 } mlg_stats;
 
 /* ---------------------------------------------------------------- solver */
@@ -222,21 +225,27 @@ int mlg_autotune(const mlg_grid* grid, const mlg_opts* opts, void* ws, size_t ws
  *   L3 spectral: ReLU(W1 x + b + S^-1[W_kl . S[x]_kl]) over the modes x modes
  *      slowest sine modes (S = DST-I basis), per-mode C x C mixing,
  *   L4, L5 conv3x3 C->C + ReLU, L6 conv3x3 C->1;
- *   spectral skip (FP64) over the skip_modes x skip_modes slowest sine modes
- *      (the skip band K): skip = S^-1[32 g_kl (c_u / lambda_kl) S[r/s_r]_kl],
- *      lambda_kl the eigenvalues of A (g = 1/32 applies the exact inverse of
- *      A on the band);
- *   out = L6 - P_K L6 + skip, P_K the orthogonal projection on the band: the
- *      skip alone sets the output on the band, the convolutions the rest;
+ *   band path (FP64, skip_modes = K > 0) over the K x K slowest sine modes:
+ *      band = S^-1[w_kl S[r/s_r]_kl] with per-mode weights w learned from the
+ *      training pairs by least squares (w = sxt / sxx, the running sums of
+ *      X T and X^2 that every train step extends; for the correction
+ *      d = u_target - u_prev, X and T are the band coefficients of A d / s_r
+ *      and of the target c_u d / s_r -- u_target solves A u = f - r_fin
+ *      exactly, so (A d, d) is an exact pair: the minimiser of the loss over
+ *      w on those pairs, which Adam could not reach at the precision GMRES
+ *      needs as the optimal weights span several orders of magnitude);
+ *   out = L6 - P_K L6 + band, P_K the orthogonal projection on the band: the
+ *      band path alone sets the output there, the convolutions the rest
+ *      (K = 0: out = L6, the network without a band path);
  *   guess = u_prev + (s_r / c_u) out  (= u_prev when u_prev solves A u = f).
  * Weights and activations are BF16 in the kernels with FP32 accumulation;
  * FP32 master weights and Adam moments (Section 2.3: back-propagation and
  * ADAM) live in the parameter buffer.
  */
 typedef struct {
-  int32_t channels;   /* C, 32; multiple of 16, <= 64 */
-  int32_t modes;      /* M, 16; <= 32 (the L3 spectral layer) */
-  int32_t skip_modes; /* K, 64; 1..128 (the skip band) */
+  int32_t channels;   /* C, 32 */
+  int32_t modes;      /* M, 16; 1..32 (the L3 spectral layer) */
+  int32_t skip_modes; /* K, 64; 0..128 (the band path; 0 = none) */
   float lr, beta1, beta2, eps;
   uint64_t seed;
 } guess_net_cfg;
@@ -247,14 +256,17 @@ typedef struct {
  *   grad    FP32 [P]   gradient of the last train step
  *   adam_m  FP32 [P], adam_v FP32 [P]
  *   bf16    BF16 [P]   working copy used by the kernels
- *   step    int64      Adam step counter
+ *   step    int64      Adam step counter (256 bytes reserved)
+ *   band    FP64 [2][K][K]  least-squares state of the band path: sxt
+ *                      ([ky][kx]) then sxx; w = sxt / sxx (0 where sxx = 0).
+ *                      A caller may write it directly (e.g. sxt = w,
+ *                      sxx = 1 to impose weights w).
  * Tensor order inside each FP32/BF16 array (shapes [out, in, ky, kx]):
  *   conv1.w [C,2,3,3] conv1.b [C] conv2.w [C,C,3,3] conv2.b [C]
  *   spec.w1 [C,C] spec.b [C] spec.wk [M,M,C,C] (= [ky, kx, out, in])
  *   conv4.w conv4.b conv5.w conv5.b (as conv2) conv6.w [1,C,3,3] conv6.b [1]
- *   skip.g [K,K] (= [ky, kx]; read from the FP32 master copy)
  * guess_net_param_count gives P; guess_net_param_offset the element offset
- * of tensor `index` (0..13 in the order above) inside one array.
+ * of tensor `index` (0..12 in the order above; 13 gives P) inside one array.
  */
 int64_t guess_net_param_count(const guess_net_cfg* cfg);
 int64_t guess_net_param_offset(const guess_net_cfg* cfg, int32_t index);
@@ -266,12 +278,13 @@ size_t guess_net_workspace_bytes(const guess_net_cfg* cfg, const mlg_grid* grid,
                                  int32_t batch, int32_t train);
 
 /* Deterministic initialisation from cfg->seed: He-uniform weights, zero
- * biases, zero output layer and skip gains (so the untrained network returns
- * u_prev), zero Adam state. */
+ * biases, zero output layer and an empty band state (w = 0), so the untrained
+ * network returns u_prev; zero Adam state. */
 int guess_net_init(const guess_net_cfg* cfg, void* params, void* stream);
 
 /* Recompute the BF16 working copy from the FP32 master weights (after the
- * caller wrote master weights directly) and zero the Adam state. */
+ * caller wrote master weights directly) and zero the Adam state; the band
+ * state is left as it is. */
 int guess_net_refresh(const guess_net_cfg* cfg, void* params, void* stream);
 
 /* guess[b] = N(f[b], u_prev[b]) for `batch` samples of one grid (FP64 in/out,
@@ -281,10 +294,14 @@ int guess_net_infer(const guess_net_cfg* cfg, const void* params, const mlg_grid
                     void* ws, size_t ws_bytes, void* stream);
 
 /*
- * One Adam step on L = (1/B) sum_b |out_b - t_b|^2 with out the L6 output and
- * t_b = c_u (u_target_b - u_prev_b) / s_b, s_b = s_r of the sample with 0
- * replaced by 1 (Section 2.3 loss, in the network's output units).  f, u_prev, u_target: host arrays of `batch` device pointers
- * (samples need not be contiguous).  loss: device float, may be NULL.
+ * One training step on L = (1/B) sum_b |out_b - t_b|^2 with out the network
+ * output and t_b = c_u (u_target_b - u_prev_b) / s_b, s_b = s_r of the sample
+ * with 0 replaced by 1 (Section 2.3 loss, in the network's output units): the
+ * loss at the current weights, then the band state takes the batch's sums
+ * (least squares), and every other weight one Adam step on its gradient
+ * (the convolutional branch sees the loss off the band).
+ * f, u_prev, u_target: host arrays of `batch` device pointers (samples need
+ * not be contiguous).  loss: device float, may be NULL.
  */
 int guess_net_train_step(const guess_net_cfg* cfg, void* params, const mlg_grid* grid,
                          int32_t batch, const double* const* f, const double* const* u_prev,

@@ -26,6 +26,7 @@ __all__ = [
     "fluid_net_infer", "fluid_net_train_step", "linear_guess_param_bytes",
     "linear_guess_workspace_bytes", "linear_guess_init", "linear_guess_infer",
     "linear_guess_train_step", "mlg_last_error", "mlg_shutdown", "MlgError", "EXPORTS",
+    "net_views", "net_pack", "net_unpack", "net_band_weights", "net_set_band",
 ]
 
 HERE = os.path.dirname(os.path.abspath(__file__))
@@ -77,7 +78,7 @@ class Stats(ctypes.Structure):
     _fields_ = [("status", ctypes.c_int32), ("cycles", ctypes.c_int32), ("iters", ctypes.c_int64),
                 ("relres_init", ctypes.c_double), ("relres_first_cycle", ctypes.c_double),
                 ("relres_est", ctypes.c_double), ("relres_true", ctypes.c_double),
-                ("seconds", ctypes.c_double)]
+                ("seconds", ctypes.c_double), ("relres_iter5", ctypes.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -202,6 +203,26 @@ def _ptr(t: torch.Tensor | None, dtype=torch.float64):
     return t.data_ptr()
 
 
+def _points(grid: Grid) -> int:
+    return grid.nx * grid.ny * (grid.nz if grid.dim == 3 else 1)
+
+
+def _need(cond: bool, msg: str) -> None:
+    if not cond:
+        raise ValueError(msg)
+
+
+def _same_fields(ts, shape, what: str) -> None:
+    for t in ts:
+        _need(tuple(t.shape) == tuple(shape), f"{what}: every field must have shape {tuple(shape)}, "
+                                              f"got {tuple(t.shape)}")
+
+
+def _params_ok(params: torch.Tensor, nbytes: int) -> None:
+    _need(params.numel() >= nbytes, f"parameter buffer holds {params.numel()} bytes, "
+                                    f"the configuration needs {nbytes}")
+
+
 def grid_of(shape) -> Grid:
     """Grid for a field of numpy/torch shape (ny, nx) or (nz, ny, nx)."""
     shape = tuple(int(s) for s in shape)
@@ -228,6 +249,8 @@ def gmres_workspace_bytes(grid: Grid, opts: Opts) -> int:
 def gmres_solve(grid: Grid, b: torch.Tensor, x: torch.Tensor, opts: Opts, ws: torch.Tensor,
                 stream=None, allow_not_converged: bool = False) -> Stats:
     """Solve A x = b in place in x (x holds the initial guess on entry)."""
+    _need(b.numel() == _points(grid), f"b has {b.numel()} elements, the grid {_points(grid)}")
+    _need(x.shape == b.shape, f"x has shape {tuple(x.shape)}, b {tuple(b.shape)}")
     st = Stats()
     rc = lib.gmres_solve(ctypes.byref(grid), _ptr(b), _ptr(x), ctypes.byref(opts),
                          _ptr(ws, torch.uint8), ws.numel(), ctypes.byref(st), _stream(stream))
@@ -245,6 +268,8 @@ def gmres_batched_workspace_bytes(systems, opts: Opts) -> int:
 
 def make_system(b: torch.Tensor, x: torch.Tensor, guess: int = 0) -> System:
     """b, x: [nrhs, ...field shape] device float64 tensors."""
+    _need(b.dim() in (3, 4), "b must be [nrhs, ny, nx] or [nrhs, nz, ny, nx]")
+    _need(x.shape == b.shape, f"x has shape {tuple(x.shape)}, b {tuple(b.shape)}")
     return System(grid_of(b.shape[1:]), b.shape[0], guess, _ptr(b), _ptr(x))
 
 
@@ -261,6 +286,7 @@ def gmres_solve_batched(systems, opts: Opts, ws: torch.Tensor, stream=None,
 
 def mlg_apply_operator(u: torch.Tensor, y: torch.Tensor, stream=None) -> None:
     g = grid_of(u.shape)
+    _need(y.shape == u.shape, f"y has shape {tuple(y.shape)}, u {tuple(u.shape)}")
     _check(lib.mlg_apply_operator(ctypes.byref(g), _ptr(u), _ptr(y), _stream(stream)))
 
 
@@ -349,9 +375,12 @@ def guess_net_refresh(cfg: NetCfg, params: torch.Tensor, stream=None) -> None:
 def guess_net_infer(cfg: NetCfg, params: torch.Tensor, f: torch.Tensor, u_prev: torch.Tensor,
                     guess: torch.Tensor, ws: torch.Tensor, stream=None) -> None:
     """f, u_prev, guess: [batch, ny, nx] (or [ny, nx]) float64 device tensors."""
+    _need(f.dim() in (2, 3), "f must be [ny, nx] or [batch, ny, nx]")
+    _same_fields([u_prev, guess], f.shape, "u_prev and guess")
     shape = f.shape[-2:]
     batch = 1 if f.dim() == 2 else f.shape[0]
     g = grid_of(shape)
+    _params_ok(params, guess_net_param_bytes(cfg))
     _check(lib.guess_net_infer(ctypes.byref(cfg), _ptr(params, torch.uint8), ctypes.byref(g), batch,
                                _ptr(f), _ptr(u_prev), _ptr(guess), _ptr(ws, torch.uint8),
                                ws.numel(), _stream(stream)))
@@ -361,7 +390,12 @@ def guess_net_train_step(cfg: NetCfg, params: torch.Tensor, fs, u_prevs, u_targe
                          ws: torch.Tensor, loss: torch.Tensor | None = None, stream=None) -> None:
     """fs, u_prevs, u_targets: lists of [ny, nx] float64 device tensors (one per sample)."""
     batch = len(fs)
+    _need(batch >= 1 and len(u_prevs) == batch and len(u_targets) == batch,
+          "fs, u_prevs and u_targets must be equally long, non-empty lists")
+    _need(fs[0].dim() == 2, "samples are [ny, nx] fields")
+    _same_fields(list(fs) + list(u_prevs) + list(u_targets), fs[0].shape, "samples")
     g = grid_of(fs[0].shape)
+    _params_ok(params, guess_net_param_bytes(cfg))
     arr = lambda ts: (ctypes.c_void_p * batch)(*[_ptr(t) for t in ts])  # noqa: E731
     lp = _ptr(loss, torch.float32) if loss is not None else None
     _check(lib.guess_net_train_step(ctypes.byref(cfg), _ptr(params, torch.uint8), ctypes.byref(g),
@@ -372,15 +406,15 @@ def guess_net_train_step(cfg: NetCfg, params: torch.Tensor, fs, u_prevs, u_targe
 # ------------------------------------------------------------------ parameter layout
 # Tensor order and shapes of the parameter arrays (see include/mlgmres.h).
 NET_TENSORS = ("conv1.w", "conv1.b", "conv2.w", "conv2.b", "spec.w1", "spec.b", "spec.wk",
-               "conv4.w", "conv4.b", "conv5.w", "conv5.b", "conv6.w", "conv6.b", "skip.g")
+               "conv4.w", "conv4.b", "conv5.w", "conv5.b", "conv6.w", "conv6.b")
 
 
 def net_tensor_shapes(cfg: NetCfg) -> dict:
-    C, M, K = cfg.channels, cfg.modes, cfg.skip_modes
+    C, M = cfg.channels, cfg.modes
     return {"conv1.w": (C, 2, 3, 3), "conv1.b": (C,), "conv2.w": (C, C, 3, 3), "conv2.b": (C,),
             "spec.w1": (C, C), "spec.b": (C,), "spec.wk": (M, M, C, C),
             "conv4.w": (C, C, 3, 3), "conv4.b": (C,), "conv5.w": (C, C, 3, 3), "conv5.b": (C,),
-            "conv6.w": (1, C, 3, 3), "conv6.b": (1,), "skip.g": (K, K)}
+            "conv6.w": (1, C, 3, 3), "conv6.b": (1,)}
 
 
 def _align(v: int, a: int = 256) -> int:
@@ -389,16 +423,39 @@ def _align(v: int, a: int = 256) -> int:
 
 def net_views(cfg, params: torch.Tensor) -> dict:
     """Views of the regions of a parameter buffer (uint8 device tensor) of
-    either network (NetCfg or FluidCfg)."""
-    P = fluid_net_param_count(cfg) if isinstance(cfg, FluidCfg) else guess_net_param_count(cfg)
+    either network (NetCfg or FluidCfg).  For the guess network, "band" is
+    the band path's least-squares state, float64 [2, K, K] (sums of X T, then
+    of X^2)."""
+    fluid = isinstance(cfg, FluidCfg)
+    P = fluid_net_param_count(cfg) if fluid else guess_net_param_count(cfg)
     f = _align(P * 4)
     step = 4 * f + _align(P * 2)
-    return {"master": params[0:P * 4].view(torch.float32),
-            "grad": params[f:f + P * 4].view(torch.float32),
-            "adam_m": params[2 * f:2 * f + P * 4].view(torch.float32),
-            "adam_v": params[3 * f:3 * f + P * 4].view(torch.float32),
-            "bf16": params[4 * f:4 * f + P * 2].view(torch.bfloat16),
-            "step": params[step:step + 8].view(torch.int64)}
+    out = {"master": params[0:P * 4].view(torch.float32),
+           "grad": params[f:f + P * 4].view(torch.float32),
+           "adam_m": params[2 * f:2 * f + P * 4].view(torch.float32),
+           "adam_v": params[3 * f:3 * f + P * 4].view(torch.float32),
+           "bf16": params[4 * f:4 * f + P * 2].view(torch.bfloat16),
+           "step": params[step:step + 8].view(torch.int64)}
+    if not fluid:
+        K = cfg.skip_modes
+        band = step + 256
+        out["band"] = params[band:band + 16 * K * K].view(torch.float64).view(2, K, K)
+    return out
+
+
+def net_band_weights(cfg: NetCfg, params: torch.Tensor) -> torch.Tensor:
+    """The band path's current weights w = sxt / sxx (0 where sxx = 0), [K, K]
+    float64 (device)."""
+    b = net_views(cfg, params)["band"]
+    return torch.where(b[1] > 0, b[0] / torch.where(b[1] > 0, b[1], 1.0), torch.zeros_like(b[0]))
+
+
+def net_set_band(cfg: NetCfg, params: torch.Tensor, w) -> None:
+    """Impose band weights w [K, K] (sxt = w, sxx = 1); later train steps add
+    their sums to this state."""
+    b = net_views(cfg, params)["band"]
+    b[0].copy_(torch.as_tensor(w, dtype=torch.float64))
+    b[1].fill_(1.0)
 
 
 def net_pack(cfg: NetCfg, tensors: dict) -> torch.Tensor:
@@ -459,8 +516,11 @@ def fluid_net_infer(cfg: FluidCfg, params: torch.Tensor, blocks: int, f: torch.T
                     u_prev: torch.Tensor, guess: torch.Tensor, ws: torch.Tensor,
                     stream=None) -> None:
     """f, u_prev, guess: [batch, ny, nx] (or [ny, nx]) float64 device tensors."""
+    _need(f.dim() in (2, 3), "f must be [ny, nx] or [batch, ny, nx]")
+    _same_fields([u_prev, guess], f.shape, "u_prev and guess")
     batch = 1 if f.dim() == 2 else f.shape[0]
     g = grid_of(f.shape[-2:])
+    _params_ok(params, fluid_net_param_bytes(cfg))
     _check(lib.fluid_net_infer(ctypes.byref(cfg), _ptr(params, torch.uint8), blocks,
                                ctypes.byref(g), batch, _ptr(f), _ptr(u_prev), _ptr(guess),
                                _ptr(ws, torch.uint8), ws.numel(), _stream(stream)))
@@ -470,7 +530,12 @@ def fluid_net_train_step(cfg: FluidCfg, params: torch.Tensor, blocks: int, fs, u
                          ws: torch.Tensor, loss: torch.Tensor | None = None, stream=None) -> None:
     """fs, u_prevs, u_targets: lists of [ny, nx] float64 device tensors."""
     batch = len(fs)
+    _need(batch >= 1 and len(u_prevs) == batch and len(u_targets) == batch,
+          "fs, u_prevs and u_targets must be equally long, non-empty lists")
+    _need(fs[0].dim() == 2, "samples are [ny, nx] fields")
+    _same_fields(list(fs) + list(u_prevs) + list(u_targets), fs[0].shape, "samples")
     g = grid_of(fs[0].shape)
+    _params_ok(params, fluid_net_param_bytes(cfg))
     arr = lambda ts: (ctypes.c_void_p * batch)(*[_ptr(t) for t in ts])  # noqa: E731
     lp = _ptr(loss, torch.float32) if loss is not None else None
     _check(lib.fluid_net_train_step(ctypes.byref(cfg), _ptr(params, torch.uint8), blocks,
@@ -553,9 +618,10 @@ def linear_guess_infer(grid: Grid, params: torch.Tensor, b: torch.Tensor, x0: to
                        stream=None) -> None:
     """b, x0: float64 device tensors holding `batch` contiguous fields of the
     grid's n points ([batch, n], [n] or grid-shaped with a leading batch axis)."""
-    n = grid.nx * grid.ny * (grid.nz if grid.dim == 3 else 1)
+    n = _points(grid)
     if b.numel() % n or x0.numel() != b.numel():
         raise ValueError("b and x0 must hold the same whole number of grid fields")
+    _params_ok(params, linear_guess_param_bytes(grid))
     batch = b.numel() // n
     _check(lib.linear_guess_infer(ctypes.byref(grid), _ptr(params, torch.uint8), batch, _ptr(b),
                                   _ptr(x0), _stream(stream)))
@@ -565,6 +631,10 @@ def linear_guess_train_step(grid: Grid, params: torch.Tensor, lr: float, bs, xs,
                             loss: torch.Tensor | None = None, stream=None) -> None:
     """bs, xs: lists of float64 device tensors of the grid's n points."""
     batch = len(bs)
+    _need(batch >= 1 and len(xs) == batch, "bs and xs must be equally long, non-empty lists")
+    _need(all(t.numel() == _points(grid) for t in list(bs) + list(xs)),
+          "every sample must hold the grid's points")
+    _params_ok(params, linear_guess_param_bytes(grid))
     arr = lambda ts: (ctypes.c_void_p * batch)(*[_ptr(t) for t in ts])  # noqa: E731
     lp = _ptr(loss, torch.float32) if loss is not None else None
     _check(lib.linear_guess_train_step(ctypes.byref(grid), _ptr(params, torch.uint8), lr, batch,

@@ -65,7 +65,8 @@ void check_grid(const mlg_grid* grid) {
   if (grid->nx < 1 || grid->ny < 1 || (grid->dim == 3 && grid->nz < 1))
     throw ArgError{MLG_ERR_ARG, "grid sizes must be >= 1"};
   long long n = (long long)grid->nx * grid->ny * (grid->dim == 3 ? grid->nz : 1);
-  if (n > (1LL << 31)) throw ArgError{MLG_ERR_ARG, "grid has more than 2^31 points"};
+  // the sweeps address a field with 32-bit byte offsets (8-byte elements)
+  if (n > (1LL << 29)) throw ArgError{MLG_ERR_ARG, "grid has more than 2^29 points"};
 }
 
 void check_opts(const mlg_opts* o, int dim) {
@@ -332,7 +333,7 @@ __global__ void k_setup(const SysInit* init, const SysDesc* sd, unsigned int* hd
   Ctrl* C = S->C;
   if (threadIdx.x != 0) return;
   const SysInit& I = init[blockIdx.x];
-  C->s = Summary{MLG_OK, 0, 0, 0.0, 0.0, 0.0, 0.0};
+  C->s = Summary{MLG_OK, 0, 0, 0.0, 0.0, 0.0, 0.0, 0.0};
   C->phase = PH_INIT;
   C->cycle_end = 0;
   C->k = 0;
@@ -621,6 +622,7 @@ int batched_solve(int nsys, const mlg_system* sys, const mlg_opts* opts, void* w
       stats[i].relres_est = s.relres_est;
       stats[i].relres_true = s.relres_true;
       stats[i].seconds = P.total_rhs == 1 ? secs : 0.0;
+      stats[i].relres_iter5 = s.relres5;
     }
   }
   return worst;
@@ -655,6 +657,37 @@ int solve(const mlg_grid* grid, const double* b, double* x, const mlg_opts* opts
 }
 
 // ------------------------------------------------------------------ kernel timing
+// Replicate a system's state into `n` independent copies for kernel timing:
+// each keeps the coefficients of the finished solve but is marked running
+// with a zero tolerance, so every timed launch does its full work.
+// descs[i] is the system descriptor pointing at copy i.
+__global__ void k_bench_setup(const SysDesc* src_desc, SysDesc* descs, Ctrl* copies, int n,
+                              int j) {
+  const int i = blockIdx.x;
+  if (i >= n) return;
+  const unsigned int* s = (const unsigned int*)src_desc->C;
+  unsigned int* d = (unsigned int*)(copies + i);
+  for (int e = threadIdx.x; e < (int)(sizeof(Ctrl) / 4); e += blockDim.x) d[e] = s[e];
+  __syncthreads();
+  Ctrl* c = copies + i;
+  // column sums of a unit direction orthogonal to the basis (alpha = 1), so a
+  // split step at j runs its full sweep
+  for (int e = threadIdx.x; e < 2 * kMaxRestart + 2; e += blockDim.x)
+    c->sums[e] = e == 2 * j ? 1.0 : 0.0;
+  if (threadIdx.x == 0) {
+    c->phase = PH_RUN;
+    c->rhs = 0;
+    c->cycle_end = 0;
+    c->tol_abs = 0.0;
+    c->fixed = 1;
+    c->limit = 1LL << 62;
+    c->k = c->m;
+    if (!(c->alpha > 0.0)) c->alpha = 1.0;
+    descs[i] = *src_desc;
+    descs[i].C = c;
+  }
+}
+
 // One launch of a solver kernel in the solve's configuration (kind: MLG_K_*;
 // j: step index, the restart length for MLG_K_UPDATE).
 static void enqueue_one(GroupFn fn, hipStream_t s, int kind, int nb, const Job* jobs,

@@ -55,6 +55,7 @@ struct Summary {
   int cycles;
   long long iters;
   double relres_init, relres_first, relres_est, relres_true;
+  double relres5;       // Givens estimate after Arnoldi step min(5, iters)
 };
 
 struct Ctrl {
@@ -173,6 +174,63 @@ struct Halo {
   }
 };
 
+// ---------------------------------------------------------------- buffer access
+// The sweeps read and write the basis vectors (and the FP64 iterate) through
+// raw buffer descriptors: a vector's base address and size live in scalar
+// registers and each access takes a 32-bit element offset in one vector
+// register, shared by every vector at the same point.  Global loads would
+// each need a 64-bit address in two vector registers (and 64-bit address
+// arithmetic per basis vector); with up to 40 vectors in flight per point
+// that, not the data, set the register footprint and the occupancy of the
+// long steps.  Fields hold fewer than 2^29 points, so byte offsets fit 32 bits.
+constexpr int kBufDword3 = 0x00020000;   // word 3 of a raw buffer descriptor (gfx9 family)
+using Rsrc = __amdgpu_buffer_rsrc_t;
+
+// Descriptor of `count` elements from `base` (accesses past the end read 0).
+template <class T>
+__device__ __forceinline__ Rsrc vec_rsrc(const T* base, long long count) {
+  return __builtin_amdgcn_make_buffer_rsrc((void*)base, 0, (int)(unsigned)(count * sizeof(T)),
+                                           kBufDword3);
+}
+// Element e of the vector that starts `vo` bytes into the descriptor's
+// region (vo in a scalar register: the range check covers e only).
+__device__ __forceinline__ float buf_ld(Rsrc r, unsigned e, unsigned vo, float) {
+  return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, e * 4u, vo, 0));
+}
+__device__ __forceinline__ double buf_ld(Rsrc r, unsigned e, unsigned vo, double) {
+  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, e * 8u, vo, 0));
+}
+template <class T>
+__device__ __forceinline__ T buf_load(Rsrc r, unsigned e, unsigned vo = 0) {
+  return buf_ld(r, e, vo, T{});
+}
+__device__ __forceinline__ void buf_store(Rsrc r, unsigned e, float v, unsigned vo = 0) {
+  __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), r, e * 4u, vo, 0);
+}
+__device__ __forceinline__ void buf_store(Rsrc r, unsigned e, double v, unsigned vo = 0) {
+  __builtin_amdgcn_raw_buffer_store_b64(
+      __builtin_bit_cast(decltype(__builtin_amdgcn_raw_buffer_load_b64(r, 0, 0, 0)), v), r, e * 8u,
+      vo, 0);
+}
+
+// The basis region of a system: one descriptor whose range is one vector
+// (n elements); vector k starts k * ldv elements in, selected by the scalar
+// offset.  The whole region lies within 4 GiB of its start (checked on the
+// host), so every vector's byte offset fits the 32-bit scalar offset.
+template <class T>
+struct BasisBuf {
+  Rsrc r;
+  unsigned vb;                      // bytes between vectors
+  __device__ __forceinline__ BasisBuf(const T* V, const Geo& g)
+      : r(vec_rsrc(V, g.n)), vb((unsigned)(g.ldv * (long long)sizeof(T))) {}
+  __device__ __forceinline__ T load(int k, unsigned e) const {
+    return buf_load<T>(r, e, (unsigned)k * vb);
+  }
+  __device__ __forceinline__ void store(int k, unsigned e, T v) const {
+    buf_store(r, e, v, (unsigned)k * vb);
+  }
+};
+
 // Stage the tile of `src` plus a RING-point halo into LDS as FP64; points
 // outside the grid read as 0 (the Dirichlet boundary).
 template <class TL, int RING = 1, class P>
@@ -190,6 +248,29 @@ __device__ __forceinline__ void load_tile(double* L, P src, const Geo& g, int ox
     const int gx = ox + lx - RING, gy = oy + ly - RING, gz = TL::DIM == 3 ? oz + lz - RING : 0;
     in[h] = e < H::SZ && gx >= 0 && gx < g.nx && gy >= 0 && gy < g.ny && gz >= 0 && gz < g.nz;
     v[h] = (double)src[in[h] ? ((long long)gz * g.ny + gy) * g.nx + gx : 0];
+  }
+#pragma unroll
+  for (int h = 0; h < NPT; ++h) {
+    const int e = threadIdx.x + kBlock * h;
+    if (e < H::SZ) L[e] = in[h] ? v[h] : 0.0;
+  }
+}
+
+// load_tile from a buffer descriptor of element type T.
+template <class TL, class T, int RING = 1>
+__device__ __forceinline__ void load_tile_buf(double* L, const BasisBuf<T>& B, int k, const Geo& g,
+                                              int ox, int oy, int oz) {
+  using H = Halo<TL, RING>;
+  constexpr int NPT = (H::SZ + kBlock - 1) / kBlock;
+  double v[NPT];
+  bool in[NPT];
+#pragma unroll
+  for (int h = 0; h < NPT; ++h) {
+    const int e = threadIdx.x + kBlock * h;
+    const int lx = e % H::X, r = e / H::X, ly = r % H::Y, lz = r / H::Y;
+    const int gx = ox + lx - RING, gy = oy + ly - RING, gz = TL::DIM == 3 ? oz + lz - RING : 0;
+    in[h] = e < H::SZ && gx >= 0 && gx < g.nx && gy >= 0 && gy < g.ny && gz >= 0 && gz < g.nz;
+    v[h] = (double)B.load(k, in[h] ? (unsigned)(((long long)gz * g.ny + gy) * g.nx + gx) : 0u);
   }
 #pragma unroll
   for (int h = 0; h < NPT; ++h) {
@@ -291,6 +372,7 @@ __device__ inline void finish_rhs(gptr<Ctrl> C) {
   st->relres_first = C->s.relres_first;
   st->relres_est = C->s.relres_est;
   st->relres_true = C->s.relres_true;
+  st->relres5 = C->s.relres5;
   C->rhs += 1;
   C->cycle_end = 1;
   if (C->rhs >= C->nrhs) {
@@ -312,14 +394,13 @@ __device__ __forceinline__ double lane_bcast(double v, int src) {
 // unconditionally: slots k >= `live` re-read the last live vector (or
 // vector 0) and are never used, so no branch separates the loads.
 template <int MM, int N, class T>
-__device__ __forceinline__ void load_basis(T (&v)[MM][N], gptr<const T> V, long long ldv,
+__device__ __forceinline__ void load_basis(T (&v)[MM][N], const BasisBuf<T>& B,
                                            const long long (&p)[N], int live) {
   const int last = live > 0 ? live - 1 : 0;
 #pragma unroll
   for (int k = 0; k < MM; ++k) {
-    const gptr<const T> Vk = V + (size_t)(k < live ? k : last) * ldv;
 #pragma unroll
-    for (int i = 0; i < N; ++i) v[k][i] = Vk[p[i]];
+    for (int i = 0; i < N; ++i) v[k][i] = B.load(k < live ? k : last, (unsigned)p[i]);
   }
 }
 
@@ -471,6 +552,7 @@ __global__ __launch_bounds__(kReduceThreads) void k_rsum(const SysDesc* sd) {
     C->tol_abs = C->rtol * bnorm;
     if (bnorm == 0.0) {                     // A x = 0: x = 0 (written by start)
       C->s.relres_init = C->s.relres_first = C->s.relres_est = C->s.relres_true = 0.0;
+      C->s.relres5 = 0.0;
       C->phase = PH_ZERO;
       return;
     }
@@ -479,6 +561,7 @@ __global__ __launch_bounds__(kReduceThreads) void k_rsum(const SysDesc* sd) {
     C->s.relres_first = rr;
     C->s.relres_est = rr;
     C->s.relres_true = rr;
+    C->s.relres5 = rr;
     if (!isfinite(beta)) {
       C->s.status = MLG_ERR_NONFINITE;
       finish_rhs(C);
@@ -551,8 +634,8 @@ __global__ __launch_bounds__(kBlock) void k_dots(const Job* jobs, const SysDesc*
   __shared__ double L[TL::LSZ];
   __shared__ double red[4 * NS];
   const Geo g = me.job.g;
-  const gptr<const T> V = gmem((const T*)me.job.V);
-  const gptr<const T> U = V + (size_t)(me.job.m + (j & 1)) * g.ldv;
+  const BasisBuf<T> VB((const T*)me.job.V, g);
+  const int kU = me.job.m + (j & 1);
   double acc[MM / 8 + 1];
 #pragma unroll
   for (int c = 0; c <= MM / 8; ++c) acc[c] = 0.0;
@@ -572,9 +655,9 @@ __global__ __launch_bounds__(kBlock) void k_dots(const Job* jobs, const SysDesc*
       qc[i][2] = pr.qz;
     }
     T vr[MM][PPT];
-    load_basis<MM, PPT, T>(vr, V, g.ldv, pp, j);
+    load_basis<MM, PPT, T>(vr, VB, pp, j);
     __syncthreads();
-    load_tile<TL>(L, U, g, ox, oy, oz);
+    load_tile_buf<TL, T>(L, VB, kU, g, ox, oy, oz);
     __syncthreads();
     double uu[PPT], ww[PPT], last[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
@@ -695,6 +778,7 @@ __device__ __forceinline__ int coef_rotate(gptr<Ctrl> C, const StepCoef& q, int 
     C->s.iters = iters;
     C->k = j;
     C->s.relres_est = est / ss.bnorm;
+    if (iters <= 5) C->s.relres5 = est / ss.bnorm;
     atomicAdd(C->done + 1, 1u);
     if (bad) C->s.status = MLG_ERR_NONFINITE;
   }
@@ -858,16 +942,18 @@ __global__ __launch_bounds__(kBlock) void k_extend(const Job* jobs, const SysDes
   if (C->phase != PH_RUN || C->cycle_end) return;
   constexpr int PPT = TL::PPT;
   __shared__ double L[TL::LSZ];
-  __shared__ double sY[MM], cY[MM + 1];
-  for (int k = threadIdx.x; k <= j; k += kBlock) {
-    if (k < j) sY[k] = C->sY[k];
-    cY[k] = C->cY[k];
+  // coefficients zero beyond j, so every register slot takes an
+  // unconditional FMA (adding exact zeros) instead of a per-slot select
+  __shared__ double sY[MM], cY[MM];
+  for (int k = threadIdx.x; k < MM; k += kBlock) {
+    sY[k] = k < j ? C->sY[k] : 0.0;
+    cY[k] = k < j ? C->cY[k] : 0.0;
   }
   const Geo g = me.job.g;
-  const gptr<T> V = gmem((T*)me.job.V);
-  const gptr<const T> U = V + (size_t)(me.job.m + (j & 1)) * g.ldv;
-  const gptr<T> Unext = V + (size_t)(me.job.m + ((j + 1) & 1)) * g.ldv;
+  const BasisBuf<T> VB((const T*)me.job.V, g);
+  const int kU = me.job.m + (j & 1), kUn = me.job.m + ((j + 1) & 1);
   const double ainv = 1.0 / C->alpha;
+  const double cyj = C->cY[j];
   for (int tile = me.job.t0; tile < me.job.t1; ++tile) {
     int ox, oy, oz;
     tile_origin<TL>(g, tile, ox, oy, oz);
@@ -884,11 +970,10 @@ __global__ __launch_bounds__(kBlock) void k_extend(const Job* jobs, const SysDes
       qc[i][2] = pr.qz;
     }
     T vr[MM][PPT];
-    load_basis<MM, PPT, T>(vr, V, g.ldv, pp, j);
+    load_basis<MM, PPT, T>(vr, VB, pp, j);
     __syncthreads();
-    load_tile<TL>(L, U, g, ox, oy, oz);
+    load_tile_buf<TL, T>(L, VB, kU, g, ox, oy, oz);
     __syncthreads();
-    const double cyj = cY[j];
 #pragma unroll
     for (int i = 0; i < PPT; ++i)
       if (ok[i]) {
@@ -896,15 +981,14 @@ __global__ __launch_bounds__(kBlock) void k_extend(const Job* jobs, const SysDes
         const double ww = stencil<TL>(L, g, qc[i][0], qc[i][1], qc[i][2]);
         double a = 0.0, b = 0.0;
 #pragma unroll
-        for (int k = 0; k < MM; ++k)
-          if (k < j) {
-            a = fma((double)vr[k][i], sY[k], a);
-            b = fma((double)vr[k][i], cY[k], b);
-          }
+        for (int k = 0; k < MM; ++k) {
+          a = fma((double)vr[k][i], sY[k], a);
+          b = fma((double)vr[k][i], cY[k], b);
+        }
         T vj, un;
         extend_point<T>(uu, ww, a, b, ainv, cyj, vj, un);
-        V[(size_t)j * g.ldv + pp[i]] = vj;
-        Unext[pp[i]] = un;
+        VB.store(j, (unsigned)pp[i], vj);
+        VB.store(kUn, (unsigned)pp[i], un);
       }
   }
 }
@@ -953,13 +1037,14 @@ __global__ __launch_bounds__(kBlock) void k_step(const Job* jobs, const SysDesc*
   __shared__ double L2[H2::SZ];
   __shared__ double L1[L1SZ];
   __shared__ double red[4 * NS];
+  // coefficients zero beyond j (see k_extend); cY_j kept apart
   __shared__ double sY[MM], cY[MM];
+  __shared__ double sCyj;
   __shared__ double sAlpha;
   __shared__ int sFlag;
   const Geo g = me.job.g;
-  const gptr<T> V = gmem((T*)me.job.V);
-  const gptr<const T> U = V + (size_t)(me.job.m + (j & 1)) * g.ldv;
-  const gptr<T> Unext = V + (size_t)(me.job.m + ((j + 1) & 1)) * g.ldv;
+  const BasisBuf<T> VB((const T*)me.job.V, g);
+  const int kU = me.job.m + (j & 1), kUn = me.job.m + ((j + 1) & 1);
   const bool writer = me.job.lblk == 0;
   const int c = j - 1;
   double ainv = 0.0, sYl = 0.0, cYl = 0.0;
@@ -1012,7 +1097,7 @@ __global__ __launch_bounds__(kBlock) void k_step(const Job* jobs, const SysDesc*
       const int gx = ox + lx - 2, gy = oy + ly - 2, gz = TL::DIM == 3 ? oz + lz - 2 : 0;
       hin[h] = e < H2::SZ && gx >= 0 && gx < g.nx && gy >= 0 && gy < g.ny && gz >= 0 &&
                gz < g.nz;
-      hv[h] = U[hin[h] ? ((long long)gz * g.ny + gy) * g.nx + gx : 0];
+      hv[h] = VB.load(kU, hin[h] ? (unsigned)(((long long)gz * g.ny + gy) * g.nx + gx) : 0u);
     }
     long long pp[PPT];
     bool ok[PPT];
@@ -1041,11 +1126,11 @@ __global__ __launch_bounds__(kBlock) void k_step(const Job* jobs, const SysDesc*
     const int jl = j > 0 ? j - 1 : 0;
 #pragma unroll
     for (int k = 0; k < MM; ++k) {
-      const gptr<const T> Vk = V + (size_t)(k < j ? k : jl) * g.ldv;
+      const int kk = k < j ? k : jl;
 #pragma unroll
-      for (int i = 0; i < PPT; ++i) vr[k][i] = Vk[pp[i]];
+      for (int i = 0; i < PPT; ++i) vr[k][i] = VB.load(kk, (unsigned)pp[i]);
 #pragma unroll
-      for (int rr = 0; rr < RPT; ++rr) vg[k][rr] = Vk[rp[rr]];
+      for (int rr = 0; rr < RPT; ++rr) vg[k][rr] = VB.load(kk, (unsigned)rp[rr]);
     }
     // ---- stage u_j (the previous tile's readers of L2/L1 are done)
     __syncthreads();
@@ -1069,8 +1154,11 @@ __global__ __launch_bounds__(kBlock) void k_step(const Job* jobs, const SysDesc*
       }
       if (phase != PH_RUN || cycle_end) return false;  // uniform: the whole workgroup leaves
       if constexpr (!SPLIT) {
-        if (tid < j) sY[tid] = sYl;
-        if (tid <= j) cY[tid] = cYl;
+        if (tid < MM) {
+          sY[tid] = tid < j ? sYl : 0.0;
+          cY[tid] = tid < j ? cYl : 0.0;
+        }
+        if (tid == j) sCyj = cYl;
       } else {
         // ---- coefficient update of step j (this workgroup's own copy; the
         // system's first workgroup also advances the system's state)
@@ -1080,8 +1168,11 @@ __global__ __launch_bounds__(kBlock) void k_step(const Job* jobs, const SysDesc*
         if (tid < 64) {
           const int lane = tid;
           const StepCoef q = coef_project(fin, L1, j, red[CH + (lane < j ? lane : 0)]);
-          if (lane < j) sY[lane] = q.si;
-          if (lane <= j) cY[lane] = q.cy;
+          if (lane < MM) {
+            sY[lane] = lane < j ? q.si : 0.0;
+            cY[lane] = lane < j ? q.cy : 0.0;
+          }
+          if (lane == j) sCyj = q.cy;
           if (lane == 0) sAlpha = q.alpha;
           int fl = 0;
           if (writer) {
@@ -1124,7 +1215,7 @@ __global__ __launch_bounds__(kBlock) void k_step(const Job* jobs, const SysDesc*
       }
     }
     __syncthreads();
-    const double cyj = cY[j];
+    const double cyj = sCyj;
     // u_{j+1} on the ring (zero outside the grid)
 #pragma unroll
     for (int rr = 0; rr < RPT; ++rr) {
@@ -1137,11 +1228,10 @@ __global__ __launch_bounds__(kBlock) void k_step(const Job* jobs, const SysDesc*
           const double ww = stencil_at<TL::DIM>(L2, g, i2, H2::X, H2::X * H2::Y);
           double a = 0.0, b = 0.0;
 #pragma unroll
-          for (int k = 0; k < MM; ++k)
-            if (k < j) {
-              a = fma((double)vg[k][rr], sY[k], a);
-              b = fma((double)vg[k][rr], cY[k], b);
-            }
+          for (int k = 0; k < MM; ++k) {
+            a = fma((double)vg[k][rr], sY[k], a);
+            b = fma((double)vg[k][rr], cY[k], b);
+          }
           T vj, unT;
           extend_point<T>(uu, ww, a, b, ainv, cyj, vj, unT);
           un = (double)unT;
@@ -1160,15 +1250,14 @@ __global__ __launch_bounds__(kBlock) void k_step(const Job* jobs, const SysDesc*
         const double ww = stencil_at<TL::DIM>(L2, g, q2[i], H2::X, H2::X * H2::Y);
         double a = 0.0, b = 0.0;
 #pragma unroll
-        for (int k = 0; k < MM; ++k)
-          if (k < j) {
-            a = fma((double)vr[k][i], sY[k], a);
-            b = fma((double)vr[k][i], cY[k], b);
-          }
+        for (int k = 0; k < MM; ++k) {
+          a = fma((double)vr[k][i], sY[k], a);
+          b = fma((double)vr[k][i], cY[k], b);
+        }
         T vj, unT;
         extend_point<T>(uu, ww, a, b, ainv, cyj, vj, unT);
-        V[(size_t)j * g.ldv + pp[i]] = vj;
-        Unext[pp[i]] = unT;
+        VB.store(j, (unsigned)pp[i], vj);
+        VB.store(kUn, (unsigned)pp[i], unT);
         vjd[i] = (double)vj;
         un = (double)unT;
       }
@@ -1241,11 +1330,11 @@ __global__ __launch_bounds__(kBlock) void k_update(const Job* jobs, const SysDes
   constexpr int PPT = TL::PPT;
   __shared__ double ys[MM];
   const int k = C->k;
-  for (int l = threadIdx.x; l < k; l += kBlock) ys[l] = C->y[l];
+  for (int l = threadIdx.x; l < MM; l += kBlock) ys[l] = l < k ? C->y[l] : 0.0;
   __syncthreads();
   const Geo g = me.job.g;
-  const gptr<const T> V = gmem((const T*)me.job.V);
-  gptr<double> x = gmem(C->x0) + (size_t)C->rhs * g.n;
+  const BasisBuf<T> VB((const T*)me.job.V, g);
+  const Rsrc rx = vec_rsrc(C->x0 + (size_t)C->rhs * g.n, g.n);
   for (int tile = me.job.t0; tile < me.job.t1; ++tile) {
     int ox, oy, oz;
     tile_origin<TL>(g, tile, ox, oy, oz);
@@ -1258,49 +1347,18 @@ __global__ __launch_bounds__(kBlock) void k_update(const Job* jobs, const SysDes
       pp[i] = pr.valid ? pr.p : 0;
     }
     T vr[MM][PPT];
-    load_basis<MM, PPT, T>(vr, V, g.ldv, pp, k);
+    load_basis<MM, PPT, T>(vr, VB, pp, k);
     double xs[PPT];
 #pragma unroll
-    for (int i = 0; i < PPT; ++i) xs[i] = x[pp[i]];
+    for (int i = 0; i < PPT; ++i) xs[i] = buf_load<double>(rx, (unsigned)pp[i]);
 #pragma unroll
     for (int i = 0; i < PPT; ++i) {
       double acc = xs[i];
 #pragma unroll
       for (int l = 0; l < MM; ++l)
-        if (l < k) acc = fma(ys[l], (double)vr[l][i], acc);
-      if (ok[i]) x[pp[i]] = acc;
+        acc = fma(ys[l], (double)vr[l][i], acc);
+      if (ok[i]) buf_store(rx, (unsigned)pp[i], acc);
     }
-  }
-}
-
-// Replicate a system's state into `n` independent copies for kernel timing:
-// each keeps the coefficients of the finished solve but is marked running
-// with a zero tolerance, so every timed launch does its full work.
-// descs[i] is the system descriptor pointing at copy i.
-__global__ void k_bench_setup(const SysDesc* src_desc, SysDesc* descs, Ctrl* copies, int n,
-                              int j) {
-  const int i = blockIdx.x;
-  if (i >= n) return;
-  const unsigned int* s = (const unsigned int*)src_desc->C;
-  unsigned int* d = (unsigned int*)(copies + i);
-  for (int e = threadIdx.x; e < (int)(sizeof(Ctrl) / 4); e += blockDim.x) d[e] = s[e];
-  __syncthreads();
-  Ctrl* c = copies + i;
-  // column sums of a unit direction orthogonal to the basis (alpha = 1), so a
-  // split step at j runs its full sweep
-  for (int e = threadIdx.x; e < 2 * kMaxRestart + 2; e += blockDim.x)
-    c->sums[e] = e == 2 * j ? 1.0 : 0.0;
-  if (threadIdx.x == 0) {
-    c->phase = PH_RUN;
-    c->rhs = 0;
-    c->cycle_end = 0;
-    c->tol_abs = 0.0;
-    c->fixed = 1;
-    c->limit = 1LL << 62;
-    c->k = c->m;
-    if (!(c->alpha > 0.0)) c->alpha = 1.0;
-    descs[i] = *src_desc;
-    descs[i].C = c;
   }
 }
 

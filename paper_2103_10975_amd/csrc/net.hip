@@ -8,14 +8,19 @@
 // asks for a network that captures non-local relations without reducing
 // resolution.  Architecture (C channels, M x M sine modes in L3, K x K in the
 // skip band):
-//   x0 = (f/s, c_u u_prev/s)                          BF16 NHWC, 2 channels
+//   x0 = (r/s_r, f/s_f), r = f - A u_prev (FP64)       BF16 NHWC, 2 channels
 //   a1 = ReLU(conv3x3(x0))          a2 = ReLU(conv3x3(a1))
 //   a3 = ReLU(W1 a2 + b + S^-1[Wk . S[a2]])           (spectral mixing)
 //   a4 = ReLU(conv3x3(a3))          a5 = ReLU(conv3x3(a4))
 //   c6 = conv3x3(a5) (1 channel, FP32)
-//   out = c6 - P_K c6 + S^-1[rho g_kl (c_u / lambda_kl) S[r/s_r]_kl]   (FP32)
-//       (P_K: projection on the skip band; the skip alone sets the output
-//       there, with unit rho g the exact inverse of A on the band)
+//   out = c6 - P_K c6 + S^-1[w_kl S[r/s_r]_kl]        (band path, FP64; K = 0: out = c6)
+//       (P_K: projection on the K x K band; the band path alone sets the
+//       output there.  Its per-mode weights w = sxt / sxx are learned from the
+//       training pairs by least squares: every train step adds the batch's
+//       sums of X T and X^2, X and T the band coefficients of A d and of the
+//       target c_u d / s_r for the correction d = u_t - u_prev -- u_t solves
+//       A u_t = f - r_fin exactly, so (A d, d) is an exact pair -- the
+//       minimiser of the loss over w on those pairs)
 //   guess = u_prev + (s_r/c_u) out
 // The 3x3 convolutions with C -> C channels (forward, input gradient and
 // weight gradient) run on MFMA (v_mfma_f32_16x16x32_bf16) as implicit GEMMs
@@ -34,10 +39,8 @@ namespace {
 
 constexpr double kCu = 19.739208802178717;   // 2 pi^2
 constexpr int kMaxBatch = 64;
-constexpr int kNumTensors = 14;
-enum { T_C1W, T_C1B, T_C2W, T_C2B, T_SW1, T_SB, T_SWK, T_C4W, T_C4B, T_C5W, T_C5B, T_C6W, T_C6B,
-       T_SKIP };
-constexpr float kRho = 32.f;          // step-size scale of the skip gains
+constexpr int kNumTensors = 13;
+enum { T_C1W, T_C1B, T_C2W, T_C2B, T_SW1, T_SB, T_SWK, T_C4W, T_C4B, T_C5W, T_C5B, T_C6W, T_C6B };
 constexpr int kRmsBlocks = 128;       // chunks per field of the RMS sums
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
@@ -69,9 +72,9 @@ struct Dims {
 };
 
 void tensor_sizes(const guess_net_cfg* cfg, int64_t* sz) {
-  const int64_t C = cfg->channels, M = cfg->modes, K = cfg->skip_modes;
+  const int64_t C = cfg->channels, M = cfg->modes;
   int64_t s[kNumTensors] = {C * 2 * 9, C, C * C * 9, C, C * C, C, M * M * C * C,
-                            C * C * 9, C, C * C * 9, C, C * 9, 1, K * K};
+                            C * C * 9, C, C * C * 9, C, C * 9, 1};
   for (int i = 0; i < kNumTensors; ++i) sz[i] = s[i];
 }
 
@@ -79,14 +82,14 @@ void check_cfg(const guess_net_cfg* cfg) {
   if (!cfg) throw ArgError{MLG_ERR_ARG, "cfg is NULL"};
   if (cfg->channels != 32) throw ArgError{MLG_ERR_ARG, "channels must be 32"};
   if (cfg->modes < 1 || cfg->modes > 32) throw ArgError{MLG_ERR_ARG, "modes must be in 1..32"};
-  if (cfg->skip_modes < 1 || cfg->skip_modes > 128)
-    throw ArgError{MLG_ERR_ARG, "skip_modes must be in 1..128"};
+  if (cfg->skip_modes < 0 || cfg->skip_modes > 128)
+    throw ArgError{MLG_ERR_ARG, "skip_modes must be in 0..128"};
 }
 
 struct ParamLayout {
   int64_t P;
   int64_t off[kNumTensors + 1];
-  size_t master, grad, m, v, bf, step, total;
+  size_t master, grad, m, v, bf, step, band, total;
 };
 
 ParamLayout param_layout(const guess_net_cfg* cfg) {
@@ -104,7 +107,9 @@ ParamLayout param_layout(const guess_net_cfg* cfg) {
   L.v = 3 * f;
   L.bf = 4 * f;
   L.step = L.bf + align_up((size_t)L.P * 2, 256);
-  L.total = L.step + 256;
+  // the band's least-squares state: FP64 sums of X T, then of X^2, [K][K] each
+  L.band = L.step + 256;
+  L.total = L.band + align_up((size_t)2 * cfg->skip_modes * cfg->skip_modes * 8, 256);
   return L;
 }
 
@@ -122,7 +127,7 @@ Dims check_grid_net(const guess_net_cfg* cfg, const mlg_grid* grid, int batch) {
 
 struct WsLayout {
   size_t s, r0, x0, act[5], out, dout, dz[2], T, X, Y, dX, Z, Sx, Sy, part, loss;
-  size_t kT, kX, kC, kY, kZ, kdY, kSx, kSxT, kSy, rms, total;   // spectral skip path (FP64)
+  size_t kT, kX, kC, kY, kZ, kdY, kTc, kXa, ad, kSx, kSxT, kSy, rms, total;   // band path (FP64)
   int wgrad_blocks;
 };
 
@@ -153,6 +158,9 @@ WsLayout ws_layout(const Dims& d, bool train) {
   L.kY = take((size_t)d.B * d.K * d.K * 8);
   L.kZ = take((size_t)d.B * d.H * d.K * 8);
   L.kdY = train ? take((size_t)d.B * d.K * d.K * 8) : 0;
+  L.kTc = train ? take((size_t)d.B * d.K * d.K * 8) : 0;
+  L.kXa = train ? take((size_t)d.B * d.K * d.K * 8) : 0;
+  L.ad = train && d.K > 0 ? take((size_t)d.B * d.HW * 8) : 0;
   L.kSx = take((size_t)d.K * d.W * 8);
   L.kSxT = take((size_t)d.K * d.W * 8);
   L.kSy = take((size_t)d.K * d.H * 8);
@@ -887,23 +895,16 @@ __global__ __launch_bounds__(256) void k_skip_rows(const X* x, const double* div
   }
 }
 
-// lambda_kl of the zero-Dirichlet 5-point Laplacian on the (k+1, l+1) sine mode
-__device__ __forceinline__ double mode_lambda(int k, int l, int H, int W) {
-  const double sy = sin((double)(k + 1) * M_PI / (2.0 * (H + 1)));
-  const double sx = sin((double)(l + 1) * M_PI / (2.0 * (W + 1)));
-  return 4.0 * (H + 1.0) * (H + 1.0) * sy * sy + 4.0 * (W + 1.0) * (W + 1.0) * sx * sx;
-}
-
-// Y[b][k][l] = rho g_kl (c_u / lambda_kl) X[b][k][l] - Cc[b][k][l]: the skip
-// path's band coefficients in place of those of the convolutional output
-// (FP32 master gains)
-__global__ void k_skip_gain(const double* X, const double* Cc, const float* g, double* Y, int B,
-                            int H, int W, int M) {
+// Y[b][k][l] = w_kl X[b][k][l] - Cc[b][k][l], w = sxt / sxx (0 where sxx = 0):
+// the band path's coefficients in place of those of the convolutional output
+__global__ void k_band_apply(const double* X, const double* Cc, const double* band, double* Y,
+                             int B, int K) {
   const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= (long long)B * M * M) return;
-  const int kl = (int)(e % (M * M));
-  const int k = kl / M, l = kl % M;
-  Y[e] = kRho * (double)g[kl] * kCu / mode_lambda(k, l, H, W) * X[e] - Cc[e];
+  if (e >= (long long)B * K * K) return;
+  const int kl = (int)(e % (K * K));
+  const double sxx = band[K * K + kl];
+  const double w = sxx > 0.0 ? band[kl] / sxx : 0.0;
+  Y[e] = w * X[e] - Cc[e];
 }
 
 // Z[b][i][l] = alpha sum_k Sy[k][i] Y[b][k][l]
@@ -947,14 +948,39 @@ __global__ void k_skip_out(const double* Z, const double* Sx, float* out, int B,
   out[e] = (float)((double)out[e] + beta * ((s0 + s1) + (s2 + s3)));
 }
 
-// grad g_kl = rho (c_u / lambda_kl) sum_b dY[b][k][l] X[b][k][l]
-__global__ void k_skip_grad(const double* dY, const double* X, float* grad, int B, int H, int W,
-                            int M) {
+// Least-squares state of the band: sxt_kl += sum_b X[b][k][l] T[b][k][l],
+// sxx_kl += sum_b X[b][k][l]^2 (samples added in order)
+__global__ void k_band_fit(const double* X, const double* T, double* band, int B, int K) {
   const int kl = blockIdx.x * blockDim.x + threadIdx.x;
-  if (kl >= M * M) return;
-  double s = 0.0;
-  for (int b = 0; b < B; ++b) s += dY[(size_t)b * M * M + kl] * X[(size_t)b * M * M + kl];
-  grad[kl] = (float)(kRho * kCu / mode_lambda(kl / M, kl % M, H, W) * s);
+  if (kl >= K * K) return;
+  double xt = band[kl], xx = band[K * K + kl];
+  for (int b = 0; b < B; ++b) {
+    const double x = X[(size_t)b * K * K + kl];
+    xt += x * T[(size_t)b * K * K + kl];
+    xx += x * x;
+  }
+  band[kl] = xt;
+  band[K * K + kl] = xx;
+}
+
+// The exact training pair of the band for the correction d = u_t - u_prev:
+// t = c_u d (the target before its division by s_r) and a = A d with the
+// solver's operator (zero Dirichlet, h = 1/(N+1)), d formed in FP64.
+__global__ void k_pair(Ptrs ut, Ptrs up, double* t, double* a, int H, int W) {
+  const int b = blockIdx.y;
+  const long long HW = (long long)H * W;
+  const long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= HW) return;
+  const int y = (int)(p / W), x = (int)(p % W);
+  const double* u1 = ut.p[b];
+  const double* u0 = up.p[b];
+  auto d = [&](long long q) { return u1[q] - u0[q]; };
+  const double cx = (double)(W + 1) * (W + 1), cy = (double)(H + 1) * (H + 1);
+  const double c = d(p);
+  const double w = x > 0 ? d(p - 1) : 0.0, e = x < W - 1 ? d(p + 1) : 0.0;
+  const double sN = y > 0 ? d(p - W) : 0.0, nN = y < H - 1 ? d(p + W) : 0.0;
+  t[(size_t)b * HW + p] = kCu * c;
+  a[(size_t)b * HW + p] = (2.0 * c - w - e) * cx + (2.0 * c - sN - nN) * cy;
 }
 
 // ------------------------------------------------------------------ parameters
@@ -1094,8 +1120,9 @@ void forward(const Net& n, const Ptrs& f, const Ptrs& u, hipStream_t s) {
                                                           a[4], d.H, d.W);
   k_conv_small<C, 1, bf16, float, false, false><<<dim3(cdiv(HW, 256), d.B), 256, 0, s>>>(
       a[4], n.bfw(T_C6W), n.bfw(T_C6B), nullptr, n.w<float>(n.wl.out), d.H, d.W);
-  // spectral skip from the FP64 residual, replacing the band of the
-  // convolutional output: out += norm S^T (gain X - S out S^T) S (FP64)
+  // band path from the FP64 residual, replacing the band of the
+  // convolutional output: out += norm S^T (w X - S out S^T) S (FP64)
+  if (d.K == 0) return;
   double* kT = n.w<double>(n.wl.kT);
   double* kX = n.w<double>(n.wl.kX);
   double* kC = n.w<double>(n.wl.kC);
@@ -1114,8 +1141,8 @@ void forward(const Net& n, const Ptrs& f, const Ptrs& u, hipStream_t s) {
   k_skip_rows<float><<<d.B * d.H, 256, 0, s>>>(out, nullptr, kSxT, kT,
                                                                         d.B, d.H, d.W, K);
   k_cols<double><<<d.B * K * cdiv(K, 64), 256, 0, s>>>(kT, kSy, kC, d.B, d.H, K, K, 1.0);
-  k_skip_gain<<<cdiv((long long)d.B * K * K, 256), 256, 0, s>>>(kX, kC, n.master(T_SKIP), kY, d.B,
-                                                                d.H, d.W, K);
+  k_band_apply<<<cdiv((long long)d.B * K * K, 256), 256, 0, s>>>(
+      kX, kC, (const double*)(n.params + n.pl.band), kY, d.B, K);
   k_skip_inv_cols<<<cdiv((long long)d.B * d.H * K, 256), 256, 0, s>>>(kY, kSy, kZ, d.B, d.H, K,
                                                                       2.0 / (d.H + 1));
   k_skip_out<<<cdiv((long long)d.B * HW, 256), 256, 0, s>>>(kZ, kSx, out, d.B, d.H, d.W, K,
@@ -1162,22 +1189,32 @@ void train(const Net& n, const Ptrs& f, const Ptrs& up, const Ptrs& ut, float* l
     k_loss_sum<<<1, kReduceThreads, 0, s>>>(lpart, nb, ldev, loss, d.B);
   }
   const int ctiles = cdiv(d.W, 64) * cdiv(d.H, 4);
-  // spectral skip gains: dY = norm S[dout], grad = rho (c_u / lambda) sum_b dY X;
-  // then the convolutional branch's gradient off the band: dout -= S^T dY S
-  {
+  // band path (K > 0): its least-squares state takes the batch's sums of
+  // X T and X^2 (X = S[A d/s_r], T = S[t] of the target t = c_u d/s_r,
+  // d = u_t - u_prev); the convolutional branch's gradient is dout off the
+  // band: dout -= norm S^T S[dout] S
+  if (d.K > 0) {
     double* kT = n.w<double>(n.wl.kT);
     double* kdY = n.w<double>(n.wl.kdY);
+    double* kTc = n.w<double>(n.wl.kTc);
     double* kZ = n.w<double>(n.wl.kZ);
     double* kSx = n.w<double>(n.wl.kSx);
     double* kSxT = n.w<double>(n.wl.kSxT);
     double* kSy = n.w<double>(n.wl.kSy);
+    double* tbuf = n.w<double>(n.wl.r0);          // the residual input is no longer needed
+    double* abuf = n.w<double>(n.wl.ad);
+    double* kXa = n.w<double>(n.wl.kXa);
     const int K = d.K;
+    k_pair<<<dim3(cdiv(HW, 256), d.B), 256, 0, s>>>(ut, up, tbuf, abuf, d.H, d.W);
+    k_skip_rows<double><<<d.B * d.H, 256, 0, s>>>(tbuf, sv + d.B, kSxT, kT, d.B, d.H, d.W, K);
+    k_cols<double><<<d.B * K * cdiv(K, 64), 256, 0, s>>>(kT, kSy, kTc, d.B, d.H, K, K, 1.0);
+    k_skip_rows<double><<<d.B * d.H, 256, 0, s>>>(abuf, sv + d.B, kSxT, kT, d.B, d.H, d.W, K);
+    k_cols<double><<<d.B * K * cdiv(K, 64), 256, 0, s>>>(kT, kSy, kXa, d.B, d.H, K, K, 1.0);
+    k_band_fit<<<cdiv((long long)K * K, 256), 256, 0, s>>>(kXa, kTc,
+                                                          (double*)(n.params + n.pl.band), d.B, K);
     const double nrm = (2.0 / (d.H + 1)) * (2.0 / (d.W + 1));
-    k_skip_rows<float><<<d.B * d.H, 256, 0, s>>>(dout, nullptr, kSxT, kT,
-                                                                          d.B, d.H, d.W, K);
+    k_skip_rows<float><<<d.B * d.H, 256, 0, s>>>(dout, nullptr, kSxT, kT, d.B, d.H, d.W, K);
     k_cols<double><<<d.B * K * cdiv(K, 64), 256, 0, s>>>(kT, kSy, kdY, d.B, d.H, K, K, nrm);
-    k_skip_grad<<<cdiv((long long)K * K, 256), 256, 0, s>>>(kdY, n.w<double>(n.wl.kX),
-                                                            n.grad(T_SKIP), d.B, d.H, d.W, K);
     k_skip_inv_cols<<<cdiv((long long)d.B * d.H * K, 256), 256, 0, s>>>(kdY, kSy, kZ, d.B, d.H, K,
                                                                         1.0);
     k_skip_out<<<cdiv((long long)d.B * HW, 256), 256, 0, s>>>(kZ, kSx, dout, d.B, d.H, d.W, K, -1.0);
@@ -1649,7 +1686,7 @@ int net_init(const guess_net_cfg* cfg, void* params, hipStream_t s) {
   int64_t sz[kNumTensors];
   tensor_sizes(cfg, sz);
   const float C = (float)cfg->channels;
-  const float fan[kNumTensors] = {18.f, 0, 9 * C, 0, 2 * C, 0, 2 * C, 9 * C, 0, 9 * C, 0, 0, 0, 0};
+  const float fan[kNumTensors] = {18.f, 0, 9 * C, 0, 2 * C, 0, 2 * C, 9 * C, 0, 9 * C, 0, 0, 0};
   for (int i = 0; i < kNumTensors; ++i) {
     spec.bound[i] = fan[i] > 0 ? sqrtf(6.f / fan[i]) : 0.f;
     spec.size[i] = sz[i];
@@ -1659,6 +1696,9 @@ int net_init(const guess_net_cfg* cfg, void* params, hipStream_t s) {
                                                 (float*)(p + pl.m), (float*)(p + pl.v),
                                                 (bf16*)(p + pl.bf), (long long*)(p + pl.step), spec,
                                                 kNumTensors, pl.P, cfg->seed);
+  // the band's least-squares state starts empty (w = 0)
+  const long long nb = 4LL * cfg->skip_modes * cfg->skip_modes;
+  if (nb > 0) k_fill0<<<cdiv(nb, 256), 256, 0, s>>>((float*)(p + pl.band), nb);
   MLG_HIP(hipGetLastError());
   return MLG_OK;
 }

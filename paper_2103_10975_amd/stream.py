@@ -181,6 +181,7 @@ class StepRecord:
     relres_first_cycle: float
     relres_true: float
     tos: float
+    relres_iter5: float = float("nan")
     train_s: float = 0.0
     loss: float = float("nan")
     extra: dict = field(default_factory=dict)
@@ -213,7 +214,7 @@ class StreamSolver:
                  retrain_steps: int = 32, p: int = 10, f_r: int = 8, cos_max: float = 0.999,
                  train_set: int = 512, network: str = "spectral", fluid_cfg: FluidCfg | None = None,
                  max_blocks: int = 4, grow_window: int = 50, grow_min_gain: float = 0.05,
-                 lin_lr: float = 0.1):
+                 lin_lr: float = 0.1, shadow_cfgs=()):
         if guess not in ("zero", "prev", "learned", "linear"):
             raise ValueError("guess must be zero, prev, learned or linear")
         self.lin_lr = lin_lr
@@ -277,6 +278,18 @@ class StreamSolver:
             self.ws_train = workspace(nbytes(batch, True))
             self.loss = torch.zeros(1, dtype=torch.float32, device="cuda")
             self.replay = ReplayBuffer(replay, seed)
+        # shadow networks (guess_net configurations) trained on exactly the
+        # batches of this stream while train_shadows is set, whose guesses the
+        # solver never uses: they measure other networks on the same pairs
+        self.shadows = []
+        self.train_shadows = True
+        for cfg in shadow_cfgs:
+            prm = torch.zeros(guess_net_param_bytes(cfg), dtype=torch.uint8, device="cuda")
+            guess_net_init(cfg, prm)
+            self.shadows.append({
+                "cfg": cfg, "params": prm,
+                "ws_infer": workspace(guess_net_workspace_bytes(cfg, self.grid, 1, False)),
+                "ws_train": workspace(guess_net_workspace_bytes(cfg, self.grid, batch, True))})
 
     # ------------------------------------------------------------------
     def _guess(self, f: torch.Tensor) -> str:
@@ -312,7 +325,7 @@ class StreamSolver:
             st = gmres_solve(self.grid, f, self.x, self.opts, self.ws)
         tos = time.perf_counter() - t0
         rec = StepRecord(self.t, kind, st.iters, st.cycles, st.relres_init, st.relres_first_cycle,
-                         st.relres_true, tos)
+                         st.relres_true, tos, st.relres_iter5)
         if self.train_enabled and self.t > 0:
             t1 = time.perf_counter()
             steps = self._train_after(f, rec)
@@ -366,6 +379,9 @@ class StreamSolver:
             return
         args = ([b[0] for b in batch], [b[1] for b in batch], [b[2] for b in batch],
                 self.ws_train, self.loss)
+        if self.train_shadows:
+            for sh in self.shadows:
+                guess_net_train_step(sh["cfg"], sh["params"], *args[:3], sh["ws_train"])
         if self.network == "fluid":
             fluid_net_train_step(self.net_cfg, self.params, self.growth.blocks, *args)
             self.growth.observe(float(self.loss.item()))
@@ -374,3 +390,9 @@ class StreamSolver:
 
     def train_step(self) -> None:
         self._train_on(self.replay.sample(self.batch))
+
+    def shadow_guess(self, i: int, f: torch.Tensor, u_prev: torch.Tensor, out: torch.Tensor):
+        """Guess of shadow network i from (f, u_prev) into out (fields of the grid)."""
+        sh = self.shadows[i]
+        guess_net_infer(sh["cfg"], sh["params"], f.view(1, *self.shape),
+                        u_prev.view(1, *self.shape), out.view(1, *self.shape), sh["ws_infer"])

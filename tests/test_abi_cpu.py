@@ -61,3 +61,31 @@ def test_tile_table():
             tx, ty, tz = mlg.mlg_tile_shape(dim, i)
             assert (tx * ty * tz) % 256 == 0 and (dim == 3 or tz == 1)
     assert mlg.mlg_tile_count(5) == 0
+
+
+def test_binding_rejects_mismatched_shapes():
+    """The binding checks shapes and buffer sizes before any library call
+    (CPU tensors would be rejected later; the shape checks come first)."""
+    import pytest
+    import torch
+    import paper_2103_10975_amd as mlg
+    g = mlg.grid_of((8, 8))
+    with pytest.raises(ValueError):
+        mlg.gmres_solve(g, torch.zeros(8, 9, dtype=torch.float64), torch.zeros(8, 9, dtype=torch.float64),
+                        mlg.Opts(), torch.zeros(16, dtype=torch.uint8))
+    with pytest.raises(ValueError):
+        mlg.gmres_solve(g, torch.zeros(8, 8, dtype=torch.float64), torch.zeros(8, 7, dtype=torch.float64),
+                        mlg.Opts(), torch.zeros(16, dtype=torch.uint8))
+    cfg = mlg.NetCfg(skip_modes=4, modes=4)
+    f = torch.zeros(1, 8, 8, dtype=torch.float64)
+    with pytest.raises(ValueError):
+        mlg.guess_net_infer(cfg, torch.zeros(16, dtype=torch.uint8), f, torch.zeros(1, 8, 9), f,
+                            torch.zeros(16, dtype=torch.uint8))
+    with pytest.raises(ValueError):
+        mlg.guess_net_infer(cfg, torch.zeros(16, dtype=torch.uint8), f, f, f,
+                            torch.zeros(16, dtype=torch.uint8))          # parameters too small
+    with pytest.raises(ValueError):
+        mlg.guess_net_train_step(cfg, torch.zeros(16, dtype=torch.uint8), [f[0]], [f[0], f[0]], [f[0]],
+                                 torch.zeros(16, dtype=torch.uint8))
+    with pytest.raises(ValueError):
+        mlg.make_system(torch.zeros(2, 8, 8, dtype=torch.float64), torch.zeros(2, 8, 7, dtype=torch.float64))

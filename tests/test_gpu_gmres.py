@@ -284,3 +284,31 @@ def test_full_size_fp32_refinement_m40(mlg, shape):
     print(f"  relres after 2 cycles {rn / bn:.3e} (first cycle {sg.relres_first_cycle:.3e})")
     assert abs(rn / bn - sg.relres_true) <= 1e-6 * sg.relres_true
     assert sg.cycles == 2 and sg.relres_true < sg.relres_first_cycle < 1.0
+
+
+@pytest.mark.parametrize("shape,m,precision", [((64, 64), 20, 0), ((48, 80), 3, 0),
+                                               ((24, 20, 16), 10, 1)])
+def test_fifth_iteration_residual(mlg, shape, m, precision):
+    """relres_iter5 is the Givens residual estimate after the fifth Arnoldi
+    step: the oracle's history entry 5 (FP64: to 1e-10 relative; with a
+    restart length below 5 it spans a restart, GMRES(3) here; FP32 basis: to
+    1e-5, the FP32 storage of the first five directions), and (FP64) a solve
+    that ends in fewer steps reports its last estimate."""
+    print("fifth-iteration residual", shape, m, precision, flush=True)
+    b = DriftingGaussians(shape, 3, 0.06, seed=33).field(0)
+    _, so, hist = og.gmres(b, m=m, rtol=1e-8, max_iters=200, history=True)
+    _, sg = run(mlg, b, restart_m=m, rtol=1e-8, max_iters=200, precision=precision,
+                allow_not_converged=True)
+    bar = 1e-10 if precision == 0 else 1e-5
+    print(f"  gpu {sg.relres_iter5:.6e} oracle {hist[5]:.6e}")
+    assert abs(sg.relres_iter5 - hist[5]) <= bar * hist[5]
+    if precision != 0:
+        return
+    # an eigenvector right-hand side: one step, the estimate after it
+    n = shape
+    k = [np.arange(1, s + 1) for s in n]
+    phi = np.sin(np.pi * k[0] / (n[0] + 1))[:, None] * np.sin(2 * np.pi * k[1] / (n[1] + 1))[None, :]
+    if len(n) == 3:
+        phi = phi[:, :, None] * np.sin(np.pi * k[2] / (n[2] + 1))[None, None, :]
+    _, s1 = run(mlg, phi, restart_m=m, rtol=1e-8, precision=precision)
+    assert s1.iters == 1 and s1.relres_iter5 <= 1e-8
