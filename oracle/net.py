@@ -26,9 +26,12 @@ design notes of the repository):
            w_kl = sum X T / sum X^2 over the training samples seen (X, T the
            band coefficients of the right-hand side the correction
            u_t - u_prev solves exactly and of the target; see band_stats)
-  out = L6 - P_K L6 + band, P_K the orthogonal projection on the K x K
-        modes: the band path alone sets the output there, the
-        convolutional branch the rest
+  out = gamma (L6 - P_K L6) + band, P_K the orthogonal projection on the
+        K x K modes: the band path alone sets the output there, the
+        convolutional branch the rest, scaled by its output gain gamma (the
+        least-squares gain of that branch against the off-band targets of
+        recent training batches, see gate_stats; 1 while training and while
+        no batch has been seen)
   guess = u_prev + (s_r / c_u) * out, c_u = 2 pi^2
 Convolutions are cross-correlations with zero padding (the Dirichlet zero),
 weights in [out, in, ky, kx] layout.  Everything is float64, NCHW, written
@@ -181,6 +184,21 @@ def band_stats(f: np.ndarray, u_prev: np.ndarray, u_target: np.ndarray, K: int):
     return np.sum(X * T, axis=0), np.sum(X * X, axis=0)
 
 
+def gate_stats(params: dict, f, u_prev, u_target):
+    """The sums a training batch adds to the output gain's least-squares
+    state: (sum_b <c_b, t_b>, sum_b |c_b|^2) with c_b the convolutional
+    branch's output off the band (L6 - P_K L6) and t_b the target off the
+    band; gamma = their ratio minimises sum_b |gamma c_b - t_b|^2.  Requires
+    a band path (K > 0)."""
+    K = band_modes(params)
+    _, _, s, c = forward({**params, "gate": 1.0}, f, u_prev, keep=True)
+    c6 = conv3x3(c["a5"], params["conv6.w"], params["conv6.b"])[:, 0]
+    co = c6 - band_project(c6, K)
+    t = target(u_target, u_prev, s)
+    to = t - band_project(t, K)
+    return float(np.sum(co * to)), float(np.sum(co * co))
+
+
 # ---------------------------------------------------------------- network
 def band_modes(params: dict) -> int:
     """K of the band path (0: no band path)."""
@@ -203,7 +221,7 @@ def forward(params: dict, f: np.ndarray, u_prev: np.ndarray, keep: bool = False)
     out = c6
     if K > 0:
         band, _ = skip_forward(x0[:, 0], params["band.w"])
-        out = c6 - band_project(c6, K) + band
+        out = params.get("gate", 1.0) * (c6 - band_project(c6, K)) + band
     guess = u_prev + (s_r / C_U)[:, None, None] * out
     if keep:
         c.update(a1=a1, a2=a2, a3=a3, a4=a4, a5=a5, spec=sc)
@@ -218,9 +236,10 @@ def target(u_target: np.ndarray, u_prev: np.ndarray, s: np.ndarray) -> np.ndarra
 
 def loss_and_grads(params: dict, f, u_prev, u_target):
     """L = (1/B) sum_b |out_b - t_b|_2^2 and its gradient for every parameter
-    trained by gradient (all but the band weights)."""
+    trained by gradient (all but the band weights and the output gain; the
+    convolutional branch trains on its raw output, gain 1)."""
     B = f.shape[0]
-    _, out, s, c = forward(params, f, u_prev, keep=True)
+    _, out, s, c = forward({**params, "gate": 1.0}, f, u_prev, keep=True)
     t = target(u_target, u_prev, s)
     diff = out - t
     loss = float(np.sum(diff ** 2) / B)

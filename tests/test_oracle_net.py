@@ -346,6 +346,38 @@ def test_band_fit_is_the_least_squares_minimiser():
         assert abs(Lp - Lm) <= 1e-6 * abs(Lz - L_zero)
 
 
+def test_output_gain_is_the_least_squares_scale_of_the_branch():
+    """gate_stats: gamma = <c, t> / |c|^2 minimises |gamma c - t|^2 over the
+    off-band part (brute force over a scan of gammas), and with that gamma
+    the network's loss off the band is the minimum over gains; gamma = 0
+    gives the band-only guess, gamma = 1 the raw network."""
+    H, W, K, B = 10, 9, 3, 2
+    rng = np.random.default_rng(29)
+    p = guess_net_params(31, channels=4, modes=3, zero_last=False, skip_modes=K)
+    f = rng.standard_normal((B, H, W))
+    u = rng.standard_normal((B, H, W)) * 0.05
+    ut = u + rng.standard_normal((B, H, W)) * 0.05
+    sct, scc = net.gate_stats(p, f, u, ut)
+    g = sct / scc
+    losses = [net.loss_and_grads({**p, "band.w": p["band.w"]}, f, u, ut)[0]]
+    _, out1, s = net.forward({**p, "gate": 1.0}, f, u)
+    t = net.target(ut, u, s)
+
+    def off_loss(gamma):
+        _, out, _ = net.forward({**p, "gate": gamma}, f, u)
+        d = out - t
+        return float(np.sum((d - net.band_project(d, K)) ** 2))
+    scan = np.linspace(g - 1.0, g + 1.0, 41)
+    assert min(off_loss(x) for x in scan) >= off_loss(g) - 1e-12 * off_loss(g)
+    assert off_loss(g) <= off_loss(1.0) and off_loss(g) <= off_loss(0.0)
+    # the training loss does not see the gain
+    assert net.loss_and_grads({**p, "gate": 0.3}, f, u, ut)[0] == losses[0]
+    g0, _, _ = net.forward({**p, "gate": 0.0}, f, u)
+    pb = {**p, "conv6.w": np.zeros_like(p["conv6.w"]), "conv6.b": np.zeros_like(p["conv6.b"])}
+    gb, _, _ = net.forward(pb, f, u)
+    assert np.allclose(g0, gb, rtol=1e-13, atol=1e-15)
+
+
 def test_adam_first_step_closed_form_and_torch():
     rng = np.random.default_rng(3)
     p = {"a": rng.standard_normal((4, 5)), "b": rng.standard_normal(3)}
