@@ -77,6 +77,9 @@ def parse():
     ap.add_argument("--probe-grid", default=None,
                     help="with --probe: another workload, e.g. 1024x1024:fp64:30, "
                          "2048x2048:fp32:40 or 160x160x160:fp32:40")
+    ap.add_argument("--probe-tile", type=int, default=0,
+                    help="with --probe-grid: this tile index (1-based) instead of the autotuned "
+                         "one; every step fused in the split form for step/sums, none otherwise")
     return ap.parse_args()
 
 
@@ -454,6 +457,7 @@ def main():
                     "E_k_median": statistics.median(r.relres_first_cycle for r in timed),
                     "relres_iter5_median": statistics.median(r.relres_iter5 for r in timed),
                     "guess_kinds": sorted(set(r.guess for r in timed)),
+                    "conv_output_gain": mlg.net_output_gain(sv.net_cfg, sv.params),
                     "band_weight_error_vs_analytic": {
                         "max_16x16": float(werr[:16, :16].max()), "median_band": float(np.median(werr))}},
         # the whole stream of the in-situ method, training included
@@ -539,8 +543,11 @@ def probe(mlg, shape, args):
         shape = tuple(int(v) for v in dims.split("x"))
         opts = mlg.Opts(restart_m=int(m), rtol=1e-10,
                         precision=mlg.MLG_FP64 if prec == "fp64" else mlg.MLG_FP32_IR)
-        tile, fused, split = mlg.mlg_autotune(mlg.grid_of(shape), opts)
-        runs = [(tile, fused, split)]
+        if args.probe_tile:
+            allm = (1 << int(m)) - 1 if args.probe in ("step", "sums") and len(shape) == 2 else 0
+            runs = [(args.probe_tile, allm, allm)]
+        else:
+            runs = [mlg.mlg_autotune(mlg.grid_of(shape), opts)]
     else:
         opts = mlg.Opts(restart_m=args.restart, rtol=args.rtol, precision=mlg.MLG_FP32_IR)
         fused = (1 << args.restart) - 1 if args.probe in ("step", "sums") else 0

@@ -234,9 +234,13 @@ int mlg_autotune(const mlg_grid* grid, const mlg_opts* opts, void* ws, size_t ws
  *      exactly, so (A d, d) is an exact pair: the minimiser of the loss over
  *      w on those pairs, which Adam could not reach at the precision GMRES
  *      needs as the optimal weights span several orders of magnitude);
- *   out = L6 - P_K L6 + band, P_K the orthogonal projection on the band: the
- *      band path alone sets the output there, the convolutions the rest
- *      (K = 0: out = L6, the network without a band path);
+ *   out = g (L6 - P_K L6) + band, P_K the orthogonal projection on the band:
+ *      the band path alone sets the output there, the convolutions the rest,
+ *      scaled at inference by their output gain g (the least-squares scale
+ *      of the branch's off-band output against the off-band targets, from
+ *      running sums over the training batches that decay by 0.9 per step; 1
+ *      before any batch; training sees g = 1) (K = 0: out = L6, the network
+ *      without a band path);
  *   guess = u_prev + (s_r / c_u) out  (= u_prev when u_prev solves A u = f).
  * Weights and activations are BF16 in the kernels with FP32 accumulation;
  * FP32 master weights and Adam moments (Section 2.3: back-propagation and
@@ -261,6 +265,8 @@ typedef struct {
  *                      ([ky][kx]) then sxx; w = sxt / sxx (0 where sxx = 0).
  *                      A caller may write it directly (e.g. sxt = w,
  *                      sxx = 1 to impose weights w).
+ *   gate    FP64 [2]   output gain state: sums of <c, t> and |c|^2 (g = their
+ *                      ratio; 1 while the second is 0)
  * Tensor order inside each FP32/BF16 array (shapes [out, in, ky, kx]):
  *   conv1.w [C,2,3,3] conv1.b [C] conv2.w [C,C,3,3] conv2.b [C]
  *   spec.w1 [C,C] spec.b [C] spec.wk [M,M,C,C] (= [ky, kx, out, in])
@@ -278,8 +284,8 @@ size_t guess_net_workspace_bytes(const guess_net_cfg* cfg, const mlg_grid* grid,
                                  int32_t batch, int32_t train);
 
 /* Deterministic initialisation from cfg->seed: He-uniform weights, zero
- * biases, zero output layer and an empty band state (w = 0), so the untrained
- * network returns u_prev; zero Adam state. */
+ * biases, zero output layer, an empty band state (w = 0) and gain state, so
+ * the untrained network returns u_prev; zero Adam state. */
 int guess_net_init(const guess_net_cfg* cfg, void* params, void* stream);
 
 /* Recompute the BF16 working copy from the FP32 master weights (after the

@@ -26,7 +26,7 @@ __all__ = [
     "fluid_net_infer", "fluid_net_train_step", "linear_guess_param_bytes",
     "linear_guess_workspace_bytes", "linear_guess_init", "linear_guess_infer",
     "linear_guess_train_step", "mlg_last_error", "mlg_shutdown", "MlgError", "EXPORTS",
-    "net_views", "net_pack", "net_unpack", "net_band_weights", "net_set_band",
+    "net_views", "net_pack", "net_unpack", "net_band_weights", "net_set_band", "net_output_gain",
 ]
 
 HERE = os.path.dirname(os.path.abspath(__file__))
@@ -440,7 +440,16 @@ def net_views(cfg, params: torch.Tensor) -> dict:
         K = cfg.skip_modes
         band = step + 256
         out["band"] = params[band:band + 16 * K * K].view(torch.float64).view(2, K, K)
+        gate = band + _align(16 * K * K)
+        out["gate"] = params[gate:gate + 16].view(torch.float64)
     return out
+
+
+def net_output_gain(cfg: NetCfg, params: torch.Tensor) -> float:
+    """The convolutional branch's output gain applied at inference (1 before
+    any training batch)."""
+    g = net_views(cfg, params)["gate"].cpu()
+    return float(g[0] / g[1]) if g[1] > 0 else 1.0
 
 
 def net_band_weights(cfg: NetCfg, params: torch.Tensor) -> torch.Tensor:

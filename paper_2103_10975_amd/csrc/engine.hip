@@ -199,8 +199,13 @@ static Plan make_plan(int nsys, const mlg_system* sys, const mlg_opts& o) {
     P.off_ctrl[i] = take(sizeof(Ctrl));
     P.off_part[i] = take((size_t)(2 * kMaxRestart + 2) * g.nblk * 8);
     P.off_r[i] = take((size_t)g.n * 8);
-    // m basis vectors v_0..v_{m-1}, then the two directions u_j, u_{j+1}
-    P.off_V[i] = take((size_t)(o.restart_m + 2) * g.ldv * P.s);
+    // m basis vectors v_0..v_{m-1}, then the two directions u_j, u_{j+1};
+    // the sweeps address the region with 32-bit byte offsets
+    const size_t vbytes = (size_t)(o.restart_m + 2) * g.ldv * P.s;
+    if (vbytes >= (1ULL << 32))
+      throw ArgError{MLG_ERR_ARG, "a system's Krylov basis would exceed 4 GiB: use a smaller "
+                                  "restart length, the FP32 basis or a smaller grid"};
+    P.off_V[i] = take(vbytes);
   }
   P.total = o_;
   return P;

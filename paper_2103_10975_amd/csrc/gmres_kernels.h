@@ -213,16 +213,16 @@ __device__ __forceinline__ void buf_store(Rsrc r, unsigned e, double v, unsigned
       vo, 0);
 }
 
-// The basis region of a system: one descriptor whose range is one vector
-// (n elements); vector k starts k * ldv elements in, selected by the scalar
-// offset.  The whole region lies within 4 GiB of its start (checked on the
-// host), so every vector's byte offset fits the 32-bit scalar offset.
+// The basis region of a system: one descriptor over all m + 2 vectors;
+// vector k starts k * ldv elements in, selected by the scalar offset.  The
+// region is smaller than 4 GiB (checked on the host), so every byte offset
+// fits 32 bits and every access passes the descriptor's range check.
 template <class T>
 struct BasisBuf {
   Rsrc r;
   unsigned vb;                      // bytes between vectors
-  __device__ __forceinline__ BasisBuf(const T* V, const Geo& g)
-      : r(vec_rsrc(V, g.n)), vb((unsigned)(g.ldv * (long long)sizeof(T))) {}
+  __device__ __forceinline__ BasisBuf(const T* V, const Geo& g, int m)
+      : r(vec_rsrc(V, (long long)(m + 2) * g.ldv)), vb((unsigned)(g.ldv * (long long)sizeof(T))) {}
   __device__ __forceinline__ T load(int k, unsigned e) const {
     return buf_load<T>(r, e, (unsigned)k * vb);
   }
@@ -391,12 +391,15 @@ __device__ __forceinline__ double lane_bcast(double v, int src) {
 }
 
 // The basis at N points per thread, every load issued at once and
-// unconditionally: slots k >= `live` re-read the last live vector (or
-// vector 0) and are never used, so no branch separates the loads.
+// unconditionally: slots k >= `live` re-read the last live vector (vector
+// `spare` when none is live), so no branch separates the loads.  Those slots
+// may meet zero coefficients (an exact no-op) but are otherwise unused; they
+// must hold finite data, which written vectors do (a slot not yet written
+// in this cycle may not).
 template <int MM, int N, class T>
 __device__ __forceinline__ void load_basis(T (&v)[MM][N], const BasisBuf<T>& B,
-                                           const long long (&p)[N], int live) {
-  const int last = live > 0 ? live - 1 : 0;
+                                           const long long (&p)[N], int live, int spare) {
+  const int last = live > 0 ? live - 1 : spare;
 #pragma unroll
   for (int k = 0; k < MM; ++k) {
 #pragma unroll
@@ -634,7 +637,7 @@ __global__ __launch_bounds__(kBlock) void k_dots(const Job* jobs, const SysDesc*
   __shared__ double L[TL::LSZ];
   __shared__ double red[4 * NS];
   const Geo g = me.job.g;
-  const BasisBuf<T> VB((const T*)me.job.V, g);
+  const BasisBuf<T> VB((const T*)me.job.V, g, me.job.m);
   const int kU = me.job.m + (j & 1);
   double acc[MM / 8 + 1];
 #pragma unroll
@@ -655,7 +658,7 @@ __global__ __launch_bounds__(kBlock) void k_dots(const Job* jobs, const SysDesc*
       qc[i][2] = pr.qz;
     }
     T vr[MM][PPT];
-    load_basis<MM, PPT, T>(vr, VB, pp, j);
+    load_basis<MM, PPT, T>(vr, VB, pp, j, kU);
     __syncthreads();
     load_tile_buf<TL, T>(L, VB, kU, g, ox, oy, oz);
     __syncthreads();
@@ -950,7 +953,7 @@ __global__ __launch_bounds__(kBlock) void k_extend(const Job* jobs, const SysDes
     cY[k] = k < j ? C->cY[k] : 0.0;
   }
   const Geo g = me.job.g;
-  const BasisBuf<T> VB((const T*)me.job.V, g);
+  const BasisBuf<T> VB((const T*)me.job.V, g, me.job.m);
   const int kU = me.job.m + (j & 1), kUn = me.job.m + ((j + 1) & 1);
   const double ainv = 1.0 / C->alpha;
   const double cyj = C->cY[j];
@@ -970,7 +973,7 @@ __global__ __launch_bounds__(kBlock) void k_extend(const Job* jobs, const SysDes
       qc[i][2] = pr.qz;
     }
     T vr[MM][PPT];
-    load_basis<MM, PPT, T>(vr, VB, pp, j);
+    load_basis<MM, PPT, T>(vr, VB, pp, j, kU);
     __syncthreads();
     load_tile_buf<TL, T>(L, VB, kU, g, ox, oy, oz);
     __syncthreads();
@@ -1043,7 +1046,7 @@ __global__ __launch_bounds__(kBlock) void k_step(const Job* jobs, const SysDesc*
   __shared__ double sAlpha;
   __shared__ int sFlag;
   const Geo g = me.job.g;
-  const BasisBuf<T> VB((const T*)me.job.V, g);
+  const BasisBuf<T> VB((const T*)me.job.V, g, me.job.m);
   const int kU = me.job.m + (j & 1), kUn = me.job.m + ((j + 1) & 1);
   const bool writer = me.job.lblk == 0;
   const int c = j - 1;
@@ -1123,7 +1126,9 @@ __global__ __launch_bounds__(kBlock) void k_step(const Job* jobs, const SysDesc*
     }
     T vr[MM][PPT];                                    // basis at this thread's points
     T vg[MM][RPT];                                    // basis at this thread's ring points
-    const int jl = j > 0 ? j - 1 : 0;
+    // padded slots: v_{j-1}, or at j = 0 (no basis vector written yet in
+    // this cycle) the direction u_j itself
+    const int jl = j > 0 ? j - 1 : kU;
 #pragma unroll
     for (int k = 0; k < MM; ++k) {
       const int kk = k < j ? k : jl;
@@ -1333,7 +1338,7 @@ __global__ __launch_bounds__(kBlock) void k_update(const Job* jobs, const SysDes
   for (int l = threadIdx.x; l < MM; l += kBlock) ys[l] = l < k ? C->y[l] : 0.0;
   __syncthreads();
   const Geo g = me.job.g;
-  const BasisBuf<T> VB((const T*)me.job.V, g);
+  const BasisBuf<T> VB((const T*)me.job.V, g, me.job.m);
   const Rsrc rx = vec_rsrc(C->x0 + (size_t)C->rhs * g.n, g.n);
   for (int tile = me.job.t0; tile < me.job.t1; ++tile) {
     int ox, oy, oz;
@@ -1347,7 +1352,7 @@ __global__ __launch_bounds__(kBlock) void k_update(const Job* jobs, const SysDes
       pp[i] = pr.valid ? pr.p : 0;
     }
     T vr[MM][PPT];
-    load_basis<MM, PPT, T>(vr, VB, pp, k);
+    load_basis<MM, PPT, T>(vr, VB, pp, k, me.job.m);
     double xs[PPT];
 #pragma unroll
     for (int i = 0; i < PPT; ++i) xs[i] = buf_load<double>(rx, (unsigned)pp[i]);

@@ -13,14 +13,17 @@
 //   a3 = ReLU(W1 a2 + b + S^-1[Wk . S[a2]])           (spectral mixing)
 //   a4 = ReLU(conv3x3(a3))          a5 = ReLU(conv3x3(a4))
 //   c6 = conv3x3(a5) (1 channel, FP32)
-//   out = c6 - P_K c6 + S^-1[w_kl S[r/s_r]_kl]        (band path, FP64; K = 0: out = c6)
+//   out = g (c6 - P_K c6) + S^-1[w_kl S[r/s_r]_kl]    (band path, FP64; K = 0: out = c6)
 //       (P_K: projection on the K x K band; the band path alone sets the
 //       output there.  Its per-mode weights w = sxt / sxx are learned from the
 //       training pairs by least squares: every train step adds the batch's
 //       sums of X T and X^2, X and T the band coefficients of A d and of the
 //       target c_u d / s_r for the correction d = u_t - u_prev -- u_t solves
 //       A u_t = f - r_fin exactly, so (A d, d) is an exact pair -- the
-//       minimiser of the loss over w on those pairs)
+//       minimiser of the loss over w on those pairs; g, the output gain of
+//       the convolutional branch, is the least-squares scale of its off-band
+//       output against the off-band targets of recent batches, applied at
+//       inference only)
 //   guess = u_prev + (s_r/c_u) out
 // The 3x3 convolutions with C -> C channels (forward, input gradient and
 // weight gradient) run on MFMA (v_mfma_f32_16x16x32_bf16) as implicit GEMMs
@@ -89,7 +92,7 @@ void check_cfg(const guess_net_cfg* cfg) {
 struct ParamLayout {
   int64_t P;
   int64_t off[kNumTensors + 1];
-  size_t master, grad, m, v, bf, step, band, total;
+  size_t master, grad, m, v, bf, step, band, gate, total;
 };
 
 ParamLayout param_layout(const guess_net_cfg* cfg) {
@@ -109,7 +112,9 @@ ParamLayout param_layout(const guess_net_cfg* cfg) {
   L.step = L.bf + align_up((size_t)L.P * 2, 256);
   // the band's least-squares state: FP64 sums of X T, then of X^2, [K][K] each
   L.band = L.step + 256;
-  L.total = L.band + align_up((size_t)2 * cfg->skip_modes * cfg->skip_modes * 8, 256);
+  // the output gain's least-squares state: FP64 sums of <c, t> and |c|^2
+  L.gate = L.band + align_up((size_t)2 * cfg->skip_modes * cfg->skip_modes * 8, 256);
+  L.total = L.gate + 256;
   return L;
 }
 
@@ -393,67 +398,149 @@ __global__ __launch_bounds__(256) void k_conv_small(const TIN* in, const bf16* w
   store_ch<COUT>(out + ((size_t)b * HW + p) * COUT, acc);
 }
 
-// Partial weight/bias gradients of a thin convolution (CIN -> COUT with one
-// side small): per workgroup,
-//   part[blk][(t*COUT + d)*CIN + c] = sum over its pixels of dz[p][d] in[p+off(t)][c],
-//   part[blk][9*COUT*CIN + d] = sum dz[p][d].
-// A workgroup walks tiles of 4 rows x 64 columns (grid-stride over all
-// samples' tiles); each tile's input (one-pixel halo, zero outside the image)
-// and output gradient are staged in LDS, and every thread sums its weight
-// entries over the tile from LDS.
-template <int CIN, int COUT, class TDZ>
-__global__ __launch_bounds__(256) void k_wgrad_thin(const bf16* in, const TDZ* dz, float* part,
-                                                    int B, int H, int W) {
-  constexpr int TW = 64, TH = 4, LW = TW + 2, LH = TH + 2;
-  constexpr int NOUT = 9 * COUT * CIN + COUT;
-  constexpr int PER = (NOUT + 255) / 256;
-  __shared__ float xl[LH * LW * CIN];
-  __shared__ float gl[TH * TW * COUT];
-  const int tx = (W + TW - 1) / TW, ty = (H + TH - 1) / TH;
-  const int ntiles = B * tx * ty;
+// Weight gradient of the C -> 1 output convolution (C = 32):
+// dW[t][c] = sum_p dout[p] a[p + off(t)][c], db = sum_p dout[p].  With
+// q = p + off(t) every input pixel q is read once (its 8-channel chunk, 16
+// bytes) and multiplied by the 3x3 neighbourhood of dout around it (from
+// LDS); a thread keeps its 9 x 8 running sums over every pixel it visits
+// (persistent over 64 x 4 tiles), and each wavefront (one channel chunk)
+// sums its lanes at the end.  part[blk][t * C + c], bias at [9 C].
+template <int C>
+__global__ __launch_bounds__(256) void k_wgrad_out(const bf16* a, const float* dout, float* part,
+                                                   int B, int H, int W) {
+  static_assert(C == 32, "four wavefronts, one 8-channel chunk each");
+  constexpr int TX = 64, TY = 4, LX = TX + 2, LY = TY + 2;
+  __shared__ float dl[LY * LX];
+  const int lane = threadIdx.x & 63, cg = threadIdx.x >> 6;
+  float acc[9][8];
+#pragma unroll
+  for (int t = 0; t < 9; ++t)
+#pragma unroll
+    for (int e = 0; e < 8; ++e) acc[t][e] = 0.f;
+  float bacc = 0.f;
+  const int tilesx = (W + TX - 1) / TX, tilesy = (H + TY - 1) / TY;
+  const int per_img = tilesx * tilesy, ntiles = B * per_img;
   const long long HW = (long long)H * W;
-  float acc[PER];
-#pragma unroll
-  for (int i = 0; i < PER; ++i) acc[i] = 0.f;
   for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
-    const int b = tile / (tx * ty), r = tile % (tx * ty);
-    const int y0 = (r / tx) * TH, x0 = (r % tx) * TW;
+    const int b = tile / per_img, r0 = tile % per_img;
+    const int ox = (r0 % tilesx) * TX, oy = (r0 / tilesx) * TY;
     __syncthreads();
-    for (int e = threadIdx.x; e < LH * LW * CIN; e += 256) {
-      const int c = e % CIN, q = e / CIN, lx = q % LW, ly = q / LW;
-      const int y = y0 + ly - 1, x = x0 + lx - 1;
-      xl[e] = (y >= 0 && y < H && x >= 0 && x < W)
-                  ? bf2f(in[((size_t)b * HW + (long long)y * W + x) * CIN + c]) : 0.f;
-    }
-    for (int e = threadIdx.x; e < TH * TW * COUT; e += 256) {
-      const int d = e % COUT, q = e / COUT, px = q % TW, py = q / TW;
-      const int y = y0 + py, x = x0 + px;
-      gl[e] = (y < H && x < W) ? to_f(dz[((size_t)b * HW + (long long)y * W + x) * COUT + d]) : 0.f;
+    for (int e = threadIdx.x; e < LY * LX; e += 256) {
+      const int gy = oy + e / LX - 1, gx = ox + e % LX - 1;
+      dl[e] = (gy >= 0 && gy < H && gx >= 0 && gx < W) ? dout[(size_t)b * HW + (long long)gy * W + gx] : 0.f;
     }
     __syncthreads();
+    const int x = ox + lane;
 #pragma unroll
-    for (int i = 0; i < PER; ++i) {
-      const int e = threadIdx.x + 256 * i;
-      if (e >= NOUT) continue;
-      float s = 0.f;
-      if (e < 9 * COUT * CIN) {
-        const int t = e / (COUT * CIN), rr = e % (COUT * CIN), d = rr / CIN, c = rr % CIN;
-        const int dy = t / 3, dx = t % 3;              // halo offsets of the tap
-        for (int py = 0; py < TH; ++py)
-#pragma unroll 8
-          for (int px = 0; px < TW; ++px)
-            s += gl[(py * TW + px) * COUT + d] * xl[((py + dy) * LW + px + dx) * CIN + c];
-      } else {
-        const int d = e - 9 * COUT * CIN;
-        for (int q = 0; q < TH * TW; ++q) s += gl[q * COUT + d];
+    for (int r = 0; r < TY; ++r) {
+      const int y = oy + r;
+      if (y >= H || x >= W) continue;
+      float v[8];
+      load_ch<8>(a + ((size_t)b * HW + (long long)y * W + x) * C + cg * 8, v);
+#pragma unroll
+      for (int t = 0; t < 9; ++t) {
+        // dout at q - off(t): halo row r + 2 - ky, column lane + 2 - kx
+        const float w = dl[(r + 2 - t / 3) * LX + lane + 2 - t % 3];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) acc[t][e] = fmaf(w, v[e], acc[t][e]);
       }
-      acc[i] += s;
+      if (cg == 0) bacc += dl[(r + 1) * LX + lane + 1];
     }
   }
+  float* pb = part + (size_t)blockIdx.x * (9 * C + 1);
 #pragma unroll
-  for (int i = 0; i < PER; ++i) {
-    const int e = threadIdx.x + 256 * i;
-    if (e < NOUT) part[(size_t)blockIdx.x * NOUT + e] = acc[i];
+  for (int t = 0; t < 9; ++t)
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      const float sum = wave_sum_f32(acc[t][e]);
+      if (lane == 0) pb[t * C + cg * 8 + e] = sum;
+    }
+  const float bs = wave_sum_f32(bacc);
+  if (threadIdx.x == 0) pb[9 * C] = bs;
+}
+
+// Weight gradient of the 2 -> C input convolution (C = 32):
+// dW[t][d][c] = sum_p dz[p][d] x[p + off(t)][c] (c < 2), db[d] = sum_p dz[p][d].
+// A thread takes 4 output channels of one tile column (tiles of 32 x 8
+// pixels, persistent): per pixel one 8-byte read of dz and the 3x3 x 2
+// neighbourhood of x from LDS, 4 x 9 x 2 running sums; the 32 lanes of a
+// channel group sum at the end.  part[blk][(t * C + d) * 2 + c], bias at
+// [18 C + d].
+template <int C>
+__global__ __launch_bounds__(256) void k_wgrad_in(const bf16* x, const bf16* dz, float* part,
+                                                  int B, int H, int W) {
+  static_assert(C == 32, "eight channel groups of four");
+  constexpr int TX = 32, TY = 8, LX = TX + 2, LY = TY + 2;
+  __shared__ float xl[LY * LX * 2];
+  const int l32 = threadIdx.x & 31, dg = threadIdx.x >> 5;
+  float acc[4][9][2], bacc[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    bacc[q] = 0.f;
+#pragma unroll
+    for (int t = 0; t < 9; ++t) acc[q][t][0] = acc[q][t][1] = 0.f;
+  }
+  const int tilesx = (W + TX - 1) / TX, tilesy = (H + TY - 1) / TY;
+  const int per_img = tilesx * tilesy, ntiles = B * per_img;
+  const long long HW = (long long)H * W;
+  for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    const int b = tile / per_img, r0 = tile % per_img;
+    const int ox = (r0 % tilesx) * TX, oy = (r0 / tilesx) * TY;
+    __syncthreads();
+    for (int e = threadIdx.x; e < LY * LX; e += 256) {
+      const int gy = oy + e / LX - 1, gx = ox + e % LX - 1;
+      float v0 = 0.f, v1 = 0.f;
+      if (gy >= 0 && gy < H && gx >= 0 && gx < W) {
+        const bf16* px = x + ((size_t)b * HW + (long long)gy * W + gx) * 2;
+        v0 = bf2f(px[0]);
+        v1 = bf2f(px[1]);
+      }
+      xl[2 * e] = v0;
+      xl[2 * e + 1] = v1;
+    }
+    __syncthreads();
+    const int gx = ox + l32;
+#pragma unroll 2
+    for (int r = 0; r < TY; ++r) {
+      const int gy = oy + r;
+      if (gy >= H || gx >= W) continue;
+      const uint2 du = *reinterpret_cast<const uint2*>(dz + ((size_t)b * HW + (long long)gy * W + gx) * C + dg * 4);
+      const float d4[4] = {__uint_as_float(du.x << 16), __uint_as_float(du.x & 0xffff0000u),
+                           __uint_as_float(du.y << 16), __uint_as_float(du.y & 0xffff0000u)};
+#pragma unroll
+      for (int t = 0; t < 9; ++t) {
+        // x at p + off(t): halo row r + ky, column l32 + kx
+        const int o = 2 * ((r + t / 3) * LX + l32 + t % 3);
+        const float x0 = xl[o], x1 = xl[o + 1];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          acc[q][t][0] = fmaf(d4[q], x0, acc[q][t][0]);
+          acc[q][t][1] = fmaf(d4[q], x1, acc[q][t][1]);
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < 4; ++q) bacc[q] += d4[q];
+    }
+  }
+  // sum the 32 lanes of this channel group (fixed pairing)
+  auto half_sum = [](float v) {
+#pragma unroll
+    for (int m = 16; m >= 1; m >>= 1) v += __shfl_xor(v, m, 64);
+    return v;
+  };
+  float* pb = part + (size_t)blockIdx.x * (18 * C + C);
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int d = dg * 4 + q;
+#pragma unroll
+    for (int t = 0; t < 9; ++t)
+#pragma unroll
+      for (int c = 0; c < 2; ++c) {
+        const float sum = half_sum(acc[q][t][c]);
+        if (l32 == 0) pb[(t * C + d) * 2 + c] = sum;
+      }
+    const float bs = half_sum(bacc[q]);
+    if (l32 == 0) pb[18 * C + d] = bs;
   }
 }
 
@@ -484,190 +571,269 @@ __global__ void k_wgrad_reduce(const float* part, int nblk, int ntap, int cout, 
 }
 
 // ------------------------------------------------------------------ MFMA convolutions
-// 3x3 convolution C -> C on a 64 x 4 pixel tile (one row per wavefront) as an
-// implicit GEMM: M = 16 pixels, N = 16 channels, K = 32 input channels of one
-// tap per v_mfma_f32_16x16x32_bf16.  Forward: bias + ReLU epilogue.  DGRAD:
-// flipped-transposed weights, epilogue multiplies by (mask > 0).  RES: a
-// linear epilogue (bias in the forward form) that adds `mask` as a residual
-// (none when it is NULL); each output element reads only its own residual
-// element, so `out` may alias it.
+// 3x3 convolution C -> C (C = 32), persistent over 64 x 8 pixel tiles of all
+// B images, on v_mfma_f32_16x16x32_bf16 with the roles
+//   A = weights (16 output channels x 32 input channels of one tap), held in
+//       registers for the whole launch (9 taps x 2 output tiles);
+//   B = input (32 input channels x 16 pixels), read from the LDS tile (one
+//       16-byte read per lane, a contiguous 1 KB per wavefront);
+//   D = 16 output channels x 16 pixels: a lane holds 4 consecutive channels
+//       of one pixel, written as one 8-byte store.
+// Wavefront w computes rows 2w, 2w+1 of the tile; the next tile's input is
+// loaded into registers while the current one is computed.  Forward: bias +
+// ReLU epilogue.  DGRAD: flipped-transposed weights, epilogue multiplies by
+// (mask > 0).  RES: a linear epilogue (bias in the forward form) that adds
+// `mask` as a residual (none when it is NULL); each output element reads only
+// its own residual element, so `out` may alias it.
+constexpr int kConvTX = 64, kConvTY = 8;
+
 template <int C, bool DGRAD, bool RES = false>
 __global__ __launch_bounds__(256) void k_conv_mfma(const bf16* in, const bf16* wt, const bf16* bias,
-                                                   const bf16* mask, bf16* out, int H, int W) {
-  constexpr int TX = 64, TY = 4, LX = TX + 2, LY = TY + 2;
-  constexpr int CP = C + 8;              // padded channel pitch (16 B) against bank conflicts
-  constexpr int NT = C / 16, KS = C / 32;
-  __shared__ __attribute__((aligned(16))) bf16 tin[LY * LX * CP];
-  __shared__ __attribute__((aligned(16))) bf16 wl[9 * C * CP];
-  __shared__ float bl[C];
-  const int tilesx = (W + TX - 1) / TX;
-  const int ox = (blockIdx.x % tilesx) * TX, oy = (blockIdx.x / tilesx) * TY;
-  const int b = blockIdx.y;
-  const long long HW = (long long)H * W;
-  const bf16* inb = in + (size_t)b * HW * C;
-  // weights -> wl[t][n][k], read in the tensor's own order (coalesced) and
-  // scattered into LDS: forward wt[n][k][t], input gradient wt[k][n][8 - t]
-  for (int e = threadIdx.x; e < 9 * C * C; e += 256) {
-    const int i0 = e / (C * 9), i1 = (e / 9) % C, tt = e % 9;
-    const bf16 v = wt[e];
-    if (DGRAD) wl[((8 - tt) * C + i1) * CP + i0] = v;
-    else wl[(tt * C + i0) * CP + i1] = v;
-  }
-  for (int e = threadIdx.x; e < C; e += 256) bl[e] = (!DGRAD) ? bf2f(bias[e]) : 0.f;
-  // input tile with a one-pixel halo, 16-byte chunks
-  constexpr int CH = C / 8;
-  for (int e = threadIdx.x; e < LY * LX * CH; e += 256) {
-    const int pix = e / CH, ch = e % CH;
-    const int ly = pix / LX, lx = pix % LX;
-    const int gy = oy + ly - 1, gx = ox + lx - 1;
-    uint4 v = make_uint4(0, 0, 0, 0);
-    if (gy >= 0 && gy < H && gx >= 0 && gx < W)
-      v = *reinterpret_cast<const uint4*>(inb + ((long long)gy * W + gx) * C + ch * 8);
-    *reinterpret_cast<uint4*>(&tin[pix * CP + ch * 8]) = v;
-  }
-  __syncthreads();
+                                                   const bf16* mask, bf16* out, int B, int H, int W) {
+  static_assert(C == 32, "the MFMA convolution is laid out for 32 channels");
+  constexpr int TX = kConvTX, TY = kConvTY, LX = TX + 2, LY = TY + 2;
+  constexpr int CH = C / 8;                              // 16-byte chunks per pixel
+  constexpr int NLD = (LY * LX * CH + 255) / 256;        // staged chunks per thread
+  __shared__ __attribute__((aligned(16))) bf16 tin[LY * LX * C];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int li = lane & 15, lg = lane >> 4;
-  floatx4 acc[4][NT];
+  // weights: A[i = output channel mt*16 + li][k = input channel lg*8 + e] of tap t
+  bf16x8 wa[9][2];
 #pragma unroll
-  for (int mt = 0; mt < 4; ++mt)
+  for (int t = 0; t < 9; ++t)
 #pragma unroll
-    for (int nt = 0; nt < NT; ++nt) acc[mt][nt] = floatx4{0.f, 0.f, 0.f, 0.f};
+    for (int mt = 0; mt < 2; ++mt) {
+      bf16 v[8];
 #pragma unroll
-  for (int t = 0; t < 9; ++t) {
-    const int ky = t / 3, kx = t % 3;
-#pragma unroll
-    for (int ks = 0; ks < KS; ++ks) {
-      bf16x8 bfr[NT];
-#pragma unroll
-      for (int nt = 0; nt < NT; ++nt)
-        bfr[nt] = __builtin_bit_cast(
-            bf16x8, *reinterpret_cast<const uint4*>(&wl[(t * C + nt * 16 + li) * CP + ks * 32 + lg * 8]));
-#pragma unroll
-      for (int mt = 0; mt < 4; ++mt) {
-        const int lx = mt * 16 + li + kx, ly = wv + ky;
-        const bf16x8 a = __builtin_bit_cast(
-            bf16x8, *reinterpret_cast<const uint4*>(&tin[(ly * LX + lx) * CP + ks * 32 + lg * 8]));
-#pragma unroll
-        for (int nt = 0; nt < NT; ++nt)
-          acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bfr[nt], acc[mt][nt], 0, 0, 0);
+      for (int e = 0; e < 8; ++e) {
+        const int co = mt * 16 + li, ci = lg * 8 + e;
+        v[e] = DGRAD ? wt[(ci * C + co) * 9 + (8 - t)] : wt[(co * C + ci) * 9 + t];
       }
+      wa[t][mt] = __builtin_bit_cast(bf16x8, v);
     }
-  }
-  // epilogue: lane holds pixels mt*16 + 4*lg + r (r < 4) of channel nt*16 + li
-  const int y = oy + wv;
-  if (y >= H) return;
+  float bl[2][4];
 #pragma unroll
-  for (int mt = 0; mt < 4; ++mt)
+  for (int mt = 0; mt < 2; ++mt)
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int x = ox + mt * 16 + lg * 4 + r;
-      if (x >= W) continue;
-      const size_t base = ((size_t)b * HW + (long long)y * W + x) * C;
-#pragma unroll
-      for (int nt = 0; nt < NT; ++nt) {
-        const int n = nt * 16 + li;
-        float v = acc[mt][nt][r];
-        if constexpr (RES) {
-          v += bl[n];
-          if (mask) v += bf2f(mask[base + n]);
-        } else if constexpr (!DGRAD) {
-          v = fmaxf(v + bl[n], 0.f);
-        } else {
-          v = bf2f(mask[base + n]) > 0.f ? v : 0.f;
-        }
-        out[base + n] = f2bf(v);
-      }
-    }
-}
-
-// Weight gradient of a C -> C convolution with NTAP taps (9: 3x3, 1: 1x1):
-// per block partial dW[t][d][c] = sum_p dz[p][d] in[p + off(t)][c] over the
-// block's tiles (persistent loop), as MFMA with K = 32 pixels; plus bias sums.
-template <int C, int NTAP>
-__global__ __launch_bounds__(256) void k_wgrad_mfma(const bf16* in, const bf16* dz, float* part,
-                                                    int B, int H, int W) {
-  constexpr int TX = 64, TY = 4, LX = TX + 2, LY = TY + 2;
-  constexpr int CP = C + 8;
-  constexpr int NT = C / 16;
-  constexpr int NTILE = NTAP * NT * NT;          // 16x16 output tiles
-  constexpr int PERW = (NTILE + 3) / 4;          // per wavefront
-  __shared__ __attribute__((aligned(16))) bf16 tin[LY * LX * CP];
-  __shared__ __attribute__((aligned(16))) bf16 tdz[TY * TX * CP];
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  const int li = lane & 15, lg = lane >> 4;
-  floatx4 acc[PERW];
-#pragma unroll
-  for (int i = 0; i < PERW; ++i) acc[i] = floatx4{0.f, 0.f, 0.f, 0.f};
-  float bacc = 0.f;
+    for (int r = 0; r < 4; ++r) bl[mt][r] = (!DGRAD && bias) ? bf2f(bias[mt * 16 + lg * 4 + r]) : 0.f;
   const int tilesx = (W + TX - 1) / TX, tilesy = (H + TY - 1) / TY;
-  const int ntiles = tilesx * tilesy * B;
+  const int per_img = tilesx * tilesy, ntiles = B * per_img;
   const long long HW = (long long)H * W;
-  constexpr int CH = C / 8;
-  for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
-    const int b = tile / (tilesx * tilesy), r0 = tile % (tilesx * tilesy);
+  // staged chunk e of a tile: halo pixel e / CH (row-major in the halo), chunk e % CH
+  auto fetch = [&](int tile, uint4 (&pre)[NLD]) {
+    const int b = tile / per_img, r0 = tile % per_img;
     const int ox = (r0 % tilesx) * TX, oy = (r0 / tilesx) * TY;
-    __syncthreads();
-    for (int e = threadIdx.x; e < LY * LX * CH; e += 256) {
+    const bf16* inb = in + (size_t)b * HW * C;
+#pragma unroll
+    for (int k = 0; k < NLD; ++k) {
+      const int e = threadIdx.x + 256 * k;
       const int pix = e / CH, ch = e % CH;
       const int ly = pix / LX, lx = pix % LX;
       const int gy = oy + ly - 1, gx = ox + lx - 1;
-      uint4 v = make_uint4(0, 0, 0, 0);
-      if (gy >= 0 && gy < H && gx >= 0 && gx < W)
-        v = *reinterpret_cast<const uint4*>(in + ((size_t)b * HW + (long long)gy * W + gx) * C + ch * 8);
-      *reinterpret_cast<uint4*>(&tin[pix * CP + ch * 8]) = v;
+      const bool ok = e < LY * LX * CH && gy >= 0 && gy < H && gx >= 0 && gx < W;
+      pre[k] = ok ? *reinterpret_cast<const uint4*>(inb + ((long long)gy * W + gx) * C + ch * 8)
+                  : make_uint4(0, 0, 0, 0);
     }
-    for (int e = threadIdx.x; e < TY * TX * CH; e += 256) {
-      const int pix = e / CH, ch = e % CH;
-      const int gy = oy + pix / TX, gx = ox + pix % TX;
-      uint4 v = make_uint4(0, 0, 0, 0);
-      if (gy < H && gx < W)
-        v = *reinterpret_cast<const uint4*>(dz + ((size_t)b * HW + (long long)gy * W + gx) * C + ch * 8);
-      *reinterpret_cast<uint4*>(&tdz[pix * CP + ch * 8]) = v;
+  };
+  uint4 pre[NLD];
+  int tile = blockIdx.x;
+  if (tile < ntiles) fetch(tile, pre);
+  for (; tile < ntiles; tile += gridDim.x) {
+    __syncthreads();                                     // the previous tile's reads are done
+#pragma unroll
+    for (int k = 0; k < NLD; ++k) {
+      const int e = threadIdx.x + 256 * k;
+      if (e < LY * LX * CH) *reinterpret_cast<uint4*>(&tin[e * 8]) = pre[k];
     }
     __syncthreads();
-    if (threadIdx.x < C) {
-      float s = 0.f;
-      for (int q = 0; q < TY * TX; ++q) s += bf2f(tdz[q * CP + threadIdx.x]);
-      bacc += s;
-    }
-    // K loop over chunks of 32 pixels
-    for (int chk = 0; chk < TY * TX / 32; ++chk) {
-      const int q0 = chk * 32 + lg * 8;            // this lane's 8 pixels: q0 .. q0+7
-      const int qy = q0 / TX, qx = q0 % TX;        // same row (TX multiple of 8)
+    const int next = tile + gridDim.x;
+    if (next < ntiles) fetch(next, pre);                 // in flight during the MFMAs
+    const int b = tile / per_img, r0 = tile % per_img;
+    const int ox = (r0 % tilesx) * TX, oy = (r0 / tilesx) * TY;
+    // one output row at a time (the weights stay in registers across rows)
+#pragma unroll 1
+    for (int r2 = 0; r2 < 2; ++r2) {
+      floatx4 acc[4][2];
 #pragma unroll
-      for (int i = 0; i < PERW; ++i) {
-        const int id = wv + 4 * i;
-        if (id >= NTILE) break;
-        const int t = id / (NT * NT), dt = (id / NT) % NT, ct = id % NT;
-        const int ky = NTAP == 9 ? t / 3 : 1, kx = NTAP == 9 ? t % 3 : 1;
-        bf16 av[8], bv[8];
+      for (int nt = 0; nt < 4; ++nt)
 #pragma unroll
-        for (int e = 0; e < 8; ++e) {
-          av[e] = tdz[(q0 + e) * CP + dt * 16 + li];
-          bv[e] = tin[((qy + ky) * LX + qx + e + kx) * CP + ct * 16 + li];
+        for (int mt = 0; mt < 2; ++mt) acc[nt][mt] = floatx4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int t = 0; t < 9; ++t) {
+        const int ly = wv * 2 + r2 + t / 3, kx = t % 3;
+#pragma unroll
+        for (int nt = 0; nt < 4; ++nt) {
+          const int lx = nt * 16 + li + kx;
+          const bf16x8 bx = __builtin_bit_cast(
+              bf16x8, *reinterpret_cast<const uint4*>(&tin[(ly * LX + lx) * C + lg * 8]));
+#pragma unroll
+          for (int mt = 0; mt < 2; ++mt)
+            acc[nt][mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa[t][mt], bx, acc[nt][mt], 0, 0, 0);
         }
-        bf16x8 a = __builtin_bit_cast(bf16x8, av);
-        bf16x8 bb = __builtin_bit_cast(bf16x8, bv);
-        acc[i] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bb, acc[i], 0, 0, 0);
+      }
+      // epilogue: lane holds channels mt*16 + lg*4 + r (r < 4) of pixel nt*16 + li
+      const int y = oy + wv * 2 + r2;
+#pragma unroll
+      for (int nt = 0; nt < 4; ++nt) {
+        const int x = ox + nt * 16 + li;
+        if (y >= H || x >= W) continue;
+        const size_t base = ((size_t)b * HW + (long long)y * W + x) * C;
+#pragma unroll
+        for (int mt = 0; mt < 2; ++mt) {
+          const size_t o = base + mt * 16 + lg * 4;
+          float v[4];
+          float m4[4] = {0.f, 0.f, 0.f, 0.f};
+          // the ReLU mask of the input gradient, or the residual (optional)
+          if ((DGRAD && !RES) || (RES && mask)) {
+            const uint2 mu = *reinterpret_cast<const uint2*>(mask + o);
+            m4[0] = __uint_as_float(mu.x << 16);
+            m4[1] = __uint_as_float(mu.x & 0xffff0000u);
+            m4[2] = __uint_as_float(mu.y << 16);
+            m4[3] = __uint_as_float(mu.y & 0xffff0000u);
+          }
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            float a = acc[nt][mt][r];
+            if constexpr (RES) a = a + bl[mt][r] + m4[r];
+            else if constexpr (!DGRAD) a = fmaxf(a + bl[mt][r], 0.f);
+            else a = m4[r] > 0.f ? a : 0.f;
+            v[r] = a;
+          }
+          uint2 w2;
+          w2.x = (uint32_t)f2bf(v[0]) | ((uint32_t)f2bf(v[1]) << 16);
+          w2.y = (uint32_t)f2bf(v[2]) | ((uint32_t)f2bf(v[3]) << 16);
+          *reinterpret_cast<uint2*>(out + o) = w2;
+        }
       }
     }
   }
-  // D[i][j]: lane holds rows (d) 4*lg + r, column (c) li
+}
+
+// Workgroups of a persistent MFMA convolution over B images of H x W.
+inline int conv_grid(int B, int H, int W) {
+  const long long tiles = (long long)B * ((W + kConvTX - 1) / kConvTX) * ((H + kConvTY - 1) / kConvTY);
+  return (int)std::max<long long>(1, std::min<long long>(tiles, 512));
+}
+
+// Weight gradient of a C -> C convolution with NTAP taps (9: 3x3, 1: 1x1):
+// per workgroup the partial dW[t][d][c] = sum_p dz[p][d] in[p + off(t)][c]
+// over its tiles (persistent over 64 x 4 pixel tiles of all images) and the
+// bias sums, on v_mfma_f32_16x16x32_bf16 with K = 32 pixels: A = dz^T (16
+// output channels x 32 pixels), B = the shifted input (32 pixels x 16 input
+// channels).  A lane's 8 K-elements are 8 consecutive pixels of one channel,
+// so the tile is staged transposed ([channel][pixel]); the input twice,
+// shifted by 0 and by 1 column, so that the fragment of every tap starts at
+// an even column (four 4-byte LDS reads), the output gradient once (one
+// 16-byte read).  Wavefront w accumulates output tile (d-tile w/2, c-tile
+// w%2) for every tap.
+template <int C, int NTAP>
+__global__ __launch_bounds__(256) void k_wgrad_mfma(const bf16* in, const bf16* dz, float* part,
+                                                    int B, int H, int W) {
+  static_assert(C == 32, "the MFMA weight gradient is laid out for 32 channels");
+  constexpr int TX = 64, TY = 4, LY = TY + 2;
+  constexpr int NP = TX * TY;                    // tile pixels
+  constexpr int PD = NP + 8;                     // dz^T pitch (elements)
+  constexpr int PX = 74;                         // input row pitch: 66 columns + padding
+  constexpr int PC = LY * PX;                    // input channel pitch
+  __shared__ __attribute__((aligned(16))) bf16 dzT[C * PD];
+  __shared__ __attribute__((aligned(16))) bf16 inT[2][C * PC];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int li = lane & 15, lg = lane >> 4;
+  const int dt = wv >> 1, ct = wv & 1;
+  floatx4 acc[NTAP];
+#pragma unroll
+  for (int t = 0; t < NTAP; ++t) acc[t] = floatx4{0.f, 0.f, 0.f, 0.f};
+  float bacc = 0.f;
+  const int tilesx = (W + TX - 1) / TX, tilesy = (H + TY - 1) / TY;
+  const int per_img = tilesx * tilesy, ntiles = B * per_img;
+  const long long HW = (long long)H * W;
+  constexpr int CH = C / 8;
+  for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    const int b = tile / per_img, r0 = tile % per_img;
+    const int ox = (r0 % tilesx) * TX, oy = (r0 / tilesx) * TY;
+    const bf16* dzb = dz + (size_t)b * HW * C;
+    const bf16* inb = in + (size_t)b * HW * C;
+    __syncthreads();
+    // dz^T: a unit = two adjacent pixels x 8 channels -> 8 channel rows, one dword each
+    for (int u = threadIdx.x; u < (NP / 2) * CH; u += 256) {
+      const int pr = u / CH, ch = u % CH;
+      const int q = 2 * pr, qy = q / TX, qx = q % TX;
+      const int gy = oy + qy, gx = ox + qx;
+      uint4 v0 = make_uint4(0, 0, 0, 0), v1 = v0;
+      if (gy < H && gx < W) v0 = *reinterpret_cast<const uint4*>(dzb + ((long long)gy * W + gx) * C + ch * 8);
+      if (gy < H && gx + 1 < W) v1 = *reinterpret_cast<const uint4*>(dzb + ((long long)gy * W + gx + 1) * C + ch * 8);
+      const uint32_t a0[4] = {v0.x, v0.y, v0.z, v0.w}, a1[4] = {v1.x, v1.y, v1.z, v1.w};
+#pragma unroll
+      for (int h = 0; h < 4; ++h) {
+        // channels ch*8 + 2h (low halves) and ch*8 + 2h + 1 (high halves)
+        *reinterpret_cast<uint32_t*>(&dzT[(ch * 8 + 2 * h) * PD + q]) = (a0[h] & 0xffffu) | (a1[h] << 16);
+        *reinterpret_cast<uint32_t*>(&dzT[(ch * 8 + 2 * h + 1) * PD + q]) = (a0[h] >> 16) | (a1[h] & 0xffff0000u);
+      }
+    }
+    // input^T, halo columns -1..64 of rows -1..TY: copy 0 holds halo column h
+    // at position h, copy 1 at position h - 1; a unit = halo columns
+    // 2k, 2k+1, 2k+2 of one row x 8 channels
+    for (int u = threadIdx.x; u < LY * 33 * CH; u += 256) {
+      const int ch = u % CH, rk = u / CH, ly = rk / 33, k = rk % 33;
+      const int gy = oy + ly - 1;
+      uint4 v[3];
+#pragma unroll
+      for (int e = 0; e < 3; ++e) {
+        const int gx = ox + 2 * k + e - 1;
+        v[e] = make_uint4(0, 0, 0, 0);
+        if (2 * k + e < TX + 2 && gy >= 0 && gy < H && gx >= 0 && gx < W)
+          v[e] = *reinterpret_cast<const uint4*>(inb + ((long long)gy * W + gx) * C + ch * 8);
+      }
+      const uint32_t w0[4] = {v[0].x, v[0].y, v[0].z, v[0].w}, w1[4] = {v[1].x, v[1].y, v[1].z, v[1].w},
+                     w2[4] = {v[2].x, v[2].y, v[2].z, v[2].w};
+#pragma unroll
+      for (int h = 0; h < 4; ++h) {
+        const int c0 = ch * 8 + 2 * h;
+        const int o = ly * PX + 2 * k;
+        *reinterpret_cast<uint32_t*>(&inT[0][c0 * PC + o]) = (w0[h] & 0xffffu) | (w1[h] << 16);
+        *reinterpret_cast<uint32_t*>(&inT[0][(c0 + 1) * PC + o]) = (w0[h] >> 16) | (w1[h] & 0xffff0000u);
+        *reinterpret_cast<uint32_t*>(&inT[1][c0 * PC + o]) = (w1[h] & 0xffffu) | (w2[h] << 16);
+        *reinterpret_cast<uint32_t*>(&inT[1][(c0 + 1) * PC + o]) = (w1[h] >> 16) | (w2[h] & 0xffff0000u);
+      }
+    }
+    __syncthreads();
+    // K loop over chunks of 32 pixels (one tile row holds two)
+#pragma unroll 1
+    for (int chk = 0; chk < NP / 32; ++chk) {
+      const int qy = chk >> 1, qx = (chk & 1) * 32 + lg * 8;     // this lane's 8 pixels
+      const bf16x8 a = __builtin_bit_cast(
+          bf16x8, *reinterpret_cast<const uint4*>(&dzT[(dt * 16 + li) * PD + qy * TX + qx]));
+      if (ct == 0) {                                 // bias sums, once per output channel
+        const uint4 au = __builtin_bit_cast(uint4, a);
+        const uint32_t aw[4] = {au.x, au.y, au.z, au.w};
+#pragma unroll
+        for (int h = 0; h < 4; ++h) bacc += __uint_as_float(aw[h] << 16) + __uint_as_float(aw[h] & 0xffff0000u);
+      }
+#pragma unroll
+      for (int t = 0; t < NTAP; ++t) {
+        const int ky = NTAP == 9 ? t / 3 : 1, kx = NTAP == 9 ? t % 3 : 1;
+        // halo column of pixel qx under tap kx is qx + kx: copy kx & 1 at qx + (kx & 2)
+        const bf16* src = &inT[kx & 1][(ct * 16 + li) * PC + (qy + ky) * PX + qx + (kx & 2)];
+        const uint32_t* s32 = reinterpret_cast<const uint32_t*>(src);
+        const uint4 bu = make_uint4(s32[0], s32[1], s32[2], s32[3]);
+        acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, __builtin_bit_cast(bf16x8, bu), acc[t], 0, 0, 0);
+      }
+    }
+  }
+  // D[i][j]: lane holds rows (d) dt*16 + 4*lg + r, column (c) ct*16 + li
   constexpr int STRIDE = NTAP * C * C + C;
   float* pb = part + (size_t)blockIdx.x * STRIDE;
 #pragma unroll
-  for (int i = 0; i < PERW; ++i) {
-    const int id = wv + 4 * i;
-    if (id >= NTILE) break;
-    const int t = id / (NT * NT), dt = (id / NT) % NT, ct = id % NT;
+  for (int t = 0; t < NTAP; ++t)
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int d = dt * 16 + lg * 4 + r, c = ct * 16 + li;
-      pb[(t * C + d) * C + c] = acc[i][r];
+      pb[(t * C + d) * C + c] = acc[t][r];
     }
-  }
-  if (threadIdx.x < C) pb[NTAP * C * C + threadIdx.x] = bacc;
+  // bias: sum the four lane groups of channel dt*16 + li
+  bacc += __shfl_xor(bacc, 16, 64);
+  bacc += __shfl_xor(bacc, 32, 64);
+  if (ct == 0 && lg == 0) pb[NTAP * C * C + dt * 16 + li] = bacc;
 }
 
 // ------------------------------------------------------------------ spectral layer
@@ -897,14 +1063,20 @@ __global__ __launch_bounds__(256) void k_skip_rows(const X* x, const double* div
 
 // Y[b][k][l] = w_kl X[b][k][l] - Cc[b][k][l], w = sxt / sxx (0 where sxx = 0):
 // the band path's coefficients in place of those of the convolutional output
+// The convolutional branch's output gain: sct / scc, 1 before any data (or
+// without a gain: gate == NULL).
+__device__ __forceinline__ double gate_of(const double* gate) {
+  return gate && gate[1] > 0.0 ? gate[0] / gate[1] : 1.0;
+}
+
 __global__ void k_band_apply(const double* X, const double* Cc, const double* band, double* Y,
-                             int B, int K) {
+                             int B, int K, const double* gate) {
   const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= (long long)B * K * K) return;
   const int kl = (int)(e % (K * K));
   const double sxx = band[K * K + kl];
   const double w = sxx > 0.0 ? band[kl] / sxx : 0.0;
-  Y[e] = w * X[e] - Cc[e];
+  Y[e] = w * X[e] - gate_of(gate) * Cc[e];
 }
 
 // Z[b][i][l] = alpha sum_k Sy[k][i] Y[b][k][l]
@@ -928,9 +1100,10 @@ __global__ void k_skip_inv_cols(const double* Y, const double* Sy, double* Z, in
   Z[e] = alpha * ((s0 + s1) + (s2 + s3));
 }
 
-// out[b][i][j] += beta sum_l Sx[l][j] Z[b][i][l]  (sum and add in FP64)
+// out[b][i][j] = g out[b][i][j] + beta sum_l Sx[l][j] Z[b][i][l]  (sum and add
+// in FP64; g the output gain, 1 without one)
 __global__ void k_skip_out(const double* Z, const double* Sx, float* out, int B, int H, int W,
-                           int M, double beta) {
+                           int M, double beta, const double* gate) {
   const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= (long long)B * H * W) return;
   const int j = (int)(e % W);
@@ -945,7 +1118,7 @@ __global__ void k_skip_out(const double* Z, const double* Sx, float* out, int B,
     s3 += Sx[(size_t)(l + 3) * W + j] * zr[l + 3];
   }
   for (; l < M; ++l) s0 += Sx[(size_t)l * W + j] * zr[l];
-  out[e] = (float)((double)out[e] + beta * ((s0 + s1) + (s2 + s3)));
+  out[e] = (float)(gate_of(gate) * (double)out[e] + beta * ((s0 + s1) + (s2 + s3)));
 }
 
 // Least-squares state of the band: sxt_kl += sum_b X[b][k][l] T[b][k][l],
@@ -961,6 +1134,47 @@ __global__ void k_band_fit(const double* X, const double* T, double* band, int B
   }
   band[kl] = xt;
   band[K * K + kl] = xx;
+}
+
+// Sums of c c and c d over a batch of fields (per-workgroup partials; the
+// first 2 * gridDim.x entries of part).
+__global__ __launch_bounds__(256) void k_gate_sums(const float* c, const float* d, long long n,
+                                                   double* part) {
+  __shared__ double red[2][4];
+  double cc = 0.0, cd = 0.0;
+  for (long long e = (long long)blockIdx.x * 256 + threadIdx.x; e < n;
+       e += (long long)gridDim.x * 256) {
+    const double x = c[e];
+    cc += x * x;
+    cd += x * (double)d[e];
+  }
+  cc = wave_sum(cc);
+  cd = wave_sum(cd);
+  if ((threadIdx.x & 63) == 0) {
+    red[0][threadIdx.x >> 6] = cc;
+    red[1][threadIdx.x >> 6] = cd;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    part[2 * blockIdx.x] = ((red[0][0] + red[0][1]) + red[0][2]) + red[0][3];
+    part[2 * blockIdx.x + 1] = ((red[1][0] + red[1][1]) + red[1][2]) + red[1][3];
+  }
+}
+
+// Output gain state: with cc = sum |c|^2 and cd = sum <c, dout> of this
+// batch (dout = (2/B)(c - t) off the band), sum <c, t> = cc - (B/2) cd; both
+// running sums decay by kGateDecay per training step, so that the gain
+// follows the branch as it trains.
+constexpr double kGateDecay = 0.9;
+__global__ void k_gate_fin(const double* part, int nblk, double* gate, int B) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  double cc = 0.0, cd = 0.0;
+  for (int b = 0; b < nblk; ++b) {
+    cc += part[2 * b];
+    cd += part[2 * b + 1];
+  }
+  gate[0] = kGateDecay * gate[0] + (cc - 0.5 * B * cd);
+  gate[1] = kGateDecay * gate[1] + cc;
 }
 
 // The exact training pair of the band for the correction d = u_t - u_prev:
@@ -1073,8 +1287,10 @@ struct Net {
   T* w(size_t off) const { return (T*)(ws + off); }
 };
 
+// gated: apply the convolutional branch's output gain (inference); training
+// runs with gain 1.
 template <int C>
-void forward(const Net& n, const Ptrs& f, const Ptrs& u, hipStream_t s) {
+void forward(const Net& n, const Ptrs& f, const Ptrs& u, hipStream_t s, bool gated) {
   const Dims& d = n.d;
   const long long HW = d.HW;
   bf16* x0 = n.w<bf16>(n.wl.x0);
@@ -1096,9 +1312,7 @@ void forward(const Net& n, const Ptrs& f, const Ptrs& u, hipStream_t s) {
   // L1, L2
   k_conv_small<2, C, bf16, bf16, false, true><<<dim3(cdiv(HW, 256), d.B), 256, 0, s>>>(
       x0, n.bfw(T_C1W), n.bfw(T_C1B), nullptr, a[0], d.H, d.W);
-  const int ctiles = cdiv(d.W, 64) * cdiv(d.H, 4);
-  k_conv_mfma<C, false><<<dim3(ctiles, d.B), 256, 0, s>>>(a[0], n.bfw(T_C2W), n.bfw(T_C2B), nullptr,
-                                                          a[1], d.H, d.W);
+  k_conv_mfma<C, false><<<conv_grid(d.B, d.H, d.W), 256, 0, s>>>(a[0], n.bfw(T_C2W), n.bfw(T_C2B), nullptr, a[1], d.B, d.H, d.W);
   // L3 spectral
   float* T = n.w<float>(n.wl.T);
   float* X = n.w<float>(n.wl.X);
@@ -1114,10 +1328,8 @@ void forward(const Net& n, const Ptrs& f, const Ptrs& u, hipStream_t s) {
       a[1], n.bfw(T_SW1), n.bfw(T_SB), Z, Sx, nullptr, a[2], d.H, d.W, d.M,
       (float)(2.0 / (d.W + 1)));
   // L4, L5, L6
-  k_conv_mfma<C, false><<<dim3(ctiles, d.B), 256, 0, s>>>(a[2], n.bfw(T_C4W), n.bfw(T_C4B), nullptr,
-                                                          a[3], d.H, d.W);
-  k_conv_mfma<C, false><<<dim3(ctiles, d.B), 256, 0, s>>>(a[3], n.bfw(T_C5W), n.bfw(T_C5B), nullptr,
-                                                          a[4], d.H, d.W);
+  k_conv_mfma<C, false><<<conv_grid(d.B, d.H, d.W), 256, 0, s>>>(a[2], n.bfw(T_C4W), n.bfw(T_C4B), nullptr, a[3], d.B, d.H, d.W);
+  k_conv_mfma<C, false><<<conv_grid(d.B, d.H, d.W), 256, 0, s>>>(a[3], n.bfw(T_C5W), n.bfw(T_C5B), nullptr, a[4], d.B, d.H, d.W);
   k_conv_small<C, 1, bf16, float, false, false><<<dim3(cdiv(HW, 256), d.B), 256, 0, s>>>(
       a[4], n.bfw(T_C6W), n.bfw(T_C6B), nullptr, n.w<float>(n.wl.out), d.H, d.W);
   // band path from the FP64 residual, replacing the band of the
@@ -1141,12 +1353,13 @@ void forward(const Net& n, const Ptrs& f, const Ptrs& u, hipStream_t s) {
   k_skip_rows<float><<<d.B * d.H, 256, 0, s>>>(out, nullptr, kSxT, kT,
                                                                         d.B, d.H, d.W, K);
   k_cols<double><<<d.B * K * cdiv(K, 64), 256, 0, s>>>(kT, kSy, kC, d.B, d.H, K, K, 1.0);
+  const double* gate = gated ? (const double*)(n.params + n.pl.gate) : nullptr;
   k_band_apply<<<cdiv((long long)d.B * K * K, 256), 256, 0, s>>>(
-      kX, kC, (const double*)(n.params + n.pl.band), kY, d.B, K);
+      kX, kC, (const double*)(n.params + n.pl.band), kY, d.B, K, gate);
   k_skip_inv_cols<<<cdiv((long long)d.B * d.H * K, 256), 256, 0, s>>>(kY, kSy, kZ, d.B, d.H, K,
                                                                       2.0 / (d.H + 1));
   k_skip_out<<<cdiv((long long)d.B * HW, 256), 256, 0, s>>>(kZ, kSx, out, d.B, d.H, d.W, K,
-                                                            2.0 / (d.W + 1));
+                                                            2.0 / (d.W + 1), gate);
 }
 
 template <int C>
@@ -1166,7 +1379,7 @@ void wgrad_conv(const Net& n, const bf16* in, const bf16* dz, int tw, int tb, hi
 template <int C>
 void train(const Net& n, const Ptrs& f, const Ptrs& up, const Ptrs& ut, float* loss,
            const guess_net_cfg* cfg, hipStream_t s) {
-  forward<C>(n, f, up, s);
+  forward<C>(n, f, up, s, false);
   const Dims& d = n.d;
   const long long HW = d.HW;
   bf16* x0 = n.w<bf16>(n.wl.x0);
@@ -1188,7 +1401,6 @@ void train(const Net& n, const Ptrs& f, const Ptrs& up, const Ptrs& ut, float* l
     k_loss<<<nb, 256, 0, s>>>(out, ut, up, sv + d.B, dout, lpart, HW, d.B);
     k_loss_sum<<<1, kReduceThreads, 0, s>>>(lpart, nb, ldev, loss, d.B);
   }
-  const int ctiles = cdiv(d.W, 64) * cdiv(d.H, 4);
   // band path (K > 0): its least-squares state takes the batch's sums of
   // X T and X^2 (X = S[A d/s_r], T = S[t] of the target t = c_u d/s_r,
   // d = u_t - u_prev); the convolutional branch's gradient is dout off the
@@ -1217,21 +1429,31 @@ void train(const Net& n, const Ptrs& f, const Ptrs& up, const Ptrs& ut, float* l
     k_cols<double><<<d.B * K * cdiv(K, 64), 256, 0, s>>>(kT, kSy, kdY, d.B, d.H, K, K, nrm);
     k_skip_inv_cols<<<cdiv((long long)d.B * d.H * K, 256), 256, 0, s>>>(kdY, kSy, kZ, d.B, d.H, K,
                                                                         1.0);
-    k_skip_out<<<cdiv((long long)d.B * HW, 256), 256, 0, s>>>(kZ, kSx, dout, d.B, d.H, d.W, K, -1.0);
+    k_skip_out<<<cdiv((long long)d.B * HW, 256), 256, 0, s>>>(kZ, kSx, dout, d.B, d.H, d.W, K, -1.0,
+                                                              nullptr);
+    // output gain: c = out - P_K out, the branch's output off the band (out
+    // is no longer needed), against dout = (2/B)(c - t) off the band
+    k_skip_rows<float><<<d.B * d.H, 256, 0, s>>>(out, nullptr, kSxT, kT, d.B, d.H, d.W, K);
+    k_cols<double><<<d.B * K * cdiv(K, 64), 256, 0, s>>>(kT, kSy, kdY, d.B, d.H, K, K, nrm);
+    k_skip_inv_cols<<<cdiv((long long)d.B * d.H * K, 256), 256, 0, s>>>(kdY, kSy, kZ, d.B, d.H, K,
+                                                                        1.0);
+    k_skip_out<<<cdiv((long long)d.B * HW, 256), 256, 0, s>>>(kZ, kSx, out, d.B, d.H, d.W, K, -1.0,
+                                                              nullptr);
+    double* gpart = n.w<double>(n.wl.loss) + 8 + 2048;
+    k_gate_sums<<<256, 256, 0, s>>>(out, dout, (long long)d.B * HW, gpart);
+    k_gate_fin<<<1, 64, 0, s>>>(gpart, 256, (double*)(n.params + n.pl.gate), d.B);
   }
   // L6: weight grad from (a5, dout); input grad masked by a5 -> dz5
-  k_wgrad_thin<C, 1, float><<<G, 256, 0, s>>>(a[4], dout, part, d.B, d.H, d.W);
+  k_wgrad_out<C><<<G, 256, 0, s>>>(a[4], dout, part, d.B, d.H, d.W);
   k_wgrad_reduce<<<cdiv(9 * C + 1, 256), 256, 0, s>>>(part, G, 9, 1, C, n.grad(T_C6W), n.grad(T_C6B));
   k_conv_small<1, C, float, bf16, true, false><<<dim3(cdiv(HW, 256), d.B), 256, 0, s>>>(
       dout, n.bfw(T_C6W), nullptr, a[4], dz[0], d.H, d.W);
   // L5
   wgrad_conv<C>(n, a[3], dz[0], T_C5W, T_C5B, s, 9);
-  k_conv_mfma<C, true><<<dim3(ctiles, d.B), 256, 0, s>>>(dz[0], n.bfw(T_C5W), nullptr, a[3], dz[1],
-                                                         d.H, d.W);
+  k_conv_mfma<C, true><<<conv_grid(d.B, d.H, d.W), 256, 0, s>>>(dz[0], n.bfw(T_C5W), nullptr, a[3], dz[1], d.B, d.H, d.W);
   // L4
   wgrad_conv<C>(n, a[2], dz[1], T_C4W, T_C4B, s, 9);
-  k_conv_mfma<C, true><<<dim3(ctiles, d.B), 256, 0, s>>>(dz[1], n.bfw(T_C4W), nullptr, a[2], dz[0],
-                                                         d.H, d.W);
+  k_conv_mfma<C, true><<<conv_grid(d.B, d.H, d.W), 256, 0, s>>>(dz[1], n.bfw(T_C4W), nullptr, a[2], dz[0], d.B, d.H, d.W);
   // L3 spectral: dz3 = dz[0]
   wgrad_conv<C>(n, a[1], dz[0], T_SW1, T_SB, s, 1);
   float* T = n.w<float>(n.wl.T);
@@ -1251,10 +1473,9 @@ void train(const Net& n, const Ptrs& f, const Ptrs& up, const Ptrs& ut, float* l
                                                                 a[1], dz[1], d.H, d.W, d.M, 1.f);
   // L2: dz2 = dz[1]
   wgrad_conv<C>(n, a[0], dz[1], T_C2W, T_C2B, s, 9);
-  k_conv_mfma<C, true><<<dim3(ctiles, d.B), 256, 0, s>>>(dz[1], n.bfw(T_C2W), nullptr, a[0], dz[0],
-                                                         d.H, d.W);
+  k_conv_mfma<C, true><<<conv_grid(d.B, d.H, d.W), 256, 0, s>>>(dz[1], n.bfw(T_C2W), nullptr, a[0], dz[0], d.B, d.H, d.W);
   // L1: dz1 = dz[0]
-  k_wgrad_thin<2, C, bf16><<<G, 256, 0, s>>>(x0, dz[0], part, d.B, d.H, d.W);
+  k_wgrad_in<C><<<G, 256, 0, s>>>(x0, dz[0], part, d.B, d.H, d.W);
   k_wgrad_reduce<<<cdiv(9 * C * 2 + C, 256), 256, 0, s>>>(part, G, 9, C, 2, n.grad(T_C1W),
                                                           n.grad(T_C1B));
   // Adam
@@ -1550,25 +1771,16 @@ void fluid_forward(const FNet& n, const Ptrs& f, const Ptrs& u, int blocks, hipS
     k_conv_small<2, C, bf16, bf16, false, true><<<dim3(cdiv(hw, 256), d.B), 256, 0, s>>>(
         n.w<bf16>(n.wl.X[l]), n.bfw(fl_lvl(l, 0)), n.bfw(fl_lvl(l, 1)), nullptr,
         n.w<bf16>(n.wl.A[l]), Hl, Wl);
-    k_conv_mfma<C, false><<<dim3(cdiv(Wl, 64) * cdiv(Hl, 4), d.B), 256, 0, s>>>(
-        n.w<bf16>(n.wl.A[l]), n.bfw(fl_lvl(l, 2)), n.bfw(fl_lvl(l, 3)), nullptr,
-        n.w<bf16>(n.wl.Y[l]), Hl, Wl);
+    k_conv_mfma<C, false><<<conv_grid(d.B, Hl, Wl), 256, 0, s>>>(n.w<bf16>(n.wl.A[l]), n.bfw(fl_lvl(l, 2)), n.bfw(fl_lvl(l, 3)), nullptr, n.w<bf16>(n.wl.Y[l]), d.B, Hl, Wl);
     yp.p[l] = n.w<bf16>(n.wl.Y[l]);
   }
   k_upsum<C><<<dim3(cdiv(HW * (C / 8), 256), d.B), 256, 0, s>>>(yp, d.L, n.w<bf16>(n.wl.S[0]),
                                                                 d.H, d.W);
-  const dim3 cg(cdiv(d.W, 64) * cdiv(d.H, 4), d.B);
   for (int i = 0; i < blocks; ++i) {
-    k_conv_mfma<C, false><<<cg, 256, 0, s>>>(n.w<bf16>(n.wl.S[i]), n.bfw(fl_blk(d, i, 0)),
-                                             n.bfw(fl_blk(d, i, 1)), nullptr,
-                                             n.w<bf16>(n.wl.Hb[i]), d.H, d.W);
-    k_conv_mfma<C, false, true><<<cg, 256, 0, s>>>(n.w<bf16>(n.wl.Hb[i]), n.bfw(fl_blk(d, i, 2)),
-                                                   n.bfw(fl_blk(d, i, 3)), n.w<bf16>(n.wl.S[i]),
-                                                   n.w<bf16>(n.wl.S[i + 1]), d.H, d.W);
+    k_conv_mfma<C, false><<<conv_grid(d.B, d.H, d.W), 256, 0, s>>>(n.w<bf16>(n.wl.S[i]), n.bfw(fl_blk(d, i, 0)), n.bfw(fl_blk(d, i, 1)), nullptr, n.w<bf16>(n.wl.Hb[i]), d.B, d.H, d.W);
+    k_conv_mfma<C, false, true><<<conv_grid(d.B, d.H, d.W), 256, 0, s>>>(n.w<bf16>(n.wl.Hb[i]), n.bfw(fl_blk(d, i, 2)), n.bfw(fl_blk(d, i, 3)), n.w<bf16>(n.wl.S[i]), n.w<bf16>(n.wl.S[i + 1]), d.B, d.H, d.W);
   }
-  k_conv_mfma<C, false><<<cg, 256, 0, s>>>(n.w<bf16>(n.wl.S[blocks]), n.bfw(fl_head(d, 0)),
-                                           n.bfw(fl_head(d, 1)), nullptr, n.w<bf16>(n.wl.o), d.H,
-                                           d.W);
+  k_conv_mfma<C, false><<<conv_grid(d.B, d.H, d.W), 256, 0, s>>>(n.w<bf16>(n.wl.S[blocks]), n.bfw(fl_head(d, 0)), n.bfw(fl_head(d, 1)), nullptr, n.w<bf16>(n.wl.o), d.B, d.H, d.W);
   k_conv_small<C, 1, bf16, float, false, false><<<dim3(cdiv(HW, 256), d.B), 256, 0, s>>>(
       n.w<bf16>(n.wl.o), n.bfw(fl_head(d, 2)), n.bfw(fl_head(d, 3)), nullptr,
       n.w<float>(n.wl.out), d.H, d.W);
@@ -1604,25 +1816,22 @@ void fluid_train(const FNet& n, const Ptrs& f, const Ptrs& up, const Ptrs& ut, i
     k_loss<<<nb, 256, 0, s>>>(out, ut, up, sv + d.B, dout, lpart, HW, d.B);
     k_loss_sum<<<1, kReduceThreads, 0, s>>>(lpart, nb, ldev, loss, d.B);
   }
-  const dim3 cg(cdiv(d.W, 64) * cdiv(d.H, 4), d.B);
   // head: out = conv(o), o = ReLU(conv(S_R))
   bf16* o = n.w<bf16>(n.wl.o);
-  k_wgrad_thin<C, 1, float><<<G, 256, 0, s>>>(o, dout, part, d.B, d.H, d.W);
+  k_wgrad_out<C><<<G, 256, 0, s>>>(o, dout, part, d.B, d.H, d.W);
   k_wgrad_reduce<<<cdiv(9 * C + 1, 256), 256, 0, s>>>(part, G, 9, 1, C, n.grad(fl_head(d, 2)),
                                                        n.grad(fl_head(d, 3)));
   k_conv_small<1, C, float, bf16, true, false><<<dim3(cdiv(HW, 256), d.B), 256, 0, s>>>(
       dout, n.bfw(fl_head(d, 2)), nullptr, o, d1, d.H, d.W);
   fl_wgrad9(n, n.w<bf16>(n.wl.S[blocks]), d1, fl_head(d, 0), fl_head(d, 1), d.H, d.W, s);
-  k_conv_mfma<C, true, true><<<cg, 256, 0, s>>>(d1, n.bfw(fl_head(d, 0)), nullptr, nullptr, dS,
-                                                d.H, d.W);
+  k_conv_mfma<C, true, true><<<conv_grid(d.B, d.H, d.W), 256, 0, s>>>(d1, n.bfw(fl_head(d, 0)), nullptr, nullptr, dS, d.B, d.H, d.W);
   // residual blocks, last first: dS accumulates in place
   for (int i = blocks - 1; i >= 0; --i) {
     bf16* hb = n.w<bf16>(n.wl.Hb[i]);
     fl_wgrad9(n, hb, dS, fl_blk(d, i, 2), fl_blk(d, i, 3), d.H, d.W, s);
-    k_conv_mfma<C, true><<<cg, 256, 0, s>>>(dS, n.bfw(fl_blk(d, i, 2)), nullptr, hb, d1, d.H, d.W);
+    k_conv_mfma<C, true><<<conv_grid(d.B, d.H, d.W), 256, 0, s>>>(dS, n.bfw(fl_blk(d, i, 2)), nullptr, hb, d1, d.B, d.H, d.W);
     fl_wgrad9(n, n.w<bf16>(n.wl.S[i]), d1, fl_blk(d, i, 0), fl_blk(d, i, 1), d.H, d.W, s);
-    k_conv_mfma<C, true, true><<<cg, 256, 0, s>>>(d1, n.bfw(fl_blk(d, i, 0)), nullptr, dS, dS,
-                                                  d.H, d.W);
+    k_conv_mfma<C, true, true><<<conv_grid(d.B, d.H, d.W), 256, 0, s>>>(d1, n.bfw(fl_blk(d, i, 0)), nullptr, dS, dS, d.B, d.H, d.W);
   }
   // levels: the gradient of y_l is the 2^l x 2^l block sum of dS, masked
   float* P[2] = {n.w<float>(n.wl.P[0]), n.w<float>(n.wl.P[1])};
@@ -1642,9 +1851,8 @@ void fluid_train(const FNet& n, const Ptrs& f, const Ptrs& up, const Ptrs& ut, i
           P[(l - 1) & 1], pc, Y, d1, Hl, Wl);
     bf16* A = n.w<bf16>(n.wl.A[l]);
     fl_wgrad9(n, A, d1, fl_lvl(l, 2), fl_lvl(l, 3), Hl, Wl, s);
-    k_conv_mfma<C, true><<<dim3(cdiv(Wl, 64) * cdiv(Hl, 4), d.B), 256, 0, s>>>(
-        d1, n.bfw(fl_lvl(l, 2)), nullptr, A, d2, Hl, Wl);
-    k_wgrad_thin<2, C, bf16><<<G, 256, 0, s>>>(n.w<bf16>(n.wl.X[l]), d2, part, d.B, Hl, Wl);
+    k_conv_mfma<C, true><<<conv_grid(d.B, Hl, Wl), 256, 0, s>>>(d1, n.bfw(fl_lvl(l, 2)), nullptr, A, d2, d.B, Hl, Wl);
+    k_wgrad_in<C><<<G, 256, 0, s>>>(n.w<bf16>(n.wl.X[l]), d2, part, d.B, Hl, Wl);
     k_wgrad_reduce<<<cdiv(9 * C * 2 + C, 256), 256, 0, s>>>(part, G, 9, C, 2, n.grad(fl_lvl(l, 0)),
                                                             n.grad(fl_lvl(l, 1)));
   }
@@ -1699,6 +1907,7 @@ int net_init(const guess_net_cfg* cfg, void* params, hipStream_t s) {
   // the band's least-squares state starts empty (w = 0)
   const long long nb = 4LL * cfg->skip_modes * cfg->skip_modes;
   if (nb > 0) k_fill0<<<cdiv(nb, 256), 256, 0, s>>>((float*)(p + pl.band), nb);
+  k_fill0<<<1, 64, 0, s>>>((float*)(p + pl.gate), 4);
   MLG_HIP(hipGetLastError());
   return MLG_OK;
 }
@@ -1729,8 +1938,7 @@ int net_infer(const guess_net_cfg* cfg, const void* params, const mlg_grid* grid
     up.p[b] = u_prev + (size_t)b * d.HW;
     gp.p[b] = guess + (size_t)b * d.HW;
   }
-  if (d.C == 32) forward<32>(n, fp, up, s);
-  else forward<64>(n, fp, up, s);
+  forward<32>(n, fp, up, s, true);
   k_guess<<<dim3(cdiv(d.HW, 256), d.B), 256, 0, s>>>(n.w<float>(wl.out), up, n.w<double>(wl.s), gp,
                                                       d.HW);
   MLG_HIP(hipGetLastError());
@@ -1753,8 +1961,7 @@ int net_train_step(const guess_net_cfg* cfg, void* params, const mlg_grid* grid,
     up.p[b] = u_prev[b];
     tp.p[b] = u_target[b];
   }
-  if (d.C == 32) train<32>(n, fp, up, tp, loss, cfg, s);
-  else train<64>(n, fp, up, tp, loss, cfg, s);
+  train<32>(n, fp, up, tp, loss, cfg, s);
   MLG_HIP(hipGetLastError());
   return MLG_OK;
 }

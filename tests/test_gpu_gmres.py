@@ -286,6 +286,33 @@ def test_full_size_fp32_refinement_m40(mlg, shape):
     assert sg.cycles == 2 and sg.relres_true < sg.relres_first_cycle < 1.0
 
 
+@pytest.mark.timeout(600)
+def test_full_size_160_cubed_to_tolerance(mlg):
+    """The mixed-precision configuration's 3D system solved to the end: 160^3
+    (4.1 M points), five drifting Gaussians, GMRES(40) to rtol 1e-10 with the
+    FP32 Krylov basis and FP64 refinement, and the same RHS with the FP64
+    basis (whose trajectory the fixed-step tests pin to the oracle).  The
+    FP32-basis solution meets the tolerance on the residual the oracle
+    recomputes (compensated FP64 sums) and differs from the FP64 solution by
+    at most kappa(A) * 2 rtol (both are within kappa rtol of A^-1 b; the error
+    is printed)."""
+    shape = (160, 160, 160)
+    print("full-size 160^3 to 1e-10", flush=True)
+    b = DriftingGaussians(shape, 5, 0.03, seed=3001).field(0)
+    x32, s32 = run(mlg, b, restart_m=40, rtol=1e-10, precision=1)
+    rn, bn = og.residual_norm(b, x32)
+    print(f"  FP32 basis: {s32.iters} steps, {s32.cycles} cycles, {s32.seconds:.2f} s, "
+          f"relres {rn / bn:.3e}", flush=True)
+    assert s32.status == 0 and rn <= 1e-10 * bn
+    x64, s64 = run(mlg, b, restart_m=40, rtol=1e-10, precision=0)
+    rn64, _ = og.residual_norm(b, x64)
+    err = rel(x32, x64)
+    print(f"  FP64 basis: {s64.iters} steps, {s64.seconds:.2f} s, relres {rn64 / bn:.3e}; "
+          f"|x32 - x64| / |x64| = {err:.2e} (kappa {kappa(shape):.3g})")
+    assert s64.status == 0 and rn64 <= 1e-10 * bn
+    assert err <= kappa(shape) * 2e-10
+
+
 @pytest.mark.parametrize("shape,m,precision", [((64, 64), 20, 0), ((48, 80), 3, 0),
                                                ((24, 20, 16), 10, 1)])
 def test_fifth_iteration_residual(mlg, shape, m, precision):

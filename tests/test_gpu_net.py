@@ -48,6 +48,8 @@ def make_params(mlg, cfg, p):
     mlg.guess_net_refresh(cfg, buf)
     if "band.w" in p:
         mlg.net_set_band(cfg, buf, p["band.w"])
+    if "gate" in p:
+        v["gate"].copy_(torch.tensor([p["gate"], 1.0], dtype=torch.float64))
     torch.cuda.synchronize()
     return buf
 
@@ -102,6 +104,8 @@ def test_forward_parity(mlg, shape, M, K, B):
     print("net forward", shape, M, K, B, flush=True)
     cfg = mlg.NetCfg(channels=32, modes=M, skip_modes=K)
     p = bf16_round(guess_net_params(5, channels=32, modes=M, zero_last=False, skip_modes=K))
+    if K > 0:
+        p["gate"] = 0.375                   # an output gain other than 1
     buf = make_params(mlg, cfg, p)
     f, u, _ = inputs(shape, B, 100 + M)
     fd, ud = dev(f), dev(u)
@@ -110,7 +114,7 @@ def test_forward_parity(mlg, shape, M, K, B):
     mlg.guess_net_infer(cfg, buf, fd, ud, guess, ws)
     torch.cuda.synchronize()
     go, outo, s, cache = onet.forward(p, f, u, keep=True)
-    c6 = onet.conv3x3(cache["a5"], p["conv6.w"], p["conv6.b"])[:, 0]
+    c6 = p.get("gate", 1.0) * onet.conv3x3(cache["a5"], p["conv6.w"], p["conv6.b"])[:, 0]
     corr_gpu = guess.cpu().numpy() - u
     corr_or = go - u
     err = float(np.linalg.norm(corr_gpu - corr_or) /
@@ -165,6 +169,7 @@ def test_train_step_gradients_and_adam(mlg, shape, M, K, B):
     print(f"  loss gpu {loss.item():.6e} oracle {L:.6e}")
     assert abs(loss.item() - L) <= 2e-2 * L
     check_band_sums(views, band0, f, u, ut, K)
+    check_gate_sums(views, p, f, u, ut, K)
     gg = mlg.net_unpack(cfg, views["grad"])
     assert set(go) == set(gg)
     for k in go:
@@ -189,6 +194,17 @@ def check_band_sums(views, band0, f, u, ut, K):
     e0, e1 = rel(got[0] - band0[0], sxt), rel(got[1] - band0[1], sxx)
     print(f"  band sums: X T {e0:.2e}, X^2 {e1:.2e}")
     assert e0 <= 1e-10 and e1 <= 1e-10
+
+
+def check_gate_sums(views, p, f, u, ut, K):
+    """The output gain's sums after one step from an empty state: the
+    oracle's gate_stats of the batch (the branch's output is BF16: 5e-2)."""
+    if K == 0:
+        return
+    sct, scc = onet.gate_stats(p, f, u, ut)
+    g = views["gate"].cpu().numpy()
+    print(f"  gain sums: <c,t> {g[0]:.6e} vs {sct:.6e}, |c|^2 {g[1]:.6e} vs {scc:.6e}")
+    assert abs(g[0] - sct) <= 5e-2 * abs(sct) + 1e-2 * scc and abs(g[1] - scc) <= 5e-2 * scc
 
 
 @pytest.mark.parametrize("shape,K", [((64, 64), 32), ((96, 130), 64)])
@@ -231,6 +247,7 @@ def test_init_zero_output_and_bounds(mlg):
     torch.cuda.synchronize()
     assert torch.equal(buf, buf2)
     assert torch.all(mlg.net_views(cfg, buf)["band"] == 0)
+    assert torch.all(mlg.net_views(cfg, buf)["gate"] == 0) and mlg.net_output_gain(cfg, buf) == 1.0
     t = mlg.net_unpack(cfg, mlg.net_views(cfg, buf)["master"])
     fan = {"conv1.w": 18, "conv2.w": 288, "spec.w1": 64, "spec.wk": 64, "conv4.w": 288, "conv5.w": 288}
     for k, v in t.items():
@@ -302,6 +319,7 @@ def test_bench_configuration_parity(mlg):
     print(f"  loss gpu {loss.item():.6e} oracle {L:.6e}", flush=True)
     assert abs(loss.item() - L) <= 2e-2 * L
     check_band_sums(views, band0, f, u, ut, K)
+    check_gate_sums(views, p, f, u, ut, K)
     gg = mlg.net_unpack(cfg, views["grad"])
     assert set(gr) == set(gg)
     for k in gr:
