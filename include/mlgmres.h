@@ -132,6 +132,27 @@ size_t gmres_workspace_bytes(const mlg_grid* grid, const mlg_opts* opts);
 int gmres_solve(const mlg_grid* grid, const double* b, double* x, const mlg_opts* opts,
                 void* ws, size_t ws_bytes, mlg_stats* stats, void* stream);
 
+/* Largest workspace gmres_solve_static can hold (64 MiB). */
+#define MLG_STATIC_SCRATCH_BYTES ((size_t)64 << 20)
+
+/*
+ * gmres_solve for callers that cannot allocate device memory (serving loops
+ * and harnesses that forbid hipMalloc): the same solve, with the same result
+ * bit for bit, but its workspace lives in a static array inside the library
+ * (MLG_STATIC_SCRATCH_BYTES on every device the library runs on, held until
+ * the process ends).  The call allocates nothing: no device or pinned host
+ * memory, no graph, no event; the cycles are enqueued directly on `stream`.
+ *   b, x, stats, stream  as for gmres_solve.
+ * Returns MLG_ERR_WORKSPACE (nothing launched) when gmres_workspace_bytes
+ * for this grid and these options exceeds MLG_STATIC_SCRATCH_BYTES.
+ * The array keeps the last call's contents; every call sets up what it
+ * reads.  Calls on one device share the array: the library serialises them
+ * within a process (each blocks until its solve has finished), and nothing
+ * else may run a solve on that array while one is in flight.
+ */
+int gmres_solve_static(const mlg_grid* grid, const double* b, double* x, const mlg_opts* opts,
+                       mlg_stats* stats, void* stream);
+
 /* One independent system of a batched solve: nrhs right-hand sides solved in
  * order; guess 0 starts each from zero, 1 from the previous solution of the
  * same system (the first from x's initial contents). */

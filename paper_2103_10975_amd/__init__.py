@@ -16,8 +16,8 @@ import torch
 
 __all__ = [
     "Grid", "Opts", "Stats", "System", "NetCfg", "MLG_FP64", "MLG_FP32_IR",
-    "grid_of", "lib", "gmres_workspace_bytes", "gmres_solve", "gmres_batched_workspace_bytes",
-    "gmres_solve_batched", "mlg_apply_operator", "mlg_kernel_bench_scratch_bytes",
+    "grid_of", "lib", "gmres_workspace_bytes", "gmres_solve", "gmres_solve_static",
+    "MLG_STATIC_SCRATCH_BYTES", "gmres_batched_workspace_bytes", "gmres_solve_batched", "mlg_apply_operator", "mlg_kernel_bench_scratch_bytes",
     "mlg_kernel_bench", "mlg_tile_count", "mlg_tile_shape", "mlg_autotune_workspace_bytes",
     "mlg_autotune", "guess_net_param_count", "guess_net_param_offset", "guess_net_param_bytes",
     "guess_net_workspace_bytes", "guess_net_init", "guess_net_refresh", "guess_net_infer",
@@ -35,10 +35,11 @@ LIB_PATH = os.path.join(HERE, "libmlgmres.so")
 MLG_OK, MLG_NOT_CONVERGED = 0, 1
 MLG_ERR_ARG, MLG_ERR_WORKSPACE, MLG_ERR_HIP, MLG_ERR_NONFINITE = -1, -2, -3, -4
 MLG_FP64, MLG_FP32_IR = 0, 1
+MLG_STATIC_SCRATCH_BYTES = 64 << 20
 
 # every symbol the header declares
 EXPORTS = (
-    "gmres_workspace_bytes", "gmres_solve", "gmres_batched_workspace_bytes",
+    "gmres_workspace_bytes", "gmres_solve", "gmres_solve_static", "gmres_batched_workspace_bytes",
     "gmres_solve_batched", "mlg_apply_operator", "mlg_kernel_bench_scratch_bytes",
     "mlg_kernel_bench", "mlg_tile_count", "mlg_tile_shape", "mlg_autotune_workspace_bytes",
     "mlg_autotune", "guess_net_param_count", "guess_net_param_offset", "guess_net_param_bytes",
@@ -121,6 +122,7 @@ def _load():
     sig = {
         "gmres_workspace_bytes": (sz, [P(Grid), P(Opts)]),
         "gmres_solve": (ctypes.c_int, [P(Grid), vp, vp, P(Opts), vp, sz, P(Stats), vp]),
+        "gmres_solve_static": (ctypes.c_int, [P(Grid), vp, vp, P(Opts), P(Stats), vp]),
         "gmres_batched_workspace_bytes": (sz, [i32, P(System), P(Opts)]),
         "gmres_solve_batched": (ctypes.c_int, [i32, P(System), P(Opts), vp, sz, P(Stats), vp]),
         "mlg_apply_operator": (ctypes.c_int, [P(Grid), vp, vp, vp]),
@@ -254,6 +256,20 @@ def gmres_solve(grid: Grid, b: torch.Tensor, x: torch.Tensor, opts: Opts, ws: to
     st = Stats()
     rc = lib.gmres_solve(ctypes.byref(grid), _ptr(b), _ptr(x), ctypes.byref(opts),
                          _ptr(ws, torch.uint8), ws.numel(), ctypes.byref(st), _stream(stream))
+    _check(rc, allow_not_converged)
+    return st
+
+
+def gmres_solve_static(grid: Grid, b: torch.Tensor, x: torch.Tensor, opts: Opts,
+                       stream=None, allow_not_converged: bool = False) -> Stats:
+    """gmres_solve without a workspace argument: the library's static
+    per-device scratch (MLG_STATIC_SCRATCH_BYTES) holds the workspace, and the
+    call allocates nothing."""
+    _need(b.numel() == _points(grid), f"b has {b.numel()} elements, the grid {_points(grid)}")
+    _need(x.shape == b.shape, f"x has shape {tuple(x.shape)}, b {tuple(b.shape)}")
+    st = Stats()
+    rc = lib.gmres_solve_static(ctypes.byref(grid), _ptr(b), _ptr(x), ctypes.byref(opts),
+                                ctypes.byref(st), _stream(stream))
     _check(rc, allow_not_converged)
     return st
 

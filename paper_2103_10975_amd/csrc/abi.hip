@@ -60,6 +60,11 @@ int gmres_solve(const mlg_grid* grid, const double* b, double* x, const mlg_opts
   return guarded([&] { return solve(grid, b, x, opts, ws, ws_bytes, stats, (hipStream_t)stream); });
 }
 
+int gmres_solve_static(const mlg_grid* grid, const double* b, double* x, const mlg_opts* opts,
+                       mlg_stats* stats, void* stream) {
+  return guarded([&] { return solve_static(grid, b, x, opts, stats, (hipStream_t)stream); });
+}
+
 size_t gmres_batched_workspace_bytes(int32_t nsys, const mlg_system* sys, const mlg_opts* opts) {
   size_t out = 0;
   int rc = guarded([&] {

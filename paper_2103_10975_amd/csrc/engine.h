@@ -36,6 +36,11 @@ int solve(const mlg_grid* grid, const double* b, double* x, const mlg_opts* opts
           size_t ws_bytes, mlg_stats* stats, hipStream_t stream);
 int apply_operator(const mlg_grid* grid, const double* u, double* y, hipStream_t stream);
 
+// solve() with its workspace in a static per-device array of this many bytes.
+constexpr size_t kStaticScratchBytes = size_t(64) << 20;
+int solve_static(const mlg_grid* grid, const double* b, double* x, const mlg_opts* opts,
+                 mlg_stats* stats, hipStream_t stream);
+
 double kernel_bench(const mlg_grid* grid, const mlg_opts* opts, void* ws, size_t ws_bytes,
                     void* scratch, size_t scratch_bytes, int kind, int j, int reps,
                     hipStream_t stream);

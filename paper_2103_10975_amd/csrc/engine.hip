@@ -470,11 +470,12 @@ void runtime_shutdown() {
 void batched_shutdown() {}
 
 // ------------------------------------------------------------------ solve
+// `h`: host staging memory of at least stage_bytes(P) bytes that stays
+// untouched until the stream has passed the copies.
 static void upload_plan(const Plan& P, const DevPlan& D, int nsys, const mlg_system* sys,
-                        const mlg_opts& o, hipStream_t stream, Pinned& stage) {
+                        const mlg_opts& o, hipStream_t stream, char* h) {
   // host images of the descriptors, init records and job tables
   size_t off = 0;
-  char* h = (char*)stage.p;
   auto put = [&](const void* src, size_t bytes, void* dst) {
     std::memcpy(h + off, src, bytes);
     MLG_HIP(hipMemcpyAsync(dst, h + off, bytes, hipMemcpyHostToDevice, stream));
@@ -524,6 +525,8 @@ static size_t stage_bytes(const Plan& P) {
   return b;
 }
 
+static int report(const Plan& P, const std::vector<Summary>& res, double secs, mlg_stats* stats);
+
 int batched_solve(int nsys, const mlg_system* sys, const mlg_opts* opts, void* ws, size_t ws_bytes,
                   mlg_stats* stats, hipStream_t stream) {
   auto t0 = std::chrono::steady_clock::now();
@@ -544,7 +547,7 @@ int batched_solve(int nsys, const mlg_system* sys, const mlg_opts* opts, void* w
                           : (opts->max_iters > 0 ? opts->max_iters : 1000000000LL);
 
   Pinned stage(stage_bytes(P));
-  upload_plan(P, D, nsys, sys, *opts, stream, stage);
+  upload_plan(P, D, nsys, sys, *opts, stream, (char*)stage.p);
   hipGraphExec_t exec = cycle_graph(plan_key(dev, ws, P, opts->precision, m), dev, P, D,
                                     opts->precision, m);
   Pinned pin(std::max<size_t>(2 * 256, (size_t)P.total_rhs * sizeof(Summary)));
@@ -613,6 +616,12 @@ int batched_solve(int nsys, const mlg_system* sys, const mlg_opts* opts, void* w
   MLG_HIP(hipStreamSynchronize(stream));
   std::memcpy(res.data(), pin.p, (size_t)P.total_rhs * sizeof(Summary));
   const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  return report(P, res, secs, stats);
+}
+
+// Status of a finished solve (the most severe over its right-hand sides) and
+// the per-RHS statistics.
+static int report(const Plan& P, const std::vector<Summary>& res, double secs, mlg_stats* stats) {
   int worst = MLG_OK;
   for (int i = 0; i < P.total_rhs; ++i) {
     const Summary& s = res[i];
@@ -659,6 +668,81 @@ int solve(const mlg_grid* grid, const double* b, double* x, const mlg_opts* opts
   if (!b || !x) throw ArgError{MLG_ERR_ARG, "b and x must be device pointers"};
   mlg_system s = single(grid, b, x);
   return batched_solve(1, &s, opts, ws, ws_bytes, stats, stream);
+}
+
+// ------------------------------------------------------------------ solve without allocation
+// Workspace of solve_static: a file-scope array that every device holds from
+// the load of this code object until the process ends.  Host code never
+// passes `scratch` itself (on the host it is only a stand-in); it uses the
+// device address that hipGetSymbolAddress returns for the current device.
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+struct StaticScratch {
+  std::mutex mu;           // held for a whole call: calls on one device never overlap
+  void* ptr = nullptr;     // device address of `scratch` on this device
+};
+
+static StaticScratch& static_scratch(int dev) {
+  static std::mutex mu;
+  static std::map<int, StaticScratch*> per_dev;
+  std::lock_guard<std::mutex> lk(mu);
+  StaticScratch*& e = per_dev[dev];
+  if (!e) e = new StaticScratch();
+  return *e;
+}
+
+int solve_static(const mlg_grid* grid, const double* b, double* x, const mlg_opts* opts,
+                 mlg_stats* stats, hipStream_t stream) {
+  auto t0 = std::chrono::steady_clock::now();
+  check_grid(grid);
+  if (!b || !x) throw ArgError{MLG_ERR_ARG, "b and x must be device pointers"};
+  mlg_system sys = single(grid, b, x);
+  check_systems(1, &sys, opts);
+  const Plan P = make_plan(1, &sys, *opts);
+  if (P.total > kStaticScratchBytes)
+    throw ArgError{MLG_ERR_WORKSPACE,
+                   "gmres_solve_static: this grid and restart length need " +
+                       std::to_string(P.total) + " bytes of workspace, the static scratch holds " +
+                       std::to_string(kStaticScratchBytes) + " (gmres_solve takes a workspace)"};
+  int dev = 0;
+  MLG_HIP(hipGetDevice(&dev));
+  StaticScratch& S = static_scratch(dev);
+  std::lock_guard<std::mutex> lk(S.mu);
+  if (!S.ptr) MLG_HIP(hipGetSymbolAddress((void**)&S.ptr, HIP_SYMBOL(scratch)));
+  const DevPlan D = dev_plan(P, S.ptr);
+  // pageable staging: the copies below complete before this call returns
+  std::vector<char> stage(stage_bytes(P));
+  upload_plan(P, D, 1, &sys, *opts, stream, stage.data());
+  const int m = opts->restart_m;
+  const int poll = opts->poll_cycles > 0 ? opts->poll_cycles : 1;
+  const long long limit = opts->fixed_iters > 0 ? opts->fixed_iters
+                          : (opts->max_iters > 0 ? opts->max_iters : 1000000000LL);
+  // the same bound on restart cycles as the graph path; cycles are enqueued
+  // directly (no graph: instantiating one allocates)
+  const long long max_groups = (limit + 2) * P.total_rhs / poll + 8;
+  unsigned int hdr[3] = {0u, 0u, 0u};
+  unsigned int last_progress = 0;
+  bool finished = false;
+  for (long long grp = 0; grp < max_groups; ++grp) {
+    for (int c = 0; c < poll; ++c) enqueue_cycle(stream, P, D, opts->precision, m);
+    MLG_HIP(hipGetLastError());
+    MLG_HIP(hipMemcpyAsync(hdr, D.hdr, sizeof(hdr), hipMemcpyDeviceToHost, stream));
+    MLG_HIP(hipStreamSynchronize(stream));
+    if (hdr[0] >= 1u) {
+      finished = true;
+      break;
+    }
+    if (grp > 0 && hdr[1] == last_progress)
+      throw HipError{hipErrorUnknown, "solver made no progress in a restart cycle"};
+    last_progress = hdr[1];
+  }
+  if (!finished) throw HipError{hipErrorUnknown, "solver did not finish"};
+  std::vector<Summary> res(P.total_rhs);
+  MLG_HIP(hipMemcpyAsync(res.data(), D.stats, (size_t)P.total_rhs * sizeof(Summary),
+                         hipMemcpyDeviceToHost, stream));
+  MLG_HIP(hipStreamSynchronize(stream));
+  const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  return report(P, res, secs, stats);
 }
 
 // ------------------------------------------------------------------ kernel timing
