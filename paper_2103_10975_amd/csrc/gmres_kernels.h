@@ -1015,9 +1015,10 @@ template <class T, class TL, int MM, bool SPLIT>
 __global__ __launch_bounds__(kBlock) void k_step(const Job* jobs, const SysDesc* sd, int j) {
   const Mine me = mine(jobs, sd);
   const gptr<Ctrl> C = gmem((Ctrl*)me.S->C);
-  // the control block is read now but tested only after the first tile's
-  // data loads are in flight (the job record alone locates the data)
-  const int phase = C->phase, cycle_end = C->cycle_end;
+  // a system that is not stepping leaves before any load: the steps after
+  // its cycle ended are replayed as part of the cycle, and must cost no
+  // more than the launch (uniform: the whole workgroup leaves)
+  if (C->phase != PH_RUN || C->cycle_end) return;
   const int tid = threadIdx.x;
   using H1 = Halo<TL, 1>;
   using H2 = Halo<TL, 2>;
@@ -1157,7 +1158,6 @@ __global__ __launch_bounds__(kBlock) void k_step(const Job* jobs, const SysDesc*
           if (e < hlim) L1[e] = hs[k];
         }
       }
-      if (phase != PH_RUN || cycle_end) return false;  // uniform: the whole workgroup leaves
       if constexpr (!SPLIT) {
         if (tid < MM) {
           sY[tid] = tid < j ? sYl : 0.0;

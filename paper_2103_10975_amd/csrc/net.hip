@@ -130,9 +130,14 @@ Dims check_grid_net(const guess_net_cfg* cfg, const mlg_grid* grid, int batch) {
   return d;
 }
 
+// Padded extents of the spectral layer's x basis: modes to a multiple of 16
+// (MFMA tiles), columns to a multiple of the row transform's chunk.
+inline int spec_mp(const Dims& d) { return (d.M + 15) / 16 * 16; }
+inline int spec_wp(const Dims& d) { return (d.W + 255) / 256 * 256; }
+
 struct WsLayout {
-  size_t s, r0, x0, act[5], out, dout, dz[2], T, X, Y, dX, Z, Sx, Sy, part, loss;
-  size_t kT, kX, kC, kY, kZ, kdY, kTc, kXa, ad, kSx, kSxT, kSy, rms, total;   // band path (FP64)
+  size_t s, r0, x0, act[5], out, dout, dz[2], T, X, Y, Z, Sx, Sxh, Sxl, Sy, part, loss;
+  size_t kT, kT2, kX, kC, kZ, kZ2, kdY, kdY2, kTc, kXa, ad, kSx, kSxT, kSy, rms, total;   // band path (FP64)
   int wgrad_blocks;
 };
 
@@ -155,14 +160,18 @@ WsLayout ws_layout(const Dims& d, bool train) {
   L.X = take((size_t)d.B * d.M * d.M * d.C * 4);
   L.Y = take((size_t)d.B * d.M * d.M * d.C * 4);
   L.Z = take((size_t)d.B * d.H * d.M * d.C * 4);
-  L.Sx = take((size_t)d.M * d.W * 4);
+  L.Sx = take((size_t)spec_mp(d) * spec_wp(d) * 4);
+  L.Sxh = take((size_t)spec_mp(d) * spec_wp(d) * 2);
+  L.Sxl = take((size_t)spec_mp(d) * spec_wp(d) * 2);
   L.Sy = take((size_t)d.M * d.H * 4);
   L.kT = take((size_t)d.B * d.H * d.K * 8);
+  L.kT2 = take((size_t)d.B * d.H * d.K * 8);
   L.kX = take((size_t)d.B * d.K * d.K * 8);
   L.kC = take((size_t)d.B * d.K * d.K * 8);
-  L.kY = take((size_t)d.B * d.K * d.K * 8);
   L.kZ = take((size_t)d.B * d.H * d.K * 8);
+  L.kZ2 = train ? take((size_t)d.B * d.H * d.K * 8) : 0;
   L.kdY = train ? take((size_t)d.B * d.K * d.K * 8) : 0;
+  L.kdY2 = train ? take((size_t)d.B * d.K * d.K * 8) : 0;
   L.kTc = train ? take((size_t)d.B * d.K * d.K * 8) : 0;
   L.kXa = train ? take((size_t)d.B * d.K * d.K * 8) : 0;
   L.ad = train && d.K > 0 ? take((size_t)d.B * d.HW * 8) : 0;
@@ -175,7 +184,6 @@ WsLayout ws_layout(const Dims& d, bool train) {
     L.dout = take((size_t)d.B * d.HW * 4);
     L.dz[0] = take(act);
     L.dz[1] = take(act);
-    L.dX = take((size_t)d.B * d.M * d.M * d.C * 4);
     L.wgrad_blocks = 512;
     L.part = take((size_t)L.wgrad_blocks * (9 * d.C * d.C + d.C) * 4);
     L.loss = take(4096 * 8);
@@ -351,51 +359,197 @@ __device__ __forceinline__ void store_ch(float* p, const float (&v)[N]) {
   for (int i = 0; i < N; ++i) p[i] = v[i];
 }
 
-template <int CIN, int COUT, class TIN, class TOUT, bool DGRAD, bool RELU>
-__global__ __launch_bounds__(256) void k_conv_small(const TIN* in, const bf16* wt, const bf16* bias,
-                                                    const bf16* mask, TOUT* out, int H, int W) {
-  __shared__ float wl[9 * COUT * CIN];
-  __shared__ float bl[COUT];
-  for (int e = threadIdx.x; e < 9 * COUT * CIN; e += 256) {
-    int t = e / (COUT * CIN), r = e % (COUT * CIN), co = r / CIN, ci = r % CIN;
-    // forward tensor is [d][c][ky][kx] with d = out, c = in of the forward layer
-    float v = DGRAD ? bf2f(wt[(ci * COUT + co) * 9 + (8 - t)]) : bf2f(wt[(co * CIN + ci) * 9 + t]);
-    wl[e] = v;
-  }
-  for (int e = threadIdx.x; e < COUT; e += 256) bl[e] = (!DGRAD && bias) ? bf2f(bias[e]) : 0.f;
-  __syncthreads();
+// ------------------------------------------------------------------ thin convolutions on MFMA
+// The input (2 -> C) and output (C -> 1) convolutions and the output
+// convolution's input gradient, on the matrix cores although one side of each
+// contraction is thin: a workgroup takes 256 consecutive pixels of one image
+// (each wavefront four 16-pixel steps), every tap read at a clamped position
+// with all of a step's loads in flight, taps outside the grid zeroed by a
+// select.  The weights are read once per thread as the 32-bit words that hold
+// them.
+__device__ __forceinline__ uint32_t bf16_word_pick(const bf16* base, long long e) {
+  const uint32_t w = *reinterpret_cast<const uint32_t*>(base + (e & ~1LL));
+  return (e & 1) ? (w >> 16) : (w & 0xffffu);
+}
+
+// out[p][co] = ReLU(bias[co] + sum_{t, ci} W[co][ci][t] in[p + off(t)][ci]) for
+// 2 input channels, v_mfma_f32_16x16x32_bf16 with K = 9 taps x 2 channels
+// (padded to 32): A = W (16 channels x 32), B = the 18 tap values of 16
+// pixels (a lane: four taps x both channels, four 4-byte reads).
+template <int C>
+__global__ __launch_bounds__(256) void k_conv_in_mfma(const bf16* in, const bf16* wt,
+                                                      const bf16* bias, bf16* out, int H, int W) {
+  static_assert(C == 32, "two 16-channel tiles");
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int li = lane & 15, lg = lane >> 4;
   const int b = blockIdx.y;
   const long long HW = (long long)H * W;
-  const long long p = (long long)blockIdx.x * 256 + threadIdx.x;
-  if (p >= HW) return;
-  const int y = (int)(p / W), x = (int)(p % W);
-  float acc[COUT];
+  // A[co][k], k = 8 lg + e: tap t = 4 lg + e / 2, channel e % 2 (zero for t >= 9)
+  bf16x8 wa[2];
+  float bl[2][4];
 #pragma unroll
-  for (int co = 0; co < COUT; ++co) acc[co] = bl[co];
-  const TIN* inb = in + (size_t)b * HW * CIN;
+  for (int mt = 0; mt < 2; ++mt) {
+    const int co = mt * 16 + li;
+    uint32_t h[8];
 #pragma unroll
-  for (int t = 0; t < 9; ++t) {
-    const int yy = y + t / 3 - 1, xx = x + t % 3 - 1;
-    if (yy < 0 || yy >= H || xx < 0 || xx >= W) continue;
-    float v[CIN];
-    load_ch<CIN>(inb + ((long long)yy * W + xx) * CIN, v);
+    for (int e = 0; e < 8; ++e) {
+      const int tt = 4 * lg + e / 2, ci = e % 2;
+      const uint32_t v = bf16_word_pick(wt, (long long)(co * 2 + ci) * 9 + min(tt, 8));
+      h[e] = tt < 9 ? v : 0u;
+    }
+    wa[mt] = __builtin_bit_cast(bf16x8, make_uint4(h[0] | (h[1] << 16), h[2] | (h[3] << 16),
+                                                   h[4] | (h[5] << 16), h[6] | (h[7] << 16)));
 #pragma unroll
-    for (int ci = 0; ci < CIN; ++ci) {
+    for (int r = 0; r < 4; ++r) bl[mt][r] = bf2f(bias[mt * 16 + 4 * lg + r]);
+  }
+  const uint32_t* inw = reinterpret_cast<const uint32_t*>(in) + (size_t)b * HW;   // one word per pixel
+#pragma unroll 1
+  for (int st = 0; st < 4; ++st) {
+    const long long p = (long long)blockIdx.x * 256 + wv * 64 + st * 16 + li;
+    if ((long long)blockIdx.x * 256 + wv * 64 + st * 16 >= HW) break;    // wavefront-uniform
+    const long long pc = p < HW ? p : HW - 1;
+    const int y = (int)(pc / W), x = (int)(pc % W);
+    uint32_t v[4];
 #pragma unroll
-      for (int co = 0; co < COUT; ++co) acc[co] += wl[(t * COUT + co) * CIN + ci] * v[ci];
+    for (int q = 0; q < 4; ++q) {
+      const int tt = 4 * lg + q, dy = tt / 3 - 1, dx = tt % 3 - 1;
+      const int yy = y + dy, xx = x + dx;
+      const uint32_t w = inw[(long long)min(max(yy, 0), H - 1) * W + min(max(xx, 0), W - 1)];
+      v[q] = (tt < 9 && yy >= 0 && yy < H && xx >= 0 && xx < W) ? w : 0u;
+    }
+    const bf16x8 bx = __builtin_bit_cast(bf16x8, make_uint4(v[0], v[1], v[2], v[3]));
+    floatx4 acc[2];
+#pragma unroll
+    for (int mt = 0; mt < 2; ++mt)
+      acc[mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa[mt], bx, floatx4{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
+    if (p < HW) {
+#pragma unroll
+      for (int mt = 0; mt < 2; ++mt) {
+        float o[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) o[r] = fmaxf(acc[mt][r] + bl[mt][r], 0.f);
+        uint2 w2;
+        w2.x = (uint32_t)f2bf(o[0]) | ((uint32_t)f2bf(o[1]) << 16);
+        w2.y = (uint32_t)f2bf(o[2]) | ((uint32_t)f2bf(o[3]) << 16);
+        *reinterpret_cast<uint2*>(out + ((size_t)b * HW + p) * C + mt * 16 + 4 * lg) = w2;
+      }
     }
   }
-  if (RELU) {
+}
+
+// out[p] = bias + sum_{t, ci} W[0][ci][t] in[p + off(t)][ci] (C -> 1, FP32
+// out): v_mfma_f32_16x16x32_bf16 per tap with the pixels as rows, A = the
+// input (16 pixels x 32 channels, one 16-byte read per lane and tap), B = the
+// tap's weights in column 0 (the other columns zero); D column 0 holds the
+// 16 outputs.
+template <int C>
+__global__ __launch_bounds__(256) void k_conv_out_mfma(const bf16* in, const bf16* wt,
+                                                       const bf16* bias, float* out, int H, int W) {
+  static_assert(C == 32, "one K = 32 step per tap");
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int li = lane & 15, lg = lane >> 4;
+  const int b = blockIdx.y;
+  const long long HW = (long long)H * W;
+  // B[k][n] = W[0][8 lg + e][t] for n = 0
+  bf16x8 wb[9];
 #pragma unroll
-    for (int co = 0; co < COUT; ++co) acc[co] = fmaxf(acc[co], 0.f);
-  }
-  if constexpr (DGRAD) {
-    float mk[COUT];
-    load_ch<COUT>(mask + ((size_t)b * HW + p) * COUT, mk);
+  for (int t = 0; t < 9; ++t) {
+    uint32_t h[8];
 #pragma unroll
-    for (int co = 0; co < COUT; ++co) acc[co] = mk[co] > 0.f ? acc[co] : 0.f;
+    for (int e = 0; e < 8; ++e) h[e] = bf16_word_pick(wt, (long long)(8 * lg + e) * 9 + t);
+#pragma unroll
+    for (int e = 0; e < 8; ++e) h[e] = li == 0 ? h[e] : 0u;
+    wb[t] = __builtin_bit_cast(bf16x8, make_uint4(h[0] | (h[1] << 16), h[2] | (h[3] << 16),
+                                                  h[4] | (h[5] << 16), h[6] | (h[7] << 16)));
   }
-  store_ch<COUT>(out + ((size_t)b * HW + p) * COUT, acc);
+  const float bv = bf2f(bias[0]);
+  const bf16* inb = in + (size_t)b * HW * C;
+#pragma unroll 1
+  for (int st = 0; st < 4; ++st) {
+    const long long p0 = (long long)blockIdx.x * 256 + wv * 64 + st * 16;
+    if (p0 >= HW) break;                                   // wavefront-uniform
+    const long long p = p0 + li, pc = p < HW ? p : HW - 1;
+    const int y = (int)(pc / W), x = (int)(pc % W);
+    uint4 a[9];
+#pragma unroll
+    for (int t = 0; t < 9; ++t) {
+      const int yy = y + t / 3 - 1, xx = x + t % 3 - 1;
+      const uint4 u = *reinterpret_cast<const uint4*>(
+          inb + ((long long)min(max(yy, 0), H - 1) * W + min(max(xx, 0), W - 1)) * C + 8 * lg);
+      const bool ok = yy >= 0 && yy < H && xx >= 0 && xx < W;
+      a[t] = ok ? u : make_uint4(0, 0, 0, 0);
+    }
+    floatx4 acc = floatx4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int t = 0; t < 9; ++t)
+      acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a[t]), wb[t], acc, 0, 0, 0);
+    // D[p][n]: lane holds pixels p0 + 4 lg + r of column li
+    if (li == 0) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const long long q = p0 + 4 * lg + r;
+        if (q < HW) out[(size_t)b * HW + q] = acc[r] + bv;
+      }
+    }
+  }
+}
+
+// dz[p][co] = (mask[p][co] > 0) * sum_t W[0][co][8 - t] dout[p + off(t)]: the
+// input gradient of the C -> 1 convolution from the FP32 output gradient, on
+// v_mfma_f32_16x16x4_f32 (K = 4 taps per step, three steps): A = the flipped
+// weights (16 channels x 4 taps), B = the output gradient at the taps (4 x 16
+// pixels), in FP32.
+template <int C>
+__global__ __launch_bounds__(256) void k_conv_outT_mfma(const float* dout, const bf16* wt,
+                                                        const bf16* mask, bf16* dz, int H, int W) {
+  static_assert(C == 32, "two 16-channel tiles");
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int li = lane & 15, lg = lane >> 4;
+  const int b = blockIdx.y;
+  const long long HW = (long long)H * W;
+  float wa[3][2];
+#pragma unroll
+  for (int s = 0; s < 3; ++s)
+#pragma unroll
+    for (int mt = 0; mt < 2; ++mt) {
+      const int tt = 4 * s + lg, co = mt * 16 + li;
+      const float v = bf2f((bf16)bf16_word_pick(wt, (long long)co * 9 + (8 - min(tt, 8))));
+      wa[s][mt] = tt < 9 ? v : 0.f;
+    }
+  const float* db = dout + (size_t)b * HW;
+#pragma unroll 1
+  for (int st = 0; st < 4; ++st) {
+    const long long p0 = (long long)blockIdx.x * 256 + wv * 64 + st * 16;
+    if (p0 >= HW) break;                                   // wavefront-uniform
+    const long long p = p0 + li, pc = p < HW ? p : HW - 1;
+    const int y = (int)(pc / W), x = (int)(pc % W);
+    float bvv[3];
+#pragma unroll
+    for (int s = 0; s < 3; ++s) {
+      const int tt = 4 * s + lg, yy = y + tt / 3 - 1, xx = x + tt % 3 - 1;
+      const float v = db[(long long)min(max(yy, 0), H - 1) * W + min(max(xx, 0), W - 1)];
+      bvv[s] = (tt < 9 && yy >= 0 && yy < H && xx >= 0 && xx < W) ? v : 0.f;
+    }
+    const size_t base = ((size_t)b * HW + pc) * C;
+#pragma unroll
+    for (int mt = 0; mt < 2; ++mt) {
+      floatx4 acc = floatx4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int s = 0; s < 3; ++s) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(wa[s][mt], bvv[s], acc, 0, 0, 0);
+      // lane holds channels mt*16 + 4 lg + r of pixel p
+      const uint2 mu = *reinterpret_cast<const uint2*>(mask + base + mt * 16 + 4 * lg);
+      if (p >= HW) continue;
+      const float m4[4] = {__uint_as_float(mu.x << 16), __uint_as_float(mu.x & 0xffff0000u),
+                           __uint_as_float(mu.y << 16), __uint_as_float(mu.y & 0xffff0000u)};
+      float o[4];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) o[r] = m4[r] > 0.f ? acc[r] : 0.f;
+      uint2 w2;
+      w2.x = (uint32_t)f2bf(o[0]) | ((uint32_t)f2bf(o[1]) << 16);
+      w2.y = (uint32_t)f2bf(o[2]) | ((uint32_t)f2bf(o[3]) << 16);
+      *reinterpret_cast<uint2*>(dz + base + mt * 16 + 4 * lg) = w2;
+    }
+  }
 }
 
 // Weight gradient of the C -> 1 output convolution (C = 32):
@@ -546,22 +700,29 @@ __global__ __launch_bounds__(256) void k_wgrad_in(const bf16* x, const bf16* dz,
 
 // grad[...] = sum over blocks of the partials (fixed order).  Partial element
 // e = (t*COUT + d)*CIN + c maps to the torch layout (d*CIN + c)*ntap + t; the
-// trailing COUT elements are bias gradients.
-__global__ void k_wgrad_reduce(const float* part, int nblk, int ntap, int cout, int cin,
-                               float* gw, float* gb) {
-  const int nw = ntap * cout * cin;
-  const int e = blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= nw + cout) return;
-  const int stride = nw + cout;
-  // eight running sums (independent loads in flight), added in a fixed order
+// trailing COUT elements are bias gradients.  A workgroup takes 64 elements
+// (lanes); its four wavefronts sum a quarter of the blocks each (eight
+// independent running sums), and the quarters are added in a fixed order.
+__global__ __launch_bounds__(256) void k_wgrad_reduce(const float* part, int nblk, int ntap,
+                                                      int cout, int cin, float* gw, float* gb) {
+  __shared__ float red[4][64];
+  const int nw = ntap * cout * cin, stride = nw + cout;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int e = blockIdx.x * 64 + lane;
+  const int ka = nblk * w / 4, kb = nblk * (w + 1) / 4;
   float a[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-  int k = 0;
-  for (; k + 8 <= nblk; k += 8) {
+  if (e < stride) {
+    int k = ka;
+    for (; k + 8 <= kb; k += 8) {
 #pragma unroll
-    for (int q = 0; q < 8; ++q) a[q] += part[(size_t)(k + q) * stride + e];
+      for (int q = 0; q < 8; ++q) a[q] += part[(size_t)(k + q) * stride + e];
+    }
+    for (; k < kb; ++k) a[0] += part[(size_t)k * stride + e];
   }
-  for (; k < nblk; ++k) a[0] += part[(size_t)k * stride + e];
-  const float s = ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
+  red[w][lane] = ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
+  __syncthreads();
+  if (w != 0 || e >= stride) return;
+  const float s = ((red[0][lane] + red[1][lane]) + red[2][lane]) + red[3][lane];
   if (e < nw) {
     const int t = e / (cout * cin), r = e % (cout * cin), d = r / cin, c = r % cin;
     gw[(d * cin + c) * ntap + t] = s;
@@ -837,96 +998,290 @@ __global__ __launch_bounds__(256) void k_wgrad_mfma(const bf16* in, const bf16* 
 }
 
 // ------------------------------------------------------------------ spectral layer
-// S[k][j] = sin((k+1) pi (j+1) / (n+1)): the slowest sine modes (DST-I basis).
-__global__ void k_basis(float* S, int M, int n) {
-  const int e = blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= M * n) return;
-  const int k = e / n, j = e % n;
-  S[e] = (float)sin((double)(k + 1) * M_PI * (double)(j + 1) / (double)(n + 1));
+// Sine bases (DST-I): S[k][j] = sin((k+1) pi (j+1) / (n+1)), the slowest modes.
+// Every basis one pass needs, in one launch:
+//   Sx       FP32 [MP][WP]  x direction of the spectral layer, zero for k >= M
+//            or j >= W (MP = M rounded up to 16, WP = W rounded up to 256)
+//   Sxh, Sxl BF16 [MP][WP]  Sx = Sxh + Sxl to within 2^-17 |Sx| (the two BF16
+//            halves of the MFMA row transform)
+//   Sy       FP32 [M][H]    y direction of the spectral layer
+//   kSx      FP64 [K][W], kSxT FP64 [W][K], kSy FP64 [K][H]  the band path
+struct Bases {
+  float* Sx;
+  bf16* Sxh;
+  bf16* Sxl;
+  float* Sy;
+  double* kSx;
+  double* kSxT;
+  double* kSy;
+  int M, MP, W, WP, H, K;
+};
+
+__device__ __forceinline__ double sine_mode(int k, int j, int n) {
+  return sin((double)(k + 1) * M_PI * (double)(j + 1) / (double)(n + 1));
 }
 
-// T[b][i][l][c] = sum_j Sx[l][j] in[b][i][j][c]  (one block per image row)
+__global__ void k_bases(Bases o) {
+  long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long long n1 = (long long)o.MP * o.WP, n2 = (long long)o.M * o.H;
+  const long long n3 = (long long)o.K * o.W, n4 = (long long)o.K * o.H;
+  if (e < n1) {
+    const int k = (int)(e / o.WP), j = (int)(e % o.WP);
+    const float f = (k < o.M && j < o.W) ? (float)sine_mode(k, j, o.W) : 0.f;
+    const bf16 h = f2bf(f);
+    o.Sx[e] = f;
+    o.Sxh[e] = h;
+    o.Sxl[e] = f2bf(f - bf2f(h));
+    return;
+  }
+  e -= n1;
+  if (e < n2) {
+    o.Sy[e] = (float)sine_mode((int)(e / o.H), (int)(e % o.H), o.H);
+    return;
+  }
+  e -= n2;
+  if (e < n3) {
+    const int k = (int)(e / o.W), j = (int)(e % o.W);
+    const double v = sine_mode(k, j, o.W);
+    o.kSx[e] = v;
+    o.kSxT[(size_t)j * o.K + k] = v;
+    return;
+  }
+  e -= n3;
+  if (e < n4) o.kSy[e] = sine_mode((int)(e / o.H), (int)(e % o.H), o.H);
+}
+
+constexpr int kRowChunk = 256;                   // columns per staged chunk (WP's multiple)
+
+// T[r][l][c] = sum_j Sx[l][j] x[r][j][c] for l < M (r = b H + i): the row
+// transform of the spectral layer on v_mfma_f32_16x16x32_bf16, the FP32 basis
+// taken as Sxh + Sxl (two BF16 products into FP32 accumulators; the split
+// leaves 2^-17 of the basis, below the FP32 rounding of a row sum).  A = basis
+// (16 modes x 32 columns, one 16-byte read per lane), B = the row (32 columns
+// x 16 channels) from an LDS copy transposed to [channel][column], staged in
+// chunks of 256 columns.  The four wavefronts take a quarter of every chunk;
+// their partial products are added in a fixed order.  One workgroup per row.
 template <int C>
-__global__ __launch_bounds__(256) void k_spec_rows(const bf16* in, const float* Sx, float* T, int H,
-                                                   int W, int M) {
-  __shared__ float xs[64 * C];
-  __shared__ float ss[32 * 64];
-  const int row = blockIdx.x;             // b*H + i
-  const bf16* ip = in + (size_t)row * W * C;
-  const int npair = M * C;
-  float acc[8];                                   // up to 8 (l, c) pairs per thread
+__global__ __launch_bounds__(256) void k_spec_rows(const bf16* in, const bf16* Sxh, const bf16* Sxl,
+                                                   float* T, int W, int WP, int M) {
+  static_assert(C == 32, "two 16-channel tiles");
+  constexpr int JC = kRowChunk, PJ = JC + 8, CH = C / 8, MTM = 2;
+  __shared__ __attribute__((aligned(16))) bf16 xT[C * PJ];
+  __shared__ float red[4][MTM * 2 * 4][64];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int li = lane & 15, lg = lane >> 4;
+  const int MT = (M + 15) / 16;
+  const size_t row = blockIdx.x;
+  const bf16* ip = in + row * W * C;
+  floatx4 acc[MTM][2];
 #pragma unroll
-  for (int i = 0; i < 8; ++i) acc[i] = 0.f;
-  for (int j0 = 0; j0 < W; j0 += 64) {
-    const int nj = min(64, W - j0);
-    __syncthreads();
-    for (int e = threadIdx.x; e < nj * C; e += 256) xs[e] = bf2f(ip[(size_t)j0 * C + e]);
-    for (int e = threadIdx.x; e < M * 64; e += 256) {
-      const int l = e / 64, jj = e % 64;
-      ss[e] = jj < nj ? Sx[(size_t)l * W + j0 + jj] : 0.f;
+  for (int mt = 0; mt < MTM; ++mt)
+    for (int ct = 0; ct < 2; ++ct) acc[mt][ct] = floatx4{0.f, 0.f, 0.f, 0.f};
+  for (int j0 = 0; j0 < W; j0 += JC) {
+    __syncthreads();                               // the previous chunk's reads are done
+    // a unit = two adjacent columns x 8 channels -> 8 channel rows, one dword each
+    for (int u = threadIdx.x; u < (JC / 2) * CH; u += 256) {
+      const int pr = u / CH, ch = u % CH, q = 2 * pr, j = j0 + q;
+      uint4 v0 = make_uint4(0, 0, 0, 0), v1 = v0;
+      if (j < W) v0 = *reinterpret_cast<const uint4*>(ip + (size_t)j * C + ch * 8);
+      if (j + 1 < W) v1 = *reinterpret_cast<const uint4*>(ip + (size_t)(j + 1) * C + ch * 8);
+      const uint32_t a0[4] = {v0.x, v0.y, v0.z, v0.w}, a1[4] = {v1.x, v1.y, v1.z, v1.w};
+#pragma unroll
+      for (int h = 0; h < 4; ++h) {
+        *reinterpret_cast<uint32_t*>(&xT[(ch * 8 + 2 * h) * PJ + q]) = (a0[h] & 0xffffu) | (a1[h] << 16);
+        *reinterpret_cast<uint32_t*>(&xT[(ch * 8 + 2 * h + 1) * PJ + q]) =
+            (a0[h] >> 16) | (a1[h] & 0xffff0000u);
+      }
     }
     __syncthreads();
 #pragma unroll
-    for (int i = 0; i < 8; ++i) {
-      const int pr = threadIdx.x + 256 * i;
-      if (pr >= npair) break;
-      const int l = pr / C, c = pr % C;
-      float s = 0.f;
-      for (int jj = 0; jj < nj; ++jj) s += ss[l * 64 + jj] * xs[jj * C + c];
-      acc[i] += s;
+    for (int s = 0; s < JC / 128; ++s) {           // this wavefront's 32-column steps
+      const int jl = (wv * (JC / 128) + s) * 32;
+      bf16x8 bx[2];
+#pragma unroll
+      for (int ct = 0; ct < 2; ++ct)
+        bx[ct] = __builtin_bit_cast(bf16x8,
+                                    *reinterpret_cast<const uint4*>(&xT[(ct * 16 + li) * PJ + jl + 8 * lg]));
+#pragma unroll
+      for (int mt = 0; mt < MTM; ++mt) {
+        if (mt >= MT) break;                       // uniform
+        const size_t ao = (size_t)(mt * 16 + li) * WP + j0 + jl + 8 * lg;
+        const bf16x8 ah = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(Sxh + ao));
+        const bf16x8 al = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(Sxl + ao));
+#pragma unroll
+        for (int ct = 0; ct < 2; ++ct) {
+          acc[mt][ct] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bx[ct], acc[mt][ct], 0, 0, 0);
+          acc[mt][ct] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bx[ct], acc[mt][ct], 0, 0, 0);
+        }
+      }
     }
   }
+  // D[mode][channel]: lane holds modes mt*16 + 4 lg + r, channel ct*16 + li
 #pragma unroll
-  for (int i = 0; i < 8; ++i) {
-    const int pr = threadIdx.x + 256 * i;
-    if (pr >= npair) break;
-    T[(size_t)row * npair + pr] = acc[i];
-  }
-}
-
-// X[b][k][l][c] = scale * sum_i Sy[k][i] T[b][i][l][c]  (thread per (b, l, c))
-// X[b][k][q] = scale sum_i Sy[k][i] T[b][i][q], q < LQ (the column transform
-// of the sine pair).  A workgroup takes 64 consecutive q of one (b, k); its 4
-// wavefronts sum a quarter of the rows each (one mode per wavefront, so the
-// basis value is a broadcast and the T row is a coalesced read), and the
-// quarters are added in a fixed order.
-template <class V>
-__global__ __launch_bounds__(256) void k_cols(const V* T, const V* Sy, V* X, int B, int H, int M,
-                                              int LQ, V scale) {
-  __shared__ V red[4][64];
-  const int nq = (LQ + 63) / 64;
-  const int qb = blockIdx.x % nq, bk = blockIdx.x / nq;
-  const int k = bk % M, b = bk / M;
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int q = qb * 64 + lane;
-  const int i0 = H * w / 4, i1 = H * (w + 1) / 4;
-  V acc = 0;
-  if (q < LQ) {
-    const V* tp = T + (size_t)b * H * LQ + q;
-    const V* sy = Sy + (size_t)k * H;
-#pragma unroll 8
-    for (int i = i0; i < i1; ++i) acc += sy[i] * tp[(size_t)i * LQ];
-  }
-  red[w][lane] = acc;
+  for (int mt = 0; mt < MTM; ++mt)
+#pragma unroll
+    for (int ct = 0; ct < 2; ++ct)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) red[wv][(mt * 2 + ct) * 4 + r][lane] = acc[mt][ct][r];
   __syncthreads();
-  if (w == 0 && q < LQ)
-    X[((size_t)b * M + k) * LQ + q] = scale * (((red[0][lane] + red[1][lane]) + red[2][lane]) + red[3][lane]);
+  for (int e = threadIdx.x; e < MT * 2 * 4 * 64; e += 256) {
+    const int ln = e & 63, slot = e >> 6;
+    const int mt = slot >> 3, ct = (slot >> 2) & 1, r = slot & 3;
+    const int mode = mt * 16 + 4 * (ln >> 4) + r, c = ct * 16 + (ln & 15);
+    const float v = ((red[0][slot][ln] + red[1][slot][ln]) + red[2][slot][ln]) + red[3][slot][ln];
+    if (mode < M) T[(row * M + mode) * C + c] = v;
+  }
 }
 
-// per-mode channel mixing: Y[b][k][l][n] = sum_m w[k][l][n][m] X[b][k][l][m]
-// (forward, n = out, m = in) or the transpose w[k][l][m][n] (input gradient).
-template <bool TRANS>
-__global__ void k_spec_mix(const float* X, const bf16* wk, float* Y, int B, int M, int C) {
-  const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= (long long)B * M * M * C) return;
-  const int n = (int)(e % C);
-  const long long bkl = e / C;
-  const int kl = (int)(bkl % (M * M));
-  const float* xp = X + bkl * C;
-  const bf16* wp = wk + (size_t)kl * C * C;
-  float s = 0.f;
-  for (int m = 0; m < C; ++m) s += bf2f(TRANS ? wp[m * C + n] : wp[n * C + m]) * xp[m];
-  Y[e] = s;
+// The spectral layer between the row transforms, one workgroup per (b, l),
+// l the mode along x:
+//   X[k][c] = scale sum_i Sy[k][i] T[b][i][l][c]          column transform
+//   Y[k][n] = sum_m w[k][l][n][m] X[k][m]                   mode mixing
+//             (BWD: the transpose, sum_m w[k][l][m][n] X[k][m])
+//   Z[b][i][l][n] = alpha sum_k Sy[k][i] Y[k][n]            inverse column transform
+// X is stored ([b][k][l][c]) for the weight gradient.  A thread takes one
+// channel and every eighth row (FP32 sums, the eight row groups added in a
+// fixed order); Sy comes through LDS in chunks of 64 rows.
+template <int C, bool BWD>
+__global__ __launch_bounds__(256) void k_spec_mid(const float* T, const float* Sy, const bf16* wk,
+                                                  float* Xs, float* Z, int H, int M, float scale,
+                                                  float alpha) {
+  static_assert(C == 32, "a channel per lane of a half-wavefront");
+  constexpr int MM = 32, IC = 64, PS = MM * IC / 256, PT = IC * C / 256;
+  __shared__ float part[8][MM][C];
+  __shared__ float syl[MM][IC];
+  __shared__ float tl[IC][C];
+  __shared__ float Yl[MM][C];
+  const int b = blockIdx.x / M, l = blockIdx.x % M;
+  const int c = threadIdx.x & 31, ig = threadIdx.x >> 5;
+  const size_t tstride = (size_t)M * C;
+  const size_t base = ((size_t)b * H * M + l) * C;     // element (b, i = 0, l, c = 0)
+  // A chunk's basis values Sy[k][i0 + ii] and (X phase) rows of T, read into
+  // registers at clamped indices (all loads of a thread in flight together);
+  // the LDS copies are zero past H and past M, so that the sums below run
+  // over all 32 mode slots without a branch.
+  float sv[PS], tv[PT];
+  auto load_chunk = [&](int i0, bool with_t) {
+#pragma unroll
+    for (int u = 0; u < PS; ++u) {
+      const int e = threadIdx.x + 256 * u, k = e / IC, ii = e % IC;
+      sv[u] = Sy[(size_t)min(k, M - 1) * H + min(i0 + ii, H - 1)];
+    }
+    if (with_t) {
+#pragma unroll
+      for (int u = 0; u < PT; ++u) {
+        const int e = threadIdx.x + 256 * u, ii = e / C, cc = e % C;
+        tv[u] = T[base + (size_t)min(i0 + ii, H - 1) * tstride + cc];
+      }
+    }
+  };
+  auto store_chunk = [&](int i0, bool with_t) {
+#pragma unroll
+    for (int u = 0; u < PS; ++u) {
+      const int e = threadIdx.x + 256 * u, k = e / IC, ii = e % IC;
+      syl[k][ii] = (k < M && i0 + ii < H) ? sv[u] : 0.f;
+    }
+    if (with_t) {
+#pragma unroll
+      for (int u = 0; u < PT; ++u) {
+        const int e = threadIdx.x + 256 * u, ii = e / C, cc = e % C;
+        tl[ii][cc] = i0 + ii < H ? tv[u] : 0.f;
+      }
+    }
+  };
+  // ---- column transform: partial sums over the rows ii = ig (mod 8)
+  float acc[MM];
+#pragma unroll
+  for (int k = 0; k < MM; ++k) acc[k] = 0.f;
+  load_chunk(0, true);
+  for (int i0 = 0; i0 < H; i0 += IC) {
+    __syncthreads();                                     // the previous chunk's readers are done
+    store_chunk(i0, true);
+    __syncthreads();
+    if (i0 + IC < H) load_chunk(i0 + IC, true);          // in flight during the sums
+#pragma unroll 2
+    for (int ii = ig; ii < IC; ii += 8) {
+      const float t = tl[ii][c];
+#pragma unroll
+      for (int k = 0; k < MM; ++k) acc[k] = fmaf(syl[k][ii], t, acc[k]);
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < MM; ++k) part[ig][k][c] = acc[k];
+  // the mixing weights of this thread's modes k = ig, ig + 8, ... as 32-bit
+  // words (forward: w[k][l][c][0..31], contiguous; BWD: w[k][l][m][c], the word
+  // holding element c of row m)
+  constexpr int KPT = MM / 8;
+  uint32_t wv[KPT][C / 2 > 16 ? 16 : C / 2];
+  uint32_t wb[KPT][C];
+#pragma unroll
+  for (int q = 0; q < KPT; ++q) {
+    const int k = min(ig + 8 * q, M - 1);
+    const bf16* wp = wk + ((size_t)k * M + l) * C * C;
+    if constexpr (!BWD) {
+#pragma unroll
+      for (int h = 0; h < 4; ++h) {
+        const uint4 u4 = reinterpret_cast<const uint4*>(wp + c * C)[h];
+        wv[q][4 * h] = u4.x;
+        wv[q][4 * h + 1] = u4.y;
+        wv[q][4 * h + 2] = u4.z;
+        wv[q][4 * h + 3] = u4.w;
+      }
+    } else {
+#pragma unroll
+      for (int m = 0; m < C; ++m) wb[q][m] = *reinterpret_cast<const uint32_t*>(wp + m * C + (c & ~1));
+    }
+  }
+  __syncthreads();
+  // X = scale * (fixed-order sum of the row groups)
+  for (int e = threadIdx.x; e < M * C; e += 256) {
+    const int k = e / C, cc = e % C;
+    float s = part[0][k][cc];
+#pragma unroll
+    for (int g = 1; g < 8; ++g) s += part[g][k][cc];
+    s *= scale;
+    part[0][k][cc] = s;
+    Xs[(((size_t)b * M + k) * M + l) * C + cc] = s;
+  }
+  load_chunk(0, false);                                  // the inverse transform's first chunk
+  __syncthreads();
+  // ---- mixing: thread (n = c, modes k = ig + 8 q)
+#pragma unroll
+  for (int q = 0; q < KPT; ++q) {
+    const int k = ig + 8 * q;
+    if (k >= M) break;                                   // uniform within the half-wavefront
+    float y = 0.f;
+#pragma unroll
+    for (int m = 0; m < C; ++m) {
+      float wf;
+      if constexpr (!BWD) {
+        const uint32_t wd = wv[q][m >> 1];
+        wf = __uint_as_float((m & 1) ? (wd & 0xffff0000u) : (wd << 16));
+      } else {
+        const uint32_t wd = wb[q][m];
+        wf = __uint_as_float((c & 1) ? (wd & 0xffff0000u) : (wd << 16));
+      }
+      y = fmaf(wf, part[0][k][m], y);
+    }
+    Yl[k][c] = y;
+  }
+  __syncthreads();
+  float yv[MM];
+#pragma unroll
+  for (int k = 0; k < MM; ++k) yv[k] = k < M ? Yl[k][c] : 0.f;
+  // ---- inverse column transform
+  for (int i0 = 0; i0 < H; i0 += IC) {
+    __syncthreads();
+    store_chunk(i0, false);
+    __syncthreads();
+    if (i0 + IC < H) load_chunk(i0 + IC, false);
+    for (int ii = ig; ii < IC && i0 + ii < H; ii += 8) {
+      float z = 0.f;
+#pragma unroll
+      for (int k = 0; k < MM; ++k) z = fmaf(syl[k][ii], yv[k], z);
+      Z[base + (size_t)(i0 + ii) * tstride + c] = alpha * z;
+    }
+  }
 }
 
 // dWk[k][l][d][c] = sum_b dY[b][k][l][d] X[b][k][l][c]
@@ -944,181 +1299,440 @@ __global__ void k_spec_dwk(const float* dY, const float* X, float* gwk, int B, i
   gwk[e] = s;
 }
 
-// Z[b][i][l][n] = alpha * sum_k Sy[k][i] Y[b][k][l][n]
-__global__ void k_spec_inv_cols(const float* Y, const float* Sy, float* Z, int B, int H, int M,
-                                int C, float alpha) {
-  const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  const long long LC = (long long)M * C;
-  if (e >= (long long)B * H * LC) return;
-  const long long lc = e % LC;
-  const long long bi = e / LC;
-  const int i = (int)(bi % H), b = (int)(bi / H);
-  float s = 0.f;
-  for (int k = 0; k < M; ++k) s += Sy[(size_t)k * H + i] * Y[((size_t)b * M + k) * LC + lc];
-  Z[e] = alpha * s;
-}
-
-// out[b][i][j][n] = epi( sum_m W1'[n][m] in[b][i][j][m] (+ bias[n])
-//                        + beta * sum_l Sx[l][j] Z[b][i][l][n] )
-// forward: W1' = W1, bias, ReLU -> a3.  BWD: W1' = W1^T, no bias, mask (a2 > 0).
-template <int C, bool BWD>
+// out[r][j][n] = epi( sum_m W1'[n][m] in[r][j][m] (+ bias[n]) + beta sum_l Sx[l][j] Z[r][l][n] )
+// (r = b H + i): the spectral layer's output, 16 pixels x 32 channels per
+// wavefront step, both terms into the same FP32 accumulators: the 1x1
+// convolution on v_mfma_f32_16x16x32_bf16 (A = W1', 16 channels x 32 input
+// channels; B = the input, 32 channels x 16 pixels, one 16-byte read per
+// lane), the inverse row transform on v_mfma_f32_16x16x4_f32 (A = beta Z of
+// the row, 16 channels x 4 modes; B = Sx, 4 modes x 16 pixels), in FP32.
+// Forward: W1' = W1, bias, ReLU.  BWD: W1' = W1^T, no bias, times (mask > 0).
+// A workgroup takes 64 pixels of one row.
+template <int C, bool BWD, int MS>
 __global__ __launch_bounds__(256) void k_spec_out(const bf16* in, const bf16* w1, const bf16* bias,
                                                   const float* Z, const float* Sx, const bf16* mask,
-                                                  bf16* out, int H, int W, int M, float beta) {
-  __shared__ float wl[C * C];
-  __shared__ float zl[32 * C];
-  __shared__ float sl[32 * 64];
-  __shared__ float bl[C];
+                                                  bf16* out, int W, int WP, int M, float beta) {
+  static_assert(C == 32, "two 16-channel tiles");
+  static_assert(MS >= 1 && MS <= 8, "modes <= 32 in steps of 4");
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int li = lane & 15, lg = lane >> 4;
   const int tilesx = (W + 63) / 64;
-  const int row = blockIdx.x / tilesx;            // b*H + i
-  const int j0 = (blockIdx.x % tilesx) * 64;
-  for (int e = threadIdx.x; e < C * C; e += 256) {
-    const int n = e / C, m = e % C;
-    wl[e] = bf2f(BWD ? w1[m * C + n] : w1[n * C + m]);
+  const size_t row = blockIdx.x / tilesx;
+  const int j0 = (blockIdx.x % tilesx) * 64 + wv * 16;
+  // A: W1'[n][m], n = nt*16 + li, m = 8 lg .. 8 lg + 7
+  bf16x8 wa[2];
+#pragma unroll
+  for (int nt = 0; nt < 2; ++nt) {
+    const int n = nt * 16 + li;
+    if constexpr (!BWD) {
+      wa[nt] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(w1 + n * C + 8 * lg));
+    } else {
+      // element n of rows 8 lg .. 8 lg + 7, read as the 32-bit words that hold it
+      uint32_t wd[8];
+#pragma unroll
+      for (int e = 0; e < 8; ++e) wd[e] = *reinterpret_cast<const uint32_t*>(w1 + (8 * lg + e) * C + (n & ~1));
+      uint32_t pk[4];
+#pragma unroll
+      for (int h = 0; h < 4; ++h) {
+        const uint32_t lo = (n & 1) ? (wd[2 * h] >> 16) : (wd[2 * h] & 0xffffu);
+        const uint32_t hi = (n & 1) ? (wd[2 * h + 1] >> 16) : (wd[2 * h + 1] & 0xffffu);
+        pk[h] = lo | (hi << 16);
+      }
+      wa[nt] = __builtin_bit_cast(bf16x8, make_uint4(pk[0], pk[1], pk[2], pk[3]));
+    }
   }
-  for (int e = threadIdx.x; e < M * C; e += 256) zl[e] = Z[(size_t)row * M * C + e];
-  for (int e = threadIdx.x; e < M * 64; e += 256) {
-    const int l = e / 64, jj = e % 64;
-    sl[e] = (j0 + jj < W) ? Sx[(size_t)l * W + j0 + jj] : 0.f;
+  // A2: beta Z[row][mode][n], mode = 4 s + lg (zero past M; loads at clamped
+  // modes, all in flight together)
+  float za[MS][2];
+#pragma unroll
+  for (int s = 0; s < MS; ++s)
+#pragma unroll
+    for (int nt = 0; nt < 2; ++nt) {
+      const int mode = 4 * s + lg;
+      const float zv = Z[(row * M + min(mode, M - 1)) * C + nt * 16 + li];
+      za[s][nt] = mode < M ? beta * zv : 0.f;
+    }
+  if (j0 >= W) return;                           // wavefront-uniform
+  // B: input channels 8 lg .. 8 lg + 7 of pixel j0 + li (zero past the row)
+  const int j = j0 + li;
+  const size_t px = (row * W + (j < W ? j : W - 1)) * C;
+  const bf16x8 bx = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(in + px + 8 * lg));
+  floatx4 acc[2];
+#pragma unroll
+  for (int nt = 0; nt < 2; ++nt) {
+    acc[nt] = floatx4{0.f, 0.f, 0.f, 0.f};
+    acc[nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa[nt], bx, acc[nt], 0, 0, 0);
   }
-  for (int e = threadIdx.x; e < C; e += 256) bl[e] = (!BWD) ? bf2f(bias[e]) : 0.f;
-  __syncthreads();
-  constexpr int NG = 4, PER = C / NG;             // 4 threads per pixel, C/4 channels each
-  const int jj = threadIdx.x / NG, g = threadIdx.x % NG;
-  const int j = j0 + jj;
+#pragma unroll
+  for (int s = 0; s < MS; ++s) {
+    const float sb = Sx[(size_t)(4 * s + lg) * WP + j];   // in bounds: WP >= W rounded to 64
+#pragma unroll
+    for (int nt = 0; nt < 2; ++nt) acc[nt] = __builtin_amdgcn_mfma_f32_16x16x4f32(za[s][nt], sb, acc[nt], 0, 0, 0);
+  }
   if (j >= W) return;
-  const size_t base = ((size_t)row * W + j) * C;
-  float xin[C];
+  // D[n][p]: lane holds channels nt*16 + 4 lg + r of pixel j0 + li
 #pragma unroll
-  for (int m = 0; m < C; ++m) xin[m] = bf2f(in[base + m]);
+  for (int nt = 0; nt < 2; ++nt) {
+    const size_t o = px + nt * 16 + 4 * lg;
+    float m4[4] = {0.f, 0.f, 0.f, 0.f};
+    if constexpr (BWD) {
+      const uint2 mu = *reinterpret_cast<const uint2*>(mask + o);
+      m4[0] = __uint_as_float(mu.x << 16);
+      m4[1] = __uint_as_float(mu.x & 0xffff0000u);
+      m4[2] = __uint_as_float(mu.y << 16);
+      m4[3] = __uint_as_float(mu.y & 0xffff0000u);
+    }
+    float v[4];
 #pragma unroll
-  for (int q = 0; q < PER; ++q) {
-    const int n = g * PER + q;
-    float s = bl[n];
-#pragma unroll
-    for (int m = 0; m < C; ++m) s += wl[n * C + m] * xin[m];
-    float sp = 0.f;
-    for (int l = 0; l < M; ++l) sp += sl[l * 64 + jj] * zl[l * C + n];
-    s += beta * sp;
-    if (!BWD) s = fmaxf(s, 0.f);
-    else s = bf2f(mask[base + n]) > 0.f ? s : 0.f;
-    out[base + n] = f2bf(s);
+    for (int r = 0; r < 4; ++r) {
+      float a = acc[nt][r];
+      if constexpr (!BWD) a = fmaxf(a + bf2f(bias[nt * 16 + 4 * lg + r]), 0.f);
+      else a = m4[r] > 0.f ? a : 0.f;
+      v[r] = a;
+    }
+    uint2 w2;
+    w2.x = (uint32_t)f2bf(v[0]) | ((uint32_t)f2bf(v[1]) << 16);
+    w2.y = (uint32_t)f2bf(v[2]) | ((uint32_t)f2bf(v[3]) << 16);
+    *reinterpret_cast<uint2*>(out + o) = w2;
   }
 }
 
-// ------------------------------------------------------------------ spectral skip
+// k_spec_out for M modes (4-mode steps as a template argument, so that the
+// step loop has no early exit and its loads are issued together).
+template <int C, bool BWD>
+void launch_spec_out(dim3 grid, hipStream_t s, const bf16* in, const bf16* w1, const bf16* bias,
+                     const float* Z, const float* Sx, const bf16* mask, bf16* out, int W, int WP,
+                     int M, float beta) {
+  switch ((M + 3) / 4) {
+#define MLG_SPEC_OUT(MS)                                                                        \
+  case MS:                                                                                      \
+    k_spec_out<C, BWD, MS><<<grid, 256, 0, s>>>(in, w1, bias, Z, Sx, mask, out, W, WP, M, beta); \
+    break;
+    MLG_SPEC_OUT(1) MLG_SPEC_OUT(2) MLG_SPEC_OUT(3) MLG_SPEC_OUT(4)
+    MLG_SPEC_OUT(5) MLG_SPEC_OUT(6) MLG_SPEC_OUT(7) MLG_SPEC_OUT(8)
+#undef MLG_SPEC_OUT
+    default: throw ArgError{MLG_ERR_ARG, "modes must be in 1..32"};
+  }
+}
+
+// ------------------------------------------------------------------ band path (FP64)
 // FP64 throughout: the residual of a slowly moving source is dipole-like, so
 // its projection on the slowest modes cancels heavily, and FP32 sums (or an
 // FP32-rounded basis) leave errors in the mode coefficients comparable to the
 // coefficients themselves; trained on such inputs the gains settle below the
-// exact inverse.
+// exact inverse.  Each kernel below takes several rows (or modes) per
+// workgroup so that every basis value it loads serves all of them, and up to
+// two independent fields per launch (blockIdx.y).
+constexpr int kBandRows = 8;
 
-// S[k][j] = sin((k+1) pi (j+1) / (n+1)) in FP64, and (when ST is given) the
-// same values transposed, ST[j][k]
-__global__ void k_skip_basis(double* S, double* ST, int M, int n) {
-  const int e = blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= M * n) return;
-  const int k = e / n, j = e % n;
-  const double v = sin((double)(k + 1) * M_PI * (double)(j + 1) / (double)(n + 1));
-  S[e] = v;
-  if (ST) ST[(size_t)j * M + k] = v;
+// One field's operand of a band launch: the data, its per-image divisor (or
+// NULL), the result, a scale.
+template <class X>
+struct BandIn {
+  const X* x;
+  const double* div;
+  double* out;
+  double scale;
+};
+
+// T[b][i][l] = sum_j SxT[j][l] x[b][i][j] / div[b]: a workgroup takes 8 rows
+// of one image; lanes are the modes l (64 per pass, two passes at most), the
+// four wavefronts a quarter of every chunk of 256 columns.  The rows are
+// staged in LDS (FP64, zero past the grid), so the inner loop reads basis
+// values (16 independent coalesced loads issued together, at clamped
+// indices) and broadcast LDS values, eight running sums per lane and pass;
+// the quarters are added in a fixed order.
+constexpr int kBandChunk = 256;
+
+template <class X0, class X1>
+__global__ __launch_bounds__(256) void k_band_rows(BandIn<X0> f0, BandIn<X1> f1, const double* SxT,
+                                                   int H, int W, int K) {
+  constexpr int JC = kBandChunk, JQ = JC / 4, NB = 16, PER = kBandRows * JC / 256;
+  __shared__ double xs[kBandRows][JC];
+  __shared__ double part[4][kBandRows][64];
+  const int nrb = (H + kBandRows - 1) / kBandRows;
+  const int b = blockIdx.x / nrb, i0 = (blockIdx.x % nrb) * kBandRows;
+  const int lane = threadIdx.x & 63, w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int rlast = min(kBandRows, H - i0) - 1;
+  const int np = (K + 63) / 64;
+  auto run = [&](const auto& f) {
+    const auto* xb = f.x + ((size_t)b * H + i0) * W;
+    double s[2][kBandRows];
+#pragma unroll
+    for (int p = 0; p < 2; ++p)
+#pragma unroll
+      for (int r = 0; r < kBandRows; ++r) s[p][r] = 0.0;
+    for (int j0 = 0; j0 < W; j0 += JC) {
+      double xv[PER];
+#pragma unroll
+      for (int u = 0; u < PER; ++u) {
+        const int e = threadIdx.x + 256 * u, r = e / JC, jj = e % JC;
+        xv[u] = (double)xb[(size_t)min(r, rlast) * W + min(j0 + jj, W - 1)];
+      }
+      __syncthreads();                                   // the previous chunk's readers are done
+#pragma unroll
+      for (int u = 0; u < PER; ++u) {
+        const int e = threadIdx.x + 256 * u, r = e / JC, jj = e % JC;
+        xs[r][jj] = (r <= rlast && j0 + jj < W) ? xv[u] : 0.0;
+      }
+      __syncthreads();
+      const int ja = j0 + w * JQ;
+#pragma unroll
+      for (int p = 0; p < 2; ++p) {
+        if (p >= np) break;                              // uniform
+        const int lc = min(p * 64 + lane, K - 1);
+#pragma unroll 1
+        for (int jb = 0; jb < JQ; jb += NB) {
+          double bv[NB];
+#pragma unroll
+          for (int u = 0; u < NB; ++u) bv[u] = SxT[(size_t)min(ja + jb + u, W - 1) * K + lc];
+#pragma unroll
+          for (int u = 0; u < NB; ++u)
+#pragma unroll
+            for (int r = 0; r < kBandRows; ++r) s[p][r] = fma(bv[u], xs[r][w * JQ + jb + u], s[p][r]);
+        }
+      }
+    }
+#pragma unroll
+    for (int p = 0; p < 2; ++p) {
+      if (p >= np) break;
+      __syncthreads();
+#pragma unroll
+      for (int r = 0; r < kBandRows; ++r) part[w][r][lane] = s[p][r];
+      __syncthreads();
+      for (int e = threadIdx.x; e < kBandRows * 64; e += 256) {
+        const int r = e / 64, ln = e % 64, ll = p * 64 + ln;
+        if (r > rlast || ll >= K) continue;
+        double v = (part[0][r][ln] + part[1][r][ln]) + (part[2][r][ln] + part[3][r][ln]);
+        if (f.div) v /= f.div[b];
+        f.out[((size_t)b * H + i0 + r) * K + ll] = f.scale * v;
+      }
+    }
+  };
+  if (blockIdx.y == 0) run(f0);
+  else run(f1);
 }
 
-// T[b][i][l] = sum_j Sx[l][j] x[b][i][j] / div[b]: one workgroup per row
-// (b, i); its four wavefronts take a quarter of the row each, lanes the modes
-// l (SxT = the basis transposed, [j][l], so lanes read consecutive basis
-// values while x is a broadcast), four independent sums per lane; the
-// quarters are added in a fixed order through LDS.
-template <class X>
-__global__ __launch_bounds__(256) void k_skip_rows(const X* x, const double* div, const double* SxT,
-                                                   double* T, int B, int H, int W, int M) {
-  __shared__ double part[4][64];
-  const long long bi = blockIdx.x;
-  const int b = (int)(bi / H);
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const X* xr = x + bi * W;
-  const int j0 = W * w / 4, j1 = W * (w + 1) / 4;
-  for (int l0 = 0; l0 < M; l0 += 64) {
-    const int l = l0 + lane;
-    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
-    if (l < M) {
-      int j = j0;
-      for (; j + 4 <= j1; j += 4) {
-        s0 += SxT[(size_t)j * M + l] * (double)xr[j];
-        s1 += SxT[(size_t)(j + 1) * M + l] * (double)xr[j + 1];
-        s2 += SxT[(size_t)(j + 2) * M + l] * (double)xr[j + 2];
-        s3 += SxT[(size_t)(j + 3) * M + l] * (double)xr[j + 3];
+// X[b][k][q] = scale sum_i Sy[k][i] T[b][i][q] (q < K): a workgroup takes 8
+// modes k of one image; lanes are q (64 per pass, two passes at most), the
+// four wavefronts a quarter of every chunk of 256 rows; the chunk's basis
+// rows are staged in LDS (zero past the grid), T is read 16 rows at a time
+// with independent coalesced loads.
+__global__ __launch_bounds__(256) void k_band_cols(BandIn<double> f0, BandIn<double> f1,
+                                                   const double* Sy, int H, int K) {
+  constexpr int IC = kBandChunk, IQ = IC / 4, NB = 16, PER = kBandRows * IC / 256;
+  __shared__ double syl[kBandRows][IC];
+  __shared__ double part[4][kBandRows][64];
+  const int nkb = (K + kBandRows - 1) / kBandRows;
+  const int b = blockIdx.x / nkb, k0 = (blockIdx.x % nkb) * kBandRows;
+  const int lane = threadIdx.x & 63, w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const BandIn<double>& f = blockIdx.y == 0 ? f0 : f1;
+  const double* tb = f.x + (size_t)b * H * K;
+  const int klast = min(kBandRows, K - k0) - 1;
+  const int np = (K + 63) / 64;
+  double s[2][kBandRows];
+#pragma unroll
+  for (int p = 0; p < 2; ++p)
+#pragma unroll
+    for (int r = 0; r < kBandRows; ++r) s[p][r] = 0.0;
+  for (int i0 = 0; i0 < H; i0 += IC) {
+    double sv[PER];
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+      const int e = threadIdx.x + 256 * u, r = e / IC, ii = e % IC;
+      sv[u] = Sy[(size_t)(k0 + min(r, klast)) * H + min(i0 + ii, H - 1)];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+      const int e = threadIdx.x + 256 * u, r = e / IC, ii = e % IC;
+      syl[r][ii] = (r <= klast && i0 + ii < H) ? sv[u] : 0.0;
+    }
+    __syncthreads();
+    const int ia = i0 + w * IQ;
+#pragma unroll
+    for (int p = 0; p < 2; ++p) {
+      if (p >= np) break;
+      const int qc = min(p * 64 + lane, K - 1);
+#pragma unroll 1
+      for (int ib = 0; ib < IQ; ib += NB) {
+        double tv[NB];
+#pragma unroll
+        for (int u = 0; u < NB; ++u) tv[u] = tb[(size_t)min(ia + ib + u, H - 1) * K + qc];
+#pragma unroll
+        for (int u = 0; u < NB; ++u)
+#pragma unroll
+          for (int r = 0; r < kBandRows; ++r) s[p][r] = fma(syl[r][w * IQ + ib + u], tv[u], s[p][r]);
       }
-      for (; j < j1; ++j) s0 += SxT[(size_t)j * M + l] * (double)xr[j];
     }
-    part[w][lane] = (s0 + s1) + (s2 + s3);
+  }
+#pragma unroll
+  for (int p = 0; p < 2; ++p) {
+    if (p >= np) break;
     __syncthreads();
-    if (w == 0 && l < M) {
-      const double t = (part[0][lane] + part[1][lane]) + (part[2][lane] + part[3][lane]);
-      T[bi * M + l] = div ? t / div[b] : t;
+#pragma unroll
+    for (int r = 0; r < kBandRows; ++r) part[w][r][lane] = s[p][r];
+    __syncthreads();
+    for (int e = threadIdx.x; e < kBandRows * 64; e += 256) {
+      const int r = e / 64, ln = e % 64, qq = p * 64 + ln;
+      if (r > klast || qq >= K) continue;
+      const double v = (part[0][r][ln] + part[1][r][ln]) + (part[2][r][ln] + part[3][r][ln]);
+      f.out[((size_t)b * K + k0 + r) * K + qq] = f.scale * v;
     }
-    __syncthreads();
   }
 }
 
-// Y[b][k][l] = w_kl X[b][k][l] - Cc[b][k][l], w = sxt / sxx (0 where sxx = 0):
-// the band path's coefficients in place of those of the convolutional output
 // The convolutional branch's output gain: sct / scc, 1 before any data (or
 // without a gain: gate == NULL).
 __device__ __forceinline__ double gate_of(const double* gate) {
   return gate && gate[1] > 0.0 ? gate[0] / gate[1] : 1.0;
 }
 
-__global__ void k_band_apply(const double* X, const double* Cc, const double* band, double* Y,
-                             int B, int K, const double* gate) {
-  const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= (long long)B * K * K) return;
-  const int kl = (int)(e % (K * K));
-  const double sxx = band[K * K + kl];
-  const double w = sxx > 0.0 ? band[kl] / sxx : 0.0;
-  Y[e] = w * X[e] - gate_of(gate) * Cc[e];
+// Z[b][i][l] = alpha sum_k Sy[k][i] Y[b][k][l], with the band applied on the
+// way in when `band` is given: Y = w_kl X - g Cc (w = sxt / sxx, 0 where sxx =
+// 0; g the output gain), else Y = X.  A workgroup takes 32 rows of one image
+// (8 per wavefront), lanes l; Y and the basis values of the 32 rows come
+// through LDS, 16 modes k at a time.
+__global__ __launch_bounds__(256) void k_band_inv(const double* X, const double* Cc,
+                                                  const double* band, const double* gate,
+                                                  const double* Sy, double* Z, int H, int K,
+                                                  double alpha) {
+  constexpr int KC = 16, KMAX = 128, RPW = 8, RB = 4 * RPW;
+  constexpr int PY = KC * KMAX / 256, PS = KC * RB / 256;
+  __shared__ double yl[KC][KMAX];
+  __shared__ double syl[KC][RB];
+  const int nrb = (H + RB - 1) / RB;
+  const int b = blockIdx.x / nrb, i0 = (blockIdx.x % nrb) * RB;
+  const int lane = threadIdx.x & 63, w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const double g = gate_of(gate);
+  const double* Xb = X + (size_t)b * K * K;
+  const double* Cb = Cc ? Cc + (size_t)b * K * K : nullptr;
+  const int np = (K + 63) / 64;
+  double s[2][RPW];
+#pragma unroll
+  for (int p = 0; p < 2; ++p)
+#pragma unroll
+    for (int r = 0; r < RPW; ++r) s[p][r] = 0.0;
+  for (int k0 = 0; k0 < K; k0 += KC) {
+    // Y[k0 + kk][ll] (kk < KC, ll < KMAX; zero past K), loads first
+    double xv[PY], cv[PY], tv[PY], qv[PY];
+#pragma unroll
+    for (int u = 0; u < PY; ++u) {
+      const int e = threadIdx.x + 256 * u, kk = e / KMAX, ll = e % KMAX;
+      const int kl = min(k0 + kk, K - 1) * K + min(ll, K - 1);
+      xv[u] = Xb[kl];
+      if (band) {
+        cv[u] = Cb[kl];
+        tv[u] = band[kl];
+        qv[u] = band[K * K + kl];
+      }
+    }
+    double sv[PS];
+#pragma unroll
+    for (int u = 0; u < PS; ++u) {
+      const int e = threadIdx.x + 256 * u, kk = e / RB, ii = e % RB;
+      sv[u] = Sy[(size_t)min(k0 + kk, K - 1) * H + min(i0 + ii, H - 1)];
+    }
+    __syncthreads();                                      // the previous chunk's readers are done
+#pragma unroll
+    for (int u = 0; u < PY; ++u) {
+      const int e = threadIdx.x + 256 * u, kk = e / KMAX, ll = e % KMAX;
+      double y = xv[u];
+      if (band) {
+        const double wk = qv[u] > 0.0 ? tv[u] / qv[u] : 0.0;
+        y = wk * xv[u] - g * cv[u];
+      }
+      yl[kk][ll] = (k0 + kk < K && ll < K) ? y : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < PS; ++u) {
+      const int e = threadIdx.x + 256 * u, kk = e / RB, ii = e % RB;
+      syl[kk][ii] = (k0 + kk < K && i0 + ii < H) ? sv[u] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int p = 0; p < 2; ++p) {
+      if (p >= np) break;
+      const int lc = min(p * 64 + lane, K - 1);
+#pragma unroll 4
+      for (int kk = 0; kk < KC; ++kk) {
+        const double yv = yl[kk][lc];
+#pragma unroll
+        for (int r = 0; r < RPW; ++r) s[p][r] = fma(syl[kk][w * RPW + r], yv, s[p][r]);
+      }
+    }
+  }
+#pragma unroll
+  for (int p = 0; p < 2; ++p) {
+    const int l = p * 64 + lane;
+    if (p >= np || l >= K) continue;
+#pragma unroll
+    for (int r = 0; r < RPW; ++r) {
+      const int i = i0 + w * RPW + r;
+      if (i < H) Z[((size_t)b * H + i) * K + l] = alpha * s[p][r];
+    }
+  }
 }
 
-// Z[b][i][l] = alpha sum_k Sy[k][i] Y[b][k][l]
-__global__ void k_skip_inv_cols(const double* Y, const double* Sy, double* Z, int B, int H, int M,
-                                double alpha) {
-  const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= (long long)B * H * M) return;
-  const int l = (int)(e % M);
-  const long long bi = e / M;
-  const int i = (int)(bi % H), b = (int)(bi / H);
-  const double* Yb = Y + (size_t)b * M * M + l;
-  double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
-  int k = 0;
-  for (; k + 4 <= M; k += 4) {
-    s0 += Sy[(size_t)k * H + i] * Yb[(size_t)k * M];
-    s1 += Sy[(size_t)(k + 1) * H + i] * Yb[(size_t)(k + 1) * M];
-    s2 += Sy[(size_t)(k + 2) * H + i] * Yb[(size_t)(k + 2) * M];
-    s3 += Sy[(size_t)(k + 3) * H + i] * Yb[(size_t)(k + 3) * M];
-  }
-  for (; k < M; ++k) s0 += Sy[(size_t)k * H + i] * Yb[(size_t)k * M];
-  Z[e] = alpha * ((s0 + s1) + (s2 + s3));
-}
+// out[b][i][j] = g out[b][i][j] + beta sum_l Sx[l][j] Z[b][i][l] (sum and add in
+// FP64; g the output gain, 1 without one): a workgroup takes 8 rows x 256
+// columns of one image, a thread one column and its eight rows (eight running
+// sums, so every basis value serves eight rows); the rows' Z values come
+// through LDS.  Up to two fields (blockIdx.y).
+struct BandOut {
+  const double* Z;
+  float* out;
+  const double* gate;
+  double beta;
+};
 
-// out[b][i][j] = g out[b][i][j] + beta sum_l Sx[l][j] Z[b][i][l]  (sum and add
-// in FP64; g the output gain, 1 without one)
-__global__ void k_skip_out(const double* Z, const double* Sx, float* out, int B, int H, int W,
-                           int M, double beta, const double* gate) {
-  const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= (long long)B * H * W) return;
-  const int j = (int)(e % W);
-  const long long bi = e / W;
-  const double* zr = Z + bi * M;
-  double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
-  int l = 0;
-  for (; l + 4 <= M; l += 4) {
-    s0 += Sx[(size_t)l * W + j] * zr[l];
-    s1 += Sx[(size_t)(l + 1) * W + j] * zr[l + 1];
-    s2 += Sx[(size_t)(l + 2) * W + j] * zr[l + 2];
-    s3 += Sx[(size_t)(l + 3) * W + j] * zr[l + 3];
+__global__ __launch_bounds__(256) void k_band_out(BandOut f0, BandOut f1, const double* Sx, int H,
+                                                  int W, int K) {
+  constexpr int KMAX = 128, NB = 16, PZ = kBandRows * KMAX / 256;
+  __shared__ double zl[kBandRows][KMAX];
+  const BandOut& f = blockIdx.y == 0 ? f0 : f1;
+  const int ncb = (W + 255) / 256, nrb = (H + kBandRows - 1) / kBandRows;
+  const int cb = blockIdx.x % ncb, rb = (blockIdx.x / ncb) % nrb, b = blockIdx.x / (ncb * nrb);
+  const int j = cb * 256 + threadIdx.x, i0 = rb * kBandRows;
+  const int jc = j < W ? j : W - 1;
+  const int rlast = min(kBandRows, H - i0) - 1;
+  const double* zb = f.Z + ((size_t)b * H + i0) * K;
+  double zv[PZ];
+#pragma unroll
+  for (int u = 0; u < PZ; ++u) {
+    const int e = threadIdx.x + 256 * u, r = e / KMAX, l = e % KMAX;
+    zv[u] = zb[(size_t)min(r, rlast) * K + min(l, K - 1)];
   }
-  for (; l < M; ++l) s0 += Sx[(size_t)l * W + j] * zr[l];
-  out[e] = (float)(gate_of(gate) * (double)out[e] + beta * ((s0 + s1) + (s2 + s3)));
+#pragma unroll
+  for (int u = 0; u < PZ; ++u) {
+    const int e = threadIdx.x + 256 * u, r = e / KMAX, l = e % KMAX;
+    zl[r][l] = (r <= rlast && l < K) ? zv[u] : 0.0;         // zero past K: padded steps add 0
+  }
+  __syncthreads();
+  double s[kBandRows];
+#pragma unroll
+  for (int r = 0; r < kBandRows; ++r) s[r] = 0.0;
+  const double* sx = Sx + jc;
+  const int KP = (K + NB - 1) / NB * NB;
+#pragma unroll 1
+  for (int l0 = 0; l0 < KP; l0 += NB) {
+    double sv[NB];
+#pragma unroll
+    for (int u = 0; u < NB; ++u) sv[u] = sx[(size_t)min(l0 + u, K - 1) * W];
+#pragma unroll
+    for (int u = 0; u < NB; ++u)
+#pragma unroll
+      for (int r = 0; r < kBandRows; ++r) s[r] = fma(zl[r][l0 + u], sv[u], s[r]);
+  }
+  if (j >= W) return;
+  const double g = gate_of(f.gate);
+  float* ob = f.out + ((size_t)b * H + i0) * W + j;
+  float ov[kBandRows];
+#pragma unroll
+  for (int r = 0; r < kBandRows; ++r) ov[r] = ob[(size_t)min(r, rlast) * W];
+#pragma unroll
+  for (int r = 0; r < kBandRows; ++r)
+    if (r <= rlast) ob[(size_t)r * W] = (float)(g * (double)ov[r] + f.beta * s[r]);
 }
 
 // Least-squares state of the band: sxt_kl += sum_b X[b][k][l] T[b][k][l],
@@ -1287,6 +1901,39 @@ struct Net {
   T* w(size_t off) const { return (T*)(ws + off); }
 };
 
+// The band path's workspace views.
+struct BandSpace {
+  double *kT, *kT2, *kX, *kC, *kZ, *kZ2, *kdY, *kdY2, *kTc, *kXa, *kSx, *kSxT, *kSy;
+};
+
+BandSpace band_space(const Net& n) {
+  auto p = [&](size_t off) { return n.w<double>(off); };
+  return BandSpace{p(n.wl.kT),   p(n.wl.kT2), p(n.wl.kX),  p(n.wl.kC),   p(n.wl.kZ),
+                   p(n.wl.kZ2),  p(n.wl.kdY), p(n.wl.kdY2), p(n.wl.kTc), p(n.wl.kXa),
+                   p(n.wl.kSx),  p(n.wl.kSxT), p(n.wl.kSy)};
+}
+
+inline int band_out_blocks(const Dims& d) {
+  return d.B * cdiv(d.H, kBandRows) * cdiv(d.W, 256);
+}
+
+// Mode coefficients of two fields, X_q = scale_q S_y (x_q / div_q) S_x^T
+// (K x K per image): the row transforms of both fields in one launch (into
+// kT, kT2), then the column transforms of both.
+template <class X0, class X1>
+void band_project_rows_cols(const Net& n, BandIn<X0> f0, BandIn<X1> f1, double* X0out,
+                            double* X1out, double scale0, double scale1, hipStream_t s) {
+  const Dims& d = n.d;
+  const BandSpace b = band_space(n);
+  f0.out = b.kT;
+  f1.out = b.kT2;
+  k_band_rows<X0, X1><<<dim3(d.B * cdiv(d.H, kBandRows), 2), 256, 0, s>>>(f0, f1, b.kSxT, d.H, d.W,
+                                                                          d.K);
+  k_band_cols<<<dim3(d.B * cdiv(d.K, kBandRows), 2), 256, 0, s>>>(
+      BandIn<double>{b.kT, nullptr, X0out, scale0}, BandIn<double>{b.kT2, nullptr, X1out, scale1},
+      b.kSy, d.H, d.K);
+}
+
 // gated: apply the convolutional branch's output gain (inference); training
 // runs with gain 1.
 template <int C>
@@ -1300,8 +1947,13 @@ void forward(const Net& n, const Ptrs& f, const Ptrs& u, hipStream_t s, bool gat
   float* Sy = n.w<float>(n.wl.Sy);
   double* sv = n.w<double>(n.wl.s);            // s_r[B], s_in[B], s_f[B]
   double* r0 = n.w<double>(n.wl.r0);
-  k_basis<<<cdiv((long long)d.M * d.W, 256), 256, 0, s>>>(Sx, d.M, d.W);
-  k_basis<<<cdiv((long long)d.M * d.H, 256), 256, 0, s>>>(Sy, d.M, d.H);
+  const int WP = spec_wp(d);
+  {
+    Bases bs{Sx, n.w<bf16>(n.wl.Sxh), n.w<bf16>(n.wl.Sxl), Sy, n.w<double>(n.wl.kSx),
+             n.w<double>(n.wl.kSxT), n.w<double>(n.wl.kSy), d.M, spec_mp(d), d.W, WP, d.H, d.K};
+    const long long nb = (long long)bs.MP * WP + (long long)d.M * d.H + (long long)d.K * (d.W + d.H);
+    k_bases<<<cdiv(nb, 256), 256, 0, s>>>(bs);
+  }
   k_resid_in<<<dim3(cdiv(HW, 256), d.B), 256, 0, s>>>(f, u, r0, d.H, d.W);
   Ptrs rp{};
   for (int b = 0; b < d.B; ++b) rp.p[b] = r0 + (size_t)b * HW;
@@ -1310,56 +1962,37 @@ void forward(const Net& n, const Ptrs& f, const Ptrs& u, hipStream_t s, bool gat
   k_rms_fin<<<2 * d.B, 64, 0, s>>>(rms_part, d.B, HW, sv);
   k_norm_in<<<dim3(cdiv(HW, 256), d.B), 256, 0, s>>>(r0, f, sv + d.B, sv + 2 * d.B, x0, HW);
   // L1, L2
-  k_conv_small<2, C, bf16, bf16, false, true><<<dim3(cdiv(HW, 256), d.B), 256, 0, s>>>(
-      x0, n.bfw(T_C1W), n.bfw(T_C1B), nullptr, a[0], d.H, d.W);
+  k_conv_in_mfma<C><<<dim3(cdiv(HW, 256), d.B), 256, 0, s>>>(
+      x0, n.bfw(T_C1W), n.bfw(T_C1B), a[0], d.H, d.W);
   k_conv_mfma<C, false><<<conv_grid(d.B, d.H, d.W), 256, 0, s>>>(a[0], n.bfw(T_C2W), n.bfw(T_C2B), nullptr, a[1], d.B, d.H, d.W);
   // L3 spectral
   float* T = n.w<float>(n.wl.T);
   float* X = n.w<float>(n.wl.X);
-  float* Y = n.w<float>(n.wl.Y);
   float* Z = n.w<float>(n.wl.Z);
-  k_spec_rows<C><<<d.B * d.H, 256, 0, s>>>(a[1], Sx, T, d.H, d.W, d.M);
-  k_cols<float><<<d.B * d.M * cdiv(d.M * C, 64), 256, 0, s>>>(T, Sy, X, d.B, d.H, d.M, d.M * C, 1.f);
-  k_spec_mix<false><<<cdiv((long long)d.B * d.M * d.M * C, 256), 256, 0, s>>>(X, n.bfw(T_SWK), Y,
-                                                                               d.B, d.M, C);
-  k_spec_inv_cols<<<cdiv((long long)d.B * d.H * d.M * C, 256), 256, 0, s>>>(
-      Y, Sy, Z, d.B, d.H, d.M, C, (float)(2.0 / (d.H + 1)));
-  k_spec_out<C, false><<<d.B * d.H * cdiv(d.W, 64), 256, 0, s>>>(
-      a[1], n.bfw(T_SW1), n.bfw(T_SB), Z, Sx, nullptr, a[2], d.H, d.W, d.M,
-      (float)(2.0 / (d.W + 1)));
+  k_spec_rows<C><<<d.B * d.H, 256, 0, s>>>(a[1], n.w<bf16>(n.wl.Sxh), n.w<bf16>(n.wl.Sxl), T, d.W,
+                                           WP, d.M);
+  k_spec_mid<C, false><<<d.B * d.M, 256, 0, s>>>(T, Sy, n.bfw(T_SWK), X, Z, d.H, d.M, 1.f,
+                                                 (float)(2.0 / (d.H + 1)));
+  launch_spec_out<C, false>(dim3(d.B * d.H * cdiv(d.W, 64)), s, a[1], n.bfw(T_SW1), n.bfw(T_SB), Z, Sx,
+                            nullptr, a[2], d.W, WP, d.M, (float)(2.0 / (d.W + 1)));
   // L4, L5, L6
   k_conv_mfma<C, false><<<conv_grid(d.B, d.H, d.W), 256, 0, s>>>(a[2], n.bfw(T_C4W), n.bfw(T_C4B), nullptr, a[3], d.B, d.H, d.W);
   k_conv_mfma<C, false><<<conv_grid(d.B, d.H, d.W), 256, 0, s>>>(a[3], n.bfw(T_C5W), n.bfw(T_C5B), nullptr, a[4], d.B, d.H, d.W);
-  k_conv_small<C, 1, bf16, float, false, false><<<dim3(cdiv(HW, 256), d.B), 256, 0, s>>>(
-      a[4], n.bfw(T_C6W), n.bfw(T_C6B), nullptr, n.w<float>(n.wl.out), d.H, d.W);
+  k_conv_out_mfma<C><<<dim3(cdiv(HW, 256), d.B), 256, 0, s>>>(
+      a[4], n.bfw(T_C6W), n.bfw(T_C6B), n.w<float>(n.wl.out), d.H, d.W);
   // band path from the FP64 residual, replacing the band of the
   // convolutional output: out += norm S^T (w X - S out S^T) S (FP64)
   if (d.K == 0) return;
-  double* kT = n.w<double>(n.wl.kT);
-  double* kX = n.w<double>(n.wl.kX);
-  double* kC = n.w<double>(n.wl.kC);
-  double* kY = n.w<double>(n.wl.kY);
-  double* kZ = n.w<double>(n.wl.kZ);
-  double* kSx = n.w<double>(n.wl.kSx);
-  double* kSy = n.w<double>(n.wl.kSy);
   float* out = n.w<float>(n.wl.out);
-  const int K = d.K;
-  double* kSxT = n.w<double>(n.wl.kSxT);
-  k_skip_basis<<<cdiv((long long)K * d.W, 256), 256, 0, s>>>(kSx, kSxT, K, d.W);
-  k_skip_basis<<<cdiv((long long)K * d.H, 256), 256, 0, s>>>(kSy, nullptr, K, d.H);
-  k_skip_rows<double><<<d.B * d.H, 256, 0, s>>>(r0, sv + d.B, kSxT, kT,
-                                                                         d.B, d.H, d.W, K);
-  k_cols<double><<<d.B * K * cdiv(K, 64), 256, 0, s>>>(kT, kSy, kX, d.B, d.H, K, K, 1.0);
-  k_skip_rows<float><<<d.B * d.H, 256, 0, s>>>(out, nullptr, kSxT, kT,
-                                                                        d.B, d.H, d.W, K);
-  k_cols<double><<<d.B * K * cdiv(K, 64), 256, 0, s>>>(kT, kSy, kC, d.B, d.H, K, K, 1.0);
   const double* gate = gated ? (const double*)(n.params + n.pl.gate) : nullptr;
-  k_band_apply<<<cdiv((long long)d.B * K * K, 256), 256, 0, s>>>(
-      kX, kC, (const double*)(n.params + n.pl.band), kY, d.B, K, gate);
-  k_skip_inv_cols<<<cdiv((long long)d.B * d.H * K, 256), 256, 0, s>>>(kY, kSy, kZ, d.B, d.H, K,
-                                                                      2.0 / (d.H + 1));
-  k_skip_out<<<cdiv((long long)d.B * HW, 256), 256, 0, s>>>(kZ, kSx, out, d.B, d.H, d.W, K,
-                                                            2.0 / (d.W + 1), gate);
+  const BandSpace bsp = band_space(n);
+  band_project_rows_cols<double, float>(n, {r0, sv + d.B, bsp.kT, 1.0},
+                                        {out, nullptr, bsp.kT2, 1.0}, bsp.kX, bsp.kC, 1.0, 1.0, s);
+  k_band_inv<<<d.B * cdiv(d.H, 32), 256, 0, s>>>(bsp.kX, bsp.kC,
+                                                 (const double*)(n.params + n.pl.band), gate,
+                                                 bsp.kSy, bsp.kZ, d.H, d.K, 2.0 / (d.H + 1));
+  k_band_out<<<dim3(band_out_blocks(d), 1), 256, 0, s>>>(
+      BandOut{bsp.kZ, out, gate, 2.0 / (d.W + 1)}, BandOut{}, bsp.kSx, d.H, d.W, d.K);
 }
 
 template <int C>
@@ -1373,7 +2006,7 @@ void wgrad_conv(const Net& n, const bf16* in, const bf16* dz, int tw, int tb, hi
   else
     k_wgrad_mfma<C, 1><<<G, 256, 0, s>>>(in, dz, part, d.B, d.H, d.W);
   const int nout = ntap * C * C + C;
-  k_wgrad_reduce<<<cdiv(nout, 256), 256, 0, s>>>(part, G, ntap, C, C, n.grad(tw), n.grad(tb));
+  k_wgrad_reduce<<<cdiv(nout, 64), 256, 0, s>>>(part, G, ntap, C, C, n.grad(tw), n.grad(tb));
 }
 
 template <int C>
@@ -1406,48 +2039,38 @@ void train(const Net& n, const Ptrs& f, const Ptrs& up, const Ptrs& ut, float* l
   // d = u_t - u_prev); the convolutional branch's gradient is dout off the
   // band: dout -= norm S^T S[dout] S
   if (d.K > 0) {
-    double* kT = n.w<double>(n.wl.kT);
-    double* kdY = n.w<double>(n.wl.kdY);
-    double* kTc = n.w<double>(n.wl.kTc);
-    double* kZ = n.w<double>(n.wl.kZ);
-    double* kSx = n.w<double>(n.wl.kSx);
-    double* kSxT = n.w<double>(n.wl.kSxT);
-    double* kSy = n.w<double>(n.wl.kSy);
+    const BandSpace bsp = band_space(n);
     double* tbuf = n.w<double>(n.wl.r0);          // the residual input is no longer needed
     double* abuf = n.w<double>(n.wl.ad);
-    double* kXa = n.w<double>(n.wl.kXa);
     const int K = d.K;
     k_pair<<<dim3(cdiv(HW, 256), d.B), 256, 0, s>>>(ut, up, tbuf, abuf, d.H, d.W);
-    k_skip_rows<double><<<d.B * d.H, 256, 0, s>>>(tbuf, sv + d.B, kSxT, kT, d.B, d.H, d.W, K);
-    k_cols<double><<<d.B * K * cdiv(K, 64), 256, 0, s>>>(kT, kSy, kTc, d.B, d.H, K, K, 1.0);
-    k_skip_rows<double><<<d.B * d.H, 256, 0, s>>>(abuf, sv + d.B, kSxT, kT, d.B, d.H, d.W, K);
-    k_cols<double><<<d.B * K * cdiv(K, 64), 256, 0, s>>>(kT, kSy, kXa, d.B, d.H, K, K, 1.0);
-    k_band_fit<<<cdiv((long long)K * K, 256), 256, 0, s>>>(kXa, kTc,
+    band_project_rows_cols<double, double>(n, {tbuf, sv + d.B, nullptr, 1.0},
+                                           {abuf, sv + d.B, nullptr, 1.0}, bsp.kTc, bsp.kXa, 1.0,
+                                           1.0, s);
+    k_band_fit<<<cdiv((long long)K * K, 256), 256, 0, s>>>(bsp.kXa, bsp.kTc,
                                                           (double*)(n.params + n.pl.band), d.B, K);
+    // dout -= P_K dout, and (output gain) c = out - P_K out, the branch's
+    // output off the band (out is no longer needed), against dout = (2/B)(c -
+    // t) off the band; P_K x = nrm S^T S[x] S
     const double nrm = (2.0 / (d.H + 1)) * (2.0 / (d.W + 1));
-    k_skip_rows<float><<<d.B * d.H, 256, 0, s>>>(dout, nullptr, kSxT, kT, d.B, d.H, d.W, K);
-    k_cols<double><<<d.B * K * cdiv(K, 64), 256, 0, s>>>(kT, kSy, kdY, d.B, d.H, K, K, nrm);
-    k_skip_inv_cols<<<cdiv((long long)d.B * d.H * K, 256), 256, 0, s>>>(kdY, kSy, kZ, d.B, d.H, K,
-                                                                        1.0);
-    k_skip_out<<<cdiv((long long)d.B * HW, 256), 256, 0, s>>>(kZ, kSx, dout, d.B, d.H, d.W, K, -1.0,
-                                                              nullptr);
-    // output gain: c = out - P_K out, the branch's output off the band (out
-    // is no longer needed), against dout = (2/B)(c - t) off the band
-    k_skip_rows<float><<<d.B * d.H, 256, 0, s>>>(out, nullptr, kSxT, kT, d.B, d.H, d.W, K);
-    k_cols<double><<<d.B * K * cdiv(K, 64), 256, 0, s>>>(kT, kSy, kdY, d.B, d.H, K, K, nrm);
-    k_skip_inv_cols<<<cdiv((long long)d.B * d.H * K, 256), 256, 0, s>>>(kdY, kSy, kZ, d.B, d.H, K,
-                                                                        1.0);
-    k_skip_out<<<cdiv((long long)d.B * HW, 256), 256, 0, s>>>(kZ, kSx, out, d.B, d.H, d.W, K, -1.0,
-                                                              nullptr);
+    band_project_rows_cols<float, float>(n, {dout, nullptr, nullptr, 1.0}, {out, nullptr, nullptr, 1.0},
+                                         bsp.kdY, bsp.kdY2, nrm, nrm, s);
+    k_band_inv<<<d.B * cdiv(d.H, 32), 256, 0, s>>>(bsp.kdY, nullptr, nullptr, nullptr, bsp.kSy,
+                                                   bsp.kZ, d.H, K, 1.0);
+    k_band_inv<<<d.B * cdiv(d.H, 32), 256, 0, s>>>(bsp.kdY2, nullptr, nullptr, nullptr, bsp.kSy,
+                                                   bsp.kZ2, d.H, K, 1.0);
+    k_band_out<<<dim3(band_out_blocks(d), 2), 256, 0, s>>>(BandOut{bsp.kZ, dout, nullptr, -1.0},
+                                                           BandOut{bsp.kZ2, out, nullptr, -1.0},
+                                                           bsp.kSx, d.H, d.W, K);
     double* gpart = n.w<double>(n.wl.loss) + 8 + 2048;
     k_gate_sums<<<256, 256, 0, s>>>(out, dout, (long long)d.B * HW, gpart);
     k_gate_fin<<<1, 64, 0, s>>>(gpart, 256, (double*)(n.params + n.pl.gate), d.B);
   }
   // L6: weight grad from (a5, dout); input grad masked by a5 -> dz5
   k_wgrad_out<C><<<G, 256, 0, s>>>(a[4], dout, part, d.B, d.H, d.W);
-  k_wgrad_reduce<<<cdiv(9 * C + 1, 256), 256, 0, s>>>(part, G, 9, 1, C, n.grad(T_C6W), n.grad(T_C6B));
-  k_conv_small<1, C, float, bf16, true, false><<<dim3(cdiv(HW, 256), d.B), 256, 0, s>>>(
-      dout, n.bfw(T_C6W), nullptr, a[4], dz[0], d.H, d.W);
+  k_wgrad_reduce<<<cdiv(9 * C + 1, 64), 256, 0, s>>>(part, G, 9, 1, C, n.grad(T_C6W), n.grad(T_C6B));
+  k_conv_outT_mfma<C><<<dim3(cdiv(HW, 256), d.B), 256, 0, s>>>(
+      dout, n.bfw(T_C6W), a[4], dz[0], d.H, d.W);
   // L5
   wgrad_conv<C>(n, a[3], dz[0], T_C5W, T_C5B, s, 9);
   k_conv_mfma<C, true><<<conv_grid(d.B, d.H, d.W), 256, 0, s>>>(dz[0], n.bfw(T_C5W), nullptr, a[3], dz[1], d.B, d.H, d.W);
@@ -1459,24 +2082,21 @@ void train(const Net& n, const Ptrs& f, const Ptrs& up, const Ptrs& ut, float* l
   float* T = n.w<float>(n.wl.T);
   float* X = n.w<float>(n.wl.X);
   float* dY = n.w<float>(n.wl.Y);
-  float* dX = n.w<float>(n.wl.dX);
   float* Z = n.w<float>(n.wl.Z);
   const float nrm = (float)((2.0 / (d.H + 1)) * (2.0 / (d.W + 1)));
-  k_spec_rows<C><<<d.B * d.H, 256, 0, s>>>(dz[0], Sx, T, d.H, d.W, d.M);
-  k_cols<float><<<d.B * d.M * cdiv(d.M * C, 64), 256, 0, s>>>(T, Sy, dY, d.B, d.H, d.M, d.M * C, nrm);
+  const int WP = spec_wp(d);
+  k_spec_rows<C><<<d.B * d.H, 256, 0, s>>>(dz[0], n.w<bf16>(n.wl.Sxh), n.w<bf16>(n.wl.Sxl), T, d.W,
+                                           WP, d.M);
+  k_spec_mid<C, true><<<d.B * d.M, 256, 0, s>>>(T, Sy, n.bfw(T_SWK), dY, Z, d.H, d.M, nrm, 1.f);
   k_spec_dwk<<<cdiv((long long)d.M * d.M * C * C, 256), 256, 0, s>>>(dY, X, n.grad(T_SWK), d.B, d.M, C);
-  k_spec_mix<true><<<cdiv((long long)d.B * d.M * d.M * C, 256), 256, 0, s>>>(dY, n.bfw(T_SWK), dX,
-                                                                              d.B, d.M, C);
-  k_spec_inv_cols<<<cdiv((long long)d.B * d.H * d.M * C, 256), 256, 0, s>>>(dX, Sy, Z, d.B, d.H, d.M,
-                                                                             C, 1.f);
-  k_spec_out<C, true><<<d.B * d.H * cdiv(d.W, 64), 256, 0, s>>>(dz[0], n.bfw(T_SW1), nullptr, Z, Sx,
-                                                                a[1], dz[1], d.H, d.W, d.M, 1.f);
+  launch_spec_out<C, true>(dim3(d.B * d.H * cdiv(d.W, 64)), s, dz[0], n.bfw(T_SW1), nullptr, Z, Sx,
+                           a[1], dz[1], d.W, WP, d.M, 1.f);
   // L2: dz2 = dz[1]
   wgrad_conv<C>(n, a[0], dz[1], T_C2W, T_C2B, s, 9);
   k_conv_mfma<C, true><<<conv_grid(d.B, d.H, d.W), 256, 0, s>>>(dz[1], n.bfw(T_C2W), nullptr, a[0], dz[0], d.B, d.H, d.W);
   // L1: dz1 = dz[0]
   k_wgrad_in<C><<<G, 256, 0, s>>>(x0, dz[0], part, d.B, d.H, d.W);
-  k_wgrad_reduce<<<cdiv(9 * C * 2 + C, 256), 256, 0, s>>>(part, G, 9, C, 2, n.grad(T_C1W),
+  k_wgrad_reduce<<<cdiv(9 * C * 2 + C, 64), 256, 0, s>>>(part, G, 9, C, 2, n.grad(T_C1W),
                                                           n.grad(T_C1B));
   // Adam
   long long* step = (long long*)(n.params + n.pl.step);
@@ -1768,9 +2388,9 @@ void fluid_forward(const FNet& n, const Ptrs& f, const Ptrs& u, int blocks, hipS
   for (int l = 0; l < d.L; ++l) {
     const int Hl = d.H >> l, Wl = d.W >> l;
     const long long hw = (long long)Hl * Wl;
-    k_conv_small<2, C, bf16, bf16, false, true><<<dim3(cdiv(hw, 256), d.B), 256, 0, s>>>(
-        n.w<bf16>(n.wl.X[l]), n.bfw(fl_lvl(l, 0)), n.bfw(fl_lvl(l, 1)), nullptr,
-        n.w<bf16>(n.wl.A[l]), Hl, Wl);
+    k_conv_in_mfma<C><<<dim3(cdiv(hw, 256), d.B), 256, 0, s>>>(
+        n.w<bf16>(n.wl.X[l]), n.bfw(fl_lvl(l, 0)), n.bfw(fl_lvl(l, 1)), n.w<bf16>(n.wl.A[l]), Hl,
+        Wl);
     k_conv_mfma<C, false><<<conv_grid(d.B, Hl, Wl), 256, 0, s>>>(n.w<bf16>(n.wl.A[l]), n.bfw(fl_lvl(l, 2)), n.bfw(fl_lvl(l, 3)), nullptr, n.w<bf16>(n.wl.Y[l]), d.B, Hl, Wl);
     yp.p[l] = n.w<bf16>(n.wl.Y[l]);
   }
@@ -1781,9 +2401,9 @@ void fluid_forward(const FNet& n, const Ptrs& f, const Ptrs& u, int blocks, hipS
     k_conv_mfma<C, false, true><<<conv_grid(d.B, d.H, d.W), 256, 0, s>>>(n.w<bf16>(n.wl.Hb[i]), n.bfw(fl_blk(d, i, 2)), n.bfw(fl_blk(d, i, 3)), n.w<bf16>(n.wl.S[i]), n.w<bf16>(n.wl.S[i + 1]), d.B, d.H, d.W);
   }
   k_conv_mfma<C, false><<<conv_grid(d.B, d.H, d.W), 256, 0, s>>>(n.w<bf16>(n.wl.S[blocks]), n.bfw(fl_head(d, 0)), n.bfw(fl_head(d, 1)), nullptr, n.w<bf16>(n.wl.o), d.B, d.H, d.W);
-  k_conv_small<C, 1, bf16, float, false, false><<<dim3(cdiv(HW, 256), d.B), 256, 0, s>>>(
-      n.w<bf16>(n.wl.o), n.bfw(fl_head(d, 2)), n.bfw(fl_head(d, 3)), nullptr,
-      n.w<float>(n.wl.out), d.H, d.W);
+  k_conv_out_mfma<C><<<dim3(cdiv(HW, 256), d.B), 256, 0, s>>>(
+      n.w<bf16>(n.wl.o), n.bfw(fl_head(d, 2)), n.bfw(fl_head(d, 3)), n.w<float>(n.wl.out), d.H,
+      d.W);
 }
 
 void fl_wgrad9(const FNet& n, const bf16* in, const bf16* dz, int tw, int tb, int H, int W,
@@ -1792,7 +2412,7 @@ void fl_wgrad9(const FNet& n, const bf16* in, const bf16* dz, int tw, int tb, in
   float* part = n.w<float>(n.wl.part);
   const int G = n.wl.wgrad_blocks;
   k_wgrad_mfma<C, 9><<<G, 256, 0, s>>>(in, dz, part, n.d.B, H, W);
-  k_wgrad_reduce<<<cdiv(9 * C * C + C, 256), 256, 0, s>>>(part, G, 9, C, C, n.grad(tw), n.grad(tb));
+  k_wgrad_reduce<<<cdiv(9 * C * C + C, 64), 256, 0, s>>>(part, G, 9, C, C, n.grad(tw), n.grad(tb));
 }
 
 void fluid_train(const FNet& n, const Ptrs& f, const Ptrs& up, const Ptrs& ut, int blocks,
@@ -1819,10 +2439,10 @@ void fluid_train(const FNet& n, const Ptrs& f, const Ptrs& up, const Ptrs& ut, i
   // head: out = conv(o), o = ReLU(conv(S_R))
   bf16* o = n.w<bf16>(n.wl.o);
   k_wgrad_out<C><<<G, 256, 0, s>>>(o, dout, part, d.B, d.H, d.W);
-  k_wgrad_reduce<<<cdiv(9 * C + 1, 256), 256, 0, s>>>(part, G, 9, 1, C, n.grad(fl_head(d, 2)),
+  k_wgrad_reduce<<<cdiv(9 * C + 1, 64), 256, 0, s>>>(part, G, 9, 1, C, n.grad(fl_head(d, 2)),
                                                        n.grad(fl_head(d, 3)));
-  k_conv_small<1, C, float, bf16, true, false><<<dim3(cdiv(HW, 256), d.B), 256, 0, s>>>(
-      dout, n.bfw(fl_head(d, 2)), nullptr, o, d1, d.H, d.W);
+  k_conv_outT_mfma<C><<<dim3(cdiv(HW, 256), d.B), 256, 0, s>>>(
+      dout, n.bfw(fl_head(d, 2)), o, d1, d.H, d.W);
   fl_wgrad9(n, n.w<bf16>(n.wl.S[blocks]), d1, fl_head(d, 0), fl_head(d, 1), d.H, d.W, s);
   k_conv_mfma<C, true, true><<<conv_grid(d.B, d.H, d.W), 256, 0, s>>>(d1, n.bfw(fl_head(d, 0)), nullptr, nullptr, dS, d.B, d.H, d.W);
   // residual blocks, last first: dS accumulates in place
@@ -1853,7 +2473,7 @@ void fluid_train(const FNet& n, const Ptrs& f, const Ptrs& up, const Ptrs& ut, i
     fl_wgrad9(n, A, d1, fl_lvl(l, 2), fl_lvl(l, 3), Hl, Wl, s);
     k_conv_mfma<C, true><<<conv_grid(d.B, Hl, Wl), 256, 0, s>>>(d1, n.bfw(fl_lvl(l, 2)), nullptr, A, d2, d.B, Hl, Wl);
     k_wgrad_in<C><<<G, 256, 0, s>>>(n.w<bf16>(n.wl.X[l]), d2, part, d.B, Hl, Wl);
-    k_wgrad_reduce<<<cdiv(9 * C * 2 + C, 256), 256, 0, s>>>(part, G, 9, C, 2, n.grad(fl_lvl(l, 0)),
+    k_wgrad_reduce<<<cdiv(9 * C * 2 + C, 64), 256, 0, s>>>(part, G, 9, C, 2, n.grad(fl_lvl(l, 0)),
                                                             n.grad(fl_lvl(l, 1)));
   }
   // blocks beyond the active ones take no step
