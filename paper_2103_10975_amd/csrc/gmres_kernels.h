@@ -390,47 +390,26 @@ __device__ __forceinline__ double lane_bcast(double v, int src) {
   return __hiloint2double(hi, lo);
 }
 
-// The basis at N points per thread, every load issued at once and
-// unconditionally: slots k >= `live` re-read the last live vector (vector
-// `spare` when none is live), so no branch separates the loads.  Those slots
-// may meet zero coefficients (an exact no-op) but are otherwise unused; they
-// must hold finite data, which written vectors do (a slot not yet written
-// in this cycle may not).
-template <int MM, int N, class T>
-__device__ __forceinline__ void load_basis(T (&v)[MM][N], const BasisBuf<T>& B,
-                                           const long long (&p)[N], int live, int spare) {
+// Slots k0 .. k0 + KC - 1 of the basis at this thread's points, every load of
+// the chunk issued at once and unconditionally: slots k >= `live` re-read the
+// last live vector (vector `spare` when none is live), so no branch separates
+// the loads.  Those slots may meet zero coefficients (an exact no-op) but are
+// otherwise unused; they must hold finite data, which written vectors do (a
+// slot not yet written in this cycle may not).  The sweeps stream the basis
+// through registers one chunk at a time, the next chunk's loads in flight
+// while the current one is used, so their register use does not grow with
+// the restart length and larger tiles stay resident.
+template <int KC, int N, class T>
+__device__ __forceinline__ void load_basis_chunk(T (&v)[KC][N], const BasisBuf<T>& B,
+                                                 const long long (&p)[N], int k0, int live,
+                                                 int spare) {
   const int last = live > 0 ? live - 1 : spare;
 #pragma unroll
-  for (int k = 0; k < MM; ++k) {
+  for (int q = 0; q < KC; ++q) {
+    const int k = k0 + q;
 #pragma unroll
-    for (int i = 0; i < N; ++i) v[k][i] = B.load(k < live ? k : last, (unsigned)p[i]);
+    for (int i = 0; i < N; ++i) v[q][i] = B.load(k < live ? k : last, (unsigned)p[i]);
   }
-}
-
-// Products of the first `live` basis slots with x and y at this thread's
-// points, folded across the wavefront in chunks of 8 slots (16 sums each)
-// into acc[c]; `last` (4 further sums) goes to acc[MM / 8].
-template <int MM, int N, class T>
-__device__ __forceinline__ void fold_products(double (&acc)[MM / 8 + 1], const T (&v)[MM][N],
-                                              const double (&x)[N], const double (&y)[N],
-                                              const double (&last)[4], int live) {
-#pragma unroll
-  for (int c = 0; c < MM / 8; ++c)
-    if (8 * c < live) {
-      double prod[16];
-#pragma unroll
-      for (int q = 0; q < 8; ++q) {
-        prod[q] = 0.0;
-        prod[8 + q] = 0.0;
-#pragma unroll
-        for (int i = 0; i < N; ++i) {
-          prod[q] = fma((double)v[8 * c + q][i], x[i], prod[q]);
-          prod[8 + q] = fma((double)v[8 * c + q][i], y[i], prod[8 + q]);
-        }
-      }
-      acc[c] += rs16(prod);
-    }
-  acc[MM / 8] += rs4(last);
 }
 
 // Block sums of the folded products into this workgroup's partial columns.
@@ -657,8 +636,9 @@ __global__ __launch_bounds__(kBlock) void k_dots(const Job* jobs, const SysDesc*
       qc[i][1] = pr.qy;
       qc[i][2] = pr.qz;
     }
-    T vr[MM][PPT];
-    load_basis<MM, PPT, T>(vr, VB, pp, j, kU);
+    constexpr int KC = 8, NCH = MM / KC;
+    T vb[2][KC][PPT];
+    load_basis_chunk<KC, PPT, T>(vb[0], VB, pp, 0, j, kU);   // in flight during the staging
     __syncthreads();
     load_tile_buf<TL, T>(L, VB, kU, g, ox, oy, oz);
     __syncthreads();
@@ -670,7 +650,30 @@ __global__ __launch_bounds__(kBlock) void k_dots(const Job* jobs, const SysDesc*
       last[0] = fma(uu[i], uu[i], last[0]);
       last[1] = fma(uu[i], ww[i], last[1]);
     }
-    fold_products<MM, PPT, T>(acc, vr, uu, ww, last, j);
+    // products per chunk of 8 slots, folded across the wavefront (16 sums)
+#pragma unroll
+    for (int c = 0; c < NCH; ++c) {
+      // the scheduler keeps each chunk's loads here (one chunk ahead), not
+      // hoisted to the top, so only two chunks occupy registers
+      __builtin_amdgcn_sched_barrier(0);
+      if (c + 1 < NCH && KC * (c + 1) < j)
+        load_basis_chunk<KC, PPT, T>(vb[(c + 1) & 1], VB, pp, KC * (c + 1), j, kU);
+      if (KC * c < j) {
+        double prod[16];
+#pragma unroll
+        for (int q = 0; q < KC; ++q) {
+          prod[q] = 0.0;
+          prod[KC + q] = 0.0;
+#pragma unroll
+          for (int i = 0; i < PPT; ++i) {
+            prod[q] = fma((double)vb[c & 1][q][i], uu[i], prod[q]);
+            prod[KC + q] = fma((double)vb[c & 1][q][i], ww[i], prod[KC + q]);
+          }
+        }
+        acc[c] += rs16(prod);
+      }
+    }
+    acc[NCH] += rs4(last);
   }
   store_folded<MM>(acc, red, gmem(me.job.part), g.nblk, me.job.lblk,
                    [j](int slot, bool y) { return slot < j ? (y ? j + slot : slot) : -1; },
@@ -972,24 +975,41 @@ __global__ __launch_bounds__(kBlock) void k_extend(const Job* jobs, const SysDes
       qc[i][1] = pr.qy;
       qc[i][2] = pr.qz;
     }
-    T vr[MM][PPT];
-    load_basis<MM, PPT, T>(vr, VB, pp, j, kU);
+    constexpr int KC = 8, NCH = MM / KC;
+    T vb[2][KC][PPT];
+    load_basis_chunk<KC, PPT, T>(vb[0], VB, pp, 0, j, kU);
     __syncthreads();
     load_tile_buf<TL, T>(L, VB, kU, g, ox, oy, oz);
     __syncthreads();
+    // a = V s, b = V cY at this thread's points, slot by slot in order (the
+    // chunks past j hold zero coefficients only and are skipped)
+    double a[PPT], b[PPT];
+#pragma unroll
+    for (int i = 0; i < PPT; ++i) a[i] = b[i] = 0.0;
+#pragma unroll
+    for (int c = 0; c < NCH; ++c) {
+      // the scheduler keeps each chunk's loads here (one chunk ahead), not
+      // hoisted to the top, so only two chunks occupy registers
+      __builtin_amdgcn_sched_barrier(0);
+      if (c + 1 < NCH && KC * (c + 1) < j)
+        load_basis_chunk<KC, PPT, T>(vb[(c + 1) & 1], VB, pp, KC * (c + 1), j, kU);
+      if (KC * c < j) {
+#pragma unroll
+        for (int q = 0; q < KC; ++q)
+#pragma unroll
+          for (int i = 0; i < PPT; ++i) {
+            a[i] = fma((double)vb[c & 1][q][i], sY[KC * c + q], a[i]);
+            b[i] = fma((double)vb[c & 1][q][i], cY[KC * c + q], b[i]);
+          }
+      }
+    }
 #pragma unroll
     for (int i = 0; i < PPT; ++i)
       if (ok[i]) {
         const double uu = centre<TL>(L, qc[i][0], qc[i][1], qc[i][2]);
         const double ww = stencil<TL>(L, g, qc[i][0], qc[i][1], qc[i][2]);
-        double a = 0.0, b = 0.0;
-#pragma unroll
-        for (int k = 0; k < MM; ++k) {
-          a = fma((double)vr[k][i], sY[k], a);
-          b = fma((double)vr[k][i], cY[k], b);
-        }
         T vj, un;
-        extend_point<T>(uu, ww, a, b, ainv, cyj, vj, un);
+        extend_point<T>(uu, ww, a[i], b[i], ainv, cyj, vj, un);
         VB.store(j, (unsigned)pp[i], vj);
         VB.store(kUn, (unsigned)pp[i], un);
       }
@@ -1351,19 +1371,29 @@ __global__ __launch_bounds__(kBlock) void k_update(const Job* jobs, const SysDes
       ok[i] = pr.valid;
       pp[i] = pr.valid ? pr.p : 0;
     }
-    T vr[MM][PPT];
-    load_basis<MM, PPT, T>(vr, VB, pp, k, me.job.m);
-    double xs[PPT];
+    constexpr int KC = 8, NCH = MM / KC;
+    T vb[2][KC][PPT];
+    load_basis_chunk<KC, PPT, T>(vb[0], VB, pp, 0, k, me.job.m);
+    double acc[PPT];
 #pragma unroll
-    for (int i = 0; i < PPT; ++i) xs[i] = buf_load<double>(rx, (unsigned)pp[i]);
+    for (int i = 0; i < PPT; ++i) acc[i] = buf_load<double>(rx, (unsigned)pp[i]);
 #pragma unroll
-    for (int i = 0; i < PPT; ++i) {
-      double acc = xs[i];
+    for (int c = 0; c < NCH; ++c) {
+      // the scheduler keeps each chunk's loads here (one chunk ahead), not
+      // hoisted to the top, so only two chunks occupy registers
+      __builtin_amdgcn_sched_barrier(0);
+      if (c + 1 < NCH && KC * (c + 1) < k)
+        load_basis_chunk<KC, PPT, T>(vb[(c + 1) & 1], VB, pp, KC * (c + 1), k, me.job.m);
+      if (KC * c < k) {
 #pragma unroll
-      for (int l = 0; l < MM; ++l)
-        acc = fma(ys[l], (double)vr[l][i], acc);
-      if (ok[i]) buf_store(rx, (unsigned)pp[i], acc);
+        for (int q = 0; q < KC; ++q)
+#pragma unroll
+          for (int i = 0; i < PPT; ++i) acc[i] = fma(ys[KC * c + q], (double)vb[c & 1][q][i], acc[i]);
+      }
     }
+#pragma unroll
+    for (int i = 0; i < PPT; ++i)
+      if (ok[i]) buf_store(rx, (unsigned)pp[i], acc[i]);
   }
 }
 

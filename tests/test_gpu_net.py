@@ -99,7 +99,12 @@ def dev(a):
 
 
 @pytest.mark.parametrize("shape,M,K,B", [((42, 70), 8, 12, 2), ((64, 64), 16, 32, 1),
-                                         ((33, 129), 12, 20, 3), ((40, 72), 8, 0, 2)])
+                                         ((33, 129), 12, 20, 3), ((40, 72), 8, 0, 2),
+                                         # two lane passes of the band kernels (K > 64),
+                                         # row chunks past 256 columns, 5 mode steps
+                                         ((96, 300), 18, 80, 1),
+                                         # column chunks past 256 rows, 2 mode steps
+                                         ((270, 72), 6, 40, 2)])
 def test_forward_parity(mlg, shape, M, K, B):
     print("net forward", shape, M, K, B, flush=True)
     cfg = mlg.NetCfg(channels=32, modes=M, skip_modes=K)
@@ -150,7 +155,7 @@ def test_forward_homogeneous_bitwise(mlg):
 # fraction of that (much larger) output; measured on 40 x 68 the worst tensor
 # error grows from 1e-2 at K = 4 to 1e-1 at K = 16.
 @pytest.mark.parametrize("shape,M,K,B", [((40, 68), 8, 4, 2), ((64, 64), 16, 8, 3),
-                                         ((48, 40), 8, 0, 2)])
+                                         ((48, 40), 8, 0, 2), ((72, 264), 13, 8, 2)])
 def test_train_step_gradients_and_adam(mlg, shape, M, K, B):
     print("net train", shape, M, K, B, flush=True)
     cfg = mlg.NetCfg(channels=32, modes=M, skip_modes=K, lr=1e-3)
