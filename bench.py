@@ -73,7 +73,8 @@ def parse():
                     help="counter-collection run: a 256 MiB device copy (the byte-count "
                          "calibration) then every launch of KERNEL (step, dots, extend, update, "
                          "resid) in one restart cycle, in the learned-guess solve's launch "
-                         "configuration")
+                         "configuration; `net`: three inference calls (batch 1) and three "
+                         "training steps (batch 8) of the guess network instead")
     ap.add_argument("--probe-grid", default=None,
                     help="with --probe: another workload, e.g. 1024x1024:fp64:30, "
                          "2048x2048:fp32:40 or 160x160x160:fp32:40")
@@ -393,6 +394,9 @@ def main():
 
     torch.cuda.set_device(0)
     shape = (args.grid, args.grid)
+    if args.probe == "net":
+        probe_net(mlg, shape, args)
+        return
     if args.probe:
         probe(mlg, shape, args)
         return
@@ -521,6 +525,36 @@ def main():
     if args.json_out:
         with open(args.json_out, "w") as fh:
             fh.write(line + "\n")
+
+
+def probe_net(mlg, shape, args):
+    """Guess-network launches for counter runs: the 256 MiB copy calibration,
+    then three inference calls (batch 1) and three training steps (batch 8,
+    the replay batch) of the benchmark's network at the benchmark's grid."""
+    from synthetic import DriftingGaussians
+    a = torch.ones(64 << 20, dtype=torch.float32, device="cuda")       # 256 MiB
+    for _ in range(3):
+        a.clone()
+    torch.cuda.synchronize()
+    gen = DriftingGaussians(shape, 4, 0.03, seed=args.seed)
+    fs = [torch.from_numpy(gen.field(t)).cuda() for t in range(10)]
+    grid = mlg.grid_of(shape)
+    cfg = mlg.NetCfg(channels=32, modes=16, skip_modes=min(64, *shape), seed=1)
+    params = torch.zeros(mlg.guess_net_param_bytes(cfg), dtype=torch.uint8, device="cuda")
+    mlg.guess_net_init(cfg, params)
+    wsi = mlg.workspace(mlg.guess_net_workspace_bytes(cfg, grid, 1, False))
+    wst = mlg.workspace(mlg.guess_net_workspace_bytes(cfg, grid, 8, True))
+    u = 0.01 * fs[0]
+    x = torch.empty_like(u)
+    loss = torch.zeros(1, dtype=torch.float32, device="cuda")
+    for _ in range(3):
+        mlg.guess_net_infer(cfg, params, fs[1].view(1, *shape), u.view(1, *shape),
+                            x.view(1, *shape), wsi)
+    for _ in range(3):
+        mlg.guess_net_train_step(cfg, params, fs[:8], [u] * 8, fs[1:9], wst, loss)
+    torch.cuda.synchronize()
+    print(json.dumps({"probe": "net", "workload": "x".join(map(str, shape)),
+                      "copy_bytes": 2 * a.numel() * 4}), flush=True)
 
 
 def probe(mlg, shape, args):
