@@ -931,10 +931,28 @@ __global__ __launch_bounds__(256) void k_wgrad_mfma(const bf16* in, const bf16* 
         *reinterpret_cast<uint32_t*>(&dzT[(ch * 8 + 2 * h + 1) * PD + q]) = (a0[h] >> 16) | (a1[h] & 0xffff0000u);
       }
     }
-    // input^T, halo columns -1..64 of rows -1..TY: copy 0 holds halo column h
-    // at position h, copy 1 at position h - 1; a unit = halo columns
-    // 2k, 2k+1, 2k+2 of one row x 8 channels
-    for (int u = threadIdx.x; u < LY * 33 * CH; u += 256) {
+    // input^T.  1x1: the tile's own pixels only, in copy 1 (image column ox + h
+    // at position h, the position the tap reads), two columns x 8 channels a
+    // unit.  3x3: halo columns -1..64 of rows -1..TY: copy 0 holds halo column
+    // h at position h, copy 1 at position h - 1; a unit = halo columns 2k,
+    // 2k+1, 2k+2 of one row x 8 channels.
+    if constexpr (NTAP == 1) {
+      for (int u = threadIdx.x; u < TY * 32 * CH; u += 256) {
+        const int ch = u % CH, rk = u / CH, r = rk / 32, k = rk % 32;
+        const int gy = oy + r, gx = ox + 2 * k;
+        uint4 v1 = make_uint4(0, 0, 0, 0), v2 = v1;
+        if (gy < H && gx < W) v1 = *reinterpret_cast<const uint4*>(inb + ((long long)gy * W + gx) * C + ch * 8);
+        if (gy < H && gx + 1 < W) v2 = *reinterpret_cast<const uint4*>(inb + ((long long)gy * W + gx + 1) * C + ch * 8);
+        const uint32_t w1[4] = {v1.x, v1.y, v1.z, v1.w}, w2[4] = {v2.x, v2.y, v2.z, v2.w};
+#pragma unroll
+        for (int h = 0; h < 4; ++h) {
+          const int c0 = ch * 8 + 2 * h, o = (r + 1) * PX + 2 * k;
+          *reinterpret_cast<uint32_t*>(&inT[1][c0 * PC + o]) = (w1[h] & 0xffffu) | (w2[h] << 16);
+          *reinterpret_cast<uint32_t*>(&inT[1][(c0 + 1) * PC + o]) = (w1[h] >> 16) | (w2[h] & 0xffff0000u);
+        }
+      }
+    }
+    for (int u = threadIdx.x; NTAP == 9 && u < LY * 33 * CH; u += 256) {
       const int ch = u % CH, rk = u / CH, ly = rk / 33, k = rk % 33;
       const int gy = oy + ly - 1;
       uint4 v[3];
@@ -1133,154 +1151,159 @@ __global__ __launch_bounds__(256) void k_spec_rows(const bf16* in, const bf16* S
   }
 }
 
-// The spectral layer between the row transforms, one workgroup per (b, l),
-// l the mode along x:
-//   X[k][c] = scale sum_i Sy[k][i] T[b][i][l][c]          column transform
-//   Y[k][n] = sum_m w[k][l][n][m] X[k][m]                   mode mixing
-//             (BWD: the transpose, sum_m w[k][l][m][n] X[k][m])
-//   Z[b][i][l][n] = alpha sum_k Sy[k][i] Y[k][n]            inverse column transform
-// X is stored ([b][k][l][c]) for the weight gradient.  A thread takes one
-// channel and every eighth row (FP32 sums, the eight row groups added in a
-// fixed order); Sy comes through LDS in chunks of 64 rows.
-template <int C, bool BWD>
-__global__ __launch_bounds__(256) void k_spec_mid(const float* T, const float* Sy, const bf16* wk,
-                                                  float* Xs, float* Z, int H, int M, float scale,
-                                                  float alpha) {
-  static_assert(C == 32, "a channel per lane of a half-wavefront");
-  constexpr int MM = 32, IC = 64, PS = MM * IC / 256, PT = IC * C / 256;
-  __shared__ float part[8][MM][C];
-  __shared__ float syl[MM][IC];
-  __shared__ float tl[IC][C];
-  __shared__ float Yl[MM][C];
-  const int b = blockIdx.x / M, l = blockIdx.x % M;
-  const int c = threadIdx.x & 31, ig = threadIdx.x >> 5;
-  const size_t tstride = (size_t)M * C;
-  const size_t base = ((size_t)b * H * M + l) * C;     // element (b, i = 0, l, c = 0)
-  // A chunk's basis values Sy[k][i0 + ii] and (X phase) rows of T, read into
-  // registers at clamped indices (all loads of a thread in flight together);
-  // the LDS copies are zero past H and past M, so that the sums below run
-  // over all 32 mode slots without a branch.
-  float sv[PS], tv[PT];
-  auto load_chunk = [&](int i0, bool with_t) {
+// Column transform of the spectral layer: X[b][k][q] = scale sum_i Sy[k][i]
+// T[b][i][q] for q = l C + c < M C (the row-transformed activations).  A
+// workgroup takes 8 modes k and 64 consecutive q of one image; lanes are q,
+// the four wavefronts a quarter of every chunk of 256 rows; the chunk's
+// basis rows are staged in LDS (zero past H or M), T is read 16 rows at a
+// time with independent coalesced loads; the quarters are added in a fixed
+// order.  X ([b][k][l][c]) is kept for the mode mixing and its weight gradient.
+__global__ __launch_bounds__(256) void k_spec_cols(const float* T, const float* Sy, float* X, int H,
+                                                   int M, int LQ, float scale) {
+  constexpr int KB = 8, IC = 256, IQ = IC / 4, NB = 16, PER = KB * IC / 256;
+  __shared__ float syl[KB][IC];
+  __shared__ float part[4][KB][64];
+  const int nkb = (M + KB - 1) / KB, nqb = (LQ + 63) / 64;
+  const int qb = blockIdx.x % nqb, kb = (blockIdx.x / nqb) % nkb, b = blockIdx.x / (nqb * nkb);
+  const int k0 = kb * KB;
+  const int lane = threadIdx.x & 63, w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int q = qb * 64 + lane, qc = min(q, LQ - 1);
+  const int klast = min(KB, M - k0) - 1;
+  const float* tb = T + (size_t)b * H * LQ + qc;
+  float s[KB];
 #pragma unroll
-    for (int u = 0; u < PS; ++u) {
-      const int e = threadIdx.x + 256 * u, k = e / IC, ii = e % IC;
-      sv[u] = Sy[(size_t)min(k, M - 1) * H + min(i0 + ii, H - 1)];
-    }
-    if (with_t) {
-#pragma unroll
-      for (int u = 0; u < PT; ++u) {
-        const int e = threadIdx.x + 256 * u, ii = e / C, cc = e % C;
-        tv[u] = T[base + (size_t)min(i0 + ii, H - 1) * tstride + cc];
-      }
-    }
-  };
-  auto store_chunk = [&](int i0, bool with_t) {
-#pragma unroll
-    for (int u = 0; u < PS; ++u) {
-      const int e = threadIdx.x + 256 * u, k = e / IC, ii = e % IC;
-      syl[k][ii] = (k < M && i0 + ii < H) ? sv[u] : 0.f;
-    }
-    if (with_t) {
-#pragma unroll
-      for (int u = 0; u < PT; ++u) {
-        const int e = threadIdx.x + 256 * u, ii = e / C, cc = e % C;
-        tl[ii][cc] = i0 + ii < H ? tv[u] : 0.f;
-      }
-    }
-  };
-  // ---- column transform: partial sums over the rows ii = ig (mod 8)
-  float acc[MM];
-#pragma unroll
-  for (int k = 0; k < MM; ++k) acc[k] = 0.f;
-  load_chunk(0, true);
+  for (int r = 0; r < KB; ++r) s[r] = 0.f;
   for (int i0 = 0; i0 < H; i0 += IC) {
-    __syncthreads();                                     // the previous chunk's readers are done
-    store_chunk(i0, true);
-    __syncthreads();
-    if (i0 + IC < H) load_chunk(i0 + IC, true);          // in flight during the sums
-#pragma unroll 2
-    for (int ii = ig; ii < IC; ii += 8) {
-      const float t = tl[ii][c];
+    float sv[PER];
 #pragma unroll
-      for (int k = 0; k < MM; ++k) acc[k] = fmaf(syl[k][ii], t, acc[k]);
+    for (int u = 0; u < PER; ++u) {
+      const int e = threadIdx.x + 256 * u, r = e / IC, ii = e % IC;
+      sv[u] = Sy[(size_t)(k0 + min(r, klast)) * H + min(i0 + ii, H - 1)];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+      const int e = threadIdx.x + 256 * u, r = e / IC, ii = e % IC;
+      syl[r][ii] = (r <= klast && i0 + ii < H) ? sv[u] : 0.f;
+    }
+    __syncthreads();
+    const int ia = i0 + w * IQ;
+#pragma unroll 1
+    for (int ib = 0; ib < IQ; ib += NB) {
+      float tv[NB];
+#pragma unroll
+      for (int u = 0; u < NB; ++u) tv[u] = tb[(size_t)min(ia + ib + u, H - 1) * LQ];
+#pragma unroll
+      for (int u = 0; u < NB; ++u)
+#pragma unroll
+        for (int r = 0; r < KB; ++r) s[r] = fmaf(syl[r][w * IQ + ib + u], tv[u], s[r]);
     }
   }
 #pragma unroll
-  for (int k = 0; k < MM; ++k) part[ig][k][c] = acc[k];
-  // the mixing weights of this thread's modes k = ig, ig + 8, ... as 32-bit
-  // words (forward: w[k][l][c][0..31], contiguous; BWD: w[k][l][m][c], the word
-  // holding element c of row m)
-  constexpr int KPT = MM / 8;
-  uint32_t wv[KPT][C / 2 > 16 ? 16 : C / 2];
+  for (int r = 0; r < KB; ++r) part[w][r][lane] = s[r];
+  __syncthreads();
+  for (int e = threadIdx.x; e < KB * 64; e += 256) {
+    const int r = e / 64, ln = e % 64, qq = qb * 64 + ln;
+    if (r > klast || qq >= LQ) continue;
+    const float v = ((part[0][r][ln] + part[1][r][ln]) + part[2][r][ln]) + part[3][r][ln];
+    X[((size_t)b * M + k0 + r) * LQ + qq] = scale * v;
+  }
+}
+
+// Mode mixing and inverse column transform of the spectral layer, one
+// workgroup per (b, l, block of 64 rows), l the mode along x:
+//   Y[k][n] = sum_m w[k][l][n][m] X[b][k][l][m]   (BWD: the transpose w[k][l][m][n])
+//   Z[b][i][l][n] = alpha sum_k Sy[k][i] Y[k][n]  for the block's rows i.
+// Every workgroup of a (b, l) forms the same Y (a few thousand operations),
+// so that the rows spread over many workgroups.
+template <int C, bool BWD>
+__global__ __launch_bounds__(256) void k_spec_minv(const float* X, const bf16* wk, const float* Sy,
+                                                   float* Z, int H, int M, float alpha) {
+  static_assert(C == 32, "a channel per lane of a half-wavefront");
+  constexpr int MM = 32, RB = 64, KPT = MM / 8;
+  __shared__ float xl[MM][C];
+  __shared__ float yl[MM][C];
+  __shared__ float syl[MM][RB];
+  const int nrb = (H + RB - 1) / RB;
+  const int rb = blockIdx.x % nrb, bl = blockIdx.x / nrb;
+  const int b = bl / M, l = bl % M, i0 = rb * RB;
+  const int c = threadIdx.x & 31, ig = threadIdx.x >> 5;
+  // X[b][k][l][:] and Sy[k][i0 .. i0 + 63] (zero past M or H), and this
+  // thread's mixing weights, all loads issued together
+  float xv[KPT], sv[MM * RB / 256];
+#pragma unroll
+  for (int u = 0; u < KPT; ++u) {
+    const int k = ig + 8 * u;
+    xv[u] = X[(((size_t)b * M + min(k, M - 1)) * M + l) * C + c];
+  }
+#pragma unroll
+  for (int u = 0; u < MM * RB / 256; ++u) {
+    const int e = threadIdx.x + 256 * u, k = e / RB, ii = e % RB;
+    sv[u] = Sy[(size_t)min(k, M - 1) * H + min(i0 + ii, H - 1)];
+  }
+  uint32_t wv[KPT][16];
   uint32_t wb[KPT][C];
 #pragma unroll
-  for (int q = 0; q < KPT; ++q) {
-    const int k = min(ig + 8 * q, M - 1);
+  for (int u = 0; u < KPT; ++u) {
+    const int k = min(ig + 8 * u, M - 1);
     const bf16* wp = wk + ((size_t)k * M + l) * C * C;
     if constexpr (!BWD) {
 #pragma unroll
       for (int h = 0; h < 4; ++h) {
         const uint4 u4 = reinterpret_cast<const uint4*>(wp + c * C)[h];
-        wv[q][4 * h] = u4.x;
-        wv[q][4 * h + 1] = u4.y;
-        wv[q][4 * h + 2] = u4.z;
-        wv[q][4 * h + 3] = u4.w;
+        wv[u][4 * h] = u4.x;
+        wv[u][4 * h + 1] = u4.y;
+        wv[u][4 * h + 2] = u4.z;
+        wv[u][4 * h + 3] = u4.w;
       }
     } else {
 #pragma unroll
-      for (int m = 0; m < C; ++m) wb[q][m] = *reinterpret_cast<const uint32_t*>(wp + m * C + (c & ~1));
+      for (int m = 0; m < C; ++m) wb[u][m] = *reinterpret_cast<const uint32_t*>(wp + m * C + (c & ~1));
     }
   }
-  __syncthreads();
-  // X = scale * (fixed-order sum of the row groups)
-  for (int e = threadIdx.x; e < M * C; e += 256) {
-    const int k = e / C, cc = e % C;
-    float s = part[0][k][cc];
 #pragma unroll
-    for (int g = 1; g < 8; ++g) s += part[g][k][cc];
-    s *= scale;
-    part[0][k][cc] = s;
-    Xs[(((size_t)b * M + k) * M + l) * C + cc] = s;
+  for (int u = 0; u < KPT; ++u) {
+    const int k = ig + 8 * u;
+    xl[k][c] = k < M ? xv[u] : 0.f;
   }
-  load_chunk(0, false);                                  // the inverse transform's first chunk
-  __syncthreads();
-  // ---- mixing: thread (n = c, modes k = ig + 8 q)
 #pragma unroll
-  for (int q = 0; q < KPT; ++q) {
-    const int k = ig + 8 * q;
-    if (k >= M) break;                                   // uniform within the half-wavefront
+  for (int u = 0; u < MM * RB / 256; ++u) {
+    const int e = threadIdx.x + 256 * u, k = e / RB, ii = e % RB;
+    syl[k][ii] = (k < M && i0 + ii < H) ? sv[u] : 0.f;
+  }
+  __syncthreads();
+  // mixing: thread (n = c, modes k = ig + 8 u)
+#pragma unroll
+  for (int u = 0; u < KPT; ++u) {
+    const int k = ig + 8 * u;
     float y = 0.f;
 #pragma unroll
     for (int m = 0; m < C; ++m) {
       float wf;
       if constexpr (!BWD) {
-        const uint32_t wd = wv[q][m >> 1];
+        const uint32_t wd = wv[u][m >> 1];
         wf = __uint_as_float((m & 1) ? (wd & 0xffff0000u) : (wd << 16));
       } else {
-        const uint32_t wd = wb[q][m];
+        const uint32_t wd = wb[u][m];
         wf = __uint_as_float((c & 1) ? (wd & 0xffff0000u) : (wd << 16));
       }
-      y = fmaf(wf, part[0][k][m], y);
+      y = fmaf(wf, xl[k][m], y);
     }
-    Yl[k][c] = y;
+    yl[k][c] = k < M ? y : 0.f;
   }
   __syncthreads();
   float yv[MM];
 #pragma unroll
-  for (int k = 0; k < MM; ++k) yv[k] = k < M ? Yl[k][c] : 0.f;
-  // ---- inverse column transform
-  for (int i0 = 0; i0 < H; i0 += IC) {
-    __syncthreads();
-    store_chunk(i0, false);
-    __syncthreads();
-    if (i0 + IC < H) load_chunk(i0 + IC, false);
-    for (int ii = ig; ii < IC && i0 + ii < H; ii += 8) {
-      float z = 0.f;
+  for (int k = 0; k < MM; ++k) yv[k] = yl[k][c];
+  const size_t tstride = (size_t)M * C;
+  float* zb = Z + ((size_t)b * H * M + l) * C + c;
+#pragma unroll 2
+  for (int ii = ig; ii < RB; ii += 8) {
+    if (i0 + ii >= H) break;
+    float z = 0.f;
 #pragma unroll
-      for (int k = 0; k < MM; ++k) z = fmaf(syl[k][ii], yv[k], z);
-      Z[base + (size_t)(i0 + ii) * tstride + c] = alpha * z;
-    }
+    for (int k = 0; k < MM; ++k) z = fmaf(syl[k][ii], yv[k], z);
+    zb[(size_t)(i0 + ii) * tstride] = alpha * z;
   }
 }
 
@@ -1781,14 +1804,21 @@ __global__ __launch_bounds__(256) void k_gate_sums(const float* c, const float* 
 // follows the branch as it trains.
 constexpr double kGateDecay = 0.9;
 __global__ void k_gate_fin(const double* part, int nblk, double* gate, int B) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  // one wavefront: lane l sums partials l, l + 64, ... in order, then the
+  // lanes are added in a fixed tree
+  const int lane = threadIdx.x & 63;
+  if (blockIdx.x != 0 || threadIdx.x >= 64) return;
   double cc = 0.0, cd = 0.0;
-  for (int b = 0; b < nblk; ++b) {
+  for (int b = lane; b < nblk; b += 64) {
     cc += part[2 * b];
     cd += part[2 * b + 1];
   }
-  gate[0] = kGateDecay * gate[0] + (cc - 0.5 * B * cd);
-  gate[1] = kGateDecay * gate[1] + cc;
+  cc = wave_sum(cc);
+  cd = wave_sum(cd);
+  if (lane == 0) {
+    gate[0] = kGateDecay * gate[0] + (cc - 0.5 * B * cd);
+    gate[1] = kGateDecay * gate[1] + cc;
+  }
 }
 
 // The exact training pair of the band for the correction d = u_t - u_prev:
@@ -1971,8 +2001,9 @@ void forward(const Net& n, const Ptrs& f, const Ptrs& u, hipStream_t s, bool gat
   float* Z = n.w<float>(n.wl.Z);
   k_spec_rows<C><<<d.B * d.H, 256, 0, s>>>(a[1], n.w<bf16>(n.wl.Sxh), n.w<bf16>(n.wl.Sxl), T, d.W,
                                            WP, d.M);
-  k_spec_mid<C, false><<<d.B * d.M, 256, 0, s>>>(T, Sy, n.bfw(T_SWK), X, Z, d.H, d.M, 1.f,
-                                                 (float)(2.0 / (d.H + 1)));
+  k_spec_cols<<<d.B * cdiv(d.M, 8) * cdiv(d.M * C, 64), 256, 0, s>>>(T, Sy, X, d.H, d.M, d.M * C, 1.f);
+  k_spec_minv<C, false><<<d.B * d.M * cdiv(d.H, 64), 256, 0, s>>>(X, n.bfw(T_SWK), Sy, Z, d.H, d.M,
+                                                                  (float)(2.0 / (d.H + 1)));
   launch_spec_out<C, false>(dim3(d.B * d.H * cdiv(d.W, 64)), s, a[1], n.bfw(T_SW1), n.bfw(T_SB), Z, Sx,
                             nullptr, a[2], d.W, WP, d.M, (float)(2.0 / (d.W + 1)));
   // L4, L5, L6
@@ -2087,7 +2118,8 @@ void train(const Net& n, const Ptrs& f, const Ptrs& up, const Ptrs& ut, float* l
   const int WP = spec_wp(d);
   k_spec_rows<C><<<d.B * d.H, 256, 0, s>>>(dz[0], n.w<bf16>(n.wl.Sxh), n.w<bf16>(n.wl.Sxl), T, d.W,
                                            WP, d.M);
-  k_spec_mid<C, true><<<d.B * d.M, 256, 0, s>>>(T, Sy, n.bfw(T_SWK), dY, Z, d.H, d.M, nrm, 1.f);
+  k_spec_cols<<<d.B * cdiv(d.M, 8) * cdiv(d.M * C, 64), 256, 0, s>>>(T, Sy, dY, d.H, d.M, d.M * C, nrm);
+  k_spec_minv<C, true><<<d.B * d.M * cdiv(d.H, 64), 256, 0, s>>>(dY, n.bfw(T_SWK), Sy, Z, d.H, d.M, 1.f);
   k_spec_dwk<<<cdiv((long long)d.M * d.M * C * C, 256), 256, 0, s>>>(dY, X, n.grad(T_SWK), d.B, d.M, C);
   launch_spec_out<C, true>(dim3(d.B * d.H * cdiv(d.W, 64)), s, dz[0], n.bfw(T_SW1), nullptr, Z, Sx,
                            a[1], dz[1], d.W, WP, d.M, 1.f);
