@@ -755,23 +755,39 @@ __global__ __launch_bounds__(256) void k_conv_mfma(const bf16* in, const bf16* w
   constexpr int TX = kConvTX, TY = kConvTY, LX = TX + 2, LY = TY + 2;
   constexpr int CH = C / 8;                              // 16-byte chunks per pixel
   constexpr int NLD = (LY * LX * CH + 255) / 256;        // staged chunks per thread
+  constexpr bool EPI = (DGRAD && !RES) || RES;           // the epilogue reads `mask`
   __shared__ __attribute__((aligned(16))) bf16 tin[LY * LX * C];
+  // weights: A[i = output channel mt*16 + li][k = input channel lg*8 + e] of
+  // tap t (32-bit word reads).  With a masked epilogue they are gathered once
+  // per workgroup into LDS and read per row (the registers hold the masks);
+  // the forward keeps them in registers for the whole launch.
+  __shared__ uint4 wfr[EPI ? 9 : 1][2][64];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int li = lane & 15, lg = lane >> 4;
-  // weights: A[i = output channel mt*16 + li][k = input channel lg*8 + e] of tap t
-  bf16x8 wa[9][2];
+  auto frag = [&](int t, int mt, int ln) {
+    const int co = mt * 16 + (ln & 15), cb = (ln >> 4) * 8;
+    uint32_t h[8];
 #pragma unroll
-  for (int t = 0; t < 9; ++t)
-#pragma unroll
-    for (int mt = 0; mt < 2; ++mt) {
-      bf16 v[8];
-#pragma unroll
-      for (int e = 0; e < 8; ++e) {
-        const int co = mt * 16 + li, ci = lg * 8 + e;
-        v[e] = DGRAD ? wt[(ci * C + co) * 9 + (8 - t)] : wt[(co * C + ci) * 9 + t];
-      }
-      wa[t][mt] = __builtin_bit_cast(bf16x8, v);
+    for (int q = 0; q < 8; ++q) {
+      const int ci = cb + q;
+      h[q] = bf16_word_pick(wt, DGRAD ? (long long)(ci * C + co) * 9 + (8 - t) : (long long)(co * C + ci) * 9 + t);
     }
+    return make_uint4(h[0] | (h[1] << 16), h[2] | (h[3] << 16), h[4] | (h[5] << 16), h[6] | (h[7] << 16));
+  };
+  bf16x8 wa[EPI ? 1 : 9][2];
+  if constexpr (EPI) {
+    for (int e = threadIdx.x; e < 9 * 2 * 64; e += 256) wfr[e / 128][(e / 64) % 2][e % 64] = frag(e / 128, (e / 64) % 2, e % 64);
+  } else {
+#pragma unroll
+    for (int t = 0; t < 9; ++t)
+#pragma unroll
+      for (int mt = 0; mt < 2; ++mt) {
+        bf16 v[8];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) v[e] = wt[((mt * 16 + li) * C + lg * 8 + e) * 9 + t];
+        wa[t][mt] = __builtin_bit_cast(bf16x8, v);
+      }
+  }
   float bl[2][4];
 #pragma unroll
   for (int mt = 0; mt < 2; ++mt)
@@ -807,13 +823,38 @@ __global__ __launch_bounds__(256) void k_conv_mfma(const bf16* in, const bf16* w
       if (e < LY * LX * CH) *reinterpret_cast<uint4*>(&tin[e * 8]) = pre[k];
     }
     __syncthreads();
-    const int next = tile + gridDim.x;
-    if (next < ntiles) fetch(next, pre);                 // in flight during the MFMAs
     const int b = tile / per_img, r0 = tile % per_img;
     const int ox = (r0 % tilesx) * TX, oy = (r0 / tilesx) * TY;
-    // one output row at a time (the weights stay in registers across rows)
+    // the epilogue's mask (or residual) of both rows, read before the next
+    // tile's loads so that waiting for it leaves those in flight (clamped
+    // positions; entries outside the grid are never used)
+    uint2 mk[2][4][2];
+    if constexpr (EPI) {
+      if (mask) {
+#pragma unroll
+        for (int r2 = 0; r2 < 2; ++r2) {
+          const int y = min(oy + wv * 2 + r2, H - 1);
+#pragma unroll
+          for (int nt = 0; nt < 4; ++nt) {
+            const int x = min(ox + nt * 16 + li, W - 1);
+            const size_t base = ((size_t)b * HW + (long long)y * W + x) * C;
+#pragma unroll
+            for (int mt = 0; mt < 2; ++mt) mk[r2][nt][mt] = *reinterpret_cast<const uint2*>(mask + base + mt * 16 + lg * 4);
+          }
+        }
+      }
+    }
+    const int next = tile + gridDim.x;
+    if (next < ntiles) fetch(next, pre);                 // in flight during the MFMAs
+    // one output row at a time (its accumulators only); the row's masks are
+    // picked by a select, so both rows' stay in registers
 #pragma unroll 1
     for (int r2 = 0; r2 < 2; ++r2) {
+      // with a masked epilogue, an index the compiler cannot see to be
+      // `lane`, so that the weight fragments are read from LDS per row (the
+      // registers hold the masks); the forward keeps them in registers
+      int wl = lane;
+      if constexpr (EPI) asm volatile("" : "+v"(wl));
       floatx4 acc[4][2];
 #pragma unroll
       for (int nt = 0; nt < 4; ++nt)
@@ -822,14 +863,21 @@ __global__ __launch_bounds__(256) void k_conv_mfma(const bf16* in, const bf16* w
 #pragma unroll
       for (int t = 0; t < 9; ++t) {
         const int ly = wv * 2 + r2 + t / 3, kx = t % 3;
+        bf16x8 wa0, wa1;
+        if constexpr (EPI) {
+          wa0 = __builtin_bit_cast(bf16x8, wfr[t][0][wl]);
+          wa1 = __builtin_bit_cast(bf16x8, wfr[t][1][wl]);
+        } else {
+          wa0 = wa[t][0];
+          wa1 = wa[t][1];
+        }
 #pragma unroll
         for (int nt = 0; nt < 4; ++nt) {
           const int lx = nt * 16 + li + kx;
           const bf16x8 bx = __builtin_bit_cast(
               bf16x8, *reinterpret_cast<const uint4*>(&tin[(ly * LX + lx) * C + lg * 8]));
-#pragma unroll
-          for (int mt = 0; mt < 2; ++mt)
-            acc[nt][mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa[t][mt], bx, acc[nt][mt], 0, 0, 0);
+          acc[nt][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa0, bx, acc[nt][0], 0, 0, 0);
+          acc[nt][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa1, bx, acc[nt][1], 0, 0, 0);
         }
       }
       // epilogue: lane holds channels mt*16 + lg*4 + r (r < 4) of pixel nt*16 + li
@@ -845,8 +893,8 @@ __global__ __launch_bounds__(256) void k_conv_mfma(const bf16* in, const bf16* w
           float v[4];
           float m4[4] = {0.f, 0.f, 0.f, 0.f};
           // the ReLU mask of the input gradient, or the residual (optional)
-          if ((DGRAD && !RES) || (RES && mask)) {
-            const uint2 mu = *reinterpret_cast<const uint2*>(mask + o);
+          if (EPI && mask) {
+            const uint2 mu = r2 ? mk[1][nt][mt] : mk[0][nt][mt];
             m4[0] = __uint_as_float(mu.x << 16);
             m4[1] = __uint_as_float(mu.x & 0xffff0000u);
             m4[2] = __uint_as_float(mu.y << 16);
@@ -914,15 +962,58 @@ __global__ __launch_bounds__(256) void k_wgrad_mfma(const bf16* in, const bf16* 
     const int ox = (r0 % tilesx) * TX, oy = (r0 / tilesx) * TY;
     const bf16* dzb = dz + (size_t)b * HW * C;
     const bf16* inb = in + (size_t)b * HW * C;
-    __syncthreads();
+    // Every global load of the tile is issued before the first LDS write, at
+    // clamped positions (values outside the grid replaced by zero).
     // dz^T: a unit = two adjacent pixels x 8 channels -> 8 channel rows, one dword each
-    for (int u = threadIdx.x; u < (NP / 2) * CH; u += 256) {
+    constexpr int UD = (NP / 2) * CH / 256;              // dz units per thread
+    constexpr int NUI = NTAP == 9 ? LY * 33 * CH : TY * 32 * CH;
+    constexpr int UI = (NUI + 255) / 256;                // input units per thread
+    constexpr int LI = NTAP == 9 ? 3 : 2;                // loads per input unit
+    static_assert((NP / 2) * CH % 256 == 0, "whole dz units per thread");
+    uint4 dv[UD][2], iv[UI][LI];
+#pragma unroll
+    for (int s = 0; s < UD; ++s) {
+      const int u = threadIdx.x + 256 * s;
+      const int pr = u / CH, ch = u % CH;
+      const int q = 2 * pr, qy = q / TX, qx = q % TX;
+      const int gy = min(oy + qy, H - 1);
+#pragma unroll
+      for (int e = 0; e < 2; ++e) {
+        const int gx = min(ox + qx + e, W - 1);
+        dv[s][e] = *reinterpret_cast<const uint4*>(dzb + ((long long)gy * W + gx) * C + ch * 8);
+      }
+    }
+#pragma unroll
+    for (int s = 0; s < UI; ++s) {
+      const int u = min(threadIdx.x + 256 * s, NUI - 1);
+      const int ch = u % CH;
+      if constexpr (NTAP == 9) {
+        const int rk = u / CH, ly = rk / 33, k = rk % 33;
+        const int gy = min(max(oy + ly - 1, 0), H - 1);
+#pragma unroll
+        for (int e = 0; e < 3; ++e) {
+          const int gx = min(max(ox + 2 * k + e - 1, 0), W - 1);
+          iv[s][e] = *reinterpret_cast<const uint4*>(inb + ((long long)gy * W + gx) * C + ch * 8);
+        }
+      } else {
+        const int rk = u / CH, r = rk / 32, k = rk % 32;
+        const int gy = min(oy + r, H - 1);
+#pragma unroll
+        for (int e = 0; e < 2; ++e) {
+          const int gx = min(ox + 2 * k + e, W - 1);
+          iv[s][e] = *reinterpret_cast<const uint4*>(inb + ((long long)gy * W + gx) * C + ch * 8);
+        }
+      }
+    }
+    __syncthreads();                                     // the previous tile's readers are done
+#pragma unroll
+    for (int s = 0; s < UD; ++s) {
+      const int u = threadIdx.x + 256 * s;
       const int pr = u / CH, ch = u % CH;
       const int q = 2 * pr, qy = q / TX, qx = q % TX;
       const int gy = oy + qy, gx = ox + qx;
-      uint4 v0 = make_uint4(0, 0, 0, 0), v1 = v0;
-      if (gy < H && gx < W) v0 = *reinterpret_cast<const uint4*>(dzb + ((long long)gy * W + gx) * C + ch * 8);
-      if (gy < H && gx + 1 < W) v1 = *reinterpret_cast<const uint4*>(dzb + ((long long)gy * W + gx + 1) * C + ch * 8);
+      const uint4 z = make_uint4(0, 0, 0, 0);
+      const uint4 v0 = (gy < H && gx < W) ? dv[s][0] : z, v1 = (gy < H && gx + 1 < W) ? dv[s][1] : z;
       const uint32_t a0[4] = {v0.x, v0.y, v0.z, v0.w}, a1[4] = {v1.x, v1.y, v1.z, v1.w};
 #pragma unroll
       for (int h = 0; h < 4; ++h) {
@@ -936,13 +1027,36 @@ __global__ __launch_bounds__(256) void k_wgrad_mfma(const bf16* in, const bf16* 
     // unit.  3x3: halo columns -1..64 of rows -1..TY: copy 0 holds halo column
     // h at position h, copy 1 at position h - 1; a unit = halo columns 2k,
     // 2k+1, 2k+2 of one row x 8 channels.
-    if constexpr (NTAP == 1) {
-      for (int u = threadIdx.x; u < TY * 32 * CH; u += 256) {
-        const int ch = u % CH, rk = u / CH, r = rk / 32, k = rk % 32;
+#pragma unroll
+    for (int s = 0; s < UI; ++s) {
+      const int u = threadIdx.x + 256 * s;
+      if (u >= NUI) break;
+      const int ch = u % CH;
+      const uint4 z = make_uint4(0, 0, 0, 0);
+      if constexpr (NTAP == 9) {
+        const int rk = u / CH, ly = rk / 33, k = rk % 33;
+        const int gy = oy + ly - 1;
+        uint4 v[3];
+#pragma unroll
+        for (int e = 0; e < 3; ++e) {
+          const int gx = ox + 2 * k + e - 1;
+          v[e] = (2 * k + e < TX + 2 && gy >= 0 && gy < H && gx >= 0 && gx < W) ? iv[s][e] : z;
+        }
+        const uint32_t w0[4] = {v[0].x, v[0].y, v[0].z, v[0].w}, w1[4] = {v[1].x, v[1].y, v[1].z, v[1].w},
+                       w2[4] = {v[2].x, v[2].y, v[2].z, v[2].w};
+#pragma unroll
+        for (int h = 0; h < 4; ++h) {
+          const int c0 = ch * 8 + 2 * h;
+          const int o = ly * PX + 2 * k;
+          *reinterpret_cast<uint32_t*>(&inT[0][c0 * PC + o]) = (w0[h] & 0xffffu) | (w1[h] << 16);
+          *reinterpret_cast<uint32_t*>(&inT[0][(c0 + 1) * PC + o]) = (w0[h] >> 16) | (w1[h] & 0xffff0000u);
+          *reinterpret_cast<uint32_t*>(&inT[1][c0 * PC + o]) = (w1[h] & 0xffffu) | (w2[h] << 16);
+          *reinterpret_cast<uint32_t*>(&inT[1][(c0 + 1) * PC + o]) = (w1[h] >> 16) | (w2[h] & 0xffff0000u);
+        }
+      } else {
+        const int rk = u / CH, r = rk / 32, k = rk % 32;
         const int gy = oy + r, gx = ox + 2 * k;
-        uint4 v1 = make_uint4(0, 0, 0, 0), v2 = v1;
-        if (gy < H && gx < W) v1 = *reinterpret_cast<const uint4*>(inb + ((long long)gy * W + gx) * C + ch * 8);
-        if (gy < H && gx + 1 < W) v2 = *reinterpret_cast<const uint4*>(inb + ((long long)gy * W + gx + 1) * C + ch * 8);
+        const uint4 v1 = (gy < H && gx < W) ? iv[s][0] : z, v2 = (gy < H && gx + 1 < W) ? iv[s][1] : z;
         const uint32_t w1[4] = {v1.x, v1.y, v1.z, v1.w}, w2[4] = {v2.x, v2.y, v2.z, v2.w};
 #pragma unroll
         for (int h = 0; h < 4; ++h) {
@@ -950,29 +1064,6 @@ __global__ __launch_bounds__(256) void k_wgrad_mfma(const bf16* in, const bf16* 
           *reinterpret_cast<uint32_t*>(&inT[1][c0 * PC + o]) = (w1[h] & 0xffffu) | (w2[h] << 16);
           *reinterpret_cast<uint32_t*>(&inT[1][(c0 + 1) * PC + o]) = (w1[h] >> 16) | (w2[h] & 0xffff0000u);
         }
-      }
-    }
-    for (int u = threadIdx.x; NTAP == 9 && u < LY * 33 * CH; u += 256) {
-      const int ch = u % CH, rk = u / CH, ly = rk / 33, k = rk % 33;
-      const int gy = oy + ly - 1;
-      uint4 v[3];
-#pragma unroll
-      for (int e = 0; e < 3; ++e) {
-        const int gx = ox + 2 * k + e - 1;
-        v[e] = make_uint4(0, 0, 0, 0);
-        if (2 * k + e < TX + 2 && gy >= 0 && gy < H && gx >= 0 && gx < W)
-          v[e] = *reinterpret_cast<const uint4*>(inb + ((long long)gy * W + gx) * C + ch * 8);
-      }
-      const uint32_t w0[4] = {v[0].x, v[0].y, v[0].z, v[0].w}, w1[4] = {v[1].x, v[1].y, v[1].z, v[1].w},
-                     w2[4] = {v[2].x, v[2].y, v[2].z, v[2].w};
-#pragma unroll
-      for (int h = 0; h < 4; ++h) {
-        const int c0 = ch * 8 + 2 * h;
-        const int o = ly * PX + 2 * k;
-        *reinterpret_cast<uint32_t*>(&inT[0][c0 * PC + o]) = (w0[h] & 0xffffu) | (w1[h] << 16);
-        *reinterpret_cast<uint32_t*>(&inT[0][(c0 + 1) * PC + o]) = (w0[h] >> 16) | (w1[h] & 0xffff0000u);
-        *reinterpret_cast<uint32_t*>(&inT[1][c0 * PC + o]) = (w1[h] & 0xffffu) | (w2[h] << 16);
-        *reinterpret_cast<uint32_t*>(&inT[1][(c0 + 1) * PC + o]) = (w1[h] >> 16) | (w2[h] & 0xffff0000u);
       }
     }
     __syncthreads();
