@@ -68,6 +68,10 @@ def parse():
     ap.add_argument("--no-scale", action="store_true", help="skip the large-size rooflines")
     ap.add_argument("--batched-cycles", type=int, default=3,
                     help="restart cycles per system in the batched leg")
+    ap.add_argument("--no-config3", action="store_true",
+                    help="skip the mixed-precision configuration's solves to 1e-10 (160^3, 2048^2)")
+    ap.add_argument("--records", default=None, metavar="PATH",
+                    help="write every right-hand side's record of the stream as a JSON line")
     ap.add_argument("--json-out", default=None)
     ap.add_argument("--probe", default=None, metavar="KERNEL",
                     help="counter-collection run: a 256 MiB device copy (the byte-count "
@@ -187,6 +191,64 @@ def scale_rooflines(mlg, seed):
         out[key] = r
         del b
         torch.cuda.empty_cache()
+    return out
+
+
+def config3_leg(mlg, seed, budget_2d=20000):
+    """The mixed-precision configuration solved to rel. residual 1e-10: FP32
+    Krylov basis (GMRES(40), FP64 refinement) and, for the error the FP32
+    path leaves, the FP64 basis on the same right-hand side.  160^3 runs to
+    the tolerance; 2048^2 needs of the order of 10^5-10^6 restarted steps, so
+    it runs a budget of steps and reports the residual reached and a
+    projection of the steps to 1e-10 from the measured reduction per restart
+    cycle (labelled as such)."""
+    import math
+    from synthetic import DriftingGaussians
+    out = {}
+    shape = (160, 160, 160)
+    b = torch.from_numpy(DriftingGaussians(shape, 5, 0.03, seed=seed + 3).field(0)).cuda()
+    grid = mlg.grid_of(shape)
+    res = {}
+    for name, prec in (("fp32_basis", mlg.MLG_FP32_IR), ("fp64_basis", mlg.MLG_FP64)):
+        opts = mlg.Opts(restart_m=40, precision=prec, rtol=1e-10)
+        mlg.mlg_autotune(grid, opts)
+        ws = mlg.workspace(mlg.gmres_workspace_bytes(grid, opts))
+        x = torch.zeros_like(b)
+        st = mlg.gmres_solve(grid, b, x, opts, ws)
+        res[name] = (x, st)
+        del ws
+    x32, s32 = res["fp32_basis"]
+    x64, s64 = res["fp64_basis"]
+    out["160x160x160"] = {
+        "workload": "3D 7-point Poisson 160^3, 5 drifting Gaussians (sigma 0.03), GMRES(40), rtol 1e-10",
+        "fp32_basis": {"iters": s32.iters, "cycles": s32.cycles, "seconds": s32.seconds,
+                       "relres_true": s32.relres_true},
+        "fp64_basis": {"iters": s64.iters, "cycles": s64.cycles, "seconds": s64.seconds,
+                       "relres_true": s64.relres_true},
+        "fp32_vs_fp64_rel_error": float((x32 - x64).norm() / x64.norm()),
+        "speedup_fp32_basis": s64.seconds / s32.seconds}
+    del res, x32, x64, b
+    torch.cuda.empty_cache()
+    shape = (2048, 2048)
+    b = torch.from_numpy(DriftingGaussians(shape, 5, 0.02, seed=seed + 3).field(0)).cuda()
+    grid = mlg.grid_of(shape)
+    opts = mlg.Opts(restart_m=40, precision=mlg.MLG_FP32_IR, rtol=1e-10, max_iters=budget_2d)
+    mlg.mlg_autotune(grid, opts)
+    ws = mlg.workspace(mlg.gmres_workspace_bytes(grid, opts))
+    x = torch.zeros_like(b)
+    st = mlg.gmres_solve(grid, b, x, opts, ws, allow_not_converged=True)
+    rate = st.relres_true ** (1.0 / max(1, st.cycles))        # mean reduction per cycle
+    proj = (math.log(1e-10) / math.log(rate)) * 40 if 0.0 < rate < 1.0 else None
+    out["2048x2048"] = {
+        "workload": "2D 5-point Poisson 2048^2, 5 drifting Gaussians (sigma 0.02), GMRES(40), "
+                    f"FP32 basis, a budget of {budget_2d} steps",
+        "iters": st.iters, "cycles": st.cycles, "seconds": st.seconds,
+        "relres_true": st.relres_true, "ms_per_step": 1e3 * st.seconds / max(1, st.iters),
+        "projected_steps_to_1e-10": proj,
+        "projected_seconds_to_1e-10": proj * st.seconds / max(1, st.iters) if proj else None,
+        "projection": "steps = 40 log(1e-10) / log(mean reduction per cycle over the budget)"}
+    del ws, x, b
+    torch.cuda.empty_cache()
     return out
 
 
@@ -433,6 +495,13 @@ def main():
     elapsed = time.perf_counter() - t0
     timed = sv.records[t_timed:]
     tos_learned = statistics.fmean(r.tos for r in timed)
+    if args.records:
+        import dataclasses
+        with open(args.records, "w") as fh:
+            for r in sv.records:
+                fh.write(json.dumps({"phase": "learn" if r.t < t_warm else
+                                     ("warmup" if r.t < t_timed else "timed"),
+                                     **dataclasses.asdict(r)}) + "\n")
     learn = sv.records[:t_warm]
     K = sv.net_cfg.skip_modes
     w = mlg.net_band_weights(sv.net_cfg, sv.params).cpu().numpy()
@@ -512,6 +581,9 @@ def main():
         result["roofline_at_scale"] = scale_rooflines(mlg, args.seed)
         print(json.dumps({"progress": "large-size rooflines done"}), flush=True)
 
+    if not args.no_config3:
+        result["config3"] = config3_leg(mlg, args.seed)
+        print(json.dumps({"progress": "mixed-precision configuration done"}), flush=True)
     if not args.no_batched:
         result["batched"] = batched_leg(mlg, args.seed, args.batched_cycles)
 
