@@ -6,12 +6,13 @@ previous solution u_{t-1}, and from the learned guess (network trained one step
 per solved pair on the replay buffer).  Measured over steps [100, 200):
 
 * the previous solution beats the zero guess in iterations, and the learned
-  guess needs well under the previous solution's count (measured 2041 vs
-  5352; the skip gains are still converging over this window);
+  guess needs well under the previous solution's count (measured 10 vs
+  5352: the band path's least-squares weights on exact training pairs are
+  right after the first batches);
 * the trained network removes nearly all of the slow-mode error of u_{t-1}
   (its projection on the 16 x 16 slowest sine modes of the Dirichlet
   Laplacian -- the error restarted GMRES converges slowest on): measured
-  832x.
+  5e9x.
 
 The paper prints no iteration counts for this network or workload, so the
 sizes of these gains are measured and printed, not pinned.
@@ -80,8 +81,8 @@ def test_algorithm1_schedule(mlg):
     first 50 steps trains the network, then only under-performing steps feed
     the candidate set and trigger retraining.  On the same stream the trained
     guess needs well under the previous solution's iterations (measured over
-    [80, 140): 64 vs 5273), the candidate set takes a fraction of the judged
-    steps (measured 19 of 90), and every retraining is counted."""
+    [80, 140): 9 vs 5273), the candidate set takes a fraction of the judged
+    steps (measured 30 of 90), and every retraining is counted."""
     from paper_2103_10975_amd.stream import StreamSolver
     print("stream algorithm1", flush=True)
     n, steps, w0 = 256, 140, 80
