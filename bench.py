@@ -173,7 +173,7 @@ def scale_rooflines(mlg, seed):
                                        ((2048, 2048), mlg.MLG_FP32_IR, 40, 5, 0.02),
                                        ((160, 160, 160), mlg.MLG_FP32_IR, 40, 5, 0.03)]:
         opts = mlg.Opts(restart_m=m, precision=prec, rtol=1e-10)
-        tile, fused, split = mlg.mlg_autotune(mlg.grid_of(shape), opts)
+        tile, fused, split, _ = mlg.mlg_autotune(mlg.grid_of(shape), opts)
         b = torch.from_numpy(DriftingGaussians(shape, src, sigma, seed=seed).field(0)).cuda()
         kr = kernel_roofline(mlg, shape, opts, b, tile, fused, split, reps=10)
         r = roofline_of(kr)
@@ -557,9 +557,10 @@ def main():
         print(json.dumps({"progress": "legs done"}), flush=True)
 
     # roofline of the dominant kernel of the learned-guess solve
-    tile, fused, split = sv.tuned
+    tile, fused, split, launch = sv.tuned
     tshape = mlg.mlg_tile_shape(2, tile - 1)
     result["config"]["tile"] = list(tshape)
+    result["config"]["launch"] = "direct" if launch == 2 else "graph"
     result["config"]["fused_steps"] = bin(fused).count("1")
     result["config"]["split_steps"] = bin(split).count("1")
     kr = kernel_roofline(mlg, shape, sv.opts, fields[0], tile, fused, split)
@@ -653,7 +654,7 @@ def probe(mlg, shape, args):
             allm = (1 << int(m)) - 1 if args.probe in ("step", "sums") and len(shape) == 2 else 0
             runs = [(args.probe_tile, allm, allm)]
         else:
-            runs = [mlg.mlg_autotune(mlg.grid_of(shape), opts)]
+            runs = [mlg.mlg_autotune(mlg.grid_of(shape), opts)[:3]]
     else:
         opts = mlg.Opts(restart_m=args.restart, rtol=args.rtol, precision=mlg.MLG_FP32_IR)
         fused = (1 << args.restart) - 1 if args.probe in ("step", "sums") else 0

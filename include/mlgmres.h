@@ -79,6 +79,12 @@ typedef struct {
  *                 step's partials are summed by many workgroups at once and
  *                 every workgroup of the sweep forms the step's coefficients
  *                 itself (bitwise the same results as 2).
+ *   launch        how restart cycles reach the device (same kernels, same
+ *                 order, bitwise the same results): 0 = as tuned by
+ *                 mlg_autotune for this grid (graph replay when untuned),
+ *                 1 = replay of a captured graph of the cycle, 2 = direct
+ *                 kernel launches.  gmres_solve_static always launches
+ *                 directly.
  */
 typedef struct {
   int32_t restart_m;
@@ -89,6 +95,7 @@ typedef struct {
   int32_t tile;
   int32_t poll_cycles;
   int32_t schedule;
+  int32_t launch;
 } mlg_opts;
 
 /* Per-solve statistics (host).  relres_first_cycle is the paper's metric E_k
@@ -218,21 +225,27 @@ int mlg_tile_shape(int32_t dim, int32_t index, int32_t* tx, int32_t* ty, int32_t
  * tile shape and, per Arnoldi step, the separate extend + dot-product sweeps
  * against the fused sweep (kernel timings), then whole restart cycles of
  * every tile with the fused steps' sums in either form, on synthetic data in
- * `ws`, in the launch configuration the solver uses; records the fastest tile
- * and per-step schedule in a process-wide table that gmres_solve /
- * gmres_solve_batched consult when opts->tile == 0 (tile) and
- * opts->schedule == 0 (schedule).  A batched solve takes the entry of its
- * largest system per dimension.
+ * `ws`, in the launch configuration the solver uses, then whole solves of
+ * the chosen configuration with graph replay against direct launches;
+ * records the fastest tile, per-step schedule and launch mode in a
+ * process-wide table that gmres_solve / gmres_solve_batched consult when
+ * opts->tile == 0 (tile), opts->schedule == 0 (schedule) and opts->launch
+ * == 0 (launch mode).  A batched solve takes the entry of its largest system
+ * per dimension (and launches directly only when every dimension's entry
+ * chose that).
  *   ws      >= mlg_autotune_workspace_bytes(grid, opts) bytes (overwritten).
  *   tile    host, may be NULL: the chosen tile index (1-based, as opts->tile).
  *   fused   host, may be NULL: bit j set = step j runs fused.
  *   split   host, may be NULL: bit j set = ... in the split form (a subset
  *           of `fused`).
+ *   launch  host, may be NULL: the chosen launch mode (1 graph, 2 direct, as
+ *           opts->launch).
  * Blocks until done.  Entries live until mlg_shutdown.
  */
 size_t mlg_autotune_workspace_bytes(const mlg_grid* grid, const mlg_opts* opts);
 int mlg_autotune(const mlg_grid* grid, const mlg_opts* opts, void* ws, size_t ws_bytes,
-                 int32_t* tile, uint64_t* fused, uint64_t* split, void* stream);
+                 int32_t* tile, uint64_t* fused, uint64_t* split, int32_t* launch,
+                 void* stream);
 
 /* ---------------------------------------------------------------- network */
 

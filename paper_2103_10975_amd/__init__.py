@@ -67,12 +67,13 @@ class Opts(ctypes.Structure):
     _fields_ = [("restart_m", ctypes.c_int32), ("precision", ctypes.c_int32),
                 ("rtol", ctypes.c_double), ("max_iters", ctypes.c_int64),
                 ("fixed_iters", ctypes.c_int64), ("tile", ctypes.c_int32),
-                ("poll_cycles", ctypes.c_int32), ("schedule", ctypes.c_int32)]
+                ("poll_cycles", ctypes.c_int32), ("schedule", ctypes.c_int32),
+                ("launch", ctypes.c_int32)]
 
     def __init__(self, restart_m=30, precision=MLG_FP64, rtol=1e-8, max_iters=0,
-                 fixed_iters=0, tile=0, poll_cycles=1, schedule=0):
+                 fixed_iters=0, tile=0, poll_cycles=1, schedule=0, launch=0):
         super().__init__(restart_m, precision, rtol, max_iters, fixed_iters, tile, poll_cycles,
-                         schedule)
+                         schedule, launch)
 
 
 class Stats(ctypes.Structure):
@@ -133,7 +134,7 @@ def _load():
         "mlg_tile_shape": (ctypes.c_int, [i32, i32, P(i32), P(i32), P(i32)]),
         "mlg_autotune_workspace_bytes": (sz, [P(Grid), P(Opts)]),
         "mlg_autotune": (ctypes.c_int, [P(Grid), P(Opts), vp, sz, P(i32), P(ctypes.c_uint64),
-                                        P(ctypes.c_uint64), vp]),
+                                        P(ctypes.c_uint64), P(i32), vp]),
         "guess_net_param_count": (i64, [P(NetCfg)]),
         "guess_net_param_offset": (i64, [P(NetCfg), i32]),
         "guess_net_param_bytes": (sz, [P(NetCfg)]),
@@ -337,17 +338,19 @@ def mlg_autotune_workspace_bytes(grid: Grid, opts: Opts) -> int:
 
 
 def mlg_autotune(grid: Grid, opts: Opts, ws: torch.Tensor | None = None, stream=None):
-    """Time every tile and per-step sweep schedule for (grid, opts) and record
-    the fastest for later solves with tile=0, schedule=0.  Returns (tile,
-    fused-step bit mask, split-form bit mask).  ws: scratch of
+    """Time every tile, per-step sweep schedule and launch mode for (grid,
+    opts) and record the fastest for later solves with tile=0, schedule=0,
+    launch=0.  Returns (tile, fused-step bit mask, split-form bit mask, launch
+    mode: 1 graph replay, 2 direct launches).  ws: scratch of
     mlg_autotune_workspace_bytes bytes (allocated here when None)."""
     if ws is None:
         ws = workspace(mlg_autotune_workspace_bytes(grid, opts))
     tile, fused, split = ctypes.c_int32(), ctypes.c_uint64(), ctypes.c_uint64()
+    launch = ctypes.c_int32()
     _check(lib.mlg_autotune(ctypes.byref(grid), ctypes.byref(opts), _ptr(ws, torch.uint8),
                             ws.numel(), ctypes.byref(tile), ctypes.byref(fused),
-                            ctypes.byref(split), _stream(stream)))
-    return tile.value, fused.value, split.value
+                            ctypes.byref(split), ctypes.byref(launch), _stream(stream)))
+    return tile.value, fused.value, split.value, launch.value
 
 
 def mlg_tile_count(dim: int) -> int:

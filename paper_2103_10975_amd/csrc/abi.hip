@@ -109,14 +109,16 @@ size_t mlg_autotune_workspace_bytes(const mlg_grid* grid, const mlg_opts* opts) 
 }
 
 int mlg_autotune(const mlg_grid* grid, const mlg_opts* opts, void* ws, size_t ws_bytes,
-                 int32_t* tile, uint64_t* fused, uint64_t* split, void* stream) {
+                 int32_t* tile, uint64_t* fused, uint64_t* split, int32_t* launch,
+                 void* stream) {
   return guarded([&] {
-    int t = 0;
+    int t = 0, l = 0;
     unsigned long long f = 0, sp = 0;
-    const int rc = autotune(grid, opts, ws, ws_bytes, &t, &f, &sp, (hipStream_t)stream);
+    const int rc = autotune(grid, opts, ws, ws_bytes, &t, &f, &sp, &l, (hipStream_t)stream);
     if (tile) *tile = t;
     if (fused) *fused = (uint64_t)f;
     if (split) *split = (uint64_t)sp;
+    if (launch) *launch = l;
     return rc;
   });
 }

@@ -23,13 +23,15 @@ struct TuneEntry {
   int tile;
   unsigned long long fused[kMaxTiles];    // bit j: step j runs as the fused sweep
   unsigned long long split[kMaxTiles];    // bit j: ... with sums(j), coefficients in the sweep
+  bool direct;                            // restart cycles launched directly, not as graph replays
 };
 bool autotune_find(const mlg_grid& g, const mlg_opts& o, TuneEntry* e);
 void autotune_store(const mlg_grid& g, const mlg_opts& o, const TuneEntry& e);
 void autotune_clear();
 size_t autotune_workspace_bytes(const mlg_grid* grid, const mlg_opts* opts);
 int autotune(const mlg_grid* grid, const mlg_opts* opts, void* ws, size_t ws_bytes, int* tile,
-             unsigned long long* fused, unsigned long long* split, hipStream_t stream);
+             unsigned long long* fused, unsigned long long* split, int* launch,
+             hipStream_t stream);
 
 size_t solve_workspace_bytes(const mlg_grid* grid, const mlg_opts* opts);
 int solve(const mlg_grid* grid, const double* b, double* x, const mlg_opts* opts, void* ws,

@@ -79,6 +79,7 @@ void check_opts(const mlg_opts* o, int dim) {
   if (o->max_iters < 0 || o->fixed_iters < 0) throw ArgError{MLG_ERR_ARG, "negative iteration cap"};
   if (o->tile < 0 || o->tile > tile_count(dim)) throw ArgError{MLG_ERR_ARG, "tile index out of range"};
   if (o->schedule < 0 || o->schedule > 3) throw ArgError{MLG_ERR_ARG, "schedule must be in 0..3"};
+  if (o->launch < 0 || o->launch > 2) throw ArgError{MLG_ERR_ARG, "launch must be in 0..2"};
 }
 
 // Default tile when the caller leaves the choice to the library and the
@@ -110,6 +111,7 @@ struct Plan {
   std::vector<Group> groups;
   size_t off_hdr, off_stats, off_desc, off_init, total;
   int total_rhs;
+  bool direct;                      // launch cycles directly (tuned), else replay a graph
 };
 
 struct SysInit {                    // per-call fields of a system's control block
@@ -125,6 +127,7 @@ static Plan make_plan(int nsys, const mlg_system* sys, const mlg_opts& o) {
   P.s = o.precision == MLG_FP64 ? 8 : 4;
   P.total_rhs = 0;
   for (int i = 0; i < nsys; ++i) P.total_rhs += sys[i].nrhs;
+  int ngroups = 0, ndirect = 0;
   // one group per dimension (all systems of a group share the tile shape)
   for (int dim = 2; dim <= 3; ++dim) {
     Group G{};
@@ -150,8 +153,12 @@ static Plan make_plan(int nsys, const mlg_system* sys, const mlg_opts& o) {
       G.fused = te.fused[G.tile];
       G.split = te.split[G.tile] & G.fused;
     }
+    ++ngroups;
+    ndirect += (tuned && te.direct) ? 1 : 0;
     P.groups.push_back(G);
   }
+  // as tuned: direct launches only when every group's entry chose them
+  P.direct = o.launch == 2 || (o.launch == 0 && ngroups > 0 && ndirect == ngroups);
   P.geo.resize(nsys);
   for (auto& G : P.groups) {
     long long total_tiles = 0;
@@ -548,8 +555,9 @@ int batched_solve(int nsys, const mlg_system* sys, const mlg_opts* opts, void* w
 
   Pinned stage(stage_bytes(P));
   upload_plan(P, D, nsys, sys, *opts, stream, (char*)stage.p);
-  hipGraphExec_t exec = cycle_graph(plan_key(dev, ws, P, opts->precision, m), dev, P, D,
-                                    opts->precision, m);
+  hipGraphExec_t exec = P.direct ? nullptr
+                                  : cycle_graph(plan_key(dev, ws, P, opts->precision, m), dev, P,
+                                                D, opts->precision, m);
   Pinned pin(std::max<size_t>(2 * 256, (size_t)P.total_rhs * sizeof(Summary)));
   volatile unsigned int* host = (volatile unsigned int*)pin.p;   // [slot * 64]: done count
   hipEvent_t ev[2];
@@ -574,13 +582,24 @@ int batched_solve(int nsys, const mlg_system* sys, const mlg_opts* opts, void* w
   // round trip when the forecast was wrong.
   int slot = 0, queue[2] = {0, 0}, nq = 0;
   auto launch = [&]() {
-    for (int c = 0; c < poll; ++c) MLG_HIP(hipGraphLaunch(exec, stream));
+    for (int c = 0; c < poll; ++c) {
+      if (P.direct) {
+        enqueue_cycle(stream, P, D, opts->precision, m);
+        MLG_HIP(hipGetLastError());
+      } else {
+        MLG_HIP(hipGraphLaunch(exec, stream));
+      }
+    }
     MLG_HIP(hipMemcpyAsync((void*)(host + 64 * slot), D.hdr, 12, hipMemcpyDeviceToHost, stream));
     MLG_HIP(hipEventRecord(ev[slot], stream));
     queue[nq++] = slot;
     slot ^= 1;
   };
-  bool forecast = false;
+  // A single right-hand side launches no speculative second cycle before the
+  // first one has been read: a good initial guess finishes in one cycle, and
+  // the speculative one's idle kernels would then delay the end of the solve
+  // (a solve that needs more cycles pays one host round trip, once).
+  bool forecast = P.total_rhs == 1;
   unsigned int last_progress = 0;
   long long grp = 0, reads = 0;
   launch();
@@ -877,7 +896,8 @@ size_t autotune_workspace_bytes(const mlg_grid* grid, const mlg_opts* opts) {
 }
 
 int autotune(const mlg_grid* grid, const mlg_opts* opts, void* ws, size_t ws_bytes, int* tile_out,
-             unsigned long long* fused_out, unsigned long long* split_out, hipStream_t stream) {
+             unsigned long long* fused_out, unsigned long long* split_out, int* launch_out,
+             hipStream_t stream) {
   check_grid(grid);
   check_opts(opts, grid->dim);
   if (!ws || ws_bytes < autotune_workspace_bytes(grid, opts) || (uintptr_t)ws % 256)
@@ -911,6 +931,7 @@ int autotune(const mlg_grid* grid, const mlg_opts* opts, void* ws, size_t ws_byt
     mlg_opts o = *opts;
     o.tile = t + 1;
     o.schedule = 1;
+    o.launch = 1;
     o.fixed_iters = m;                         // one full cycle fills the basis
     o.max_iters = 0;
     k_tune_fill<<<(unsigned)((n + 255) / 256), 256, 0, stream>>>(b, x, (long long)n);
@@ -952,6 +973,7 @@ int autotune(const mlg_grid* grid, const mlg_opts* opts, void* ws, size_t ws_byt
       mlg_opts o = *opts;
       o.tile = t + 1;
       o.schedule = 0;                          // the entry just stored
+      o.launch = 1;
       o.fixed_iters = 2 * m;
       o.max_iters = 0;
       o.poll_cycles = 2;
@@ -972,10 +994,38 @@ int autotune(const mlg_grid* grid, const mlg_opts* opts, void* ws, size_t ws_byt
   for (int t = 1; t < nt; ++t)
     if (best(t) < best(fastest)) fastest = t;
   te.tile = best(fastest) < 0.95 * best(dflt) ? fastest : dflt;
+  // stage 3: the chosen configuration's restart cycles replayed as captured
+  // graphs or launched directly (a graph node starts later after its
+  // predecessor than a directly launched kernel does on some sizes, while
+  // direct launches cost host time per kernel); direct only when at least
+  // 3% faster
+  te.direct = false;
+  autotune_store(*grid, *opts, te);
+  double lm[2] = {1e300, 1e300};
+  for (int direct = 0; direct < 2; ++direct) {
+    mlg_opts o = *opts;
+    o.tile = 0;
+    o.schedule = 0;
+    o.launch = direct ? 2 : 1;
+    o.fixed_iters = 2 * m;
+    o.max_iters = 0;
+    o.poll_cycles = 1;
+    for (int rep = 0; rep < 5; ++rep) {        // the first run also captures the graph
+      k_tune_fill<<<(unsigned)((n + 255) / 256), 256, 0, stream>>>(b, x, (long long)n);
+      MLG_HIP(hipGetLastError());
+      MLG_HIP(hipStreamSynchronize(stream));
+      const auto t0 = std::chrono::steady_clock::now();
+      solve(grid, b, x, &o, ws, solve_bytes, nullptr, stream);
+      const auto t1 = std::chrono::steady_clock::now();
+      if (rep > 0) lm[direct] = std::min(lm[direct], std::chrono::duration<double>(t1 - t0).count());
+    }
+  }
+  te.direct = lm[1] < 0.97 * lm[0];
   autotune_store(*grid, *opts, te);
   if (tile_out) *tile_out = te.tile + 1;
   if (fused_out) *fused_out = te.fused[te.tile];
   if (split_out) *split_out = te.split[te.tile];
+  if (launch_out) *launch_out = te.direct ? 2 : 1;
   return MLG_OK;
 }
 

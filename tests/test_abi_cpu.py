@@ -32,7 +32,8 @@ def test_argument_validation_without_device_work():
     g = mlg.grid_of((64, 64))
     assert mlg.gmres_workspace_bytes(g, mlg.Opts(restart_m=20)) > 0
     for bad in (mlg.Opts(restart_m=0), mlg.Opts(restart_m=65), mlg.Opts(precision=7),
-                mlg.Opts(rtol=-1.0), mlg.Opts(tile=99)):
+                mlg.Opts(rtol=-1.0), mlg.Opts(tile=99), mlg.Opts(schedule=4),
+                mlg.Opts(launch=3), mlg.Opts(launch=-1)):
         with pytest.raises(mlg.MlgError):
             mlg.gmres_workspace_bytes(g, bad)
     with pytest.raises(mlg.MlgError):

@@ -1,5 +1,6 @@
 """The autotuner: its choice is valid, recorded, and solves that use it
-(tile 0, schedule 0) match the explicit tile/schedule bitwise and the oracle."""
+(tile 0, schedule 0) match the explicit tile/schedule bitwise and the oracle;
+the two launch modes (graph replay, direct launches) give the same bits."""
 import numpy as np
 import pytest
 import torch
@@ -33,9 +34,10 @@ def test_autotune_choice_is_used(mlg, shape, m, precision):
     print("autotune", shape, m, precision, flush=True)
     grid = mlg.grid_of(shape)
     tune = mlg.Opts(restart_m=m, precision=precision)
-    tile, fused, split = mlg.mlg_autotune(grid, tune)
-    print(f"  tile {tile} fused mask {fused:#x} split mask {split:#x}")
+    tile, fused, split, launch = mlg.mlg_autotune(grid, tune)
+    print(f"  tile {tile} fused mask {fused:#x} split mask {split:#x} launch {launch}")
     assert 1 <= tile <= mlg.mlg_tile_count(len(shape))
+    assert launch in (1, 2)
     assert fused < (1 << m) and split & ~fused == 0
     if len(shape) == 3:
         assert fused == 0                       # no fused sweep in 3D
@@ -66,3 +68,47 @@ def test_autotune_errors(mlg):
     assert e.value.code == mlg.MLG_ERR_WORKSPACE
     with pytest.raises(mlg.MlgError):
         mlg.mlg_autotune(grid, mlg.Opts(restart_m=0))
+
+
+@pytest.mark.parametrize("shape,m,precision,schedule,poll",
+                         [((200, 150), 20, 0, 3, 1), ((96, 96), 12, 1, 1, 2),
+                          ((24, 20, 28), 16, 0, 1, 1), ((130, 70), 9, 1, 2, 3)])
+def test_launch_modes_give_the_same_bits(mlg, shape, m, precision, schedule, poll):
+    """Graph replay and direct launches enqueue the same kernels in the same
+    order: solutions and statistics agree bitwise, over many restart cycles
+    and several host poll intervals."""
+    print("launch modes", shape, m, precision, schedule, poll, flush=True)
+    b = DriftingGaussians(shape, 3, 0.06, seed=7).field(0)
+    runs = [solve(mlg, b, restart_m=m, rtol=1e-9, precision=precision, schedule=schedule,
+                  poll_cycles=poll, launch=launch) for launch in (1, 2)]
+    (xg, sg), (xd, sd) = runs
+    assert sg.status == 0 and sd.status == 0 and sg.cycles > 3
+    assert np.array_equal(xg, xd)
+    for f in ("iters", "cycles", "relres_init", "relres_first_cycle", "relres_est",
+              "relres_true", "relres_iter5"):
+        assert getattr(sg, f) == getattr(sd, f), f
+
+
+def test_launch_modes_batched(mlg):
+    """A batched solve of a 2D and a 3D system (several right-hand sides each)
+    gives the same bits with graph replay and direct launches."""
+    print("launch modes batched", flush=True)
+    shapes = [(90, 110), (20, 18, 22)]
+    rhs = [np.stack([DriftingGaussians(sh, 3, 0.08, seed=30 + i).field(t) for t in range(3)])
+           for i, sh in enumerate(shapes)]
+    out = []
+    for launch in (1, 2):
+        bs = [torch.from_numpy(r).cuda() for r in rhs]
+        xs = [torch.zeros_like(b) for b in bs]
+        systems = [mlg.make_system(b, x, 1) for b, x in zip(bs, xs)]
+        opts = mlg.Opts(restart_m=14, rtol=1e-9, precision=1, launch=launch)
+        ws = mlg.workspace(mlg.gmres_batched_workspace_bytes(systems, opts))
+        stats = mlg.gmres_solve_batched(systems, opts, ws)
+        torch.cuda.synchronize()
+        out.append(([x.cpu().numpy() for x in xs], [(s.status, s.iters, s.relres_true)
+                                                     for s in stats]))
+    (xg, sg), (xd, sd) = out
+    assert all(s[0] == 0 for s in sg)
+    assert sg == sd
+    assert all(np.array_equal(a, c) for a, c in zip(xg, xd))
+
