@@ -25,7 +25,7 @@ FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
 # dimension, tile index); it is compiled once per triple so that the
 # instantiations build in parallel.
 SWEEP_UNITS = [(p, 2, t) for p in (0, 1) for t in range(5)] + \
-              [(p, 3, t) for p in (0, 1) for t in range(4)]
+              [(p, 3, t) for p in (0, 1) for t in range(5)]
 
 
 def _units():

@@ -27,8 +27,11 @@ template <> struct TileOf<3, 0> { using type = TileT<3, 64, 2, 4>; };
 template <> struct TileOf<3, 1> { using type = TileT<3, 64, 2, 2>; };
 template <> struct TileOf<3, 2> { using type = TileT<3, 32, 4, 2>; };
 template <> struct TileOf<3, 3> { using type = TileT<3, 64, 4, 4>; };
+// 32 wide: rows of a multiple of 32 (but not of 64) points leave no
+// half-empty tile column, whose loads cost as much as full ones
+template <> struct TileOf<3, 4> { using type = TileT<3, 32, 8, 4>; };
 constexpr int kNumTiles2 = 5;
-constexpr int kNumTiles3 = 4;
+constexpr int kNumTiles3 = 5;
 
 #define MLG_TILE_SWITCH(DIM, IDX, EXPR_TL)                                   \
   if ((DIM) == 2) {                                                          \
@@ -44,7 +47,8 @@ constexpr int kNumTiles3 = 4;
       case 0: { using TL = TileOf<3, 0>::type; EXPR_TL; }                    \
       case 1: { using TL = TileOf<3, 1>::type; EXPR_TL; }                    \
       case 2: { using TL = TileOf<3, 2>::type; EXPR_TL; }                    \
-      default: { using TL = TileOf<3, 3>::type; EXPR_TL; }                   \
+      case 3: { using TL = TileOf<3, 3>::type; EXPR_TL; }                    \
+      default: { using TL = TileOf<3, 4>::type; EXPR_TL; }                   \
     }                                                                        \
   }
 
@@ -65,8 +69,8 @@ GroupFn group_fn(int dim, int tile, int prec);
 #define MLG_SWEEP_DECL(P, D, T) GroupFn MLG_SWEEP_NAME(P, D, T)();
 #define MLG_SWEEP_ALL(X)                                                          \
   X(0, 2, 0) X(0, 2, 1) X(0, 2, 2) X(0, 2, 3) X(0, 2, 4) X(0, 3, 0) X(0, 3, 1)    \
-  X(0, 3, 2) X(0, 3, 3) X(1, 2, 0) X(1, 2, 1) X(1, 2, 2) X(1, 2, 3) X(1, 2, 4)    \
-  X(1, 3, 0) X(1, 3, 1) X(1, 3, 2) X(1, 3, 3)
+  X(0, 3, 2) X(0, 3, 3) X(0, 3, 4) X(1, 2, 0) X(1, 2, 1) X(1, 2, 2) X(1, 2, 3)    \
+  X(1, 2, 4) X(1, 3, 0) X(1, 3, 1) X(1, 3, 2) X(1, 3, 3) X(1, 3, 4)
 MLG_SWEEP_ALL(MLG_SWEEP_DECL)
 
 }  // namespace mlg

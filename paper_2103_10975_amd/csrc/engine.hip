@@ -27,7 +27,7 @@ constexpr TileDesc tile_of() {
 static const TileDesc kTiles2[kNumTiles2] = {tile_of<2, 0>(), tile_of<2, 1>(), tile_of<2, 2>(),
                                              tile_of<2, 3>(), tile_of<2, 4>()};
 static const TileDesc kTiles3[kNumTiles3] = {tile_of<3, 0>(), tile_of<3, 1>(), tile_of<3, 2>(),
-                                             tile_of<3, 3>()};
+                                             tile_of<3, 3>(), tile_of<3, 4>()};
 
 int tile_count(int dim) { return dim == 3 ? kNumTiles3 : kNumTiles2; }
 TileDesc tile_desc(int dim, int idx) { return dim == 3 ? kTiles3[idx] : kTiles2[idx]; }
@@ -109,7 +109,7 @@ struct Plan {
   std::vector<Geo> geo;
   std::vector<size_t> off_ctrl, off_part, off_r, off_V;
   std::vector<Group> groups;
-  size_t off_hdr, off_stats, off_desc, off_init, total;
+  size_t off_hdr, off_stats, off_desc, off_init, off_plan_end, total;
   int total_rhs;
   bool direct;                      // launch cycles directly (tuned), else replay a graph
 };
@@ -119,6 +119,9 @@ struct SysInit {                    // per-call fields of a system's control blo
   double* x0;
   int nrhs, guess;
   Summary* stats;
+  int m, fixed;                     // restart length; 1 = run exactly `limit` steps
+  long long limit;                  // step cap
+  double rtol;
 };
 
 static Plan make_plan(int nsys, const mlg_system* sys, const mlg_opts& o) {
@@ -197,6 +200,7 @@ static Plan make_plan(int nsys, const mlg_system* sys, const mlg_opts& o) {
     G.off_jobs = take(G.jobs.size() * sizeof(Job));
     G.off_list = take(G.systems.size() * sizeof(int));
   }
+  P.off_plan_end = o_;              // descriptors .. lists: one contiguous upload
   P.off_ctrl.resize(nsys);
   P.off_part.resize(nsys);
   P.off_r.resize(nsys);
@@ -286,7 +290,42 @@ static DevPlan dev_plan(const Plan& P, void* ws) {
   return D;
 }
 
-static void enqueue_cycle(hipStream_t s, const Plan& P, const DevPlan& D, int prec, int m) {
+// Per-call set-up of every control block (pointers, counts, options), and of
+// the shared counters.  One workgroup per system.
+__global__ void k_setup(const SysInit* init, const SysDesc* sd, unsigned int* hdr) {
+  const SysDesc* S = sd + blockIdx.x;
+  Ctrl* C = S->C;
+  if (threadIdx.x != 0) return;
+  const SysInit& I = init[blockIdx.x];
+  const int m = I.m, fixed = I.fixed;
+  const long long limit = I.limit;
+  const double rtol = I.rtol;
+  C->s = Summary{MLG_OK, 0, 0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  C->phase = PH_INIT;
+  C->cycle_end = 0;
+  C->k = 0;
+  C->m = m;
+  C->fixed = fixed;
+  C->guess = I.guess;
+  C->rhs = 0;
+  C->nrhs = I.nrhs;
+  C->limit = limit;
+  C->rtol = rtol;
+  C->b0 = I.b0;
+  C->x0 = I.x0;
+  C->stats = I.stats;
+  C->done = hdr;
+  if (blockIdx.x == 0) {
+    hdr[0] = 0u;
+    hdr[1] = 0u;
+    hdr[2] = 0u;
+  }
+}
+
+// One restart cycle of every system; `setup` first sets up the control
+// blocks from the uploaded init records (the first cycle of a call).
+static void enqueue_cycle(hipStream_t s, const Plan& P, const DevPlan& D, int prec, int m,
+                          bool setup = false) {
   std::vector<GroupFn> fns;
   for (auto& G : P.groups) fns.push_back(group_fn(G.dim, G.tile, prec));
   const size_t ng = P.groups.size();
@@ -297,6 +336,7 @@ static void enqueue_cycle(hipStream_t s, const Plan& P, const DevPlan& D, int pr
   const int ns = P.nsys;
   int maxblk = 1;
   for (auto& G : P.groups) maxblk = std::max(maxblk, G.maxblk);
+  if (setup) k_setup<<<ns, 64, 0, s>>>(D.init, D.desc, D.hdr);
   each(G_BEGIN, 0);
   each(G_RESID0, 0);
   k_rsum<true><<<ns, kReduceThreads, 0, s>>>(D.desc);
@@ -335,36 +375,6 @@ static void enqueue_cycle(hipStream_t s, const Plan& P, const DevPlan& D, int pr
   each(G_UPDATE, m);
   each(G_RESID, 0);
   k_rsum<false><<<ns, kReduceThreads, 0, s>>>(D.desc);
-}
-
-// Per-call set-up of every control block (pointers, counts, options), and of
-// the shared counters.  One workgroup per system.
-__global__ void k_setup(const SysInit* init, const SysDesc* sd, unsigned int* hdr, int m,
-                        int fixed, long long limit, double rtol) {
-  const SysDesc* S = sd + blockIdx.x;
-  Ctrl* C = S->C;
-  if (threadIdx.x != 0) return;
-  const SysInit& I = init[blockIdx.x];
-  C->s = Summary{MLG_OK, 0, 0, 0.0, 0.0, 0.0, 0.0, 0.0};
-  C->phase = PH_INIT;
-  C->cycle_end = 0;
-  C->k = 0;
-  C->m = m;
-  C->fixed = fixed;
-  C->guess = I.guess;
-  C->rhs = 0;
-  C->nrhs = I.nrhs;
-  C->limit = limit;
-  C->rtol = rtol;
-  C->b0 = I.b0;
-  C->x0 = I.x0;
-  C->stats = I.stats;
-  C->done = hdr;
-  if (blockIdx.x == 0) {
-    hdr[0] = 0u;
-    hdr[1] = 0u;
-    hdr[2] = 0u;
-  }
 }
 
 // ------------------------------------------------------------------ caches
@@ -406,9 +416,11 @@ static std::string plan_key(int dev, const void* ws, const Plan& P, int prec, in
   return k;
 }
 
-// Captured graph of one restart cycle for this workspace and plan.
-static hipGraphExec_t cycle_graph(const std::string& key, int dev, const Plan& P, const DevPlan& D,
-                                  int prec, int m) {
+// Captured graph of one restart cycle for this workspace and plan (with the
+// set-up of the control blocks in front when `setup`).
+static hipGraphExec_t cycle_graph(const std::string& key0, int dev, const Plan& P, const DevPlan& D,
+                                  int prec, int m, bool setup) {
+  const std::string key = key0 + (setup ? "+setup" : "");
   auto& R = rt();
   std::lock_guard<std::mutex> lk(R.mu);
   auto it = R.graphs.find(key);
@@ -426,7 +438,7 @@ static hipGraphExec_t cycle_graph(const std::string& key, int dev, const Plan& P
   hipStream_t cs = capture_stream(dev);
   hipGraph_t graph;
   MLG_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeRelaxed));
-  enqueue_cycle(cs, P, D, prec, m);
+  enqueue_cycle(cs, P, D, prec, m, setup);
   hipError_t ce = hipStreamEndCapture(cs, &graph);
   MLG_HIP(ce);
   hipGraphExec_t exec;
@@ -481,13 +493,13 @@ void batched_shutdown() {}
 // untouched until the stream has passed the copies.
 static void upload_plan(const Plan& P, const DevPlan& D, int nsys, const mlg_system* sys,
                         const mlg_opts& o, hipStream_t stream, char* h) {
-  // host images of the descriptors, init records and job tables
-  size_t off = 0;
-  auto put = [&](const void* src, size_t bytes, void* dst) {
-    std::memcpy(h + off, src, bytes);
-    MLG_HIP(hipMemcpyAsync(dst, h + off, bytes, hipMemcpyHostToDevice, stream));
-    off = align_up(off + bytes, 64);
-  };
+  // host image of the descriptors, init records and job tables, laid out as
+  // in the workspace, and one copy of it
+  const size_t base = P.off_desc;
+  std::memset(h, 0, P.off_plan_end - base);
+  auto put = [&](const void* src, size_t bytes, size_t off) { std::memcpy(h + (off - base), src, bytes); };
+  const long long limit = o.fixed_iters > 0 ? o.fixed_iters
+                          : (o.max_iters > 0 ? o.max_iters : 1000000000LL);
   std::vector<SysDesc> desc(nsys);
   std::vector<SysInit> init(nsys);
   int stat_base = 0;
@@ -502,10 +514,14 @@ static void upload_plan(const Plan& P, const DevPlan& D, int nsys, const mlg_sys
     init[i].nrhs = sys[i].nrhs;
     init[i].guess = sys[i].guess;
     init[i].stats = D.stats + stat_base;
+    init[i].m = o.restart_m;
+    init[i].fixed = o.fixed_iters > 0 ? 1 : 0;
+    init[i].limit = limit;
+    init[i].rtol = o.rtol;
     stat_base += sys[i].nrhs;
   }
-  put(desc.data(), desc.size() * sizeof(SysDesc), D.desc);
-  put(init.data(), init.size() * sizeof(SysInit), D.init);
+  put(desc.data(), desc.size() * sizeof(SysDesc), P.off_desc);
+  put(init.data(), init.size() * sizeof(SysInit), P.off_init);
   for (size_t gi = 0; gi < P.groups.size(); ++gi) {
     std::vector<Job> jobs = P.groups[gi].jobs;
     for (Job& J : jobs) {
@@ -515,22 +531,14 @@ static void upload_plan(const Plan& P, const DevPlan& D, int nsys, const mlg_sys
       J.r = desc[J.sys].r;
       J.part = desc[J.sys].part;
     }
-    put(jobs.data(), jobs.size() * sizeof(Job), (void*)D.jobs[gi]);
+    put(jobs.data(), jobs.size() * sizeof(Job), P.groups[gi].off_jobs);
     put(P.groups[gi].systems.data(), P.groups[gi].systems.size() * sizeof(int),
-        (void*)D.lists[gi]);
+        P.groups[gi].off_list);
   }
-  const long long limit = o.fixed_iters > 0 ? o.fixed_iters
-                          : (o.max_iters > 0 ? o.max_iters : 1000000000LL);
-  k_setup<<<nsys, 64, 0, stream>>>(D.init, D.desc, D.hdr, o.restart_m, o.fixed_iters > 0 ? 1 : 0,
-                                   limit, o.rtol);
-  MLG_HIP(hipGetLastError());
+  MLG_HIP(hipMemcpyAsync(D.desc, h, P.off_plan_end - base, hipMemcpyHostToDevice, stream));
 }
 
-static size_t stage_bytes(const Plan& P) {
-  size_t b = P.nsys * (sizeof(SysDesc) + sizeof(SysInit)) + 256;
-  for (auto& G : P.groups) b += G.jobs.size() * sizeof(Job) + G.systems.size() * sizeof(int) + 128;
-  return b;
-}
+static size_t stage_bytes(const Plan& P) { return P.off_plan_end - P.off_desc; }
 
 static int report(const Plan& P, const std::vector<Summary>& res, double secs, mlg_stats* stats);
 
@@ -555,11 +563,24 @@ int batched_solve(int nsys, const mlg_system* sys, const mlg_opts* opts, void* w
 
   Pinned stage(stage_bytes(P));
   upload_plan(P, D, nsys, sys, *opts, stream, (char*)stage.p);
-  hipGraphExec_t exec = P.direct ? nullptr
-                                  : cycle_graph(plan_key(dev, ws, P, opts->precision, m), dev, P,
-                                                D, opts->precision, m);
-  Pinned pin(std::max<size_t>(2 * 256, (size_t)P.total_rhs * sizeof(Summary)));
-  volatile unsigned int* host = (volatile unsigned int*)pin.p;   // [slot * 64]: done count
+  // the first cycle sets up the control blocks (a graph of its own)
+  hipGraphExec_t exec = nullptr, exec_first = nullptr;
+  if (!P.direct) {
+    const std::string key = plan_key(dev, ws, P, opts->precision, m);
+    exec_first = cycle_graph(key, dev, P, D, opts->precision, m, true);
+    exec = cycle_graph(key, dev, P, D, opts->precision, m, false);
+  }
+  // Each poll copies the header -- and, for up to kStatsInPoll right-hand
+  // sides, the statistics behind it in the workspace -- into one of two
+  // pinned slots, so that a finished solve needs no further round trip.
+  constexpr int kStatsInPoll = 64;
+  const bool stats_in_poll = P.total_rhs <= kStatsInPoll;
+  const size_t stats_bytes = (size_t)P.total_rhs * sizeof(Summary);
+  const size_t poll_bytes = (P.off_stats - P.off_hdr) + (stats_in_poll ? stats_bytes : 0);
+  const size_t slot_bytes = align_up(poll_bytes, 256);
+  Pinned pin(2 * slot_bytes + stats_bytes);
+  auto slot_ptr = [&](int sl) { return (char*)pin.p + sl * slot_bytes; };
+  auto slot_hdr = [&](int sl) { return (volatile unsigned int*)slot_ptr(sl); };
   hipEvent_t ev[2];
   MLG_HIP(hipEventCreateWithFlags(&ev[0], hipEventDisableTiming));
   MLG_HIP(hipEventCreateWithFlags(&ev[1], hipEventDisableTiming));
@@ -581,16 +602,18 @@ int batched_solve(int nsys, const mlg_system* sys, const mlg_opts* opts, void* w
   // whole cycle of no-op kernels at the end of a solve, and costs one host
   // round trip when the forecast was wrong.
   int slot = 0, queue[2] = {0, 0}, nq = 0;
+  bool first = true;
   auto launch = [&]() {
     for (int c = 0; c < poll; ++c) {
       if (P.direct) {
-        enqueue_cycle(stream, P, D, opts->precision, m);
+        enqueue_cycle(stream, P, D, opts->precision, m, first);
         MLG_HIP(hipGetLastError());
       } else {
-        MLG_HIP(hipGraphLaunch(exec, stream));
+        MLG_HIP(hipGraphLaunch(first ? exec_first : exec, stream));
       }
+      first = false;
     }
-    MLG_HIP(hipMemcpyAsync((void*)(host + 64 * slot), D.hdr, 12, hipMemcpyDeviceToHost, stream));
+    MLG_HIP(hipMemcpyAsync(slot_ptr(slot), D.hdr, poll_bytes, hipMemcpyDeviceToHost, stream));
     MLG_HIP(hipEventRecord(ev[slot], stream));
     queue[nq++] = slot;
     slot ^= 1;
@@ -602,6 +625,7 @@ int batched_solve(int nsys, const mlg_system* sys, const mlg_opts* opts, void* w
   bool forecast = P.total_rhs == 1;
   unsigned int last_progress = 0;
   long long grp = 0, reads = 0;
+  int done_slot = -1;
   launch();
   ++grp;
   while (true) {
@@ -613,8 +637,12 @@ int batched_solve(int nsys, const mlg_system* sys, const mlg_opts* opts, void* w
     queue[0] = queue[1];
     --nq;
     MLG_HIP(hipEventSynchronize(ev[p]));
-    const unsigned int fin = host[64 * p], prog = host[64 * p + 1], fc = host[64 * p + 2];
-    if (fin >= (unsigned)nsys) break;
+    volatile unsigned int* host = slot_hdr(p);
+    const unsigned int fin = host[0], prog = host[1], fc = host[2];
+    if (fin >= (unsigned)nsys) {
+      done_slot = p;
+      break;
+    }
     if (reads > 0 && prog == last_progress)
       throw HipError{hipErrorUnknown, "solver made no progress in a restart cycle"};
     ++reads;
@@ -626,14 +654,19 @@ int batched_solve(int nsys, const mlg_system* sys, const mlg_opts* opts, void* w
       ++grp;
     }
   }
-  MLG_HIP(hipMemcpyAsync((void*)host, D.hdr, 8, hipMemcpyDeviceToHost, stream));
-  MLG_HIP(hipStreamSynchronize(stream));
-  if (host[0] < (unsigned)nsys) throw HipError{hipErrorUnknown, "solver did not finish"};
+  // a group still in flight (launched ahead) runs idle; it must pass before
+  // the pinned slots are reused
+  if (nq > 0) MLG_HIP(hipStreamSynchronize(stream));
+  if (done_slot < 0) throw HipError{hipErrorUnknown, "solver did not finish"};
   std::vector<Summary> res(P.total_rhs);
-  MLG_HIP(hipMemcpyAsync(pin.p, D.stats, (size_t)P.total_rhs * sizeof(Summary),
-                         hipMemcpyDeviceToHost, stream));
-  MLG_HIP(hipStreamSynchronize(stream));
-  std::memcpy(res.data(), pin.p, (size_t)P.total_rhs * sizeof(Summary));
+  if (stats_in_poll) {
+    std::memcpy(res.data(), slot_ptr(done_slot) + (P.off_stats - P.off_hdr), stats_bytes);
+  } else {
+    char* sp = (char*)pin.p + 2 * slot_bytes;
+    MLG_HIP(hipMemcpyAsync(sp, D.stats, stats_bytes, hipMemcpyDeviceToHost, stream));
+    MLG_HIP(hipStreamSynchronize(stream));
+    std::memcpy(res.data(), sp, stats_bytes);
+  }
   const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   return report(P, res, secs, stats);
 }
@@ -743,7 +776,7 @@ int solve_static(const mlg_grid* grid, const double* b, double* x, const mlg_opt
   unsigned int last_progress = 0;
   bool finished = false;
   for (long long grp = 0; grp < max_groups; ++grp) {
-    for (int c = 0; c < poll; ++c) enqueue_cycle(stream, P, D, opts->precision, m);
+    for (int c = 0; c < poll; ++c) enqueue_cycle(stream, P, D, opts->precision, m, grp == 0 && c == 0);
     MLG_HIP(hipGetLastError());
     MLG_HIP(hipMemcpyAsync(hdr, D.hdr, sizeof(hdr), hipMemcpyDeviceToHost, stream));
     MLG_HIP(hipStreamSynchronize(stream));

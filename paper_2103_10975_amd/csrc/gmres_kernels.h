@@ -256,28 +256,41 @@ __device__ __forceinline__ void load_tile(double* L, P src, const Geo& g, int ox
   }
 }
 
-// load_tile from a buffer descriptor of element type T.
+// A tile of a basis slot plus a RING-point halo, staged in two parts: issue()
+// starts the loads into registers and write() later stores the values into
+// LDS as FP64 (points outside the grid as 0, the Dirichlet boundary).  Loads
+// issued in between stay in flight across write(): the memory counter is in
+// order, so write() waits for the halo alone when the halo loads went first.
+// Every halo load is unconditional (out-of-grid points read element 0); the
+// empty asm at write() keeps the compiler from turning the masking select
+// into a branch around each load, which would move the loads past the
+// barrier that precedes write() and serialise them.
 template <class TL, class T, int RING = 1>
-__device__ __forceinline__ void load_tile_buf(double* L, const BasisBuf<T>& B, int k, const Geo& g,
-                                              int ox, int oy, int oz) {
+struct HaloStage {
   using H = Halo<TL, RING>;
-  constexpr int NPT = (H::SZ + kBlock - 1) / kBlock;
-  double v[NPT];
+  static constexpr int NPT = (H::SZ + kBlock - 1) / kBlock;
+  T v[NPT];
   bool in[NPT];
+  __device__ __forceinline__ void issue(const BasisBuf<T>& B, int k, const Geo& g, int ox, int oy,
+                                        int oz) {
 #pragma unroll
-  for (int h = 0; h < NPT; ++h) {
-    const int e = threadIdx.x + kBlock * h;
-    const int lx = e % H::X, r = e / H::X, ly = r % H::Y, lz = r / H::Y;
-    const int gx = ox + lx - RING, gy = oy + ly - RING, gz = TL::DIM == 3 ? oz + lz - RING : 0;
-    in[h] = e < H::SZ && gx >= 0 && gx < g.nx && gy >= 0 && gy < g.ny && gz >= 0 && gz < g.nz;
-    v[h] = (double)B.load(k, in[h] ? (unsigned)(((long long)gz * g.ny + gy) * g.nx + gx) : 0u);
+    for (int h = 0; h < NPT; ++h) {
+      const int e = threadIdx.x + kBlock * h;
+      const int lx = e % H::X, r = e / H::X, ly = r % H::Y, lz = r / H::Y;
+      const int gx = ox + lx - RING, gy = oy + ly - RING, gz = TL::DIM == 3 ? oz + lz - RING : 0;
+      in[h] = e < H::SZ && gx >= 0 && gx < g.nx && gy >= 0 && gy < g.ny && gz >= 0 && gz < g.nz;
+      v[h] = B.load(k, in[h] ? (unsigned)(((long long)gz * g.ny + gy) * g.nx + gx) : 0u);
+    }
   }
+  __device__ __forceinline__ void write(double* L) {
 #pragma unroll
-  for (int h = 0; h < NPT; ++h) {
-    const int e = threadIdx.x + kBlock * h;
-    if (e < H::SZ) L[e] = in[h] ? v[h] : 0.0;
+    for (int h = 0; h < NPT; ++h) {
+      asm volatile("" : "+v"(v[h]));
+      const int e = threadIdx.x + kBlock * h;
+      if (e < H::SZ) L[e] = in[h] ? (double)v[h] : 0.0;
+    }
   }
-}
+};
 
 // (A u) at LDS index i of a staged tile with row pitch px and plane pitch pxy:
 // sum over axes of (2 u - u_minus - u_plus) / h^2.  Not contracted, so that
@@ -399,6 +412,13 @@ __device__ __forceinline__ double lane_bcast(double v, int src) {
 // through registers one chunk at a time, the next chunk's loads in flight
 // while the current one is used, so their register use does not grow with
 // the restart length and larger tiles stay resident.
+// Chunks of basis slots in flight ahead of the one in use (chunk buffers
+// minus one) in the dot-product and extension sweeps.
+#ifndef MLG_SWEEP_NB
+#define MLG_SWEEP_NB 2
+#endif
+constexpr int kSweepBufs = MLG_SWEEP_NB;
+
 template <int KC, int N, class T>
 __device__ __forceinline__ void load_basis_chunk(T (&v)[KC][N], const BasisBuf<T>& B,
                                                  const long long (&p)[N], int k0, int live,
@@ -636,11 +656,20 @@ __global__ __launch_bounds__(kBlock) void k_dots(const Job* jobs, const SysDesc*
       qc[i][1] = pr.qy;
       qc[i][2] = pr.qz;
     }
-    constexpr int KC = 8, NCH = MM / KC;
-    T vb[2][KC][PPT];
-    load_basis_chunk<KC, PPT, T>(vb[0], VB, pp, 0, j, kU);   // in flight during the staging
+    constexpr int KC = 8, NCH = MM / KC, NB = kSweepBufs;
+    // the halo of u_j first, then the first chunks of the basis: those stay
+    // in flight while the halo is written to LDS and the stencil applied
+    HaloStage<TL, T> hs;
+    hs.issue(VB, kU, g, ox, oy, oz);
+    T vb[NB][KC][PPT];
+    __builtin_amdgcn_sched_barrier(0);
+    load_basis_chunk<KC, PPT, T>(vb[0], VB, pp, 0, j, kU);
+#pragma unroll
+    for (int c = 1; c < NB - 1; ++c)
+      if (c < NCH && KC * c < j) load_basis_chunk<KC, PPT, T>(vb[c], VB, pp, KC * c, j, kU);
+    __builtin_amdgcn_sched_barrier(0);
     __syncthreads();
-    load_tile_buf<TL, T>(L, VB, kU, g, ox, oy, oz);
+    hs.write(L);
     __syncthreads();
     double uu[PPT], ww[PPT], last[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
@@ -653,11 +682,11 @@ __global__ __launch_bounds__(kBlock) void k_dots(const Job* jobs, const SysDesc*
     // products per chunk of 8 slots, folded across the wavefront (16 sums)
 #pragma unroll
     for (int c = 0; c < NCH; ++c) {
-      // the scheduler keeps each chunk's loads here (one chunk ahead), not
-      // hoisted to the top, so only two chunks occupy registers
+      // the scheduler keeps each chunk's loads here (NB - 1 chunks ahead),
+      // not hoisted to the top, so only NB chunks occupy registers
       __builtin_amdgcn_sched_barrier(0);
-      if (c + 1 < NCH && KC * (c + 1) < j)
-        load_basis_chunk<KC, PPT, T>(vb[(c + 1) & 1], VB, pp, KC * (c + 1), j, kU);
+      if (c + NB - 1 < NCH && KC * (c + NB - 1) < j)
+        load_basis_chunk<KC, PPT, T>(vb[(c + NB - 1) % NB], VB, pp, KC * (c + NB - 1), j, kU);
       if (KC * c < j) {
         double prod[16];
 #pragma unroll
@@ -666,8 +695,8 @@ __global__ __launch_bounds__(kBlock) void k_dots(const Job* jobs, const SysDesc*
           prod[KC + q] = 0.0;
 #pragma unroll
           for (int i = 0; i < PPT; ++i) {
-            prod[q] = fma((double)vb[c & 1][q][i], uu[i], prod[q]);
-            prod[KC + q] = fma((double)vb[c & 1][q][i], ww[i], prod[KC + q]);
+            prod[q] = fma((double)vb[c % NB][q][i], uu[i], prod[q]);
+            prod[KC + q] = fma((double)vb[c % NB][q][i], ww[i], prod[KC + q]);
           }
         }
         acc[c] += rs16(prod);
@@ -975,11 +1004,20 @@ __global__ __launch_bounds__(kBlock) void k_extend(const Job* jobs, const SysDes
       qc[i][1] = pr.qy;
       qc[i][2] = pr.qz;
     }
-    constexpr int KC = 8, NCH = MM / KC;
-    T vb[2][KC][PPT];
+    constexpr int KC = 8, NCH = MM / KC, NB = kSweepBufs;
+    // the halo of u_j first, then the first chunks (in flight across the
+    // LDS write)
+    HaloStage<TL, T> hs;
+    hs.issue(VB, kU, g, ox, oy, oz);
+    T vb[NB][KC][PPT];
+    __builtin_amdgcn_sched_barrier(0);
     load_basis_chunk<KC, PPT, T>(vb[0], VB, pp, 0, j, kU);
+#pragma unroll
+    for (int c = 1; c < NB - 1; ++c)
+      if (c < NCH && KC * c < j) load_basis_chunk<KC, PPT, T>(vb[c], VB, pp, KC * c, j, kU);
+    __builtin_amdgcn_sched_barrier(0);
     __syncthreads();
-    load_tile_buf<TL, T>(L, VB, kU, g, ox, oy, oz);
+    hs.write(L);
     __syncthreads();
     // a = V s, b = V cY at this thread's points, slot by slot in order (the
     // chunks past j hold zero coefficients only and are skipped)
@@ -988,18 +1026,18 @@ __global__ __launch_bounds__(kBlock) void k_extend(const Job* jobs, const SysDes
     for (int i = 0; i < PPT; ++i) a[i] = b[i] = 0.0;
 #pragma unroll
     for (int c = 0; c < NCH; ++c) {
-      // the scheduler keeps each chunk's loads here (one chunk ahead), not
-      // hoisted to the top, so only two chunks occupy registers
+      // the scheduler keeps each chunk's loads here (NB - 1 chunks ahead),
+      // not hoisted to the top, so only NB chunks occupy registers
       __builtin_amdgcn_sched_barrier(0);
-      if (c + 1 < NCH && KC * (c + 1) < j)
-        load_basis_chunk<KC, PPT, T>(vb[(c + 1) & 1], VB, pp, KC * (c + 1), j, kU);
+      if (c + NB - 1 < NCH && KC * (c + NB - 1) < j)
+        load_basis_chunk<KC, PPT, T>(vb[(c + NB - 1) % NB], VB, pp, KC * (c + NB - 1), j, kU);
       if (KC * c < j) {
 #pragma unroll
         for (int q = 0; q < KC; ++q)
 #pragma unroll
           for (int i = 0; i < PPT; ++i) {
-            a[i] = fma((double)vb[c & 1][q][i], sY[KC * c + q], a[i]);
-            b[i] = fma((double)vb[c & 1][q][i], cY[KC * c + q], b[i]);
+            a[i] = fma((double)vb[c % NB][q][i], sY[KC * c + q], a[i]);
+            b[i] = fma((double)vb[c % NB][q][i], cY[KC * c + q], b[i]);
           }
       }
     }
