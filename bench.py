@@ -376,6 +376,9 @@ def legs_on_window(mlg, sv, fields, prevs, t0, args):
     K = sv.net_cfg.skip_modes
     fp32 = mlg.Opts(restart_m=args.restart, precision=mlg.MLG_FP32_IR, rtol=args.rtol)
     fp64 = mlg.Opts(restart_m=args.restart, precision=mlg.MLG_FP64, rtol=args.rtol)
+    # the FP64 baselines in their own tuned launch configuration (the FP32
+    # ones share the stream's)
+    mlg.mlg_autotune(grid, fp64)
     ws = {p: mlg.workspace(mlg.gmres_workspace_bytes(grid, o)) for p, o in
           ((0, fp64), (1, fp32))}
     # the band at its analytic optimum (c_u / lambda_kl of the 5-point

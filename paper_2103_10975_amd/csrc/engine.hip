@@ -303,6 +303,7 @@ __global__ void k_setup(const SysInit* init, const SysDesc* sd, unsigned int* hd
   C->s = Summary{MLG_OK, 0, 0, 0.0, 0.0, 0.0, 0.0, 0.0};
   C->phase = PH_INIT;
   C->cycle_end = 0;
+  C->tail_done = 0;
   C->k = 0;
   C->m = m;
   C->fixed = fixed;
@@ -319,13 +320,23 @@ __global__ void k_setup(const SysInit* init, const SysDesc* sd, unsigned int* hd
     hdr[0] = 0u;
     hdr[1] = 0u;
     hdr[2] = 0u;
+    hdr[3] = 0u;
   }
 }
 
-// One restart cycle of every system; `setup` first sets up the control
-// blocks from the uploaded init records (the first cycle of a call).
-static void enqueue_cycle(hipStream_t s, const Plan& P, const DevPlan& D, int prec, int m,
-                          bool setup = false) {
+// A part of a restart cycle of every system: with `head`, the cycle's start
+// (new right-hand sides, initial residual, first direction); steps j0..j1-1;
+// then the end of the cycle (after the final coefficients when j1 = m),
+// which the device runs only once the cycle has stopped stepping.  `setup`
+// first sets up the control blocks from the uploaded init records (the first
+// part of a call).  A whole cycle is part(head, 0, m).
+struct CyclePart {
+  bool setup, head;
+  int j0, j1;
+};
+
+static void enqueue_part(hipStream_t s, const Plan& P, const DevPlan& D, int prec, int m,
+                         CyclePart cp) {
   std::vector<GroupFn> fns;
   for (auto& G : P.groups) fns.push_back(group_fn(G.dim, G.tile, prec));
   const size_t ng = P.groups.size();
@@ -336,13 +347,15 @@ static void enqueue_cycle(hipStream_t s, const Plan& P, const DevPlan& D, int pr
   const int ns = P.nsys;
   int maxblk = 1;
   for (auto& G : P.groups) maxblk = std::max(maxblk, G.maxblk);
-  if (setup) k_setup<<<ns, 64, 0, s>>>(D.init, D.desc, D.hdr);
-  each(G_BEGIN, 0);
-  each(G_RESID0, 0);
-  k_rsum<true><<<ns, kReduceThreads, 0, s>>>(D.desc);
-  each(G_START, 0);
-  each(G_DOTS, 0);
-  for (int j = 0; j < m; ++j) {
+  if (cp.setup) k_setup<<<ns, 64, 0, s>>>(D.init, D.desc, D.hdr);
+  if (cp.head) {
+    each(G_BEGIN, 0);
+    each(G_RESID0, 0);
+    k_rsum<true><<<ns, kReduceThreads, 0, s>>>(D.desc);
+    each(G_START, 0);
+    each(G_DOTS, 0);
+  }
+  for (int j = cp.j0; j < cp.j1; ++j) {
     // the grid-wide sums of step j: coef(j), or sums(j) for groups whose step
     // runs in the split form (one launch over all systems when every group
     // takes the same form)
@@ -371,16 +384,24 @@ static void enqueue_cycle(hipStream_t s, const Plan& P, const DevPlan& D, int pr
       }
     }
   }
-  launch_coef(s, ns, nullptr, maxblk, D.desc, m);
+  if (cp.j1 == m) launch_coef(s, ns, nullptr, maxblk, D.desc, m);
   each(G_UPDATE, m);
   each(G_RESID, 0);
   k_rsum<false><<<ns, kReduceThreads, 0, s>>>(D.desc);
+}
+
+static void enqueue_cycle(hipStream_t s, const Plan& P, const DevPlan& D, int prec, int m,
+                          bool setup = false) {
+  enqueue_part(s, P, D, prec, m, CyclePart{setup, true, 0, m});
 }
 
 // ------------------------------------------------------------------ caches
 struct Runtime {
   std::mutex mu;
   std::map<std::string, std::pair<hipGraphExec_t, unsigned long long>> graphs;
+  // Arnoldi steps each restart cycle of the last single right-hand side
+  // solved with a plan (by plan key): where the next solve splits its cycles
+  std::map<std::string, std::vector<int>> steps_hist;
   unsigned long long tick = 0;
   std::map<int, hipStream_t> capture_streams;
   std::vector<std::pair<void*, size_t>> pinned_free;
@@ -416,11 +437,11 @@ static std::string plan_key(int dev, const void* ws, const Plan& P, int prec, in
   return k;
 }
 
-// Captured graph of one restart cycle for this workspace and plan (with the
-// set-up of the control blocks in front when `setup`).
-static hipGraphExec_t cycle_graph(const std::string& key0, int dev, const Plan& P, const DevPlan& D,
-                                  int prec, int m, bool setup) {
-  const std::string key = key0 + (setup ? "+setup" : "");
+// Captured graph of a cycle part for this workspace and plan.
+static hipGraphExec_t part_graph(const std::string& key0, int dev, const Plan& P, const DevPlan& D,
+                                 int prec, int m, CyclePart cp) {
+  const std::string key = key0 + "/" + std::to_string(cp.setup) + std::to_string(cp.head) + "," +
+                          std::to_string(cp.j0) + "," + std::to_string(cp.j1);
   auto& R = rt();
   std::lock_guard<std::mutex> lk(R.mu);
   auto it = R.graphs.find(key);
@@ -428,7 +449,7 @@ static hipGraphExec_t cycle_graph(const std::string& key0, int dev, const Plan& 
     it->second.second = ++R.tick;
     return it->second.first;
   }
-  if (R.graphs.size() >= 32) {                      // evict the least recently used
+  if (R.graphs.size() >= 128) {                     // evict the least recently used
     auto victim = R.graphs.begin();
     for (auto i = R.graphs.begin(); i != R.graphs.end(); ++i)
       if (i->second.second < victim->second.second) victim = i;
@@ -438,7 +459,7 @@ static hipGraphExec_t cycle_graph(const std::string& key0, int dev, const Plan& 
   hipStream_t cs = capture_stream(dev);
   hipGraph_t graph;
   MLG_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeRelaxed));
-  enqueue_cycle(cs, P, D, prec, m, setup);
+  enqueue_part(cs, P, D, prec, m, cp);
   hipError_t ce = hipStreamEndCapture(cs, &graph);
   MLG_HIP(ce);
   hipGraphExec_t exec;
@@ -563,13 +584,7 @@ int batched_solve(int nsys, const mlg_system* sys, const mlg_opts* opts, void* w
 
   Pinned stage(stage_bytes(P));
   upload_plan(P, D, nsys, sys, *opts, stream, (char*)stage.p);
-  // the first cycle sets up the control blocks (a graph of its own)
-  hipGraphExec_t exec = nullptr, exec_first = nullptr;
-  if (!P.direct) {
-    const std::string key = plan_key(dev, ws, P, opts->precision, m);
-    exec_first = cycle_graph(key, dev, P, D, opts->precision, m, true);
-    exec = cycle_graph(key, dev, P, D, opts->precision, m, false);
-  }
+  const std::string key = plan_key(dev, ws, P, opts->precision, m);
   // Each poll copies the header -- and, for up to kStatsInPoll right-hand
   // sides, the statistics behind it in the workspace -- into one of two
   // pinned slots, so that a finished solve needs no further round trip.
@@ -595,63 +610,139 @@ int batched_solve(int nsys, const mlg_system* sys, const mlg_opts* opts, void* w
   // guards the host against a solver that stopped making progress.
   long long rhs_total = P.total_rhs;
   const long long max_groups = (limit + 2) * rhs_total / poll + 8;
-  // Groups of `poll` cycles are launched one ahead of the group whose header
-  // the host reads, so the device never waits for the host -- except when the
-  // group read forecasts (header [2]) that the group in flight finishes every
-  // system: then the host waits for it before launching more, which saves a
-  // whole cycle of no-op kernels at the end of a solve, and costs one host
-  // round trip when the forecast was wrong.
   int slot = 0, queue[2] = {0, 0}, nq = 0;
   bool first = true;
-  auto launch = [&]() {
-    for (int c = 0; c < poll; ++c) {
+  // enqueue cycle parts (graph replays, or direct launches), then the poll
+  auto launch_parts = [&](const CyclePart* parts, int n) {
+    for (int c = 0; c < n; ++c) {
+      CyclePart cp = parts[c];
+      cp.setup = first;
+      first = false;
       if (P.direct) {
-        enqueue_cycle(stream, P, D, opts->precision, m, first);
+        enqueue_part(stream, P, D, opts->precision, m, cp);
         MLG_HIP(hipGetLastError());
       } else {
-        MLG_HIP(hipGraphLaunch(first ? exec_first : exec, stream));
+        MLG_HIP(hipGraphLaunch(part_graph(key, dev, P, D, opts->precision, m, cp), stream));
       }
-      first = false;
     }
     MLG_HIP(hipMemcpyAsync(slot_ptr(slot), D.hdr, poll_bytes, hipMemcpyDeviceToHost, stream));
     MLG_HIP(hipEventRecord(ev[slot], stream));
     queue[nq++] = slot;
     slot ^= 1;
   };
-  // A single right-hand side launches no speculative second cycle before the
-  // first one has been read: a good initial guess finishes in one cycle, and
-  // the speculative one's idle kernels would then delay the end of the solve
-  // (a solve that needs more cycles pays one host round trip, once).
-  bool forecast = P.total_rhs == 1;
-  unsigned int last_progress = 0;
-  long long grp = 0, reads = 0;
+  const CyclePart whole{false, true, 0, m};
+  std::vector<CyclePart> group(poll, whole);
+  auto launch = [&]() { launch_parts(group.data(), poll); };
   int done_slot = -1;
-  launch();
-  ++grp;
-  while (true) {
-    if (!forecast && nq < 2 && grp < max_groups) {
-      launch();
-      ++grp;
+  if (P.total_rhs == 1) {
+    // A single right-hand side.  A cycle that the plan's previous solve ended
+    // early is split after the steps it took then (plus a margin): the first
+    // part ends with the cycle's end, which the device runs only if the cycle
+    // stopped within it, and the rest of the cycle is launched only if the
+    // header shows that it did not -- so the steps that a stopped cycle would
+    // skip are rarely launched at all.  Whole cycles are launched one ahead
+    // of the one whose header the host reads, unless that read forecasts
+    // (header [2]) that the cycle in flight finishes the right-hand side (the
+    // first cycle is read before the next is launched: a good initial guess
+    // finishes in one).
+    constexpr int kSplitMargin = 2;
+    std::vector<int> hist;
+    {
+      std::lock_guard<std::mutex> lk(rt().mu);
+      auto it = rt().steps_hist.find(key);
+      if (it != rt().steps_hist.end()) hist = it->second;
     }
-    const int p = queue[0];
-    queue[0] = queue[1];
-    --nq;
-    MLG_HIP(hipEventSynchronize(ev[p]));
-    volatile unsigned int* host = slot_hdr(p);
-    const unsigned int fin = host[0], prog = host[1], fc = host[2];
-    if (fin >= (unsigned)nsys) {
-      done_slot = p;
-      break;
+    std::vector<int> took;
+    unsigned int progress = 0;
+    struct Entry {
+      int slot, cyc;
+      bool first_part;              // the first part of a split cycle
+    };
+    std::vector<Entry> q;
+    long long next = 0;
+    auto split_of = [&](long long c) { return c < (long long)hist.size() ? hist[c] + kSplitMargin : m; };
+    auto launch_cycle = [&](long long c) {
+      const int sp = split_of(c);
+      const CyclePart part = sp < m ? CyclePart{false, true, 0, sp} : whole;
+      launch_parts(&part, 1);
+      q.push_back(Entry{queue[nq - 1], (int)c, sp < m});
+      --nq;                         // this path keeps its own queue
+    };
+    bool ahead_ok = false;
+    launch_cycle(next++);
+    while (true) {
+      if (q.size() == 1 && !q[0].first_part && ahead_ok && next < max_groups)
+        launch_cycle(next++);
+      const Entry e = q.front();
+      q.erase(q.begin());
+      MLG_HIP(hipEventSynchronize(ev[e.slot]));
+      volatile unsigned int* host = slot_hdr(e.slot);
+      const unsigned int fin = host[0], prog = host[1], fc = host[2], ends = host[3];
+      const bool over = fin >= 1u || ends >= (unsigned)(e.cyc + 1);
+      if (over) took.push_back((int)(prog - progress));
+      if (fin >= 1u) {
+        done_slot = e.slot;
+        break;
+      }
+      if (prog == progress)
+        throw HipError{hipErrorUnknown, "solver made no progress in a restart cycle"};
+      if (over) progress = prog;
+      ahead_ok = fin + fc < 1u;
+      if (!over) {
+        // a split cycle still stepping: its rest (nothing was launched
+        // behind its first part)
+        const CyclePart rest{false, false, split_of(e.cyc), m};
+        launch_parts(&rest, 1);
+        q.push_back(Entry{queue[nq - 1], e.cyc, false});
+        --nq;
+      } else if (q.empty()) {
+        if (next >= max_groups) break;
+        launch_cycle(next++);
+      }
     }
-    if (reads > 0 && prog == last_progress)
-      throw HipError{hipErrorUnknown, "solver made no progress in a restart cycle"};
-    ++reads;
-    last_progress = prog;
-    forecast = fin + fc >= (unsigned)nsys;
-    if (nq == 0) {
-      if (grp >= max_groups) break;
-      launch();
-      ++grp;
+    // a cycle launched ahead runs idle; it must pass before the slots are reused
+    if (!q.empty()) MLG_HIP(hipStreamSynchronize(stream));
+    if (done_slot >= 0) {
+      std::lock_guard<std::mutex> lk(rt().mu);
+      rt().steps_hist[key] = took;
+    }
+  } else {
+    // Groups of `poll` cycles are launched one ahead of the group whose
+    // header the host reads, so the device never waits for the host --
+    // except when the group read forecasts (header [2]) that the group in
+    // flight finishes every system: then the host waits for it before
+    // launching more, which saves a whole cycle of no-op kernels at the end
+    // of a solve, and costs one host round trip when the forecast was wrong.
+    bool forecast = false;
+    unsigned int last_progress = 0;
+    long long grp = 0, reads = 0;
+    launch();
+    ++grp;
+    while (true) {
+      if (!forecast && nq < 2 && grp < max_groups) {
+        launch();
+        ++grp;
+      }
+      const int p = queue[0];
+      queue[0] = queue[1];
+      --nq;
+      MLG_HIP(hipEventSynchronize(ev[p]));
+      volatile unsigned int* host = slot_hdr(p);
+      const unsigned int fin = host[0], prog = host[1], fc = host[2];
+      if (fin >= (unsigned)nsys) {
+        done_slot = p;
+        break;
+      }
+      if (reads > 0 && prog == last_progress)
+        throw HipError{hipErrorUnknown, "solver made no progress in a restart cycle"};
+      ++reads;
+      last_progress = prog;
+      forecast = fin + fc >= (unsigned)nsys;
+      if (nq == 0) {
+        if (grp >= max_groups) break;
+        launch();
+        ++grp;
+      }
     }
   }
   // a group still in flight (launched ahead) runs idle; it must pass before
@@ -803,7 +894,7 @@ int solve_static(const mlg_grid* grid, const double* b, double* x, const mlg_opt
 // with a zero tolerance, so every timed launch does its full work.
 // descs[i] is the system descriptor pointing at copy i.
 __global__ void k_bench_setup(const SysDesc* src_desc, SysDesc* descs, Ctrl* copies, int n,
-                              int j) {
+                              int j, int tail) {
   const int i = blockIdx.x;
   if (i >= n) return;
   const unsigned int* s = (const unsigned int*)src_desc->C;
@@ -818,7 +909,10 @@ __global__ void k_bench_setup(const SysDesc* src_desc, SysDesc* descs, Ctrl* cop
   if (threadIdx.x == 0) {
     c->phase = PH_RUN;
     c->rhs = 0;
-    c->cycle_end = 0;
+    // the cycle-end kernels (update, residual) run on a stopped cycle whose
+    // end is pending; the step kernels on a running one
+    c->cycle_end = tail;
+    c->tail_done = 0;
     c->tol_abs = 0.0;
     c->fixed = 1;
     c->limit = 1LL << 62;
@@ -880,9 +974,10 @@ double kernel_bench(const mlg_grid* grid, const mlg_opts* opts, void* ws, size_t
     ~Gd() { hipEventDestroy(a); hipEventDestroy(b); }
   } guard{e0, e1};
   const int jj = kind == MLG_K_UPDATE ? opts->restart_m : j;
-  k_bench_setup<<<reps, 256, 0, stream>>>(D.desc, descs, copies, reps, jj);
+  const int tail = kind == MLG_K_UPDATE || kind == MLG_K_RESIDUAL ? 1 : 0;
+  k_bench_setup<<<reps, 256, 0, stream>>>(D.desc, descs, copies, reps, jj, tail);
   enqueue_one(fn, stream, kind, nb, D.jobs[0], descs, jj);    // untimed warm-up launch
-  k_bench_setup<<<reps, 256, 0, stream>>>(D.desc, descs, copies, reps, jj);
+  k_bench_setup<<<reps, 256, 0, stream>>>(D.desc, descs, copies, reps, jj, tail);
   MLG_HIP(hipEventRecord(e0, stream));
   for (int i = 0; i < reps; ++i) enqueue_one(fn, stream, kind, nb, D.jobs[0], descs + i, jj);
   MLG_HIP(hipEventRecord(e1, stream));

@@ -61,7 +61,8 @@ struct Summary {
 struct Ctrl {
   Summary s;            // statistics of the current right-hand side
   int phase;
-  int cycle_end;        // the current cycle stopped stepping
+  int cycle_end;        // the current cycle stopped stepping (until the next cycle opens)
+  int tail_done;        // the current cycle's end (update, true residual) has run
   int k;                // Arnoldi columns of the current cycle
   int m, fixed, guess;
   int rhs, nrhs;        // current / total right-hand sides of this system
@@ -74,7 +75,8 @@ struct Ctrl {
   unsigned int* done;   // [0]: systems with every right-hand side solved,
                         // [1]: progress count (Arnoldi columns + finished RHS),
                         // [2]: systems forecast to finish in the next cycle
-                        //      (counted by this cycle's k_rsum<false>)
+                        //      (counted by this cycle's k_rsum<false>),
+                        // [3]: cycle ends run (update + true residual), all systems
   // first-projection coefficients h_{j-1}: step j reads row j & 1 and writes
   // row (j + 1) & 1, so a launch may read and write them at once
   double hprev[2][kMaxRestart + 1];
@@ -373,6 +375,13 @@ __device__ __forceinline__ Mine mine(const Job* jobs, const SysDesc* sd) {
   return me;
 }
 
+// The end of a cycle (update, true residual and its test) runs once, after
+// the cycle stopped stepping: a launch sequence may place it after any step.
+template <class CP>
+__device__ __forceinline__ bool cycle_tail_pending(const CP& C) {
+  return C->phase == PH_RUN && C->cycle_end && !C->tail_done;
+}
+
 // A finished right-hand side: record its statistics and move on to the next
 // one (phase INIT) or mark the system done.  One thread.
 __device__ inline void finish_rhs(gptr<Ctrl> C) {
@@ -484,7 +493,7 @@ template <class T, class TL, bool INIT>
 __global__ __launch_bounds__(kBlock) void k_resid(const Job* jobs, const SysDesc* sd) {
   const Mine me = mine(jobs, sd);
   const gptr<const Ctrl> C = gmem((const Ctrl*)me.S->C);
-  if (C->phase != (INIT ? PH_INIT : PH_RUN)) return;
+  if (INIT ? C->phase != PH_INIT : !cycle_tail_pending(C)) return;
   constexpr int PPT = TL::PPT;
   __shared__ double L[TL::LSZ];
   __shared__ double red[4 * 4];
@@ -534,9 +543,17 @@ template <bool INIT>
 __global__ __launch_bounds__(kReduceThreads) void k_rsum(const SysDesc* sd) {
   const SysDesc* S = sd + blockIdx.x;
   const gptr<Ctrl> C = gmem(S->C);
-  // k_rsum<true> opens every cycle: clear the cycle's forecast count
+  // k_rsum<true> opens every cycle: clear the cycle's forecast count, and
+  // let a system that continues its right-hand side step again
   if (INIT && blockIdx.x == 0 && threadIdx.x == 0) C->done[2] = 0u;
-  if (C->phase != (INIT ? PH_INIT : PH_RUN)) return;
+  if (INIT && C->phase == PH_RUN) {
+    if (threadIdx.x == 0) {
+      C->cycle_end = 0;
+      C->tail_done = 0;
+    }
+    return;
+  }
+  if (INIT ? C->phase != PH_INIT : !cycle_tail_pending(C)) return;
   __shared__ double fin[2];
   reduce_partials(gmem((const double*)S->part), S->g.nblk, INIT ? 2 : 1, fin);
   if (threadIdx.x != 0) return;
@@ -544,7 +561,15 @@ __global__ __launch_bounds__(kReduceThreads) void k_rsum(const SysDesc* sd) {
   C->beta = beta;
   C->g[0] = beta;
   C->k = 0;
-  C->cycle_end = 0;
+  if (INIT) {
+    C->cycle_end = 0;
+    C->tail_done = 0;
+  } else {
+    // the cycle stays stopped (its remaining steps, if launched, do nothing)
+    // until the next cycle opens it
+    C->tail_done = 1;
+    atomicAdd(C->done + 3, 1u);
+  }
   if (INIT) {
     const double bnorm = sqrt(fin[1]);
     C->s.status = MLG_OK;
@@ -1196,13 +1221,11 @@ __global__ __launch_bounds__(kBlock) void k_step(const Job* jobs, const SysDesc*
 #pragma unroll
       for (int rr = 0; rr < RPT; ++rr) vg[k][rr] = VB.load(kk, (unsigned)rp[rr]);
     }
-    // ---- stage u_j (the previous tile's readers of L2/L1 are done)
+    // (the previous tile's readers of L2/L1 are done)
     __syncthreads();
-#pragma unroll
-    for (int h = 0; h < HPT; ++h) {
-      const int e = threadIdx.x + kBlock * h;
-      if (e < H2::SZ) L2[e] = hin[h] ? (double)hv[h] : 0.0;
-    }
+    // ---- the step's coefficients first (first tile): their inputs were
+    // loaded before the tile's data, so the update runs while the tile's
+    // loads are in flight
     if constexpr (FIRST) {
       if constexpr (SPLIT) {
         // the coefficient inputs go to LDS before any branch, so that waiting
@@ -1276,6 +1299,12 @@ __global__ __launch_bounds__(kBlock) void k_step(const Job* jobs, const SysDesc*
         }
         ainv = 1.0 / sAlpha;
       }
+    }
+    // ---- stage u_j
+#pragma unroll
+    for (int h = 0; h < HPT; ++h) {
+      const int e = threadIdx.x + kBlock * h;
+      if (e < H2::SZ) L2[e] = hin[h] ? (double)hv[h] : 0.0;
     }
     __syncthreads();
     const double cyj = sCyj;
@@ -1389,7 +1418,7 @@ template <class T, class TL, int MM>
 __global__ __launch_bounds__(kBlock) void k_update(const Job* jobs, const SysDesc* sd) {
   const Mine me = mine(jobs, sd);
   const gptr<const Ctrl> C = gmem((const Ctrl*)me.S->C);
-  if (C->phase != PH_RUN) return;
+  if (!cycle_tail_pending(C)) return;
   constexpr int PPT = TL::PPT;
   __shared__ double ys[MM];
   const int k = C->k;

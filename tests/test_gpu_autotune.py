@@ -112,3 +112,36 @@ def test_launch_modes_batched(mlg):
     assert sg == sd
     assert all(np.array_equal(a, c) for a, c in zip(xg, xd))
 
+
+
+@pytest.mark.parametrize("precision,launch", [(0, 1), (1, 1), (1, 2)])
+def test_split_cycles_give_the_same_bits(mlg, precision, launch):
+    """A single right-hand side whose workspace has solved before splits each
+    restart cycle after the steps the previous solve took there (the rest of
+    the cycle launched only when needed).  The kernels and their order are
+    those of whole cycles: solves after a shorter one (cycles longer than the
+    split) and after a longer one (cycles that stop inside the first part)
+    give the bits of the static entry point, which always runs whole cycles."""
+    print("split cycles", precision, launch, flush=True)
+    shape, m, tol = (200, 150), 20, 1e-9
+    grid = mlg.grid_of(shape)
+    opts = mlg.Opts(restart_m=m, rtol=tol, precision=precision, launch=launch)
+    f = [torch.from_numpy(DriftingGaussians(shape, 3, 0.06, seed=11).field(t)).cuda()
+         for t in range(3)]
+    ws = mlg.workspace(mlg.gmres_workspace_bytes(grid, opts))
+    zero = torch.zeros_like(f[0])
+    x = zero.clone()
+    mlg.gmres_solve(grid, f[0], x, opts, ws)
+    close = x.clone()
+    # from a close guess (short cycles), from zero (cycles longer than that
+    # history), from a close guess again (stops inside the first part)
+    for b, x0 in [(f[1], close), (f[2], zero), (f[1], close), (f[1], close)]:
+        xs = x0.clone()
+        ss = mlg.gmres_solve(grid, b, xs, opts, ws)
+        xw = x0.clone()
+        sw = mlg.gmres_solve_static(grid, b, xw, opts)
+        torch.cuda.synchronize()
+        assert ss.status == 0 and sw.status == 0
+        assert ss.iters == sw.iters and ss.cycles == sw.cycles
+        assert ss.relres_true == sw.relres_true and ss.relres_first_cycle == sw.relres_first_cycle
+        assert torch.equal(xs, xw)
