@@ -1707,12 +1707,13 @@ __device__ __forceinline__ double gate_of(const double* gate) {
 // 0; g the output gain), else Y = X.  A workgroup takes 32 rows of one image
 // (8 per wavefront), lanes l; Y and the basis values of the 32 rows come
 // through LDS, 16 modes k at a time.
+template <int KMAX, int RPW>
 __global__ __launch_bounds__(256) void k_band_inv(const double* X, const double* Cc,
                                                   const double* band, const double* gate,
                                                   const double* Sy, double* Z, int H, int K,
                                                   double alpha) {
-  constexpr int KC = 16, KMAX = 128, RPW = 8, RB = 4 * RPW;
-  constexpr int PY = KC * KMAX / 256, PS = KC * RB / 256;
+  constexpr int KC = 16, RB = 4 * RPW;
+  constexpr int PY = KC * KMAX / 256, PS = (KC * RB + 255) / 256;
   __shared__ double yl[KC][KMAX];
   __shared__ double syl[KC][RB];
   const int nrb = (H + RB - 1) / RB;
@@ -1722,9 +1723,10 @@ __global__ __launch_bounds__(256) void k_band_inv(const double* X, const double*
   const double* Xb = X + (size_t)b * K * K;
   const double* Cb = Cc ? Cc + (size_t)b * K * K : nullptr;
   const int np = (K + 63) / 64;
-  double s[2][RPW];
+  constexpr int NP = KMAX / 64;
+  double s[NP][RPW];
 #pragma unroll
-  for (int p = 0; p < 2; ++p)
+  for (int p = 0; p < NP; ++p)
 #pragma unroll
     for (int r = 0; r < RPW; ++r) s[p][r] = 0.0;
   for (int k0 = 0; k0 < K; k0 += KC) {
@@ -1744,7 +1746,7 @@ __global__ __launch_bounds__(256) void k_band_inv(const double* X, const double*
     double sv[PS];
 #pragma unroll
     for (int u = 0; u < PS; ++u) {
-      const int e = threadIdx.x + 256 * u, kk = e / RB, ii = e % RB;
+      const int e = threadIdx.x + 256 * u, kk = min(e / RB, KC - 1), ii = e % RB;
       sv[u] = Sy[(size_t)min(k0 + kk, K - 1) * H + min(i0 + ii, H - 1)];
     }
     __syncthreads();                                      // the previous chunk's readers are done
@@ -1761,11 +1763,11 @@ __global__ __launch_bounds__(256) void k_band_inv(const double* X, const double*
 #pragma unroll
     for (int u = 0; u < PS; ++u) {
       const int e = threadIdx.x + 256 * u, kk = e / RB, ii = e % RB;
-      syl[kk][ii] = (k0 + kk < K && i0 + ii < H) ? sv[u] : 0.0;
+      if (e < KC * RB) syl[kk][ii] = (k0 + kk < K && i0 + ii < H) ? sv[u] : 0.0;
     }
     __syncthreads();
 #pragma unroll
-    for (int p = 0; p < 2; ++p) {
+    for (int p = 0; p < NP; ++p) {
       if (p >= np) break;
       const int lc = min(p * 64 + lane, K - 1);
 #pragma unroll 4
@@ -1777,7 +1779,7 @@ __global__ __launch_bounds__(256) void k_band_inv(const double* X, const double*
     }
   }
 #pragma unroll
-  for (int p = 0; p < 2; ++p) {
+  for (int p = 0; p < NP; ++p) {
     const int l = p * 64 + lane;
     if (p >= np || l >= K) continue;
 #pragma unroll
@@ -1786,6 +1788,19 @@ __global__ __launch_bounds__(256) void k_band_inv(const double* X, const double*
       if (i < H) Z[((size_t)b * H + i) * K + l] = alpha * s[p][r];
     }
   }
+}
+
+// k_band_inv over 8 rows per workgroup (a B x H/8 grid), the mode tile sized
+// to the band (up to 64 or up to 128 modes)
+static void launch_band_inv(hipStream_t s, int B, const double* X, const double* Cc,
+                            const double* band, const double* gate, const double* Sy, double* Z,
+                            int H, int K, double alpha) {
+  constexpr int RPW = 2, RB = 4 * RPW;
+  const dim3 grid(B * ((H + RB - 1) / RB));
+  if (K <= 64)
+    k_band_inv<64, RPW><<<grid, 256, 0, s>>>(X, Cc, band, gate, Sy, Z, H, K, alpha);
+  else
+    k_band_inv<128, RPW><<<grid, 256, 0, s>>>(X, Cc, band, gate, Sy, Z, H, K, alpha);
 }
 
 // out[b][i][j] = g out[b][i][j] + beta sum_l Sx[l][j] Z[b][i][l] (sum and add in
@@ -2110,9 +2125,8 @@ void forward(const Net& n, const Ptrs& f, const Ptrs& u, hipStream_t s, bool gat
   const BandSpace bsp = band_space(n);
   band_project_rows_cols<double, float>(n, {r0, sv + d.B, bsp.kT, 1.0},
                                         {out, nullptr, bsp.kT2, 1.0}, bsp.kX, bsp.kC, 1.0, 1.0, s);
-  k_band_inv<<<d.B * cdiv(d.H, 32), 256, 0, s>>>(bsp.kX, bsp.kC,
-                                                 (const double*)(n.params + n.pl.band), gate,
-                                                 bsp.kSy, bsp.kZ, d.H, d.K, 2.0 / (d.H + 1));
+  launch_band_inv(s, d.B, bsp.kX, bsp.kC, (const double*)(n.params + n.pl.band), gate, bsp.kSy,
+                  bsp.kZ, d.H, d.K, 2.0 / (d.H + 1));
   k_band_out<<<dim3(band_out_blocks(d), 1), 256, 0, s>>>(
       BandOut{bsp.kZ, out, gate, 2.0 / (d.W + 1)}, BandOut{}, bsp.kSx, d.H, d.W, d.K);
 }
@@ -2177,10 +2191,8 @@ void train(const Net& n, const Ptrs& f, const Ptrs& up, const Ptrs& ut, float* l
     const double nrm = (2.0 / (d.H + 1)) * (2.0 / (d.W + 1));
     band_project_rows_cols<float, float>(n, {dout, nullptr, nullptr, 1.0}, {out, nullptr, nullptr, 1.0},
                                          bsp.kdY, bsp.kdY2, nrm, nrm, s);
-    k_band_inv<<<d.B * cdiv(d.H, 32), 256, 0, s>>>(bsp.kdY, nullptr, nullptr, nullptr, bsp.kSy,
-                                                   bsp.kZ, d.H, K, 1.0);
-    k_band_inv<<<d.B * cdiv(d.H, 32), 256, 0, s>>>(bsp.kdY2, nullptr, nullptr, nullptr, bsp.kSy,
-                                                   bsp.kZ2, d.H, K, 1.0);
+    launch_band_inv(s, d.B, bsp.kdY, nullptr, nullptr, nullptr, bsp.kSy, bsp.kZ, d.H, K, 1.0);
+    launch_band_inv(s, d.B, bsp.kdY2, nullptr, nullptr, nullptr, bsp.kSy, bsp.kZ2, d.H, K, 1.0);
     k_band_out<<<dim3(band_out_blocks(d), 2), 256, 0, s>>>(BandOut{bsp.kZ, dout, nullptr, -1.0},
                                                            BandOut{bsp.kZ2, out, nullptr, -1.0},
                                                            bsp.kSx, d.H, d.W, K);
