@@ -70,7 +70,9 @@ typedef struct {
  *   tile          0 = autotuned/default tile shape; otherwise an index into
  *                 the tile table (mlg_tile_count / mlg_tile_shape).
  *   poll_cycles   restart cycles enqueued between host polls of the
- *                 convergence flag (0 = 1).
+ *                 convergence flag (0 = 1) when a call holds several
+ *                 right-hand sides; a single one is polled after every
+ *                 cycle (or cycle part, see gmres_solve).
  *   schedule      how an Arnoldi step sweeps the basis (same arithmetic):
  *                 0 = as tuned by mlg_autotune for this grid (separate sweeps
  *                 when untuned), 1 = separate extend and dot-product sweeps,
@@ -129,6 +131,11 @@ size_t gmres_workspace_bytes(const mlg_grid* grid, const mlg_opts* opts);
  * the true residual meets rtol.  A cycle stops early when the Givens residual
  * estimate reaches rtol |b| or on breakdown; acceptance is on the recomputed
  * true residual.
+ * The library remembers, per workspace and plan, how many Arnoldi steps each
+ * cycle of the last solve took, and launches a cycle that ended early then in
+ * two parts split just after that count: the second part only if the cycle
+ * is still running after the first.  The kernels and their order are the same
+ * either way, so the result does not depend on this history.
  *   b      [n] right-hand side (read only).
  *   x      [n] initial guess on entry, solution on exit.
  *   ws     >= gmres_workspace_bytes(grid, opts) bytes, 256-byte aligned.
