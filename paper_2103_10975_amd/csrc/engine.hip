@@ -1,7 +1,7 @@
 // Host engine of restarted GMRES(m) for one or many systems: workspace plan,
-// job tables, kernel dispatch over the tile table, per-cycle HIP graphs and
-// the host polling loop.  gmres_solve is the batched engine with one system
-// and one right-hand side.
+// job tables, kernel dispatch over the tile table, HIP graphs of restart
+// cycles (or parts of them) and the host polling loop.  gmres_solve is the
+// batched engine with one system and one right-hand side.
 #include <algorithm>
 #include <chrono>
 #include <cmath>
@@ -500,6 +500,7 @@ void runtime_shutdown() {
   std::lock_guard<std::mutex> lk(R.mu);
   for (auto& kv : R.graphs) hipGraphExecDestroy(kv.second.first);
   R.graphs.clear();
+  R.steps_hist.clear();
   for (auto& kv : R.capture_streams) hipStreamDestroy(kv.second);
   R.capture_streams.clear();
   for (auto* p : R.pinned_all) hipHostFree(p);
@@ -704,7 +705,10 @@ int batched_solve(int nsys, const mlg_system* sys, const mlg_opts* opts, void* w
     if (!q.empty()) MLG_HIP(hipStreamSynchronize(stream));
     if (done_slot >= 0) {
       std::lock_guard<std::mutex> lk(rt().mu);
-      rt().steps_hist[key] = took;
+      auto& H = rt().steps_hist;
+      // a bounded table (callers may use a new workspace for every call)
+      if (H.size() >= 256 && H.find(key) == H.end()) H.erase(H.begin());
+      H[key] = took;
     }
   } else {
     // Groups of `poll` cycles are launched one ahead of the group whose
