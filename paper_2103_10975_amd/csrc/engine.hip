@@ -329,10 +329,14 @@ __global__ void k_setup(const SysInit* init, const SysDesc* sd, unsigned int* hd
 // then the end of the cycle (after the final coefficients when j1 = m),
 // which the device runs only once the cycle has stopped stepping.  `setup`
 // first sets up the control blocks from the uploaded init records (the first
-// part of a call).  A whole cycle is part(head, 0, m).
+// part of a call).  A whole cycle is part(head, 0, m).  A call with a single
+// right-hand side leaves out of the head what cannot act on it: the guess of a
+// later right-hand side (`begin`), and after its first cycle the initial
+// residual of a new one (`resid0`).
 struct CyclePart {
   bool setup, head;
   int j0, j1;
+  bool begin = true, resid0 = true;
 };
 
 static void enqueue_part(hipStream_t s, const Plan& P, const DevPlan& D, int prec, int m,
@@ -349,8 +353,8 @@ static void enqueue_part(hipStream_t s, const Plan& P, const DevPlan& D, int pre
   for (auto& G : P.groups) maxblk = std::max(maxblk, G.maxblk);
   if (cp.setup) k_setup<<<ns, 64, 0, s>>>(D.init, D.desc, D.hdr);
   if (cp.head) {
-    each(G_BEGIN, 0);
-    each(G_RESID0, 0);
+    if (cp.begin) each(G_BEGIN, 0);
+    if (cp.resid0) each(G_RESID0, 0);
     k_rsum<true><<<ns, kReduceThreads, 0, s>>>(D.desc);
     each(G_START, 0);
     each(G_DOTS, 0);
@@ -440,7 +444,8 @@ static std::string plan_key(int dev, const void* ws, const Plan& P, int prec, in
 // Captured graph of a cycle part for this workspace and plan.
 static hipGraphExec_t part_graph(const std::string& key0, int dev, const Plan& P, const DevPlan& D,
                                  int prec, int m, CyclePart cp) {
-  const std::string key = key0 + "/" + std::to_string(cp.setup) + std::to_string(cp.head) + "," +
+  const std::string key = key0 + "/" + std::to_string(cp.setup) + std::to_string(cp.head) +
+                          std::to_string(cp.begin) + std::to_string(cp.resid0) + "," +
                           std::to_string(cp.j0) + "," + std::to_string(cp.j1);
   auto& R = rt();
   std::lock_guard<std::mutex> lk(R.mu);
@@ -664,7 +669,9 @@ int batched_solve(int nsys, const mlg_system* sys, const mlg_opts* opts, void* w
     auto split_of = [&](long long c) { return c < (long long)hist.size() ? hist[c] + kSplitMargin : m; };
     auto launch_cycle = [&](long long c) {
       const int sp = split_of(c);
-      const CyclePart part = sp < m ? CyclePart{false, true, 0, sp} : whole;
+      CyclePart part = sp < m ? CyclePart{false, true, 0, sp} : whole;
+      part.begin = false;
+      part.resid0 = c == 0;
       launch_parts(&part, 1);
       q.push_back(Entry{queue[nq - 1], (int)c, sp < m});
       --nq;                         // this path keeps its own queue
