@@ -640,25 +640,44 @@ __global__ __launch_bounds__(256) void k_wgrad_in(const bf16* x, const bf16* dz,
   for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
     const int b = tile / per_img, r0 = tile % per_img;
     const int ox = (r0 % tilesx) * TX, oy = (r0 / tilesx) * TY;
-    __syncthreads();
-    for (int e = threadIdx.x; e < LY * LX; e += 256) {
-      const int gy = oy + e / LX - 1, gx = ox + e % LX - 1;
-      float v0 = 0.f, v1 = 0.f;
-      if (gy >= 0 && gy < H && gx >= 0 && gx < W) {
-        const bf16* px = x + ((size_t)b * HW + (long long)gy * W + gx) * 2;
-        v0 = bf2f(px[0]);
-        v1 = bf2f(px[1]);
-      }
-      xl[2 * e] = v0;
-      xl[2 * e + 1] = v1;
-    }
-    __syncthreads();
+    // every load of the tile first, at clamped addresses (no branch between
+    // them): this thread's four gradient channels on each of the tile's rows,
+    // then the input halo as 32-bit words (both channels of a pixel)
     const int gx = ox + l32;
-#pragma unroll 2
+    uint2 dv[TY];
+    bool okr[TY];
+#pragma unroll
     for (int r = 0; r < TY; ++r) {
       const int gy = oy + r;
-      if (gy >= H || gx >= W) continue;
-      const uint2 du = *reinterpret_cast<const uint2*>(dz + ((size_t)b * HW + (long long)gy * W + gx) * C + dg * 4);
+      okr[r] = gy < H && gx < W;
+      const long long pix = (long long)min(gy, H - 1) * W + min(gx, W - 1);
+      dv[r] = *reinterpret_cast<const uint2*>(dz + ((size_t)b * HW + pix) * C + dg * 4);
+    }
+    constexpr int NH = (LY * LX + 255) / 256;
+    unsigned int hw[NH];
+    bool hin[NH];
+#pragma unroll
+    for (int h = 0; h < NH; ++h) {
+      const int e = threadIdx.x + 256 * h;
+      const int gy = oy + e / LX - 1, gx2 = ox + e % LX - 1;
+      hin[h] = e < LY * LX && gy >= 0 && gy < H && gx2 >= 0 && gx2 < W;
+      const long long pix = hin[h] ? (long long)gy * W + gx2 : 0;
+      hw[h] = *reinterpret_cast<const unsigned int*>(x + ((size_t)b * HW + pix) * 2);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int h = 0; h < NH; ++h) {
+      const int e = threadIdx.x + 256 * h;
+      if (e < LY * LX) {
+        xl[2 * e] = hin[h] ? __uint_as_float(hw[h] << 16) : 0.f;
+        xl[2 * e + 1] = hin[h] ? __uint_as_float(hw[h] & 0xffff0000u) : 0.f;
+      }
+    }
+    __syncthreads();
+#pragma unroll 2
+    for (int r = 0; r < TY; ++r) {
+      // rows outside the grid add exact zeros (finite inputs)
+      const uint2 du = okr[r] ? dv[r] : make_uint2(0u, 0u);
       const float d4[4] = {__uint_as_float(du.x << 16), __uint_as_float(du.x & 0xffff0000u),
                            __uint_as_float(du.y << 16), __uint_as_float(du.y & 0xffff0000u)};
 #pragma unroll
