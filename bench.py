@@ -162,13 +162,33 @@ def roofline_of(kr):
             "cycle_GBs_own": own / (us * 1e-6) / 1e9}
 
 
+def copy_rate(nbytes=256 << 20, reps=5):
+    """HBM rate of a plain device-to-device copy (torch's copy kernel), read +
+    write bytes over the HIP-event time of one copy (median of `reps`)."""
+    a = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda").fill_(1.0)
+    b = torch.empty_like(a)
+    b.copy_(a)
+    s = torch.cuda.current_stream()
+    ts = []
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(s)
+        b.copy_(a)
+        e1.record(s)
+        e1.synchronize()
+        ts.append(e0.elapsed_time(e1) * 1e-3)
+    del a, b
+    torch.cuda.empty_cache()
+    return 2 * nbytes / statistics.median(ts) / 1e9
+
+
 def scale_rooflines(mlg, seed):
     """Per-step rooflines of one restart cycle at the large single-system
     sizes, whose Krylov basis does not fit the 256 MB last-level cache:
     1024^2 FP64 GMRES(30), 2048^2 and 160^3 FP32 basis GMRES(40), each in its
     autotuned launch configuration, on a drifting-Gaussian right-hand side."""
     from synthetic import DriftingGaussians
-    out = {}
+    out = {"copy_reference_GBs": copy_rate()}
     for shape, prec, m, src, sigma in [((1024, 1024), mlg.MLG_FP64, 30, 5, 0.02),
                                        ((2048, 2048), mlg.MLG_FP32_IR, 40, 5, 0.02),
                                        ((160, 160, 160), mlg.MLG_FP32_IR, 40, 5, 0.03)]:
@@ -181,6 +201,8 @@ def scale_rooflines(mlg, seed):
         r.update({"frac": r["achieved"] / HBM_PEAK_GBS,
                   "cycle_frac_cgs2": r["cycle_GBs_cgs2"] / HBM_PEAK_GBS,
                   "cycle_frac_own": r["cycle_GBs_own"] / HBM_PEAK_GBS,
+                  # the bytes the kernel moves against a plain device copy
+                  "kernel_own_vs_copy": r["achieved_own_bytes"] / out["copy_reference_GBs"],
                   "us_per_step": r["cycle_us"] / m,
                   "tile": list(mlg.mlg_tile_shape(len(shape), tile - 1)),
                   "fused_steps": bin(fused).count("1"), "split_steps": bin(split).count("1"),
