@@ -403,21 +403,37 @@ __global__ __launch_bounds__(256) void k_conv_in_mfma(const bf16* in, const bf16
     for (int r = 0; r < 4; ++r) bl[mt][r] = bf2f(bias[mt * 16 + 4 * lg + r]);
   }
   const uint32_t* inw = reinterpret_cast<const uint32_t*>(in) + (size_t)b * HW;   // one word per pixel
-#pragma unroll 1
+  // the neighbourhoods of all four 16-pixel steps of this wavefront are
+  // loaded first, at clamped positions (no branch between the loads); the
+  // out-of-grid taps are zeroed afterwards (the empty asm keeps the compiler
+  // from turning that select into a branch around each load)
+  uint32_t v[4][4];
+  bool in_tap[4][4];
+#pragma unroll
   for (int st = 0; st < 4; ++st) {
     const long long p = (long long)blockIdx.x * 256 + wv * 64 + st * 16 + li;
-    if ((long long)blockIdx.x * 256 + wv * 64 + st * 16 >= HW) break;    // wavefront-uniform
     const long long pc = p < HW ? p : HW - 1;
     const int y = (int)(pc / W), x = (int)(pc % W);
-    uint32_t v[4];
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       const int tt = 4 * lg + q, dy = tt / 3 - 1, dx = tt % 3 - 1;
       const int yy = y + dy, xx = x + dx;
-      const uint32_t w = inw[(long long)min(max(yy, 0), H - 1) * W + min(max(xx, 0), W - 1)];
-      v[q] = (tt < 9 && yy >= 0 && yy < H && xx >= 0 && xx < W) ? w : 0u;
+      v[st][q] = inw[(long long)min(max(yy, 0), H - 1) * W + min(max(xx, 0), W - 1)];
+      in_tap[st][q] = tt < 9 && yy >= 0 && yy < H && xx >= 0 && xx < W;
     }
-    const bf16x8 bx = __builtin_bit_cast(bf16x8, make_uint4(v[0], v[1], v[2], v[3]));
+  }
+#pragma unroll
+  for (int st = 0; st < 4; ++st) {
+    const long long p = (long long)blockIdx.x * 256 + wv * 64 + st * 16 + li;
+    if ((long long)blockIdx.x * 256 + wv * 64 + st * 16 >= HW) break;    // wavefront-uniform
+    uint32_t vm[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      uint32_t w = v[st][q];
+      asm volatile("" : "+v"(w));
+      vm[q] = in_tap[st][q] ? w : 0u;
+    }
+    const bf16x8 bx = __builtin_bit_cast(bf16x8, make_uint4(vm[0], vm[1], vm[2], vm[3]));
     floatx4 acc[2];
 #pragma unroll
     for (int mt = 0; mt < 2; ++mt)
@@ -578,19 +594,47 @@ __global__ __launch_bounds__(256) void k_wgrad_out(const bf16* a, const float* d
   for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
     const int b = tile / per_img, r0 = tile % per_img;
     const int ox = (r0 % tilesx) * TX, oy = (r0 / tilesx) * TY;
-    __syncthreads();
-    for (int e = threadIdx.x; e < LY * LX; e += 256) {
-      const int gy = oy + e / LX - 1, gx = ox + e % LX - 1;
-      dl[e] = (gy >= 0 && gy < H && gx >= 0 && gx < W) ? dout[(size_t)b * HW + (long long)gy * W + gx] : 0.f;
-    }
-    __syncthreads();
+    // every load of the tile first, at clamped addresses: this thread's
+    // 8-channel chunk on each row, then the halo of the output gradient
     const int x = ox + lane;
+    uint4 av[TY];
+    bool okr[TY];
 #pragma unroll
     for (int r = 0; r < TY; ++r) {
       const int y = oy + r;
-      if (y >= H || x >= W) continue;
+      okr[r] = y < H && x < W;
+      const long long pix = (long long)min(y, H - 1) * W + min(x, W - 1);
+      av[r] = *reinterpret_cast<const uint4*>(a + ((size_t)b * HW + pix) * C + cg * 8);
+    }
+    constexpr int NH = (LY * LX + 255) / 256;
+    float hv[NH];
+    bool hin[NH];
+#pragma unroll
+    for (int h = 0; h < NH; ++h) {
+      const int e = threadIdx.x + 256 * h;
+      const int gy = oy + e / LX - 1, gx = ox + e % LX - 1;
+      hin[h] = e < LY * LX && gy >= 0 && gy < H && gx >= 0 && gx < W;
+      hv[h] = dout[(size_t)b * HW + (hin[h] ? (long long)gy * W + gx : 0)];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int h = 0; h < NH; ++h) {
+      const int e = threadIdx.x + 256 * h;
+      if (e < LY * LX) dl[e] = hin[h] ? hv[h] : 0.f;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < TY; ++r) {
+      if (!okr[r]) continue;
       float v[8];
-      load_ch<8>(a + ((size_t)b * HW + (long long)y * W + x) * C + cg * 8, v);
+      {
+        const uint32_t w4[4] = {av[r].x, av[r].y, av[r].z, av[r].w};
+#pragma unroll
+        for (int h2 = 0; h2 < 4; ++h2) {
+          v[2 * h2] = __uint_as_float(w4[h2] << 16);
+          v[2 * h2 + 1] = __uint_as_float(w4[h2] & 0xffff0000u);
+        }
+      }
 #pragma unroll
       for (int t = 0; t < 9; ++t) {
         // dout at q - off(t): halo row r + 2 - ky, column lane + 2 - kx
