@@ -68,6 +68,9 @@ def parse():
     ap.add_argument("--no-scale", action="store_true", help="skip the large-size rooflines")
     ap.add_argument("--batched-cycles", type=int, default=3,
                     help="restart cycles per system in the batched leg")
+    ap.add_argument("--config2", type=int, default=0, metavar="N",
+                    help="also solve N steps of the 1024^2 FP64 stream from zero and from the "
+                         "previous solution (minutes per step; off by default)")
     ap.add_argument("--no-config3", action="store_true",
                     help="skip the mixed-precision configuration's solves to 1e-10 (160^3, 2048^2)")
     ap.add_argument("--records", default=None, metavar="PATH",
@@ -270,6 +273,42 @@ def config3_leg(mlg, seed, budget_2d=20000):
         "projected_seconds_to_1e-10": proj * st.seconds / max(1, st.iters) if proj else None,
         "projection": "steps = 40 log(1e-10) / log(mean reduction per cycle over the budget)"}
     del ws, x, b
+    torch.cuda.empty_cache()
+    return out
+
+
+def config2_leg(mlg, seed, steps):
+    """A sample of the 1024^2 FP64 stream: `steps` consecutive right-hand
+    sides of five drifting Gaussians (sigma 0.02), each solved to rel. residual
+    1e-8 with GMRES(30) from zero and from the previous solution (the
+    classical initial guess), in the tuned launch configuration."""
+    from synthetic import DriftingGaussians
+    shape = (1024, 1024)
+    gen = DriftingGaussians(shape, 5, 0.02, seed=seed + 2)
+    grid = mlg.grid_of(shape)
+    opts = mlg.Opts(restart_m=30, precision=mlg.MLG_FP64, rtol=1e-8)
+    mlg.mlg_autotune(grid, opts)
+    ws = mlg.workspace(mlg.gmres_workspace_bytes(grid, opts))
+    prev = None
+    recs = {"zero": [], "prev": []}
+    for t in range(steps + 1):
+        b = torch.from_numpy(gen.field(t)).cuda()
+        x = torch.zeros_like(b)
+        st = mlg.gmres_solve(grid, b, x, opts, ws)
+        if t > 0:                                   # step 0 only seeds u_{t-1}
+            recs["zero"].append((st.seconds, st.iters))
+            xp = prev.clone()
+            sp = mlg.gmres_solve(grid, b, xp, opts, ws)
+            recs["prev"].append((sp.seconds, sp.iters))
+        prev = x
+        print(json.dumps({"progress": f"config2 step {t}"}), flush=True)
+    out = {"workload": "2D 5-point Poisson 1024^2, 5 drifting Gaussians (sigma 0.02), GMRES(30) FP64, "
+                       f"rtol 1e-8, steps 1..{steps} of the stream"}
+    for k, v in recs.items():
+        out[k] = {"tos_mean": statistics.fmean(s for s, _ in v),
+                  "iters_mean": statistics.fmean(i for _, i in v)}
+    out["prev_over_zero_iters"] = out["prev"]["iters_mean"] / out["zero"]["iters_mean"]
+    del ws
     torch.cuda.empty_cache()
     return out
 
@@ -609,6 +648,8 @@ def main():
 
     if not args.no_config3:
         result["config3"] = config3_leg(mlg, args.seed)
+    if args.config2 > 0:
+        result["config2_sample"] = config2_leg(mlg, args.seed, args.config2)
         print(json.dumps({"progress": "mixed-precision configuration done"}), flush=True)
     if not args.no_batched:
         result["batched"] = batched_leg(mlg, args.seed, args.batched_cycles)
