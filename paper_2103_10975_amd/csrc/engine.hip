@@ -458,7 +458,7 @@ static hipGraphExec_t part_graph(const std::string& key0, int dev, const Plan& P
     auto victim = R.graphs.begin();
     for (auto i = R.graphs.begin(); i != R.graphs.end(); ++i)
       if (i->second.second < victim->second.second) victim = i;
-    hipGraphExecDestroy(victim->second.first);
+    (void)hipGraphExecDestroy(victim->second.first);
     R.graphs.erase(victim);
   }
   hipStream_t cs = capture_stream(dev);
@@ -469,7 +469,7 @@ static hipGraphExec_t part_graph(const std::string& key0, int dev, const Plan& P
   MLG_HIP(ce);
   hipGraphExec_t exec;
   hipError_t e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
-  hipGraphDestroy(graph);
+  (void)hipGraphDestroy(graph);
   MLG_HIP(e);
   R.graphs[key] = {exec, ++R.tick};
   return exec;
@@ -503,12 +503,12 @@ struct Pinned {
 void runtime_shutdown() {
   auto& R = rt();
   std::lock_guard<std::mutex> lk(R.mu);
-  for (auto& kv : R.graphs) hipGraphExecDestroy(kv.second.first);
+  for (auto& kv : R.graphs) (void)hipGraphExecDestroy(kv.second.first);
   R.graphs.clear();
   R.steps_hist.clear();
-  for (auto& kv : R.capture_streams) hipStreamDestroy(kv.second);
+  for (auto& kv : R.capture_streams) (void)hipStreamDestroy(kv.second);
   R.capture_streams.clear();
-  for (auto* p : R.pinned_all) hipHostFree(p);
+  for (auto* p : R.pinned_all) (void)hipHostFree(p);
   R.pinned_all.clear();
   R.pinned_free.clear();
 }
@@ -607,7 +607,7 @@ int batched_solve(int nsys, const mlg_system* sys, const mlg_opts* opts, void* w
   MLG_HIP(hipEventCreateWithFlags(&ev[1], hipEventDisableTiming));
   struct EvGuard {
     hipEvent_t* e;
-    ~EvGuard() { hipEventDestroy(e[0]); hipEventDestroy(e[1]); }
+    ~EvGuard() { (void)hipEventDestroy(e[0]); (void)hipEventDestroy(e[1]); }
   } evg{ev};
 
   const int poll = opts->poll_cycles > 0 ? opts->poll_cycles : 1;
@@ -982,7 +982,7 @@ double kernel_bench(const mlg_grid* grid, const mlg_opts* opts, void* ws, size_t
   MLG_HIP(hipEventCreate(&e1));
   struct Gd {
     hipEvent_t a, b;
-    ~Gd() { hipEventDestroy(a); hipEventDestroy(b); }
+    ~Gd() { (void)hipEventDestroy(a); (void)hipEventDestroy(b); }
   } guard{e0, e1};
   const int jj = kind == MLG_K_UPDATE ? opts->restart_m : j;
   const int tail = kind == MLG_K_UPDATE || kind == MLG_K_RESIDUAL ? 1 : 0;

@@ -58,8 +58,6 @@ __device__ __forceinline__ bf16 f2bf(float f) {
   return (bf16)(u >> 16);
 }
 __device__ __forceinline__ float bf2f(bf16 h) { return __uint_as_float((uint32_t)h << 16); }
-__device__ __forceinline__ float to_f(bf16 h) { return bf2f(h); }
-__device__ __forceinline__ float to_f(float h) { return h; }
 
 struct Ptrs {
   const double* p[kMaxBatch];
