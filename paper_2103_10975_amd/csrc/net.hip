@@ -1312,7 +1312,7 @@ __global__ __launch_bounds__(256) void k_spec_rows(const bf16* in, const bf16* S
 // order.  X ([b][k][l][c]) is kept for the mode mixing and its weight gradient.
 __global__ __launch_bounds__(256) void k_spec_cols(const float* T, const float* Sy, float* X, int H,
                                                    int M, int LQ, float scale) {
-  constexpr int KB = 8, IC = 256, IQ = IC / 4, NB = 16, PER = KB * IC / 256;
+  constexpr int KB = 8, IC = 256, IQ = IC / 4, NB = IQ, PER = KB * IC / 256;
   __shared__ float syl[KB][IC];
   __shared__ float part[4][KB][64];
   const int nkb = (M + KB - 1) / KB, nqb = (LQ + 63) / 64;
