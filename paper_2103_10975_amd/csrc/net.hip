@@ -1595,10 +1595,35 @@ void launch_spec_out(dim3 grid, hipStream_t s, const bf16* in, const bf16* w1, c
 // its projection on the slowest modes cancels heavily, and FP32 sums (or an
 // FP32-rounded basis) leave errors in the mode coefficients comparable to the
 // coefficients themselves; trained on such inputs the gains settle below the
-// exact inverse.  Each kernel below takes several rows (or modes) per
-// workgroup so that every basis value it loads serves all of them, and up to
-// two independent fields per launch (blockIdx.y).
-constexpr int kBandRows = 8;
+// exact inverse.  The four transforms of the band (rows, columns, inverse
+// with the band weights, output) are dense FP64 products of the field with
+// the sine basis, run on the FP64 matrix cores in 16 x 16 tiles: both
+// operands come from registers (loaded straight from memory, every load of
+// a wavefront's batch issued before its first MFMA), which leaves the LDS to
+// the fixed-order sum of the wavefronts' partial tiles.  The row and output
+// transforms also have a vector form (8 rows per workgroup, all modes),
+// faster once a launch has enough rows to fill the device.  Up to two
+// independent fields per launch (blockIdx.y).
+typedef double doublex4 __attribute__((ext_vector_type(4)));
+
+// D(16 x 16) += A(16 x 4) B(4 x 16) in FP64 on the matrix cores: lane t holds
+// A[t % 16][t / 16] and B[t / 16][t % 16]; register r of D holds
+// D[4 r + t / 16][t % 16] (rows interleaved over the four lane groups).
+__device__ __forceinline__ doublex4 mfma_f64(double a, double b, doublex4 c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+// MFMA steps (4 terms each) per wavefront and batch of loads.
+constexpr int kBandSteps = 32;
+
+// Every value of a batch of loads counts as used here, in order, before the
+// first MFMA: the whole batch is in flight at once (left to itself the
+// compiler issues each load next to its MFMA and waits for it there).
+template <int N>
+__device__ __forceinline__ void band_batch_fence(double (&a)[N], double (&b)[N]) {
+#pragma unroll
+  for (int s = 0; s < N; ++s) asm volatile("" : "+v"(a[s]), "+v"(b[s]));
+}
 
 // One field's operand of a band launch: the data, its per-image divisor (or
 // NULL), the result, a scale.
@@ -1610,6 +1635,66 @@ struct BandIn {
   double scale;
 };
 
+// The four wavefronts' 16 x 16 partial tiles (register r of lane t of
+// wavefront w at part[w][4 r + t / 16][t % 16]), summed in a fixed order:
+// returns element (e / 16, e % 16) for e = threadIdx.x.
+__device__ __forceinline__ double band_tile_sum(double (*part)[16][16], const doublex4& acc) {
+  const int t = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) part[w][4 * r + t / 16][t % 16] = acc[r];
+  __syncthreads();
+  const int m = threadIdx.x / 16, n = threadIdx.x % 16;
+  return (part[0][m][n] + part[1][m][n]) + (part[2][m][n] + part[3][m][n]);
+}
+
+// T[b][i][l] = scale (sum_j x[b][i][j] SxT[j][l]) / div[b]: a workgroup takes
+// 16 rows x 16 modes of one image, its wavefront w the columns w*128.. of
+// every chunk of 512 (32 steps: A = the rows' values, zero past the grid;
+// B = the basis).
+template <class X0, class X1>
+__global__ __launch_bounds__(256) void k_band_rows(BandIn<X0> f0, BandIn<X1> f1, const double* SxT,
+                                                   int H, int W, int K) {
+  constexpr int NS = kBandSteps, JC = 16 * NS;
+  __shared__ double part[4][16][16];
+  const int nlb = (K + 15) / 16, nrb = (H + 15) / 16;
+  const int lb = blockIdx.x % nlb, rb = (blockIdx.x / nlb) % nrb, b = blockIdx.x / (nlb * nrb);
+  const int i0 = rb * 16, l0 = lb * 16;
+  const int t = threadIdx.x & 63, w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int m = t % 16, kq = t / 16;
+  auto run = [&](const auto& f) {
+    const auto* xr = f.x + ((size_t)b * H + min(i0 + m, H - 1)) * W;
+    const double* sb = SxT + min(l0 + m, K - 1);
+    doublex4 acc = {0.0, 0.0, 0.0, 0.0};
+    for (int j0 = 0; j0 < W; j0 += JC) {
+      const int jw = j0 + w * 4 * NS + kq;
+      double a[NS], bb[NS];
+#pragma unroll
+      for (int s = 0; s < NS; ++s) {
+        const int j = min(jw + 4 * s, W - 1);
+        a[s] = (double)xr[j];
+        bb[s] = sb[(size_t)j * K];
+      }
+      band_batch_fence(a, bb);
+#pragma unroll
+      for (int s = 0; s < NS; ++s) acc = mfma_f64(jw + 4 * s < W ? a[s] : 0.0, bb[s], acc);
+    }
+    const double v = band_tile_sum(part, acc);
+    const int i = i0 + threadIdx.x / 16, l = l0 + threadIdx.x % 16;
+    if (i < H && l < K) {
+      double o = v;
+      if (f.div) o /= f.div[b];
+      f.out[((size_t)b * H + i) * K + l] = f.scale * o;
+    }
+  };
+  if (blockIdx.y == 0) run(f0);
+  else run(f1);
+}
+
+// The row transform on the vector units, for launches with enough rows to
+// fill the device (a batch of training pairs): a workgroup takes 8 rows of
+// one image and all modes, so every basis value it loads serves all 8 rows.
+constexpr int kBandRows = 8;
+
 // T[b][i][l] = sum_j SxT[j][l] x[b][i][j] / div[b]: a workgroup takes 8 rows
 // of one image; lanes are the modes l (64 per pass, two passes at most), the
 // four wavefronts a quarter of every chunk of 256 columns.  The rows are
@@ -1620,8 +1705,8 @@ struct BandIn {
 constexpr int kBandChunk = 256;
 
 template <class X0, class X1>
-__global__ __launch_bounds__(256) void k_band_rows(BandIn<X0> f0, BandIn<X1> f1, const double* SxT,
-                                                   int H, int W, int K) {
+__global__ __launch_bounds__(256) void k_band_rows_vec(BandIn<X0> f0, BandIn<X1> f1,
+                                                       const double* SxT, int H, int W, int K) {
   constexpr int JC = kBandChunk, JQ = JC / 4, NB = 16, PER = kBandRows * JC / 256;
   __shared__ double xs[kBandRows][JC];
   __shared__ double part[4][kBandRows][64];
@@ -1688,73 +1773,38 @@ __global__ __launch_bounds__(256) void k_band_rows(BandIn<X0> f0, BandIn<X1> f1,
   else run(f1);
 }
 
-// X[b][k][q] = scale sum_i Sy[k][i] T[b][i][q] (q < K): a workgroup takes 8
-// modes k of one image; lanes are q (64 per pass, two passes at most), the
-// four wavefronts a quarter of every chunk of 256 rows; the chunk's basis
-// rows are staged in LDS (zero past the grid), T is read 16 rows at a time
-// with independent coalesced loads.
+// X[b][k][q] = scale sum_i Sy[k][i] T[b][i][q] (k, q < K): a workgroup takes
+// 16 x 16 of (k, q) of one image, its wavefront w the rows w*128.. of every
+// chunk of 512 (A = the basis, zero past the grid; B = T).
 __global__ __launch_bounds__(256) void k_band_cols(BandIn<double> f0, BandIn<double> f1,
                                                    const double* Sy, int H, int K) {
-  constexpr int IC = kBandChunk, IQ = IC / 4, NB = 16, PER = kBandRows * IC / 256;
-  __shared__ double syl[kBandRows][IC];
-  __shared__ double part[4][kBandRows][64];
-  const int nkb = (K + kBandRows - 1) / kBandRows;
-  const int b = blockIdx.x / nkb, k0 = (blockIdx.x % nkb) * kBandRows;
-  const int lane = threadIdx.x & 63, w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  constexpr int NS = kBandSteps, IC = 16 * NS;
+  __shared__ double part[4][16][16];
+  const int nkb = (K + 15) / 16;
+  const int qb = blockIdx.x % nkb, kb = (blockIdx.x / nkb) % nkb, b = blockIdx.x / (nkb * nkb);
+  const int k0 = kb * 16, q0 = qb * 16;
+  const int t = threadIdx.x & 63, w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int m = t % 16, kq = t / 16;
   const BandIn<double>& f = blockIdx.y == 0 ? f0 : f1;
-  const double* tb = f.x + (size_t)b * H * K;
-  const int klast = min(kBandRows, K - k0) - 1;
-  const int np = (K + 63) / 64;
-  double s[2][kBandRows];
+  const double* sr = Sy + (size_t)min(k0 + m, K - 1) * H;
+  const double* tq = f.x + (size_t)b * H * K + min(q0 + m, K - 1);
+  doublex4 acc = {0.0, 0.0, 0.0, 0.0};
+  for (int c0 = 0; c0 < H; c0 += IC) {
+    const int iw = c0 + w * 4 * NS + kq;
+    double a[NS], bb[NS];
 #pragma unroll
-  for (int p = 0; p < 2; ++p)
-#pragma unroll
-    for (int r = 0; r < kBandRows; ++r) s[p][r] = 0.0;
-  for (int i0 = 0; i0 < H; i0 += IC) {
-    double sv[PER];
-#pragma unroll
-    for (int u = 0; u < PER; ++u) {
-      const int e = threadIdx.x + 256 * u, r = e / IC, ii = e % IC;
-      sv[u] = Sy[(size_t)(k0 + min(r, klast)) * H + min(i0 + ii, H - 1)];
+    for (int s = 0; s < NS; ++s) {
+      const int i = min(iw + 4 * s, H - 1);
+      a[s] = sr[i];
+      bb[s] = tq[(size_t)i * K];
     }
-    __syncthreads();
+    band_batch_fence(a, bb);
 #pragma unroll
-    for (int u = 0; u < PER; ++u) {
-      const int e = threadIdx.x + 256 * u, r = e / IC, ii = e % IC;
-      syl[r][ii] = (r <= klast && i0 + ii < H) ? sv[u] : 0.0;
-    }
-    __syncthreads();
-    const int ia = i0 + w * IQ;
-#pragma unroll
-    for (int p = 0; p < 2; ++p) {
-      if (p >= np) break;
-      const int qc = min(p * 64 + lane, K - 1);
-#pragma unroll 1
-      for (int ib = 0; ib < IQ; ib += NB) {
-        double tv[NB];
-#pragma unroll
-        for (int u = 0; u < NB; ++u) tv[u] = tb[(size_t)min(ia + ib + u, H - 1) * K + qc];
-#pragma unroll
-        for (int u = 0; u < NB; ++u)
-#pragma unroll
-          for (int r = 0; r < kBandRows; ++r) s[p][r] = fma(syl[r][w * IQ + ib + u], tv[u], s[p][r]);
-      }
-    }
+    for (int s = 0; s < NS; ++s) acc = mfma_f64(iw + 4 * s < H ? a[s] : 0.0, bb[s], acc);
   }
-#pragma unroll
-  for (int p = 0; p < 2; ++p) {
-    if (p >= np) break;
-    __syncthreads();
-#pragma unroll
-    for (int r = 0; r < kBandRows; ++r) part[w][r][lane] = s[p][r];
-    __syncthreads();
-    for (int e = threadIdx.x; e < kBandRows * 64; e += 256) {
-      const int r = e / 64, ln = e % 64, qq = p * 64 + ln;
-      if (r > klast || qq >= K) continue;
-      const double v = (part[0][r][ln] + part[1][r][ln]) + (part[2][r][ln] + part[3][r][ln]);
-      f.out[((size_t)b * K + k0 + r) * K + qq] = f.scale * v;
-    }
-  }
+  const double v = band_tile_sum(part, acc);
+  const int k = k0 + threadIdx.x / 16, q = q0 + threadIdx.x % 16;
+  if (k < K && q < K) f.out[((size_t)b * K + k) * K + q] = f.scale * v;
 }
 
 // The convolutional branch's output gain: sct / scc, 1 before any data (or
@@ -1765,110 +1815,68 @@ __device__ __forceinline__ double gate_of(const double* gate) {
 
 // Z[b][i][l] = alpha sum_k Sy[k][i] Y[b][k][l], with the band applied on the
 // way in when `band` is given: Y = w_kl X - g Cc (w = sxt / sxx, 0 where sxx =
-// 0; g the output gain), else Y = X.  A workgroup takes 32 rows of one image
-// (8 per wavefront), lanes l; Y and the basis values of the 32 rows come
-// through LDS, 16 modes k at a time.
-template <int KMAX, int RPW>
+// 0; g the output gain), else Y = X.  A workgroup takes 16 rows x 16 modes l
+// of one image, its wavefront w the modes k = w*16.. of every chunk of 64 (A
+// = the basis, B = Y, zero past the band).
 __global__ __launch_bounds__(256) void k_band_inv(const double* X, const double* Cc,
                                                   const double* band, const double* gate,
                                                   const double* Sy, double* Z, int H, int K,
                                                   double alpha) {
-  constexpr int KC = 16, RB = 4 * RPW;
-  constexpr int PY = KC * KMAX / 256, PS = (KC * RB + 255) / 256;
-  __shared__ double yl[KC][KMAX];
-  __shared__ double syl[KC][RB];
-  const int nrb = (H + RB - 1) / RB;
-  const int b = blockIdx.x / nrb, i0 = (blockIdx.x % nrb) * RB;
-  const int lane = threadIdx.x & 63, w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  constexpr int NS = 4, KC = 16 * NS;
+  __shared__ double part[4][16][16];
+  const int nlb = (K + 15) / 16, nrb = (H + 15) / 16;
+  const int lb = blockIdx.x % nlb, rb = (blockIdx.x / nlb) % nrb, b = blockIdx.x / (nlb * nrb);
+  const int i0 = rb * 16, l0 = lb * 16;
+  const int t = threadIdx.x & 63, w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int m = t % 16, kq = t / 16;
   const double g = gate_of(gate);
+  const int ic = min(i0 + m, H - 1), lc = min(l0 + m, K - 1);
   const double* Xb = X + (size_t)b * K * K;
   const double* Cb = Cc ? Cc + (size_t)b * K * K : nullptr;
-  const int np = (K + 63) / 64;
-  constexpr int NP = KMAX / 64;
-  double s[NP][RPW];
+  doublex4 acc = {0.0, 0.0, 0.0, 0.0};
+  for (int c0 = 0; c0 < K; c0 += KC) {
+    const int kw = c0 + w * 4 * NS + kq;
+    double a[NS], y[NS];
+    if (band) {
+      double cv[NS], tv[NS], qv[NS];
 #pragma unroll
-  for (int p = 0; p < NP; ++p)
+      for (int s = 0; s < NS; ++s) {
+        const int k = min(kw + 4 * s, K - 1);
+        a[s] = Sy[(size_t)k * H + ic];
+        y[s] = Xb[k * K + lc];
+        cv[s] = Cb[k * K + lc];
+        tv[s] = band[k * K + lc];
+        qv[s] = band[K * K + k * K + lc];
+      }
 #pragma unroll
-    for (int r = 0; r < RPW; ++r) s[p][r] = 0.0;
-  for (int k0 = 0; k0 < K; k0 += KC) {
-    // Y[k0 + kk][ll] (kk < KC, ll < KMAX; zero past K), loads first
-    double xv[PY], cv[PY], tv[PY], qv[PY];
+      for (int s = 0; s < NS; ++s) {
+        const double wk = qv[s] > 0.0 ? tv[s] / qv[s] : 0.0;
+        y[s] = wk * y[s] - g * cv[s];
+      }
+    } else {
 #pragma unroll
-    for (int u = 0; u < PY; ++u) {
-      const int e = threadIdx.x + 256 * u, kk = e / KMAX, ll = e % KMAX;
-      const int kl = min(k0 + kk, K - 1) * K + min(ll, K - 1);
-      xv[u] = Xb[kl];
-      if (band) {
-        cv[u] = Cb[kl];
-        tv[u] = band[kl];
-        qv[u] = band[K * K + kl];
+      for (int s = 0; s < NS; ++s) {
+        const int k = min(kw + 4 * s, K - 1);
+        a[s] = Sy[(size_t)k * H + ic];
+        y[s] = Xb[k * K + lc];
       }
     }
-    double sv[PS];
+    band_batch_fence(a, y);
 #pragma unroll
-    for (int u = 0; u < PS; ++u) {
-      const int e = threadIdx.x + 256 * u, kk = min(e / RB, KC - 1), ii = e % RB;
-      sv[u] = Sy[(size_t)min(k0 + kk, K - 1) * H + min(i0 + ii, H - 1)];
-    }
-    __syncthreads();                                      // the previous chunk's readers are done
-#pragma unroll
-    for (int u = 0; u < PY; ++u) {
-      const int e = threadIdx.x + 256 * u, kk = e / KMAX, ll = e % KMAX;
-      double y = xv[u];
-      if (band) {
-        const double wk = qv[u] > 0.0 ? tv[u] / qv[u] : 0.0;
-        y = wk * xv[u] - g * cv[u];
-      }
-      yl[kk][ll] = (k0 + kk < K && ll < K) ? y : 0.0;
-    }
-#pragma unroll
-    for (int u = 0; u < PS; ++u) {
-      const int e = threadIdx.x + 256 * u, kk = e / RB, ii = e % RB;
-      if (e < KC * RB) syl[kk][ii] = (k0 + kk < K && i0 + ii < H) ? sv[u] : 0.0;
-    }
-    __syncthreads();
-#pragma unroll
-    for (int p = 0; p < NP; ++p) {
-      if (p >= np) break;
-      const int lc = min(p * 64 + lane, K - 1);
-#pragma unroll 4
-      for (int kk = 0; kk < KC; ++kk) {
-        const double yv = yl[kk][lc];
-#pragma unroll
-        for (int r = 0; r < RPW; ++r) s[p][r] = fma(syl[kk][w * RPW + r], yv, s[p][r]);
-      }
-    }
+    for (int s = 0; s < NS; ++s) acc = mfma_f64(a[s], kw + 4 * s < K ? y[s] : 0.0, acc);
   }
-#pragma unroll
-  for (int p = 0; p < NP; ++p) {
-    const int l = p * 64 + lane;
-    if (p >= np || l >= K) continue;
-#pragma unroll
-    for (int r = 0; r < RPW; ++r) {
-      const int i = i0 + w * RPW + r;
-      if (i < H) Z[((size_t)b * H + i) * K + l] = alpha * s[p][r];
-    }
-  }
-}
-
-// k_band_inv over 8 rows per workgroup (a B x H/8 grid), the mode tile sized
-// to the band (up to 64 or up to 128 modes)
-static void launch_band_inv(hipStream_t s, int B, const double* X, const double* Cc,
-                            const double* band, const double* gate, const double* Sy, double* Z,
-                            int H, int K, double alpha) {
-  constexpr int RPW = 2, RB = 4 * RPW;
-  const dim3 grid(B * ((H + RB - 1) / RB));
-  if (K <= 64)
-    k_band_inv<64, RPW><<<grid, 256, 0, s>>>(X, Cc, band, gate, Sy, Z, H, K, alpha);
-  else
-    k_band_inv<128, RPW><<<grid, 256, 0, s>>>(X, Cc, band, gate, Sy, Z, H, K, alpha);
+  const double v = band_tile_sum(part, acc);
+  const int i = i0 + threadIdx.x / 16, l = l0 + threadIdx.x % 16;
+  if (i < H && l < K) Z[((size_t)b * H + i) * K + l] = alpha * v;
 }
 
 // out[b][i][j] = g out[b][i][j] + beta sum_l Sx[l][j] Z[b][i][l] (sum and add in
-// FP64; g the output gain, 1 without one): a workgroup takes 8 rows x 256
-// columns of one image, a thread one column and its eight rows (eight running
-// sums, so every basis value serves eight rows); the rows' Z values come
-// through LDS.  Up to two fields (blockIdx.y).
+// FP64; g the output gain, 1 without one): a workgroup takes 16 rows x 64
+// columns of one image, its wavefront w the 16 columns w*16.., lane group g
+// the 16 consecutive modes 16g.. of every 64 (A = the rows' Z, read along
+// the row and zero past the band; B = the basis); the output values and a
+// band of up to 64 modes are loaded in one batch.  Up to two fields
+// (blockIdx.y).
 struct BandOut {
   const double* Z;
   float* out;
@@ -1878,6 +1886,47 @@ struct BandOut {
 
 __global__ __launch_bounds__(256) void k_band_out(BandOut f0, BandOut f1, const double* Sx, int H,
                                                   int W, int K) {
+  constexpr int NS = 16;
+  const BandOut& f = blockIdx.y == 0 ? f0 : f1;
+  const int ncb = (W + 63) / 64, nrb = (H + 15) / 16;
+  const int cb = blockIdx.x % ncb, rb = (blockIdx.x / ncb) % nrb, b = blockIdx.x / (ncb * nrb);
+  const int t = threadIdx.x & 63, w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int m = t % 16, kq = t / 16;
+  const int i0 = rb * 16, j = cb * 64 + w * 16 + m;
+  const int jc = min(j, W - 1);
+  float ov[4];
+#pragma unroll
+  for (int r = 0; r < 4; ++r) ov[r] = f.out[((size_t)b * H + min(i0 + 4 * r + kq, H - 1)) * W + jc];
+  const double* zr = f.Z + ((size_t)b * H + min(i0 + m, H - 1)) * K;
+  const double* sc = Sx + jc;
+  doublex4 acc = {0.0, 0.0, 0.0, 0.0};
+  for (int c0 = 0; c0 < K; c0 += 4 * NS) {
+    double a[NS], bb[NS];
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+      const int l = min(c0 + 4 * s + kq, K - 1);
+      a[s] = zr[l];
+      bb[s] = sc[(size_t)l * W];
+    }
+    band_batch_fence(a, bb);
+#pragma unroll
+    for (int s = 0; s < NS; ++s) acc = mfma_f64(c0 + 4 * s + kq < K ? a[s] : 0.0, bb[s], acc);
+  }
+  if (j >= W) return;
+  const double g = gate_of(f.gate);
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int i = i0 + 4 * r + kq;
+    if (i < H) f.out[((size_t)b * H + i) * W + j] = (float)(g * (double)ov[r] + f.beta * acc[r]);
+  }
+}
+
+// The output transform on the vector units, for launches with enough rows
+// to fill the device: a workgroup takes 8 rows x 256 columns of one image, a
+// thread one column and its eight rows (eight running sums, so every basis
+// value serves eight rows); the rows' Z values come through LDS.
+__global__ __launch_bounds__(256) void k_band_out_vec(BandOut f0, BandOut f1, const double* Sx,
+                                                      int H, int W, int K) {
   constexpr int KMAX = 128, NB = 16, PZ = kBandRows * KMAX / 256;
   __shared__ double zl[kBandRows][KMAX];
   const BandOut& f = blockIdx.y == 0 ? f0 : f1;
@@ -2110,8 +2159,28 @@ BandSpace band_space(const Net& n) {
                    p(n.wl.kSx),  p(n.wl.kSxT), p(n.wl.kSy)};
 }
 
-inline int band_out_blocks(const Dims& d) {
-  return d.B * cdiv(d.H, kBandRows) * cdiv(d.W, 256);
+// Launch shapes of the band kernels: 16 x 16 tiles (rows x modes, modes x
+// modes), 16 x 64 output tiles; up to two fields as blockIdx.y.
+inline dim3 band_rows_grid(const Dims& d) { return dim3(d.B * cdiv(d.H, 16) * cdiv(d.K, 16), 2); }
+inline dim3 band_cols_grid(const Dims& d) { return dim3(d.B * cdiv(d.K, 16) * cdiv(d.K, 16), 2); }
+inline dim3 band_inv_grid(const Dims& d) { return dim3(d.B * cdiv(d.H, 16) * cdiv(d.K, 16)); }
+inline dim3 band_out_grid(const Dims& d, int fields) {
+  return dim3(d.B * cdiv(d.H, 16) * cdiv(d.W, 64), fields);
+}
+
+// The row and output transforms run on the vector units when their 8-row
+// workgroups alone fill the 256 compute units (a training batch at the
+// benchmark's size), and on the matrix cores otherwise (inference of one
+// field, where the vector form would leave most of the device idle).
+inline bool band_vector(const Dims& d) { return (long long)d.B * cdiv(d.H, kBandRows) >= 256; }
+
+void launch_band_out(hipStream_t s, const Dims& d, int fields, BandOut f0, BandOut f1,
+                     const double* Sx) {
+  if (band_vector(d))
+    k_band_out_vec<<<dim3(d.B * cdiv(d.H, kBandRows) * cdiv(d.W, 256), fields), 256, 0, s>>>(
+        f0, f1, Sx, d.H, d.W, d.K);
+  else
+    k_band_out<<<band_out_grid(d, fields), 256, 0, s>>>(f0, f1, Sx, d.H, d.W, d.K);
 }
 
 // Mode coefficients of two fields, X_q = scale_q S_y (x_q / div_q) S_x^T
@@ -2124,9 +2193,12 @@ void band_project_rows_cols(const Net& n, BandIn<X0> f0, BandIn<X1> f1, double* 
   const BandSpace b = band_space(n);
   f0.out = b.kT;
   f1.out = b.kT2;
-  k_band_rows<X0, X1><<<dim3(d.B * cdiv(d.H, kBandRows), 2), 256, 0, s>>>(f0, f1, b.kSxT, d.H, d.W,
-                                                                          d.K);
-  k_band_cols<<<dim3(d.B * cdiv(d.K, kBandRows), 2), 256, 0, s>>>(
+  if (band_vector(d))
+    k_band_rows_vec<X0, X1><<<dim3(d.B * cdiv(d.H, kBandRows), 2), 256, 0, s>>>(f0, f1, b.kSxT, d.H,
+                                                                              d.W, d.K);
+  else
+    k_band_rows<X0, X1><<<band_rows_grid(d), 256, 0, s>>>(f0, f1, b.kSxT, d.H, d.W, d.K);
+  k_band_cols<<<band_cols_grid(d), 256, 0, s>>>(
       BandIn<double>{b.kT, nullptr, X0out, scale0}, BandIn<double>{b.kT2, nullptr, X1out, scale1},
       b.kSy, d.H, d.K);
 }
@@ -2186,10 +2258,9 @@ void forward(const Net& n, const Ptrs& f, const Ptrs& u, hipStream_t s, bool gat
   const BandSpace bsp = band_space(n);
   band_project_rows_cols<double, float>(n, {r0, sv + d.B, bsp.kT, 1.0},
                                         {out, nullptr, bsp.kT2, 1.0}, bsp.kX, bsp.kC, 1.0, 1.0, s);
-  launch_band_inv(s, d.B, bsp.kX, bsp.kC, (const double*)(n.params + n.pl.band), gate, bsp.kSy,
-                  bsp.kZ, d.H, d.K, 2.0 / (d.H + 1));
-  k_band_out<<<dim3(band_out_blocks(d), 1), 256, 0, s>>>(
-      BandOut{bsp.kZ, out, gate, 2.0 / (d.W + 1)}, BandOut{}, bsp.kSx, d.H, d.W, d.K);
+  k_band_inv<<<band_inv_grid(d), 256, 0, s>>>(bsp.kX, bsp.kC, (const double*)(n.params + n.pl.band),
+                                               gate, bsp.kSy, bsp.kZ, d.H, d.K, 2.0 / (d.H + 1));
+  launch_band_out(s, d, 1, BandOut{bsp.kZ, out, gate, 2.0 / (d.W + 1)}, BandOut{}, bsp.kSx);
 }
 
 template <int C>
@@ -2252,11 +2323,12 @@ void train(const Net& n, const Ptrs& f, const Ptrs& up, const Ptrs& ut, float* l
     const double nrm = (2.0 / (d.H + 1)) * (2.0 / (d.W + 1));
     band_project_rows_cols<float, float>(n, {dout, nullptr, nullptr, 1.0}, {out, nullptr, nullptr, 1.0},
                                          bsp.kdY, bsp.kdY2, nrm, nrm, s);
-    launch_band_inv(s, d.B, bsp.kdY, nullptr, nullptr, nullptr, bsp.kSy, bsp.kZ, d.H, K, 1.0);
-    launch_band_inv(s, d.B, bsp.kdY2, nullptr, nullptr, nullptr, bsp.kSy, bsp.kZ2, d.H, K, 1.0);
-    k_band_out<<<dim3(band_out_blocks(d), 2), 256, 0, s>>>(BandOut{bsp.kZ, dout, nullptr, -1.0},
-                                                           BandOut{bsp.kZ2, out, nullptr, -1.0},
-                                                           bsp.kSx, d.H, d.W, K);
+    k_band_inv<<<band_inv_grid(d), 256, 0, s>>>(bsp.kdY, nullptr, nullptr, nullptr, bsp.kSy, bsp.kZ,
+                                                 d.H, K, 1.0);
+    k_band_inv<<<band_inv_grid(d), 256, 0, s>>>(bsp.kdY2, nullptr, nullptr, nullptr, bsp.kSy,
+                                                 bsp.kZ2, d.H, K, 1.0);
+    launch_band_out(s, d, 2, BandOut{bsp.kZ, dout, nullptr, -1.0},
+                    BandOut{bsp.kZ2, out, nullptr, -1.0}, bsp.kSx);
     double* gpart = n.w<double>(n.wl.loss) + 8 + 2048;
     k_gate_sums<<<256, 256, 0, s>>>(out, dout, (long long)d.B * HW, gpart);
     k_gate_fin<<<1, 64, 0, s>>>(gpart, 256, (double*)(n.params + n.pl.gate), d.B);
