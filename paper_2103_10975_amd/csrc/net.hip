@@ -192,65 +192,81 @@ WsLayout ws_layout(const Dims& d, bool train) {
 
 // ------------------------------------------------------------------ small kernels
 
-// r = f - A u_prev with the solver's operator (zero Dirichlet, h = 1/(N+1)).
-__global__ void k_resid_in(Ptrs f, Ptrs u, double* r, int H, int W) {
-  const int b = blockIdx.y;
-  const long long HW = (long long)H * W;
-  const long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= HW) return;
-  const int y = (int)(p / W), x = (int)(p % W);
-  const double* ub = u.p[b];
-  const double cx = (double)(W + 1) * (W + 1), cy = (double)(H + 1) * (H + 1);
-  const double c = ub[p];
-  const double w = x > 0 ? ub[p - 1] : 0.0, e = x < W - 1 ? ub[p + 1] : 0.0;
-  const double sN = y > 0 ? ub[p - W] : 0.0, nN = y < H - 1 ? ub[p + W] : 0.0;
-  r[(size_t)b * HW + p] = f.p[b][p] - ((2.0 * c - w - e) * cx + (2.0 * c - sN - nN) * cy);
-}
-
-// RMS of the B residuals r_b and the B sources f_b: sums of squares over
-// kRmsBlocks contiguous chunks per field (blockIdx.y: field r_0..r_{B-1},
-// f_0..f_{B-1}), then one workgroup per field adds its chunks in order.
-__global__ __launch_bounds__(256) void k_sumsq(Ptrs r, Ptrs f, int B, long long n, double* part) {
+// The residual r_b = f_b - A u_b of each image (FP64, the 5-point operator
+// of the solver) written out, with the sums of squares of the B residuals
+// and the B sources over kRmsBlocks contiguous chunks per field (blockIdx.y:
+// field r_0..r_{B-1}, f_0..f_{B-1}); each chunk's sum in a fixed order.
+__global__ __launch_bounds__(256) void k_resid_sumsq(Ptrs f, Ptrs u, double* r, int B, int H, int W,
+                                                     double* part) {
   __shared__ double red[4];
   const int fi = blockIdx.y;
-  const double* x = fi < B ? r.p[fi] : f.p[fi - B];
+  const long long n = (long long)H * W;
   const long long c0 = n * blockIdx.x / kRmsBlocks, c1 = n * (blockIdx.x + 1) / kRmsBlocks;
   double acc = 0.0;
-  for (long long i = c0 + threadIdx.x; i < c1; i += 256) acc += x[i] * x[i];
+  if (fi < B) {
+    const double* ub = u.p[fi];
+    const double* fb = f.p[fi];
+    double* rb = r + (size_t)fi * n;
+    const double cx = (double)(W + 1) * (W + 1), cy = (double)(H + 1) * (H + 1);
+    for (long long p = c0 + threadIdx.x; p < c1; p += 256) {
+      const int y = (int)(p / W), x = (int)(p % W);
+      const double c = ub[p];
+      const double w = x > 0 ? ub[p - 1] : 0.0, e = x < W - 1 ? ub[p + 1] : 0.0;
+      const double sN = y > 0 ? ub[p - W] : 0.0, nN = y < H - 1 ? ub[p + W] : 0.0;
+      const double v = fb[p] - ((2.0 * c - w - e) * cx + (2.0 * c - sN - nN) * cy);
+      rb[p] = v;
+      acc += v * v;
+    }
+  } else {
+    const double* x = f.p[fi - B];
+    for (long long p = c0 + threadIdx.x; p < c1; p += 256) acc += x[p] * x[p];
+  }
   acc = wave_sum(acc);
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
   __syncthreads();
   if (threadIdx.x == 0)
     part[(size_t)fi * kRmsBlocks + blockIdx.x] = ((red[0] + red[1]) + red[2]) + red[3];
 }
-// sv[0..B): RMS(r_b) (raw); sv[B..2B): its division-safe version (1 when 0);
-// sv[2B..3B): the division-safe RMS(f_b).
-__global__ __launch_bounds__(64) void k_rms_fin(const double* part, int B, long long n, double* sv) {
-  const int fi = blockIdx.x;
+
+// RMS of field fi from its kRmsBlocks chunk sums, added in a fixed order by
+// one wavefront (every lane returns it).
+__device__ __forceinline__ double rms_of(const double* part, int fi, long long n) {
   double v = 0.0;
-  for (int k = threadIdx.x; k < kRmsBlocks; k += 64) v += part[(size_t)fi * kRmsBlocks + k];
+  for (int k = threadIdx.x & 63; k < kRmsBlocks; k += 64) v += part[(size_t)fi * kRmsBlocks + k];
   v = wave_sum(v);
-  if (threadIdx.x == 0) {
-    const double rms = sqrt(v / (double)n);
-    const double safe = rms > 0.0 ? rms : 1.0;
-    if (fi < B) {
-      sv[fi] = rms;
-      sv[B + fi] = safe;
-    } else {
-      sv[2 * B + fi - B] = safe;
-    }
-  }
+  return sqrt(v / (double)n);
 }
 
-// x0[b][p] = (r/s_in, f/s_f) in BF16 (2 channels).
-__global__ void k_norm_in(const double* r, Ptrs f, const double* s_in, const double* s_f, bf16* x0,
-                          long long HW) {
-  const int b = blockIdx.y;
+// x0[b][p] = (r/s_r, f/s_f) in BF16 (2 channels), s_r and s_f the
+// division-safe RMS of r_b and f_b (1 where the RMS is 0), formed in every
+// workgroup from the chunk sums (wavefront 0: r_b, wavefront 1: f_b); the
+// first workgroup of each image also stores sv[b] = RMS(r_b) (raw),
+// sv[B + b] = s_r and sv[2B + b] = s_f.
+__global__ __launch_bounds__(256) void k_norm_in(const double* r, Ptrs f, const double* part,
+                                                 double* sv, int B, bf16* x0, long long HW) {
+  __shared__ double sc[2];
+  const int b = blockIdx.y, wv = threadIdx.x >> 6;
+  if (wv < 2) {
+    const double rms = rms_of(part, wv == 0 ? b : B + b, HW);
+    const double safe = rms > 0.0 ? rms : 1.0;
+    if ((threadIdx.x & 63) == 0) {
+      sc[wv] = safe;
+      if (blockIdx.x == 0) {
+        if (wv == 0) {
+          sv[b] = rms;
+          sv[B + b] = safe;
+        } else {
+          sv[2 * B + b] = safe;
+        }
+      }
+    }
+  }
+  __syncthreads();
   const long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= HW) return;
   bf16* o = x0 + ((size_t)b * HW + p) * 2;
-  o[0] = f2bf((float)(r[(size_t)b * HW + p] / s_in[b]));
-  o[1] = f2bf((float)(f.p[b][p] / s_f[b]));
+  o[0] = f2bf((float)(r[(size_t)b * HW + p] / sc[0]));
+  o[1] = f2bf((float)(f.p[b][p] / sc[1]));
 }
 
 // guess = u_prev + (s_r / c_u) out
@@ -1304,61 +1320,49 @@ __global__ __launch_bounds__(256) void k_spec_rows(const bf16* in, const bf16* S
 }
 
 // Column transform of the spectral layer: X[b][k][q] = scale sum_i Sy[k][i]
-// T[b][i][q] for q = l C + c < M C (the row-transformed activations).  A
-// workgroup takes 8 modes k and 64 consecutive q of one image; lanes are q,
-// the four wavefronts a quarter of every chunk of 256 rows; the chunk's
-// basis rows are staged in LDS (zero past H or M), T is read 16 rows at a
-// time with independent coalesced loads; the quarters are added in a fixed
-// order.  X ([b][k][l][c]) is kept for the mode mixing and its weight gradient.
+// T[b][i][q] for q = l C + c < M C (the row-transformed activations), on the
+// FP32 matrix cores (v_mfma_f32_16x16x4f32: lane t holds A[t % 16][t / 16]
+// and B[t / 16][t % 16], register r of the result D[4 (t / 16) + r][t % 16]).
+// A workgroup takes 16 modes k x 16 columns q of one image, its wavefront w
+// the rows w*128.. of every chunk of 512 (A = the basis, zero past H; B =
+// T), every load of a chunk issued before the first MFMA; the four partial
+// tiles are added in LDS in a fixed order.  X ([b][k][l][c]) is kept for the
+// mode mixing and its weight gradient.
 __global__ __launch_bounds__(256) void k_spec_cols(const float* T, const float* Sy, float* X, int H,
                                                    int M, int LQ, float scale) {
-  constexpr int KB = 8, IC = 256, IQ = IC / 4, NB = IQ, PER = KB * IC / 256;
-  __shared__ float syl[KB][IC];
-  __shared__ float part[4][KB][64];
-  const int nkb = (M + KB - 1) / KB, nqb = (LQ + 63) / 64;
+  constexpr int NS = 32, IC = 16 * NS;
+  __shared__ float part[4][16][16];
+  const int nqb = (LQ + 15) / 16, nkb = (M + 15) / 16;
   const int qb = blockIdx.x % nqb, kb = (blockIdx.x / nqb) % nkb, b = blockIdx.x / (nqb * nkb);
-  const int k0 = kb * KB;
-  const int lane = threadIdx.x & 63, w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int q = qb * 64 + lane, qc = min(q, LQ - 1);
-  const int klast = min(KB, M - k0) - 1;
-  const float* tb = T + (size_t)b * H * LQ + qc;
-  float s[KB];
+  const int k0 = kb * 16, q0 = qb * 16;
+  const int t = threadIdx.x & 63, w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int m = t % 16, kq = t / 16;
+  const float* sr = Sy + (size_t)min(k0 + m, M - 1) * H;
+  const float* tq = T + (size_t)b * H * LQ + min(q0 + m, LQ - 1);
+  floatx4 acc = floatx4{0.f, 0.f, 0.f, 0.f};
+  for (int c0 = 0; c0 < H; c0 += IC) {
+    const int iw = c0 + w * 4 * NS + kq;
+    float a[NS], bb[NS];
 #pragma unroll
-  for (int r = 0; r < KB; ++r) s[r] = 0.f;
-  for (int i0 = 0; i0 < H; i0 += IC) {
-    float sv[PER];
-#pragma unroll
-    for (int u = 0; u < PER; ++u) {
-      const int e = threadIdx.x + 256 * u, r = e / IC, ii = e % IC;
-      sv[u] = Sy[(size_t)(k0 + min(r, klast)) * H + min(i0 + ii, H - 1)];
+    for (int s = 0; s < NS; ++s) {
+      const int i = min(iw + 4 * s, H - 1);
+      a[s] = sr[i];
+      bb[s] = tq[(size_t)i * LQ];
     }
-    __syncthreads();
 #pragma unroll
-    for (int u = 0; u < PER; ++u) {
-      const int e = threadIdx.x + 256 * u, r = e / IC, ii = e % IC;
-      syl[r][ii] = (r <= klast && i0 + ii < H) ? sv[u] : 0.f;
-    }
-    __syncthreads();
-    const int ia = i0 + w * IQ;
-#pragma unroll 1
-    for (int ib = 0; ib < IQ; ib += NB) {
-      float tv[NB];
+    for (int s = 0; s < NS; ++s) asm volatile("" : "+v"(a[s]), "+v"(bb[s]));
 #pragma unroll
-      for (int u = 0; u < NB; ++u) tv[u] = tb[(size_t)min(ia + ib + u, H - 1) * LQ];
-#pragma unroll
-      for (int u = 0; u < NB; ++u)
-#pragma unroll
-        for (int r = 0; r < KB; ++r) s[r] = fmaf(syl[r][w * IQ + ib + u], tv[u], s[r]);
-    }
+    for (int s = 0; s < NS; ++s)
+      acc = __builtin_amdgcn_mfma_f32_16x16x4f32(iw + 4 * s < H ? a[s] : 0.f, bb[s], acc, 0, 0, 0);
   }
 #pragma unroll
-  for (int r = 0; r < KB; ++r) part[w][r][lane] = s[r];
+  for (int r = 0; r < 4; ++r) part[w][4 * kq + r][m] = acc[r];
   __syncthreads();
-  for (int e = threadIdx.x; e < KB * 64; e += 256) {
-    const int r = e / 64, ln = e % 64, qq = qb * 64 + ln;
-    if (r > klast || qq >= LQ) continue;
-    const float v = ((part[0][r][ln] + part[1][r][ln]) + part[2][r][ln]) + part[3][r][ln];
-    X[((size_t)b * M + k0 + r) * LQ + qq] = scale * v;
+  const int mm = threadIdx.x / 16, nn = threadIdx.x % 16;
+  const int k = k0 + mm, q = q0 + nn;
+  if (k < M && q < LQ) {
+    const float v = (part[0][mm][nn] + part[1][mm][nn]) + (part[2][mm][nn] + part[3][mm][nn]);
+    X[((size_t)b * M + k) * LQ + q] = scale * v;
   }
 }
 
@@ -2134,6 +2138,15 @@ __global__ void k_adam(float* master, const float* grad, float* m, float* v, bf1
 // ------------------------------------------------------------------ host helpers
 inline int cdiv(long long a, long long b) { return (int)((a + b - 1) / b); }
 
+// The network inputs of a batch: residuals r0 (FP64), their and the sources'
+// RMS in sv, and the normalised two-channel BF16 input x0.
+static void normalise_inputs(const Ptrs& f, const Ptrs& u, double* r0, double* rms_part, double* sv,
+                             bf16* x0, int B, int H, int W, hipStream_t s) {
+  const long long HW = (long long)H * W;
+  k_resid_sumsq<<<dim3(kRmsBlocks, 2 * B), 256, 0, s>>>(f, u, r0, B, H, W, rms_part);
+  k_norm_in<<<dim3(cdiv(HW, 256), B), 256, 0, s>>>(r0, f, rms_part, sv, B, x0, HW);
+}
+
 struct Net {
   Dims d;
   ParamLayout pl;
@@ -2223,13 +2236,7 @@ void forward(const Net& n, const Ptrs& f, const Ptrs& u, hipStream_t s, bool gat
     const long long nb = (long long)bs.MP * WP + (long long)d.M * d.H + (long long)d.K * (d.W + d.H);
     k_bases<<<cdiv(nb, 256), 256, 0, s>>>(bs);
   }
-  k_resid_in<<<dim3(cdiv(HW, 256), d.B), 256, 0, s>>>(f, u, r0, d.H, d.W);
-  Ptrs rp{};
-  for (int b = 0; b < d.B; ++b) rp.p[b] = r0 + (size_t)b * HW;
-  double* rms_part = n.w<double>(n.wl.rms);
-  k_sumsq<<<dim3(kRmsBlocks, 2 * d.B), 256, 0, s>>>(rp, f, d.B, HW, rms_part);
-  k_rms_fin<<<2 * d.B, 64, 0, s>>>(rms_part, d.B, HW, sv);
-  k_norm_in<<<dim3(cdiv(HW, 256), d.B), 256, 0, s>>>(r0, f, sv + d.B, sv + 2 * d.B, x0, HW);
+  normalise_inputs(f, u, r0, n.w<double>(n.wl.rms), sv, x0, d.B, d.H, d.W, s);
   // L1, L2
   k_conv_in_mfma<C><<<dim3(cdiv(HW, 256), d.B), 256, 0, s>>>(
       x0, n.bfw(T_C1W), n.bfw(T_C1B), a[0], d.H, d.W);
@@ -2240,7 +2247,7 @@ void forward(const Net& n, const Ptrs& f, const Ptrs& u, hipStream_t s, bool gat
   float* Z = n.w<float>(n.wl.Z);
   k_spec_rows<C><<<d.B * d.H, 256, 0, s>>>(a[1], n.w<bf16>(n.wl.Sxh), n.w<bf16>(n.wl.Sxl), T, d.W,
                                            WP, d.M);
-  k_spec_cols<<<d.B * cdiv(d.M, 8) * cdiv(d.M * C, 64), 256, 0, s>>>(T, Sy, X, d.H, d.M, d.M * C, 1.f);
+  k_spec_cols<<<d.B * cdiv(d.M, 16) * cdiv(d.M * C, 16), 256, 0, s>>>(T, Sy, X, d.H, d.M, d.M * C, 1.f);
   k_spec_minv<C, false><<<d.B * d.M * cdiv(d.H, 64), 256, 0, s>>>(X, n.bfw(T_SWK), Sy, Z, d.H, d.M,
                                                                   (float)(2.0 / (d.H + 1)));
   launch_spec_out<C, false>(dim3(d.B * d.H * cdiv(d.W, 64)), s, a[1], n.bfw(T_SW1), n.bfw(T_SB), Z, Sx,
@@ -2354,7 +2361,7 @@ void train(const Net& n, const Ptrs& f, const Ptrs& up, const Ptrs& ut, float* l
   const int WP = spec_wp(d);
   k_spec_rows<C><<<d.B * d.H, 256, 0, s>>>(dz[0], n.w<bf16>(n.wl.Sxh), n.w<bf16>(n.wl.Sxl), T, d.W,
                                            WP, d.M);
-  k_spec_cols<<<d.B * cdiv(d.M, 8) * cdiv(d.M * C, 64), 256, 0, s>>>(T, Sy, dY, d.H, d.M, d.M * C, nrm);
+  k_spec_cols<<<d.B * cdiv(d.M, 16) * cdiv(d.M * C, 16), 256, 0, s>>>(T, Sy, dY, d.H, d.M, d.M * C, nrm);
   k_spec_minv<C, true><<<d.B * d.M * cdiv(d.H, 64), 256, 0, s>>>(dY, n.bfw(T_SWK), Sy, Z, d.H, d.M, 1.f);
   k_spec_dwk<<<cdiv((long long)d.M * d.M * C * C, 256), 256, 0, s>>>(dY, X, n.grad(T_SWK), d.B, d.M, C);
   launch_spec_out<C, true>(dim3(d.B * d.H * cdiv(d.W, 64)), s, dz[0], n.bfw(T_SW1), nullptr, Z, Sx,
@@ -2639,14 +2646,7 @@ void fluid_forward(const FNet& n, const Ptrs& f, const Ptrs& u, int blocks, hipS
   const long long HW = d.HW;
   double* sv = n.w<double>(n.wl.s);
   double* r0 = n.w<double>(n.wl.r0);
-  k_resid_in<<<dim3(cdiv(HW, 256), d.B), 256, 0, s>>>(f, u, r0, d.H, d.W);
-  Ptrs rp{};
-  for (int b = 0; b < d.B; ++b) rp.p[b] = r0 + (size_t)b * HW;
-  double* rms_part = n.w<double>(n.wl.rms);
-  k_sumsq<<<dim3(kRmsBlocks, 2 * d.B), 256, 0, s>>>(rp, f, d.B, HW, rms_part);
-  k_rms_fin<<<2 * d.B, 64, 0, s>>>(rms_part, d.B, HW, sv);
-  k_norm_in<<<dim3(cdiv(HW, 256), d.B), 256, 0, s>>>(r0, f, sv + d.B, sv + 2 * d.B,
-                                                      n.w<bf16>(n.wl.X[0]), HW);
+  normalise_inputs(f, u, r0, n.w<double>(n.wl.rms), sv, n.w<bf16>(n.wl.X[0]), d.B, d.H, d.W, s);
   for (int l = 1; l < d.L; ++l) {
     const int Hl = d.H >> l, Wl = d.W >> l;
     k_pool_in<<<dim3(cdiv((long long)Hl * Wl, 256), d.B), 256, 0, s>>>(
