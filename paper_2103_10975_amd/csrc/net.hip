@@ -386,6 +386,18 @@ __device__ __forceinline__ uint32_t bf16_word_pick(const bf16* base, long long e
   return (e & 1) ? (w >> 16) : (w & 0xffffu);
 }
 
+// Block index of this workgroup along x (n = gridDim.x blocks): workgroup g
+// runs on XCD g mod 8 (each XCD has its own L2), so when 8 divides n the
+// blocks are dealt out as 8 contiguous ranges, one per XCD; the 3 x 3
+// neighbourhoods of adjacent rows then come from the L2 that already holds
+// them instead of being fetched again by another XCD (the output
+// convolution read 3.2x its input without this).  With a y dimension the
+// workgroup's linear index is x + n y, so the XCD is still x mod 8.
+__device__ __forceinline__ int xcd_block() {
+  const int n = gridDim.x, g = blockIdx.x;
+  return n % 8 ? g : (g % 8) * (n / 8) + g / 8;
+}
+
 // out[p][co] = ReLU(bias[co] + sum_{t, ci} W[co][ci][t] in[p + off(t)][ci]) for
 // 2 input channels, v_mfma_f32_16x16x32_bf16 with K = 9 taps x 2 channels
 // (padded to 32): A = W (16 channels x 32), B = the 18 tap values of 16
@@ -417,6 +429,7 @@ __global__ __launch_bounds__(256) void k_conv_in_mfma(const bf16* in, const bf16
     for (int r = 0; r < 4; ++r) bl[mt][r] = bf2f(bias[mt * 16 + 4 * lg + r]);
   }
   const uint32_t* inw = reinterpret_cast<const uint32_t*>(in) + (size_t)b * HW;   // one word per pixel
+  const long long blk = xcd_block();
   // the neighbourhoods of all four 16-pixel steps of this wavefront are
   // loaded first, at clamped positions (no branch between the loads); the
   // out-of-grid taps are zeroed afterwards (the empty asm keeps the compiler
@@ -425,7 +438,7 @@ __global__ __launch_bounds__(256) void k_conv_in_mfma(const bf16* in, const bf16
   bool in_tap[4][4];
 #pragma unroll
   for (int st = 0; st < 4; ++st) {
-    const long long p = (long long)blockIdx.x * 256 + wv * 64 + st * 16 + li;
+    const long long p = blk * 256 + wv * 64 + st * 16 + li;
     const long long pc = p < HW ? p : HW - 1;
     const int y = (int)(pc / W), x = (int)(pc % W);
 #pragma unroll
@@ -438,8 +451,8 @@ __global__ __launch_bounds__(256) void k_conv_in_mfma(const bf16* in, const bf16
   }
 #pragma unroll
   for (int st = 0; st < 4; ++st) {
-    const long long p = (long long)blockIdx.x * 256 + wv * 64 + st * 16 + li;
-    if ((long long)blockIdx.x * 256 + wv * 64 + st * 16 >= HW) break;    // wavefront-uniform
+    const long long p = blk * 256 + wv * 64 + st * 16 + li;
+    if (blk * 256 + wv * 64 + st * 16 >= HW) break;                     // wavefront-uniform
     uint32_t vm[4];
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
@@ -494,9 +507,10 @@ __global__ __launch_bounds__(256) void k_conv_out_mfma(const bf16* in, const bf1
   }
   const float bv = bf2f(bias[0]);
   const bf16* inb = in + (size_t)b * HW * C;
+  const long long blk = xcd_block();
 #pragma unroll 1
   for (int st = 0; st < 4; ++st) {
-    const long long p0 = (long long)blockIdx.x * 256 + wv * 64 + st * 16;
+    const long long p0 = blk * 256 + wv * 64 + st * 16;
     if (p0 >= HW) break;                                   // wavefront-uniform
     const long long p = p0 + li, pc = p < HW ? p : HW - 1;
     const int y = (int)(pc / W), x = (int)(pc % W);
@@ -547,9 +561,10 @@ __global__ __launch_bounds__(256) void k_conv_outT_mfma(const float* dout, const
       wa[s][mt] = tt < 9 ? v : 0.f;
     }
   const float* db = dout + (size_t)b * HW;
+  const long long blk = xcd_block();
 #pragma unroll 1
   for (int st = 0; st < 4; ++st) {
-    const long long p0 = (long long)blockIdx.x * 256 + wv * 64 + st * 16;
+    const long long p0 = blk * 256 + wv * 64 + st * 16;
     if (p0 >= HW) break;                                   // wavefront-uniform
     const long long p = p0 + li, pc = p < HW ? p : HW - 1;
     const int y = (int)(pc / W), x = (int)(pc % W);
