@@ -192,14 +192,80 @@ WsLayout ws_layout(const Dims& d, bool train) {
 
 // ------------------------------------------------------------------ small kernels
 
+// Sine bases (DST-I): S[k][j] = sin((k+1) pi (j+1) / (n+1)), the slowest modes.
+// Every basis one pass needs (filled beside the network input, see k_resid_sumsq):
+//   Sx       FP32 [MP][WP]  x direction of the spectral layer, zero for k >= M
+//            or j >= W (MP = M rounded up to 16, WP = W rounded up to 256)
+//   Sxh, Sxl BF16 [MP][WP]  Sx = Sxh + Sxl to within 2^-17 |Sx| (the two BF16
+//            halves of the MFMA row transform)
+//   Sy       FP32 [M][H]    y direction of the spectral layer
+//   kSx      FP64 [K][W], kSxT FP64 [W][K], kSy FP64 [K][H]  the band path
+struct Bases {
+  float* Sx;
+  bf16* Sxh;
+  bf16* Sxl;
+  float* Sy;
+  double* kSx;
+  double* kSxT;
+  double* kSy;
+  int M, MP, W, WP, H, K;
+};
+
+__device__ __forceinline__ double sine_mode(int k, int j, int n) {
+  return sin((double)(k + 1) * M_PI * (double)(j + 1) / (double)(n + 1));
+}
+
+// Element e of the concatenated bases (Sx with its BF16 halves, Sy, kSx with
+// kSxT, kSy).
+__device__ __forceinline__ void bases_at(const Bases& o, long long e) {
+  const long long n1 = (long long)o.MP * o.WP, n2 = (long long)o.M * o.H;
+  const long long n3 = (long long)o.K * o.W, n4 = (long long)o.K * o.H;
+  if (e < n1) {
+    const int k = (int)(e / o.WP), j = (int)(e % o.WP);
+    const float f = (k < o.M && j < o.W) ? (float)sine_mode(k, j, o.W) : 0.f;
+    const bf16 h = f2bf(f);
+    o.Sx[e] = f;
+    o.Sxh[e] = h;
+    o.Sxl[e] = f2bf(f - bf2f(h));
+    return;
+  }
+  e -= n1;
+  if (e < n2) {
+    o.Sy[e] = (float)sine_mode((int)(e / o.H), (int)(e % o.H), o.H);
+    return;
+  }
+  e -= n2;
+  if (e < n3) {
+    const int k = (int)(e / o.W), j = (int)(e % o.W);
+    const double v = sine_mode(k, j, o.W);
+    o.kSx[e] = v;
+    o.kSxT[(size_t)j * o.K + k] = v;
+    return;
+  }
+  e -= n3;
+  if (e < n4) o.kSy[e] = sine_mode((int)(e / o.H), (int)(e % o.H), o.H);
+}
+
+inline long long bases_count(const Bases& o) {
+  return (long long)o.MP * o.WP + (long long)o.M * o.H + (long long)o.K * (o.W + o.H);
+}
+
 // The residual r_b = f_b - A u_b of each image (FP64, the 5-point operator
 // of the solver) written out, with the sums of squares of the B residuals
 // and the B sources over kRmsBlocks contiguous chunks per field (blockIdx.y:
-// field r_0..r_{B-1}, f_0..f_{B-1}); each chunk's sum in a fixed order.
+// field r_0..r_{B-1}, f_0..f_{B-1}); each chunk's sum in a fixed order.  A
+// plane blockIdx.y = 2B, when launched, fills the network's sine bases
+// (nbases elements), which depend on nothing else.
 __global__ __launch_bounds__(256) void k_resid_sumsq(Ptrs f, Ptrs u, double* r, int B, int H, int W,
-                                                     double* part) {
+                                                     double* part, Bases o, long long nbases) {
   __shared__ double red[4];
   const int fi = blockIdx.y;
+  if (fi == 2 * B) {                                     // the extra plane: the sine bases
+    for (long long e = (long long)blockIdx.x * 256 + threadIdx.x; e < nbases;
+         e += (long long)gridDim.x * 256)
+      bases_at(o, e);
+    return;
+  }
   const long long n = (long long)H * W;
   const long long c0 = n * blockIdx.x / kRmsBlocks, c1 = n * (blockIdx.x + 1) / kRmsBlocks;
   double acc = 0.0;
@@ -429,52 +495,54 @@ __global__ __launch_bounds__(256) void k_conv_in_mfma(const bf16* in, const bf16
     for (int r = 0; r < 4; ++r) bl[mt][r] = bf2f(bias[mt * 16 + 4 * lg + r]);
   }
   const uint32_t* inw = reinterpret_cast<const uint32_t*>(in) + (size_t)b * HW;   // one word per pixel
-  const long long blk = xcd_block();
-  // the neighbourhoods of all four 16-pixel steps of this wavefront are
-  // loaded first, at clamped positions (no branch between the loads); the
-  // out-of-grid taps are zeroed afterwards (the empty asm keeps the compiler
-  // from turning that select into a branch around each load)
-  uint32_t v[4][4];
-  bool in_tap[4][4];
+  const long long nblk = (HW + 255) / 256;
+  for (long long blk = xcd_block(); blk < nblk; blk += gridDim.x) {
+    // the neighbourhoods of all four 16-pixel steps of this wavefront are
+    // loaded first, at clamped positions (no branch between the loads); the
+    // out-of-grid taps are zeroed afterwards (the empty asm keeps the compiler
+    // from turning that select into a branch around each load)
+    uint32_t v[4][4];
+    bool in_tap[4][4];
 #pragma unroll
-  for (int st = 0; st < 4; ++st) {
-    const long long p = blk * 256 + wv * 64 + st * 16 + li;
-    const long long pc = p < HW ? p : HW - 1;
-    const int y = (int)(pc / W), x = (int)(pc % W);
+    for (int st = 0; st < 4; ++st) {
+      const long long p = blk * 256 + wv * 64 + st * 16 + li;
+      const long long pc = p < HW ? p : HW - 1;
+      const int y = (int)(pc / W), x = (int)(pc % W);
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int tt = 4 * lg + q, dy = tt / 3 - 1, dx = tt % 3 - 1;
-      const int yy = y + dy, xx = x + dx;
-      v[st][q] = inw[(long long)min(max(yy, 0), H - 1) * W + min(max(xx, 0), W - 1)];
-      in_tap[st][q] = tt < 9 && yy >= 0 && yy < H && xx >= 0 && xx < W;
+      for (int q = 0; q < 4; ++q) {
+        const int tt = 4 * lg + q, dy = tt / 3 - 1, dx = tt % 3 - 1;
+        const int yy = y + dy, xx = x + dx;
+        v[st][q] = inw[(long long)min(max(yy, 0), H - 1) * W + min(max(xx, 0), W - 1)];
+        in_tap[st][q] = tt < 9 && yy >= 0 && yy < H && xx >= 0 && xx < W;
+      }
     }
-  }
 #pragma unroll
-  for (int st = 0; st < 4; ++st) {
-    const long long p = blk * 256 + wv * 64 + st * 16 + li;
-    if (blk * 256 + wv * 64 + st * 16 >= HW) break;                     // wavefront-uniform
-    uint32_t vm[4];
+    for (int st = 0; st < 4; ++st) {
+      const long long p = blk * 256 + wv * 64 + st * 16 + li;
+      if (blk * 256 + wv * 64 + st * 16 >= HW) break;                     // wavefront-uniform
+      uint32_t vm[4];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      uint32_t w = v[st][q];
-      asm volatile("" : "+v"(w));
-      vm[q] = in_tap[st][q] ? w : 0u;
-    }
-    const bf16x8 bx = __builtin_bit_cast(bf16x8, make_uint4(vm[0], vm[1], vm[2], vm[3]));
-    floatx4 acc[2];
+      for (int q = 0; q < 4; ++q) {
+        uint32_t w = v[st][q];
+        asm volatile("" : "+v"(w));
+        vm[q] = in_tap[st][q] ? w : 0u;
+      }
+      const bf16x8 bx = __builtin_bit_cast(bf16x8, make_uint4(vm[0], vm[1], vm[2], vm[3]));
+      floatx4 acc[2];
 #pragma unroll
-    for (int mt = 0; mt < 2; ++mt)
-      acc[mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa[mt], bx, floatx4{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
-    if (p < HW) {
+      for (int mt = 0; mt < 2; ++mt)
+        acc[mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa[mt], bx, floatx4{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
+      if (p < HW) {
 #pragma unroll
-      for (int mt = 0; mt < 2; ++mt) {
-        float o[4];
+        for (int mt = 0; mt < 2; ++mt) {
+          float o[4];
 #pragma unroll
-        for (int r = 0; r < 4; ++r) o[r] = fmaxf(acc[mt][r] + bl[mt][r], 0.f);
-        uint2 w2;
-        w2.x = (uint32_t)f2bf(o[0]) | ((uint32_t)f2bf(o[1]) << 16);
-        w2.y = (uint32_t)f2bf(o[2]) | ((uint32_t)f2bf(o[3]) << 16);
-        *reinterpret_cast<uint2*>(out + ((size_t)b * HW + p) * C + mt * 16 + 4 * lg) = w2;
+          for (int r = 0; r < 4; ++r) o[r] = fmaxf(acc[mt][r] + bl[mt][r], 0.f);
+          uint2 w2;
+          w2.x = (uint32_t)f2bf(o[0]) | ((uint32_t)f2bf(o[1]) << 16);
+          w2.y = (uint32_t)f2bf(o[2]) | ((uint32_t)f2bf(o[3]) << 16);
+          *reinterpret_cast<uint2*>(out + ((size_t)b * HW + p) * C + mt * 16 + 4 * lg) = w2;
+        }
       }
     }
   }
@@ -507,32 +575,34 @@ __global__ __launch_bounds__(256) void k_conv_out_mfma(const bf16* in, const bf1
   }
   const float bv = bf2f(bias[0]);
   const bf16* inb = in + (size_t)b * HW * C;
-  const long long blk = xcd_block();
+  const long long nblk = (HW + 255) / 256;
+  for (long long blk = xcd_block(); blk < nblk; blk += gridDim.x) {
 #pragma unroll 1
-  for (int st = 0; st < 4; ++st) {
-    const long long p0 = blk * 256 + wv * 64 + st * 16;
-    if (p0 >= HW) break;                                   // wavefront-uniform
-    const long long p = p0 + li, pc = p < HW ? p : HW - 1;
-    const int y = (int)(pc / W), x = (int)(pc % W);
-    uint4 a[9];
+    for (int st = 0; st < 4; ++st) {
+      const long long p0 = blk * 256 + wv * 64 + st * 16;
+      if (p0 >= HW) break;                                   // wavefront-uniform
+      const long long p = p0 + li, pc = p < HW ? p : HW - 1;
+      const int y = (int)(pc / W), x = (int)(pc % W);
+      uint4 a[9];
 #pragma unroll
-    for (int t = 0; t < 9; ++t) {
-      const int yy = y + t / 3 - 1, xx = x + t % 3 - 1;
-      const uint4 u = *reinterpret_cast<const uint4*>(
-          inb + ((long long)min(max(yy, 0), H - 1) * W + min(max(xx, 0), W - 1)) * C + 8 * lg);
-      const bool ok = yy >= 0 && yy < H && xx >= 0 && xx < W;
-      a[t] = ok ? u : make_uint4(0, 0, 0, 0);
-    }
-    floatx4 acc = floatx4{0.f, 0.f, 0.f, 0.f};
+      for (int t = 0; t < 9; ++t) {
+        const int yy = y + t / 3 - 1, xx = x + t % 3 - 1;
+        const uint4 u = *reinterpret_cast<const uint4*>(
+            inb + ((long long)min(max(yy, 0), H - 1) * W + min(max(xx, 0), W - 1)) * C + 8 * lg);
+        const bool ok = yy >= 0 && yy < H && xx >= 0 && xx < W;
+        a[t] = ok ? u : make_uint4(0, 0, 0, 0);
+      }
+      floatx4 acc = floatx4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-    for (int t = 0; t < 9; ++t)
-      acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a[t]), wb[t], acc, 0, 0, 0);
-    // D[p][n]: lane holds pixels p0 + 4 lg + r of column li
-    if (li == 0) {
+      for (int t = 0; t < 9; ++t)
+        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a[t]), wb[t], acc, 0, 0, 0);
+      // D[p][n]: lane holds pixels p0 + 4 lg + r of column li
+      if (li == 0) {
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const long long q = p0 + 4 * lg + r;
-        if (q < HW) out[(size_t)b * HW + q] = acc[r] + bv;
+        for (int r = 0; r < 4; ++r) {
+          const long long q = p0 + 4 * lg + r;
+          if (q < HW) out[(size_t)b * HW + q] = acc[r] + bv;
+        }
       }
     }
   }
@@ -561,38 +631,40 @@ __global__ __launch_bounds__(256) void k_conv_outT_mfma(const float* dout, const
       wa[s][mt] = tt < 9 ? v : 0.f;
     }
   const float* db = dout + (size_t)b * HW;
-  const long long blk = xcd_block();
+  const long long nblk = (HW + 255) / 256;
+  for (long long blk = xcd_block(); blk < nblk; blk += gridDim.x) {
 #pragma unroll 1
-  for (int st = 0; st < 4; ++st) {
-    const long long p0 = blk * 256 + wv * 64 + st * 16;
-    if (p0 >= HW) break;                                   // wavefront-uniform
-    const long long p = p0 + li, pc = p < HW ? p : HW - 1;
-    const int y = (int)(pc / W), x = (int)(pc % W);
-    float bvv[3];
+    for (int st = 0; st < 4; ++st) {
+      const long long p0 = blk * 256 + wv * 64 + st * 16;
+      if (p0 >= HW) break;                                   // wavefront-uniform
+      const long long p = p0 + li, pc = p < HW ? p : HW - 1;
+      const int y = (int)(pc / W), x = (int)(pc % W);
+      float bvv[3];
 #pragma unroll
-    for (int s = 0; s < 3; ++s) {
-      const int tt = 4 * s + lg, yy = y + tt / 3 - 1, xx = x + tt % 3 - 1;
-      const float v = db[(long long)min(max(yy, 0), H - 1) * W + min(max(xx, 0), W - 1)];
-      bvv[s] = (tt < 9 && yy >= 0 && yy < H && xx >= 0 && xx < W) ? v : 0.f;
-    }
-    const size_t base = ((size_t)b * HW + pc) * C;
+      for (int s = 0; s < 3; ++s) {
+        const int tt = 4 * s + lg, yy = y + tt / 3 - 1, xx = x + tt % 3 - 1;
+        const float v = db[(long long)min(max(yy, 0), H - 1) * W + min(max(xx, 0), W - 1)];
+        bvv[s] = (tt < 9 && yy >= 0 && yy < H && xx >= 0 && xx < W) ? v : 0.f;
+      }
+      const size_t base = ((size_t)b * HW + pc) * C;
 #pragma unroll
-    for (int mt = 0; mt < 2; ++mt) {
-      floatx4 acc = floatx4{0.f, 0.f, 0.f, 0.f};
+      for (int mt = 0; mt < 2; ++mt) {
+        floatx4 acc = floatx4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-      for (int s = 0; s < 3; ++s) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(wa[s][mt], bvv[s], acc, 0, 0, 0);
-      // lane holds channels mt*16 + 4 lg + r of pixel p
-      const uint2 mu = *reinterpret_cast<const uint2*>(mask + base + mt * 16 + 4 * lg);
-      if (p >= HW) continue;
-      const float m4[4] = {__uint_as_float(mu.x << 16), __uint_as_float(mu.x & 0xffff0000u),
-                           __uint_as_float(mu.y << 16), __uint_as_float(mu.y & 0xffff0000u)};
-      float o[4];
+        for (int s = 0; s < 3; ++s) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(wa[s][mt], bvv[s], acc, 0, 0, 0);
+        // lane holds channels mt*16 + 4 lg + r of pixel p
+        const uint2 mu = *reinterpret_cast<const uint2*>(mask + base + mt * 16 + 4 * lg);
+        if (p >= HW) continue;
+        const float m4[4] = {__uint_as_float(mu.x << 16), __uint_as_float(mu.x & 0xffff0000u),
+                             __uint_as_float(mu.y << 16), __uint_as_float(mu.y & 0xffff0000u)};
+        float o[4];
 #pragma unroll
-      for (int r = 0; r < 4; ++r) o[r] = m4[r] > 0.f ? acc[r] : 0.f;
-      uint2 w2;
-      w2.x = (uint32_t)f2bf(o[0]) | ((uint32_t)f2bf(o[1]) << 16);
-      w2.y = (uint32_t)f2bf(o[2]) | ((uint32_t)f2bf(o[3]) << 16);
-      *reinterpret_cast<uint2*>(dz + base + mt * 16 + 4 * lg) = w2;
+        for (int r = 0; r < 4; ++r) o[r] = m4[r] > 0.f ? acc[r] : 0.f;
+        uint2 w2;
+        w2.x = (uint32_t)f2bf(o[0]) | ((uint32_t)f2bf(o[1]) << 16);
+        w2.y = (uint32_t)f2bf(o[2]) | ((uint32_t)f2bf(o[3]) << 16);
+        *reinterpret_cast<uint2*>(dz + base + mt * 16 + 4 * lg) = w2;
+      }
     }
   }
 }
@@ -1199,59 +1271,6 @@ __global__ __launch_bounds__(256) void k_wgrad_mfma(const bf16* in, const bf16* 
 }
 
 // ------------------------------------------------------------------ spectral layer
-// Sine bases (DST-I): S[k][j] = sin((k+1) pi (j+1) / (n+1)), the slowest modes.
-// Every basis one pass needs, in one launch:
-//   Sx       FP32 [MP][WP]  x direction of the spectral layer, zero for k >= M
-//            or j >= W (MP = M rounded up to 16, WP = W rounded up to 256)
-//   Sxh, Sxl BF16 [MP][WP]  Sx = Sxh + Sxl to within 2^-17 |Sx| (the two BF16
-//            halves of the MFMA row transform)
-//   Sy       FP32 [M][H]    y direction of the spectral layer
-//   kSx      FP64 [K][W], kSxT FP64 [W][K], kSy FP64 [K][H]  the band path
-struct Bases {
-  float* Sx;
-  bf16* Sxh;
-  bf16* Sxl;
-  float* Sy;
-  double* kSx;
-  double* kSxT;
-  double* kSy;
-  int M, MP, W, WP, H, K;
-};
-
-__device__ __forceinline__ double sine_mode(int k, int j, int n) {
-  return sin((double)(k + 1) * M_PI * (double)(j + 1) / (double)(n + 1));
-}
-
-__global__ void k_bases(Bases o) {
-  long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  const long long n1 = (long long)o.MP * o.WP, n2 = (long long)o.M * o.H;
-  const long long n3 = (long long)o.K * o.W, n4 = (long long)o.K * o.H;
-  if (e < n1) {
-    const int k = (int)(e / o.WP), j = (int)(e % o.WP);
-    const float f = (k < o.M && j < o.W) ? (float)sine_mode(k, j, o.W) : 0.f;
-    const bf16 h = f2bf(f);
-    o.Sx[e] = f;
-    o.Sxh[e] = h;
-    o.Sxl[e] = f2bf(f - bf2f(h));
-    return;
-  }
-  e -= n1;
-  if (e < n2) {
-    o.Sy[e] = (float)sine_mode((int)(e / o.H), (int)(e % o.H), o.H);
-    return;
-  }
-  e -= n2;
-  if (e < n3) {
-    const int k = (int)(e / o.W), j = (int)(e % o.W);
-    const double v = sine_mode(k, j, o.W);
-    o.kSx[e] = v;
-    o.kSxT[(size_t)j * o.K + k] = v;
-    return;
-  }
-  e -= n3;
-  if (e < n4) o.kSy[e] = sine_mode((int)(e / o.H), (int)(e % o.H), o.H);
-}
-
 constexpr int kRowChunk = 256;                   // columns per staged chunk (WP's multiple)
 
 // T[r][l][c] = sum_j Sx[l][j] x[r][j][c] for l < M (r = b H + i): the row
@@ -2153,12 +2172,28 @@ __global__ void k_adam(float* master, const float* grad, float* m, float* v, bf1
 // ------------------------------------------------------------------ host helpers
 inline int cdiv(long long a, long long b) { return (int)((a + b - 1) / b); }
 
+// Workgroups per image of the per-pixel convolutions, which loop over the
+// image's 256-pixel blocks: at most 2048 over the batch (measured at 512²:
+// a batch of 8 with 256 per image ran the input and output convolutions in
+// 49 and 84 µs against 61 and 101 µs with one workgroup per block, while a
+// single image keeps one per block, 1024).  The output-gradient convolution
+// keeps one workgroup per block (capped it ran 78 against 69 µs).
+constexpr int kPixelBlocksTotal = 2048;
+inline int pixel_blocks(long long hw, int B) {
+  return (int)std::max<long long>(1, std::min<long long>(cdiv(hw, 256), kPixelBlocksTotal / B));
+}
+
 // The network inputs of a batch: residuals r0 (FP64), their and the sources'
-// RMS in sv, and the normalised two-channel BF16 input x0.
+// RMS in sv, and the normalised two-channel BF16 input x0; with `bases`, the
+// same launch fills the sine bases.
 static void normalise_inputs(const Ptrs& f, const Ptrs& u, double* r0, double* rms_part, double* sv,
-                             bf16* x0, int B, int H, int W, hipStream_t s) {
+                             bf16* x0, int B, int H, int W, hipStream_t s,
+                             const Bases* bases = nullptr) {
   const long long HW = (long long)H * W;
-  k_resid_sumsq<<<dim3(kRmsBlocks, 2 * B), 256, 0, s>>>(f, u, r0, B, H, W, rms_part);
+  const Bases o = bases ? *bases : Bases{};
+  const long long nb = bases ? bases_count(o) : 0;
+  k_resid_sumsq<<<dim3(kRmsBlocks, 2 * B + (bases ? 1 : 0)), 256, 0, s>>>(f, u, r0, B, H, W,
+                                                                          rms_part, o, nb);
   k_norm_in<<<dim3(cdiv(HW, 256), B), 256, 0, s>>>(r0, f, rms_part, sv, B, x0, HW);
 }
 
@@ -2245,15 +2280,11 @@ void forward(const Net& n, const Ptrs& f, const Ptrs& u, hipStream_t s, bool gat
   double* sv = n.w<double>(n.wl.s);            // s_r[B], s_in[B], s_f[B]
   double* r0 = n.w<double>(n.wl.r0);
   const int WP = spec_wp(d);
-  {
-    Bases bs{Sx, n.w<bf16>(n.wl.Sxh), n.w<bf16>(n.wl.Sxl), Sy, n.w<double>(n.wl.kSx),
-             n.w<double>(n.wl.kSxT), n.w<double>(n.wl.kSy), d.M, spec_mp(d), d.W, WP, d.H, d.K};
-    const long long nb = (long long)bs.MP * WP + (long long)d.M * d.H + (long long)d.K * (d.W + d.H);
-    k_bases<<<cdiv(nb, 256), 256, 0, s>>>(bs);
-  }
-  normalise_inputs(f, u, r0, n.w<double>(n.wl.rms), sv, x0, d.B, d.H, d.W, s);
+  const Bases bs{Sx, n.w<bf16>(n.wl.Sxh), n.w<bf16>(n.wl.Sxl), Sy, n.w<double>(n.wl.kSx),
+                 n.w<double>(n.wl.kSxT), n.w<double>(n.wl.kSy), d.M, spec_mp(d), d.W, WP, d.H, d.K};
+  normalise_inputs(f, u, r0, n.w<double>(n.wl.rms), sv, x0, d.B, d.H, d.W, s, &bs);
   // L1, L2
-  k_conv_in_mfma<C><<<dim3(cdiv(HW, 256), d.B), 256, 0, s>>>(
+  k_conv_in_mfma<C><<<dim3(pixel_blocks(HW, d.B), d.B), 256, 0, s>>>(
       x0, n.bfw(T_C1W), n.bfw(T_C1B), a[0], d.H, d.W);
   k_conv_mfma<C, false><<<conv_grid(d.B, d.H, d.W), 256, 0, s>>>(a[0], n.bfw(T_C2W), n.bfw(T_C2B), nullptr, a[1], d.B, d.H, d.W);
   // L3 spectral
@@ -2270,7 +2301,7 @@ void forward(const Net& n, const Ptrs& f, const Ptrs& u, hipStream_t s, bool gat
   // L4, L5, L6
   k_conv_mfma<C, false><<<conv_grid(d.B, d.H, d.W), 256, 0, s>>>(a[2], n.bfw(T_C4W), n.bfw(T_C4B), nullptr, a[3], d.B, d.H, d.W);
   k_conv_mfma<C, false><<<conv_grid(d.B, d.H, d.W), 256, 0, s>>>(a[3], n.bfw(T_C5W), n.bfw(T_C5B), nullptr, a[4], d.B, d.H, d.W);
-  k_conv_out_mfma<C><<<dim3(cdiv(HW, 256), d.B), 256, 0, s>>>(
+  k_conv_out_mfma<C><<<dim3(pixel_blocks(HW, d.B), d.B), 256, 0, s>>>(
       a[4], n.bfw(T_C6W), n.bfw(T_C6B), n.w<float>(n.wl.out), d.H, d.W);
   // band path from the FP64 residual, replacing the band of the
   // convolutional output: out += norm S^T (w X - S out S^T) S (FP64)
@@ -2671,7 +2702,7 @@ void fluid_forward(const FNet& n, const Ptrs& f, const Ptrs& u, int blocks, hipS
   for (int l = 0; l < d.L; ++l) {
     const int Hl = d.H >> l, Wl = d.W >> l;
     const long long hw = (long long)Hl * Wl;
-    k_conv_in_mfma<C><<<dim3(cdiv(hw, 256), d.B), 256, 0, s>>>(
+    k_conv_in_mfma<C><<<dim3(pixel_blocks(hw, d.B), d.B), 256, 0, s>>>(
         n.w<bf16>(n.wl.X[l]), n.bfw(fl_lvl(l, 0)), n.bfw(fl_lvl(l, 1)), n.w<bf16>(n.wl.A[l]), Hl,
         Wl);
     k_conv_mfma<C, false><<<conv_grid(d.B, Hl, Wl), 256, 0, s>>>(n.w<bf16>(n.wl.A[l]), n.bfw(fl_lvl(l, 2)), n.bfw(fl_lvl(l, 3)), nullptr, n.w<bf16>(n.wl.Y[l]), d.B, Hl, Wl);
@@ -2684,7 +2715,7 @@ void fluid_forward(const FNet& n, const Ptrs& f, const Ptrs& u, int blocks, hipS
     k_conv_mfma<C, false, true><<<conv_grid(d.B, d.H, d.W), 256, 0, s>>>(n.w<bf16>(n.wl.Hb[i]), n.bfw(fl_blk(d, i, 2)), n.bfw(fl_blk(d, i, 3)), n.w<bf16>(n.wl.S[i]), n.w<bf16>(n.wl.S[i + 1]), d.B, d.H, d.W);
   }
   k_conv_mfma<C, false><<<conv_grid(d.B, d.H, d.W), 256, 0, s>>>(n.w<bf16>(n.wl.S[blocks]), n.bfw(fl_head(d, 0)), n.bfw(fl_head(d, 1)), nullptr, n.w<bf16>(n.wl.o), d.B, d.H, d.W);
-  k_conv_out_mfma<C><<<dim3(cdiv(HW, 256), d.B), 256, 0, s>>>(
+  k_conv_out_mfma<C><<<dim3(pixel_blocks(HW, d.B), d.B), 256, 0, s>>>(
       n.w<bf16>(n.wl.o), n.bfw(fl_head(d, 2)), n.bfw(fl_head(d, 3)), n.w<float>(n.wl.out), d.H,
       d.W);
 }
