@@ -456,8 +456,8 @@ __device__ __forceinline__ uint32_t bf16_word_pick(const bf16* base, long long e
 // runs on XCD g mod 8 (each XCD has its own L2), so when 8 divides n the
 // blocks are dealt out as 8 contiguous ranges, one per XCD; the 3 x 3
 // neighbourhoods of adjacent rows then come from the L2 that already holds
-// them instead of being fetched again by another XCD (the output
-// convolution read 3.2x its input without this).  With a y dimension the
+// them instead of being fetched again by another XCD (a per-pixel 3 x 3
+// read of 32 channels fetched 3.2x its input without this).  With a y dimension the
 // workgroup's linear index is x + n y, so the XCD is still x mod 8.
 __device__ __forceinline__ int xcd_block() {
   const int n = gridDim.x, g = blockIdx.x;
@@ -542,66 +542,6 @@ __global__ __launch_bounds__(256) void k_conv_in_mfma(const bf16* in, const bf16
           w2.x = (uint32_t)f2bf(o[0]) | ((uint32_t)f2bf(o[1]) << 16);
           w2.y = (uint32_t)f2bf(o[2]) | ((uint32_t)f2bf(o[3]) << 16);
           *reinterpret_cast<uint2*>(out + ((size_t)b * HW + p) * C + mt * 16 + 4 * lg) = w2;
-        }
-      }
-    }
-  }
-}
-
-// out[p] = bias + sum_{t, ci} W[0][ci][t] in[p + off(t)][ci] (C -> 1, FP32
-// out): v_mfma_f32_16x16x32_bf16 per tap with the pixels as rows, A = the
-// input (16 pixels x 32 channels, one 16-byte read per lane and tap), B = the
-// tap's weights in column 0 (the other columns zero); D column 0 holds the
-// 16 outputs.
-template <int C>
-__global__ __launch_bounds__(256) void k_conv_out_mfma(const bf16* in, const bf16* wt,
-                                                       const bf16* bias, float* out, int H, int W) {
-  static_assert(C == 32, "one K = 32 step per tap");
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  const int li = lane & 15, lg = lane >> 4;
-  const int b = blockIdx.y;
-  const long long HW = (long long)H * W;
-  // B[k][n] = W[0][8 lg + e][t] for n = 0
-  bf16x8 wb[9];
-#pragma unroll
-  for (int t = 0; t < 9; ++t) {
-    uint32_t h[8];
-#pragma unroll
-    for (int e = 0; e < 8; ++e) h[e] = bf16_word_pick(wt, (long long)(8 * lg + e) * 9 + t);
-#pragma unroll
-    for (int e = 0; e < 8; ++e) h[e] = li == 0 ? h[e] : 0u;
-    wb[t] = __builtin_bit_cast(bf16x8, make_uint4(h[0] | (h[1] << 16), h[2] | (h[3] << 16),
-                                                  h[4] | (h[5] << 16), h[6] | (h[7] << 16)));
-  }
-  const float bv = bf2f(bias[0]);
-  const bf16* inb = in + (size_t)b * HW * C;
-  const long long nblk = (HW + 255) / 256;
-  for (long long blk = xcd_block(); blk < nblk; blk += gridDim.x) {
-#pragma unroll 1
-    for (int st = 0; st < 4; ++st) {
-      const long long p0 = blk * 256 + wv * 64 + st * 16;
-      if (p0 >= HW) break;                                   // wavefront-uniform
-      const long long p = p0 + li, pc = p < HW ? p : HW - 1;
-      const int y = (int)(pc / W), x = (int)(pc % W);
-      uint4 a[9];
-#pragma unroll
-      for (int t = 0; t < 9; ++t) {
-        const int yy = y + t / 3 - 1, xx = x + t % 3 - 1;
-        const uint4 u = *reinterpret_cast<const uint4*>(
-            inb + ((long long)min(max(yy, 0), H - 1) * W + min(max(xx, 0), W - 1)) * C + 8 * lg);
-        const bool ok = yy >= 0 && yy < H && xx >= 0 && xx < W;
-        a[t] = ok ? u : make_uint4(0, 0, 0, 0);
-      }
-      floatx4 acc = floatx4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-      for (int t = 0; t < 9; ++t)
-        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a[t]), wb[t], acc, 0, 0, 0);
-      // D[p][n]: lane holds pixels p0 + 4 lg + r of column li
-      if (li == 0) {
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const long long q = p0 + 4 * lg + r;
-          if (q < HW) out[(size_t)b * HW + q] = acc[r] + bv;
         }
       }
     }
@@ -1099,6 +1039,101 @@ __global__ __launch_bounds__(256) void k_conv_mfma(const bf16* in, const bf16* w
                                         reinterpret_cast<unsigned long long*>(out + o));
           else
             *reinterpret_cast<uint2*>(out + o) = w2;
+        }
+      }
+    }
+  }
+}
+
+// out[p] = bias + sum_{t, ci} W[0][ci][t] in[p + off(t)][ci] (C -> 1, FP32
+// out), persistent over 64 x 8 pixel tiles staged in LDS with their halo as in
+// k_conv_mfma (the next tile's input in flight during the MFMAs): a pixel's
+// 3 x 3 neighbourhood then comes from LDS instead of nine 64-byte reads from
+// the caches.  v_mfma_f32_16x16x32_bf16 per tap and 16 pixels: A = the tap's
+// weights in row 0 (rows 1..15 zero), B = the input (32 channels x 16 pixels);
+// row 0 of D (register 0 of lanes 0..15) holds the 16 outputs.  Wavefront w
+// computes rows 2w, 2w+1 of the tile.
+template <int C>
+__global__ __launch_bounds__(256) void k_conv_out_tile(const bf16* in, const bf16* wt,
+                                                       const bf16* bias, float* out, int B, int H,
+                                                       int W) {
+  static_assert(C == 32, "one K = 32 step per tap");
+  constexpr int TX = kConvTX, TY = kConvTY, LX = TX + 2, LY = TY + 2;
+  constexpr int CH = C / 8;                              // 16-byte chunks per pixel
+  constexpr int NLD = (LY * LX * CH + 255) / 256;        // staged chunks per thread
+  __shared__ __attribute__((aligned(16))) bf16 tin[LY * LX * C];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int li = lane & 15, lg = lane >> 4;
+  const int tilesx = (W + TX - 1) / TX, tilesy = (H + TY - 1) / TY;
+  const int per_img = tilesx * tilesy, ntiles = B * per_img;
+  const long long HW = (long long)H * W;
+  auto fetch = [&](int tile, uint4 (&pre)[NLD]) {
+    const int b = tile / per_img, r0 = tile % per_img;
+    const int ox = (r0 % tilesx) * TX, oy = (r0 / tilesx) * TY;
+    const bf16* inb = in + (size_t)b * HW * C;
+#pragma unroll
+    for (int k = 0; k < NLD; ++k) {
+      const int e = threadIdx.x + 256 * k;
+      const int pix = e / CH, ch = e % CH;
+      const int ly = pix / LX, lx = pix % LX;
+      const int gy = oy + ly - 1, gx = ox + lx - 1;
+      const bool ok = e < LY * LX * CH && gy >= 0 && gy < H && gx >= 0 && gx < W;
+      pre[k] = ok ? *reinterpret_cast<const uint4*>(inb + ((long long)gy * W + gx) * C + ch * 8)
+                  : make_uint4(0, 0, 0, 0);
+    }
+  };
+  uint4 pre[NLD];
+  int tile = blockIdx.x;
+  if (tile < ntiles) fetch(tile, pre);                   // the first tile's loads go out first
+  // A[i][k] = W[0][lg*8 + e][t] in row i = 0 (lanes li == 0), zero in the others
+  bf16x8 wa[9];
+#pragma unroll
+  for (int t = 0; t < 9; ++t) {
+    uint32_t h[8];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) h[e] = bf16_word_pick(wt, (long long)(lg * 8 + e) * 9 + t);
+#pragma unroll
+    for (int e = 0; e < 8; ++e) h[e] = li == 0 ? h[e] : 0u;
+    wa[t] = __builtin_bit_cast(bf16x8, make_uint4(h[0] | (h[1] << 16), h[2] | (h[3] << 16),
+                                                  h[4] | (h[5] << 16), h[6] | (h[7] << 16)));
+  }
+  const float bv = bf2f((bf16)bf16_word_pick(bias, 0));
+  for (; tile < ntiles; tile += gridDim.x) {
+    __syncthreads();                                     // the previous tile's reads are done
+#pragma unroll
+    for (int k = 0; k < NLD; ++k) {
+      const int e = threadIdx.x + 256 * k;
+      if (e < LY * LX * CH) *reinterpret_cast<uint4*>(&tin[e * 8]) = pre[k];
+    }
+    __syncthreads();
+    const int b = tile / per_img, r0 = tile % per_img;
+    const int ox = (r0 % tilesx) * TX, oy = (r0 / tilesx) * TY;
+    const int next = tile + gridDim.x;
+    if (next < ntiles) fetch(next, pre);                 // in flight during the MFMAs
+#pragma unroll 1
+    for (int r2 = 0; r2 < 2; ++r2) {
+      floatx4 acc[4];
+#pragma unroll
+      for (int nt = 0; nt < 4; ++nt) acc[nt] = floatx4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int t = 0; t < 9; ++t) {
+        const int ly = wv * 2 + r2 + t / 3, kx = t % 3;
+#pragma unroll
+        for (int nt = 0; nt < 4; ++nt) {
+          const int lx = nt * 16 + li + kx;
+          const bf16x8 bx = __builtin_bit_cast(
+              bf16x8, *reinterpret_cast<const uint4*>(&tin[(ly * LX + lx) * C + lg * 8]));
+          acc[nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa[t], bx, acc[nt], 0, 0, 0);
+        }
+      }
+      // D[i][p]: lane li + 16 lg holds rows 4 lg + r of pixel li; output channel 0
+      // is register 0 of lanes 0..15
+      const int y = oy + wv * 2 + r2;
+      if (lg == 0 && y < H) {
+#pragma unroll
+        for (int nt = 0; nt < 4; ++nt) {
+          const int x = ox + nt * 16 + li;
+          if (x < W) out[(size_t)b * HW + (long long)y * W + x] = acc[nt][0] + bv;
         }
       }
     }
@@ -2329,8 +2364,8 @@ void forward(const Net& n, const Ptrs& f, const Ptrs& u, hipStream_t s, bool gat
   // L4, L5, L6
   k_conv_mfma<C, false><<<conv_grid(d.B, d.H, d.W), 256, 0, s>>>(a[2], n.bfw(T_C4W), n.bfw(T_C4B), nullptr, a[3], d.B, d.H, d.W);
   k_conv_mfma<C, false><<<conv_grid(d.B, d.H, d.W), 256, 0, s>>>(a[3], n.bfw(T_C5W), n.bfw(T_C5B), nullptr, a[4], d.B, d.H, d.W);
-  k_conv_out_mfma<C><<<dim3(pixel_blocks(HW, d.B), d.B), 256, 0, s>>>(
-      a[4], n.bfw(T_C6W), n.bfw(T_C6B), n.w<float>(n.wl.out), d.H, d.W);
+  k_conv_out_tile<C><<<conv_grid(d.B, d.H, d.W), 256, 0, s>>>(a[4], n.bfw(T_C6W), n.bfw(T_C6B),
+                                                              n.w<float>(n.wl.out), d.B, d.H, d.W);
   // band path from the FP64 residual, replacing the band of the
   // convolutional output: out += norm S^T (w X - S out S^T) S (FP64)
   if (d.K == 0) return;
@@ -2743,8 +2778,8 @@ void fluid_forward(const FNet& n, const Ptrs& f, const Ptrs& u, int blocks, hipS
     k_conv_mfma<C, false, true><<<conv_grid(d.B, d.H, d.W), 256, 0, s>>>(n.w<bf16>(n.wl.Hb[i]), n.bfw(fl_blk(d, i, 2)), n.bfw(fl_blk(d, i, 3)), n.w<bf16>(n.wl.S[i]), n.w<bf16>(n.wl.S[i + 1]), d.B, d.H, d.W);
   }
   k_conv_mfma<C, false><<<conv_grid(d.B, d.H, d.W), 256, 0, s>>>(n.w<bf16>(n.wl.S[blocks]), n.bfw(fl_head(d, 0)), n.bfw(fl_head(d, 1)), nullptr, n.w<bf16>(n.wl.o), d.B, d.H, d.W);
-  k_conv_out_mfma<C><<<dim3(pixel_blocks(HW, d.B), d.B), 256, 0, s>>>(
-      n.w<bf16>(n.wl.o), n.bfw(fl_head(d, 2)), n.bfw(fl_head(d, 3)), n.w<float>(n.wl.out), d.H,
+  k_conv_out_tile<C><<<conv_grid(d.B, d.H, d.W), 256, 0, s>>>(
+      n.w<bf16>(n.wl.o), n.bfw(fl_head(d, 2)), n.bfw(fl_head(d, 3)), n.w<float>(n.wl.out), d.B, d.H,
       d.W);
 }
 
