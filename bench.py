@@ -76,6 +76,10 @@ def parse():
     ap.add_argument("--records", default=None, metavar="PATH",
                     help="write every right-hand side's record of the stream as a JSON line")
     ap.add_argument("--json-out", default=None)
+    ap.add_argument("--log-jsonl", default=None, metavar="PATH",
+                    help="append one JSON line per right-hand side of the learned stream "
+                         "(guess, Arnoldi steps, initial, fifth-iteration and final residuals, "
+                         "time to solution, training) to PATH")
     ap.add_argument("--probe", default=None, metavar="KERNEL",
                     help="counter-collection run: a 256 MiB device copy (the byte-count "
                          "calibration) then every launch of KERNEL (step, dots, extend, update, "
@@ -536,7 +540,7 @@ def main():
     shadow = mlg.NetCfg(skip_modes=0, seed=args.seed)
     sv = StreamSolver(shape, guess="learned", restart_m=args.restart, rtol=args.rtol,
                       precision=mlg.MLG_FP32_IR, seed=args.seed, time_train=False,
-                      shadow_cfgs=[shadow])
+                      shadow_cfgs=[shadow], log_path=args.log_jsonl)
     torch.cuda.synchronize()
     ts0 = time.perf_counter()
     for t in range(t_warm):

@@ -21,9 +21,10 @@ Every computation runs in the HIP library; this module only sequences calls.
 """
 from __future__ import annotations
 
+import json
 import time
 from collections import deque
-from dataclasses import dataclass, field
+from dataclasses import asdict, dataclass, field
 
 import numpy as np
 import torch
@@ -187,6 +188,17 @@ class StepRecord:
     extra: dict = field(default_factory=dict)
 
 
+def record_json(rec: StepRecord) -> str:
+    """One step's record as a JSON object (NaN written as null)."""
+    def clean(v):
+        if isinstance(v, float) and v != v:
+            return None
+        if isinstance(v, dict):
+            return {k: clean(x) for k, x in v.items()}
+        return v
+    return json.dumps({k: clean(v) for k, v in asdict(rec).items()}, sort_keys=True)
+
+
 class StreamSolver:
     """Solve a stream of right-hand sides on one grid with a chosen guess policy.
 
@@ -214,7 +226,7 @@ class StreamSolver:
                  retrain_steps: int = 32, p: int = 10, f_r: int = 8, cos_max: float = 0.999,
                  train_set: int = 512, network: str = "spectral", fluid_cfg: FluidCfg | None = None,
                  max_blocks: int = 4, grow_window: int = 50, grow_min_gain: float = 0.05,
-                 lin_lr: float = 0.1, shadow_cfgs=()):
+                 lin_lr: float = 0.1, shadow_cfgs=(), log_path: str | None = None):
         if guess not in ("zero", "prev", "learned", "linear"):
             raise ValueError("guess must be zero, prev, learned or linear")
         self.lin_lr = lin_lr
@@ -248,6 +260,9 @@ class StreamSolver:
         self.u_prev = torch.zeros(self.shape, dtype=torch.float64, device="cuda")
         self.x = torch.empty_like(self.u_prev)
         self.records: list[StepRecord] = []
+        # one JSON object per right-hand side (the step's record), appended to
+        # log_path as the stream runs
+        self.log = open(log_path, "a") if log_path else None
         if guess == "linear":
             self.warmup = 1
             self.params = torch.zeros(linear_guess_param_bytes(self.grid), dtype=torch.uint8,
@@ -336,6 +351,9 @@ class StreamSolver:
             rec.extra["train_steps"] = steps
         self.u_prev.copy_(self.x)
         self.records.append(rec)
+        if self.log:
+            self.log.write(record_json(rec) + "\n")
+            self.log.flush()
         self.t += 1
         return rec
 

@@ -170,3 +170,26 @@ def test_multiscale_network_stream(mlg):
           f"zero guess {ek_zero:.3f}, multi-scale network {ek:.3f}")
     assert sv.growth.blocks == 2 and [e[1] for e in sv.growth.events] == [1, 2]
     assert math.isfinite(ek)
+
+
+def test_stream_jsonl_log(mlg, tmp_path):
+    """The per-RHS log: one JSON object per solved right-hand side, the same
+    figures as the in-memory records (NaN written as null)."""
+    import json
+    from paper_2103_10975_amd.stream import StreamSolver
+    print("stream log", flush=True)
+    shape = (48, 40)
+    g = DriftingGaussians(shape, 2, 0.1, seed=31)
+    path = tmp_path / "stream.jsonl"
+    sv = StreamSolver(shape, guess="prev", restart_m=12, rtol=1e-9, autotune=False,
+                      log_path=str(path))
+    for t in range(3):
+        sv.step(torch.from_numpy(g.field(t)).cuda())
+    sv.log.close()
+    lines = path.read_text().splitlines()
+    assert len(lines) == 3
+    for line, rec in zip(lines, sv.records):
+        d = json.loads(line)
+        assert d["t"] == rec.t and d["guess"] == rec.guess and d["iters"] == rec.iters
+        assert d["relres_true"] == rec.relres_true and d["relres_true"] <= 1e-9
+        assert d["tos"] > 0 and d["loss"] is None

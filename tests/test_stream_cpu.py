@@ -107,3 +107,15 @@ def test_fluid_levels():
     assert fluid_levels((96, 136)) == 4      # 136 = 8 * 17
     assert fluid_levels((50, 64)) == 2       # 50 = 2 * 25
     assert fluid_levels((7, 9)) == 1
+
+
+def test_record_json_writes_nan_as_null():
+    import json
+    from paper_2103_10975_amd.stream import StepRecord, record_json
+    rec = StepRecord(3, "learned", 17, 1, 1.3e-5, 2e-9, 9e-9, 4.7e-4, relres_iter5=float("nan"))
+    rec.extra["train_steps"] = 1
+    d = json.loads(record_json(rec))
+    assert d["t"] == 3 and d["guess"] == "learned" and d["iters"] == 17
+    assert d["relres_iter5"] is None and d["loss"] is None
+    assert d["extra"] == {"train_steps": 1}
+    assert list(d) == sorted(d)
