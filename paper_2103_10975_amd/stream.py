@@ -307,6 +307,60 @@ class StreamSolver:
                 "ws_train": workspace(guess_net_workspace_bytes(cfg, self.grid, batch, True))})
 
     # ------------------------------------------------------------------
+    def state_dict(self) -> dict:
+        """What the stream carries from one step to the next, in host memory:
+        the step count, u_{t-1}, the network's parameter buffer (weights, Adam
+        moments and step, the band's least-squares sums, the output gain), the
+        replay buffer's pairs and its generator state, and the shadow networks.
+        Resuming from it continues the stream as if it had not stopped (the
+        kernels are deterministic).  Covers the replay policy with the spectral
+        network or the linear model."""
+        if self.policy != "replay" or (self.guess_kind == "learned" and self.network != "spectral"):
+            raise NotImplementedError("checkpoints cover the replay policy with the spectral "
+                                      "network or the linear model")
+        st = {"t": self.t, "u_prev": self.u_prev.cpu(),
+              "shadows": [sh["params"].cpu() for sh in self.shadows]}
+        if hasattr(self, "params"):
+            st["params"] = self.params.cpu()
+        if hasattr(self, "replay"):
+            st["replay"] = [torch.stack([a.cpu() for a in item]) for item in self.replay.items]
+            st["replay_rng"] = self.replay.rng.bit_generator.state
+        return st
+
+    def load_state_dict(self, st: dict) -> None:
+        """Resume from state_dict() of a stream with the same configuration."""
+        if self.policy != "replay" or (self.guess_kind == "learned" and self.network != "spectral"):
+            raise NotImplementedError("checkpoints cover the replay policy with the spectral "
+                                      "network or the linear model")
+        if tuple(st["u_prev"].shape) != self.shape:
+            raise ValueError(f"checkpoint grid {tuple(st['u_prev'].shape)}, stream {self.shape}")
+        if ("params" in st) != hasattr(self, "params") or len(st["shadows"]) != len(self.shadows):
+            raise ValueError("checkpoint of a stream with another guess or other shadow networks")
+        if "params" in st:
+            if st["params"].numel() != self.params.numel():
+                raise ValueError("checkpoint of another network configuration")
+            self.params.copy_(st["params"].to(self.params.device))
+        for sh, prm in zip(self.shadows, st["shadows"]):
+            if prm.numel() != sh["params"].numel():
+                raise ValueError("checkpoint of another shadow network configuration")
+            sh["params"].copy_(prm.to(sh["params"].device))
+        self.t = int(st["t"])
+        self.u_prev.copy_(st["u_prev"].to(self.u_prev.device))
+        if hasattr(self, "replay"):
+            self.replay.items.clear()
+            for item in st.get("replay", []):
+                self.replay.push(*(x.cuda() for x in item.unbind(0)))
+            self.replay.rng.bit_generator.state = st["replay_rng"]
+
+    def save(self, path) -> None:
+        torch.save(self.state_dict(), path)
+
+    def load(self, path) -> None:
+        """Resume from a file written by save() (read with the loader that
+        executes nothing from the file)."""
+        self.load_state_dict(torch.load(path, weights_only=True))
+
+    # ------------------------------------------------------------------
     def _guess(self, f: torch.Tensor) -> str:
         if self.guess_kind == "zero" or self.t == 0:
             self.x.zero_()

@@ -193,3 +193,32 @@ def test_stream_jsonl_log(mlg, tmp_path):
         assert d["t"] == rec.t and d["guess"] == rec.guess and d["iters"] == rec.iters
         assert d["relres_true"] == rec.relres_true and d["relres_true"] <= 1e-9
         assert d["tos"] > 0 and d["loss"] is None
+
+
+def test_stream_checkpoint_resume(mlg, tmp_path):
+    """A stream saved after step 6 and resumed in a fresh solver (another
+    workspace, another process's worth of state) continues bit for bit: the
+    same guesses, Arnoldi steps and solutions as the uninterrupted stream."""
+    from paper_2103_10975_amd.stream import StreamSolver
+    print("stream checkpoint", flush=True)
+    shape = (64, 64)
+    g = DriftingGaussians(shape, 3, 0.05, seed=77)
+    fields = [torch.from_numpy(g.field(t)).cuda() for t in range(12)]
+    kw = dict(guess="learned", restart_m=20, rtol=1e-9, warmup=3, replay=16, batch=4, seed=5,
+              autotune=False, shadow_cfgs=[mlg.NetCfg(skip_modes=0, seed=5)])
+    a = StreamSolver(shape, **kw)
+    for t in range(6):
+        a.step(fields[t])
+    path = tmp_path / "stream.pt"
+    a.save(path)
+    for t in range(6, 12):
+        a.step(fields[t])
+    b = StreamSolver(shape, **kw)
+    b.load(path)
+    assert b.t == 6
+    for t in range(6, 12):
+        rb = b.step(fields[t])
+        ra = a.records[t]
+        assert (rb.guess, rb.iters, rb.relres_true) == (ra.guess, ra.iters, ra.relres_true), t
+    assert torch.equal(a.u_prev, b.u_prev)
+    assert torch.equal(a.params, b.params)
