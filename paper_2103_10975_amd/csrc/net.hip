@@ -26,11 +26,14 @@
 //       inference only)
 //   guess = u_prev + (s_r/c_u) out
 // The 3x3 convolutions with C -> C channels (forward, input gradient and
-// weight gradient) run on MFMA (v_mfma_f32_16x16x32_bf16) as implicit GEMMs
-// over LDS tiles; the thin layers (2 -> C, C -> 1), the sine transforms (GEMMs
-// with 16 outputs per row, bandwidth bound) and the element-wise work run on
-// the vector ALUs.  Activations and gradients are BF16, accumulation FP32,
-// master weights and Adam state FP32.
+// weight gradient) and C -> 1 run on MFMA (v_mfma_f32_16x16x32_bf16) as
+// implicit GEMMs over LDS tiles, the 2 -> C input layer per pixel block; the
+// spectral layer's sine transforms on the BF16 and FP32 matrix cores; the
+// band path's four FP64 transforms on the FP64 matrix cores
+// (v_mfma_f64_16x16x4f64; the row and output transforms also in a vector
+// form for launches that fill the device); the element-wise work on the
+// vector ALUs.  Activations and gradients are BF16, accumulation FP32, master
+// weights and Adam state FP32, the band path FP64.
 #include <algorithm>
 #include <cmath>
 #include <vector>
