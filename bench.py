@@ -76,6 +76,10 @@ def parse():
     ap.add_argument("--records", default=None, metavar="PATH",
                     help="write every right-hand side's record of the stream as a JSON line")
     ap.add_argument("--json-out", default=None)
+    ap.add_argument("--schedule", type=int, default=0, choices=(0, 1, 2, 3),
+                    help="step schedule of the learned stream's solves (mlg_opts.schedule; 0 = "
+                         "autotuned): pins the tuned choice for profiled runs, whose timings "
+                         "the profiler shifts")
     ap.add_argument("--log-jsonl", default=None, metavar="PATH",
                     help="append one JSON line per right-hand side of the learned stream "
                          "(guess, Arnoldi steps, initial, fifth-iteration and final residuals, "
@@ -541,6 +545,8 @@ def main():
     sv = StreamSolver(shape, guess="learned", restart_m=args.restart, rtol=args.rtol,
                       precision=mlg.MLG_FP32_IR, seed=args.seed, time_train=False,
                       shadow_cfgs=[shadow], log_path=args.log_jsonl)
+    if args.schedule:
+        sv.opts.schedule = args.schedule
     torch.cuda.synchronize()
     ts0 = time.perf_counter()
     for t in range(t_warm):
@@ -626,6 +632,11 @@ def main():
 
     # roofline of the dominant kernel of the learned-guess solve
     tile, fused, split, launch = sv.tuned
+    if args.schedule:                     # the pinned schedule, for every step
+        allm = (1 << args.restart) - 1
+        fused = allm if args.schedule >= 2 else 0
+        split = allm if args.schedule == 3 else 0
+        result["config"]["schedule"] = args.schedule
     tshape = mlg.mlg_tile_shape(2, tile - 1)
     result["config"]["tile"] = list(tshape)
     result["config"]["launch"] = "direct" if launch == 2 else "graph"
