@@ -1988,8 +1988,20 @@ struct BandOut {
   double beta;
 };
 
+// The guess written by the output transform's epilogue (inference): guess =
+// u_prev + (s_r / c_u) out, from the stored FP32 output value (the same
+// arithmetic as k_guess).
+struct GuessOut {
+  Ptrs u;
+  MPtrs g;
+  const double* s;
+};
+struct NoGuess {};
+
+template <bool GUESS>
 __global__ __launch_bounds__(256) void k_band_out(BandOut f0, BandOut f1, const double* Sx, int H,
-                                                  int W, int K) {
+                                                  int W, int K,
+                                                  std::conditional_t<GUESS, GuessOut, NoGuess> go) {
   constexpr int NS = 16;
   const BandOut& f = blockIdx.y == 0 ? f0 : f1;
   const int ncb = (W + 63) / 64, nrb = (H + 15) / 16;
@@ -2021,7 +2033,14 @@ __global__ __launch_bounds__(256) void k_band_out(BandOut f0, BandOut f1, const 
 #pragma unroll
   for (int r = 0; r < 4; ++r) {
     const int i = i0 + 4 * r + kq;
-    if (i < H) f.out[((size_t)b * H + i) * W + j] = (float)(g * (double)ov[r] + f.beta * acc[r]);
+    if (i < H) {
+      const float o = (float)(g * (double)ov[r] + f.beta * acc[r]);
+      f.out[((size_t)b * H + i) * W + j] = o;
+      if constexpr (GUESS) {
+        const size_t q = (size_t)i * W + j;
+        go.g.p[b][q] = go.u.p[b][q] + (go.s[b] / kCu) * (double)o;
+      }
+    }
   }
 }
 
@@ -2303,13 +2322,21 @@ inline dim3 band_out_grid(const Dims& d, int fields) {
 // field, where the vector form would leave most of the device idle).
 inline bool band_vector(const Dims& d) { return (long long)d.B * cdiv(d.H, kBandRows) >= 256; }
 
-void launch_band_out(hipStream_t s, const Dims& d, int fields, BandOut f0, BandOut f1,
-                     const double* Sx) {
-  if (band_vector(d))
+// With `go` (inference of one field), the matrix-core form also writes the
+// guess; returns whether it did.
+bool launch_band_out(hipStream_t s, const Dims& d, int fields, BandOut f0, BandOut f1,
+                     const double* Sx, const GuessOut* go = nullptr) {
+  if (band_vector(d)) {
     k_band_out_vec<<<dim3(d.B * cdiv(d.H, kBandRows) * cdiv(d.W, 256), fields), 256, 0, s>>>(
         f0, f1, Sx, d.H, d.W, d.K);
-  else
-    k_band_out<<<band_out_grid(d, fields), 256, 0, s>>>(f0, f1, Sx, d.H, d.W, d.K);
+    return false;
+  }
+  if (go) {
+    k_band_out<true><<<band_out_grid(d, fields), 256, 0, s>>>(f0, f1, Sx, d.H, d.W, d.K, *go);
+    return true;
+  }
+  k_band_out<false><<<band_out_grid(d, fields), 256, 0, s>>>(f0, f1, Sx, d.H, d.W, d.K, NoGuess{});
+  return false;
 }
 
 // Mode coefficients of two fields, X_q = scale_q S_y (x_q / div_q) S_x^T
@@ -2335,7 +2362,8 @@ void band_project_rows_cols(const Net& n, BandIn<X0> f0, BandIn<X1> f1, double* 
 // gated: apply the convolutional branch's output gain (inference); training
 // runs with gain 1.
 template <int C>
-void forward(const Net& n, const Ptrs& f, const Ptrs& u, hipStream_t s, bool gated) {
+bool forward(const Net& n, const Ptrs& f, const Ptrs& u, hipStream_t s, bool gated,
+             const GuessOut* go = nullptr) {
   const Dims& d = n.d;
   const long long HW = d.HW;
   bf16* x0 = n.w<bf16>(n.wl.x0);
@@ -2370,8 +2398,9 @@ void forward(const Net& n, const Ptrs& f, const Ptrs& u, hipStream_t s, bool gat
   k_conv_out_tile<C><<<conv_grid(d.B, d.H, d.W), 256, 0, s>>>(a[4], n.bfw(T_C6W), n.bfw(T_C6B),
                                                               n.w<float>(n.wl.out), d.B, d.H, d.W);
   // band path from the FP64 residual, replacing the band of the
-  // convolutional output: out += norm S^T (w X - S out S^T) S (FP64)
-  if (d.K == 0) return;
+  // convolutional output: out += norm S^T (w X - S out S^T) S (FP64); with
+  // `go`, the output transform may also write the guess (returns whether)
+  if (d.K == 0) return false;
   float* out = n.w<float>(n.wl.out);
   const double* gate = gated ? (const double*)(n.params + n.pl.gate) : nullptr;
   const BandSpace bsp = band_space(n);
@@ -2379,7 +2408,8 @@ void forward(const Net& n, const Ptrs& f, const Ptrs& u, hipStream_t s, bool gat
                                         {out, nullptr, bsp.kT2, 1.0}, bsp.kX, bsp.kC, 1.0, 1.0, s);
   k_band_inv<<<band_inv_grid(d), 256, 0, s>>>(bsp.kX, bsp.kC, (const double*)(n.params + n.pl.band),
                                                gate, bsp.kSy, bsp.kZ, d.H, d.K, 2.0 / (d.H + 1));
-  launch_band_out(s, d, 1, BandOut{bsp.kZ, out, gate, 2.0 / (d.W + 1)}, BandOut{}, bsp.kSx);
+  return launch_band_out(s, d, 1, BandOut{bsp.kZ, out, gate, 2.0 / (d.W + 1)}, BandOut{}, bsp.kSx,
+                         go);
 }
 
 template <int C>
@@ -2938,9 +2968,10 @@ int net_infer(const guess_net_cfg* cfg, const void* params, const mlg_grid* grid
     up.p[b] = u_prev + (size_t)b * d.HW;
     gp.p[b] = guess + (size_t)b * d.HW;
   }
-  forward<32>(n, fp, up, s, true);
-  k_guess<<<dim3(cdiv(d.HW, 256), d.B), 256, 0, s>>>(n.w<float>(wl.out), up, n.w<double>(wl.s), gp,
-                                                      d.HW);
+  const GuessOut go{up, gp, n.w<double>(wl.s)};
+  if (!forward<32>(n, fp, up, s, true, &go))
+    k_guess<<<dim3(cdiv(d.HW, 256), d.B), 256, 0, s>>>(n.w<float>(wl.out), up, n.w<double>(wl.s), gp,
+                                                        d.HW);
   MLG_HIP(hipGetLastError());
   return MLG_OK;
 }
