@@ -147,6 +147,37 @@ def test_forward_homogeneous_bitwise(mlg):
     assert torch.isfinite(g1).all() and (g1 - u).abs().max() > 0
 
 
+def test_batched_inference_band_forms_agree(mlg):
+    """A batch of 4 at 512² runs the band path's row and output transforms in
+    their vector form (the launch fills the device) with a separate guess
+    kernel; one image at a time runs them on the FP64 matrix cores with the
+    guess written by the output transform.  The two agree to the FP32
+    rounding of the network output (the FP64 band sums differ only in their
+    order)."""
+    print("net batched band forms", flush=True)
+    cfg = mlg.NetCfg(channels=32, modes=16, skip_modes=64)
+    p = bf16_round(guess_net_params(13, channels=32, modes=16, skip_modes=64))
+    buf = make_params(mlg, cfg, p)
+    shape = (512, 512)
+    g = DriftingGaussians(shape, 4, 0.03, seed=4100)
+    f = dev(np.stack([g.field(t + 1) for t in range(4)]))
+    u = dev(np.stack([0.9 * g.field(t) for t in range(4)]))
+    grid = mlg.grid_of(shape)
+    ws4 = mlg.workspace(mlg.guess_net_workspace_bytes(cfg, grid, 4, False))
+    ws1 = mlg.workspace(mlg.guess_net_workspace_bytes(cfg, grid, 1, False))
+    g4 = torch.empty_like(f)
+    mlg.guess_net_infer(cfg, buf, f, u, g4, ws4)
+    g1 = torch.empty_like(f)
+    for b in range(4):
+        mlg.guess_net_infer(cfg, buf, f[b:b + 1], u[b:b + 1], g1[b:b + 1], ws1)
+    torch.cuda.synchronize()
+    corr = (g1 - u).abs().amax(dim=(1, 2))
+    diff = (g4 - g1).abs().amax(dim=(1, 2))
+    print("  max |batch - single| / max |correction|:", (diff / corr).tolist())
+    assert bool(torch.all(corr > 0))
+    assert bool(torch.all(diff <= 1e-6 * corr))
+
+
 # The band is kept to at most 1/8 of the grid per axis, as in the benchmark
 # (64 of 512): gradient parity is measured relative to the oracle gradient,
 # and when the band covers a large part of the spectrum the gradient
