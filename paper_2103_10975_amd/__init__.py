@@ -217,13 +217,15 @@ def _need(cond: bool, msg: str) -> None:
 
 def _same_fields(ts, shape, what: str) -> None:
     for t in ts:
-        _need(tuple(t.shape) == tuple(shape), f"{what}: every field must have shape {tuple(shape)}, "
-                                              f"got {tuple(t.shape)}")
+        if t.shape != shape:                              # the message only on failure
+            raise ValueError(f"{what}: every field must have shape {tuple(shape)}, "
+                             f"got {tuple(t.shape)}")
 
 
 def _params_ok(params: torch.Tensor, nbytes: int) -> None:
-    _need(params.numel() >= nbytes, f"parameter buffer holds {params.numel()} bytes, "
-                                    f"the configuration needs {nbytes}")
+    if params.numel() < nbytes:
+        raise ValueError(f"parameter buffer holds {params.numel()} bytes, "
+                         f"the configuration needs {nbytes}")
 
 
 def grid_of(shape) -> Grid:

@@ -259,6 +259,9 @@ class StreamSolver:
         self.t = 0
         self.u_prev = torch.zeros(self.shape, dtype=torch.float64, device="cuda")
         self.x = torch.empty_like(self.u_prev)
+        # batch-of-one views of the two fixed fields (the guess call's arguments)
+        self._u1 = self.u_prev.view(1, *self.shape)
+        self._x1 = self.x.view(1, *self.shape)
         self.records: list[StepRecord] = []
         # one JSON object per right-hand side (the step's record), appended to
         # log_path as the stream runs
@@ -371,8 +374,7 @@ class StreamSolver:
         if self.guess_kind == "linear":
             linear_guess_infer(self.grid, self.params, f.reshape(1, -1), self.x.view(1, -1))
             return "linear"
-        args = (f.view(1, *self.shape), self.u_prev.view(1, *self.shape),
-                self.x.view(1, *self.shape), self.ws_infer)
+        args = (f.view(1, *self.shape), self._u1, self._x1, self.ws_infer)
         if self.network == "fluid":
             fluid_net_infer(self.net_cfg, self.params, self.growth.blocks, *args)
         else:
