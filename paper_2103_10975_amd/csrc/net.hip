@@ -2257,12 +2257,12 @@ __global__ void k_adam(float* master, const float* grad, float* m, float* v, bf1
 // ------------------------------------------------------------------ host helpers
 inline int cdiv(long long a, long long b) { return (int)((a + b - 1) / b); }
 
-// Workgroups per image of the per-pixel convolutions, which loop over the
-// image's 256-pixel blocks: at most 2048 over the batch (measured at 512²:
-// a batch of 8 with 256 per image ran the input and output convolutions in
-// 49 and 84 µs against 61 and 101 µs with one workgroup per block, while a
-// single image keeps one per block, 1024).  The output-gradient convolution
-// keeps one workgroup per block (capped it ran 78 against 69 µs).
+// Workgroups per image of the input convolution, which loops over the
+// image's 256-pixel blocks: at most 2048 over the batch (measured at 512²: a
+// batch of 8 with 256 per image ran it in 49 µs against 61 µs with one
+// workgroup per block, while a single image keeps one per block, 1024).  The
+// output-gradient convolution keeps one workgroup per block (capped it ran
+// 78 against 69 µs).
 constexpr int kPixelBlocksTotal = 2048;
 inline int pixel_blocks(long long hw, int B) {
   return (int)std::max<long long>(1, std::min<long long>(cdiv(hw, 256), kPixelBlocksTotal / B));
